@@ -1,0 +1,230 @@
+"""CPU oracle for prime paths and test paths (ctypes binding to oracle.cpp).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg may import this package; the product path never does.  It
+shares no code with the GPU engine.
+
+The C++ source states which passage of the paper each routine follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Dict, List, Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.cpp with g++ (host only)."""
+    if force or not os.path.exists(_LIB) or \
+            os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["g++", "-O3", "-std=c++17", "-shared", "-fPIC",
+                               "-pthread", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Paths(ctypes.Structure):
+    _fields_ = [("n_paths", ctypes.c_int64), ("n_vertices", ctypes.c_int64),
+                ("offsets", ctypes.POINTER(ctypes.c_int64)),
+                ("vertices", ctypes.POINTER(ctypes.c_int32))]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("n_candidates", ctypes.c_int64), ("n_cycles", ctypes.c_int64),
+                ("n_extensions", ctypes.c_int64), ("n_pp", ctypes.c_int64),
+                ("n_pp_local", ctypes.c_int64), ("max_len", ctypes.c_int64)]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        _lib = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER
+        i64p, i32p = P(ctypes.c_int64), P(ctypes.c_int32)
+        _lib.orc_prime_paths.argtypes = [ctypes.c_int, i64p, i32p, ctypes.c_int,
+                                         P(_Paths), P(_Stats), i64p, i64p]
+        _lib.orc_prime_paths_local.argtypes = [ctypes.c_int, i64p, i32p, ctypes.c_int,
+                                               ctypes.c_int, ctypes.c_int, P(_Paths),
+                                               P(_Stats)]
+        _lib.orc_count.argtypes = [ctypes.c_int, i64p, i32p, ctypes.c_int,
+                                   ctypes.c_int64, P(_Stats), i64p, i64p]
+        _lib.orc_bruteforce_pp.argtypes = [ctypes.c_int, i64p, i32p, P(_Paths), P(_Paths)]
+        _lib.orc_bfs.argtypes = [ctypes.c_int, i64p, i32p, ctypes.c_int, ctypes.c_int,
+                                 i32p, i32p, i32p, i32p]
+        _lib.orc_bruteforce_lexmin_shortest.argtypes = [ctypes.c_int, i64p, i32p,
+                                                        ctypes.c_int, ctypes.c_int, i32p,
+                                                        ctypes.c_int]
+        _lib.orc_test_paths.argtypes = [ctypes.c_int, i64p, i32p, ctypes.c_int,
+                                        ctypes.c_int, P(_Paths), P(_Paths), i64p]
+        _lib.orc_free_paths.argtypes = [P(_Paths)]
+    return _lib
+
+
+class PathList:
+    """A canonical path set: offsets int64 [n+1], vertices int32 [total]."""
+
+    def __init__(self, offsets: np.ndarray, vertices: np.ndarray) -> None:
+        self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        self.vertices = np.ascontiguousarray(vertices, dtype=np.int32)
+
+    def __len__(self) -> int:
+        return len(self.offsets) - 1
+
+    def __getitem__(self, i: int) -> List[int]:
+        return self.vertices[self.offsets[i]:self.offsets[i + 1]].tolist()
+
+    def tolist(self) -> List[List[int]]:
+        return [self[i] for i in range(len(self))]
+
+    @staticmethod
+    def from_lists(paths: List[List[int]]) -> "PathList":
+        offs = np.zeros(len(paths) + 1, dtype=np.int64)
+        offs[1:] = np.cumsum([len(p) for p in paths]) if paths else []
+        verts = np.array([v for p in paths for v in p], dtype=np.int32)
+        return PathList(offs, verts)
+
+    def _c(self) -> _Paths:
+        return _Paths(len(self), len(self.vertices),
+                      self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                      self.vertices.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+
+
+def _take(p: _Paths) -> PathList:
+    n, nv = p.n_paths, p.n_vertices
+    offs = np.ctypeslib.as_array(p.offsets, shape=(n + 1,)).copy()
+    verts = (np.ctypeslib.as_array(p.vertices, shape=(nv,)).copy() if nv
+             else np.zeros(0, np.int32))
+    _load().orc_free_paths(ctypes.byref(p))
+    return PathList(offs, verts)
+
+
+def _csr(g):
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(g.col_idx, dtype=np.int32)
+    if ci.size == 0:
+        ci = np.zeros(1, np.int32)
+    return (rp, ci, rp.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+            ci.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+
+
+def _stats(s: _Stats) -> Dict[str, int]:
+    return {k: int(getattr(s, k)) for k, _ in _Stats._fields_}
+
+
+def _threads(nthreads: Optional[int]) -> int:
+    return int(nthreads if nthreads is not None else min(16, os.cpu_count() or 1))
+
+
+def prime_paths(g, nthreads: Optional[int] = None
+                ) -> Tuple[PathList, Dict[str, int], np.ndarray, np.ndarray]:
+    """PPs in canonical order, stats, per-level acyclic counts, cycle counts."""
+    lib = _load()
+    rp, ci, prp, pci = _csr(g)
+    out, st = _Paths(), _Stats()
+    lv = np.zeros(g.n + 2, np.int64)
+    cy = np.zeros(g.n + 2, np.int64)
+    lib.orc_prime_paths(g.n, prp, pci, _threads(nthreads), ctypes.byref(out),
+                        ctypes.byref(st), lv.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                        cy.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    return _take(out), _stats(st), lv, cy
+
+
+def prime_paths_local(g, s_lo: int, s_hi: int, nthreads: Optional[int] = None
+                      ) -> Tuple[PathList, Dict[str, int]]:
+    """PPs whose first vertex lies in [s_lo, s_hi), by the local rule."""
+    lib = _load()
+    rp, ci, prp, pci = _csr(g)
+    out, st = _Paths(), _Stats()
+    lib.orc_prime_paths_local(g.n, prp, pci, s_lo, s_hi, _threads(nthreads),
+                              ctypes.byref(out), ctypes.byref(st))
+    return _take(out), _stats(st)
+
+
+def count(g, nthreads: Optional[int] = None, ext_cap: int = 0
+          ) -> Tuple[Optional[Dict[str, int]], np.ndarray, np.ndarray]:
+    """Per-level counts and the PP count without storing paths.  With
+    ext_cap > 0, returns (None, ...) once about ext_cap extensions are
+    exceeded."""
+    lib = _load()
+    rp, ci, prp, pci = _csr(g)
+    st = _Stats()
+    lv = np.zeros(g.n + 2, np.int64)
+    cy = np.zeros(g.n + 2, np.int64)
+    rc = lib.orc_count(g.n, prp, pci, _threads(nthreads), int(ext_cap), ctypes.byref(st),
+                       lv.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                       cy.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if rc == 1:
+        return None, lv, cy
+    return _stats(st), lv, cy
+
+
+def bruteforce_pp(g) -> Tuple[PathList, PathList]:
+    """(prime paths, all simple paths), straight from the definitions."""
+    lib = _load()
+    rp, ci, prp, pci = _csr(g)
+    out, allp = _Paths(), _Paths()
+    rc = lib.orc_bruteforce_pp(g.n, prp, pci, ctypes.byref(out), ctypes.byref(allp))
+    if rc != 0:
+        raise ValueError("graph too large for brute force (<= 32 vertices, "
+                         "<= 60000 simple paths)")
+    return _take(out), _take(allp)
+
+
+def bfs_tables(g) -> Dict[str, np.ndarray]:
+    lib = _load()
+    rp, ci, prp, pci = _csr(g)
+    arrs = {k: np.zeros(g.n, np.int32) for k in ("dist_f", "parent", "dist_b", "next")}
+    ptr = {k: v.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) for k, v in arrs.items()}
+    lib.orc_bfs(g.n, prp, pci, g.entry, g.exit, ptr["dist_f"], ptr["parent"],
+                ptr["dist_b"], ptr["next"])
+    return arrs
+
+
+def bruteforce_lexmin_shortest(g, a: int, b: int) -> Optional[List[int]]:
+    lib = _load()
+    rp, ci, prp, pci = _csr(g)
+    buf = np.zeros(g.n + 1, np.int32)
+    k = lib.orc_bruteforce_lexmin_shortest(g.n, prp, pci, a, b,
+                                           buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                           g.n + 1)
+    if k == -1:
+        return None
+    if k < 0:
+        raise ValueError("graph too large for exhaustive shortest paths")
+    return buf[:k].tolist()
+
+
+def test_paths(g, pps: PathList) -> Tuple[PathList, int]:
+    """(deduplicated sorted TPs, number spliced before dedup)."""
+    lib = _load()
+    rp, ci, prp, pci = _csr(g)
+    src = pps._c()
+    out = _Paths()
+    nb = ctypes.c_int64(0)
+    rc = lib.orc_test_paths(g.n, prp, pci, g.entry, g.exit, ctypes.byref(src),
+                            ctypes.byref(out), ctypes.byref(nb))
+    if rc != 0:
+        raise ValueError("a prime path is not reachable from entry or cannot reach exit")
+    return _take(out), int(nb.value)
+
+
+def canonical_bytes(pl: PathList) -> bytes:
+    """n (int64 LE) + offsets (int64 LE) + vertices (int32 LE)."""
+    return (np.int64(len(pl)).tobytes() + pl.offsets.astype("<i8").tobytes()
+            + pl.vertices.astype("<i4").tobytes())
+
+
+def sha256(pl: PathList) -> str:
+    import hashlib
+    return hashlib.sha256(canonical_bytes(pl)).hexdigest()

@@ -1,0 +1,268 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's own formula: each compares it with a
+printed example, a closed form derived by hand, a brute-force evaluation of
+the definitions, or an invariant.
+"""
+import math
+from itertools import permutations
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import PathList
+from paper_2210_16998_amd import cfggen
+from tests.goldens import read_paths, workloads
+
+
+def _pp(g):
+    pp, st, lv, cy = oracle.prime_paths(g)
+    return pp, st, lv, cy
+
+
+# --- the paper's worked example ------------------------------------------
+
+def test_fig1_prime_paths_match_paper():
+    """Def. 1 / Sec. 2.1: the 19 PPs printed for the Fig. 1 CFG."""
+    want = sorted(read_paths("fig1_pps.txt"))
+    assert len(want) == 19 and len(set(map(tuple, want))) == 19
+    pp, st, _, _ = _pp(cfggen.fig1_cfg())
+    assert pp.tolist() == want
+    assert st["n_pp"] == st["n_pp_local"] == 19
+
+
+def test_fig1_scc_internal_prime_paths():
+    """Sec. 2.1: the SCC alone has exactly the 11 printed internal PPs."""
+    want = sorted(read_paths("fig1_scc_pps.txt"))
+    pp, _, _, _ = _pp(cfggen.fig1_scc_cfg())
+    got = sorted([[cfggen.FIG1_SCC_LABELS[v] for v in p] for p in pp.tolist()])
+    assert got == want
+
+
+def test_fig1_pp_type_split():
+    """Sec. 2.1: 11 internal + 2 complete + 4 exit + 2 entry PPs."""
+    pp, _, _, _ = _pp(cfggen.fig1_cfg())
+    scc = {2, 3, 4, 5, 6, 8}
+    complete = [p for p in pp.tolist() if p[0] == 0 and p[-1] == 10]
+    internal = [p for p in pp.tolist() if set(p) <= scc]
+    exitpp = [p for p in pp.tolist() if p[0] in scc and p[-1] == 10]
+    entrypp = [p for p in pp.tolist() if p[0] == 0 and p[-1] in scc]
+    assert (len(internal), len(complete), len(exitpp), len(entrypp)) == (11, 2, 4, 2)
+
+
+# --- closed forms ----------------------------------------------------------
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6])
+def test_complete_digraph(n):
+    """K_n: every acyclic path can close, so PPs = simple cycles; with
+    rotations counted there are n!/(n-k)! of length k (k = 2..n)."""
+    pp, st, _, _ = _pp(cfggen.complete_digraph(n))
+    want = sum(math.factorial(n) // math.factorial(n - k) for k in range(2, n + 1))
+    assert len(pp) == want
+    assert all(p[0] == p[-1] for p in pp.tolist())
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 9])
+def test_cycle_graph(n):
+    """C_n: the n rotations of the one cycle; n(n-1) acyclic extensions plus
+    n closures."""
+    pp, st, _, _ = _pp(cfggen.cycle_graph(n))
+    assert len(pp) == n
+    assert st["n_extensions"] == n * n
+    assert sorted(pp.tolist()) == sorted([[(s + i) % n for i in range(n + 1)] for s in range(n)])
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 30])
+def test_path_graph(n):
+    """P_n: one PP (the whole path); n(n-1)/2 extensions."""
+    pp, st, _, _ = _pp(cfggen.path_graph(n))
+    assert pp.tolist() == [list(range(n))]
+    assert st["n_extensions"] == n * (n - 1) // 2
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 10])
+def test_diamond_chain(k):
+    """A DAG's PPs are its source-to-sink paths: 2^k here, and every TP is
+    its own PP (empty prefix and suffix)."""
+    g = cfggen.diamond_chain(k)
+    pp, _, _, _ = _pp(g)
+    assert len(pp) == 2 ** k
+    assert all(p[0] == g.entry and p[-1] == g.exit for p in pp.tolist())
+    tp, nb = oracle.test_paths(g, pp)
+    assert tp.tolist() == pp.tolist() and nb == 2 ** k
+
+
+@pytest.mark.parametrize("k", list(range(1, 12)))
+def test_loop_around_diamond_chain(k):
+    """while { k diamonds, last with a join } : counted by hand,
+    cycles 2^k (2k+2 rotations each) + entry paths 2^k + 1 + paths from the
+    first condition 2^k + paths from each arm k 2^k  = (3k+4) 2^k + 1."""
+    st, _, _ = oracle.count(cfggen.loop_diamond_chain(k))
+    assert st["n_pp"] == (3 * k + 4) * 2 ** k + 1
+    assert st["n_cycles"] == (2 * k + 2) * 2 ** k
+
+
+# --- brute force straight from the definitions ----------------------------
+
+def _graphs_small():
+    gs = []
+    for s in range(120):
+        n = 2 + s % 7
+        gs.append(cfggen.random_digraph(s, n, 0.15 + 0.05 * (s % 6)))
+    for s in range(80):
+        gs.append(cfggen.random_small_cfg(1000 + s, 3 + s % 9, extra=1 + s % 5))
+    gs += [cfggen.fig1_cfg(), cfggen.c1_cfg(0), cfggen.c1_cfg(3)]
+    return gs
+
+
+def test_bruteforce_agreement():
+    """PPs by DFS + prune pass == PPs by brute-force subsumption over all
+    simple paths; level and cycle counts == brute-force counts by length."""
+    for g in _graphs_small():
+        pp, st, lv, cy = _pp(g)
+        bf, allp = oracle.bruteforce_pp(g)
+        assert pp.tolist() == bf.tolist(), g.name
+        assert st["n_pp"] == st["n_pp_local"], g.name
+        blv = np.zeros_like(lv)
+        bcy = np.zeros_like(cy)
+        for p in allp.tolist():
+            if len(p) > 1 and p[0] == p[-1]:
+                bcy[len(p)] += 1
+            else:
+                blv[len(p)] += 1
+        assert (blv == lv).all() and (bcy == cy).all(), g.name
+        assert st["n_extensions"] == len(allp) - g.n
+
+
+def test_local_rule_agrees_with_prune_pass_on_workloads():
+    for g in [cfggen.c2_cfg(s["seed"]) for s in workloads()["c2"][:2]]:
+        pp, st, _, _ = _pp(g)
+        assert st["n_pp"] == st["n_pp_local"]
+        loc, _ = oracle.prime_paths_local(g, 0, g.n)
+        assert np.array_equal(loc.offsets, pp.offsets)
+        assert np.array_equal(loc.vertices, pp.vertices)
+
+
+def test_local_rule_chunks_concatenate():
+    g = cfggen.c1_cfg(5)
+    pp, _, _, _ = _pp(g)
+    parts = [oracle.prime_paths_local(g, lo, lo + 3)[0].tolist() for lo in range(0, g.n, 3)]
+    assert sum(parts, []) == pp.tolist()
+
+
+# --- invariants ---------------------------------------------------------------
+
+def _is_simple_or_cycle(p):
+    body = p[:-1] if len(p) > 1 and p[0] == p[-1] else p
+    return len(set(body)) == len(body)
+
+
+def _check_pp_invariants(g, pp: PathList):
+    lst = pp.tolist()
+    assert lst == sorted(lst)
+    assert len(set(map(tuple, lst))) == len(lst)
+    arcs = set(g.edges())
+    subs = set()
+    for p in lst:
+        assert _is_simple_or_cycle(p)
+        assert all((a, b) in arcs for a, b in zip(p, p[1:]))
+        for i in range(len(p)):
+            for j in range(i + 1, len(p) + 1):
+                if j - i < len(p):
+                    subs.add(tuple(p[i:j]))
+    assert not any(tuple(p) in subs for p in lst), "a PP is a proper subpath of another"
+
+
+def _check_tp_invariants(g, pp: PathList, tp: PathList):
+    arcs = set(g.edges())
+    tl = tp.tolist()
+    assert tl == sorted(tl) and len(set(map(tuple, tl))) == len(tl)
+    for t in tl:
+        assert t[0] == g.entry and t[-1] == g.exit
+        assert all((a, b) in arcs for a, b in zip(t, t[1:]))
+    # every PP is covered by some TP (as a contiguous subpath)
+    def contains(t, p):
+        return any(t[i:i + len(p)] == p for i in range(len(t) - len(p) + 1))
+    for p in pp.tolist():
+        assert any(contains(t, p) for t in tl)
+
+
+def test_invariants_c1_and_seeds():
+    for g in [cfggen.c1_cfg(s) for s in range(0, 17, 4)] + [cfggen.fig1_cfg()]:
+        pp, _, _, _ = _pp(g)
+        _check_pp_invariants(g, pp)
+        tp, _ = oracle.test_paths(g, pp)
+        _check_tp_invariants(g, pp, tp)
+
+
+def test_c1_relabel_invariance():
+    """Relabelling internal vertices permutes the PP set and keeps counts."""
+    base, st0, lv0, _ = _pp(cfggen.c1_cfg(0))
+    for s in range(1, 17):
+        pp, st, lv, _ = _pp(cfggen.c1_cfg(s))
+        assert len(pp) == len(base) and (lv == lv0).all()
+        assert st["n_extensions"] == st0["n_extensions"]
+
+
+def test_workload_counts_recorded():
+    w = workloads()
+    c1 = w["c1"]
+    _, st, lv, _ = _pp(cfggen.c1_cfg(0))
+    assert c1["n_pp"] == st["n_pp"] and c1["levels"] == [int(x) for x in lv[1:len(c1["levels"]) + 1]]
+    for rec in w["c2"][:2]:
+        g = cfggen.c2_cfg(rec["seed"])
+        st, _, _ = oracle.count(g)
+        assert st["n_pp"] == rec["n_pp"] and st["n_extensions"] == rec["n_extensions"]
+        assert cfggen.c2_shape_ok(g)
+
+
+# --- BFS tie-break --------------------------------------------------------------
+
+def test_bfs_prefix_suffix_lexmin_shortest():
+    """FIFO BFS with ascending successors gives the lexicographically smallest
+    shortest entry->v path; greedy next[] gives the smallest shortest v->exit
+    path; both checked against exhaustive search over all shortest paths."""
+    gs = [cfggen.random_small_cfg(2000 + s, 4 + s % 9, extra=2 + s % 6) for s in range(60)]
+    gs += [cfggen.fig1_cfg(), cfggen.c1_cfg(0), cfggen.c1_cfg(7)]
+    for g in gs:
+        t = oracle.bfs_tables(g)
+        for v in range(g.n):
+            pre = [v]
+            while pre[-1] != g.entry:
+                pre.append(int(t["parent"][pre[-1]]))
+            pre.reverse()
+            assert pre == oracle.bruteforce_lexmin_shortest(g, g.entry, v)
+            suf = [v]
+            while suf[-1] != g.exit:
+                suf.append(int(t["next"][suf[-1]]))
+            assert suf == oracle.bruteforce_lexmin_shortest(g, v, g.exit)
+
+
+def test_fig1_test_paths_by_definition():
+    """TPs of Fig. 1 rebuilt directly from brute-force shortest paths."""
+    g = cfggen.fig1_cfg()
+    pp, _, _, _ = _pp(g)
+    want = set()
+    for p in pp.tolist():
+        pre = oracle.bruteforce_lexmin_shortest(g, g.entry, p[0])
+        suf = oracle.bruteforce_lexmin_shortest(g, p[-1], g.exit)
+        want.add(tuple(pre[:-1] + p + suf[1:]))
+    tp, nb = oracle.test_paths(g, pp)
+    assert nb == 19 and tp.tolist() == sorted(list(x) for x in want)
+    assert len(tp) == 10
+
+
+def test_single_vertex_graph():
+    g = cfggen.from_edges(1, [], 0, 0)
+    pp, _, _, _ = _pp(g)
+    assert pp.tolist() == [[0]]
+    tp, _ = oracle.test_paths(g, pp)
+    assert tp.tolist() == [[0]]
+
+
+def test_self_loop_is_a_prime_path():
+    g = cfggen.from_edges(3, [(0, 1), (1, 1), (1, 2)], 0, 2)
+    pp, _, _, _ = _pp(g)
+    assert pp.tolist() == oracle.bruteforce_pp(g)[0].tolist()
+    assert [1, 1] in pp.tolist()
