@@ -1,0 +1,145 @@
+"""Benchmark: exact prime paths + test paths of one ~200-vertex structured CFG
+on one MI355X.
+
+One step = one pass of the whole hot path on the GPU: level-synchronous
+extension of simple paths from every vertex, backward-extendability filter,
+canonical ordering and materialization of the prime paths, BFS tables, splice
+of every prime path into a test path, sort and deduplication.  The input CSR
+is resident in HBM before timing starts and results stay in HBM.
+
+Prints one JSON line (see the fields below).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "prime paths/s + path-extensions/s, exact; batched+learned vs plain on 1 GPU"
+
+
+def _workload():
+    from paper_2210_16998_amd import cfggen
+    with open(os.path.join(ROOT, "tests", "golden", "workloads.json")) as f:
+        w = json.load(f)
+    rec = max(w["c2"], key=lambda r: r["n_pp"])
+    return cfggen.c2_cfg(rec["seed"]), rec
+
+
+def _cpu_baseline(g, reps: int):
+    """The CPU oracle on the same graph (DFS enumeration from every vertex,
+    local-rule prime test, splice + sort + dedup of test paths)."""
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    n_pp = 0
+    for _ in range(reps):
+        pp, st = oracle.prime_paths_local(g, 0, g.n, nthreads=threads)
+        tp, _ = oracle.test_paths(g, pp)
+        n_pp += len(pp)
+    dt = time.perf_counter() - t0
+    return {"value": n_pp / dt, "unit": "prime paths/s", "cores": threads, "kind": "oracle",
+            "sample": f"whole workload x{reps}: DFS from all {g.n} vertices with the local "
+                      f"prime test, then test-path splice/sort/dedup; {dt:.1f} s total"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-reps", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is "
+              f"single-GPU in this build", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2210_16998_amd import tpg
+
+    assert torch.cuda.is_available(), "no GPU"
+    torch.cuda.set_device(0)
+    g, rec = _workload()
+    ws = tpg.Workspace(0)
+    h = tpg.load_cfg(g)
+    stream = torch.cuda.Stream()
+    flags = tpg.TPG_OUT_DEVICE
+
+    def step(f=flags):
+        return tpg.test_paths(h, ws=ws, flags=f, stream=stream, want_pp=True)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pp, tp, st = step(flags | tpg.TPG_NO_TIMING)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = 1000.0 * dt / args.steps
+
+    # per-kernel timing run (HIP events on the library's stream, same launches)
+    pp, tp, st = step()
+    n_pp, n_ext = st["n_pp"], st["n_extensions"]
+    W = 1
+    while W * 64 < g.n:
+        W *= 2
+    bytes_per_ext = 16 + 2 * 8 * W
+    k_ms = st["ms_extend_kernel"]
+    achieved = (n_ext * bytes_per_ext) / (k_ms * 1e-3) / 1e9 if k_ms > 0 else 0.0
+
+    # plain per-CFG two-pass form, same graph, for context
+    for _ in range(2):
+        step(flags | tpg.TPG_FORCE_TWO_PASS)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    reps2 = max(3, args.steps // 4)
+    for _ in range(reps2):
+        step(flags | tpg.TPG_FORCE_TWO_PASS | tpg.TPG_NO_TIMING)
+    torch.cuda.synchronize()
+    ms_plain = 1000.0 * (time.perf_counter() - t1) / reps2
+
+    out = {
+        "metric": METRIC,
+        "value": n_pp / (ms * 1e-3),
+        "unit": "prime paths/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"single structured CFG, {g.n} vertices, {g.n_edges} arcs, "
+                               f"cyclomatic {g.cyclomatic}, seed {rec['seed']} (prime + test paths)",
+                   "n_pp": n_pp, "n_extensions": n_ext, "n_tp": st["n_tp"],
+                   "levels": st["n_levels"]},
+        "extensions_per_s": n_ext / (ms * 1e-3),
+        "test_paths_per_s": st["n_tp"] / (ms * 1e-3),
+        "phase_ms": {"extend": st["ms_extend"], "rank_materialize": st["ms_rank"],
+                     "test_paths": st["ms_tp"], "total_device": st["ms_total"]},
+        "plain_two_pass_ms_per_step": ms_plain,
+        "roofline": {"bound": "hbm", "kernel": "k_extend", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_extension": bytes_per_ext,
+                     "launches": st["n_extend_launches"],
+                     "avg_launch_ms": k_ms / max(1, st["n_extend_launches"])},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = _cpu_baseline(g, args.cpu_reps)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

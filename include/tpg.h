@@ -1,0 +1,194 @@
+/* tpg.h - prime-path and test-path generation on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libtpg.so.  Plain pointers and sizes only.
+ *
+ * Problem (the paper's Problem 1, Sec. 3): given a control-flow graph
+ * G = (V, E) with a start vertex s and an end vertex e, produce every prime
+ * path of G and a set of test paths that covers every prime path.
+ *
+ *  - A simple path is a vertex sequence v1..vk (k > 0) along arcs in which no
+ *    vertex repeats, except that v1 = vk is allowed (Sec. 2).
+ *  - A prime path (PP) is a simple path that is not a proper contiguous
+ *    subpath of any other simple path (Def. 1).
+ *  - A test path (TP) runs from the entry to the exit and contains a prime
+ *    path; here TP(p) = (lexicographically smallest shortest entry->v1 path,
+ *    without v1) ++ p ++ (lexicographically smallest shortest vk->exit path,
+ *    without vk)  (Sec. 6.3: every prime path is extended to the initial and
+ *    final nodes).  Duplicate TPs are removed.
+ *  - Every returned path set is in canonical order: lexicographic on the
+ *    int32 vertex ids.  Path sets are returned as CSR-like arrays:
+ *    offsets[n_paths + 1] (int64, offsets[0] = 0) into vertices[] (int32).
+ *
+ * Error behaviour: every function returns a tpg_status; on failure outputs
+ * are left empty (pointers NULL, counts 0) and nothing needs freeing.  A
+ * human-readable message for the last failure on the calling thread is
+ * available from tpg_last_error().
+ *
+ * Threading: a tpg_graph is immutable after loading and may be shared by
+ * threads.  A tpg_workspace serializes nothing by itself: use one workspace
+ * per concurrent caller (or per stream).
+ */
+#ifndef TPG_H_
+#define TPG_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TPG_VERSION_MAJOR 0
+#define TPG_VERSION_MINOR 1
+
+/* Largest vertex count the engine accepts (visited sets are bitmasks of up
+ * to 64 64-bit words) and largest out-degree (successor choice masks are one
+ * 64-bit word). */
+#define TPG_MAX_VERTICES 4096
+#define TPG_MAX_OUT_DEGREE 64
+
+typedef enum tpg_status {
+  TPG_OK = 0,
+  TPG_ERR_INVALID_ARG = -1,   /* NULL pointer, bad size, bad struct_size    */
+  TPG_ERR_BAD_CSR = -2,       /* row_ptr not 0-based/monotone, col out of range,
+                                 duplicate arcs under TPG_LOAD_STRICT        */
+  TPG_ERR_BAD_ENTRY_EXIT = -3,/* entry/exit out of range, in-deg(entry) != 0
+                                 or out-deg(exit) != 0 (Sec. 3 assumptions)   */
+  TPG_ERR_UNREACHABLE = -4,   /* a vertex is not reachable from the entry or
+                                 cannot reach the exit                        */
+  TPG_ERR_OOM_HOST = -5,
+  TPG_ERR_OOM_DEVICE = -6,
+  TPG_ERR_CAPACITY = -7,      /* would exceed opts.pool_cap_bytes            */
+  TPG_ERR_DEVICE = -8,        /* a HIP runtime call failed                   */
+  TPG_ERR_UNSUPPORTED = -9    /* > TPG_MAX_VERTICES vertices or out-degree
+                                 > TPG_MAX_OUT_DEGREE                        */
+} tpg_status;
+
+/* load_flags */
+#define TPG_LOAD_STRICT 0x1u          /* reject duplicate arcs instead of merging */
+#define TPG_LOAD_ANY_DIGRAPH 0x2u     /* skip the entry/exit degree and reachability
+                                         checks (prime paths of any digraph; test
+                                         paths then need those checks to hold)   */
+
+/* opts.flags */
+#define TPG_OUT_DEVICE 0x1u     /* results stay in device memory owned by the
+                                   workspace, valid until the next call on it */
+#define TPG_FORCE_TWO_PASS 0x2u /* plain form: per level count -> scan -> host
+                                   reads the size -> fill (no device-side sizing) */
+#define TPG_NO_TIMING 0x4u      /* skip per-phase event timing in tpg_stats     */
+
+typedef struct tpg_graph tpg_graph;         /* opaque, host memory */
+typedef struct tpg_workspace tpg_workspace; /* opaque: device arena + stream */
+
+typedef struct tpg_paths {
+  int64_t n_paths;
+  int64_t n_vertices;
+  int64_t* offsets;  /* [n_paths + 1] */
+  int32_t* vertices; /* [n_vertices]  */
+  int32_t on_device; /* 1: device pointers (TPG_OUT_DEVICE) owned by the
+                        workspace; 0: host memory owned by the library     */
+  int32_t reserved_;
+} tpg_paths;
+
+typedef struct tpg_stats {
+  int64_t n_levels;       /* deepest level (path entries) that held a path   */
+  int64_t n_nodes;        /* simple paths enumerated (all levels)            */
+  int64_t n_extensions;   /* simple paths with >= 2 entries, cycles included */
+  int64_t n_cycles;       /* closed simple cycles (all are prime)            */
+  int64_t n_pp;
+  int64_t n_pp_vertices;
+  int64_t n_tp_spliced;   /* test paths before deduplication                 */
+  int64_t n_tp;
+  int64_t n_tp_vertices;
+  int64_t n_overflows;    /* device-sized levels that overflowed and were grown */
+  int64_t device_bytes;   /* workspace device memory in use                  */
+  double ms_extend;       /* frontier extension + filter (all levels)        */
+  double ms_rank;         /* canonical-order ranking + PP materialization    */
+  double ms_tp;           /* BFS tables + splice + sort + dedup              */
+  double ms_total;        /* device time of the whole call                   */
+  double ms_extend_kernel;/* summed duration of the extension kernel launches */
+  int64_t n_extend_launches;
+} tpg_stats;
+
+typedef struct tpg_opts {
+  uint32_t struct_size;     /* sizeof(tpg_opts)                             */
+  uint32_t flags;           /* TPG_OUT_DEVICE | TPG_FORCE_TWO_PASS | ...     */
+  void* stream;             /* hipStream_t to run on; NULL: the workspace's  */
+  tpg_workspace* ws;        /* NULL: a temporary workspace for this call     */
+  uint64_t pool_cap_bytes;  /* 0: no cap                                    */
+  tpg_stats* stats;         /* optional                                     */
+  int64_t* level_counts;    /* optional: level_counts[L] = acyclic paths with
+                               L vertices, L = 0 .. level_counts_len-1      */
+  int32_t level_counts_len;
+  int32_t reserved_;
+} tpg_opts;
+
+/* ------------------------------------------------------------------------
+ * Loading (host only; no device is touched).
+ *
+ * n vertices 0..n-1; arcs of vertex v are col_idx[row_ptr[v] .. row_ptr[v+1]).
+ * row_ptr has n+1 entries with row_ptr[0] = 0 and is non-decreasing; rows need
+ * not be sorted.  Duplicate arcs are merged (rejected under TPG_LOAD_STRICT);
+ * self-loops are allowed.  Checks (Sec. 3 assumptions): in-deg(entry) = 0,
+ * out-deg(exit) = 0, and every vertex reachable from entry and reaching exit.
+ * The inputs are copied; the caller keeps ownership.  On success *out is a
+ * new handle to release with tpg_graph_free; on error *out = NULL.
+ * ---------------------------------------------------------------------- */
+tpg_status tpg_load_cfg_csr(int32_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                            int32_t entry, int32_t exit, uint32_t load_flags,
+                            tpg_graph** out);
+void tpg_graph_free(tpg_graph* g);
+/* Vertex count, canonical arc count, entry, exit of a loaded graph. */
+tpg_status tpg_graph_info(const tpg_graph* g, int32_t* n, int64_t* n_arcs, int32_t* entry,
+                          int32_t* exit);
+/* Canonical CSR (rows sorted, duplicates merged) copied into caller buffers of
+ * n+1 and n_arcs entries. */
+tpg_status tpg_graph_csr(const tpg_graph* g, int64_t* row_ptr, int32_t* col_idx);
+
+/* ------------------------------------------------------------------------
+ * Workspaces: a device arena that grows on demand and is reused across
+ * calls (no device allocation once it is large enough), plus a stream.
+ * device < 0 selects the current device.
+ * ---------------------------------------------------------------------- */
+tpg_status tpg_workspace_create(int32_t device, tpg_workspace** out);
+void tpg_workspace_free(tpg_workspace* ws);
+/* Device memory currently held by the workspace. */
+int64_t tpg_workspace_bytes(const tpg_workspace* ws);
+
+/* ------------------------------------------------------------------------
+ * Prime paths (Def. 1) of a loaded graph, in canonical order.
+ *
+ * Level-synchronous extension of simple paths from every vertex (level L =
+ * paths of L entries; a path is extended by each successor that is not on it,
+ * and closes a cycle when the successor is its first vertex - the extension
+ * rule of the paper's Update-Vertex / ExtendPath, Sec. 5); a path that cannot
+ * be extended is prime iff it cannot be extended backward either (every
+ * predecessor of its first vertex is on it); every closed cycle is prime.
+ * opts may be NULL (defaults).  *out receives the set (see tpg_paths).
+ * ---------------------------------------------------------------------- */
+tpg_status tpg_prime_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* out);
+
+/* ------------------------------------------------------------------------
+ * Test paths covering every prime path (Problem 1 output; Sec. 6.3).
+ * If pp_out is non-NULL it also receives the prime paths.  tp_out receives
+ * the deduplicated test paths in canonical order.  Requires the entry/exit
+ * checks of tpg_load_cfg_csr to hold (else TPG_ERR_UNREACHABLE).
+ * ---------------------------------------------------------------------- */
+tpg_status tpg_test_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* pp_out,
+                          tpg_paths* tp_out);
+
+/* Releases host results; device results (on_device = 1) are owned by the
+ * workspace and this only clears the struct. */
+void tpg_paths_free(tpg_paths* p);
+
+/* ------------------------------------------------------------------------
+ * Misc.
+ * ---------------------------------------------------------------------- */
+const char* tpg_status_str(tpg_status s);
+const char* tpg_last_error(void);       /* thread-local, never NULL */
+const char* tpg_version(void);
+int32_t tpg_device_count(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TPG_H_ */

@@ -1,0 +1,118 @@
+// Device-side building blocks shared by the kernels of libtpg (gfx950,
+// wave64): node encoding, wave/block scans, decoupled look-back, visited-set
+// bit tests.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace tpg {
+
+constexpr int kBlock = 256;  // threads per workgroup for path kernels (4 waves)
+
+// A path-tree node is stored as two 32-bit words:
+//   par  : global index of the parent node (-1 for a single-vertex path)
+//   info : last vertex (bits 0-11) | first vertex (bits 12-23) | flags
+constexpr uint32_t kVMask = 0xFFFu;
+constexpr uint32_t F_CYC = 1u << 24;   // closes a cycle (last vertex = first)
+constexpr uint32_t F_PP = 1u << 25;    // prime path leaf (set on terminal nodes)
+constexpr uint32_t F_TERM = 1u << 26;  // acyclic, cannot be extended forward
+
+__device__ __forceinline__ int node_v(uint32_t info) { return (int)(info & kVMask); }
+__device__ __forceinline__ int node_v1(uint32_t info) { return (int)((info >> 12) & kVMask); }
+__device__ __forceinline__ uint32_t make_info(int v, int v1, uint32_t flags) {
+  return (uint32_t)v | ((uint32_t)v1 << 12) | flags;
+}
+
+struct DGraph {
+  const int32_t* sp;  // successor row pointers [n+1]
+  const int32_t* s;   // successors, ascending per row
+  const int32_t* pp;  // predecessor row pointers [n+1]
+  const int32_t* p;   // predecessors
+  int32_t n, entry, exit, pad;
+};
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+template <class T>
+__device__ __forceinline__ T wave_incl_scan(T x) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    T y = __shfl_up(x, d, 64);
+    if (lane_id() >= d) x += y;
+  }
+  return x;
+}
+
+// Exclusive scan across a workgroup of NT threads; s_w needs NT/64 slots.
+template <int NT, class T>
+__device__ __forceinline__ T block_excl_scan(T x, T& total, T* s_w) {
+  T inc = wave_incl_scan(x);
+  const int w = (int)(threadIdx.x >> 6);
+  if (lane_id() == 63) s_w[w] = inc;
+  __syncthreads();
+  T pre = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) {
+    T v = s_w[i];
+    pre += (i < w) ? v : (T)0;
+    tot += v;
+  }
+  __syncthreads();
+  total = tot;
+  return pre + inc - x;
+}
+
+// Decoupled look-back (single-pass chained scan).  Each tile publishes its
+// aggregate, then walks back over its predecessors until it finds one with an
+// inclusive prefix.  Flag and value share one 64-bit word, so relaxed atomics
+// suffice.  Tiles are numbered in the order workgroups acquired them from an
+// atomic counter, so every predecessor is already running: the wait ends.
+constexpr uint64_t kStA = 1ull << 62;
+constexpr uint64_t kStP = 2ull << 62;
+constexpr uint64_t kStVal = (1ull << 62) - 1;
+
+__device__ __forceinline__ int64_t lookback_prefix(uint64_t* status, int64_t tile, int64_t agg) {
+  if (tile == 0) {
+    __hip_atomic_store(&status[0], kStP | (uint64_t)agg, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    return 0;
+  }
+  __hip_atomic_store(&status[tile], kStA | (uint64_t)agg, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  int64_t excl = 0;
+  int64_t j = tile - 1;
+  for (;;) {
+    const uint64_t s = __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t f = s & ~kStVal;
+    if (f == 0) {
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    excl += (int64_t)(s & kStVal);
+    if (f == kStP) break;
+    --j;
+  }
+  __hip_atomic_store(&status[tile], kStP | (uint64_t)(excl + agg), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  return excl;
+}
+
+// Visited-set bit test on a register-resident mask of W 64-bit words.
+template <int W>
+__device__ __forceinline__ bool mask_has(const uint64_t (&m)[W], int w) {
+  const int q = w >> 6;
+  uint64_t word = 0;
+#pragma unroll
+  for (int k = 0; k < W; ++k) word = (k == q) ? m[k] : word;
+  return (word >> (w & 63)) & 1ull;
+}
+
+// r-th set bit (0-based) of x; x has more than r set bits.
+__device__ __forceinline__ int select_bit(uint64_t x, int r) {
+  for (int i = 0; i < r; ++i) x &= x - 1;
+  return __builtin_ctzll(x);
+}
+
+}  // namespace tpg

@@ -1,0 +1,700 @@
+// Host orchestration of the single-graph pipeline: workspace (grow-only
+// device arena + stream), level loop, ranking, materialization, test paths.
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+using namespace tpg;
+
+struct tpg_workspace {
+  int device = 0;
+  hipStream_t own_stream = nullptr;
+  int num_cus = 256;
+  size_t bytes = 0;
+  uint64_t cap = 0;  // pool cap of the running call (0: none)
+
+  // graph cache
+  uint64_t graph_uid = 0;
+  DevBuf g_csr;
+  DGraph dg{};
+
+  // path tree
+  DevBuf par, info, cstart, mask0, mask1, tile_status, tile_ctr, ls;
+  int64_t rec_cap = 0, mask_cap = 0, max_tiles = 0;
+  int mask_words = 0;
+  // ranking
+  DevBuf sub_cnt, sub_len, leaf_by_rank, totals, cycles;
+  DevBuf pp_off, pp_vtx;
+  // scans
+  DevBuf scan_status, scan_ctr, scalars;
+  // test paths
+  DevBuf bfs_i32, pfx_off, sfx_off, pfx, sfx;
+  DevBuf tp_len, tp_off, tp_vtx, idx0, idx1, grp_cnt, rb0, rb1;
+  DevBuf keep_cnt, keep_len, keep_pos, keep_voff, out_off, out_vtx;
+
+  // pinned host mirrors
+  LevelState* h_ls = nullptr;
+  int64_t* h_scalars = nullptr;
+
+  std::vector<hipEvent_t> ev_pool;
+};
+
+namespace {
+
+tpg_status ws_reserve(tpg_workspace* ws, DevBuf& b, size_t bytes, bool keep = false,
+                      hipStream_t st = nullptr, size_t keep_bytes = 0) {
+  if (bytes == 0) bytes = 16;
+  if (b.cap >= bytes) return TPG_OK;
+  size_t want = std::max(bytes, b.cap + b.cap / 2);
+  want = (want + 255) & ~(size_t)255;
+  if (ws->cap && ws->bytes - b.cap + want > ws->cap) {
+    want = bytes;
+    if (ws->bytes - b.cap + want > ws->cap)
+      return fail(TPG_ERR_CAPACITY, "device pool would need %zu bytes (cap %llu)",
+                  ws->bytes - b.cap + want, (unsigned long long)ws->cap);
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(TPG_ERR_OOM_DEVICE, "hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
+  }
+  if (keep && b.p && keep_bytes) {
+    TPG_HIP(hipMemcpyAsync(p, b.p, std::min(keep_bytes, b.cap), hipMemcpyDeviceToDevice, st));
+    TPG_HIP(hipStreamSynchronize(st));
+  }
+  if (b.p) {
+    TPG_HIP(hipFree(b.p));
+    ws->bytes -= b.cap;
+  }
+  b.p = p;
+  b.cap = want;
+  ws->bytes += want;
+  return TPG_OK;
+}
+
+void ws_release(tpg_workspace* ws, DevBuf& b) {
+  if (b.p) {
+    (void)hipFree(b.p);
+    ws->bytes -= b.cap;
+  }
+  b.p = nullptr;
+  b.cap = 0;
+}
+
+int pow2_words(int n) {
+  int w = (n + 63) / 64;
+  int p = 1;
+  while (p < w) p <<= 1;
+  return p;
+}
+
+tpg_status upload_graph(tpg_workspace* ws, const tpg_graph* g, hipStream_t st) {
+  if (ws->graph_uid == g->uid) return TPG_OK;
+  const size_t n1 = (size_t)g->n + 1, m = g->succ.size();
+  const size_t bytes = sizeof(int32_t) * (2 * n1 + 2 * m + 4);
+  TPG_TRY(ws_reserve(ws, ws->g_csr, bytes));
+  int32_t* base = ws->g_csr.as<int32_t>();
+  int32_t* sp = base;
+  int32_t* s = sp + n1;
+  int32_t* pp = s + m + 1;
+  int32_t* p = pp + n1;
+  TPG_HIP(hipMemcpyAsync(sp, g->succ_ptr.data(), sizeof(int32_t) * n1, hipMemcpyHostToDevice, st));
+  if (m) TPG_HIP(hipMemcpyAsync(s, g->succ.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
+  TPG_HIP(hipMemcpyAsync(pp, g->pred_ptr.data(), sizeof(int32_t) * n1, hipMemcpyHostToDevice, st));
+  if (m) TPG_HIP(hipMemcpyAsync(p, g->pred.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
+  TPG_HIP(hipStreamSynchronize(st));
+  ws->dg.sp = sp;
+  ws->dg.s = s;
+  ws->dg.pp = pp;
+  ws->dg.p = p;
+  ws->dg.n = g->n;
+  ws->dg.entry = g->entry;
+  ws->dg.exit = g->exit;
+  ws->graph_uid = g->uid;
+  return TPG_OK;
+}
+
+tpg_status reserve_tree(tpg_workspace* ws, int64_t rec, int64_t msk, int W, hipStream_t st,
+                        int64_t keep_rec, int keep_parity, int64_t keep_mask) {
+  if (rec > (int64_t)INT32_MAX - 2)
+    return fail(TPG_ERR_UNSUPPORTED, "more than 2^31 simple paths in one graph");
+  TPG_TRY(ws_reserve(ws, ws->par, sizeof(int32_t) * rec, keep_rec > 0, st, sizeof(int32_t) * keep_rec));
+  TPG_TRY(ws_reserve(ws, ws->info, sizeof(uint32_t) * rec, keep_rec > 0, st, sizeof(uint32_t) * keep_rec));
+  TPG_TRY(ws_reserve(ws, ws->cstart, sizeof(int32_t) * (rec + 1), keep_rec > 0, st,
+                     sizeof(int32_t) * (keep_rec + 1)));
+  ws->rec_cap = std::min<int64_t>(ws->par.cap / sizeof(int32_t), ws->cstart.cap / sizeof(int32_t) - 1);
+  ws->rec_cap = std::min<int64_t>(ws->rec_cap, ws->info.cap / sizeof(uint32_t));
+  const size_t mb = sizeof(uint64_t) * (size_t)msk * W;
+  TPG_TRY(ws_reserve(ws, ws->mask0, mb, keep_parity == 0 && keep_mask > 0, st,
+                     sizeof(uint64_t) * (size_t)keep_mask * W));
+  TPG_TRY(ws_reserve(ws, ws->mask1, mb, keep_parity == 1 && keep_mask > 0, st,
+                     sizeof(uint64_t) * (size_t)keep_mask * W));
+  ws->mask_cap = (int64_t)(std::min(ws->mask0.cap, ws->mask1.cap) / (sizeof(uint64_t) * W));
+  ws->max_tiles = ws->mask_cap / kBlock + 2;
+  TPG_TRY(ws_reserve(ws, ws->tile_status, sizeof(uint64_t) * 2 * ws->max_tiles));
+  TPG_TRY(ws_reserve(ws, ws->tile_ctr, sizeof(uint32_t) * 4));
+  TPG_TRY(ws_reserve(ws, ws->ls, sizeof(LevelState)));
+  ws->mask_words = W;
+  return TPG_OK;
+}
+
+ExtArgs make_args(tpg_workspace* ws) {
+  ExtArgs a{};
+  a.g = ws->dg;
+  a.t.par = ws->par.as<int32_t>();
+  a.t.info = ws->info.as<uint32_t>();
+  a.t.cstart = ws->cstart.as<int32_t>();
+  a.t.mask[0] = ws->mask0.as<uint64_t>();
+  a.t.mask[1] = ws->mask1.as<uint64_t>();
+  a.t.rec_cap = ws->rec_cap;
+  a.t.mask_cap = ws->mask_cap;
+  a.t.mask_words = ws->mask_words;
+  a.ls = ws->ls.as<LevelState>();
+  a.tile_status[0] = ws->tile_status.as<uint64_t>();
+  a.tile_status[1] = ws->tile_status.as<uint64_t>() + ws->max_tiles;
+  a.tile_ctr = ws->tile_ctr.as<uint32_t>();
+  a.max_tiles = ws->max_tiles;
+  return a;
+}
+
+tpg_status reserve_scan(tpg_workspace* ws, int64_t n) {
+  TPG_TRY(ws_reserve(ws, ws->scan_status, sizeof(uint64_t) * (scan_tiles(n) + 2)));
+  TPG_TRY(ws_reserve(ws, ws->scan_ctr, sizeof(uint32_t) * 4));
+  TPG_TRY(ws_reserve(ws, ws->scalars, sizeof(int64_t) * 16));
+  return TPG_OK;
+}
+
+struct Timer {
+  tpg_workspace* ws;
+  hipStream_t st;
+  bool on;
+  std::vector<hipEvent_t> used;
+  size_t next = 0;
+  hipEvent_t mark() {
+    if (!on) return nullptr;
+    if (next >= ws->ev_pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ws->ev_pool.push_back(e);
+    }
+    hipEvent_t e = ws->ev_pool[next++];
+    (void)hipEventRecord(e, st);
+    return e;
+  }
+  static double ms(hipEvent_t a, hipEvent_t b) {
+    if (!a || !b) return 0.0;
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, a, b) != hipSuccess) return 0.0;
+    return (double)t;
+  }
+};
+
+struct TreeResult {
+  int Lmax = 0;  // deepest level holding nodes
+  std::vector<int64_t> count, off;
+  int64_t n_nodes = 0;
+  int64_t n_overflows = 0;
+  double ms_kernel = 0.0;
+  int64_t launches = 0;
+};
+
+// Level loop, one-pass device-sized form.
+tpg_status build_tree_onepass(tpg_workspace* ws, const tpg_graph* g, hipStream_t st, Timer& tm,
+                              TreeResult& R) {
+  const int W = pow2_words(g->n);
+  int64_t rec = std::max<int64_t>(ws->rec_cap, (int64_t)g->n * 64 + 4096);
+  int64_t msk = std::max<int64_t>(ws->mask_words == W ? ws->mask_cap : 0, (int64_t)g->n * 16 + 1024);
+  if (ws->mask_words && ws->mask_words != W && ws->mask_cap)
+    msk = std::max<int64_t>(msk, ws->mask_cap * ws->mask_words / W);
+  TPG_TRY(reserve_tree(ws, rec, msk, W, st, 0, -1, 0));
+  ExtArgs a = make_args(ws);
+  TPG_HIP(launch_seed(a, st));
+  const int grid = ws->num_cus * 8;
+  int batch = 4;
+  int level_before = 1;
+  for (;;) {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
+    for (int b = 0; b < batch; ++b) {
+      hipEvent_t e0 = tm.mark();
+      TPG_HIP(launch_extend(W, a, grid, st));
+      hipEvent_t e1 = tm.mark();
+      evs.emplace_back(e0, e1);
+    }
+    TPG_HIP(hipMemcpyAsync(ws->h_ls, ws->ls.p, 32, hipMemcpyDeviceToHost, st));
+    TPG_HIP(hipStreamSynchronize(st));
+    const LevelState& h = *ws->h_ls;
+    const int productive = h.level - level_before;
+    for (int i = 0; i < productive && i < (int)evs.size(); ++i) {
+      R.ms_kernel += Timer::ms(evs[i].first, evs[i].second);
+      R.launches += 1;
+    }
+    tm.next = 0;
+    level_before = h.level;
+    if (h.overflow) {
+      const int L = h.level;
+      int64_t hdr[2];
+      LevelState* dls = ws->ls.as<LevelState>();
+      TPG_HIP(hipMemcpy(&hdr[0], &dls->off[L], sizeof(int64_t), hipMemcpyDeviceToHost));
+      int64_t cnt[2];
+      TPG_HIP(hipMemcpy(cnt, &dls->count[L], 2 * sizeof(int64_t), hipMemcpyDeviceToHost));
+      const int64_t base = hdr[0], F = cnt[0], nxt = cnt[1];
+      const int64_t need_rec = base + F + nxt + 1;
+      const int64_t new_rec = std::max<int64_t>(ws->rec_cap, need_rec + need_rec / 4);
+      const int64_t new_msk = std::max<int64_t>(ws->mask_cap, nxt + nxt / 4 + 1024);
+      TPG_TRY(reserve_tree(ws, new_rec, new_msk, W, st, base + F, L & 1, F));
+      a = make_args(ws);
+      TPG_HIP(launch_resume_fix(a, L, st));
+      R.n_overflows += 1;
+      continue;
+    }
+    if (h.cur_count == 0) break;
+    batch = std::min(batch * 2, 64);
+  }
+  // level table
+  R.count.assign(kMaxLevels, 0);
+  R.off.assign(kMaxLevels, 0);
+  LevelState* dls = ws->ls.as<LevelState>();
+  TPG_HIP(hipMemcpy(ws->h_ls, dls, sizeof(LevelState), hipMemcpyDeviceToHost));
+  R.Lmax = ws->h_ls->level - 1;
+  for (int L = 0; L <= R.Lmax + 1; ++L) {
+    R.count[L] = ws->h_ls->count[L];
+    R.off[L] = ws->h_ls->off[L];
+  }
+  R.off[R.Lmax + 1] = R.off[R.Lmax] + R.count[R.Lmax];
+  R.n_nodes = R.off[R.Lmax + 1];
+  return TPG_OK;
+}
+
+// Level loop, plain two-pass form: count -> scan -> host reads the size -> fill.
+tpg_status build_tree_twopass(tpg_workspace* ws, const tpg_graph* g, hipStream_t st, Timer& tm,
+                              TreeResult& R) {
+  const int W = pow2_words(g->n);
+  int64_t rec = std::max<int64_t>(ws->rec_cap, (int64_t)g->n + 4096);
+  int64_t msk = std::max<int64_t>(ws->mask_words == W ? ws->mask_cap : 0, (int64_t)g->n + 1024);
+  TPG_TRY(reserve_tree(ws, rec, msk, W, st, 0, -1, 0));
+  ExtArgs a = make_args(ws);
+  TPG_HIP(launch_seed(a, st));
+  R.count.assign(kMaxLevels, 0);
+  R.off.assign(kMaxLevels, 0);
+  int L = 1;
+  int64_t base = 0, F = g->n;
+  R.count[1] = F;
+  for (;;) {
+    TPG_TRY(reserve_scan(ws, F));
+    hipEvent_t e0 = tm.mark();
+    TPG_HIP(launch_count(W, a, L, base, F, st));
+    int32_t* cs = ws->cstart.as<int32_t>() + base;
+    TPG_HIP(scan_i32_to_i32(cs, cs, F, base + F, ws->scalars.as<int64_t>(),
+                            ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
+    TPG_HIP(hipMemcpyAsync(ws->h_scalars, ws->scalars.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    TPG_HIP(hipStreamSynchronize(st));
+    const int64_t total = ws->h_scalars[0] - (base + F);
+    if (total == 0) {
+      hipEvent_t e1 = tm.mark();
+      R.ms_kernel += Timer::ms(e0, e1);
+      tm.next = 0;
+      break;
+    }
+    if (base + F + total + 1 > ws->rec_cap || total > ws->mask_cap) {
+      const int64_t need = base + F + total + 1;
+      TPG_TRY(reserve_tree(ws, std::max<int64_t>(ws->rec_cap, need + need / 2),
+                           std::max<int64_t>(ws->mask_cap, total + total / 2), W, st, base + F + 1,
+                           L & 1, F));
+      a = make_args(ws);
+    }
+    TPG_HIP(launch_fill(W, a, L, base, F, st));
+    hipEvent_t e1 = tm.mark();
+    TPG_HIP(hipStreamSynchronize(st));
+    R.ms_kernel += Timer::ms(e0, e1);
+    tm.next = 0;
+    R.launches += 1;
+    R.off[L + 1] = base + F;
+    R.count[L + 1] = total;
+    base += F;
+    F = total;
+    ++L;
+  }
+  R.Lmax = L;
+  R.off[L + 1] = base + F;
+  R.n_nodes = base + F;
+  return TPG_OK;
+}
+
+struct PPResult {
+  int64_t n_pp = 0, n_vtx = 0, n_cycles = 0;
+};
+
+tpg_status rank_and_materialize(tpg_workspace* ws, const tpg_graph* g, hipStream_t st,
+                                const TreeResult& R, PPResult& P) {
+  ExtArgs a = make_args(ws);
+  const int64_t N = R.n_nodes;
+  TPG_TRY(ws_reserve(ws, ws->sub_cnt, sizeof(uint32_t) * N));
+  TPG_TRY(ws_reserve(ws, ws->sub_len, sizeof(int64_t) * N));
+  TPG_TRY(ws_reserve(ws, ws->totals, sizeof(int64_t) * 4));
+  TPG_TRY(ws_reserve(ws, ws->cycles, sizeof(uint64_t) * 2));
+  TPG_HIP(launch_zero_u64(ws->cycles.as<uint64_t>(), 1, st));
+  for (int L = R.Lmax; L >= 1; --L)
+    TPG_HIP(launch_up(a, L, R.off[L], R.count[L], ws->sub_cnt.as<uint32_t>(),
+                      ws->sub_len.as<int64_t>(), ws->cycles.as<unsigned long long>(), st));
+  TPG_HIP(launch_roots(a, g->n, ws->sub_cnt.as<uint32_t>(), ws->sub_len.as<int64_t>(), nullptr,
+                       ws->totals.as<int64_t>(), 0, st));
+  TPG_HIP(hipMemcpyAsync(ws->h_scalars, ws->totals.p, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TPG_HIP(hipMemcpyAsync(ws->h_scalars + 2, ws->cycles.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TPG_HIP(hipStreamSynchronize(st));
+  P.n_pp = ws->h_scalars[0];
+  P.n_vtx = ws->h_scalars[1];
+  P.n_cycles = ws->h_scalars[2];
+  TPG_TRY(ws_reserve(ws, ws->leaf_by_rank, sizeof(int64_t) * (P.n_pp + 1)));
+  TPG_TRY(ws_reserve(ws, ws->pp_off, sizeof(int64_t) * (P.n_pp + 1)));
+  TPG_TRY(ws_reserve(ws, ws->pp_vtx, sizeof(int32_t) * (P.n_vtx + 1)));
+  TPG_HIP(launch_roots(a, g->n, ws->sub_cnt.as<uint32_t>(), ws->sub_len.as<int64_t>(),
+                       ws->leaf_by_rank.as<int64_t>(), ws->totals.as<int64_t>(), 1, st));
+  for (int L = 1; L < R.Lmax; ++L)
+    TPG_HIP(launch_down(a, R.off[L], R.count[L], ws->sub_cnt.as<uint32_t>(),
+                        ws->sub_len.as<int64_t>(), ws->leaf_by_rank.as<int64_t>(), st));
+  TPG_HIP(launch_pp_offsets(ws->leaf_by_rank.as<int64_t>(), ws->sub_len.as<int64_t>(), P.n_pp,
+                            P.n_vtx, ws->pp_off.as<int64_t>(), st));
+  TPG_HIP(launch_pp_write(a, ws->leaf_by_rank.as<int64_t>(), ws->pp_off.as<int64_t>(), P.n_pp,
+                          ws->pp_vtx.as<int32_t>(), st));
+  return TPG_OK;
+}
+
+struct TPResult {
+  int64_t n_spliced = 0, n_tp = 0, n_vtx = 0;
+};
+
+tpg_status test_paths_device(tpg_workspace* ws, const tpg_graph* g, hipStream_t st,
+                             const PPResult& P, TPResult& T) {
+  const int n = g->n;
+  TPG_TRY(ws_reserve(ws, ws->bfs_i32, sizeof(int32_t) * 4 * (size_t)n));
+  TPG_TRY(ws_reserve(ws, ws->pfx_off, sizeof(int64_t) * (n + 1)));
+  TPG_TRY(ws_reserve(ws, ws->sfx_off, sizeof(int64_t) * (n + 1)));
+  TPG_TRY(ws_reserve(ws, ws->pfx, sizeof(int32_t) * (size_t)n * n));
+  TPG_TRY(ws_reserve(ws, ws->sfx, sizeof(int32_t) * (size_t)n * n));
+  BfsOut b;
+  int32_t* bi = ws->bfs_i32.as<int32_t>();
+  b.dist_f = bi;
+  b.parent = bi + n;
+  b.dist_b = bi + 2 * n;
+  b.next = bi + 3 * n;
+  b.pfx_off = ws->pfx_off.as<int64_t>();
+  b.sfx_off = ws->sfx_off.as<int64_t>();
+  b.pfx = ws->pfx.as<int32_t>();
+  b.sfx = ws->sfx.as<int32_t>();
+  TPG_HIP(launch_bfs(ws->dg, b, st));
+
+  const int64_t np = P.n_pp;
+  T.n_spliced = np;
+  TPG_TRY(reserve_scan(ws, std::max<int64_t>(np, n)));
+  TPG_TRY(ws_reserve(ws, ws->tp_len, sizeof(int64_t) * (np + 1)));
+  TPG_TRY(ws_reserve(ws, ws->tp_off, sizeof(int64_t) * (np + 1)));
+  TPG_TRY(ws_reserve(ws, ws->grp_cnt, sizeof(int32_t) * (n + 1)));
+  TPG_TRY(ws_reserve(ws, ws->rb0, sizeof(int64_t) * (n + 2)));
+  TPG_TRY(ws_reserve(ws, ws->rb1, sizeof(int64_t) * (n + 2)));
+  TPG_TRY(ws_reserve(ws, ws->idx0, sizeof(int32_t) * (np + 1)));
+  TPG_TRY(ws_reserve(ws, ws->idx1, sizeof(int32_t) * (np + 1)));
+  TPG_HIP(launch_zero_u32(ws->grp_cnt.as<uint32_t>(), n, st));
+  TPG_HIP(launch_tp_len(ws->pp_off.as<int64_t>(), ws->pp_vtx.as<int32_t>(), np, b,
+                        ws->tp_len.as<int64_t>(), ws->grp_cnt.as<int32_t>(), st));
+  int64_t* sc = ws->scalars.as<int64_t>();
+  TPG_HIP(scan_i64(ws->tp_len.as<int64_t>(), ws->tp_off.as<int64_t>(), np, 0, sc,
+                   ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
+  TPG_HIP(scan_i32_to_i64(ws->grp_cnt.as<int32_t>(), ws->rb0.as<int64_t>(), n, 0, sc + 1,
+                          ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
+  TPG_HIP(hipMemcpyAsync(ws->h_scalars, sc, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TPG_HIP(hipStreamSynchronize(st));
+  const int64_t tp_total = ws->h_scalars[0];
+  TPG_TRY(ws_reserve(ws, ws->tp_vtx, sizeof(int32_t) * (tp_total + 1)));
+  TPG_HIP(launch_tp_write(ws->pp_off.as<int64_t>(), ws->pp_vtx.as<int32_t>(), np, b,
+                          ws->tp_off.as<int64_t>(), ws->tp_vtx.as<int32_t>(), ws->idx0.as<int32_t>(),
+                          st));
+  // merge the per-first-vertex runs
+  int64_t runs = n;
+  DevBuf* ri = &ws->rb0;
+  DevBuf* ro = &ws->rb1;
+  DevBuf* ii = &ws->idx0;
+  DevBuf* io = &ws->idx1;
+  while (runs > 1) {
+    TPG_HIP(launch_merge_round(ws->tp_off.as<int64_t>(), ws->tp_vtx.as<int32_t>(), ii->as<int32_t>(),
+                               io->as<int32_t>(), ri->as<int64_t>(), runs, np, st));
+    TPG_HIP(launch_next_runs(ri->as<int64_t>(), runs, ro->as<int64_t>(), st));
+    std::swap(ri, ro);
+    std::swap(ii, io);
+    runs = (runs + 1) / 2;
+  }
+  // dedup
+  TPG_TRY(ws_reserve(ws, ws->keep_cnt, sizeof(int64_t) * (np + 1)));
+  TPG_TRY(ws_reserve(ws, ws->keep_len, sizeof(int64_t) * (np + 1)));
+  TPG_TRY(ws_reserve(ws, ws->keep_pos, sizeof(int64_t) * (np + 1)));
+  TPG_TRY(ws_reserve(ws, ws->keep_voff, sizeof(int64_t) * (np + 1)));
+  TPG_HIP(launch_dedup_flags(ws->tp_off.as<int64_t>(), ws->tp_vtx.as<int32_t>(), ii->as<int32_t>(),
+                             np, ws->keep_cnt.as<int64_t>(), ws->keep_len.as<int64_t>(), st));
+  TPG_HIP(scan_i64(ws->keep_cnt.as<int64_t>(), ws->keep_pos.as<int64_t>(), np, 0, sc + 2,
+                   ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
+  TPG_HIP(scan_i64(ws->keep_len.as<int64_t>(), ws->keep_voff.as<int64_t>(), np, 0, sc + 3,
+                   ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
+  TPG_HIP(hipMemcpyAsync(ws->h_scalars + 2, sc + 2, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TPG_HIP(hipStreamSynchronize(st));
+  T.n_tp = ws->h_scalars[2];
+  T.n_vtx = ws->h_scalars[3];
+  TPG_TRY(ws_reserve(ws, ws->out_off, sizeof(int64_t) * (T.n_tp + 1)));
+  TPG_TRY(ws_reserve(ws, ws->out_vtx, sizeof(int32_t) * (T.n_vtx + 1)));
+  TPG_HIP(launch_gather(ws->tp_off.as<int64_t>(), ws->tp_vtx.as<int32_t>(), ii->as<int32_t>(), np,
+                        ws->keep_pos.as<int64_t>(), ws->keep_voff.as<int64_t>(),
+                        ws->keep_len.as<int64_t>(), ws->out_off.as<int64_t>(),
+                        ws->out_vtx.as<int32_t>(), st));
+  TPG_HIP(launch_set_i64(ws->out_off.as<int64_t>() + T.n_tp, sc + 3, st));
+  return TPG_OK;
+}
+
+tpg_status export_paths(const DevBuf& off, const DevBuf& vtx, int64_t n, int64_t nv, bool device,
+                        hipStream_t st, tpg_paths* out) {
+  memset(out, 0, sizeof *out);
+  out->n_paths = n;
+  out->n_vertices = nv;
+  if (device) {
+    out->on_device = 1;
+    out->offsets = off.as<int64_t>();
+    out->vertices = vtx.as<int32_t>();
+    return TPG_OK;
+  }
+  out->offsets = (int64_t*)malloc(sizeof(int64_t) * (n + 1));
+  out->vertices = (int32_t*)malloc(sizeof(int32_t) * (nv > 0 ? nv : 1));
+  if (!out->offsets || !out->vertices) {
+    free(out->offsets);
+    free(out->vertices);
+    memset(out, 0, sizeof *out);
+    return fail(TPG_ERR_OOM_HOST, "result arrays");
+  }
+  TPG_HIP(hipMemcpyAsync(out->offsets, off.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, st));
+  if (nv)
+    TPG_HIP(hipMemcpyAsync(out->vertices, vtx.p, sizeof(int32_t) * nv, hipMemcpyDeviceToHost, st));
+  TPG_HIP(hipStreamSynchronize(st));
+  return TPG_OK;
+}
+
+struct CallCtx {
+  tpg_workspace* ws = nullptr;
+  bool own_ws = false;
+  hipStream_t st = nullptr;
+  uint32_t flags = 0;
+  tpg_stats* stats = nullptr;
+  const tpg_opts* opts = nullptr;
+  ~CallCtx() {
+    if (own_ws && ws) tpg_workspace_free(ws);
+  }
+};
+
+tpg_status begin_call(const tpg_graph* g, const tpg_opts* opts, CallCtx& c) {
+  if (!g) return fail(TPG_ERR_INVALID_ARG, "graph is NULL");
+  if (opts && opts->struct_size != sizeof(tpg_opts))
+    return fail(TPG_ERR_INVALID_ARG, "opts.struct_size = %u, expected %zu", opts->struct_size,
+                sizeof(tpg_opts));
+  c.opts = opts;
+  c.flags = opts ? opts->flags : 0;
+  c.stats = opts ? opts->stats : nullptr;
+  if (opts && opts->ws) {
+    c.ws = opts->ws;
+  } else {
+    TPG_TRY(tpg_workspace_create(-1, &c.ws));
+    c.own_ws = true;
+  }
+  TPG_HIP(hipSetDevice(c.ws->device));
+  c.st = (opts && opts->stream) ? (hipStream_t)opts->stream : c.ws->own_stream;
+  c.ws->cap = opts ? opts->pool_cap_bytes : 0;
+  if (c.ws->cap && c.ws->bytes > c.ws->cap)
+    return fail(TPG_ERR_CAPACITY, "workspace already holds %zu bytes (cap %llu)", c.ws->bytes,
+                (unsigned long long)c.ws->cap);
+  TPG_TRY(upload_graph(c.ws, g, c.st));
+  return TPG_OK;
+}
+
+tpg_status run_pp(const tpg_graph* g, CallCtx& c, Timer& tm, TreeResult& R, PPResult& P,
+                  hipEvent_t* e_ext) {
+  if (c.flags & TPG_FORCE_TWO_PASS)
+    TPG_TRY(build_tree_twopass(c.ws, g, c.st, tm, R));
+  else
+    TPG_TRY(build_tree_onepass(c.ws, g, c.st, tm, R));
+  *e_ext = tm.mark();
+  TPG_TRY(rank_and_materialize(c.ws, g, c.st, R, P));
+  return TPG_OK;
+}
+
+void fill_stats(CallCtx& c, const tpg_graph* g, const TreeResult& R, const PPResult& P,
+                const TPResult* T) {
+  if (c.opts && c.opts->level_counts && c.opts->level_counts_len > 0) {
+    // acyclic paths per level: nodes minus the cycle closures of that level
+    // are not separated here; report node counts per level
+    for (int L = 0; L < c.opts->level_counts_len; ++L)
+      c.opts->level_counts[L] = (L < (int)R.count.size() && L <= R.Lmax) ? R.count[L] : 0;
+  }
+  if (!c.stats) return;
+  tpg_stats* s = c.stats;
+  s->n_levels = R.Lmax;
+  s->n_nodes = R.n_nodes;
+  s->n_extensions = R.n_nodes - g->n;
+  s->n_cycles = P.n_cycles;
+  s->n_pp = P.n_pp;
+  s->n_pp_vertices = P.n_vtx;
+  s->n_tp_spliced = T ? T->n_spliced : 0;
+  s->n_tp = T ? T->n_tp : 0;
+  s->n_tp_vertices = T ? T->n_vtx : 0;
+  s->n_overflows = R.n_overflows;
+  s->device_bytes = (int64_t)c.ws->bytes;
+  s->ms_extend_kernel = R.ms_kernel;
+  s->n_extend_launches = R.launches;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t tpg_device_count(void) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return n;
+}
+
+tpg_status tpg_workspace_create(int32_t device, tpg_workspace** out) {
+  if (!out) return fail(TPG_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev == 0) {
+    (void)hipGetLastError();
+    return fail(TPG_ERR_DEVICE, "no HIP device available");
+  }
+  if (device < 0) TPG_HIP(hipGetDevice(&device));
+  if (device >= ndev) return fail(TPG_ERR_INVALID_ARG, "device %d of %d", device, ndev);
+  tpg_workspace* ws = new (std::nothrow) tpg_workspace;
+  if (!ws) return fail(TPG_ERR_OOM_HOST, "workspace");
+  ws->device = device;
+  TPG_HIP(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) ws->num_cus = prop.multiProcessorCount;
+  if (hipStreamCreateWithFlags(&ws->own_stream, hipStreamNonBlocking) != hipSuccess) {
+    delete ws;
+    return fail(TPG_ERR_DEVICE, "hipStreamCreate failed");
+  }
+  if (hipHostMalloc((void**)&ws->h_ls, sizeof(LevelState), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&ws->h_scalars, sizeof(int64_t) * 16, hipHostMallocDefault) != hipSuccess) {
+    tpg_workspace_free(ws);
+    return fail(TPG_ERR_OOM_HOST, "pinned host buffers");
+  }
+  *out = ws;
+  return TPG_OK;
+}
+
+void tpg_workspace_free(tpg_workspace* ws) {
+  if (!ws) return;
+  (void)hipSetDevice(ws->device);
+  if (ws->own_stream) (void)hipStreamSynchronize(ws->own_stream);
+  DevBuf* bufs[] = {&ws->g_csr, &ws->par, &ws->info, &ws->cstart, &ws->mask0, &ws->mask1,
+                    &ws->tile_status, &ws->tile_ctr, &ws->ls, &ws->sub_cnt, &ws->sub_len,
+                    &ws->leaf_by_rank, &ws->totals, &ws->cycles, &ws->pp_off, &ws->pp_vtx,
+                    &ws->scan_status, &ws->scan_ctr, &ws->scalars, &ws->bfs_i32, &ws->pfx_off,
+                    &ws->sfx_off, &ws->pfx, &ws->sfx, &ws->tp_len, &ws->tp_off, &ws->tp_vtx,
+                    &ws->idx0, &ws->idx1, &ws->grp_cnt, &ws->rb0, &ws->rb1, &ws->keep_cnt,
+                    &ws->keep_len, &ws->keep_pos, &ws->keep_voff, &ws->out_off, &ws->out_vtx};
+  for (DevBuf* b : bufs) ws_release(ws, *b);
+  for (hipEvent_t e : ws->ev_pool) (void)hipEventDestroy(e);
+  if (ws->h_ls) (void)hipHostFree(ws->h_ls);
+  if (ws->h_scalars) (void)hipHostFree(ws->h_scalars);
+  if (ws->own_stream) (void)hipStreamDestroy(ws->own_stream);
+  delete ws;
+}
+
+int64_t tpg_workspace_bytes(const tpg_workspace* ws) { return ws ? (int64_t)ws->bytes : 0; }
+
+tpg_status tpg_prime_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* out) {
+  if (!out) return fail(TPG_ERR_INVALID_ARG, "out is NULL");
+  memset(out, 0, sizeof *out);
+  CallCtx c;
+  TPG_TRY(begin_call(g, opts, c));
+  Timer tm{c.ws, c.st, c.stats != nullptr && !(c.flags & TPG_NO_TIMING)};
+  const bool timing = tm.on;
+  std::vector<hipEvent_t> phase(2, nullptr);
+  if (timing) {
+    for (auto& e : phase) TPG_HIP(hipEventCreate(&e));
+    TPG_HIP(hipEventRecord(phase[0], c.st));
+  }
+  TreeResult R;
+  PPResult P;
+  hipEvent_t ext_done = nullptr;
+  tpg_status s = run_pp(g, c, tm, R, P, &ext_done);
+  if (s == TPG_OK && timing) TPG_HIP(hipEventRecord(phase[1], c.st));
+  if (s == TPG_OK)
+    s = export_paths(c.ws->pp_off, c.ws->pp_vtx, P.n_pp, P.n_vtx, c.flags & TPG_OUT_DEVICE, c.st, out);
+  if (s == TPG_OK) {
+    TPG_HIP(hipStreamSynchronize(c.st));
+    fill_stats(c, g, R, P, nullptr);
+    if (timing && c.stats) {
+      c.stats->ms_extend = Timer::ms(phase[0], ext_done);
+      c.stats->ms_rank = Timer::ms(ext_done, phase[1]);
+      c.stats->ms_tp = 0;
+      c.stats->ms_total = Timer::ms(phase[0], phase[1]);
+    }
+  }
+  for (auto& e : phase)
+    if (e) (void)hipEventDestroy(e);
+  return s;
+}
+
+tpg_status tpg_test_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* pp_out,
+                          tpg_paths* tp_out) {
+  if (!tp_out) return fail(TPG_ERR_INVALID_ARG, "tp_out is NULL");
+  memset(tp_out, 0, sizeof *tp_out);
+  if (pp_out) memset(pp_out, 0, sizeof *pp_out);
+  if (g && (g->load_flags & TPG_LOAD_ANY_DIGRAPH))
+    return fail(TPG_ERR_UNREACHABLE, "test paths need a graph loaded with the entry/exit checks");
+  CallCtx c;
+  TPG_TRY(begin_call(g, opts, c));
+  Timer tm{c.ws, c.st, c.stats != nullptr && !(c.flags & TPG_NO_TIMING)};
+  const bool timing = tm.on;
+  std::vector<hipEvent_t> phase(4, nullptr);
+  if (timing) {
+    for (auto& e : phase) TPG_HIP(hipEventCreate(&e));
+    TPG_HIP(hipEventRecord(phase[0], c.st));
+  }
+  TreeResult R;
+  PPResult P;
+  TPResult T;
+  hipEvent_t ext_done = nullptr;
+  tpg_status s = run_pp(g, c, tm, R, P, &ext_done);
+  if (s == TPG_OK && timing) TPG_HIP(hipEventRecord(phase[1], c.st));
+  if (s == TPG_OK) s = test_paths_device(c.ws, g, c.st, P, T);
+  if (s == TPG_OK && timing) TPG_HIP(hipEventRecord(phase[2], c.st));
+  const bool dev = c.flags & TPG_OUT_DEVICE;
+  if (s == TPG_OK && pp_out)
+    s = export_paths(c.ws->pp_off, c.ws->pp_vtx, P.n_pp, P.n_vtx, dev, c.st, pp_out);
+  if (s == TPG_OK) s = export_paths(c.ws->out_off, c.ws->out_vtx, T.n_tp, T.n_vtx, dev, c.st, tp_out);
+  if (s == TPG_OK) {
+    TPG_HIP(hipStreamSynchronize(c.st));
+    fill_stats(c, g, R, P, &T);
+    if (timing && c.stats) {
+      c.stats->ms_extend = Timer::ms(phase[0], ext_done);
+      c.stats->ms_rank = Timer::ms(ext_done, phase[1]);
+      c.stats->ms_tp = Timer::ms(phase[1], phase[2]);
+      c.stats->ms_total = Timer::ms(phase[0], phase[2]);
+    }
+  }
+  if (s != TPG_OK) {
+    if (pp_out) tpg_paths_free(pp_out);
+    tpg_paths_free(tp_out);
+  }
+  for (auto& e : phase)
+    if (e) (void)hipEventDestroy(e);
+  return s;
+}
+
+}  // extern "C"

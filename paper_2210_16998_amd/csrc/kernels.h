@@ -1,0 +1,117 @@
+// Host-visible declarations of the device structures and kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device.h"
+
+namespace tpg {
+
+constexpr int kMaxLevels = 4096 + 4;  // path entries <= n + 1
+
+// Level bookkeeping kept in device memory so that levels can follow each
+// other without the host learning their sizes.  The 32-byte header is what
+// the host polls.
+struct LevelState {
+  int32_t level;     // level currently to be extended (paths of `level` entries)
+  int32_t overflow;  // non-zero: the last level did not fit the buffers
+  uint32_t done;     // workgroups finished in the running launch
+  int32_t pad;
+  int64_t cur_count; // count[level]
+  int64_t pad2;
+  int64_t count[kMaxLevels];  // nodes (paths) per level, cycle closures included
+  int64_t off[kMaxLevels];    // global index of the first node of each level
+};
+
+// Buffers of the path tree and of the frontier.
+struct TreeBufs {
+  int32_t* par;       // [rec_cap]
+  uint32_t* info;     // [rec_cap]
+  int32_t* cstart;    // [rec_cap + 1] global index of the first child
+  uint64_t* mask[2];  // frontier visited sets, ping-pong by level parity [mask_cap * W]
+  int64_t rec_cap;
+  int64_t mask_cap;
+  int32_t mask_words;  // W: words per visited set (a power of two)
+  int32_t pad;
+};
+
+struct ExtArgs {
+  DGraph g;
+  TreeBufs t;
+  LevelState* ls;
+  uint64_t* tile_status[2];  // [max_tiles] each, ping-pong by level parity
+  uint32_t* tile_ctr;        // [2]
+  int64_t max_tiles;
+};
+
+// --- path tree -------------------------------------------------------------
+hipError_t launch_seed(const ExtArgs& a, hipStream_t st);
+hipError_t launch_extend(int W, const ExtArgs& a, int grid, hipStream_t st);
+hipError_t launch_resume_fix(const ExtArgs& a, int level, hipStream_t st);
+// two-pass (plain) form
+hipError_t launch_count(int W, const ExtArgs& a, int L, int64_t base, int64_t F, hipStream_t st);
+hipError_t launch_fill(int W, const ExtArgs& a, int L, int64_t base, int64_t F, hipStream_t st);
+
+// --- ranking / materialization ---------------------------------------------
+// sub_cnt / sub_len: PP leaves and their total entries per subtree, then
+// rewritten top-down into (rank of first PP, offset of its first vertex).
+hipError_t launch_up(const ExtArgs& a, int L, int64_t base, int64_t F, uint32_t* sub_cnt,
+                     int64_t* sub_len, unsigned long long* n_cycles, hipStream_t st);
+// mode 0: totals[0] = #PP, totals[1] = #PP vertices (no change to the arrays);
+// mode 1: level-1 subtree sums -> ranks / vertex offsets, root leaves recorded.
+hipError_t launch_roots(const ExtArgs& a, int64_t n_roots, uint32_t* sub_cnt, int64_t* sub_len,
+                        int64_t* leaf_by_rank, int64_t* totals, int mode, hipStream_t st);
+hipError_t launch_down(const ExtArgs& a, int64_t base, int64_t F, uint32_t* sub_cnt,
+                       int64_t* sub_len, int64_t* leaf_by_rank, hipStream_t st);
+hipError_t launch_pp_offsets(const int64_t* leaf_by_rank, const int64_t* sub_len, int64_t n_pp,
+                             int64_t total, int64_t* pp_off, hipStream_t st);
+hipError_t launch_pp_write(const ExtArgs& a, const int64_t* leaf_by_rank, const int64_t* pp_off,
+                           int64_t n_pp, int32_t* pp_vtx, hipStream_t st);
+
+// --- scans -------------------------------------------------------------------
+// out[i] = add + sum(in[0..i)), *total = add + sum(in); n may be 0.
+hipError_t scan_i32_to_i32(const int32_t* in, int32_t* out, int64_t n, int64_t add,
+                           int64_t* total, uint64_t* status, uint32_t* ctr, hipStream_t st);
+hipError_t scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, int64_t add,
+                           int64_t* total, uint64_t* status, uint32_t* ctr, hipStream_t st);
+hipError_t scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t add, int64_t* total,
+                    uint64_t* status, uint32_t* ctr, hipStream_t st);
+int64_t scan_tiles(int64_t n);  // status slots needed by the scans for n items
+
+hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t st);
+hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t st);
+
+// --- test paths --------------------------------------------------------------
+struct BfsOut {
+  int32_t* dist_f;   // [n] arcs from entry
+  int32_t* parent;   // [n] lexicographically smallest shortest-path parent
+  int32_t* dist_b;   // [n] arcs to exit
+  int32_t* next;     // [n] first step of the smallest shortest path to exit
+  int64_t* pfx_off;  // [n+1] prefix table offsets (entries before v)
+  int32_t* pfx;      // [n*n]
+  int64_t* sfx_off;  // [n+1] suffix table offsets (entries after v)
+  int32_t* sfx;      // [n*n]
+};
+hipError_t launch_bfs(const DGraph& g, const BfsOut& b, hipStream_t st);
+
+hipError_t launch_tp_len(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp,
+                         const BfsOut& b, int64_t* tp_len, int32_t* grp_cnt, hipStream_t st);
+hipError_t launch_tp_write(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp,
+                           const BfsOut& b, const int64_t* tp_off, int32_t* tp_vtx,
+                           int32_t* idx, hipStream_t st);
+// one round of pairwise merging of sorted runs [rb[r], rb[r+1]) of idx
+hipError_t launch_merge_round(const int64_t* tp_off, const int32_t* tp_vtx, const int32_t* idx_in,
+                              int32_t* idx_out, const int64_t* rb, int64_t n_runs, int64_t n,
+                              hipStream_t st);
+hipError_t launch_next_runs(const int64_t* rb, int64_t n_runs, int64_t* rb_out, hipStream_t st);
+hipError_t launch_dedup_flags(const int64_t* tp_off, const int32_t* tp_vtx, const int32_t* idx,
+                              int64_t n, int64_t* keep_cnt, int64_t* keep_len, hipStream_t st);
+hipError_t launch_gather(const int64_t* tp_off, const int32_t* tp_vtx, const int32_t* idx,
+                         int64_t n, const int64_t* keep_pos, const int64_t* keep_voff,
+                         const int64_t* keep_len, int64_t* out_off, int32_t* out_vtx,
+                         hipStream_t st);
+hipError_t launch_set_i64(int64_t* p, const int64_t* src, hipStream_t st);
+
+}  // namespace tpg

@@ -1,0 +1,524 @@
+// Path-tree kernels: level-synchronous extension of simple paths, the
+// backward-extendability filter, canonical-order ranking and prime-path
+// materialization.
+//
+// What is computed (paper Sec. 5, Update-Vertex and ExtendPath; Def. 1):
+//  * level 1 holds one path <v> per vertex (the host initialisation of the
+//    paper's algorithm puts each vertex on its own list);
+//  * a path p = (v1..vL) that has not closed a cycle is extended by every
+//    successor w of vL that is not on p, and by w = v1, which closes a cycle;
+//  * a path that gets no extension at all is terminal; a terminal path is a
+//    prime path iff it cannot be extended backward, i.e. every predecessor of
+//    v1 lies on p (the pruning of paths covered by a longer path ending at the
+//    same vertex); every closed cycle is a prime path.
+//
+// How (the paper's asynchronous thread-per-vertex schedule and its per-vertex
+// path tables are not used):
+//  * All paths of one level form a frontier of (parent index, vertex) nodes;
+//    parents keep the children contiguous and in ascending successor order,
+//    so every level is in lexicographic order and a node's subtree occupies a
+//    contiguous range of every deeper level.
+//  * The visited set of a frontier path lives as a bitmask of W 64-bit words
+//    (registers while testing, HBM between levels, two levels alive).
+//  * One workgroup handles a tile of 256 parents: choice masks over successor
+//    slots, a block scan of child counts, one decoupled look-back per tile for
+//    the tile's global child offset (order preserved in a single pass), then
+//    a load-balanced expansion where consecutive threads write consecutive
+//    children, so record and mask stores are coalesced.
+//  * Levels follow each other on the device: the level index, per-level
+//    counts and offsets live in device memory and the last workgroup of a
+//    launch advances them.  A level that does not fit sets an overflow flag;
+//    the host grows the buffers and replays that level.
+
+#include "kernels.h"
+
+namespace tpg {
+
+// ---------------------------------------------------------------------------
+// level 1
+// ---------------------------------------------------------------------------
+__global__ void k_seed(ExtArgs a) {
+  const int n = a.g.n;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // tile status buffer 1 / counters are used by level 1 (odd parity)
+  for (int64_t k = i; k < a.max_tiles; k += (int64_t)gridDim.x * blockDim.x) a.tile_status[1][k] = 0;
+  if (i == 0) {
+    a.tile_ctr[0] = 0;
+    a.tile_ctr[1] = 0;
+    LevelState* ls = a.ls;
+    ls->level = 1;
+    ls->overflow = 0;
+    ls->done = 0;
+    ls->cur_count = n;
+    ls->count[0] = 0;
+    ls->off[0] = 0;
+    ls->count[1] = n;
+    ls->off[1] = 0;
+  }
+  if (i < n) {
+    const int v = (int)i;
+    a.t.par[v] = -1;
+    a.t.info[v] = make_info(v, v, 0);
+  }
+  // masks of level 1 (parity 1): one bit each
+  const int W = a.t.mask_words;
+  for (int64_t k = i; k < (int64_t)n * W; k += (int64_t)gridDim.x * blockDim.x) {
+    const int v = (int)(k / W), q = (int)(k % W);
+    a.t.mask[1][k] = (q == (v >> 6)) ? (1ull << (v & 63)) : 0ull;
+  }
+}
+
+hipError_t launch_seed(const ExtArgs& a, hipStream_t st) {
+  const int64_t work = std::max<int64_t>(a.max_tiles, (int64_t)a.g.n * a.t.mask_words);
+  const int grid = (int)std::min<int64_t>(1024, (work + kBlock - 1) / kBlock + 1);
+  k_seed<<<grid, kBlock, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+// Resume after an overflow: clear the tile bookkeeping of the level to replay.
+__global__ void k_resume_fix(ExtArgs a, int level) {
+  const int par = level & 1;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.max_tiles;
+       k += (int64_t)gridDim.x * blockDim.x)
+    a.tile_status[par][k] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.tile_ctr[par] = 0;
+    a.ls->done = 0;
+    a.ls->overflow = 0;
+  }
+}
+
+hipError_t launch_resume_fix(const ExtArgs& a, int level, hipStream_t st) {
+  const int grid = (int)std::min<int64_t>(1024, (a.max_tiles + kBlock - 1) / kBlock + 1);
+  k_resume_fix<<<grid, kBlock, 0, st>>>(a, level);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// shared per-parent step: choice mask over successor slots + terminal filter
+// ---------------------------------------------------------------------------
+template <int W>
+__device__ __forceinline__ uint64_t choices(const DGraph& g, uint32_t inf, const uint64_t (&m)[W],
+                                            int& k0) {
+  const int v = node_v(inf), v1 = node_v1(inf);
+  k0 = g.sp[v];
+  const int k1 = g.sp[v + 1];
+  uint64_t vm = 0;
+  for (int k = k0; k < k1; ++k) {
+    const int w = g.s[k];
+    const bool ok = (w == v1) || !mask_has<W>(m, w);
+    vm |= ok ? (1ull << (k - k0)) : 0ull;
+  }
+  return vm;
+}
+
+// Backward-extendability test of a terminal path: prime iff every
+// predecessor of its first vertex is on it.
+template <int W>
+__device__ __forceinline__ bool all_preds_on(const DGraph& g, int v1, const uint64_t (&m)[W]) {
+  for (int k = g.pp[v1]; k < g.pp[v1 + 1]; ++k)
+    if (!mask_has<W>(m, g.p[k])) return false;
+  return true;
+}
+
+template <int W>
+__device__ __forceinline__ void load_mask(const uint64_t* src, uint64_t (&m)[W]) {
+  if constexpr (W == 1) {
+    m[0] = src[0];
+  } else {
+    const ulonglong2* s2 = reinterpret_cast<const ulonglong2*>(src);
+#pragma unroll
+    for (int k = 0; k < W / 2; ++k) {
+      const ulonglong2 x = s2[k];
+      m[2 * k] = x.x;
+      m[2 * k + 1] = x.y;
+    }
+  }
+}
+
+template <int W>
+__device__ __forceinline__ void store_child_mask(uint64_t* dst, const uint64_t (&m)[W], int w) {
+  const int q = w >> 6;
+  const uint64_t bit = 1ull << (w & 63);
+  if constexpr (W == 1) {
+    dst[0] = m[0] | bit;
+  } else {
+    ulonglong2* d2 = reinterpret_cast<ulonglong2*>(dst);
+#pragma unroll
+    for (int k = 0; k < W / 2; ++k) {
+      ulonglong2 x;
+      x.x = m[2 * k] | ((2 * k == q) ? bit : 0ull);
+      x.y = m[2 * k + 1] | ((2 * k + 1 == q) ? bit : 0ull);
+      d2[k] = x;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// one-pass extension of level L -> L+1 (device-sized, order preserving)
+// ---------------------------------------------------------------------------
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_extend(ExtArgs a) {
+  constexpr bool kLdsMask = W <= 8;
+  __shared__ int64_t s_tile;
+  __shared__ int64_t s_prefix;
+  __shared__ int32_t s_off[kBlock];
+  __shared__ uint64_t s_vm[kBlock];
+  __shared__ uint32_t s_inf[kBlock];
+  __shared__ int32_t s_kk[kBlock];
+  __shared__ uint64_t s_mask[kLdsMask ? kBlock * W : 1];
+  __shared__ int32_t s_w[kBlock / 64];
+
+  LevelState* ls = a.ls;
+  if (__hip_atomic_load(&ls->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  const int L = ls->level;
+  const int64_t F = ls->count[L];
+  if (F == 0) return;
+  const int64_t base = ls->off[L];
+  const int64_t nbase = base + F;
+  const int par = L & 1;
+  const uint64_t* mcur = a.t.mask[par];
+  uint64_t* mnxt = a.t.mask[par ^ 1];
+  uint64_t* status = a.tile_status[par];
+  const int tid = (int)threadIdx.x;
+
+  // clear the other parity's tile bookkeeping for the next level
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + tid; k < a.max_tiles;
+       k += (int64_t)gridDim.x * kBlock)
+    a.tile_status[par ^ 1][k] = 0;
+  if (blockIdx.x == 0 && tid == 0) a.tile_ctr[par ^ 1] = 0;
+
+  const int64_t ntiles = (F + kBlock - 1) / kBlock;
+  for (;;) {
+    if (tid == 0) s_tile = (int64_t)atomicAdd(&a.tile_ctr[par], 1u);
+    __syncthreads();
+    const int64_t t = s_tile;
+    if (t >= ntiles) break;
+    const int64_t j = t * kBlock + tid;
+    const bool valid = j < F;
+    uint32_t inf = valid ? a.t.info[base + j] : F_CYC;
+    uint64_t m[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) m[q] = 0;
+    uint64_t vm = 0;
+    int k0 = 0;
+    if (!(inf & F_CYC)) {
+      load_mask<W>(mcur + j * W, m);
+      vm = choices<W>(a.g, inf, m, k0);
+      if (vm == 0) {
+        const bool pp = all_preds_on<W>(a.g, node_v1(inf), m);
+        inf |= F_TERM | (pp ? F_PP : 0u);
+        a.t.info[base + j] = inf;
+      }
+    }
+    const int cnt = __builtin_popcountll(vm);
+    int32_t total32;
+    const int32_t my_off = block_excl_scan<kBlock, int32_t>(cnt, total32, s_w);
+    if (tid == 0) s_prefix = lookback_prefix(status, t, (int64_t)total32);
+    s_off[tid] = my_off;
+    s_vm[tid] = vm;
+    s_inf[tid] = inf;
+    s_kk[tid] = k0;
+    if constexpr (kLdsMask) {
+#pragma unroll
+      for (int q = 0; q < W; ++q) s_mask[tid * W + q] = m[q];
+    }
+    __syncthreads();
+    const int64_t prefix = s_prefix;
+    if (valid) a.t.cstart[base + j] = (int32_t)(nbase + prefix + my_off);
+    if (t == ntiles - 1 && tid == 0) {
+      const int64_t total = prefix + total32;
+      ls->count[L + 1] = total;
+      const bool ovf = (nbase + total + 1 > a.t.rec_cap) || (total > a.t.mask_cap) ||
+                       (nbase + total >= (int64_t)INT32_MAX);
+      if (ovf) {
+        __hip_atomic_store(&ls->overflow, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        a.t.cstart[nbase] = (int32_t)(nbase + total);
+      }
+    }
+    // load-balanced expansion: thread k writes the k-th child of the tile
+    for (int k = tid; k < total32; k += kBlock) {
+      int lo = 0, hi = kBlock - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_off[mid] <= k) lo = mid; else hi = mid - 1;
+      }
+      const int o = lo;
+      const int slot = select_bit(s_vm[o], k - s_off[o]);
+      const uint32_t pinf = s_inf[o];
+      const int v1 = node_v1(pinf);
+      const int w = a.g.s[s_kk[o] + slot];
+      const int64_t cl = prefix + k;
+      const int64_t cg = nbase + cl;
+      if (cg < a.t.rec_cap) {
+        a.t.par[cg] = (int32_t)(base + t * kBlock + o);
+        a.t.info[cg] = make_info(w, v1, w == v1 ? F_CYC : 0u);
+      }
+      if (w != v1 && cl < a.t.mask_cap) {
+        uint64_t pm[W];
+        if constexpr (kLdsMask) {
+#pragma unroll
+          for (int q = 0; q < W; ++q) pm[q] = s_mask[o * W + q];
+        } else {
+          load_mask<W>(mcur + (t * kBlock + o) * W, pm);
+        }
+        store_child_mask<W>(mnxt + cl * W, pm, w);
+      }
+    }
+    __syncthreads();
+  }
+
+  // level advance by the last workgroup to finish
+  if (tid == 0) {
+    __threadfence();
+    const uint32_t d = atomicAdd(&ls->done, 1u);
+    if (d == gridDim.x - 1) {
+      __threadfence();
+      ls->done = 0;
+      if (!__hip_atomic_load(&ls->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        const int64_t c = __hip_atomic_load(&ls->count[L + 1], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+        ls->off[L + 1] = nbase;
+        ls->cur_count = c;
+        __threadfence();
+        ls->level = L + 1;
+      }
+    }
+  }
+}
+
+hipError_t launch_extend(int W, const ExtArgs& a, int grid, hipStream_t st) {
+  switch (W) {
+    case 1: k_extend<1><<<grid, kBlock, 0, st>>>(a); break;
+    case 2: k_extend<2><<<grid, kBlock, 0, st>>>(a); break;
+    case 4: k_extend<4><<<grid, kBlock, 0, st>>>(a); break;
+    case 8: k_extend<8><<<grid, kBlock, 0, st>>>(a); break;
+    case 16: k_extend<16><<<grid, kBlock, 0, st>>>(a); break;
+    case 32: k_extend<32><<<grid, kBlock, 0, st>>>(a); break;
+    case 64: k_extend<64><<<grid, kBlock, 0, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// two-pass (plain) form: count, host-visible scan, fill
+// ---------------------------------------------------------------------------
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_count(ExtArgs a, int L, int64_t base, int64_t F) {
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= F) return;
+  uint32_t inf = a.t.info[base + j];
+  int cnt = 0;
+  if (!(inf & F_CYC)) {
+    uint64_t m[W];
+    load_mask<W>(a.t.mask[L & 1] + j * W, m);
+    int k0;
+    const uint64_t vm = choices<W>(a.g, inf, m, k0);
+    cnt = __builtin_popcountll(vm);
+    if (cnt == 0) {
+      const bool pp = all_preds_on<W>(a.g, node_v1(inf), m);
+      a.t.info[base + j] = inf | F_TERM | (pp ? F_PP : 0u);
+    }
+  }
+  a.t.cstart[base + j] = cnt;
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_fill(ExtArgs a, int L, int64_t base, int64_t F) {
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= F) return;
+  const uint32_t inf = a.t.info[base + j];
+  if (inf & F_CYC) return;
+  uint64_t m[W];
+  load_mask<W>(a.t.mask[L & 1] + j * W, m);
+  int k0;
+  uint64_t vm = choices<W>(a.g, inf, m, k0);
+  const int v1 = node_v1(inf);
+  const int64_t nbase = base + F;
+  int64_t c = a.t.cstart[base + j];
+  uint64_t* mnxt = a.t.mask[(L + 1) & 1];
+  while (vm) {
+    const int slot = __builtin_ctzll(vm);
+    vm &= vm - 1;
+    const int w = a.g.s[k0 + slot];
+    a.t.par[c] = (int32_t)(base + j);
+    a.t.info[c] = make_info(w, v1, w == v1 ? F_CYC : 0u);
+    if (w != v1) store_child_mask<W>(mnxt + (c - nbase) * W, m, w);
+    ++c;
+  }
+}
+
+#define TPG_W_SWITCH(W, KERNEL, GRID, ...)                                        \
+  switch (W) {                                                                      \
+    case 1: KERNEL<1><<<GRID, kBlock, 0, st>>>(__VA_ARGS__); break;                 \
+    case 2: KERNEL<2><<<GRID, kBlock, 0, st>>>(__VA_ARGS__); break;                 \
+    case 4: KERNEL<4><<<GRID, kBlock, 0, st>>>(__VA_ARGS__); break;                 \
+    case 8: KERNEL<8><<<GRID, kBlock, 0, st>>>(__VA_ARGS__); break;                 \
+    case 16: KERNEL<16><<<GRID, kBlock, 0, st>>>(__VA_ARGS__); break;               \
+    case 32: KERNEL<32><<<GRID, kBlock, 0, st>>>(__VA_ARGS__); break;               \
+    case 64: KERNEL<64><<<GRID, kBlock, 0, st>>>(__VA_ARGS__); break;               \
+    default: return hipErrorInvalidValue;                                           \
+  }
+
+hipError_t launch_count(int W, const ExtArgs& a, int L, int64_t base, int64_t F, hipStream_t st) {
+  if (F == 0) return hipSuccess;
+  const int64_t grid = (F + kBlock - 1) / kBlock;
+  TPG_W_SWITCH(W, k_count, (unsigned)grid, a, L, base, F);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(int W, const ExtArgs& a, int L, int64_t base, int64_t F, hipStream_t st) {
+  if (F == 0) return hipSuccess;
+  const int64_t grid = (F + kBlock - 1) / kBlock;
+  TPG_W_SWITCH(W, k_fill, (unsigned)grid, a, L, base, F);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// canonical order: subtree sums bottom-up, ranks top-down
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_up(ExtArgs a, int L, int64_t base, int64_t F,
+                                               uint32_t* sub_cnt, int64_t* sub_len,
+                                               unsigned long long* n_cycles) {
+  __shared__ int32_t s_w[kBlock / 64];
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  int cyc = 0;
+  if (j < F) {
+    const int64_t g = base + j;
+    const uint32_t inf = a.t.info[g];
+    uint32_t c = 0;
+    int64_t l = 0;
+    if (inf & (F_CYC | F_PP)) {
+      c = 1;
+      l = L;
+      cyc = (inf & F_CYC) ? 1 : 0;
+    } else if (!(inf & F_TERM)) {
+      const int64_t c0 = a.t.cstart[g], c1 = a.t.cstart[g + 1];
+      for (int64_t x = c0; x < c1; ++x) {
+        c += sub_cnt[x];
+        l += sub_len[x];
+      }
+    }
+    sub_cnt[g] = c;
+    sub_len[g] = l;
+  }
+  int32_t tot;
+  block_excl_scan<kBlock, int32_t>(cyc, tot, s_w);
+  if (threadIdx.x == 0 && tot) atomicAdd(n_cycles, (unsigned long long)tot);
+}
+
+hipError_t launch_up(const ExtArgs& a, int L, int64_t base, int64_t F, uint32_t* sub_cnt,
+                     int64_t* sub_len, unsigned long long* n_cycles, hipStream_t st) {
+  if (F == 0) return hipSuccess;
+  k_up<<<(unsigned)((F + kBlock - 1) / kBlock), kBlock, 0, st>>>(a, L, base, F, sub_cnt, sub_len,
+                                                                  n_cycles);
+  return hipGetLastError();
+}
+
+// Level-1 nodes: exclusive scans of their subtree sums give the rank of the
+// first PP and the offset of its first vertex.  totals[0] = #PP,
+// totals[1] = #PP vertices.  One workgroup of 1024 threads (n <= 4096).
+__global__ __launch_bounds__(1024) void k_roots(ExtArgs a, int64_t n_roots, uint32_t* sub_cnt,
+                                                int64_t* sub_len, int64_t* leaf_by_rank,
+                                                int64_t* totals, int mode) {
+  __shared__ int64_t s_w[16];
+  __shared__ int64_t s_w2[16];
+  int64_t carry_c = 0, carry_l = 0;
+  for (int64_t b = 0; b < n_roots; b += 1024) {
+    const int64_t i = b + threadIdx.x;
+    const int64_t c = i < n_roots ? (int64_t)sub_cnt[i] : 0;
+    const int64_t l = i < n_roots ? sub_len[i] : 0;
+    int64_t tc, tl;
+    const int64_t pc = block_excl_scan<1024, int64_t>(c, tc, s_w);
+    const int64_t pl = block_excl_scan<1024, int64_t>(l, tl, s_w2);
+    if (i < n_roots && mode == 1) {
+      const int64_t rank = carry_c + pc;
+      sub_cnt[i] = (uint32_t)rank;
+      sub_len[i] = carry_l + pl;
+      if (a.t.info[i] & (F_PP | F_CYC)) leaf_by_rank[rank] = i;
+    }
+    carry_c += tc;
+    carry_l += tl;
+  }
+  if (threadIdx.x == 0 && mode == 0) {
+    totals[0] = carry_c;
+    totals[1] = carry_l;
+  }
+}
+
+hipError_t launch_roots(const ExtArgs& a, int64_t n_roots, uint32_t* sub_cnt, int64_t* sub_len,
+                        int64_t* leaf_by_rank, int64_t* totals, int mode, hipStream_t st) {
+  k_roots<<<1, 1024, 0, st>>>(a, n_roots, sub_cnt, sub_len, leaf_by_rank, totals, mode);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_down(ExtArgs a, int64_t base, int64_t F,
+                                                 uint32_t* sub_cnt, int64_t* sub_len,
+                                                 int64_t* leaf_by_rank) {
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= F) return;
+  const int64_t g = base + j;
+  const uint32_t inf = a.t.info[g];
+  if (inf & (F_CYC | F_TERM)) return;
+  int64_t r = sub_cnt[g];
+  int64_t o = sub_len[g];
+  const int64_t c0 = a.t.cstart[g], c1 = a.t.cstart[g + 1];
+  for (int64_t x = c0; x < c1; ++x) {
+    const uint32_t cc = sub_cnt[x];
+    const int64_t cl = sub_len[x];
+    sub_cnt[x] = (uint32_t)r;
+    sub_len[x] = o;
+    if (a.t.info[x] & (F_PP | F_CYC)) leaf_by_rank[r] = x;
+    r += cc;
+    o += cl;
+  }
+}
+
+hipError_t launch_down(const ExtArgs& a, int64_t base, int64_t F, uint32_t* sub_cnt,
+                       int64_t* sub_len, int64_t* leaf_by_rank, hipStream_t st) {
+  if (F == 0) return hipSuccess;
+  k_down<<<(unsigned)((F + kBlock - 1) / kBlock), kBlock, 0, st>>>(a, base, F, sub_cnt, sub_len,
+                                                                    leaf_by_rank);
+  return hipGetLastError();
+}
+
+__global__ void k_pp_offsets(const int64_t* leaf_by_rank, const int64_t* sub_len, int64_t n_pp,
+                             int64_t total, int64_t* pp_off) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_pp) pp_off[i] = sub_len[leaf_by_rank[i]];
+  if (i == n_pp) pp_off[i] = total;
+}
+
+hipError_t launch_pp_offsets(const int64_t* leaf_by_rank, const int64_t* sub_len, int64_t n_pp,
+                             int64_t total, int64_t* pp_off, hipStream_t st) {
+  k_pp_offsets<<<(unsigned)((n_pp + 1 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+      leaf_by_rank, sub_len, n_pp, total, pp_off);
+  return hipGetLastError();
+}
+
+// Each thread writes one prime path by walking parent links from its leaf.
+__global__ __launch_bounds__(kBlock) void k_pp_write(ExtArgs a, const int64_t* leaf_by_rank,
+                                                     const int64_t* pp_off, int64_t n_pp,
+                                                     int32_t* pp_vtx) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n_pp) return;
+  int64_t x = leaf_by_rank[i];
+  int64_t pos = pp_off[i + 1] - 1;
+  const int64_t lo = pp_off[i];
+  while (pos >= lo && x >= 0) {
+    pp_vtx[pos--] = node_v(a.t.info[x]);
+    x = a.t.par[x];
+  }
+}
+
+hipError_t launch_pp_write(const ExtArgs& a, const int64_t* leaf_by_rank, const int64_t* pp_off,
+                           int64_t n_pp, int32_t* pp_vtx, hipStream_t st) {
+  if (n_pp == 0) return hipSuccess;
+  k_pp_write<<<(unsigned)((n_pp + kBlock - 1) / kBlock), kBlock, 0, st>>>(a, leaf_by_rank, pp_off,
+                                                                          n_pp, pp_vtx);
+  return hipGetLastError();
+}
+
+}  // namespace tpg

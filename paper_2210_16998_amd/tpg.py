@@ -1,0 +1,298 @@
+"""Thin ctypes binding of libtpg.so (include/tpg.h): argument marshalling only.
+
+Every step of the path computation runs in the library's HIP kernels; this
+module only moves arguments and results.  It fails loudly when the library
+has not been built (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtpg.so")
+
+TPG_OK = 0
+TPG_LOAD_STRICT = 0x1
+TPG_LOAD_ANY_DIGRAPH = 0x2
+TPG_OUT_DEVICE = 0x1
+TPG_FORCE_TWO_PASS = 0x2
+TPG_NO_TIMING = 0x4
+
+STATUS = {0: "TPG_OK", -1: "TPG_ERR_INVALID_ARG", -2: "TPG_ERR_BAD_CSR",
+          -3: "TPG_ERR_BAD_ENTRY_EXIT", -4: "TPG_ERR_UNREACHABLE",
+          -5: "TPG_ERR_OOM_HOST", -6: "TPG_ERR_OOM_DEVICE", -7: "TPG_ERR_CAPACITY",
+          -8: "TPG_ERR_DEVICE", -9: "TPG_ERR_UNSUPPORTED"}
+
+
+class TpgError(RuntimeError):
+    def __init__(self, status: int, message: str) -> None:
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class _Paths(ctypes.Structure):
+    _fields_ = [("n_paths", ctypes.c_int64), ("n_vertices", ctypes.c_int64),
+                ("offsets", ctypes.c_void_p), ("vertices", ctypes.c_void_p),
+                ("on_device", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int64), ("n_nodes", ctypes.c_int64),
+                ("n_extensions", ctypes.c_int64), ("n_cycles", ctypes.c_int64),
+                ("n_pp", ctypes.c_int64), ("n_pp_vertices", ctypes.c_int64),
+                ("n_tp_spliced", ctypes.c_int64), ("n_tp", ctypes.c_int64),
+                ("n_tp_vertices", ctypes.c_int64), ("n_overflows", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("ms_extend", ctypes.c_double),
+                ("ms_rank", ctypes.c_double), ("ms_tp", ctypes.c_double),
+                ("ms_total", ctypes.c_double), ("ms_extend_kernel", ctypes.c_double),
+                ("n_extend_launches", ctypes.c_int64)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("stream", ctypes.c_void_p), ("ws", ctypes.c_void_p),
+                ("pool_cap_bytes", ctypes.c_uint64), ("stats", ctypes.POINTER(_Stats)),
+                ("level_counts", ctypes.POINTER(ctypes.c_int64)),
+                ("level_counts_len", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+
+
+# every symbol include/tpg.h declares, with its signature
+_SIGS = {
+    "tpg_load_cfg_csr": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "tpg_graph_free": (None, [ctypes.c_void_p]),
+    "tpg_graph_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int32)]),
+    "tpg_graph_csr": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "tpg_workspace_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
+    "tpg_workspace_free": (None, [ctypes.c_void_p]),
+    "tpg_workspace_bytes": (ctypes.c_int64, [ctypes.c_void_p]),
+    "tpg_prime_paths": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Opts),
+                                       ctypes.POINTER(_Paths)]),
+    "tpg_test_paths": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Opts),
+                                      ctypes.POINTER(_Paths), ctypes.POINTER(_Paths)]),
+    "tpg_paths_free": (None, [ctypes.POINTER(_Paths)]),
+    "tpg_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "tpg_last_error": (ctypes.c_char_p, []),
+    "tpg_version": (ctypes.c_char_p, []),
+    "tpg_device_count": (ctypes.c_int32, []),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2210_16998_amd.build` (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def declared_symbols():
+    return list(_SIGS)
+
+
+def _check(rc: int) -> None:
+    if rc != TPG_OK:
+        msg = lib().tpg_last_error()
+        raise TpgError(rc, msg.decode() if msg else "")
+
+
+class Graph:
+    """A loaded CFG (library handle, host memory)."""
+
+    def __init__(self, handle: int) -> None:
+        self._h = ctypes.c_void_p(handle)
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def info(self) -> Tuple[int, int, int, int]:
+        n, m, e, x = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().tpg_graph_info(self._h, ctypes.byref(n), ctypes.byref(m),
+                                    ctypes.byref(e), ctypes.byref(x)))
+        return n.value, m.value, e.value, x.value
+
+    def csr(self) -> Tuple[np.ndarray, np.ndarray]:
+        n, m, _, _ = self.info()
+        rp = np.zeros(n + 1, np.int64)
+        ci = np.zeros(max(m, 1), np.int32)
+        _check(lib().tpg_graph_csr(self._h, rp.ctypes.data, ci.ctypes.data))
+        return rp, ci[:m]
+
+    def close(self) -> None:
+        if self._h:
+            lib().tpg_graph_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def load_cfg_csr(n: int, row_ptr: np.ndarray, col_idx: np.ndarray, entry: int, exit: int,
+                 flags: int = 0) -> Graph:
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    if ci.size == 0:
+        ci = np.zeros(1, np.int32)
+    h = ctypes.c_void_p()
+    _check(lib().tpg_load_cfg_csr(int(n), rp.ctypes.data, ci.ctypes.data, int(entry),
+                                  int(exit), int(flags), ctypes.byref(h)))
+    return Graph(h.value)
+
+
+def load_cfg(cfg, flags: int = 0) -> Graph:
+    """Loads a paper_2210_16998_amd.cfggen.CFG."""
+    return load_cfg_csr(cfg.n, cfg.row_ptr, cfg.col_idx, cfg.entry, cfg.exit, flags)
+
+
+class Workspace:
+    """Device arena + stream reused across calls (grows on demand)."""
+
+    def __init__(self, device: int = -1) -> None:
+        h = ctypes.c_void_p()
+        _check(lib().tpg_workspace_create(int(device), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    @property
+    def bytes(self) -> int:
+        return int(lib().tpg_workspace_bytes(self._h))
+
+    def close(self) -> None:
+        if self._h:
+            lib().tpg_workspace_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HostPaths:
+    """Host result: offsets int64 [n+1], vertices int32 (copied out of the
+    library-owned arrays, which are then released)."""
+
+    def __init__(self, p: _Paths) -> None:
+        n, nv = p.n_paths, p.n_vertices
+        self.offsets = np.ctypeslib.as_array(
+            ctypes.cast(p.offsets, ctypes.POINTER(ctypes.c_int64)), shape=(n + 1,)).copy()
+        self.vertices = (np.ctypeslib.as_array(
+            ctypes.cast(p.vertices, ctypes.POINTER(ctypes.c_int32)), shape=(nv,)).copy()
+            if nv else np.zeros(0, np.int32))
+        lib().tpg_paths_free(ctypes.byref(p))
+
+    def __len__(self) -> int:
+        return len(self.offsets) - 1
+
+    def __getitem__(self, i: int):
+        return self.vertices[self.offsets[i]:self.offsets[i + 1]].tolist()
+
+    def tolist(self):
+        return [self[i] for i in range(len(self))]
+
+
+class _CudaArray:
+    def __init__(self, ptr: int, n: int, typestr: str) -> None:
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr,
+                                         "data": (int(ptr), False), "version": 3}
+
+
+class DevicePaths:
+    """Device result view (TPG_OUT_DEVICE): pointers into the workspace,
+    valid until the next call on that workspace."""
+
+    def __init__(self, p: _Paths) -> None:
+        self.n_paths = int(p.n_paths)
+        self.n_vertices = int(p.n_vertices)
+        self.offsets_ptr = int(p.offsets or 0)
+        self.vertices_ptr = int(p.vertices or 0)
+
+    def __len__(self) -> int:
+        return self.n_paths
+
+    def torch_views(self):
+        """(offsets, vertices) as zero-copy torch tensors on the GPU."""
+        import torch
+        off = torch.as_tensor(_CudaArray(self.offsets_ptr, self.n_paths + 1, "<i8"),
+                              device="cuda")
+        vtx = torch.as_tensor(_CudaArray(self.vertices_ptr, max(self.n_vertices, 1), "<i4"),
+                              device="cuda")
+        return off, vtx[:self.n_vertices]
+
+
+def _opts(ws: Optional[Workspace], flags: int, stream, stats: Optional[_Stats],
+          pool_cap: int = 0, level_buf: Optional[np.ndarray] = None) -> _Opts:
+    o = _Opts()
+    o.struct_size = ctypes.sizeof(_Opts)
+    o.flags = int(flags)
+    if stream is not None:
+        o.stream = ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+    o.ws = ws.handle if ws is not None else None
+    o.pool_cap_bytes = int(pool_cap)
+    o.stats = ctypes.pointer(stats) if stats is not None else None
+    if level_buf is not None:
+        o.level_counts = level_buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        o.level_counts_len = len(level_buf)
+    return o
+
+
+def _stats_dict(s: _Stats) -> Dict[str, float]:
+    return {k: getattr(s, k) for k, _ in _Stats._fields_}
+
+
+def prime_paths(g: Graph, ws: Optional[Workspace] = None, flags: int = 0, stream=None,
+                pool_cap: int = 0, level_counts: Optional[np.ndarray] = None):
+    """(paths, stats).  paths is HostPaths, or DevicePaths with TPG_OUT_DEVICE."""
+    st = _Stats()
+    o = _opts(ws, flags, stream, st, pool_cap, level_counts)
+    out = _Paths()
+    _check(lib().tpg_prime_paths(g.handle, ctypes.byref(o), ctypes.byref(out)))
+    res = DevicePaths(out) if out.on_device else HostPaths(out)
+    return res, _stats_dict(st)
+
+
+def test_paths(g: Graph, ws: Optional[Workspace] = None, flags: int = 0, stream=None,
+               pool_cap: int = 0, want_pp: bool = True):
+    """(prime paths or None, test paths, stats)."""
+    st = _Stats()
+    o = _opts(ws, flags, stream, st, pool_cap)
+    pp, tp = _Paths(), _Paths()
+    _check(lib().tpg_test_paths(g.handle, ctypes.byref(o),
+                                ctypes.byref(pp) if want_pp else None, ctypes.byref(tp)))
+    wrap = DevicePaths if tp.on_device else HostPaths
+    return (wrap(pp) if want_pp else None), wrap(tp), _stats_dict(st)
+
+
+def version() -> str:
+    return lib().tpg_version().decode()
+
+
+def device_count() -> int:
+    return int(lib().tpg_device_count())

@@ -1,0 +1,143 @@
+"""GPU parity: the HIP path against the CPU oracle, element by element on the
+same seeded inputs (integer path sets: bit-exact)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2210_16998_amd import cfggen, tpg
+from tests.gpu_util import check_pp, check_tp, say, same, ws
+from tests.goldens import read_paths, workloads
+
+pytestmark = pytest.mark.gpu
+
+MODES = [0, tpg.TPG_FORCE_TWO_PASS]
+
+
+@pytest.mark.parametrize("flags", MODES)
+def test_fig1(flags):
+    say("case fig1", flags)
+    pp, tp, st = check_tp(cfggen.fig1_cfg(), flags)
+    assert pp.tolist() == sorted(read_paths("fig1_pps.txt"))
+    assert len(tp) == 10 and st["n_tp_spliced"] == 19
+
+
+@pytest.mark.parametrize("flags", MODES)
+def test_c1_layout_and_relabellings(flags):
+    for s in range(17):
+        say("case c1 seed", s, flags)
+        pp, tp, st = check_tp(cfggen.c1_cfg(s), flags)
+        assert len(pp) == 49 and st["n_extensions"] == 558 and len(tp) == 39
+
+
+def test_single_vertex():
+    say("case single vertex")
+    g = cfggen.from_edges(1, [], 0, 0)
+    pp, tp, _ = check_tp(g)
+    assert pp.tolist() == [[0]] and tp.tolist() == [[0]]
+
+
+@pytest.mark.parametrize("flags", MODES)
+def test_random_small_cfgs(flags):
+    for s in range(400):
+        n = 2 + s % 30
+        g = cfggen.random_small_cfg(50_000 + s, n, extra=1 + s % 9)
+        if s % 50 == 0:
+            say("case random cfg", s, n, flags)
+        check_tp(g, flags)
+
+
+@pytest.mark.parametrize("flags", MODES)
+def test_random_digraphs_any(flags):
+    """Prime paths of arbitrary digraphs (self-loops, dense, disconnected)."""
+    for s in range(400):
+        n = 1 + s % 11
+        g = cfggen.random_digraph(70_000 + s, n, 0.1 + 0.08 * (s % 7))
+        if s % 50 == 0:
+            say("case random digraph", s, n, flags)
+        check_pp(g, flags, tpg.TPG_LOAD_ANY_DIGRAPH)
+
+
+def test_closed_forms_on_gpu():
+    for n in range(2, 8):
+        say("case K", n)
+        check_pp(cfggen.complete_digraph(n), 0, tpg.TPG_LOAD_ANY_DIGRAPH)
+    for k in (1, 4, 9, 12):
+        say("case loop-diamond", k)
+        _, st, _ = check_pp(cfggen.loop_diamond_chain(k))
+        assert st["n_pp"] == (3 * k + 4) * 2 ** k + 1
+
+
+def test_wide_masks():
+    """Graphs needing 2..64 mask words (V up to 4096)."""
+    for n in (65, 130, 300, 700, 1500, 4096):
+        say("case wide", n)
+        g = cfggen.random_small_cfg(90_000 + n, n, extra=4)
+        check_tp(g)
+
+
+@pytest.mark.parametrize("flags", MODES)
+@pytest.mark.parametrize("k", range(8))
+def test_c2_workloads(k, flags):
+    rec = workloads()["c2"][k]
+    say("case c2 seed", rec["seed"], flags)
+    g = cfggen.c2_cfg(rec["seed"])
+    pp, tp, st = check_tp(g, flags, local=True)
+    assert st["n_pp"] == rec["n_pp"] and st["n_extensions"] == rec["n_extensions"]
+
+
+def test_overflow_growth_from_a_fresh_workspace():
+    """A fresh workspace starts small: the device-sized levels overflow, the
+    buffers grow and the level is replayed; results stay exact."""
+    w = tpg.Workspace()
+    g = cfggen.c2_cfg(workloads()["c2"][3]["seed"])
+    say("case overflow replay")
+    _, st, _ = check_pp(g, 0, 0, w, local=True)
+    assert st["n_overflows"] > 0
+    w.close()
+
+
+def test_pool_cap_is_enforced():
+    w = tpg.Workspace()
+    g = tpg.load_cfg(cfggen.c2_cfg(workloads()["c2"][3]["seed"]))
+    say("case pool cap")
+    with pytest.raises(tpg.TpgError) as ei:
+        tpg.prime_paths(g, ws=w, pool_cap=1 << 20)
+    assert ei.value.name == "TPG_ERR_CAPACITY"
+    w.close()
+
+
+def test_deterministic_bytes_across_runs_and_modes():
+    g = cfggen.c2_cfg(workloads()["c2"][0]["seed"])
+    h = tpg.load_cfg(g)
+    outs = []
+    for flags in (0, tpg.TPG_FORCE_TWO_PASS, 0):
+        say("case determinism", flags)
+        pp, tp, _ = tpg.test_paths(h, ws=ws(), flags=flags)
+        outs.append((pp.offsets.tobytes(), pp.vertices.tobytes(), tp.offsets.tobytes(),
+                     tp.vertices.tobytes()))
+    assert outs[0] == outs[1] == outs[2]
+
+
+def test_device_output_views():
+    import torch
+    g = cfggen.c1_cfg(0)
+    h = tpg.load_cfg(g)
+    say("case device views")
+    pp, tp, _ = tpg.test_paths(h, ws=ws(), flags=tpg.TPG_OUT_DEVICE)
+    off, vtx = tp.torch_views()
+    ref_pp, _, _, _ = oracle.prime_paths(g)
+    ref_tp, _ = oracle.test_paths(g, ref_pp)
+    assert np.array_equal(off.cpu().numpy(), ref_tp.offsets)
+    assert np.array_equal(vtx.cpu().numpy(), ref_tp.vertices)
+    torch.cuda.synchronize()
+
+
+def test_runs_on_a_torch_stream():
+    import torch
+    s = torch.cuda.Stream()
+    g = cfggen.c1_cfg(2)
+    h = tpg.load_cfg(g)
+    say("case torch stream")
+    pp, st = tpg.prime_paths(h, ws=ws(), stream=s)
+    ref, _, _, _ = oracle.prime_paths(g)
+    assert same(pp, ref)
