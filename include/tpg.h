@@ -107,6 +107,10 @@ typedef struct tpg_stats {
   double ms_total;        /* device time of the whole call                   */
   double ms_extend_kernel;/* summed duration of the extension kernel launches */
   int64_t n_extend_launches;
+  int64_t peak_level_nodes;      /* largest level (paths of one length)       */
+  int64_t n_unions;              /* graph unions processed (batched form)     */
+  int64_t pred_nodes;            /* predicted paths (batched form with predictions) */
+  int64_t pred_peak_level_nodes; /* predicted largest level                  */
 } tpg_stats;
 
 typedef struct tpg_opts {
@@ -116,8 +120,10 @@ typedef struct tpg_opts {
   tpg_workspace* ws;        /* NULL: a temporary workspace for this call     */
   uint64_t pool_cap_bytes;  /* 0: no cap                                    */
   tpg_stats* stats;         /* optional                                     */
-  int64_t* level_counts;    /* optional: level_counts[L] = acyclic paths with
-                               L vertices, L = 0 .. level_counts_len-1      */
+  int64_t* level_counts;    /* optional: level_counts[L] = simple paths with L
+                               entries (closed cycles included), for
+                               L = 0 .. level_counts_len-1 (batched form:
+                               see tpg_batch_test_paths)                    */
   int32_t level_counts_len;
   int32_t reserved_;
 } tpg_opts;
@@ -179,6 +185,46 @@ tpg_status tpg_test_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* p
 /* Releases host results; device results (on_device = 1) are owned by the
  * workspace and this only clears the struct. */
 void tpg_paths_free(tpg_paths* p);
+
+/* ------------------------------------------------------------------------
+ * Batched form: prime and test paths of many CFGs in one call.
+ *
+ * The same computation as tpg_test_paths, per graph.  Graphs are grouped by
+ * visited-set width and each group runs as one disjoint union, so every
+ * level of every graph in the group is extended by the same launches (all
+ * compute units busy even when each graph is small).  Results are packed
+ * graph after graph in the caller's order, each graph's sets canonical and
+ * in its own vertex ids: graph i owns prime paths pp_first[i] ..
+ * pp_first[i+1]-1 of pp (likewise tp / tp_first).
+ *
+ * predicted (optional, host, [n_graphs * 65] floats): per graph, log1p of the
+ * predicted number of simple paths with L entries for L = 1..64 (index L-1;
+ * index 63 pools all deeper levels) and log1p of the predicted prime-path
+ * count (index 64).  With it the path pool is sized in one pass from the
+ * prediction (25% margin) and, under a pool cap, graphs are admitted into
+ * unions by predicted footprint; a level that outgrows its allocation is
+ * detected on the device, grown to its exact size and replayed.  Without
+ * it, sizing starts from the workspace's current capacity (or the exact
+ * two-pass form with TPG_FORCE_TWO_PASS).  Results never depend on the
+ * prediction.
+ *
+ * opts->level_counts, if it holds >= 64 * n_graphs entries, receives the
+ * per-graph path counts of levels 1..64 (deeper levels pooled into 64):
+ * the labels the size predictor is trained on.
+ * ---------------------------------------------------------------------- */
+typedef struct tpg_batch_result {
+  tpg_paths pp;
+  tpg_paths tp;
+  int64_t* pp_first; /* [n_graphs + 1], host memory owned by the library */
+  int64_t* tp_first; /* [n_graphs + 1] */
+  int32_t n_graphs;
+  int32_t reserved_;
+} tpg_batch_result;
+
+tpg_status tpg_batch_test_paths(const tpg_graph* const* graphs, int32_t n_graphs,
+                                const tpg_opts* opts, const float* predicted,
+                                tpg_batch_result* out);
+void tpg_batch_result_free(tpg_batch_result* r);
 
 /* ------------------------------------------------------------------------
  * Misc.

@@ -13,24 +13,35 @@ constexpr int kBlock = 256;  // threads per workgroup for path kernels (4 waves)
 
 // A path-tree node is stored as two 32-bit words:
 //   par  : global index of the parent node (-1 for a single-vertex path)
-//   info : last vertex (bits 0-11) | first vertex (bits 12-23) | flags
-constexpr uint32_t kVMask = 0xFFFu;
-constexpr uint32_t F_CYC = 1u << 24;   // closes a cycle (last vertex = first)
-constexpr uint32_t F_PP = 1u << 25;    // prime path leaf (set on terminal nodes)
-constexpr uint32_t F_TERM = 1u << 26;  // acyclic, cannot be extended forward
+//   info : last vertex, graph-wide id (bits 0-16) | first vertex, id local to
+//          its component (bits 17-28) | flags (bits 29-31)
+// Several CFGs can be processed as one disjoint union ("components"); a
+// visited set indexes the local ids of the path's own component.
+constexpr uint32_t kVMask = 0x1FFFFu;
+constexpr int kV1Shift = 17;
+constexpr uint32_t kV1Mask = 0xFFFu;
+constexpr uint32_t F_CYC = 1u << 29;   // closes a cycle (last vertex = first)
+constexpr uint32_t F_PP = 1u << 30;    // prime path leaf (set on terminal nodes)
+constexpr uint32_t F_TERM = 1u << 31;  // acyclic, cannot be extended forward
+constexpr int kMaxUnionVertices = 1 << 17;
 
 __device__ __forceinline__ int node_v(uint32_t info) { return (int)(info & kVMask); }
-__device__ __forceinline__ int node_v1(uint32_t info) { return (int)((info >> 12) & kVMask); }
-__device__ __forceinline__ uint32_t make_info(int v, int v1, uint32_t flags) {
-  return (uint32_t)v | ((uint32_t)v1 << 12) | flags;
+__device__ __forceinline__ int node_v1l(uint32_t info) { return (int)((info >> kV1Shift) & kV1Mask); }
+__device__ __forceinline__ uint32_t make_info(int v, int v1l, uint32_t flags) {
+  return (uint32_t)v | ((uint32_t)v1l << kV1Shift) | flags;
 }
 
 struct DGraph {
-  const int32_t* sp;  // successor row pointers [n+1]
-  const int32_t* s;   // successors, ascending per row
-  const int32_t* pp;  // predecessor row pointers [n+1]
-  const int32_t* p;   // predecessors
-  int32_t n, entry, exit, pad;
+  const int32_t* sp;    // successor row pointers [n+1] (graph-wide ids)
+  const int32_t* s;     // successors, ascending per row
+  const int32_t* pp;    // predecessor row pointers [n+1]
+  const int32_t* p;     // predecessors
+  const int32_t* loc;   // [n] id of each vertex inside its component
+  const int32_t* comp;  // [n] component of each vertex
+  const int32_t* cbase; // [n_comp+1] first graph-wide id of each component
+  const int32_t* centry;// [n_comp] entry (graph-wide id)
+  const int32_t* cexit; // [n_comp] exit (graph-wide id)
+  int32_t n, n_comp;
 };
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }

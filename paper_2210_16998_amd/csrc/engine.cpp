@@ -1,7 +1,9 @@
-// Host orchestration of the single-graph pipeline: workspace (grow-only
-// device arena + stream), level loop, ranking, materialization, test paths.
+// Host orchestration: workspace (grow-only device arena + stream), unions of
+// CFGs, level loop (device-sized one-pass or plain two-pass), ranking,
+// materialization, test paths, and the batched entry point.
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -12,6 +14,31 @@
 
 using namespace tpg;
 
+namespace {
+
+// Outputs of one union of CFGs (graph-wide ids until localized).
+struct OutSet {
+  DevBuf pp_off, pp_vtx, tp_off, tp_vtx;
+  DevBuf comp_starts;  // int64 [4][n_comp+1]: pp, pp vertices, tp, tp vertices
+  int64_t n_pp = 0, n_ppv = 0, n_tp = 0, n_tpv = 0;
+};
+
+// A disjoint union of CFGs laid out as one graph (host side).
+struct HostUnion {
+  int32_t n = 0, n_comp = 0, W = 1;
+  std::vector<int32_t> sp{0}, s, pp{0}, p, loc, comp, cbase{0}, centry, cexit;
+  std::vector<uint64_t> uids;
+};
+
+int pow2_words(int n) {
+  int w = (n + 63) / 64;
+  int q = 1;
+  while (q < w) q <<= 1;
+  return q;
+}
+
+}  // namespace
+
 struct tpg_workspace {
   int device = 0;
   hipStream_t own_stream = nullptr;
@@ -19,8 +46,8 @@ struct tpg_workspace {
   size_t bytes = 0;
   uint64_t cap = 0;  // pool cap of the running call (0: none)
 
-  // graph cache
-  uint64_t graph_uid = 0;
+  // union on the device
+  std::vector<uint64_t> union_uids;
   DevBuf g_csr;
   DGraph dg{};
 
@@ -30,13 +57,17 @@ struct tpg_workspace {
   int mask_words = 0;
   // ranking
   DevBuf sub_cnt, sub_len, leaf_by_rank, totals, cycles;
-  DevBuf pp_off, pp_vtx;
   // scans
   DevBuf scan_status, scan_ctr, scalars;
   // test paths
   DevBuf bfs_i32, pfx_off, sfx_off, pfx, sfx;
   DevBuf tp_len, tp_off, tp_vtx, idx0, idx1, grp_cnt, rb0, rb1;
-  DevBuf keep_cnt, keep_len, keep_pos, keep_voff, out_off, out_vtx;
+  DevBuf keep_cnt, keep_len, keep_pos, keep_voff, comp_cnt;
+  // per-level, per-component counts (batched labels)
+  DevBuf lvl_comp;
+  // outputs: out[0] single-graph calls, out[k] the unions of a batch
+  std::vector<OutSet> out;
+  DevBuf b_pp_off, b_pp_vtx, b_tp_off, b_tp_vtx, b_desc;
 
   // pinned host mirrors
   LevelState* h_ls = nullptr;
@@ -54,26 +85,26 @@ tpg_status ws_reserve(tpg_workspace* ws, DevBuf& b, size_t bytes, bool keep = fa
   size_t want = std::max(bytes, b.cap + b.cap / 2);
   want = (want + 255) & ~(size_t)255;
   if (ws->cap && ws->bytes - b.cap + want > ws->cap) {
-    want = bytes;
+    want = (bytes + 255) & ~(size_t)255;
     if (ws->bytes - b.cap + want > ws->cap)
       return fail(TPG_ERR_CAPACITY, "device pool would need %zu bytes (cap %llu)",
                   ws->bytes - b.cap + want, (unsigned long long)ws->cap);
   }
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, want);
+  void* ptr = nullptr;
+  hipError_t e = hipMalloc(&ptr, want);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(TPG_ERR_OOM_DEVICE, "hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
   }
   if (keep && b.p && keep_bytes) {
-    TPG_HIP(hipMemcpyAsync(p, b.p, std::min(keep_bytes, b.cap), hipMemcpyDeviceToDevice, st));
+    TPG_HIP(hipMemcpyAsync(ptr, b.p, std::min(keep_bytes, b.cap), hipMemcpyDeviceToDevice, st));
     TPG_HIP(hipStreamSynchronize(st));
   }
   if (b.p) {
     TPG_HIP(hipFree(b.p));
     ws->bytes -= b.cap;
   }
-  b.p = p;
+  b.p = ptr;
   b.cap = want;
   ws->bytes += want;
   return TPG_OK;
@@ -88,43 +119,62 @@ void ws_release(tpg_workspace* ws, DevBuf& b) {
   b.cap = 0;
 }
 
-int pow2_words(int n) {
-  int w = (n + 63) / 64;
-  int p = 1;
-  while (p < w) p <<= 1;
-  return p;
+void add_component(HostUnion& U, const tpg_graph* g) {
+  const int32_t base = U.n;
+  for (int32_t v = 0; v < g->n; ++v) {
+    for (int32_t k = g->succ_ptr[v]; k < g->succ_ptr[v + 1]; ++k) U.s.push_back(base + g->succ[k]);
+    U.sp.push_back((int32_t)U.s.size());
+    for (int32_t k = g->pred_ptr[v]; k < g->pred_ptr[v + 1]; ++k) U.p.push_back(base + g->pred[k]);
+    U.pp.push_back((int32_t)U.p.size());
+    U.loc.push_back(v);
+    U.comp.push_back(U.n_comp);
+  }
+  U.centry.push_back(base + g->entry);
+  U.cexit.push_back(base + g->exit);
+  U.n += g->n;
+  U.cbase.push_back(U.n);
+  U.n_comp += 1;
+  U.W = std::max(U.W, pow2_words(g->n));
+  U.uids.push_back(g->uid);
 }
 
-tpg_status upload_graph(tpg_workspace* ws, const tpg_graph* g, hipStream_t st) {
-  if (ws->graph_uid == g->uid) return TPG_OK;
-  const size_t n1 = (size_t)g->n + 1, m = g->succ.size();
-  const size_t bytes = sizeof(int32_t) * (2 * n1 + 2 * m + 4);
-  TPG_TRY(ws_reserve(ws, ws->g_csr, bytes));
-  int32_t* base = ws->g_csr.as<int32_t>();
-  int32_t* sp = base;
-  int32_t* s = sp + n1;
-  int32_t* pp = s + m + 1;
-  int32_t* p = pp + n1;
-  TPG_HIP(hipMemcpyAsync(sp, g->succ_ptr.data(), sizeof(int32_t) * n1, hipMemcpyHostToDevice, st));
-  if (m) TPG_HIP(hipMemcpyAsync(s, g->succ.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
-  TPG_HIP(hipMemcpyAsync(pp, g->pred_ptr.data(), sizeof(int32_t) * n1, hipMemcpyHostToDevice, st));
-  if (m) TPG_HIP(hipMemcpyAsync(p, g->pred.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
+tpg_status upload_union(tpg_workspace* ws, const HostUnion& U, hipStream_t st) {
+  if (ws->union_uids == U.uids) return TPG_OK;
+  const size_t n1 = (size_t)U.n + 1, m = U.s.size(), nc = (size_t)U.n_comp;
+  const size_t words = 2 * n1 + 2 * (m + 1) + 2 * (size_t)U.n + (nc + 1) + 2 * nc + 8;
+  TPG_TRY(ws_reserve(ws, ws->g_csr, sizeof(int32_t) * words));
+  int32_t* q = ws->g_csr.as<int32_t>();
+  hipError_t err = hipSuccess;
+  auto put = [&](const std::vector<int32_t>& v, size_t pad) -> int32_t* {
+    int32_t* at = q;
+    if (!v.empty() && err == hipSuccess)
+      err = hipMemcpyAsync(at, v.data(), sizeof(int32_t) * v.size(), hipMemcpyHostToDevice, st);
+    q += v.size() + pad;
+    return at;
+  };
+  DGraph d{};
+  d.sp = put(U.sp, 0);
+  d.s = put(U.s, 1);
+  d.pp = put(U.pp, 0);
+  d.p = put(U.p, 1);
+  d.loc = put(U.loc, 0);
+  d.comp = put(U.comp, 0);
+  d.cbase = put(U.cbase, 0);
+  d.centry = put(U.centry, 0);
+  d.cexit = put(U.cexit, 0);
+  d.n = U.n;
+  d.n_comp = U.n_comp;
+  TPG_HIP(err);
   TPG_HIP(hipStreamSynchronize(st));
-  ws->dg.sp = sp;
-  ws->dg.s = s;
-  ws->dg.pp = pp;
-  ws->dg.p = p;
-  ws->dg.n = g->n;
-  ws->dg.entry = g->entry;
-  ws->dg.exit = g->exit;
-  ws->graph_uid = g->uid;
+  ws->dg = d;
+  ws->union_uids = U.uids;
   return TPG_OK;
 }
 
 tpg_status reserve_tree(tpg_workspace* ws, int64_t rec, int64_t msk, int W, hipStream_t st,
                         int64_t keep_rec, int keep_parity, int64_t keep_mask) {
   if (rec > (int64_t)INT32_MAX - 2)
-    return fail(TPG_ERR_UNSUPPORTED, "more than 2^31 simple paths in one graph");
+    return fail(TPG_ERR_UNSUPPORTED, "more than 2^31 simple paths in one run");
   TPG_TRY(ws_reserve(ws, ws->par, sizeof(int32_t) * rec, keep_rec > 0, st, sizeof(int32_t) * keep_rec));
   TPG_TRY(ws_reserve(ws, ws->info, sizeof(uint32_t) * rec, keep_rec > 0, st, sizeof(uint32_t) * keep_rec));
   TPG_TRY(ws_reserve(ws, ws->cstart, sizeof(int32_t) * (rec + 1), keep_rec > 0, st,
@@ -175,7 +225,6 @@ struct Timer {
   tpg_workspace* ws;
   hipStream_t st;
   bool on;
-  std::vector<hipEvent_t> used;
   size_t next = 0;
   hipEvent_t mark() {
     if (!on) return nullptr;
@@ -201,17 +250,19 @@ struct TreeResult {
   std::vector<int64_t> count, off;
   int64_t n_nodes = 0;
   int64_t n_overflows = 0;
+  int64_t peak = 0;
   double ms_kernel = 0.0;
   int64_t launches = 0;
 };
 
-// Level loop, one-pass device-sized form.
-tpg_status build_tree_onepass(tpg_workspace* ws, const tpg_graph* g, hipStream_t st, Timer& tm,
-                              TreeResult& R) {
-  const int W = pow2_words(g->n);
-  int64_t rec = std::max<int64_t>(ws->rec_cap, (int64_t)g->n * 64 + 4096);
-  int64_t msk = std::max<int64_t>(ws->mask_words == W ? ws->mask_cap : 0, (int64_t)g->n * 16 + 1024);
-  if (ws->mask_words && ws->mask_words != W && ws->mask_cap)
+// Level loop, one-pass device-sized form.  rec0 / msk0: initial capacities
+// (nodes overall / nodes of one level); 0 = what the workspace already has.
+tpg_status build_tree_onepass(tpg_workspace* ws, const HostUnion& U, hipStream_t st, Timer& tm,
+                              TreeResult& R, int64_t rec0, int64_t msk0) {
+  const int W = U.W;
+  int64_t rec = std::max<int64_t>({ws->rec_cap, (int64_t)U.n * 64 + 4096, rec0});
+  int64_t msk = std::max<int64_t>((int64_t)U.n * 16 + 1024, msk0);
+  if (ws->mask_words && ws->mask_cap)
     msk = std::max<int64_t>(msk, ws->mask_cap * ws->mask_words / W);
   TPG_TRY(reserve_tree(ws, rec, msk, W, st, 0, -1, 0));
   ExtArgs a = make_args(ws);
@@ -219,8 +270,9 @@ tpg_status build_tree_onepass(tpg_workspace* ws, const tpg_graph* g, hipStream_t
   const int grid = ws->num_cus * 8;
   int batch = 4;
   int level_before = 1;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
   for (;;) {
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
+    evs.clear();
     for (int b = 0; b < batch; ++b) {
       hipEvent_t e0 = tm.mark();
       TPG_HIP(launch_extend(W, a, grid, st));
@@ -238,13 +290,13 @@ tpg_status build_tree_onepass(tpg_workspace* ws, const tpg_graph* g, hipStream_t
     tm.next = 0;
     level_before = h.level;
     if (h.overflow) {
+      // the level's exact child count is known: grow to it and replay
       const int L = h.level;
-      int64_t hdr[2];
       LevelState* dls = ws->ls.as<LevelState>();
-      TPG_HIP(hipMemcpy(&hdr[0], &dls->off[L], sizeof(int64_t), hipMemcpyDeviceToHost));
-      int64_t cnt[2];
+      int64_t base = 0, cnt[2] = {0, 0};
+      TPG_HIP(hipMemcpy(&base, &dls->off[L], sizeof(int64_t), hipMemcpyDeviceToHost));
       TPG_HIP(hipMemcpy(cnt, &dls->count[L], 2 * sizeof(int64_t), hipMemcpyDeviceToHost));
-      const int64_t base = hdr[0], F = cnt[0], nxt = cnt[1];
+      const int64_t F = cnt[0], nxt = cnt[1];
       const int64_t need_rec = base + F + nxt + 1;
       const int64_t new_rec = std::max<int64_t>(ws->rec_cap, need_rec + need_rec / 4);
       const int64_t new_msk = std::max<int64_t>(ws->mask_cap, nxt + nxt / 4 + 1024);
@@ -257,7 +309,6 @@ tpg_status build_tree_onepass(tpg_workspace* ws, const tpg_graph* g, hipStream_t
     if (h.cur_count == 0) break;
     batch = std::min(batch * 2, 64);
   }
-  // level table
   R.count.assign(kMaxLevels, 0);
   R.off.assign(kMaxLevels, 0);
   LevelState* dls = ws->ls.as<LevelState>();
@@ -266,6 +317,7 @@ tpg_status build_tree_onepass(tpg_workspace* ws, const tpg_graph* g, hipStream_t
   for (int L = 0; L <= R.Lmax + 1; ++L) {
     R.count[L] = ws->h_ls->count[L];
     R.off[L] = ws->h_ls->off[L];
+    R.peak = std::max(R.peak, R.count[L]);
   }
   R.off[R.Lmax + 1] = R.off[R.Lmax] + R.count[R.Lmax];
   R.n_nodes = R.off[R.Lmax + 1];
@@ -273,19 +325,22 @@ tpg_status build_tree_onepass(tpg_workspace* ws, const tpg_graph* g, hipStream_t
 }
 
 // Level loop, plain two-pass form: count -> scan -> host reads the size -> fill.
-tpg_status build_tree_twopass(tpg_workspace* ws, const tpg_graph* g, hipStream_t st, Timer& tm,
+tpg_status build_tree_twopass(tpg_workspace* ws, const HostUnion& U, hipStream_t st, Timer& tm,
                               TreeResult& R) {
-  const int W = pow2_words(g->n);
-  int64_t rec = std::max<int64_t>(ws->rec_cap, (int64_t)g->n + 4096);
-  int64_t msk = std::max<int64_t>(ws->mask_words == W ? ws->mask_cap : 0, (int64_t)g->n + 1024);
+  const int W = U.W;
+  int64_t rec = std::max<int64_t>(ws->rec_cap, (int64_t)U.n + 4096);
+  int64_t msk = (int64_t)U.n + 1024;
+  if (ws->mask_words && ws->mask_cap)
+    msk = std::max<int64_t>(msk, ws->mask_cap * ws->mask_words / W);
   TPG_TRY(reserve_tree(ws, rec, msk, W, st, 0, -1, 0));
   ExtArgs a = make_args(ws);
   TPG_HIP(launch_seed(a, st));
   R.count.assign(kMaxLevels, 0);
   R.off.assign(kMaxLevels, 0);
   int L = 1;
-  int64_t base = 0, F = g->n;
+  int64_t base = 0, F = U.n;
   R.count[1] = F;
+  R.peak = F;
   for (;;) {
     TPG_TRY(reserve_scan(ws, F));
     hipEvent_t e0 = tm.mark();
@@ -317,6 +372,7 @@ tpg_status build_tree_twopass(tpg_workspace* ws, const tpg_graph* g, hipStream_t
     R.launches += 1;
     R.off[L + 1] = base + F;
     R.count[L + 1] = total;
+    R.peak = std::max(R.peak, total);
     base += F;
     F = total;
     ++L;
@@ -331,8 +387,8 @@ struct PPResult {
   int64_t n_pp = 0, n_vtx = 0, n_cycles = 0;
 };
 
-tpg_status rank_and_materialize(tpg_workspace* ws, const tpg_graph* g, hipStream_t st,
-                                const TreeResult& R, PPResult& P) {
+tpg_status rank_and_materialize(tpg_workspace* ws, const HostUnion& U, hipStream_t st,
+                                const TreeResult& R, PPResult& P, OutSet& o) {
   ExtArgs a = make_args(ws);
   const int64_t N = R.n_nodes;
   TPG_TRY(ws_reserve(ws, ws->sub_cnt, sizeof(uint32_t) * N));
@@ -343,7 +399,7 @@ tpg_status rank_and_materialize(tpg_workspace* ws, const tpg_graph* g, hipStream
   for (int L = R.Lmax; L >= 1; --L)
     TPG_HIP(launch_up(a, L, R.off[L], R.count[L], ws->sub_cnt.as<uint32_t>(),
                       ws->sub_len.as<int64_t>(), ws->cycles.as<unsigned long long>(), st));
-  TPG_HIP(launch_roots(a, g->n, ws->sub_cnt.as<uint32_t>(), ws->sub_len.as<int64_t>(), nullptr,
+  TPG_HIP(launch_roots(a, U.n, ws->sub_cnt.as<uint32_t>(), ws->sub_len.as<int64_t>(), nullptr,
                        ws->totals.as<int64_t>(), 0, st));
   TPG_HIP(hipMemcpyAsync(ws->h_scalars, ws->totals.p, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TPG_HIP(hipMemcpyAsync(ws->h_scalars + 2, ws->cycles.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -352,17 +408,23 @@ tpg_status rank_and_materialize(tpg_workspace* ws, const tpg_graph* g, hipStream
   P.n_vtx = ws->h_scalars[1];
   P.n_cycles = ws->h_scalars[2];
   TPG_TRY(ws_reserve(ws, ws->leaf_by_rank, sizeof(int64_t) * (P.n_pp + 1)));
-  TPG_TRY(ws_reserve(ws, ws->pp_off, sizeof(int64_t) * (P.n_pp + 1)));
-  TPG_TRY(ws_reserve(ws, ws->pp_vtx, sizeof(int32_t) * (P.n_vtx + 1)));
-  TPG_HIP(launch_roots(a, g->n, ws->sub_cnt.as<uint32_t>(), ws->sub_len.as<int64_t>(),
+  TPG_TRY(ws_reserve(ws, o.pp_off, sizeof(int64_t) * (P.n_pp + 1)));
+  TPG_TRY(ws_reserve(ws, o.pp_vtx, sizeof(int32_t) * (P.n_vtx + 1)));
+  TPG_TRY(ws_reserve(ws, o.comp_starts, sizeof(int64_t) * 4 * (U.n_comp + 1)));
+  TPG_HIP(launch_roots(a, U.n, ws->sub_cnt.as<uint32_t>(), ws->sub_len.as<int64_t>(),
                        ws->leaf_by_rank.as<int64_t>(), ws->totals.as<int64_t>(), 1, st));
+  int64_t* cs = o.comp_starts.as<int64_t>();
+  TPG_HIP(launch_comp_pp_starts(ws->dg, ws->sub_cnt.as<uint32_t>(), ws->sub_len.as<int64_t>(),
+                                ws->totals.as<int64_t>(), cs, cs + (U.n_comp + 1), st));
   for (int L = 1; L < R.Lmax; ++L)
     TPG_HIP(launch_down(a, R.off[L], R.count[L], ws->sub_cnt.as<uint32_t>(),
                         ws->sub_len.as<int64_t>(), ws->leaf_by_rank.as<int64_t>(), st));
   TPG_HIP(launch_pp_offsets(ws->leaf_by_rank.as<int64_t>(), ws->sub_len.as<int64_t>(), P.n_pp,
-                            P.n_vtx, ws->pp_off.as<int64_t>(), st));
-  TPG_HIP(launch_pp_write(a, ws->leaf_by_rank.as<int64_t>(), ws->pp_off.as<int64_t>(), P.n_pp,
-                          ws->pp_vtx.as<int32_t>(), st));
+                            P.n_vtx, o.pp_off.as<int64_t>(), st));
+  TPG_HIP(launch_pp_write(a, ws->leaf_by_rank.as<int64_t>(), o.pp_off.as<int64_t>(), P.n_pp,
+                          o.pp_vtx.as<int32_t>(), st));
+  o.n_pp = P.n_pp;
+  o.n_ppv = P.n_vtx;
   return TPG_OK;
 }
 
@@ -370,15 +432,17 @@ struct TPResult {
   int64_t n_spliced = 0, n_tp = 0, n_vtx = 0;
 };
 
-tpg_status test_paths_device(tpg_workspace* ws, const tpg_graph* g, hipStream_t st,
-                             const PPResult& P, TPResult& T) {
-  const int n = g->n;
+tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t st,
+                             const PPResult& P, TPResult& T, OutSet& o) {
+  const int n = U.n;
+  const int nc = U.n_comp;
   TPG_TRY(ws_reserve(ws, ws->bfs_i32, sizeof(int32_t) * 4 * (size_t)n));
   TPG_TRY(ws_reserve(ws, ws->pfx_off, sizeof(int64_t) * (n + 1)));
   TPG_TRY(ws_reserve(ws, ws->sfx_off, sizeof(int64_t) * (n + 1)));
-  TPG_TRY(ws_reserve(ws, ws->pfx, sizeof(int32_t) * (size_t)n * n));
-  TPG_TRY(ws_reserve(ws, ws->sfx, sizeof(int32_t) * (size_t)n * n));
-  BfsOut b;
+  const int64_t np = P.n_pp;
+  T.n_spliced = np;
+  TPG_TRY(reserve_scan(ws, std::max<int64_t>(np, n)));
+  BfsOut b{};
   int32_t* bi = ws->bfs_i32.as<int32_t>();
   b.dist_f = bi;
   b.parent = bi + n;
@@ -386,13 +450,13 @@ tpg_status test_paths_device(tpg_workspace* ws, const tpg_graph* g, hipStream_t 
   b.next = bi + 3 * n;
   b.pfx_off = ws->pfx_off.as<int64_t>();
   b.sfx_off = ws->sfx_off.as<int64_t>();
-  b.pfx = ws->pfx.as<int32_t>();
-  b.sfx = ws->sfx.as<int32_t>();
-  TPG_HIP(launch_bfs(ws->dg, b, st));
+  int64_t* sc = ws->scalars.as<int64_t>();
+  TPG_HIP(launch_bfs_dist(ws->dg, b, st));
+  TPG_HIP(scan_i32_to_i64(b.dist_f, b.pfx_off, n, 0, sc + 4, ws->scan_status.as<uint64_t>(),
+                          ws->scan_ctr.as<uint32_t>(), st));
+  TPG_HIP(scan_i32_to_i64(b.dist_b, b.sfx_off, n, 0, sc + 5, ws->scan_status.as<uint64_t>(),
+                          ws->scan_ctr.as<uint32_t>(), st));
 
-  const int64_t np = P.n_pp;
-  T.n_spliced = np;
-  TPG_TRY(reserve_scan(ws, std::max<int64_t>(np, n)));
   TPG_TRY(ws_reserve(ws, ws->tp_len, sizeof(int64_t) * (np + 1)));
   TPG_TRY(ws_reserve(ws, ws->tp_off, sizeof(int64_t) * (np + 1)));
   TPG_TRY(ws_reserve(ws, ws->grp_cnt, sizeof(int32_t) * (n + 1)));
@@ -401,18 +465,23 @@ tpg_status test_paths_device(tpg_workspace* ws, const tpg_graph* g, hipStream_t 
   TPG_TRY(ws_reserve(ws, ws->idx0, sizeof(int32_t) * (np + 1)));
   TPG_TRY(ws_reserve(ws, ws->idx1, sizeof(int32_t) * (np + 1)));
   TPG_HIP(launch_zero_u32(ws->grp_cnt.as<uint32_t>(), n, st));
-  TPG_HIP(launch_tp_len(ws->pp_off.as<int64_t>(), ws->pp_vtx.as<int32_t>(), np, b,
+  TPG_HIP(launch_tp_len(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), np, b,
                         ws->tp_len.as<int64_t>(), ws->grp_cnt.as<int32_t>(), st));
-  int64_t* sc = ws->scalars.as<int64_t>();
   TPG_HIP(scan_i64(ws->tp_len.as<int64_t>(), ws->tp_off.as<int64_t>(), np, 0, sc,
                    ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
   TPG_HIP(scan_i32_to_i64(ws->grp_cnt.as<int32_t>(), ws->rb0.as<int64_t>(), n, 0, sc + 1,
                           ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
   TPG_HIP(hipMemcpyAsync(ws->h_scalars, sc, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TPG_HIP(hipMemcpyAsync(ws->h_scalars + 4, sc + 4, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TPG_HIP(hipStreamSynchronize(st));
   const int64_t tp_total = ws->h_scalars[0];
+  TPG_TRY(ws_reserve(ws, ws->pfx, sizeof(int32_t) * (ws->h_scalars[4] + 1)));
+  TPG_TRY(ws_reserve(ws, ws->sfx, sizeof(int32_t) * (ws->h_scalars[5] + 1)));
+  b.pfx = ws->pfx.as<int32_t>();
+  b.sfx = ws->sfx.as<int32_t>();
+  TPG_HIP(launch_bfs_tables(ws->dg, b, st));
   TPG_TRY(ws_reserve(ws, ws->tp_vtx, sizeof(int32_t) * (tp_total + 1)));
-  TPG_HIP(launch_tp_write(ws->pp_off.as<int64_t>(), ws->pp_vtx.as<int32_t>(), np, b,
+  TPG_HIP(launch_tp_write(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), np, b,
                           ws->tp_off.as<int64_t>(), ws->tp_vtx.as<int32_t>(), ws->idx0.as<int32_t>(),
                           st));
   // merge the per-first-vertex runs
@@ -444,13 +513,28 @@ tpg_status test_paths_device(tpg_workspace* ws, const tpg_graph* g, hipStream_t 
   TPG_HIP(hipStreamSynchronize(st));
   T.n_tp = ws->h_scalars[2];
   T.n_vtx = ws->h_scalars[3];
-  TPG_TRY(ws_reserve(ws, ws->out_off, sizeof(int64_t) * (T.n_tp + 1)));
-  TPG_TRY(ws_reserve(ws, ws->out_vtx, sizeof(int32_t) * (T.n_vtx + 1)));
+  TPG_TRY(ws_reserve(ws, o.tp_off, sizeof(int64_t) * (T.n_tp + 1)));
+  TPG_TRY(ws_reserve(ws, o.tp_vtx, sizeof(int32_t) * (T.n_vtx + 1)));
+  int64_t* cc = nullptr;
+  if (nc > 1) {
+    TPG_TRY(ws_reserve(ws, ws->comp_cnt, sizeof(int64_t) * 2 * (nc + 1)));
+    cc = ws->comp_cnt.as<int64_t>();
+    TPG_HIP(launch_zero_u64(reinterpret_cast<uint64_t*>(cc), 2 * (nc + 1), st));
+  }
   TPG_HIP(launch_gather(ws->tp_off.as<int64_t>(), ws->tp_vtx.as<int32_t>(), ii->as<int32_t>(), np,
                         ws->keep_pos.as<int64_t>(), ws->keep_voff.as<int64_t>(),
-                        ws->keep_len.as<int64_t>(), ws->out_off.as<int64_t>(),
-                        ws->out_vtx.as<int32_t>(), st));
-  TPG_HIP(launch_set_i64(ws->out_off.as<int64_t>() + T.n_tp, sc + 3, st));
+                        ws->keep_len.as<int64_t>(), o.tp_off.as<int64_t>(), o.tp_vtx.as<int32_t>(),
+                        ws->dg.comp, cc, cc ? cc + (nc + 1) : nullptr, st));
+  TPG_HIP(launch_set_i64(o.tp_off.as<int64_t>() + T.n_tp, sc + 3, st));
+  int64_t* cs = o.comp_starts.as<int64_t>();
+  if (nc > 1) {
+    TPG_HIP(scan_i64(cc, cs + 2 * (nc + 1), nc, 0, nullptr, ws->scan_status.as<uint64_t>(),
+                     ws->scan_ctr.as<uint32_t>(), st));
+    TPG_HIP(scan_i64(cc + (nc + 1), cs + 3 * (nc + 1), nc, 0, nullptr,
+                     ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
+  }
+  o.n_tp = T.n_tp;
+  o.n_tpv = T.n_vtx;
   return TPG_OK;
 }
 
@@ -492,8 +576,7 @@ struct CallCtx {
   }
 };
 
-tpg_status begin_call(const tpg_graph* g, const tpg_opts* opts, CallCtx& c) {
-  if (!g) return fail(TPG_ERR_INVALID_ARG, "graph is NULL");
+tpg_status begin_call(const tpg_opts* opts, CallCtx& c) {
   if (opts && opts->struct_size != sizeof(tpg_opts))
     return fail(TPG_ERR_INVALID_ARG, "opts.struct_size = %u, expected %zu", opts->struct_size,
                 sizeof(tpg_opts));
@@ -512,44 +595,45 @@ tpg_status begin_call(const tpg_graph* g, const tpg_opts* opts, CallCtx& c) {
   if (c.ws->cap && c.ws->bytes > c.ws->cap)
     return fail(TPG_ERR_CAPACITY, "workspace already holds %zu bytes (cap %llu)", c.ws->bytes,
                 (unsigned long long)c.ws->cap);
-  TPG_TRY(upload_graph(c.ws, g, c.st));
+  if (c.ws->out.empty()) c.ws->out.resize(1);
   return TPG_OK;
 }
 
-tpg_status run_pp(const tpg_graph* g, CallCtx& c, Timer& tm, TreeResult& R, PPResult& P,
-                  hipEvent_t* e_ext) {
+tpg_status run_pp(const HostUnion& U, CallCtx& c, Timer& tm, TreeResult& R, PPResult& P,
+                  OutSet& o, hipEvent_t* e_ext, int64_t rec0 = 0, int64_t msk0 = 0) {
+  TPG_TRY(upload_union(c.ws, U, c.st));
   if (c.flags & TPG_FORCE_TWO_PASS)
-    TPG_TRY(build_tree_twopass(c.ws, g, c.st, tm, R));
+    TPG_TRY(build_tree_twopass(c.ws, U, c.st, tm, R));
   else
-    TPG_TRY(build_tree_onepass(c.ws, g, c.st, tm, R));
-  *e_ext = tm.mark();
-  TPG_TRY(rank_and_materialize(c.ws, g, c.st, R, P));
+    TPG_TRY(build_tree_onepass(c.ws, U, c.st, tm, R, rec0, msk0));
+  if (e_ext) *e_ext = tm.mark();
+  TPG_TRY(rank_and_materialize(c.ws, U, c.st, R, P, o));
   return TPG_OK;
 }
 
-void fill_stats(CallCtx& c, const tpg_graph* g, const TreeResult& R, const PPResult& P,
-                const TPResult* T) {
-  if (c.opts && c.opts->level_counts && c.opts->level_counts_len > 0) {
-    // acyclic paths per level: nodes minus the cycle closures of that level
-    // are not separated here; report node counts per level
-    for (int L = 0; L < c.opts->level_counts_len; ++L)
-      c.opts->level_counts[L] = (L < (int)R.count.size() && L <= R.Lmax) ? R.count[L] : 0;
+void add_stats(tpg_stats* s, const HostUnion& U, const TreeResult& R, const PPResult& P,
+               const TPResult* T) {
+  s->n_levels = std::max<int64_t>(s->n_levels, R.Lmax);
+  s->n_nodes += R.n_nodes;
+  s->n_extensions += R.n_nodes - U.n;
+  s->n_cycles += P.n_cycles;
+  s->n_pp += P.n_pp;
+  s->n_pp_vertices += P.n_vtx;
+  if (T) {
+    s->n_tp_spliced += T->n_spliced;
+    s->n_tp += T->n_tp;
+    s->n_tp_vertices += T->n_vtx;
   }
-  if (!c.stats) return;
-  tpg_stats* s = c.stats;
-  s->n_levels = R.Lmax;
-  s->n_nodes = R.n_nodes;
-  s->n_extensions = R.n_nodes - g->n;
-  s->n_cycles = P.n_cycles;
-  s->n_pp = P.n_pp;
-  s->n_pp_vertices = P.n_vtx;
-  s->n_tp_spliced = T ? T->n_spliced : 0;
-  s->n_tp = T ? T->n_tp : 0;
-  s->n_tp_vertices = T ? T->n_vtx : 0;
-  s->n_overflows = R.n_overflows;
-  s->device_bytes = (int64_t)c.ws->bytes;
-  s->ms_extend_kernel = R.ms_kernel;
-  s->n_extend_launches = R.launches;
+  s->n_overflows += R.n_overflows;
+  s->ms_extend_kernel += R.ms_kernel;
+  s->n_extend_launches += R.launches;
+  s->peak_level_nodes = std::max<int64_t>(s->peak_level_nodes, R.peak);
+  s->n_unions += 1;
+}
+
+tpg_status check_graph(const tpg_graph* g) {
+  if (!g) return fail(TPG_ERR_INVALID_ARG, "graph is NULL");
+  return TPG_OK;
 }
 
 }  // namespace
@@ -591,6 +675,7 @@ tpg_status tpg_workspace_create(int32_t device, tpg_workspace** out) {
     tpg_workspace_free(ws);
     return fail(TPG_ERR_OOM_HOST, "pinned host buffers");
   }
+  ws->out.resize(1);
   *out = ws;
   return TPG_OK;
 }
@@ -601,12 +686,20 @@ void tpg_workspace_free(tpg_workspace* ws) {
   if (ws->own_stream) (void)hipStreamSynchronize(ws->own_stream);
   DevBuf* bufs[] = {&ws->g_csr, &ws->par, &ws->info, &ws->cstart, &ws->mask0, &ws->mask1,
                     &ws->tile_status, &ws->tile_ctr, &ws->ls, &ws->sub_cnt, &ws->sub_len,
-                    &ws->leaf_by_rank, &ws->totals, &ws->cycles, &ws->pp_off, &ws->pp_vtx,
-                    &ws->scan_status, &ws->scan_ctr, &ws->scalars, &ws->bfs_i32, &ws->pfx_off,
-                    &ws->sfx_off, &ws->pfx, &ws->sfx, &ws->tp_len, &ws->tp_off, &ws->tp_vtx,
-                    &ws->idx0, &ws->idx1, &ws->grp_cnt, &ws->rb0, &ws->rb1, &ws->keep_cnt,
-                    &ws->keep_len, &ws->keep_pos, &ws->keep_voff, &ws->out_off, &ws->out_vtx};
+                    &ws->leaf_by_rank, &ws->totals, &ws->cycles, &ws->scan_status,
+                    &ws->scan_ctr, &ws->scalars, &ws->bfs_i32, &ws->pfx_off, &ws->sfx_off,
+                    &ws->pfx, &ws->sfx, &ws->tp_len, &ws->tp_off, &ws->tp_vtx, &ws->idx0,
+                    &ws->idx1, &ws->grp_cnt, &ws->rb0, &ws->rb1, &ws->keep_cnt, &ws->keep_len,
+                    &ws->keep_pos, &ws->keep_voff, &ws->comp_cnt, &ws->lvl_comp, &ws->b_pp_off,
+                    &ws->b_pp_vtx, &ws->b_tp_off, &ws->b_tp_vtx, &ws->b_desc};
   for (DevBuf* b : bufs) ws_release(ws, *b);
+  for (OutSet& o : ws->out) {
+    ws_release(ws, o.pp_off);
+    ws_release(ws, o.pp_vtx);
+    ws_release(ws, o.tp_off);
+    ws_release(ws, o.tp_vtx);
+    ws_release(ws, o.comp_starts);
+  }
   for (hipEvent_t e : ws->ev_pool) (void)hipEventDestroy(e);
   if (ws->h_ls) (void)hipHostFree(ws->h_ls);
   if (ws->h_scalars) (void)hipHostFree(ws->h_scalars);
@@ -619,8 +712,11 @@ int64_t tpg_workspace_bytes(const tpg_workspace* ws) { return ws ? (int64_t)ws->
 tpg_status tpg_prime_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* out) {
   if (!out) return fail(TPG_ERR_INVALID_ARG, "out is NULL");
   memset(out, 0, sizeof *out);
+  TPG_TRY(check_graph(g));
   CallCtx c;
-  TPG_TRY(begin_call(g, opts, c));
+  TPG_TRY(begin_call(opts, c));
+  HostUnion U;
+  add_component(U, g);
   Timer tm{c.ws, c.st, c.stats != nullptr && !(c.flags & TPG_NO_TIMING)};
   const bool timing = tm.on;
   std::vector<hipEvent_t> phase(2, nullptr);
@@ -631,19 +727,26 @@ tpg_status tpg_prime_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* 
   TreeResult R;
   PPResult P;
   hipEvent_t ext_done = nullptr;
-  tpg_status s = run_pp(g, c, tm, R, P, &ext_done);
+  OutSet& o = c.ws->out[0];
+  tpg_status s = run_pp(U, c, tm, R, P, o, &ext_done);
   if (s == TPG_OK && timing) TPG_HIP(hipEventRecord(phase[1], c.st));
   if (s == TPG_OK)
-    s = export_paths(c.ws->pp_off, c.ws->pp_vtx, P.n_pp, P.n_vtx, c.flags & TPG_OUT_DEVICE, c.st, out);
+    s = export_paths(o.pp_off, o.pp_vtx, P.n_pp, P.n_vtx, c.flags & TPG_OUT_DEVICE, c.st, out);
   if (s == TPG_OK) {
     TPG_HIP(hipStreamSynchronize(c.st));
-    fill_stats(c, g, R, P, nullptr);
-    if (timing && c.stats) {
-      c.stats->ms_extend = Timer::ms(phase[0], ext_done);
-      c.stats->ms_rank = Timer::ms(ext_done, phase[1]);
-      c.stats->ms_tp = 0;
-      c.stats->ms_total = Timer::ms(phase[0], phase[1]);
+    if (c.stats) {
+      memset(c.stats, 0, sizeof *c.stats);
+      add_stats(c.stats, U, R, P, nullptr);
+      c.stats->device_bytes = (int64_t)c.ws->bytes;
+      if (timing) {
+        c.stats->ms_extend = Timer::ms(phase[0], ext_done);
+        c.stats->ms_rank = Timer::ms(ext_done, phase[1]);
+        c.stats->ms_total = Timer::ms(phase[0], phase[1]);
+      }
     }
+    if (c.opts && c.opts->level_counts)
+      for (int L = 0; L < c.opts->level_counts_len; ++L)
+        c.opts->level_counts[L] = (L <= R.Lmax && L < (int)R.count.size()) ? R.count[L] : 0;
   }
   for (auto& e : phase)
     if (e) (void)hipEventDestroy(e);
@@ -655,13 +758,16 @@ tpg_status tpg_test_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* p
   if (!tp_out) return fail(TPG_ERR_INVALID_ARG, "tp_out is NULL");
   memset(tp_out, 0, sizeof *tp_out);
   if (pp_out) memset(pp_out, 0, sizeof *pp_out);
-  if (g && (g->load_flags & TPG_LOAD_ANY_DIGRAPH))
+  TPG_TRY(check_graph(g));
+  if (g->load_flags & TPG_LOAD_ANY_DIGRAPH)
     return fail(TPG_ERR_UNREACHABLE, "test paths need a graph loaded with the entry/exit checks");
   CallCtx c;
-  TPG_TRY(begin_call(g, opts, c));
+  TPG_TRY(begin_call(opts, c));
+  HostUnion U;
+  add_component(U, g);
   Timer tm{c.ws, c.st, c.stats != nullptr && !(c.flags & TPG_NO_TIMING)};
   const bool timing = tm.on;
-  std::vector<hipEvent_t> phase(4, nullptr);
+  std::vector<hipEvent_t> phase(3, nullptr);
   if (timing) {
     for (auto& e : phase) TPG_HIP(hipEventCreate(&e));
     TPG_HIP(hipEventRecord(phase[0], c.st));
@@ -670,22 +776,26 @@ tpg_status tpg_test_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* p
   PPResult P;
   TPResult T;
   hipEvent_t ext_done = nullptr;
-  tpg_status s = run_pp(g, c, tm, R, P, &ext_done);
+  OutSet& o = c.ws->out[0];
+  tpg_status s = run_pp(U, c, tm, R, P, o, &ext_done);
   if (s == TPG_OK && timing) TPG_HIP(hipEventRecord(phase[1], c.st));
-  if (s == TPG_OK) s = test_paths_device(c.ws, g, c.st, P, T);
+  if (s == TPG_OK) s = test_paths_device(c.ws, U, c.st, P, T, o);
   if (s == TPG_OK && timing) TPG_HIP(hipEventRecord(phase[2], c.st));
   const bool dev = c.flags & TPG_OUT_DEVICE;
-  if (s == TPG_OK && pp_out)
-    s = export_paths(c.ws->pp_off, c.ws->pp_vtx, P.n_pp, P.n_vtx, dev, c.st, pp_out);
-  if (s == TPG_OK) s = export_paths(c.ws->out_off, c.ws->out_vtx, T.n_tp, T.n_vtx, dev, c.st, tp_out);
+  if (s == TPG_OK && pp_out) s = export_paths(o.pp_off, o.pp_vtx, P.n_pp, P.n_vtx, dev, c.st, pp_out);
+  if (s == TPG_OK) s = export_paths(o.tp_off, o.tp_vtx, T.n_tp, T.n_vtx, dev, c.st, tp_out);
   if (s == TPG_OK) {
     TPG_HIP(hipStreamSynchronize(c.st));
-    fill_stats(c, g, R, P, &T);
-    if (timing && c.stats) {
-      c.stats->ms_extend = Timer::ms(phase[0], ext_done);
-      c.stats->ms_rank = Timer::ms(ext_done, phase[1]);
-      c.stats->ms_tp = Timer::ms(phase[1], phase[2]);
-      c.stats->ms_total = Timer::ms(phase[0], phase[2]);
+    if (c.stats) {
+      memset(c.stats, 0, sizeof *c.stats);
+      add_stats(c.stats, U, R, P, &T);
+      c.stats->device_bytes = (int64_t)c.ws->bytes;
+      if (timing) {
+        c.stats->ms_extend = Timer::ms(phase[0], ext_done);
+        c.stats->ms_rank = Timer::ms(ext_done, phase[1]);
+        c.stats->ms_tp = Timer::ms(phase[1], phase[2]);
+        c.stats->ms_total = Timer::ms(phase[0], phase[2]);
+      }
     }
   }
   if (s != TPG_OK) {
@@ -695,6 +805,217 @@ tpg_status tpg_test_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* p
   for (auto& e : phase)
     if (e) (void)hipEventDestroy(e);
   return s;
+}
+
+// ---------------------------------------------------------------------------
+// batched form
+// ---------------------------------------------------------------------------
+
+tpg_status tpg_batch_test_paths(const tpg_graph* const* graphs, int32_t n_graphs,
+                                const tpg_opts* opts, const float* predicted,
+                                tpg_batch_result* out) {
+  if (!out) return fail(TPG_ERR_INVALID_ARG, "out is NULL");
+  memset(out, 0, sizeof *out);
+  if (!graphs || n_graphs < 1) return fail(TPG_ERR_INVALID_ARG, "no graphs");
+  for (int32_t i = 0; i < n_graphs; ++i) {
+    TPG_TRY(check_graph(graphs[i]));
+    if (graphs[i]->load_flags & TPG_LOAD_ANY_DIGRAPH)
+      return fail(TPG_ERR_UNREACHABLE, "graph %d was loaded without the entry/exit checks", i);
+  }
+  CallCtx c;
+  TPG_TRY(begin_call(opts, c));
+  tpg_workspace* ws = c.ws;
+  const bool dev = c.flags & TPG_OUT_DEVICE;
+  const bool want_levels = c.opts && c.opts->level_counts &&
+                           (int64_t)c.opts->level_counts_len >= (int64_t)64 * n_graphs;
+  Timer tm{ws, c.st, c.stats != nullptr && !(c.flags & TPG_NO_TIMING)};
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (tm.on) {
+    TPG_HIP(hipEventCreate(&t0));
+    TPG_HIP(hipEventCreate(&t1));
+    TPG_HIP(hipEventRecord(t0, c.st));
+  }
+  if (c.stats) memset(c.stats, 0, sizeof *c.stats);
+
+  // unions: one per visited-set width class, split at 2^17 vertices and, with
+  // predictions and a pool cap, at half the cap of predicted footprint
+  std::vector<std::vector<int32_t>> unions;
+  {
+    std::vector<std::vector<int32_t>> cls(8);
+    for (int32_t i = 0; i < n_graphs; ++i) {
+      const int w = pow2_words(graphs[i]->n);
+      int k = 0;
+      while ((1 << k) < w) ++k;
+      cls[k].push_back(i);
+    }
+    for (int k = 0; k < 8; ++k) {
+      std::vector<int32_t> cur;
+      int64_t nv = 0;
+      double mem = 0;
+      for (int32_t i : cls[k]) {
+        double gm = 0;
+        if (predicted && ws->cap) {
+          for (int L = 0; L < 64; ++L) gm += std::expm1((double)predicted[(size_t)i * 65 + L]);
+          gm *= 24.0 + 2.0 * 8.0 * (1 << k);
+        }
+        if (!cur.empty() && (nv + graphs[i]->n > kMaxUnionVertices ||
+                             (ws->cap && mem + gm > 0.5 * (double)ws->cap))) {
+          unions.push_back(cur);
+          cur.clear();
+          nv = 0;
+          mem = 0;
+        }
+        cur.push_back(i);
+        nv += graphs[i]->n;
+        mem += gm;
+      }
+      if (!cur.empty()) unions.push_back(cur);
+    }
+  }
+  if (ws->out.size() < unions.size() + 1) ws->out.resize(unions.size() + 1);
+
+  std::vector<int32_t> g_union(n_graphs), g_comp(n_graphs);
+  std::vector<std::vector<int64_t>> starts(unions.size());
+  for (size_t u = 0; u < unions.size(); ++u) {
+    HostUnion U;
+    for (size_t k = 0; k < unions[u].size(); ++k) {
+      const int32_t i = unions[u][k];
+      add_component(U, graphs[i]);
+      g_union[i] = (int32_t)u;
+      g_comp[i] = (int32_t)k;
+    }
+    int64_t rec0 = 0, msk0 = 0;
+    if (predicted) {
+      // capacities from the predicted per-level path counts, 25% margin
+      std::vector<double> lv(64, 0.0);
+      for (int32_t i : unions[u])
+        for (int L = 0; L < 64; ++L)
+          lv[L] += std::max(0.0, std::expm1((double)predicted[(size_t)i * 65 + L]));
+      double tot = 0, peak = 0;
+      for (double x : lv) {
+        tot += x;
+        peak = std::max(peak, x);
+      }
+      rec0 = (int64_t)(1.25 * tot) + U.n + 1024;
+      msk0 = (int64_t)(1.25 * peak) + 1024;
+      if (c.stats) {
+        c.stats->pred_nodes += (int64_t)tot;
+        c.stats->pred_peak_level_nodes =
+            std::max<int64_t>(c.stats->pred_peak_level_nodes, (int64_t)peak);
+      }
+    }
+    OutSet& o = ws->out[u + 1];
+    TreeResult R;
+    PPResult P;
+    TPResult T;
+    TPG_TRY(run_pp(U, c, tm, R, P, o, nullptr, rec0, msk0));
+    TPG_TRY(test_paths_device(ws, U, c.st, P, T, o));
+    const int nc = U.n_comp;
+    if (want_levels) {
+      // per-graph path counts of levels 1..64 (deeper levels pooled into 64)
+      TPG_TRY(ws_reserve(ws, ws->lvl_comp, sizeof(int64_t) * 64 * (size_t)nc));
+      TPG_HIP(launch_zero_u64(ws->lvl_comp.as<uint64_t>(), 64 * (int64_t)nc, c.st));
+      ExtArgs a = make_args(ws);
+      for (int L = 1; L <= R.Lmax; ++L)
+        TPG_HIP(launch_level_comp_counts(a, L, R.off[L], R.count[L], ws->lvl_comp.as<int64_t>(),
+                                         c.st));
+      std::vector<int64_t> h((size_t)64 * nc);
+      TPG_HIP(hipMemcpyAsync(h.data(), ws->lvl_comp.p, sizeof(int64_t) * h.size(),
+                             hipMemcpyDeviceToHost, c.st));
+      TPG_HIP(hipStreamSynchronize(c.st));
+      for (size_t k = 0; k < unions[u].size(); ++k)
+        memcpy(c.opts->level_counts + (size_t)64 * unions[u][k], h.data() + 64 * k,
+               sizeof(int64_t) * 64);
+    }
+    // graph-wide ids -> ids of each graph; per-graph output starts
+    TPG_HIP(launch_localize(ws->dg.loc, o.pp_vtx.as<int32_t>(), o.n_ppv, c.st));
+    TPG_HIP(launch_localize(ws->dg.loc, o.tp_vtx.as<int32_t>(), o.n_tpv, c.st));
+    starts[u].assign((size_t)4 * (nc + 1), 0);
+    if (nc == 1) {
+      starts[u] = {0, o.n_pp, 0, o.n_ppv, 0, o.n_tp, 0, o.n_tpv};
+    } else {
+      TPG_HIP(hipMemcpyAsync(starts[u].data(), o.comp_starts.p, sizeof(int64_t) * starts[u].size(),
+                             hipMemcpyDeviceToHost, c.st));
+      TPG_HIP(hipStreamSynchronize(c.st));
+      starts[u][2 * (nc + 1) + nc] = o.n_tp;
+      starts[u][3 * (nc + 1) + nc] = o.n_tpv;
+    }
+    if (c.stats) add_stats(c.stats, U, R, P, &T);
+  }
+
+  // pack the unions' outputs graph by graph in caller order
+  std::vector<PackDesc> d_pp(n_graphs), d_tp(n_graphs);
+  std::vector<int64_t> pp_first(n_graphs + 1, 0), tp_first(n_graphs + 1, 0);
+  int64_t ppv = 0, tpv = 0;
+  for (int32_t i = 0; i < n_graphs; ++i) {
+    const auto& S = starts[g_union[i]];
+    const int nc = (int)unions[g_union[i]].size();
+    const int k = g_comp[i];
+    const int64_t p0 = S[k], p1 = S[k + 1], v0 = S[(nc + 1) + k], v1 = S[(nc + 1) + k + 1];
+    const int64_t q0 = S[2 * (nc + 1) + k], q1 = S[2 * (nc + 1) + k + 1];
+    const int64_t w0 = S[3 * (nc + 1) + k], w1 = S[3 * (nc + 1) + k + 1];
+    d_pp[i] = PackDesc{p0, p1 - p0, v0, v1 - v0, pp_first[i], ppv, g_union[i], 0};
+    d_tp[i] = PackDesc{q0, q1 - q0, w0, w1 - w0, tp_first[i], tpv, g_union[i], 0};
+    pp_first[i + 1] = pp_first[i] + (p1 - p0);
+    tp_first[i + 1] = tp_first[i] + (q1 - q0);
+    ppv += v1 - v0;
+    tpv += w1 - w0;
+  }
+  TPG_TRY(ws_reserve(ws, ws->b_pp_off, sizeof(int64_t) * (pp_first[n_graphs] + 1)));
+  TPG_TRY(ws_reserve(ws, ws->b_pp_vtx, sizeof(int32_t) * (ppv + 1)));
+  TPG_TRY(ws_reserve(ws, ws->b_tp_off, sizeof(int64_t) * (tp_first[n_graphs] + 1)));
+  TPG_TRY(ws_reserve(ws, ws->b_tp_vtx, sizeof(int32_t) * (tpv + 1)));
+  TPG_TRY(ws_reserve(ws, ws->b_desc, sizeof(PackDesc) * 2 * (size_t)n_graphs));
+  PackDesc* dd = ws->b_desc.as<PackDesc>();
+  TPG_HIP(hipMemcpyAsync(dd, d_pp.data(), sizeof(PackDesc) * n_graphs, hipMemcpyHostToDevice, c.st));
+  TPG_HIP(hipMemcpyAsync(dd + n_graphs, d_tp.data(), sizeof(PackDesc) * n_graphs,
+                         hipMemcpyHostToDevice, c.st));
+  for (size_t u = 0; u < unions.size(); ++u) {
+    OutSet& o = ws->out[u + 1];
+    TPG_HIP(launch_pack(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), dd, n_graphs, (int32_t)u,
+                        ws->b_pp_off.as<int64_t>(), ws->b_pp_vtx.as<int32_t>(), c.st));
+    TPG_HIP(launch_pack(o.tp_off.as<int64_t>(), o.tp_vtx.as<int32_t>(), dd + n_graphs, n_graphs,
+                        (int32_t)u, ws->b_tp_off.as<int64_t>(), ws->b_tp_vtx.as<int32_t>(), c.st));
+  }
+  TPG_HIP(launch_set_value_i64(ws->b_pp_off.as<int64_t>() + pp_first[n_graphs], ppv, c.st));
+  TPG_HIP(launch_set_value_i64(ws->b_tp_off.as<int64_t>() + tp_first[n_graphs], tpv, c.st));
+  if (tm.on) TPG_HIP(hipEventRecord(t1, c.st));
+
+  tpg_status s = export_paths(ws->b_pp_off, ws->b_pp_vtx, pp_first[n_graphs], ppv, dev, c.st, &out->pp);
+  if (s == TPG_OK)
+    s = export_paths(ws->b_tp_off, ws->b_tp_vtx, tp_first[n_graphs], tpv, dev, c.st, &out->tp);
+  if (s == TPG_OK) {
+    out->n_graphs = n_graphs;
+    out->pp_first = (int64_t*)malloc(sizeof(int64_t) * (n_graphs + 1));
+    out->tp_first = (int64_t*)malloc(sizeof(int64_t) * (n_graphs + 1));
+    if (!out->pp_first || !out->tp_first) {
+      s = fail(TPG_ERR_OOM_HOST, "batch index arrays");
+    } else {
+      memcpy(out->pp_first, pp_first.data(), sizeof(int64_t) * (n_graphs + 1));
+      memcpy(out->tp_first, tp_first.data(), sizeof(int64_t) * (n_graphs + 1));
+    }
+  }
+  if (s == TPG_OK) {
+    TPG_HIP(hipStreamSynchronize(c.st));
+    if (c.stats) {
+      c.stats->device_bytes = (int64_t)ws->bytes;
+      if (tm.on) c.stats->ms_total = Timer::ms(t0, t1);
+    }
+  } else {
+    tpg_batch_result_free(out);
+  }
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  return s;
+}
+
+void tpg_batch_result_free(tpg_batch_result* r) {
+  if (!r) return;
+  tpg_paths_free(&r->pp);
+  tpg_paths_free(&r->tp);
+  free(r->pp_first);
+  free(r->tp_first);
+  memset(r, 0, sizeof *r);
 }
 
 }  // extern "C"

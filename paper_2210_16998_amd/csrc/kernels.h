@@ -90,11 +90,19 @@ struct BfsOut {
   int32_t* dist_b;   // [n] arcs to exit
   int32_t* next;     // [n] first step of the smallest shortest path to exit
   int64_t* pfx_off;  // [n+1] prefix table offsets (entries before v)
-  int32_t* pfx;      // [n*n]
+  int32_t* pfx;      // [pfx_off[n]]
   int64_t* sfx_off;  // [n+1] suffix table offsets (entries after v)
-  int32_t* sfx;      // [n*n]
+  int32_t* sfx;      // [sfx_off[n]]
 };
-hipError_t launch_bfs(const DGraph& g, const BfsOut& b, hipStream_t st);
+// one workgroup per component: dist_f, parent, dist_b, next
+hipError_t launch_bfs_dist(const DGraph& g, const BfsOut& b, hipStream_t st);
+// after pfx_off / sfx_off are scans of dist_f / dist_b: fill pfx / sfx
+hipError_t launch_bfs_tables(const DGraph& g, const BfsOut& b, hipStream_t st);
+hipError_t launch_localize(const int32_t* loc, int32_t* v, int64_t n, hipStream_t st);
+// per-component output starts: pp_start[c] = rank of the first PP of c, etc.
+hipError_t launch_comp_pp_starts(const DGraph& g, const uint32_t* sub_cnt, const int64_t* sub_len,
+                                 const int64_t* totals, int64_t* pp_start, int64_t* ppv_start,
+                                 hipStream_t st);
 
 hipError_t launch_tp_len(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp,
                          const BfsOut& b, int64_t* tp_len, int32_t* grp_cnt, hipStream_t st);
@@ -108,10 +116,30 @@ hipError_t launch_merge_round(const int64_t* tp_off, const int32_t* tp_vtx, cons
 hipError_t launch_next_runs(const int64_t* rb, int64_t n_runs, int64_t* rb_out, hipStream_t st);
 hipError_t launch_dedup_flags(const int64_t* tp_off, const int32_t* tp_vtx, const int32_t* idx,
                               int64_t n, int64_t* keep_cnt, int64_t* keep_len, hipStream_t st);
+// comp_cnt / comp_vcnt (optional, zeroed): kept TPs and their entries per
+// component of their first vertex
 hipError_t launch_gather(const int64_t* tp_off, const int32_t* tp_vtx, const int32_t* idx,
                          int64_t n, const int64_t* keep_pos, const int64_t* keep_voff,
                          const int64_t* keep_len, int64_t* out_off, int32_t* out_vtx,
+                         const int32_t* comp, int64_t* comp_cnt, int64_t* comp_vcnt,
                          hipStream_t st);
 hipError_t launch_set_i64(int64_t* p, const int64_t* src, hipStream_t st);
+hipError_t launch_set_value_i64(int64_t* p, int64_t value, hipStream_t st);
+
+// --- batched form --------------------------------------------------------------
+// One graph's segment of a union's output, and where it goes in the packed
+// output (caller order).
+struct PackDesc {
+  int64_t src_path, n_paths, src_v0, n_v;
+  int64_t dst_path, dst_v;
+  int32_t union_id, pad;
+};
+// copies the segments of union `union_id` (one workgroup per descriptor)
+hipError_t launch_pack(const int64_t* src_off, const int32_t* src_vtx, const PackDesc* d,
+                       int32_t n_desc, int32_t union_id, int64_t* dst_off, int32_t* dst_vtx,
+                       hipStream_t st);
+// lvl_comp[c * 64 + min(L, 64) - 1] += paths of level L in component c
+hipError_t launch_level_comp_counts(const ExtArgs& a, int L, int64_t base, int64_t F,
+                                    int64_t* lvl_comp, hipStream_t st);
 
 }  // namespace tpg

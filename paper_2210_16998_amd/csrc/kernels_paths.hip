@@ -58,13 +58,14 @@ __global__ void k_seed(ExtArgs a) {
   if (i < n) {
     const int v = (int)i;
     a.t.par[v] = -1;
-    a.t.info[v] = make_info(v, v, 0);
+    a.t.info[v] = make_info(v, a.g.loc[v], 0);
   }
-  // masks of level 1 (parity 1): one bit each
+  // masks of level 1 (parity 1): one bit each, at the vertex's local id
   const int W = a.t.mask_words;
   for (int64_t k = i; k < (int64_t)n * W; k += (int64_t)gridDim.x * blockDim.x) {
     const int v = (int)(k / W), q = (int)(k % W);
-    a.t.mask[1][k] = (q == (v >> 6)) ? (1ull << (v & 63)) : 0ull;
+    const int l = a.g.loc[v];
+    a.t.mask[1][k] = (q == (l >> 6)) ? (1ull << (l & 63)) : 0ull;
   }
 }
 
@@ -97,16 +98,20 @@ hipError_t launch_resume_fix(const ExtArgs& a, int level, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // shared per-parent step: choice mask over successor slots + terminal filter
 // ---------------------------------------------------------------------------
+// Choice mask over the successor slots of the path's last vertex v: slot k
+// is set when successor w is not on the path, or is its first vertex (closes
+// a cycle).  base = graph-wide id of local id 0 of v's component.
 template <int W>
 __device__ __forceinline__ uint64_t choices(const DGraph& g, uint32_t inf, const uint64_t (&m)[W],
-                                            int& k0) {
-  const int v = node_v(inf), v1 = node_v1(inf);
+                                            int& k0, int& base) {
+  const int v = node_v(inf), v1l = node_v1l(inf);
+  base = v - g.loc[v];
   k0 = g.sp[v];
   const int k1 = g.sp[v + 1];
   uint64_t vm = 0;
   for (int k = k0; k < k1; ++k) {
-    const int w = g.s[k];
-    const bool ok = (w == v1) || !mask_has<W>(m, w);
+    const int wl = g.s[k] - base;
+    const bool ok = (wl == v1l) || !mask_has<W>(m, wl);
     vm |= ok ? (1ull << (k - k0)) : 0ull;
   }
   return vm;
@@ -115,9 +120,11 @@ __device__ __forceinline__ uint64_t choices(const DGraph& g, uint32_t inf, const
 // Backward-extendability test of a terminal path: prime iff every
 // predecessor of its first vertex is on it.
 template <int W>
-__device__ __forceinline__ bool all_preds_on(const DGraph& g, int v1, const uint64_t (&m)[W]) {
+__device__ __forceinline__ bool all_preds_on(const DGraph& g, int base, int v1l,
+                                             const uint64_t (&m)[W]) {
+  const int v1 = base + v1l;
   for (int k = g.pp[v1]; k < g.pp[v1 + 1]; ++k)
-    if (!mask_has<W>(m, g.p[k])) return false;
+    if (!mask_has<W>(m, g.p[k] - base)) return false;
   return true;
 }
 
@@ -166,6 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_extend(ExtArgs a) {
   __shared__ uint64_t s_vm[kBlock];
   __shared__ uint32_t s_inf[kBlock];
   __shared__ int32_t s_kk[kBlock];
+  __shared__ int32_t s_cb[kBlock];
   __shared__ uint64_t s_mask[kLdsMask ? kBlock * W : 1];
   __shared__ int32_t s_w[kBlock / 64];
 
@@ -201,12 +209,12 @@ __global__ __launch_bounds__(kBlock) void k_extend(ExtArgs a) {
 #pragma unroll
     for (int q = 0; q < W; ++q) m[q] = 0;
     uint64_t vm = 0;
-    int k0 = 0;
+    int k0 = 0, cb = 0;
     if (!(inf & F_CYC)) {
       load_mask<W>(mcur + j * W, m);
-      vm = choices<W>(a.g, inf, m, k0);
+      vm = choices<W>(a.g, inf, m, k0, cb);
       if (vm == 0) {
-        const bool pp = all_preds_on<W>(a.g, node_v1(inf), m);
+        const bool pp = all_preds_on<W>(a.g, cb, node_v1l(inf), m);
         inf |= F_TERM | (pp ? F_PP : 0u);
         a.t.info[base + j] = inf;
       }
@@ -219,6 +227,7 @@ __global__ __launch_bounds__(kBlock) void k_extend(ExtArgs a) {
     s_vm[tid] = vm;
     s_inf[tid] = inf;
     s_kk[tid] = k0;
+    s_cb[tid] = cb;
     if constexpr (kLdsMask) {
 #pragma unroll
       for (int q = 0; q < W; ++q) s_mask[tid * W + q] = m[q];
@@ -247,15 +256,16 @@ __global__ __launch_bounds__(kBlock) void k_extend(ExtArgs a) {
       const int o = lo;
       const int slot = select_bit(s_vm[o], k - s_off[o]);
       const uint32_t pinf = s_inf[o];
-      const int v1 = node_v1(pinf);
+      const int v1l = node_v1l(pinf);
       const int w = a.g.s[s_kk[o] + slot];
+      const int wl = w - s_cb[o];
       const int64_t cl = prefix + k;
       const int64_t cg = nbase + cl;
       if (cg < a.t.rec_cap) {
         a.t.par[cg] = (int32_t)(base + t * kBlock + o);
-        a.t.info[cg] = make_info(w, v1, w == v1 ? F_CYC : 0u);
+        a.t.info[cg] = make_info(w, v1l, wl == v1l ? F_CYC : 0u);
       }
-      if (w != v1 && cl < a.t.mask_cap) {
+      if (wl != v1l && cl < a.t.mask_cap) {
         uint64_t pm[W];
         if constexpr (kLdsMask) {
 #pragma unroll
@@ -263,7 +273,7 @@ __global__ __launch_bounds__(kBlock) void k_extend(ExtArgs a) {
         } else {
           load_mask<W>(mcur + (t * kBlock + o) * W, pm);
         }
-        store_child_mask<W>(mnxt + cl * W, pm, w);
+        store_child_mask<W>(mnxt + cl * W, pm, wl);
       }
     }
     __syncthreads();
@@ -314,11 +324,11 @@ __global__ __launch_bounds__(kBlock) void k_count(ExtArgs a, int L, int64_t base
   if (!(inf & F_CYC)) {
     uint64_t m[W];
     load_mask<W>(a.t.mask[L & 1] + j * W, m);
-    int k0;
-    const uint64_t vm = choices<W>(a.g, inf, m, k0);
+    int k0, cb;
+    const uint64_t vm = choices<W>(a.g, inf, m, k0, cb);
     cnt = __builtin_popcountll(vm);
     if (cnt == 0) {
-      const bool pp = all_preds_on<W>(a.g, node_v1(inf), m);
+      const bool pp = all_preds_on<W>(a.g, cb, node_v1l(inf), m);
       a.t.info[base + j] = inf | F_TERM | (pp ? F_PP : 0u);
     }
   }
@@ -333,9 +343,9 @@ __global__ __launch_bounds__(kBlock) void k_fill(ExtArgs a, int L, int64_t base,
   if (inf & F_CYC) return;
   uint64_t m[W];
   load_mask<W>(a.t.mask[L & 1] + j * W, m);
-  int k0;
-  uint64_t vm = choices<W>(a.g, inf, m, k0);
-  const int v1 = node_v1(inf);
+  int k0, cb;
+  uint64_t vm = choices<W>(a.g, inf, m, k0, cb);
+  const int v1l = node_v1l(inf);
   const int64_t nbase = base + F;
   int64_t c = a.t.cstart[base + j];
   uint64_t* mnxt = a.t.mask[(L + 1) & 1];
@@ -343,9 +353,10 @@ __global__ __launch_bounds__(kBlock) void k_fill(ExtArgs a, int L, int64_t base,
     const int slot = __builtin_ctzll(vm);
     vm &= vm - 1;
     const int w = a.g.s[k0 + slot];
+    const int wl = w - cb;
     a.t.par[c] = (int32_t)(base + j);
-    a.t.info[c] = make_info(w, v1, w == v1 ? F_CYC : 0u);
-    if (w != v1) store_child_mask<W>(mnxt + (c - nbase) * W, m, w);
+    a.t.info[c] = make_info(w, v1l, wl == v1l ? F_CYC : 0u);
+    if (wl != v1l) store_child_mask<W>(mnxt + (c - nbase) * W, m, wl);
     ++c;
   }
 }
@@ -518,6 +529,47 @@ hipError_t launch_pp_write(const ExtArgs& a, const int64_t* leaf_by_rank, const 
   if (n_pp == 0) return hipSuccess;
   k_pp_write<<<(unsigned)((n_pp + kBlock - 1) / kBlock), kBlock, 0, st>>>(a, leaf_by_rank, pp_off,
                                                                           n_pp, pp_vtx);
+  return hipGetLastError();
+}
+
+}  // namespace tpg
+
+namespace tpg {
+
+__global__ void k_comp_pp_starts(DGraph g, const uint32_t* sub_cnt, const int64_t* sub_len,
+                                 const int64_t* totals, int64_t* pp_start, int64_t* ppv_start) {
+  const int c = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (c < g.n_comp) {
+    pp_start[c] = sub_cnt[g.cbase[c]];
+    ppv_start[c] = sub_len[g.cbase[c]];
+  }
+  if (c == g.n_comp) {
+    pp_start[c] = totals[0];
+    ppv_start[c] = totals[1];
+  }
+}
+
+hipError_t launch_comp_pp_starts(const DGraph& g, const uint32_t* sub_cnt, const int64_t* sub_len,
+                                 const int64_t* totals, int64_t* pp_start, int64_t* ppv_start,
+                                 hipStream_t st) {
+  k_comp_pp_starts<<<(unsigned)((g.n_comp + 1 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+      g, sub_cnt, sub_len, totals, pp_start, ppv_start);
+  return hipGetLastError();
+}
+
+__global__ void k_level_comp_counts(ExtArgs a, int L, int64_t base, int64_t F, int64_t* lvl) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= F) return;
+  const int c = a.g.comp[node_v(a.t.info[base + j])];
+  const int b = (L < 64 ? L : 64) - 1;
+  atomicAdd((unsigned long long*)&lvl[(int64_t)c * 64 + b], 1ull);
+}
+
+hipError_t launch_level_comp_counts(const ExtArgs& a, int L, int64_t base, int64_t F,
+                                    int64_t* lvl_comp, hipStream_t st) {
+  if (F == 0) return hipSuccess;
+  k_level_comp_counts<<<(unsigned)((F + kBlock - 1) / kBlock), kBlock, 0, st>>>(a, L, base, F,
+                                                                                lvl_comp);
   return hipGetLastError();
 }
 

@@ -34,6 +34,11 @@ hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t st) {
 }
 
 __global__ void k_set_i64(int64_t* p, const int64_t* src) { *p = *src; }
+__global__ void k_set_value_i64(int64_t* p, int64_t v) { *p = v; }
+hipError_t launch_set_value_i64(int64_t* p, int64_t value, hipStream_t st) {
+  k_set_value_i64<<<1, 1, 0, st>>>(p, value);
+  return hipGetLastError();
+}
 hipError_t launch_set_i64(int64_t* p, const int64_t* src, hipStream_t st) {
   k_set_i64<<<1, 1, 0, st>>>(p, src);
   return hipGetLastError();

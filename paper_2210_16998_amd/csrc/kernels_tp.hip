@@ -26,83 +26,91 @@
 
 namespace tpg {
 
-constexpr int kBfsThreads = 1024;
+constexpr int kBfsThreads = 256;
+constexpr int kMaxComp = 4096;  // vertices per component
 
-// exclusive scan of data[0..m) in place, m <= 4 * kBfsThreads
-__device__ __forceinline__ void chunk_excl_scan4(int16_t* data, int m, int& total, int32_t* s_w) {
-  const int b = (int)threadIdx.x * 4;
-  int v[4];
-  int sum = 0;
+// Exclusive scan of data[0..m) in place (m <= kMaxComp), in chunks of
+// 4 * kBfsThreads; returns the total.
+__device__ int lds_excl_scan(int16_t* data, int m, int32_t* s_w) {
+  int carry = 0;
+  for (int c0 = 0; c0 < m; c0 += 4 * kBfsThreads) {
+    const int b = c0 + (int)threadIdx.x * 4;
+    int v[4];
+    int sum = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    v[k] = (b + k < m) ? (int)data[b + k] : 0;
-    sum += v[k];
-  }
-  __syncthreads();
-  int pre = block_excl_scan<kBfsThreads, int>(sum, total, s_w);
+    for (int k = 0; k < 4; ++k) {
+      v[k] = (b + k < m) ? (int)data[b + k] : 0;
+      sum += v[k];
+    }
+    int tot;
+    int pre = block_excl_scan<kBfsThreads, int>(sum, tot, s_w) + carry;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if (b + k < m) data[b + k] = (int16_t)pre;
-    pre += v[k];
+    for (int k = 0; k < 4; ++k) {
+      if (b + k < m) data[b + k] = (int16_t)pre;
+      pre += v[k];
+    }
+    carry += tot;
+    __syncthreads();
   }
-  __syncthreads();
+  return carry;
 }
 
-__global__ __launch_bounds__(kBfsThreads) void k_bfs(DGraph g, BfsOut b) {
-  __shared__ int16_t s_df[4096];
-  __shared__ int16_t s_db[4096];
-  __shared__ int32_t s_best[4096];
-  __shared__ int16_t s_layer[2][4096];
-  __shared__ int16_t s_cnt[4096];
+// One workgroup per component: distances from the entry with the FIFO
+// (smallest discoverer) parent, distances to the exit, and next[].
+__global__ __launch_bounds__(kBfsThreads) void k_bfs_dist(DGraph g, BfsOut b) {
+  __shared__ int16_t s_df[kMaxComp];
+  __shared__ int16_t s_db[kMaxComp];
+  __shared__ int32_t s_best[kMaxComp];
+  __shared__ int16_t s_layer[2][kMaxComp];
+  __shared__ int16_t s_cnt[kMaxComp];
   __shared__ int32_t s_w[kBfsThreads / 64];
-  __shared__ int64_t s_w64[kBfsThreads / 64];
   __shared__ int32_t s_m;
-  const int n = g.n;
+  const int c = (int)blockIdx.x;
+  const int base = g.cbase[c];
+  const int nc = g.cbase[c + 1] - base;
   const int tid = (int)threadIdx.x;
-  for (int v = tid; v < n; v += kBfsThreads) {
+  for (int v = tid; v < nc; v += kBfsThreads) {
     s_df[v] = -1;
     s_db[v] = -1;
     s_best[v] = INT_MAX;
-    b.parent[v] = -1;
-    b.next[v] = -1;
+    b.parent[base + v] = -1;
+    b.next[base + v] = -1;
   }
   __syncthreads();
-  // forward, with the FIFO tie-break
   if (tid == 0) {
-    s_df[g.entry] = 0;
-    s_layer[0][0] = (int16_t)g.entry;
+    s_df[g.centry[c] - base] = 0;
+    s_layer[0][0] = (int16_t)(g.centry[c] - base);
   }
   __syncthreads();
   int cur = 0, m = 1, d = 0;
   while (m > 0) {
     for (int q = tid; q < m; q += kBfsThreads) {
-      const int u = s_layer[cur][q];
+      const int u = base + s_layer[cur][q];
       for (int k = g.sp[u]; k < g.sp[u + 1]; ++k) {
-        const int w = g.s[k];
-        if (s_df[w] == -1) atomicMin(&s_best[w], q * 64 + (k - g.sp[u]));
+        const int wl = g.s[k] - base;
+        if (s_df[wl] == -1) atomicMin(&s_best[wl], q * 64 + (k - g.sp[u]));
       }
     }
     __syncthreads();
     for (int q = tid; q < m; q += kBfsThreads) {
-      const int u = s_layer[cur][q];
-      int c = 0;
+      const int u = base + s_layer[cur][q];
+      int cnt = 0;
       for (int k = g.sp[u]; k < g.sp[u + 1]; ++k) {
-        const int w = g.s[k];
-        if (s_df[w] == -1 && s_best[w] == q * 64 + (k - g.sp[u])) ++c;
+        const int wl = g.s[k] - base;
+        if (s_df[wl] == -1 && s_best[wl] == q * 64 + (k - g.sp[u])) ++cnt;
       }
-      s_cnt[q] = (int16_t)c;
+      s_cnt[q] = (int16_t)cnt;
     }
     __syncthreads();
-    int m2;
-    chunk_excl_scan4(s_cnt, m, m2, s_w);
+    const int m2 = lds_excl_scan(s_cnt, m, s_w);
     for (int q = tid; q < m; q += kBfsThreads) {
-      const int u = s_layer[cur][q];
-      int c = s_cnt[q];
+      const int u = base + s_layer[cur][q];
+      int pos = s_cnt[q];
       for (int k = g.sp[u]; k < g.sp[u + 1]; ++k) {
-        const int w = g.s[k];
-        if (s_df[w] == -1 && s_best[w] == q * 64 + (k - g.sp[u])) {
-          s_layer[cur ^ 1][c++] = (int16_t)w;
-          b.parent[w] = u;
+        const int wl = g.s[k] - base;
+        if (s_df[wl] == -1 && s_best[wl] == q * 64 + (k - g.sp[u])) {
+          s_layer[cur ^ 1][pos++] = (int16_t)wl;
+          b.parent[base + wl] = u;
         }
       }
     }
@@ -113,12 +121,14 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs(DGraph g, BfsOut b) {
     m = m2;
     ++d;
   }
-  // reverse search from the exit (distances only)
-  for (int v = tid; v < n; v += kBfsThreads) s_best[v] = 0;
+  // distances to the exit (reverse search; order does not matter)
+  for (int v = tid; v < nc; v += kBfsThreads) s_best[v] = 0;
+  __syncthreads();
   if (tid == 0) {
-    s_db[g.exit] = 0;
-    s_layer[0][0] = (int16_t)g.exit;
-    s_best[g.exit] = 1;
+    const int xl = g.cexit[c] - base;
+    s_db[xl] = 0;
+    s_layer[0][0] = (int16_t)xl;
+    s_best[xl] = 1;
   }
   __syncthreads();
   cur = 0;
@@ -128,10 +138,10 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs(DGraph g, BfsOut b) {
     if (tid == 0) s_m = 0;
     __syncthreads();
     for (int q = tid; q < m; q += kBfsThreads) {
-      const int u = s_layer[cur][q];
+      const int u = base + s_layer[cur][q];
       for (int k = g.pp[u]; k < g.pp[u + 1]; ++k) {
-        const int w = g.p[k];
-        if (atomicExch(&s_best[w], 1) == 0) s_layer[cur ^ 1][atomicAdd(&s_m, 1)] = (int16_t)w;
+        const int wl = g.p[k] - base;
+        if (atomicExch(&s_best[wl], 1) == 0) s_layer[cur ^ 1][atomicAdd(&s_m, 1)] = (int16_t)wl;
       }
     }
     __syncthreads();
@@ -142,68 +152,67 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs(DGraph g, BfsOut b) {
     m = m2;
     ++d;
   }
-  for (int v = tid; v < n; v += kBfsThreads) {
-    b.dist_f[v] = s_df[v];
-    b.dist_b[v] = s_db[v];
-    if (v != g.exit && s_db[v] > 0) {
-      for (int k = g.sp[v]; k < g.sp[v + 1]; ++k)
-        if (s_db[g.s[k]] == s_db[v] - 1) {
-          b.next[v] = g.s[k];
+  const int xl = g.cexit[c] - base;
+  for (int v = tid; v < nc; v += kBfsThreads) {
+    b.dist_f[base + v] = s_df[v];
+    b.dist_b[base + v] = s_db[v];
+    if (v != xl && s_db[v] > 0) {
+      const int u = base + v;
+      for (int k = g.sp[u]; k < g.sp[u + 1]; ++k)
+        if (s_db[g.s[k] - base] == s_db[v] - 1) {
+          b.next[u] = g.s[k];
           break;
         }
     }
   }
-  // prefix / suffix table offsets
-  {
-    int64_t carry_p = 0, carry_s = 0;
-    for (int base = 0; base < n; base += kBfsThreads) {
-      const int v = base + tid;
-      const int64_t lp = (v < n && s_df[v] > 0) ? s_df[v] : 0;
-      const int64_t lsx = (v < n && s_db[v] > 0) ? s_db[v] : 0;
-      int64_t tp, ts;
-      const int64_t pp = block_excl_scan<kBfsThreads, int64_t>(lp, tp, s_w64);
-      const int64_t ps = block_excl_scan<kBfsThreads, int64_t>(lsx, ts, s_w64);
-      if (v < n) {
-        b.pfx_off[v] = carry_p + pp;
-        b.sfx_off[v] = carry_s + ps;
-      }
-      carry_p += tp;
-      carry_s += ts;
-    }
-    if (tid == 0) {
-      b.pfx_off[n] = carry_p;
-      b.sfx_off[n] = carry_s;
+}
+
+hipError_t launch_bfs_dist(const DGraph& g, const BfsOut& b, hipStream_t st) {
+  k_bfs_dist<<<(unsigned)g.n_comp, kBfsThreads, 0, st>>>(g, b);
+  return hipGetLastError();
+}
+
+// Prefix / suffix tables (graph-wide ids): entries before v on its
+// smallest shortest path from the entry, entries after v to the exit.
+__global__ void k_bfs_tables(DGraph g, BfsOut b) {
+  const int v = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (v >= g.n) return;
+  const int df = b.dist_f[v], db = b.dist_b[v];
+  if (df > 0) {
+    const int64_t lo = b.pfx_off[v];
+    int64_t pos = lo + df - 1;
+    int x = b.parent[v];
+    while (x >= 0 && pos >= lo) {
+      b.pfx[pos--] = x;
+      x = b.parent[x];
     }
   }
-  __threadfence();
-  __syncthreads();
-  for (int v = tid; v < n; v += kBfsThreads) {
-    if (s_df[v] > 0) {
-      int64_t pos = __hip_atomic_load(&b.pfx_off[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
-                    s_df[v] - 1;
-      const int64_t lo = pos - (s_df[v] - 1);
-      int x = __hip_atomic_load(&b.parent[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      while (x >= 0 && pos >= lo) {
-        b.pfx[pos--] = x;
-        x = __hip_atomic_load(&b.parent[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    }
-    if (s_db[v] > 0) {
-      int64_t pos = __hip_atomic_load(&b.sfx_off[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const int64_t hi = pos + s_db[v];
-      int x = __hip_atomic_load(&b.next[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      while (x >= 0 && pos < hi) {
-        b.sfx[pos++] = x;
-        x = (x == g.exit) ? -1
-                          : __hip_atomic_load(&b.next[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
+  if (db > 0) {
+    int64_t pos = b.sfx_off[v];
+    const int64_t hi = pos + db;
+    int x = b.next[v];
+    while (x >= 0 && pos < hi) {
+      b.sfx[pos++] = x;
+      x = b.next[x];
     }
   }
 }
 
-hipError_t launch_bfs(const DGraph& g, const BfsOut& b, hipStream_t st) {
-  if (g.n > 4096) return hipErrorInvalidValue;
-  k_bfs<<<1, kBfsThreads, 0, st>>>(g, b);
+hipError_t launch_bfs_tables(const DGraph& g, const BfsOut& b, hipStream_t st) {
+  k_bfs_tables<<<(unsigned)((g.n + kBlock - 1) / kBlock), kBlock, 0, st>>>(g, b);
+  return hipGetLastError();
+}
+
+// Graph-wide ids -> ids local to each component (batched output).
+__global__ void k_localize(const int32_t* loc, int32_t* v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = loc[v[i]];
+}
+
+hipError_t launch_localize(const int32_t* loc, int32_t* v, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_localize<<<(unsigned)std::min<int64_t>(4096, (n + kBlock - 1) / kBlock), kBlock, 0, st>>>(loc, v, n);
   return hipGetLastError();
 }
 
@@ -347,7 +356,8 @@ hipError_t launch_dedup_flags(const int64_t* tp_off, const int32_t* tp_vtx, cons
 
 __global__ void k_gather(const int64_t* off, const int32_t* vtx, const int32_t* idx, int64_t n,
                          const int64_t* keep_pos, const int64_t* keep_voff,
-                         const int64_t* keep_len, int64_t* out_off, int32_t* out_vtx) {
+                         const int64_t* keep_len, int64_t* out_off, int32_t* out_vtx,
+                         const int32_t* comp, int64_t* comp_cnt, int64_t* comp_vcnt) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   if (keep_len[k] == 0) return;  // duplicate (every kept path has >= 1 entry)
@@ -357,15 +367,43 @@ __global__ void k_gather(const int64_t* off, const int32_t* vtx, const int32_t* 
   const int64_t l = off[a + 1] - off[a];
   const int32_t* src = vtx + off[a];
   for (int64_t q = 0; q < l; ++q) out_vtx[o + q] = src[q];
+  if (comp_cnt) {
+    const int c = comp[src[0]];
+    atomicAdd((unsigned long long*)&comp_cnt[c], 1ull);
+    atomicAdd((unsigned long long*)&comp_vcnt[c], (unsigned long long)l);
+  }
 }
 
 hipError_t launch_gather(const int64_t* tp_off, const int32_t* tp_vtx, const int32_t* idx,
                          int64_t n, const int64_t* keep_pos, const int64_t* keep_voff,
                          const int64_t* keep_len, int64_t* out_off, int32_t* out_vtx,
+                         const int32_t* comp, int64_t* comp_cnt, int64_t* comp_vcnt,
                          hipStream_t st) {
   if (n == 0) return hipSuccess;
   k_gather<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-      tp_off, tp_vtx, idx, n, keep_pos, keep_voff, keep_len, out_off, out_vtx);
+      tp_off, tp_vtx, idx, n, keep_pos, keep_voff, keep_len, out_off, out_vtx, comp, comp_cnt,
+      comp_vcnt);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// batched form: packing in caller order
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_pack(const int64_t* src_off, const int32_t* src_vtx,
+                                                 const PackDesc* d, int32_t union_id,
+                                                 int64_t* dst_off, int32_t* dst_vtx) {
+  const PackDesc e = d[blockIdx.x];
+  if (e.union_id != union_id) return;
+  for (int64_t j = threadIdx.x; j < e.n_paths; j += kBlock)
+    dst_off[e.dst_path + j] = src_off[e.src_path + j] - e.src_v0 + e.dst_v;
+  for (int64_t q = threadIdx.x; q < e.n_v; q += kBlock) dst_vtx[e.dst_v + q] = src_vtx[e.src_v0 + q];
+}
+
+hipError_t launch_pack(const int64_t* src_off, const int32_t* src_vtx, const PackDesc* d,
+                       int32_t n_desc, int32_t union_id, int64_t* dst_off, int32_t* dst_vtx,
+                       hipStream_t st) {
+  if (n_desc <= 0) return hipSuccess;
+  k_pack<<<(unsigned)n_desc, kBlock, 0, st>>>(src_off, src_vtx, d, union_id, dst_off, dst_vtx);
   return hipGetLastError();
 }
 

@@ -50,7 +50,9 @@ class _Stats(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("ms_extend", ctypes.c_double),
                 ("ms_rank", ctypes.c_double), ("ms_tp", ctypes.c_double),
                 ("ms_total", ctypes.c_double), ("ms_extend_kernel", ctypes.c_double),
-                ("n_extend_launches", ctypes.c_int64)]
+                ("n_extend_launches", ctypes.c_int64), ("peak_level_nodes", ctypes.c_int64),
+                ("n_unions", ctypes.c_int64), ("pred_nodes", ctypes.c_int64),
+                ("pred_peak_level_nodes", ctypes.c_int64)]
 
 
 class _Opts(ctypes.Structure):
@@ -59,6 +61,12 @@ class _Opts(ctypes.Structure):
                 ("pool_cap_bytes", ctypes.c_uint64), ("stats", ctypes.POINTER(_Stats)),
                 ("level_counts", ctypes.POINTER(ctypes.c_int64)),
                 ("level_counts_len", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+
+
+class _BatchResult(ctypes.Structure):
+    _fields_ = [("pp", _Paths), ("tp", _Paths), ("pp_first", ctypes.POINTER(ctypes.c_int64)),
+                ("tp_first", ctypes.POINTER(ctypes.c_int64)), ("n_graphs", ctypes.c_int32),
+                ("reserved_", ctypes.c_int32)]
 
 
 # every symbol include/tpg.h declares, with its signature
@@ -80,6 +88,10 @@ _SIGS = {
     "tpg_test_paths": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Opts),
                                       ctypes.POINTER(_Paths), ctypes.POINTER(_Paths)]),
     "tpg_paths_free": (None, [ctypes.POINTER(_Paths)]),
+    "tpg_batch_test_paths": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                            ctypes.POINTER(_Opts), ctypes.c_void_p,
+                                            ctypes.POINTER(_BatchResult)]),
+    "tpg_batch_result_free": (None, [ctypes.POINTER(_BatchResult)]),
     "tpg_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "tpg_last_error": (ctypes.c_char_p, []),
     "tpg_version": (ctypes.c_char_p, []),
@@ -93,6 +105,12 @@ def lib() -> ctypes.CDLL:
     """The loaded library; raises if it has not been built."""
     global _lib
     if _lib is None:
+        # Bind libtpg to the HIP runtime torch carries (same soname): one
+        # runtime per process, so torch streams and tensors interoperate.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2210_16998_amd.build` (no CPU fallback exists)")
@@ -296,3 +314,63 @@ def version() -> str:
 
 def device_count() -> int:
     return int(lib().tpg_device_count())
+
+
+class BatchResult:
+    """Packed results of a batched call: prime and test paths of graph i are
+    pp[pp_first[i]:pp_first[i+1]] and tp[tp_first[i]:tp_first[i+1]]."""
+
+    def __init__(self, r: _BatchResult) -> None:
+        n = r.n_graphs
+        self.n_graphs = n
+        self.pp_first = np.ctypeslib.as_array(r.pp_first, shape=(n + 1,)).copy()
+        self.tp_first = np.ctypeslib.as_array(r.tp_first, shape=(n + 1,)).copy()
+        self.on_device = bool(r.pp.on_device)
+        if self.on_device:
+            self.pp = DevicePaths(r.pp)
+            self.tp = DevicePaths(r.tp)
+            # the paths are views into the workspace; release the index arrays only
+            r.pp = _Paths()
+            r.tp = _Paths()
+            lib().tpg_batch_result_free(ctypes.byref(r))
+        else:
+            pp, tp = _Paths(), _Paths()
+            ctypes.memmove(ctypes.byref(pp), ctypes.byref(r.pp), ctypes.sizeof(_Paths))
+            ctypes.memmove(ctypes.byref(tp), ctypes.byref(r.tp), ctypes.sizeof(_Paths))
+            r.pp = _Paths()
+            r.tp = _Paths()
+            lib().tpg_batch_result_free(ctypes.byref(r))
+            self.pp = HostPaths(pp)
+            self.tp = HostPaths(tp)
+
+    def graph(self, i: int):
+        """(prime paths, test paths) of graph i as host (offsets, vertices)."""
+        def cut(pl, first):
+            a, b = int(first[i]), int(first[i + 1])
+            off = pl.offsets[a:b + 1]
+            return off - off[0], pl.vertices[off[0]:off[-1]]
+        return cut(self.pp, self.pp_first), cut(self.tp, self.tp_first)
+
+
+def batch_test_paths(graphs, ws: Optional[Workspace] = None, flags: int = 0, stream=None,
+                     pool_cap: int = 0, predicted: Optional[np.ndarray] = None,
+                     level_counts: Optional[np.ndarray] = None):
+    """(BatchResult, stats) for a list of Graph.  predicted: float32
+    [n, 65] log1p sizes; level_counts: int64 [n, 64] receives the per-graph
+    path counts of levels 1..64."""
+    n = len(graphs)
+    arr = (ctypes.c_void_p * n)(*[g.handle.value for g in graphs])
+    st = _Stats()
+    lv = None
+    if level_counts is not None:
+        assert level_counts.dtype == np.int64 and level_counts.size >= 64 * n
+        lv = level_counts.reshape(-1)
+    o = _opts(ws, flags, stream, st, pool_cap, lv)
+    pred_ptr = None
+    if predicted is not None:
+        predicted = np.ascontiguousarray(predicted, dtype=np.float32)
+        assert predicted.shape == (n, 65)
+        pred_ptr = predicted.ctypes.data
+    r = _BatchResult()
+    _check(lib().tpg_batch_test_paths(arr, n, ctypes.byref(o), pred_ptr, ctypes.byref(r)))
+    return BatchResult(r), _stats_dict(st)

@@ -1,0 +1,106 @@
+"""GPU parity of the batched form: every graph of a batch against the CPU
+oracle, element by element; sizing modes must not change a single byte."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2210_16998_amd import cfggen, tpg
+from tests.gpu_util import ref_pp, ref_tp, say, ws
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_batch(cfgs, res):
+    for i, g in enumerate(cfgs):
+        (po, pv), (to, tv) = res.graph(i)
+        rp = ref_pp(g)[0]
+        rt, _ = ref_tp(g)
+        assert np.array_equal(po, rp.offsets) and np.array_equal(pv, rp.vertices), (i, g.name, "PP")
+        assert np.array_equal(to, rt.offsets) and np.array_equal(tv, rt.vertices), (i, g.name, "TP")
+
+
+def _mixed():
+    cfgs = [cfggen.fig1_cfg(), cfggen.from_edges(1, [], 0, 0)]
+    cfgs += [cfggen.c1_cfg(s) for s in range(4)]
+    cfgs += [cfggen.random_small_cfg(7000 + s, 2 + (s * 7) % 150, extra=1 + s % 6) for s in range(40)]
+    cfgs += [cfggen.batch_member_cfg(cfggen.C3_SEED_BASE + s) for s in range(40)]
+    cfgs += [cfggen.loop_diamond_chain(k) for k in (1, 5, 9)]
+    return cfgs
+
+
+@pytest.mark.parametrize("flags", [0, tpg.TPG_FORCE_TWO_PASS])
+def test_batch_mixed(flags):
+    cfgs = _mixed()
+    say("case batch mixed", len(cfgs), flags)
+    hs = [tpg.load_cfg(g) for g in cfgs]
+    res, st = tpg.batch_test_paths(hs, ws=ws(), flags=flags)
+    assert st["n_unions"] >= 2  # several visited-set widths
+    _check_batch(cfgs, res)
+
+
+def test_batch_level_counts_are_exact():
+    cfgs = _mixed()
+    hs = [tpg.load_cfg(g) for g in cfgs]
+    lv = np.zeros((len(cfgs), 64), np.int64)
+    say("case batch level counts")
+    tpg.batch_test_paths(hs, ws=ws(), level_counts=lv)
+    for i, g in enumerate(cfgs):
+        _, rl, rc = oracle.count(g)
+        want = np.zeros(64, np.int64)
+        for L in range(1, len(rl)):
+            want[min(L, 64) - 1] += rl[L] + rc[L]
+        assert np.array_equal(lv[i], want), (i, g.name)
+
+
+def test_batch_c3_full_against_oracle_and_modes():
+    cfgs = cfggen.c3_batch(4096)
+    hs = [tpg.load_cfg(g) for g in cfgs]
+    say("case c3 batch one-pass")
+    res, st = tpg.batch_test_paths(hs, ws=ws())
+    say("  unions", st["n_unions"], "pp", st["n_pp"], "ext", st["n_extensions"])
+    _check_batch(cfgs, res)
+    # the same bytes from the plain two-pass sizing and from (exact) predictions
+    lv = np.zeros((len(cfgs), 64), np.int64)
+    say("case c3 batch two-pass")
+    res2, _ = tpg.batch_test_paths(hs, ws=ws(), flags=tpg.TPG_FORCE_TWO_PASS, level_counts=lv)
+    pred = np.zeros((len(cfgs), 65), np.float32)
+    pred[:, :64] = np.log1p(lv)
+    pred[:, 64] = np.log1p(np.diff(res.pp_first))
+    say("case c3 batch predicted")
+    w = tpg.Workspace()
+    res3, st3 = tpg.batch_test_paths(hs, ws=w, predicted=pred)
+    assert st3["n_overflows"] == 0
+    for r in (res2, res3):
+        assert np.array_equal(r.pp_first, res.pp_first) and np.array_equal(r.tp_first, res.tp_first)
+        assert np.array_equal(r.pp.offsets, res.pp.offsets)
+        assert np.array_equal(r.pp.vertices, res.pp.vertices)
+        assert np.array_equal(r.tp.offsets, res.tp.offsets)
+        assert np.array_equal(r.tp.vertices, res.tp.vertices)
+    w.close()
+
+
+def test_batch_underpredicted_sizes_fall_back_exactly():
+    cfgs = [cfggen.batch_member_cfg(cfggen.C3_SEED_BASE + s) for s in range(200)]
+    hs = [tpg.load_cfg(g) for g in cfgs]
+    pred = np.zeros((len(cfgs), 65), np.float32)  # predicts (almost) nothing
+    w = tpg.Workspace()
+    say("case batch under-prediction")
+    res, st = tpg.batch_test_paths(hs, ws=w, predicted=pred)
+    assert st["n_overflows"] > 0
+    _check_batch(cfgs, res)
+    w.close()
+
+
+def test_batch_device_output():
+    cfgs = [cfggen.c1_cfg(s) for s in range(3)] + [cfggen.fig1_cfg()]
+    hs = [tpg.load_cfg(g) for g in cfgs]
+    say("case batch device output")
+    res, _ = tpg.batch_test_paths(hs, ws=ws(), flags=tpg.TPG_OUT_DEVICE)
+    off, vtx = res.tp.torch_views()
+    off, vtx = off.cpu().numpy(), vtx.cpu().numpy()
+    for i, g in enumerate(cfgs):
+        a, b = int(res.tp_first[i]), int(res.tp_first[i + 1])
+        rt, _ = ref_tp(g)
+        o = off[a:b + 1]
+        assert np.array_equal(o - o[0], rt.offsets)
+        assert np.array_equal(vtx[o[0]:o[-1]], rt.vertices)
