@@ -227,6 +227,45 @@ tpg_status tpg_batch_test_paths(const tpg_graph* const* graphs, int32_t n_graphs
 void tpg_batch_result_free(tpg_batch_result* r);
 
 /* ------------------------------------------------------------------------
+ * Size predictor for the batched form (host features, device network).
+ *
+ * tpg_features: 32 structural features per graph from its CSR alone (sizes,
+ * cyclomatic complexity, branching bits, natural-loop depth histogram, SCCs,
+ * if-else diamonds, switch fan-outs, distances, entry-to-exit paths of the
+ * component DAG); out is [n_graphs * 32], host memory.
+ *
+ * tpg_mlp: 32 -> 128 -> 128 -> 65 perceptron (ReLU), BF16 operands on the
+ * matrix cores with FP32 accumulation, Adam (beta 0.9 / 0.999, eps 1e-8) on
+ * FP32 master weights.  Output j < 64: log1p(paths with j+1 entries), deeper
+ * levels pooled into j = 63; output 64: log1p(prime paths).  Loss: mean
+ * squared error over the 65 outputs.  Parameters are packed as W1 [32][128],
+ * b1 [128], W2 [128][128], b2 [128], W3 [128][65], b3 [65]
+ * (tpg_mlp_num_params() floats).  Inputs are normalized as (x - mean) / std
+ * before the first layer.  All x / y / t arrays are host memory, row-major.
+ * ---------------------------------------------------------------------- */
+typedef struct tpg_mlp tpg_mlp;
+#define TPG_MLP_IN 32
+#define TPG_MLP_OUT 65
+
+tpg_status tpg_features(const tpg_graph* const* graphs, int32_t n_graphs, float* out);
+int32_t tpg_mlp_num_params(void);
+tpg_status tpg_mlp_create(int32_t device, uint64_t seed, tpg_mlp** out);
+void tpg_mlp_free(tpg_mlp* m);
+tpg_status tpg_mlp_set_params(tpg_mlp* m, const float* params);
+tpg_status tpg_mlp_get_params(const tpg_mlp* m, float* params);
+tpg_status tpg_mlp_set_normalizer(tpg_mlp* m, const float* mean, const float* std);
+/* y: [n * 65] */
+tpg_status tpg_mlp_forward(tpg_mlp* m, const float* x, int32_t n, float* y);
+/* gradients of the loss w.r.t. the packed parameters, without updating */
+tpg_status tpg_mlp_gradients(tpg_mlp* m, const float* x, const float* t, int32_t n, float* grad,
+                             float* loss);
+/* forward + backward + one Adam step with learning rate lr */
+tpg_status tpg_mlp_train_step(tpg_mlp* m, const float* x, const float* t, int32_t n, float lr,
+                              float* loss);
+tpg_status tpg_mlp_save(const tpg_mlp* m, const char* path);
+tpg_status tpg_mlp_load(int32_t device, const char* path, tpg_mlp** out);
+
+/* ------------------------------------------------------------------------
  * Misc.
  * ---------------------------------------------------------------------- */
 const char* tpg_status_str(tpg_status s);

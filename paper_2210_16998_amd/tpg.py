@@ -92,6 +92,27 @@ _SIGS = {
                                             ctypes.POINTER(_Opts), ctypes.c_void_p,
                                             ctypes.POINTER(_BatchResult)]),
     "tpg_batch_result_free": (None, [ctypes.POINTER(_BatchResult)]),
+    "tpg_features": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                    ctypes.c_void_p]),
+    "tpg_mlp_num_params": (ctypes.c_int32, []),
+    "tpg_mlp_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_uint64,
+                                      ctypes.POINTER(ctypes.c_void_p)]),
+    "tpg_mlp_free": (None, [ctypes.c_void_p]),
+    "tpg_mlp_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "tpg_mlp_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "tpg_mlp_set_normalizer": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_void_p]),
+    "tpg_mlp_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                       ctypes.c_void_p]),
+    "tpg_mlp_gradients": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_float)]),
+    "tpg_mlp_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_int32, ctypes.c_float,
+                                          ctypes.POINTER(ctypes.c_float)]),
+    "tpg_mlp_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
+    "tpg_mlp_load": (ctypes.c_int, [ctypes.c_int32, ctypes.c_char_p,
+                                    ctypes.POINTER(ctypes.c_void_p)]),
     "tpg_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "tpg_last_error": (ctypes.c_char_p, []),
     "tpg_version": (ctypes.c_char_p, []),
@@ -374,3 +395,92 @@ def batch_test_paths(graphs, ws: Optional[Workspace] = None, flags: int = 0, str
     r = _BatchResult()
     _check(lib().tpg_batch_test_paths(arr, n, ctypes.byref(o), pred_ptr, ctypes.byref(r)))
     return BatchResult(r), _stats_dict(st)
+
+
+MLP_IN, MLP_OUT = 32, 65
+
+
+def features(graphs) -> np.ndarray:
+    """[n, 32] float32 structural features (computed by the library)."""
+    n = len(graphs)
+    arr = (ctypes.c_void_p * n)(*[g.handle.value for g in graphs])
+    out = np.zeros((n, MLP_IN), np.float32)
+    _check(lib().tpg_features(arr, n, out.ctypes.data))
+    return out
+
+
+def _f32(a, shape):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    assert a.shape == shape, (a.shape, shape)
+    return a
+
+
+class MLP:
+    """Size predictor on the GPU (see tpg_mlp_* in include/tpg.h)."""
+
+    def __init__(self, device: int = -1, seed: int = 0, _handle=None) -> None:
+        if _handle is None:
+            h = ctypes.c_void_p()
+            _check(lib().tpg_mlp_create(int(device), int(seed), ctypes.byref(h)))
+            _handle = h
+        self._h = _handle
+
+    @staticmethod
+    def num_params() -> int:
+        return int(lib().tpg_mlp_num_params())
+
+    @classmethod
+    def load(cls, path: str, device: int = -1) -> "MLP":
+        h = ctypes.c_void_p()
+        _check(lib().tpg_mlp_load(int(device), path.encode(), ctypes.byref(h)))
+        return cls(_handle=h)
+
+    def save(self, path: str) -> None:
+        _check(lib().tpg_mlp_save(self._h, path.encode()))
+
+    def params(self) -> np.ndarray:
+        p = np.zeros(self.num_params(), np.float32)
+        _check(lib().tpg_mlp_get_params(self._h, p.ctypes.data))
+        return p
+
+    def set_params(self, p: np.ndarray) -> None:
+        p = _f32(p, (self.num_params(),))
+        _check(lib().tpg_mlp_set_params(self._h, p.ctypes.data))
+
+    def set_normalizer(self, mean: np.ndarray, std: np.ndarray) -> None:
+        mean, std = _f32(mean, (MLP_IN,)), _f32(std, (MLP_IN,))
+        _check(lib().tpg_mlp_set_normalizer(self._h, mean.ctypes.data, std.ctypes.data))
+
+    def forward(self, x: np.ndarray) -> np.ndarray:
+        x = _f32(x, (len(x), MLP_IN))
+        y = np.zeros((len(x), MLP_OUT), np.float32)
+        _check(lib().tpg_mlp_forward(self._h, x.ctypes.data, len(x), y.ctypes.data))
+        return y
+
+    def gradients(self, x: np.ndarray, t: np.ndarray):
+        x = _f32(x, (len(x), MLP_IN))
+        t = _f32(t, (len(x), MLP_OUT))
+        g = np.zeros(self.num_params(), np.float32)
+        loss = ctypes.c_float()
+        _check(lib().tpg_mlp_gradients(self._h, x.ctypes.data, t.ctypes.data, len(x),
+                                       g.ctypes.data, ctypes.byref(loss)))
+        return g, float(loss.value)
+
+    def train_step(self, x: np.ndarray, t: np.ndarray, lr: float) -> float:
+        x = _f32(x, (len(x), MLP_IN))
+        t = _f32(t, (len(x), MLP_OUT))
+        loss = ctypes.c_float()
+        _check(lib().tpg_mlp_train_step(self._h, x.ctypes.data, t.ctypes.data, len(x),
+                                        float(lr), ctypes.byref(loss)))
+        return float(loss.value)
+
+    def close(self) -> None:
+        if self._h:
+            lib().tpg_mlp_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
