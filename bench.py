@@ -56,6 +56,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-reps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is "
@@ -135,10 +137,89 @@ def main() -> int:
                      "launches": st["n_extend_launches"],
                      "avg_launch_ms": k_ms / max(1, st["n_extend_launches"])},
     }
+    if not args.no_batch:
+        out["batched"] = _batched(args)
     if not args.no_cpu:
         out["cpu_baseline"] = _cpu_baseline(g, args.cpu_reps)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def _batched(args):
+    """4096 CFGs: plain per-CFG two-pass form vs the batched form with exact
+    two-pass sizing vs the batched form sized by the learned predictor."""
+    import numpy as np
+    import torch
+    from paper_2210_16998_amd import cfggen, sizer, tpg
+
+    cfgs = cfggen.c3_batch(4096)
+    graphs = [tpg.load_cfg(c) for c in cfgs]
+    model = sizer.DEFAULT_MODEL
+    mlp = tpg.MLP.load(model) if os.path.exists(model) else None
+    dev = tpg.TPG_OUT_DEVICE | tpg.TPG_NO_TIMING
+
+    def timed(fn, reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return 1000.0 * (time.perf_counter() - t) / reps, r
+
+    def learned(ws):
+        pred = mlp.forward(tpg.features(graphs))
+        return tpg.batch_test_paths(graphs, ws=ws, flags=dev, predicted=pred)
+
+    def twopass(ws):
+        return tpg.batch_test_paths(graphs, ws=ws, flags=dev | tpg.TPG_FORCE_TWO_PASS)
+
+    def onepass(ws):
+        return tpg.batch_test_paths(graphs, ws=ws, flags=dev)
+
+    res = {"workload": "4096 structured CFGs, vertices lognormal (median 40, clipped 10..300), "
+                       "seeds 3000000+i"}
+    ws = tpg.Workspace(0)
+    twopass(ws)
+    ms2, (r2, st2) = timed(lambda: twopass(ws), args.batch_reps)
+    res["batched_two_pass_ms"] = ms2
+    res["n_pp"] = int(st2["n_pp"])
+    res["n_extensions"] = int(st2["n_extensions"])
+    res["n_tp"] = int(st2["n_tp"])
+    if mlp is not None:
+        learned(ws)
+        msl, (rl, stl) = timed(lambda: learned(ws), args.batch_reps)
+        res["batched_learned_ms"] = msl
+        res["prime_paths_per_s_learned"] = st2["n_pp"] / (msl * 1e-3)
+        res["extensions_per_s_learned"] = st2["n_extensions"] / (msl * 1e-3)
+        res["same_results_as_two_pass"] = bool(
+            np.array_equal(rl.pp_first, r2.pp_first) and np.array_equal(rl.tp_first, r2.tp_first))
+        res["gain_vs_batched_two_pass"] = ms2 / msl
+        # cold start: fresh workspaces, predicted sizing vs growing by replay
+        wc = tpg.Workspace(0)
+        msc, (_, stc) = timed(lambda: learned(wc), 1)
+        wc.close()
+        wo = tpg.Workspace(0)
+        mso, (_, sto) = timed(lambda: onepass(wo), 1)
+        wo.close()
+        res["cold_learned_ms"] = msc
+        res["cold_learned_overflows"] = int(stc["n_overflows"])
+        res["cold_unpredicted_ms"] = mso
+        res["cold_unpredicted_overflows"] = int(sto["n_overflows"])
+        res["over_allocation"] = stc["pred_nodes"] * 1.25 / max(1, stc["n_nodes"])
+    ws1 = tpg.Workspace(0)
+    t = time.perf_counter()
+    n_plain = 0
+    for g in graphs:
+        _, tp, st = tpg.test_paths(g, ws=ws1, flags=dev | tpg.TPG_FORCE_TWO_PASS)
+        n_plain += st["n_pp"]
+    torch.cuda.synchronize()
+    msp = 1000.0 * (time.perf_counter() - t)
+    res["plain_per_cfg_two_pass_ms"] = msp
+    assert n_plain == res["n_pp"]
+    if "batched_learned_ms" in res:
+        res["speedup_learned_vs_plain"] = msp / res["batched_learned_ms"]
+    res["speedup_two_pass_batched_vs_plain"] = msp / ms2
+    return res
 
 
 if __name__ == "__main__":

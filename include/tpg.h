@@ -227,6 +227,27 @@ tpg_status tpg_batch_test_paths(const tpg_graph* const* graphs, int32_t n_graphs
 void tpg_batch_result_free(tpg_batch_result* r);
 
 /* ------------------------------------------------------------------------
+ * Launch-shape tuning of the frontier-extension kernel.
+ *
+ * Per visited-set width W = 2^i words (index i = 0..6): parents per thread
+ * (1, 2 or 4; a tile is 256 * items parents) and persistent workgroups per
+ * compute unit (1..32).  tpg_autotune times every (items, 2/4/8/16) pair on
+ * the given graphs (grouped by width as in the batched form), keeps the
+ * fastest per width in the workspace (opts->ws, required) and returns the
+ * table; results never depend on the tuning.
+ * ---------------------------------------------------------------------- */
+typedef struct tpg_tuning {
+  int32_t items[7];
+  int32_t wgs_per_cu[7];
+  double best_ms[7]; /* summed extension-kernel time of the best shape (0: untuned) */
+} tpg_tuning;
+
+tpg_status tpg_autotune(const tpg_graph* const* graphs, int32_t n_graphs, const tpg_opts* opts,
+                        tpg_tuning* out);
+tpg_status tpg_workspace_set_tuning(tpg_workspace* ws, const tpg_tuning* t);
+tpg_status tpg_workspace_get_tuning(const tpg_workspace* ws, tpg_tuning* t);
+
+/* ------------------------------------------------------------------------
  * Size predictor for the batched form (host features, device network).
  *
  * tpg_features: 32 structural features per graph from its CSR alone (sizes,

@@ -58,7 +58,7 @@ def _load():
                                                ctypes.c_int, ctypes.c_int, P(_Paths),
                                                P(_Stats)]
         _lib.orc_count.argtypes = [ctypes.c_int, i64p, i32p, ctypes.c_int,
-                                   ctypes.c_int64, P(_Stats), i64p, i64p]
+                                   ctypes.c_int64, P(_Stats), i64p, i64p, i64p]
         _lib.orc_bruteforce_pp.argtypes = [ctypes.c_int, i64p, i32p, P(_Paths), P(_Paths)]
         _lib.orc_bfs.argtypes = [ctypes.c_int, i64p, i32p, ctypes.c_int, ctypes.c_int,
                                  i32p, i32p, i32p, i32p]
@@ -151,22 +151,22 @@ def prime_paths_local(g, s_lo: int, s_hi: int, nthreads: Optional[int] = None
     return _take(out), _stats(st)
 
 
-def count(g, nthreads: Optional[int] = None, ext_cap: int = 0
-          ) -> Tuple[Optional[Dict[str, int]], np.ndarray, np.ndarray]:
+def count(g, nthreads: Optional[int] = None, ext_cap: int = 0, per_start: bool = False):
     """Per-level counts and the PP count without storing paths.  With
     ext_cap > 0, returns (None, ...) once about ext_cap extensions are
-    exceeded."""
+    exceeded.  per_start=True appends the PP count of every first vertex."""
     lib = _load()
     rp, ci, prp, pci = _csr(g)
     st = _Stats()
     lv = np.zeros(g.n + 2, np.int64)
     cy = np.zeros(g.n + 2, np.int64)
+    ps = np.zeros(g.n, np.int64)
     rc = lib.orc_count(g.n, prp, pci, _threads(nthreads), int(ext_cap), ctypes.byref(st),
                        lv.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                       cy.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
-    if rc == 1:
-        return None, lv, cy
-    return _stats(st), lv, cy
+                       cy.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                       ps.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    res = (None if rc == 1 else _stats(st), lv, cy)
+    return res + (ps,) if per_start else res
 
 
 def bruteforce_pp(g) -> Tuple[PathList, PathList]:

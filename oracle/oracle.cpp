@@ -342,7 +342,8 @@ int orc_prime_paths_local(int n, const int64_t* row_ptr, const int32_t* col_idx,
 // ext_cap > 0 bounds the work: past about that many extensions the run stops
 // and returns 1 (counts are then incomplete).
 int orc_count(int n, const int64_t* row_ptr, const int32_t* col_idx, int nthreads,
-              int64_t ext_cap, orc_stats* st, int64_t* level_counts, int64_t* cycle_counts) {
+              int64_t ext_cap, orc_stats* st, int64_t* level_counts, int64_t* cycle_counts,
+              int64_t* pp_per_start) {
   Digraph g = make_graph(n, row_ptr, col_idx);
   std::vector<StartResult> res(n);
   std::vector<int64_t> npp(n, 0);
@@ -351,6 +352,7 @@ int orc_count(int n, const int64_t* row_ptr, const int32_t* col_idx, int nthread
     dfs_from(g, s, false, res[s], &npp[s], ext_cap > 0 ? &budget : nullptr);
   });
   if (ext_cap > 0 && budget.load() < 0) return 1;
+  if (pp_per_start) memcpy(pp_per_start, npp.data(), sizeof(int64_t) * n);
   std::vector<int64_t> lv(n + 2, 0), cy(n + 2, 0);
   int64_t pp = 0;
   for (int s = 0; s < n; ++s) {

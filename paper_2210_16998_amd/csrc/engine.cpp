@@ -74,6 +74,23 @@ struct tpg_workspace {
   int64_t* h_scalars = nullptr;
 
   std::vector<hipEvent_t> ev_pool;
+
+  // captured level loops: a graph of `len` identical extension launches per
+  // batch length, valid while the launch arguments stay the same
+  struct LevelGraph {
+    int len = 0;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<LevelGraph> level_graphs;
+  ExtArgs graph_args{};
+  int graph_W = 0, graph_grid = 0, graph_items = 0;
+  hipStream_t graph_stream = nullptr;
+
+  // extension-kernel launch shape per visited-set width (index log2 W):
+  // parents per thread (tile = 256 * items) and persistent workgroups per CU
+  int tune_items[7] = {1, 1, 1, 1, 1, 1, 1};
+  int tune_wgs[7] = {8, 8, 8, 8, 8, 8, 8};
+  double tune_ms[7] = {0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -255,6 +272,52 @@ struct TreeResult {
   int64_t launches = 0;
 };
 
+void drop_level_graphs(tpg_workspace* ws) {
+  for (auto& lg : ws->level_graphs)
+    if (lg.exec) (void)hipGraphExecDestroy(lg.exec);
+  ws->level_graphs.clear();
+}
+
+// `len` extension launches, replayed from a captured HIP graph (launch
+// arguments are baked in; a change of buffers or stream drops the graphs).
+tpg_status launch_levels_graph(tpg_workspace* ws, const ExtArgs& a, int W, int items, int grid,
+                               int len, hipStream_t st) {
+  if (memcmp(&ws->graph_args, &a, sizeof a) != 0 || ws->graph_W != W || ws->graph_grid != grid ||
+      ws->graph_items != items || ws->graph_stream != st) {
+    drop_level_graphs(ws);
+    ws->graph_args = a;
+    ws->graph_W = W;
+    ws->graph_grid = grid;
+    ws->graph_items = items;
+    ws->graph_stream = st;
+  }
+  for (auto& lg : ws->level_graphs)
+    if (lg.len == len) {
+      TPG_HIP(hipGraphLaunch(lg.exec, st));
+      return TPG_OK;
+    }
+  hipGraph_t graph = nullptr;
+  TPG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  for (int i = 0; i < len; ++i) {
+    hipError_t e = launch_extend(W, items, a, grid, st);
+    if (e != hipSuccess) {
+      hipGraph_t g2 = nullptr;
+      (void)hipStreamEndCapture(st, &g2);
+      if (g2) (void)hipGraphDestroy(g2);
+      return fail(TPG_ERR_DEVICE, "capture of the level loop failed: %s", hipGetErrorString(e));
+    }
+  }
+  TPG_HIP(hipStreamEndCapture(st, &graph));
+  tpg_workspace::LevelGraph lg;
+  lg.len = len;
+  hipError_t e = hipGraphInstantiate(&lg.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  TPG_HIP(e);
+  ws->level_graphs.push_back(lg);
+  TPG_HIP(hipGraphLaunch(lg.exec, st));
+  return TPG_OK;
+}
+
 // Level loop, one-pass device-sized form.  rec0 / msk0: initial capacities
 // (nodes overall / nodes of one level); 0 = what the workspace already has.
 tpg_status build_tree_onepass(tpg_workspace* ws, const HostUnion& U, hipStream_t st, Timer& tm,
@@ -267,17 +330,24 @@ tpg_status build_tree_onepass(tpg_workspace* ws, const HostUnion& U, hipStream_t
   TPG_TRY(reserve_tree(ws, rec, msk, W, st, 0, -1, 0));
   ExtArgs a = make_args(ws);
   TPG_HIP(launch_seed(a, st));
-  const int grid = ws->num_cus * 8;
+  int wi = 0;
+  while ((1 << wi) < W) ++wi;
+  const int items = ws->tune_items[wi];
+  const int grid = ws->num_cus * ws->tune_wgs[wi];
   int batch = 4;
   int level_before = 1;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
   for (;;) {
     evs.clear();
-    for (int b = 0; b < batch; ++b) {
-      hipEvent_t e0 = tm.mark();
-      TPG_HIP(launch_extend(W, a, grid, st));
-      hipEvent_t e1 = tm.mark();
-      evs.emplace_back(e0, e1);
+    if (tm.on) {
+      for (int b = 0; b < batch; ++b) {
+        hipEvent_t e0 = tm.mark();
+        TPG_HIP(launch_extend(W, items, a, grid, st));
+        hipEvent_t e1 = tm.mark();
+        evs.emplace_back(e0, e1);
+      }
+    } else {
+      TPG_TRY(launch_levels_graph(ws, a, W, items, grid, batch, st));
     }
     TPG_HIP(hipMemcpyAsync(ws->h_ls, ws->ls.p, 32, hipMemcpyDeviceToHost, st));
     TPG_HIP(hipStreamSynchronize(st));
@@ -701,6 +771,7 @@ void tpg_workspace_free(tpg_workspace* ws) {
     ws_release(ws, o.comp_starts);
   }
   for (hipEvent_t e : ws->ev_pool) (void)hipEventDestroy(e);
+  drop_level_graphs(ws);
   if (ws->h_ls) (void)hipHostFree(ws->h_ls);
   if (ws->h_scalars) (void)hipHostFree(ws->h_scalars);
   if (ws->own_stream) (void)hipStreamDestroy(ws->own_stream);
@@ -1007,6 +1078,80 @@ tpg_status tpg_batch_test_paths(const tpg_graph* const* graphs, int32_t n_graphs
   if (t0) (void)hipEventDestroy(t0);
   if (t1) (void)hipEventDestroy(t1);
   return s;
+}
+
+tpg_status tpg_workspace_set_tuning(tpg_workspace* ws, const tpg_tuning* t) {
+  if (!ws || !t) return fail(TPG_ERR_INVALID_ARG, "NULL argument");
+  for (int i = 0; i < 7; ++i) {
+    const int it = t->items[i], wg = t->wgs_per_cu[i];
+    if ((it != 1 && it != 2 && it != 4) || wg < 1 || wg > 32)
+      return fail(TPG_ERR_INVALID_ARG, "tuning entry %d: items %d, workgroups per CU %d", i, it, wg);
+  }
+  for (int i = 0; i < 7; ++i) {
+    ws->tune_items[i] = t->items[i];
+    ws->tune_wgs[i] = t->wgs_per_cu[i];
+    ws->tune_ms[i] = t->best_ms[i];
+  }
+  return TPG_OK;
+}
+
+tpg_status tpg_workspace_get_tuning(const tpg_workspace* ws, tpg_tuning* t) {
+  if (!ws || !t) return fail(TPG_ERR_INVALID_ARG, "NULL argument");
+  for (int i = 0; i < 7; ++i) {
+    t->items[i] = ws->tune_items[i];
+    t->wgs_per_cu[i] = ws->tune_wgs[i];
+    t->best_ms[i] = ws->tune_ms[i];
+  }
+  return TPG_OK;
+}
+
+tpg_status tpg_autotune(const tpg_graph* const* graphs, int32_t n_graphs, const tpg_opts* opts,
+                        tpg_tuning* out) {
+  if (!graphs || n_graphs < 1 || !out) return fail(TPG_ERR_INVALID_ARG, "bad argument");
+  for (int32_t i = 0; i < n_graphs; ++i) TPG_TRY(check_graph(graphs[i]));
+  CallCtx c;
+  TPG_TRY(begin_call(opts, c));
+  tpg_workspace* ws = c.ws;
+  // one union per visited-set width (first 2^17 vertices of each width)
+  std::vector<HostUnion> unions(7);
+  for (int32_t i = 0; i < n_graphs; ++i) {
+    const int w = pow2_words(graphs[i]->n);
+    int k = 0;
+    while ((1 << k) < w) ++k;
+    if (unions[k].n + graphs[i]->n <= kMaxUnionVertices) add_component(unions[k], graphs[i]);
+  }
+  const int items_c[3] = {1, 2, 4};
+  const int wgs_c[4] = {2, 4, 8, 16};
+  Timer tm{ws, c.st, true};
+  for (int k = 0; k < 7; ++k) {
+    const HostUnion& U = unions[k];
+    if (U.n_comp == 0) continue;
+    TPG_TRY(upload_union(ws, U, c.st));
+    TreeResult warm;
+    TPG_TRY(build_tree_onepass(ws, U, c.st, tm, warm, 0, 0));
+    double best = 1e30;
+    int bi = ws->tune_items[k], bw = ws->tune_wgs[k];
+    for (int it : items_c)
+      for (int wg : wgs_c) {
+        ws->tune_items[k] = it;
+        ws->tune_wgs[k] = wg;
+        double t_min = 1e30;
+        for (int rep = 0; rep < 2; ++rep) {
+          TreeResult R;
+          TPG_TRY(build_tree_onepass(ws, U, c.st, tm, R, 0, 0));
+          t_min = std::min(t_min, R.ms_kernel);
+        }
+        if (t_min < best) {
+          best = t_min;
+          bi = it;
+          bw = wg;
+        }
+      }
+    ws->tune_items[k] = bi;
+    ws->tune_wgs[k] = bw;
+    ws->tune_ms[k] = best;
+  }
+  return tpg_workspace_get_tuning(ws, out);
 }
 
 void tpg_batch_result_free(tpg_batch_result* r) {

@@ -48,7 +48,8 @@ struct ExtArgs {
 
 // --- path tree -------------------------------------------------------------
 hipError_t launch_seed(const ExtArgs& a, hipStream_t st);
-hipError_t launch_extend(int W, const ExtArgs& a, int grid, hipStream_t st);
+// items: parents per thread and tile (tile = 256 * items); grid: persistent workgroups
+hipError_t launch_extend(int W, int items, const ExtArgs& a, int grid, hipStream_t st);
 hipError_t launch_resume_fix(const ExtArgs& a, int level, hipStream_t st);
 // two-pass (plain) form
 hipError_t launch_count(int W, const ExtArgs& a, int L, int64_t base, int64_t F, hipStream_t st);

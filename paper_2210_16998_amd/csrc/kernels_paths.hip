@@ -164,17 +164,21 @@ __device__ __forceinline__ void store_child_mask(uint64_t* dst, const uint64_t (
 // ---------------------------------------------------------------------------
 // one-pass extension of level L -> L+1 (device-sized, order preserving)
 // ---------------------------------------------------------------------------
-template <int W>
+// A tile is ITEMS * 256 consecutive parents.  Loads are strided by the
+// workgroup size (coalesced); the scan gives each thread ITEMS consecutive
+// parents; the expansion gives each thread every 256th child of the tile.
+template <int W, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_extend(ExtArgs a) {
-  constexpr bool kLdsMask = W <= 8;
+  constexpr int TILE = kBlock * ITEMS;
+  constexpr bool kLdsMask = W * ITEMS <= 16;  // visited sets of the tile in LDS (<= 32 KiB)
   __shared__ int64_t s_tile;
   __shared__ int64_t s_prefix;
-  __shared__ int32_t s_off[kBlock];
-  __shared__ uint64_t s_vm[kBlock];
-  __shared__ uint32_t s_inf[kBlock];
-  __shared__ int32_t s_kk[kBlock];
-  __shared__ int32_t s_cb[kBlock];
-  __shared__ uint64_t s_mask[kLdsMask ? kBlock * W : 1];
+  __shared__ int32_t s_off[TILE];
+  __shared__ uint64_t s_vm[TILE];
+  __shared__ uint32_t s_inf[TILE];
+  __shared__ int32_t s_kk[TILE];
+  __shared__ int32_t s_cb[TILE];
+  __shared__ uint64_t s_mask[kLdsMask ? TILE * W : 1];
   __shared__ int32_t s_w[kBlock / 64];
 
   LevelState* ls = a.ls;
@@ -196,45 +200,67 @@ __global__ __launch_bounds__(kBlock) void k_extend(ExtArgs a) {
     a.tile_status[par ^ 1][k] = 0;
   if (blockIdx.x == 0 && tid == 0) a.tile_ctr[par ^ 1] = 0;
 
-  const int64_t ntiles = (F + kBlock - 1) / kBlock;
+  const int64_t ntiles = (F + TILE - 1) / TILE;
   for (;;) {
     if (tid == 0) s_tile = (int64_t)atomicAdd(&a.tile_ctr[par], 1u);
     __syncthreads();
     const int64_t t = s_tile;
     if (t >= ntiles) break;
-    const int64_t j = t * kBlock + tid;
-    const bool valid = j < F;
-    uint32_t inf = valid ? a.t.info[base + j] : F_CYC;
-    uint64_t m[W];
+    const int64_t tb = t * TILE;
+    // load + choices + filter, parent p = i * 256 + tid
 #pragma unroll
-    for (int q = 0; q < W; ++q) m[q] = 0;
-    uint64_t vm = 0;
-    int k0 = 0, cb = 0;
-    if (!(inf & F_CYC)) {
-      load_mask<W>(mcur + j * W, m);
-      vm = choices<W>(a.g, inf, m, k0, cb);
-      if (vm == 0) {
-        const bool pp = all_preds_on<W>(a.g, cb, node_v1l(inf), m);
-        inf |= F_TERM | (pp ? F_PP : 0u);
-        a.t.info[base + j] = inf;
+    for (int i = 0; i < ITEMS; ++i) {
+      const int p = i * kBlock + tid;
+      const int64_t j = tb + p;
+      uint32_t inf = j < F ? a.t.info[base + j] : F_CYC;
+      uint64_t m[W];
+#pragma unroll
+      for (int q = 0; q < W; ++q) m[q] = 0;
+      uint64_t vm = 0;
+      int k0 = 0, cb = 0;
+      if (!(inf & F_CYC)) {
+        load_mask<W>(mcur + j * W, m);
+        vm = choices<W>(a.g, inf, m, k0, cb);
+        if (vm == 0) {
+          const bool pp = all_preds_on<W>(a.g, cb, node_v1l(inf), m);
+          inf |= F_TERM | (pp ? F_PP : 0u);
+          a.t.info[base + j] = inf;
+        }
+      }
+      s_off[p] = __builtin_popcountll(vm);
+      s_vm[p] = vm;
+      s_inf[p] = inf;
+      s_kk[p] = k0;
+      s_cb[p] = cb;
+      if constexpr (kLdsMask) {
+#pragma unroll
+        for (int q = 0; q < W; ++q) s_mask[p * W + q] = m[q];
       }
     }
-    const int cnt = __builtin_popcountll(vm);
-    int32_t total32;
-    const int32_t my_off = block_excl_scan<kBlock, int32_t>(cnt, total32, s_w);
-    if (tid == 0) s_prefix = lookback_prefix(status, t, (int64_t)total32);
-    s_off[tid] = my_off;
-    s_vm[tid] = vm;
-    s_inf[tid] = inf;
-    s_kk[tid] = k0;
-    s_cb[tid] = cb;
-    if constexpr (kLdsMask) {
+    __syncthreads();
+    // exclusive scan of the child counts in parent order
+    int c[ITEMS];
+    int sum = 0;
 #pragma unroll
-      for (int q = 0; q < W; ++q) s_mask[tid * W + q] = m[q];
+    for (int i = 0; i < ITEMS; ++i) {
+      c[i] = s_off[tid * ITEMS + i];
+      sum += c[i];
     }
+    int32_t total32;
+    int32_t run = block_excl_scan<kBlock, int32_t>(sum, total32, s_w);
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      s_off[tid * ITEMS + i] = run;
+      run += c[i];
+    }
+    if (tid == 0) s_prefix = lookback_prefix(status, t, (int64_t)total32);
     __syncthreads();
     const int64_t prefix = s_prefix;
-    if (valid) a.t.cstart[base + j] = (int32_t)(nbase + prefix + my_off);
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const int p = i * kBlock + tid;
+      if (tb + p < F) a.t.cstart[base + tb + p] = (int32_t)(nbase + prefix + s_off[p]);
+    }
     if (t == ntiles - 1 && tid == 0) {
       const int64_t total = prefix + total32;
       ls->count[L + 1] = total;
@@ -248,7 +274,7 @@ __global__ __launch_bounds__(kBlock) void k_extend(ExtArgs a) {
     }
     // load-balanced expansion: thread k writes the k-th child of the tile
     for (int k = tid; k < total32; k += kBlock) {
-      int lo = 0, hi = kBlock - 1;
+      int lo = 0, hi = TILE - 1;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (s_off[mid] <= k) lo = mid; else hi = mid - 1;
@@ -262,7 +288,7 @@ __global__ __launch_bounds__(kBlock) void k_extend(ExtArgs a) {
       const int64_t cl = prefix + k;
       const int64_t cg = nbase + cl;
       if (cg < a.t.rec_cap) {
-        a.t.par[cg] = (int32_t)(base + t * kBlock + o);
+        a.t.par[cg] = (int32_t)(base + tb + o);
         a.t.info[cg] = make_info(w, v1l, wl == v1l ? F_CYC : 0u);
       }
       if (wl != v1l && cl < a.t.mask_cap) {
@@ -271,7 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_extend(ExtArgs a) {
 #pragma unroll
           for (int q = 0; q < W; ++q) pm[q] = s_mask[o * W + q];
         } else {
-          load_mask<W>(mcur + (t * kBlock + o) * W, pm);
+          load_mask<W>(mcur + (tb + o) * W, pm);
         }
         store_child_mask<W>(mnxt + cl * W, pm, wl);
       }
@@ -287,10 +313,10 @@ __global__ __launch_bounds__(kBlock) void k_extend(ExtArgs a) {
       __threadfence();
       ls->done = 0;
       if (!__hip_atomic_load(&ls->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-        const int64_t c = __hip_atomic_load(&ls->count[L + 1], __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT);
+        const int64_t cn = __hip_atomic_load(&ls->count[L + 1], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
         ls->off[L + 1] = nbase;
-        ls->cur_count = c;
+        ls->cur_count = cn;
         __threadfence();
         ls->level = L + 1;
       }
@@ -298,18 +324,28 @@ __global__ __launch_bounds__(kBlock) void k_extend(ExtArgs a) {
   }
 }
 
-hipError_t launch_extend(int W, const ExtArgs& a, int grid, hipStream_t st) {
+template <int ITEMS>
+static hipError_t launch_extend_items(int W, const ExtArgs& a, int grid, hipStream_t st) {
   switch (W) {
-    case 1: k_extend<1><<<grid, kBlock, 0, st>>>(a); break;
-    case 2: k_extend<2><<<grid, kBlock, 0, st>>>(a); break;
-    case 4: k_extend<4><<<grid, kBlock, 0, st>>>(a); break;
-    case 8: k_extend<8><<<grid, kBlock, 0, st>>>(a); break;
-    case 16: k_extend<16><<<grid, kBlock, 0, st>>>(a); break;
-    case 32: k_extend<32><<<grid, kBlock, 0, st>>>(a); break;
-    case 64: k_extend<64><<<grid, kBlock, 0, st>>>(a); break;
+    case 1: k_extend<1, ITEMS><<<grid, kBlock, 0, st>>>(a); break;
+    case 2: k_extend<2, ITEMS><<<grid, kBlock, 0, st>>>(a); break;
+    case 4: k_extend<4, ITEMS><<<grid, kBlock, 0, st>>>(a); break;
+    case 8: k_extend<8, ITEMS><<<grid, kBlock, 0, st>>>(a); break;
+    case 16: k_extend<16, ITEMS><<<grid, kBlock, 0, st>>>(a); break;
+    case 32: k_extend<32, ITEMS><<<grid, kBlock, 0, st>>>(a); break;
+    case 64: k_extend<64, ITEMS><<<grid, kBlock, 0, st>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_extend(int W, int items, const ExtArgs& a, int grid, hipStream_t st) {
+  switch (items) {
+    case 1: return launch_extend_items<1>(W, a, grid, st);
+    case 2: return launch_extend_items<2>(W, a, grid, st);
+    case 4: return launch_extend_items<4>(W, a, grid, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -69,6 +69,11 @@ class _BatchResult(ctypes.Structure):
                 ("reserved_", ctypes.c_int32)]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("items", ctypes.c_int32 * 7), ("wgs_per_cu", ctypes.c_int32 * 7),
+                ("best_ms", ctypes.c_double * 7)]
+
+
 # every symbol include/tpg.h declares, with its signature
 _SIGS = {
     "tpg_load_cfg_csr": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
@@ -92,6 +97,10 @@ _SIGS = {
                                             ctypes.POINTER(_Opts), ctypes.c_void_p,
                                             ctypes.POINTER(_BatchResult)]),
     "tpg_batch_result_free": (None, [ctypes.POINTER(_BatchResult)]),
+    "tpg_autotune": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                    ctypes.POINTER(_Opts), ctypes.POINTER(_Tuning)]),
+    "tpg_workspace_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Tuning)]),
+    "tpg_workspace_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Tuning)]),
     "tpg_features": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
                                     ctypes.c_void_p]),
     "tpg_mlp_num_params": (ctypes.c_int32, []),
@@ -484,3 +493,34 @@ class MLP:
             self.close()
         except Exception:
             pass
+
+
+def _tuning_dict(tu: _Tuning) -> Dict[str, list]:
+    return {"items": list(tu.items), "wgs_per_cu": list(tu.wgs_per_cu),
+            "best_ms": list(tu.best_ms)}
+
+
+def autotune(graphs, ws: Workspace, stream=None) -> Dict[str, list]:
+    """Times the extension kernel's launch shapes on these graphs and keeps
+    the fastest per visited-set width in `ws`."""
+    n = len(graphs)
+    arr = (ctypes.c_void_p * n)(*[g.handle.value for g in graphs])
+    o = _opts(ws, 0, stream, None)
+    tu = _Tuning()
+    _check(lib().tpg_autotune(arr, n, ctypes.byref(o), ctypes.byref(tu)))
+    return _tuning_dict(tu)
+
+
+def get_tuning(ws: Workspace) -> Dict[str, list]:
+    tu = _Tuning()
+    _check(lib().tpg_workspace_get_tuning(ws.handle, ctypes.byref(tu)))
+    return _tuning_dict(tu)
+
+
+def set_tuning(ws: Workspace, t: Dict[str, list]) -> None:
+    tu = _Tuning()
+    for i in range(7):
+        tu.items[i] = int(t["items"][i])
+        tu.wgs_per_cu[i] = int(t["wgs_per_cu"][i])
+        tu.best_ms[i] = float(t.get("best_ms", [0.0] * 7)[i])
+    _check(lib().tpg_workspace_set_tuning(ws.handle, ctypes.byref(tu)))

@@ -104,3 +104,33 @@ def test_batch_device_output():
         o = off[a:b + 1]
         assert np.array_equal(o - o[0], rt.offsets)
         assert np.array_equal(vtx[o[0]:o[-1]], rt.vertices)
+
+
+def test_tile_shapes_do_not_change_a_byte():
+    """Every launch shape of the extension kernel gives identical results."""
+    g = cfggen.c2_cfg(2)
+    h = tpg.load_cfg(g)
+    w = tpg.Workspace()
+    outs = []
+    for items in (1, 2, 4):
+        for wgs in (2, 16):
+            tpg.set_tuning(w, {"items": [items] * 7, "wgs_per_cu": [wgs] * 7})
+            say("case tile shape", items, wgs)
+            pp, tp, _ = tpg.test_paths(h, ws=w)
+            outs.append((pp.offsets.tobytes(), pp.vertices.tobytes(), tp.vertices.tobytes()))
+    assert all(o == outs[0] for o in outs)
+    rp = ref_pp(g, local=True)[0]
+    assert np.array_equal(np.frombuffer(outs[0][1], np.int32), rp.vertices)
+    w.close()
+
+
+def test_autotune_then_batch_is_exact():
+    cfgs = [cfggen.batch_member_cfg(cfggen.C3_SEED_BASE + s) for s in range(300)]
+    hs = [tpg.load_cfg(g) for g in cfgs]
+    w = tpg.Workspace()
+    say("case autotune")
+    t = tpg.autotune(hs, w)
+    assert t["best_ms"][0] > 0 and t["items"][0] in (1, 2, 4)
+    res, _ = tpg.batch_test_paths(hs, ws=w)
+    _check_batch(cfgs, res)
+    w.close()
