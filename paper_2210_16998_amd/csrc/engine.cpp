@@ -529,18 +529,14 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
 
   TPG_TRY(ws_reserve(ws, ws->tp_len, sizeof(int64_t) * (np + 1)));
   TPG_TRY(ws_reserve(ws, ws->tp_off, sizeof(int64_t) * (np + 1)));
-  TPG_TRY(ws_reserve(ws, ws->grp_cnt, sizeof(int32_t) * (n + 1)));
   TPG_TRY(ws_reserve(ws, ws->rb0, sizeof(int64_t) * (n + 2)));
   TPG_TRY(ws_reserve(ws, ws->rb1, sizeof(int64_t) * (n + 2)));
   TPG_TRY(ws_reserve(ws, ws->idx0, sizeof(int32_t) * (np + 1)));
   TPG_TRY(ws_reserve(ws, ws->idx1, sizeof(int32_t) * (np + 1)));
-  TPG_HIP(launch_zero_u32(ws->grp_cnt.as<uint32_t>(), n, st));
-  TPG_HIP(launch_tp_len(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), np, b,
-                        ws->tp_len.as<int64_t>(), ws->grp_cnt.as<int32_t>(), st));
+  TPG_HIP(launch_tp_len(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), np, n, b,
+                        ws->tp_len.as<int64_t>(), ws->rb0.as<int64_t>(), st));
   TPG_HIP(scan_i64(ws->tp_len.as<int64_t>(), ws->tp_off.as<int64_t>(), np, 0, sc,
                    ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
-  TPG_HIP(scan_i32_to_i64(ws->grp_cnt.as<int32_t>(), ws->rb0.as<int64_t>(), n, 0, sc + 1,
-                          ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
   TPG_HIP(hipMemcpyAsync(ws->h_scalars, sc, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TPG_HIP(hipMemcpyAsync(ws->h_scalars + 4, sc + 4, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TPG_HIP(hipStreamSynchronize(st));
@@ -585,24 +581,15 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
   T.n_vtx = ws->h_scalars[3];
   TPG_TRY(ws_reserve(ws, o.tp_off, sizeof(int64_t) * (T.n_tp + 1)));
   TPG_TRY(ws_reserve(ws, o.tp_vtx, sizeof(int32_t) * (T.n_vtx + 1)));
-  int64_t* cc = nullptr;
-  if (nc > 1) {
-    TPG_TRY(ws_reserve(ws, ws->comp_cnt, sizeof(int64_t) * 2 * (nc + 1)));
-    cc = ws->comp_cnt.as<int64_t>();
-    TPG_HIP(launch_zero_u64(reinterpret_cast<uint64_t*>(cc), 2 * (nc + 1), st));
-  }
   TPG_HIP(launch_gather(ws->tp_off.as<int64_t>(), ws->tp_vtx.as<int32_t>(), ii->as<int32_t>(), np,
                         ws->keep_pos.as<int64_t>(), ws->keep_voff.as<int64_t>(),
                         ws->keep_len.as<int64_t>(), o.tp_off.as<int64_t>(), o.tp_vtx.as<int32_t>(),
-                        ws->dg.comp, cc, cc ? cc + (nc + 1) : nullptr, st));
+                        st));
   TPG_HIP(launch_set_i64(o.tp_off.as<int64_t>() + T.n_tp, sc + 3, st));
   int64_t* cs = o.comp_starts.as<int64_t>();
-  if (nc > 1) {
-    TPG_HIP(scan_i64(cc, cs + 2 * (nc + 1), nc, 0, nullptr, ws->scan_status.as<uint64_t>(),
-                     ws->scan_ctr.as<uint32_t>(), st));
-    TPG_HIP(scan_i64(cc + (nc + 1), cs + 3 * (nc + 1), nc, 0, nullptr,
-                     ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
-  }
+  if (nc > 1)
+    TPG_HIP(launch_comp_bounds(o.tp_off.as<int64_t>(), o.tp_vtx.as<int32_t>(), T.n_tp, ws->dg.comp,
+                               nc, cs + 2 * (nc + 1), cs + 3 * (nc + 1), st));
   o.n_tp = T.n_tp;
   o.n_tpv = T.n_vtx;
   return TPG_OK;

@@ -7,7 +7,9 @@
 // exponentially enter as logarithms.
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <thread>
 #include <cstring>
 #include <deque>
 #include <vector>
@@ -210,10 +212,17 @@ void features_of(const tpg_graph* g, float* f) {
     // Tarjan numbers components in reverse topological order
     std::vector<double> lp(ncomp, -INFINITY);
     lp[comp[g->entry]] = 0.0;
+    std::vector<int32_t> cstart(ncomp + 1, 0), members(n);
+    for (int32_t v = 0; v < n; ++v) cstart[comp[v] + 1]++;
+    for (int32_t c = 0; c < ncomp; ++c) cstart[c + 1] += cstart[c];
+    {
+      std::vector<int32_t> fill(cstart.begin(), cstart.end() - 1);
+      for (int32_t v = 0; v < n; ++v) members[fill[comp[v]]++] = v;
+    }
     for (int32_t c = ncomp - 1; c >= 0; --c) {
       if (lp[c] == -INFINITY) continue;
-      for (int32_t v = 0; v < n; ++v) {
-        if (comp[v] != c) continue;
+      for (int32_t mi = cstart[c]; mi < cstart[c + 1]; ++mi) {
+        const int32_t v = members[mi];
         for (int32_t k = g->succ_ptr[v]; k < g->succ_ptr[v + 1]; ++k) {
           const int32_t d = comp[g->succ[k]];
           if (d == c) continue;
@@ -240,10 +249,31 @@ extern "C" {
 
 tpg_status tpg_features(const tpg_graph* const* graphs, int32_t n_graphs, float* out) {
   if (!graphs || !out || n_graphs < 0) return fail(TPG_ERR_INVALID_ARG, "NULL argument");
-  for (int32_t i = 0; i < n_graphs; ++i) {
+  for (int32_t i = 0; i < n_graphs; ++i)
     if (!graphs[i]) return fail(TPG_ERR_INVALID_ARG, "graph %d is NULL", i);
-    features_of(graphs[i], out + (size_t)32 * i);
+  // each graph's features are computed once (graphs are immutable), in
+  // parallel over host threads
+  auto one = [&](int32_t i) {
+    const tpg_graph* g = graphs[i];
+    std::call_once(g->feat_once, [g]() { features_of(g, g->feat); });
+    memcpy(out + (size_t)32 * i, g->feat, sizeof(float) * 32);
+  };
+  const int nt = (int)std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency()));
+  if (n_graphs < 64 || nt == 1) {
+    for (int32_t i = 0; i < n_graphs; ++i) one(i);
+    return TPG_OK;
   }
+  std::atomic<int32_t> next{0};
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nt; ++t)
+    pool.emplace_back([&]() {
+      for (;;) {
+        const int32_t i = next.fetch_add(16);
+        if (i >= n_graphs) break;
+        for (int32_t k = i; k < std::min(n_graphs, i + 16); ++k) one(k);
+      }
+    });
+  for (auto& th : pool) th.join();
   return TPG_OK;
 }
 

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -19,6 +20,9 @@ struct tpg_graph {
   std::vector<int32_t> succ_ptr, succ;
   std::vector<int32_t> pred_ptr, pred;
   uint64_t uid = 0;  // identifies the graph in device caches
+  // structural features, computed once on first use
+  mutable std::once_flag feat_once;
+  mutable float feat[32];
 };
 
 namespace tpg {

@@ -105,8 +105,9 @@ hipError_t launch_comp_pp_starts(const DGraph& g, const uint32_t* sub_cnt, const
                                  const int64_t* totals, int64_t* pp_start, int64_t* ppv_start,
                                  hipStream_t st);
 
-hipError_t launch_tp_len(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp,
-                         const BfsOut& b, int64_t* tp_len, int32_t* grp_cnt, hipStream_t st);
+// test-path lengths, and rb[v] = first prime path with first vertex >= v (v = 0..n)
+hipError_t launch_tp_len(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp, int n,
+                         const BfsOut& b, int64_t* tp_len, int64_t* rb, hipStream_t st);
 hipError_t launch_tp_write(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp,
                            const BfsOut& b, const int64_t* tp_off, int32_t* tp_vtx,
                            int32_t* idx, hipStream_t st);
@@ -117,13 +118,14 @@ hipError_t launch_merge_round(const int64_t* tp_off, const int32_t* tp_vtx, cons
 hipError_t launch_next_runs(const int64_t* rb, int64_t n_runs, int64_t* rb_out, hipStream_t st);
 hipError_t launch_dedup_flags(const int64_t* tp_off, const int32_t* tp_vtx, const int32_t* idx,
                               int64_t n, int64_t* keep_cnt, int64_t* keep_len, hipStream_t st);
-// comp_cnt / comp_vcnt (optional, zeroed): kept TPs and their entries per
-// component of their first vertex
 hipError_t launch_gather(const int64_t* tp_off, const int32_t* tp_vtx, const int32_t* idx,
                          int64_t n, const int64_t* keep_pos, const int64_t* keep_voff,
                          const int64_t* keep_len, int64_t* out_off, int32_t* out_vtx,
-                         const int32_t* comp, int64_t* comp_cnt, int64_t* comp_vcnt,
                          hipStream_t st);
+// start[c] / vstart[c] (c = 0..n_comp) of a sorted path list; off[n] = total
+hipError_t launch_comp_bounds(const int64_t* off, const int32_t* vtx, int64_t n,
+                              const int32_t* comp, int n_comp, int64_t* start, int64_t* vstart,
+                              hipStream_t st);
 hipError_t launch_set_i64(int64_t* p, const int64_t* src, hipStream_t st);
 hipError_t launch_set_value_i64(int64_t* p, int64_t value, hipStream_t st);
 

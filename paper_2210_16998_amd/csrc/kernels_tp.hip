@@ -220,42 +220,67 @@ hipError_t launch_localize(const int32_t* loc, int32_t* v, int64_t n, hipStream_
 // splice
 // ---------------------------------------------------------------------------
 __global__ void k_tp_len(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp, BfsOut b,
-                         int64_t* tp_len, int32_t* grp_cnt) {
+                         int64_t* tp_len) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_pp) return;
   const int64_t o0 = pp_off[i], o1 = pp_off[i + 1];
   const int v1 = pp_vtx[o0], vk = pp_vtx[o1 - 1];
   tp_len[i] = (b.pfx_off[v1 + 1] - b.pfx_off[v1]) + (o1 - o0) + (b.sfx_off[vk + 1] - b.sfx_off[vk]);
-  atomicAdd(&grp_cnt[v1], 1);
 }
 
-hipError_t launch_tp_len(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp,
-                         const BfsOut& b, int64_t* tp_len, int32_t* grp_cnt, hipStream_t st) {
+// Prime paths are sorted, hence grouped by first vertex: rb[v] = index of the
+// first prime path whose first vertex is >= v (v = 0..n), from the points
+// where the first vertex changes.
+__global__ void k_run_bounds(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp, int n,
+                             int64_t* rb) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pp) return;
+  const int cur = pp_vtx[pp_off[i]];
+  const int prev = i == 0 ? -1 : pp_vtx[pp_off[i - 1]];
+  for (int u = prev + 1; u <= cur; ++u) rb[u] = i;
+  if (i == n_pp - 1)
+    for (int u = cur + 1; u <= n; ++u) rb[u] = n_pp;
+}
+
+hipError_t launch_tp_len(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp, int n,
+                         const BfsOut& b, int64_t* tp_len, int64_t* rb, hipStream_t st) {
   if (n_pp == 0) return hipSuccess;
-  k_tp_len<<<(unsigned)((n_pp + kBlock - 1) / kBlock), kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, b,
-                                                                        tp_len, grp_cnt);
+  const unsigned grid = (unsigned)((n_pp + kBlock - 1) / kBlock);
+  k_tp_len<<<grid, kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, b, tp_len);
+  k_run_bounds<<<grid, kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, n, rb);
   return hipGetLastError();
 }
 
-__global__ void k_tp_write(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp, BfsOut b,
-                           const int64_t* tp_off, int32_t* tp_vtx, int32_t* idx) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per test path: lane l writes entries l, l + 64, ... (coalesced).
+__global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, const int32_t* pp_vtx,
+                                                     int64_t n_pp, BfsOut b, const int64_t* tp_off,
+                                                     int32_t* tp_vtx, int32_t* idx) {
+  const int64_t i = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   if (i >= n_pp) return;
+  const int lane = lane_id();
   const int64_t o0 = pp_off[i], o1 = pp_off[i + 1];
   const int v1 = pp_vtx[o0], vk = pp_vtx[o1 - 1];
-  int64_t w = tp_off[i];
-  for (int64_t k = b.pfx_off[v1]; k < b.pfx_off[v1 + 1]; ++k) tp_vtx[w++] = b.pfx[k];
-  for (int64_t k = o0; k < o1; ++k) tp_vtx[w++] = pp_vtx[k];
-  for (int64_t k = b.sfx_off[vk]; k < b.sfx_off[vk + 1]; ++k) tp_vtx[w++] = b.sfx[k];
-  idx[i] = (int32_t)i;
+  const int64_t p0 = b.pfx_off[v1], lp = b.pfx_off[v1 + 1] - p0;
+  const int64_t s0 = b.sfx_off[vk], ls = b.sfx_off[vk + 1] - s0;
+  const int64_t lq = o1 - o0;
+  const int64_t w = tp_off[i];
+  for (int64_t k = lane; k < lp + lq + ls; k += 64) {
+    int32_t x;
+    if (k < lp) x = b.pfx[p0 + k];
+    else if (k < lp + lq) x = pp_vtx[o0 + (k - lp)];
+    else x = b.sfx[s0 + (k - lp - lq)];
+    tp_vtx[w + k] = x;
+  }
+  if (lane == 0) idx[i] = (int32_t)i;
 }
 
 hipError_t launch_tp_write(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp,
                            const BfsOut& b, const int64_t* tp_off, int32_t* tp_vtx,
                            int32_t* idx, hipStream_t st) {
   if (n_pp == 0) return hipSuccess;
-  k_tp_write<<<(unsigned)((n_pp + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-      pp_off, pp_vtx, n_pp, b, tp_off, tp_vtx, idx);
+  const int64_t per = kBlock / 64;
+  k_tp_write<<<(unsigned)((n_pp + per - 1) / per), kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, b,
+                                                                    tp_off, tp_vtx, idx);
   return hipGetLastError();
 }
 
@@ -354,35 +379,63 @@ hipError_t launch_dedup_flags(const int64_t* tp_off, const int32_t* tp_vtx, cons
   return hipGetLastError();
 }
 
-__global__ void k_gather(const int64_t* off, const int32_t* vtx, const int32_t* idx, int64_t n,
-                         const int64_t* keep_pos, const int64_t* keep_voff,
-                         const int64_t* keep_len, int64_t* out_off, int32_t* out_vtx,
-                         const int32_t* comp, int64_t* comp_cnt, int64_t* comp_vcnt) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per sorted test path; kept ones are copied to their final place.
+__global__ __launch_bounds__(kBlock) void k_gather(const int64_t* off, const int32_t* vtx,
+                                                   const int32_t* idx, int64_t n,
+                                                   const int64_t* keep_pos,
+                                                   const int64_t* keep_voff,
+                                                   const int64_t* keep_len, int64_t* out_off,
+                                                   int32_t* out_vtx) {
+  const int64_t k = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   if (k >= n) return;
   if (keep_len[k] == 0) return;  // duplicate (every kept path has >= 1 entry)
+  const int lane = lane_id();
   const int64_t a = idx[k];
   const int64_t o = keep_voff[k];
-  out_off[keep_pos[k]] = o;
+  if (lane == 0) out_off[keep_pos[k]] = o;
   const int64_t l = off[a + 1] - off[a];
   const int32_t* src = vtx + off[a];
-  for (int64_t q = 0; q < l; ++q) out_vtx[o + q] = src[q];
-  if (comp_cnt) {
-    const int c = comp[src[0]];
-    atomicAdd((unsigned long long*)&comp_cnt[c], 1ull);
-    atomicAdd((unsigned long long*)&comp_vcnt[c], (unsigned long long)l);
-  }
+  for (int64_t q = lane; q < l; q += 64) out_vtx[o + q] = src[q];
 }
 
 hipError_t launch_gather(const int64_t* tp_off, const int32_t* tp_vtx, const int32_t* idx,
                          int64_t n, const int64_t* keep_pos, const int64_t* keep_voff,
                          const int64_t* keep_len, int64_t* out_off, int32_t* out_vtx,
-                         const int32_t* comp, int64_t* comp_cnt, int64_t* comp_vcnt,
                          hipStream_t st) {
   if (n == 0) return hipSuccess;
-  k_gather<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-      tp_off, tp_vtx, idx, n, keep_pos, keep_voff, keep_len, out_off, out_vtx, comp, comp_cnt,
-      comp_vcnt);
+  const int64_t per = kBlock / 64;
+  k_gather<<<(unsigned)((n + per - 1) / per), kBlock, 0, st>>>(
+      tp_off, tp_vtx, idx, n, keep_pos, keep_voff, keep_len, out_off, out_vtx);
+  return hipGetLastError();
+}
+
+// Per-component starts of a sorted path list (components own contiguous
+// id ranges, so the list is grouped by the component of the first vertex):
+// start[c] = first path of component >= c, vstart[c] = its first entry
+// (c = 0..n_comp); off[n] must hold the total.
+__global__ void k_comp_bounds(const int64_t* off, const int32_t* vtx, int64_t n, const int32_t* comp,
+                              int n_comp, int64_t* start, int64_t* vstart) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int cur = comp[vtx[off[k]]];
+  const int prev = k == 0 ? -1 : comp[vtx[off[k - 1]]];
+  for (int c = prev + 1; c <= cur; ++c) {
+    start[c] = k;
+    vstart[c] = off[k];
+  }
+  if (k == n - 1)
+    for (int c = cur + 1; c <= n_comp; ++c) {
+      start[c] = n;
+      vstart[c] = off[n];
+    }
+}
+
+hipError_t launch_comp_bounds(const int64_t* off, const int32_t* vtx, int64_t n,
+                              const int32_t* comp, int n_comp, int64_t* start, int64_t* vstart,
+                              hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  k_comp_bounds<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(off, vtx, n, comp, n_comp,
+                                                                          start, vstart);
   return hipGetLastError();
 }
 
