@@ -14,6 +14,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -30,6 +31,51 @@ def _workload():
         w = json.load(f)
     rec = max(w["c2"], key=lambda r: r["n_pp"])
     return cfggen.c2_cfg(rec["seed"]), rec
+
+
+def _bytes_per_extension(n: int) -> int:
+    """Algorithmic HBM bytes per path extension: the child's 8-byte record is
+    written once and read once as a parent (16 B), and its visited set of
+    ceil(n / 64) words is written once and read once."""
+    return 16 + 2 * 8 * ((n + 63) // 64)
+
+
+def _stress(args):
+    """The 400-vertex stress CFG: one-pass prime paths (device output), with
+    the extension kernel's roofline measured on its ~4.7e8 extensions."""
+    import torch
+    from paper_2210_16998_amd import cfggen, tpg
+    g = cfggen.c5_cfg()
+    h = tpg.load_cfg(g)
+    ws = tpg.Workspace(0)
+    stream = torch.cuda.Stream()
+    cap = 64 << 30  # the stress workload's pool cap (64 GiB of HBM)
+    tpg.prime_paths(h, ws=ws, flags=tpg.TPG_OUT_DEVICE, stream=stream, pool_cap=cap)
+    torch.cuda.synchronize()
+    times, k_ms, k_launches = [], 0.0, 0
+    for _ in range(args.stress_reps):
+        t = time.perf_counter()
+        _, st = tpg.prime_paths(h, ws=ws, flags=tpg.TPG_OUT_DEVICE, stream=stream, pool_cap=cap)
+        times.append(time.perf_counter() - t)
+        k_ms += st["ms_extend_kernel"]
+        k_launches += st["n_extend_launches"]
+    bpe = _bytes_per_extension(g.n)
+    avg = k_ms / max(1, k_launches)
+    per_launch = st["n_extensions"] * bpe / max(1, st["n_extend_launches"])
+    ach = per_launch / (avg * 1e-3) / 1e9 if avg > 0 else 0.0
+    ms = 1000.0 * statistics.median(times)
+    ws.close()
+    return {"workload": f"stress CFG, {g.n} vertices, {g.n_edges} arcs (3 nested whiles, 16-way "
+                        f"switch, 60 diamonds), prime paths only",
+            "n_pp": st["n_pp"], "n_extensions": st["n_extensions"], "levels": st["n_levels"],
+            "ms_per_run_median": ms, "prime_paths_per_s": st["n_pp"] / (ms * 1e-3),
+            "extensions_per_s": st["n_extensions"] / (ms * 1e-3),
+            "extend_kernel_ms": k_ms / args.stress_reps,
+            "device_bytes": st["device_bytes"], "pool_cap_bytes": cap,
+            "roofline": {"bound": "hbm", "kernel": "k_extend", "achieved": ach,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                         "bytes_per_extension": bpe, "launches_per_run": st["n_extend_launches"],
+                         "avg_launch_ms": avg}}
 
 
 def _cpu_baseline(g, reps: int):
@@ -58,6 +104,8 @@ def main() -> int:
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--no-stress", action="store_true")
+    ap.add_argument("--stress-reps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is "
@@ -81,26 +129,39 @@ def main() -> int:
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # timed region: every call returns after its stream has drained; the
+    # level loop is replayed from captured HIP graphs
+    times = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        pp, tp, st = step(flags | tpg.TPG_NO_TIMING)
+        t = time.perf_counter()
+        step(flags | tpg.TPG_NO_TIMING)
+        times.append(time.perf_counter() - t)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms = 1000.0 * dt / args.steps
-
-    # per-kernel timing run (HIP events on the library's stream, same launches)
-    pp, tp, st = step()
+    # kernel-timed pass over the same steps: the same launches issued one by
+    # one with a HIP event pair on the library's stream around every
+    # extension launch, plus per-phase events
+    k_ms, k_launches, phases = 0.0, 0, []
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        pp, tp, st = step()
+        k_ms += st["ms_extend_kernel"]
+        k_launches += st["n_extend_launches"]
+        phases.append(st)
+    torch.cuda.synchronize()
+    ms_timed = 1000.0 * (time.perf_counter() - t2) / args.steps
     n_pp, n_ext = st["n_pp"], st["n_extensions"]
-    W = 1
-    while W * 64 < g.n:
-        W *= 2
-    bytes_per_ext = 16 + 2 * 8 * W
-    k_ms = st["ms_extend_kernel"]
-    achieved = (n_ext * bytes_per_ext) / (k_ms * 1e-3) / 1e9 if k_ms > 0 else 0.0
+    bytes_per_ext = _bytes_per_extension(g.n)
+    avg_launch_ms = k_ms / max(1, k_launches)
+    # algorithmic bytes of one launch: the run's extensions spread over its launches
+    achieved = (n_ext * bytes_per_ext / max(1, st["n_extend_launches"])) / (avg_launch_ms * 1e-3) / 1e9 \
+        if avg_launch_ms > 0 else 0.0
 
     # plain per-CFG two-pass form, same graph, for context
     for _ in range(2):
-        step(flags | tpg.TPG_FORCE_TWO_PASS)
+        step(flags | tpg.TPG_FORCE_TWO_PASS | tpg.TPG_NO_TIMING)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     reps2 = max(3, args.steps // 4)
@@ -108,6 +169,9 @@ def main() -> int:
         step(flags | tpg.TPG_FORCE_TWO_PASS | tpg.TPG_NO_TIMING)
     torch.cuda.synchronize()
     ms_plain = 1000.0 * (time.perf_counter() - t1) / reps2
+
+    def med(key):
+        return statistics.median(p[key] for p in phases)
 
     out = {
         "metric": METRIC,
@@ -128,15 +192,21 @@ def main() -> int:
                    "levels": st["n_levels"]},
         "extensions_per_s": n_ext / (ms * 1e-3),
         "test_paths_per_s": st["n_tp"] / (ms * 1e-3),
-        "phase_ms": {"extend": st["ms_extend"], "rank_materialize": st["ms_rank"],
-                     "test_paths": st["ms_tp"], "total_device": st["ms_total"]},
+        "step_ms": {"median": 1000.0 * statistics.median(times),
+                    "mean": 1000.0 * statistics.fmean(times),
+                    "kernel_timed_pass_mean": ms_timed},
+        "phase_ms_median": {"extend": med("ms_extend"), "rank_materialize": med("ms_rank"),
+                            "test_paths": med("ms_tp"), "total_device": med("ms_total"),
+                            "extend_kernel": med("ms_extend_kernel")},
         "plain_two_pass_ms_per_step": ms_plain,
         "roofline": {"bound": "hbm", "kernel": "k_extend", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "bytes_per_extension": bytes_per_ext,
-                     "launches": st["n_extend_launches"],
-                     "avg_launch_ms": k_ms / max(1, st["n_extend_launches"])},
+                     "launches_per_step": st["n_extend_launches"],
+                     "avg_launch_ms": avg_launch_ms},
     }
+    if not args.no_stress:
+        out["stress"] = _stress(args)
     if not args.no_batch:
         out["batched"] = _batched(args)
     if not args.no_cpu:

@@ -230,11 +230,12 @@ void tpg_batch_result_free(tpg_batch_result* r);
  * Launch-shape tuning of the frontier-extension kernel.
  *
  * Per visited-set width W = 2^i words (index i = 0..6): parents per thread
- * (1, 2 or 4; a tile is 256 * items parents) and persistent workgroups per
- * compute unit (1..32).  tpg_autotune times every (items, 2/4/8/16) pair on
- * the given graphs (grouped by width as in the batched form), keeps the
- * fastest per width in the workspace (opts->ws, required) and returns the
- * table; results never depend on the tuning.
+ * (2, 4, 8 or 16; a tile is 256 * items parents and claims its slice of the
+ * next level with one device-scope atomic) and persistent workgroups per
+ * compute unit (1..32; default 8 items, 4 workgroups).  tpg_autotune times
+ * every (items, 1/2/4/8) pair on the given graphs (grouped by width as in the
+ * batched form), keeps the fastest per width in the workspace (opts->ws,
+ * required) and returns the table; results never depend on the tuning.
  * ---------------------------------------------------------------------- */
 typedef struct tpg_tuning {
   int32_t items[7];

@@ -1,6 +1,5 @@
 // Device-side building blocks shared by the kernels of libtpg (gfx950,
-// wave64): node encoding, wave/block scans, decoupled look-back, visited-set
-// bit tests.
+// wave64): node encoding, wave/block scans, visited-set bit tests.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -73,41 +72,6 @@ __device__ __forceinline__ T block_excl_scan(T x, T& total, T* s_w) {
   __syncthreads();
   total = tot;
   return pre + inc - x;
-}
-
-// Decoupled look-back (single-pass chained scan).  Each tile publishes its
-// aggregate, then walks back over its predecessors until it finds one with an
-// inclusive prefix.  Flag and value share one 64-bit word, so relaxed atomics
-// suffice.  Tiles are numbered in the order workgroups acquired them from an
-// atomic counter, so every predecessor is already running: the wait ends.
-constexpr uint64_t kStA = 1ull << 62;
-constexpr uint64_t kStP = 2ull << 62;
-constexpr uint64_t kStVal = (1ull << 62) - 1;
-
-__device__ __forceinline__ int64_t lookback_prefix(uint64_t* status, int64_t tile, int64_t agg) {
-  if (tile == 0) {
-    __hip_atomic_store(&status[0], kStP | (uint64_t)agg, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-    return 0;
-  }
-  __hip_atomic_store(&status[tile], kStA | (uint64_t)agg, __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
-  int64_t excl = 0;
-  int64_t j = tile - 1;
-  for (;;) {
-    const uint64_t s = __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint64_t f = s & ~kStVal;
-    if (f == 0) {
-      __builtin_amdgcn_s_sleep(1);
-      continue;
-    }
-    excl += (int64_t)(s & kStVal);
-    if (f == kStP) break;
-    --j;
-  }
-  __hip_atomic_store(&status[tile], kStP | (uint64_t)(excl + agg), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
-  return excl;
 }
 
 // Visited-set bit test on a register-resident mask of W 64-bit words.

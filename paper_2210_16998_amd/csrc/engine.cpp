@@ -42,6 +42,11 @@ int pow2_words(int n) {
 struct tpg_workspace {
   int device = 0;
   hipStream_t own_stream = nullptr;
+  // BFS tables run on a side stream, forked after the graph upload and
+  // joined before the splice, so they overlap the extension
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool bfs_pending = false;
   int num_cus = 256;
   size_t bytes = 0;
   uint64_t cap = 0;  // pool cap of the running call (0: none)
@@ -52,16 +57,17 @@ struct tpg_workspace {
   DGraph dg{};
 
   // path tree
-  DevBuf par, info, cstart, mask0, mask1, tile_status, tile_ctr, ls;
-  int64_t rec_cap = 0, mask_cap = 0, max_tiles = 0;
+  DevBuf par, info, cstart, nch, mask0, mask1, ls;
+  int64_t rec_cap = 0, mask_cap = 0;
   int mask_words = 0;
   // ranking
   DevBuf sub_cnt, sub_len, leaf_by_rank, totals, cycles;
   // scans
   DevBuf scan_status, scan_ctr, scalars;
+  DevBuf scan2_status, scalars2;  // the side stream's own scan scratch
   // test paths
   DevBuf bfs_i32, pfx_off, sfx_off, pfx, sfx;
-  DevBuf tp_len, tp_off, tp_vtx, idx0, idx1, grp_cnt, rb0, rb1;
+  DevBuf tp_len, tp_off, tp_vtx, tp_grp, idx0, idx1, grp_cnt, rb0, rb1;
   DevBuf keep_cnt, keep_len, keep_pos, keep_voff, comp_cnt;
   // per-level, per-component counts (batched labels)
   DevBuf lvl_comp;
@@ -88,8 +94,10 @@ struct tpg_workspace {
 
   // extension-kernel launch shape per visited-set width (index log2 W):
   // parents per thread (tile = 256 * items) and persistent workgroups per CU
-  int tune_items[7] = {1, 1, 1, 1, 1, 1, 1};
-  int tune_wgs[7] = {8, 8, 8, 8, 8, 8, 8};
+  // parents per thread (tile = 256 * items; one output claim per tile) and
+  // persistent workgroups per CU, per visited-set width
+  int tune_items[7] = {8, 8, 8, 8, 8, 8, 8};
+  int tune_wgs[7] = {4, 4, 4, 4, 4, 4, 4};
   double tune_ms[7] = {0, 0, 0, 0, 0, 0, 0};
 };
 
@@ -196,17 +204,16 @@ tpg_status reserve_tree(tpg_workspace* ws, int64_t rec, int64_t msk, int W, hipS
   TPG_TRY(ws_reserve(ws, ws->info, sizeof(uint32_t) * rec, keep_rec > 0, st, sizeof(uint32_t) * keep_rec));
   TPG_TRY(ws_reserve(ws, ws->cstart, sizeof(int32_t) * (rec + 1), keep_rec > 0, st,
                      sizeof(int32_t) * (keep_rec + 1)));
+  TPG_TRY(ws_reserve(ws, ws->nch, (size_t)rec, keep_rec > 0, st, (size_t)keep_rec));
   ws->rec_cap = std::min<int64_t>(ws->par.cap / sizeof(int32_t), ws->cstart.cap / sizeof(int32_t) - 1);
   ws->rec_cap = std::min<int64_t>(ws->rec_cap, ws->info.cap / sizeof(uint32_t));
+  ws->rec_cap = std::min<int64_t>(ws->rec_cap, (int64_t)ws->nch.cap);
   const size_t mb = sizeof(uint64_t) * (size_t)msk * W;
   TPG_TRY(ws_reserve(ws, ws->mask0, mb, keep_parity == 0 && keep_mask > 0, st,
                      sizeof(uint64_t) * (size_t)keep_mask * W));
   TPG_TRY(ws_reserve(ws, ws->mask1, mb, keep_parity == 1 && keep_mask > 0, st,
                      sizeof(uint64_t) * (size_t)keep_mask * W));
   ws->mask_cap = (int64_t)(std::min(ws->mask0.cap, ws->mask1.cap) / (sizeof(uint64_t) * W));
-  ws->max_tiles = ws->mask_cap / kBlock + 2;
-  TPG_TRY(ws_reserve(ws, ws->tile_status, sizeof(uint64_t) * 2 * ws->max_tiles));
-  TPG_TRY(ws_reserve(ws, ws->tile_ctr, sizeof(uint32_t) * 4));
   TPG_TRY(ws_reserve(ws, ws->ls, sizeof(LevelState)));
   ws->mask_words = W;
   return TPG_OK;
@@ -218,16 +225,13 @@ ExtArgs make_args(tpg_workspace* ws) {
   a.t.par = ws->par.as<int32_t>();
   a.t.info = ws->info.as<uint32_t>();
   a.t.cstart = ws->cstart.as<int32_t>();
+  a.t.nch = ws->nch.as<uint8_t>();
   a.t.mask[0] = ws->mask0.as<uint64_t>();
   a.t.mask[1] = ws->mask1.as<uint64_t>();
   a.t.rec_cap = ws->rec_cap;
   a.t.mask_cap = ws->mask_cap;
   a.t.mask_words = ws->mask_words;
   a.ls = ws->ls.as<LevelState>();
-  a.tile_status[0] = ws->tile_status.as<uint64_t>();
-  a.tile_status[1] = ws->tile_status.as<uint64_t>() + ws->max_tiles;
-  a.tile_ctr = ws->tile_ctr.as<uint32_t>();
-  a.max_tiles = ws->max_tiles;
   return a;
 }
 
@@ -278,8 +282,9 @@ void drop_level_graphs(tpg_workspace* ws) {
   ws->level_graphs.clear();
 }
 
-// `len` extension launches, replayed from a captured HIP graph (launch
-// arguments are baked in; a change of buffers or stream drops the graphs).
+// `len` levels (extension + advance launches), replayed from a captured HIP
+// graph (launch arguments are baked in; a change of buffers or stream drops
+// the graphs).
 tpg_status launch_levels_graph(tpg_workspace* ws, const ExtArgs& a, int W, int items, int grid,
                                int len, hipStream_t st) {
   if (memcmp(&ws->graph_args, &a, sizeof a) != 0 || ws->graph_W != W || ws->graph_grid != grid ||
@@ -300,6 +305,7 @@ tpg_status launch_levels_graph(tpg_workspace* ws, const ExtArgs& a, int W, int i
   TPG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   for (int i = 0; i < len; ++i) {
     hipError_t e = launch_extend(W, items, a, grid, st);
+    if (e == hipSuccess) e = launch_advance(a, st);
     if (e != hipSuccess) {
       hipGraph_t g2 = nullptr;
       (void)hipStreamEndCapture(st, &g2);
@@ -338,12 +344,15 @@ tpg_status build_tree_onepass(tpg_workspace* ws, const HostUnion& U, hipStream_t
   int level_before = 1;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
   for (;;) {
+    // timed calls launch directly with an event pair around each extension
+    // launch; untimed calls replay the captured level loop
     evs.clear();
     if (tm.on) {
       for (int b = 0; b < batch; ++b) {
         hipEvent_t e0 = tm.mark();
         TPG_HIP(launch_extend(W, items, a, grid, st));
         hipEvent_t e1 = tm.mark();
+        TPG_HIP(launch_advance(a, st));
         evs.emplace_back(e0, e1);
       }
     } else {
@@ -502,30 +511,56 @@ struct TPResult {
   int64_t n_spliced = 0, n_tp = 0, n_vtx = 0;
 };
 
-tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t st,
-                             const PPResult& P, TPResult& T, OutSet& o) {
-  const int n = U.n;
-  const int nc = U.n_comp;
-  TPG_TRY(ws_reserve(ws, ws->bfs_i32, sizeof(int32_t) * 4 * (size_t)n));
-  TPG_TRY(ws_reserve(ws, ws->pfx_off, sizeof(int64_t) * (n + 1)));
-  TPG_TRY(ws_reserve(ws, ws->sfx_off, sizeof(int64_t) * (n + 1)));
-  const int64_t np = P.n_pp;
-  T.n_spliced = np;
-  TPG_TRY(reserve_scan(ws, std::max<int64_t>(np, n)));
+BfsOut bfs_views(tpg_workspace* ws, int n) {
   BfsOut b{};
   int32_t* bi = ws->bfs_i32.as<int32_t>();
   b.dist_f = bi;
   b.parent = bi + n;
   b.dist_b = bi + 2 * n;
   b.next = bi + 3 * n;
+  b.pre = bi + 4 * n;
+  b.pend = bi + 5 * n;
   b.pfx_off = ws->pfx_off.as<int64_t>();
   b.sfx_off = ws->sfx_off.as<int64_t>();
+  return b;
+}
+
+// BFS distances, tree ranks and prefix/suffix table offsets of the uploaded
+// union, on the side stream after everything already queued on `st`.
+tpg_status bfs_start(tpg_workspace* ws, const HostUnion& U, hipStream_t st) {
+  const int n = U.n;
+  TPG_TRY(ws_reserve(ws, ws->bfs_i32, sizeof(int32_t) * 6 * (size_t)n));
+  TPG_TRY(ws_reserve(ws, ws->pfx_off, sizeof(int64_t) * (n + 1)));
+  TPG_TRY(ws_reserve(ws, ws->sfx_off, sizeof(int64_t) * (n + 1)));
+  TPG_TRY(ws_reserve(ws, ws->scan2_status, sizeof(uint64_t) * (scan_tiles(n) + 2)));
+  TPG_TRY(ws_reserve(ws, ws->scalars2, sizeof(int64_t) * 8));
+  const BfsOut b = bfs_views(ws, n);
+  hipStream_t side = ws->side_stream;
+  int64_t* sc2 = ws->scalars2.as<int64_t>();
+  TPG_HIP(hipEventRecord(ws->ev_fork, st));
+  TPG_HIP(hipStreamWaitEvent(side, ws->ev_fork, 0));
+  TPG_HIP(launch_bfs_dist(ws->dg, b, side));
+  TPG_HIP(scan_i32_to_i64(b.dist_f, b.pfx_off, n, 0, sc2 + 0, ws->scan2_status.as<uint64_t>(),
+                          nullptr, side));
+  TPG_HIP(scan_i32_to_i64(b.dist_b, b.sfx_off, n, 0, sc2 + 1, ws->scan2_status.as<uint64_t>(),
+                          nullptr, side));
+  TPG_HIP(hipEventRecord(ws->ev_join, side));
+  ws->bfs_pending = true;
+  return TPG_OK;
+}
+
+tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t st,
+                             const PPResult& P, TPResult& T, OutSet& o) {
+  const int n = U.n;
+  const int nc = U.n_comp;
+  if (!ws->bfs_pending) TPG_TRY(bfs_start(ws, U, st));
+  ws->bfs_pending = false;
+  TPG_HIP(hipStreamWaitEvent(st, ws->ev_join, 0));
+  const int64_t np = P.n_pp;
+  T.n_spliced = np;
+  TPG_TRY(reserve_scan(ws, std::max<int64_t>(np, n)));
+  BfsOut b = bfs_views(ws, n);
   int64_t* sc = ws->scalars.as<int64_t>();
-  TPG_HIP(launch_bfs_dist(ws->dg, b, st));
-  TPG_HIP(scan_i32_to_i64(b.dist_f, b.pfx_off, n, 0, sc + 4, ws->scan_status.as<uint64_t>(),
-                          ws->scan_ctr.as<uint32_t>(), st));
-  TPG_HIP(scan_i32_to_i64(b.dist_b, b.sfx_off, n, 0, sc + 5, ws->scan_status.as<uint64_t>(),
-                          ws->scan_ctr.as<uint32_t>(), st));
 
   TPG_TRY(ws_reserve(ws, ws->tp_len, sizeof(int64_t) * (np + 1)));
   TPG_TRY(ws_reserve(ws, ws->tp_off, sizeof(int64_t) * (np + 1)));
@@ -533,12 +568,15 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
   TPG_TRY(ws_reserve(ws, ws->rb1, sizeof(int64_t) * (n + 2)));
   TPG_TRY(ws_reserve(ws, ws->idx0, sizeof(int32_t) * (np + 1)));
   TPG_TRY(ws_reserve(ws, ws->idx1, sizeof(int32_t) * (np + 1)));
+  TPG_TRY(ws_reserve(ws, ws->tp_grp, sizeof(int32_t) * (np + 1)));
   TPG_HIP(launch_tp_len(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), np, n, b,
-                        ws->tp_len.as<int64_t>(), ws->rb0.as<int64_t>(), st));
+                        ws->tp_len.as<int64_t>(), ws->tp_grp.as<int32_t>(), ws->rb0.as<int64_t>(),
+                        st));
   TPG_HIP(scan_i64(ws->tp_len.as<int64_t>(), ws->tp_off.as<int64_t>(), np, 0, sc,
                    ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
   TPG_HIP(hipMemcpyAsync(ws->h_scalars, sc, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  TPG_HIP(hipMemcpyAsync(ws->h_scalars + 4, sc + 4, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TPG_HIP(hipMemcpyAsync(ws->h_scalars + 4, ws->scalars2.p, 2 * sizeof(int64_t),
+                         hipMemcpyDeviceToHost, st));
   TPG_HIP(hipStreamSynchronize(st));
   const int64_t tp_total = ws->h_scalars[0];
   TPG_TRY(ws_reserve(ws, ws->pfx, sizeof(int32_t) * (ws->h_scalars[4] + 1)));
@@ -551,14 +589,16 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
                           ws->tp_off.as<int64_t>(), ws->tp_vtx.as<int32_t>(), ws->idx0.as<int32_t>(),
                           st));
   // merge the per-first-vertex runs
+  TpOrder K{ws->tp_off.as<int64_t>(), ws->tp_vtx.as<int32_t>(), ws->tp_grp.as<int32_t>(),
+            b.pre, b.pend, b.dist_f};
   int64_t runs = n;
   DevBuf* ri = &ws->rb0;
   DevBuf* ro = &ws->rb1;
   DevBuf* ii = &ws->idx0;
   DevBuf* io = &ws->idx1;
   while (runs > 1) {
-    TPG_HIP(launch_merge_round(ws->tp_off.as<int64_t>(), ws->tp_vtx.as<int32_t>(), ii->as<int32_t>(),
-                               io->as<int32_t>(), ri->as<int64_t>(), runs, np, st));
+    TPG_HIP(launch_merge_round(K, ii->as<int32_t>(), io->as<int32_t>(), ri->as<int64_t>(), runs,
+                               np, st));
     TPG_HIP(launch_next_runs(ri->as<int64_t>(), runs, ro->as<int64_t>(), st));
     std::swap(ri, ro);
     std::swap(ii, io);
@@ -569,8 +609,8 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
   TPG_TRY(ws_reserve(ws, ws->keep_len, sizeof(int64_t) * (np + 1)));
   TPG_TRY(ws_reserve(ws, ws->keep_pos, sizeof(int64_t) * (np + 1)));
   TPG_TRY(ws_reserve(ws, ws->keep_voff, sizeof(int64_t) * (np + 1)));
-  TPG_HIP(launch_dedup_flags(ws->tp_off.as<int64_t>(), ws->tp_vtx.as<int32_t>(), ii->as<int32_t>(),
-                             np, ws->keep_cnt.as<int64_t>(), ws->keep_len.as<int64_t>(), st));
+  TPG_HIP(launch_dedup_flags(K, ii->as<int32_t>(), np, ws->keep_cnt.as<int64_t>(),
+                             ws->keep_len.as<int64_t>(), st));
   TPG_HIP(scan_i64(ws->keep_cnt.as<int64_t>(), ws->keep_pos.as<int64_t>(), np, 0, sc + 2,
                    ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
   TPG_HIP(scan_i64(ws->keep_len.as<int64_t>(), ws->keep_voff.as<int64_t>(), np, 0, sc + 3,
@@ -657,8 +697,11 @@ tpg_status begin_call(const tpg_opts* opts, CallCtx& c) {
 }
 
 tpg_status run_pp(const HostUnion& U, CallCtx& c, Timer& tm, TreeResult& R, PPResult& P,
-                  OutSet& o, hipEvent_t* e_ext, int64_t rec0 = 0, int64_t msk0 = 0) {
+                  OutSet& o, hipEvent_t* e_ext, int64_t rec0 = 0, int64_t msk0 = 0,
+                  bool with_bfs = false) {
   TPG_TRY(upload_union(c.ws, U, c.st));
+  c.ws->bfs_pending = false;
+  if (with_bfs) TPG_TRY(bfs_start(c.ws, U, c.st));
   if (c.flags & TPG_FORCE_TWO_PASS)
     TPG_TRY(build_tree_twopass(c.ws, U, c.st, tm, R));
   else
@@ -727,6 +770,12 @@ tpg_status tpg_workspace_create(int32_t device, tpg_workspace** out) {
     delete ws;
     return fail(TPG_ERR_DEVICE, "hipStreamCreate failed");
   }
+  if (hipStreamCreateWithFlags(&ws->side_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&ws->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ws->ev_join, hipEventDisableTiming) != hipSuccess) {
+    tpg_workspace_free(ws);
+    return fail(TPG_ERR_DEVICE, "side stream / events");
+  }
   if (hipHostMalloc((void**)&ws->h_ls, sizeof(LevelState), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&ws->h_scalars, sizeof(int64_t) * 16, hipHostMallocDefault) != hipSuccess) {
     tpg_workspace_free(ws);
@@ -741,13 +790,15 @@ void tpg_workspace_free(tpg_workspace* ws) {
   if (!ws) return;
   (void)hipSetDevice(ws->device);
   if (ws->own_stream) (void)hipStreamSynchronize(ws->own_stream);
-  DevBuf* bufs[] = {&ws->g_csr, &ws->par, &ws->info, &ws->cstart, &ws->mask0, &ws->mask1,
-                    &ws->tile_status, &ws->tile_ctr, &ws->ls, &ws->sub_cnt, &ws->sub_len,
+  if (ws->side_stream) (void)hipStreamSynchronize(ws->side_stream);
+  DevBuf* bufs[] = {&ws->g_csr, &ws->par, &ws->info, &ws->cstart, &ws->nch, &ws->mask0,
+                    &ws->mask1, &ws->ls, &ws->sub_cnt, &ws->sub_len,
                     &ws->leaf_by_rank, &ws->totals, &ws->cycles, &ws->scan_status,
                     &ws->scan_ctr, &ws->scalars, &ws->bfs_i32, &ws->pfx_off, &ws->sfx_off,
-                    &ws->pfx, &ws->sfx, &ws->tp_len, &ws->tp_off, &ws->tp_vtx, &ws->idx0,
+                    &ws->pfx, &ws->sfx, &ws->tp_len, &ws->tp_off, &ws->tp_vtx, &ws->tp_grp, &ws->idx0,
                     &ws->idx1, &ws->grp_cnt, &ws->rb0, &ws->rb1, &ws->keep_cnt, &ws->keep_len,
                     &ws->keep_pos, &ws->keep_voff, &ws->comp_cnt, &ws->lvl_comp, &ws->b_pp_off,
+                    &ws->scan2_status, &ws->scalars2,
                     &ws->b_pp_vtx, &ws->b_tp_off, &ws->b_tp_vtx, &ws->b_desc};
   for (DevBuf* b : bufs) ws_release(ws, *b);
   for (OutSet& o : ws->out) {
@@ -762,6 +813,9 @@ void tpg_workspace_free(tpg_workspace* ws) {
   if (ws->h_ls) (void)hipHostFree(ws->h_ls);
   if (ws->h_scalars) (void)hipHostFree(ws->h_scalars);
   if (ws->own_stream) (void)hipStreamDestroy(ws->own_stream);
+  if (ws->side_stream) (void)hipStreamDestroy(ws->side_stream);
+  if (ws->ev_fork) (void)hipEventDestroy(ws->ev_fork);
+  if (ws->ev_join) (void)hipEventDestroy(ws->ev_join);
   delete ws;
 }
 
@@ -835,7 +889,7 @@ tpg_status tpg_test_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* p
   TPResult T;
   hipEvent_t ext_done = nullptr;
   OutSet& o = c.ws->out[0];
-  tpg_status s = run_pp(U, c, tm, R, P, o, &ext_done);
+  tpg_status s = run_pp(U, c, tm, R, P, o, &ext_done, 0, 0, true);
   if (s == TPG_OK && timing) TPG_HIP(hipEventRecord(phase[1], c.st));
   if (s == TPG_OK) s = test_paths_device(c.ws, U, c.st, P, T, o);
   if (s == TPG_OK && timing) TPG_HIP(hipEventRecord(phase[2], c.st));
@@ -966,7 +1020,7 @@ tpg_status tpg_batch_test_paths(const tpg_graph* const* graphs, int32_t n_graphs
     TreeResult R;
     PPResult P;
     TPResult T;
-    TPG_TRY(run_pp(U, c, tm, R, P, o, nullptr, rec0, msk0));
+    TPG_TRY(run_pp(U, c, tm, R, P, o, nullptr, rec0, msk0, true));
     TPG_TRY(test_paths_device(ws, U, c.st, P, T, o));
     const int nc = U.n_comp;
     if (want_levels) {
@@ -1071,7 +1125,7 @@ tpg_status tpg_workspace_set_tuning(tpg_workspace* ws, const tpg_tuning* t) {
   if (!ws || !t) return fail(TPG_ERR_INVALID_ARG, "NULL argument");
   for (int i = 0; i < 7; ++i) {
     const int it = t->items[i], wg = t->wgs_per_cu[i];
-    if ((it != 1 && it != 2 && it != 4) || wg < 1 || wg > 32)
+    if ((it != 2 && it != 4 && it != 8 && it != 16) || wg < 1 || wg > 32)
       return fail(TPG_ERR_INVALID_ARG, "tuning entry %d: items %d, workgroups per CU %d", i, it, wg);
   }
   for (int i = 0; i < 7; ++i) {
@@ -1107,8 +1161,8 @@ tpg_status tpg_autotune(const tpg_graph* const* graphs, int32_t n_graphs, const 
     while ((1 << k) < w) ++k;
     if (unions[k].n + graphs[i]->n <= kMaxUnionVertices) add_component(unions[k], graphs[i]);
   }
-  const int items_c[3] = {1, 2, 4};
-  const int wgs_c[4] = {2, 4, 8, 16};
+  const int items_c[4] = {2, 4, 8, 16};
+  const int wgs_c[4] = {1, 2, 4, 8};
   Timer tm{ws, c.st, true};
   for (int k = 0; k < 7; ++k) {
     const HostUnion& U = unions[k];

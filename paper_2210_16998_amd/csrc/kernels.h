@@ -17,11 +17,13 @@ constexpr int kMaxLevels = 4096 + 4;  // path entries <= n + 1
 struct LevelState {
   int32_t level;     // level currently to be extended (paths of `level` entries)
   int32_t overflow;  // non-zero: the last level did not fit the buffers
-  uint32_t done;     // workgroups finished in the running launch
+  uint32_t done;     // unused, kept zero
   int32_t pad;
   int64_t cur_count; // count[level]
   int64_t pad2;
-  int64_t count[kMaxLevels];  // nodes (paths) per level, cycle closures included
+  // nodes (paths) per level, cycle closures included; while level L is
+  // extended, count[L + 1] is the running claim counter of its tiles
+  int64_t count[kMaxLevels];
   int64_t off[kMaxLevels];    // global index of the first node of each level
 };
 
@@ -30,6 +32,7 @@ struct TreeBufs {
   int32_t* par;       // [rec_cap]
   uint32_t* info;     // [rec_cap]
   int32_t* cstart;    // [rec_cap + 1] global index of the first child
+  uint8_t* nch;       // [rec_cap] number of children (out-degree <= 64)
   uint64_t* mask[2];  // frontier visited sets, ping-pong by level parity [mask_cap * W]
   int64_t rec_cap;
   int64_t mask_cap;
@@ -41,9 +44,6 @@ struct ExtArgs {
   DGraph g;
   TreeBufs t;
   LevelState* ls;
-  uint64_t* tile_status[2];  // [max_tiles] each, ping-pong by level parity
-  uint32_t* tile_ctr;        // [2]
-  int64_t max_tiles;
 };
 
 // --- path tree -------------------------------------------------------------
@@ -51,6 +51,8 @@ hipError_t launch_seed(const ExtArgs& a, hipStream_t st);
 // items: parents per thread and tile (tile = 256 * items); grid: persistent workgroups
 hipError_t launch_extend(int W, int items, const ExtArgs& a, int grid, hipStream_t st);
 hipError_t launch_resume_fix(const ExtArgs& a, int level, hipStream_t st);
+// one thread: next level's offset and size from the claims, or the overflow flag
+hipError_t launch_advance(const ExtArgs& a, hipStream_t st);
 // two-pass (plain) form
 hipError_t launch_count(int W, const ExtArgs& a, int L, int64_t base, int64_t F, hipStream_t st);
 hipError_t launch_fill(int W, const ExtArgs& a, int L, int64_t base, int64_t F, hipStream_t st);
@@ -94,8 +96,19 @@ struct BfsOut {
   int32_t* pfx;      // [pfx_off[n]]
   int64_t* sfx_off;  // [n+1] suffix table offsets (entries after v)
   int32_t* sfx;      // [sfx_off[n]]
+  int32_t* pre;      // [n] graph-wide preorder rank in the BFS tree (children ascending)
+  int32_t* pend;     // [n] end of v's subtree rank range
 };
-// one workgroup per component: dist_f, parent, dist_b, next
+// What the test-path comparison reads.
+struct TpOrder {
+  const int64_t* off;  // [n + 1] test-path offsets
+  const int32_t* vtx;  // test-path entries
+  const int32_t* grp;  // [n] first vertex of each test path's prime path
+  const int32_t* pre;  // BfsOut::pre
+  const int32_t* pend; // BfsOut::pend
+  const int32_t* dist; // BfsOut::dist_f
+};
+// one workgroup per component: dist_f, parent, pre, pend, dist_b, next
 hipError_t launch_bfs_dist(const DGraph& g, const BfsOut& b, hipStream_t st);
 // after pfx_off / sfx_off are scans of dist_f / dist_b: fill pfx / sfx
 hipError_t launch_bfs_tables(const DGraph& g, const BfsOut& b, hipStream_t st);
@@ -107,17 +120,17 @@ hipError_t launch_comp_pp_starts(const DGraph& g, const uint32_t* sub_cnt, const
 
 // test-path lengths, and rb[v] = first prime path with first vertex >= v (v = 0..n)
 hipError_t launch_tp_len(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp, int n,
-                         const BfsOut& b, int64_t* tp_len, int64_t* rb, hipStream_t st);
+                         const BfsOut& b, int64_t* tp_len, int32_t* grp, int64_t* rb,
+                         hipStream_t st);
 hipError_t launch_tp_write(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp,
                            const BfsOut& b, const int64_t* tp_off, int32_t* tp_vtx,
                            int32_t* idx, hipStream_t st);
 // one round of pairwise merging of sorted runs [rb[r], rb[r+1]) of idx
-hipError_t launch_merge_round(const int64_t* tp_off, const int32_t* tp_vtx, const int32_t* idx_in,
-                              int32_t* idx_out, const int64_t* rb, int64_t n_runs, int64_t n,
-                              hipStream_t st);
+hipError_t launch_merge_round(const TpOrder& K, const int32_t* idx_in, int32_t* idx_out,
+                              const int64_t* rb, int64_t n_runs, int64_t n, hipStream_t st);
 hipError_t launch_next_runs(const int64_t* rb, int64_t n_runs, int64_t* rb_out, hipStream_t st);
-hipError_t launch_dedup_flags(const int64_t* tp_off, const int32_t* tp_vtx, const int32_t* idx,
-                              int64_t n, int64_t* keep_cnt, int64_t* keep_len, hipStream_t st);
+hipError_t launch_dedup_flags(const TpOrder& K, const int32_t* idx, int64_t n, int64_t* keep_cnt,
+                              int64_t* keep_len, hipStream_t st);
 hipError_t launch_gather(const int64_t* tp_off, const int32_t* tp_vtx, const int32_t* idx,
                          int64_t n, const int64_t* keep_pos, const int64_t* keep_voff,
                          const int64_t* keep_len, int64_t* out_off, int32_t* out_vtx,

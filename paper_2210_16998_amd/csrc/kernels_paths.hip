@@ -15,20 +15,24 @@
 // How (the paper's asynchronous thread-per-vertex schedule and its per-vertex
 // path tables are not used):
 //  * All paths of one level form a frontier of (parent index, vertex) nodes;
-//    parents keep the children contiguous and in ascending successor order,
-//    so every level is in lexicographic order and a node's subtree occupies a
-//    contiguous range of every deeper level.
+//    the children of one parent are contiguous and in ascending successor
+//    order, and each node records where its children start and how many
+//    there are.
 //  * The visited set of a frontier path lives as a bitmask of W 64-bit words
 //    (registers while testing, HBM between levels, two levels alive).
-//  * One workgroup handles a tile of 256 parents: choice masks over successor
-//    slots, a block scan of child counts, one decoupled look-back per tile for
-//    the tile's global child offset (order preserved in a single pass), then
-//    a load-balanced expansion where consecutive threads write consecutive
-//    children, so record and mask stores are coalesced.
+//  * One workgroup handles a tile of 256 * ITEMS parents: choice masks over
+//    successor slots, a block scan of child counts, then ONE device-scope
+//    atomic claim of the tile's slice of the next level, then a
+//    load-balanced expansion where consecutive threads write consecutive
+//    children, so record and mask stores are coalesced.  No workgroup ever
+//    waits for another one; the order of tile slices inside a level is the
+//    order in which the claims landed, which ranking does not depend on.
 //  * Levels follow each other on the device: the level index, per-level
-//    counts and offsets live in device memory and the last workgroup of a
-//    launch advances them.  A level that does not fit sets an overflow flag;
-//    the host grows the buffers and replays that level.
+//    counts and offsets live in device memory and a one-thread kernel after
+//    each extension advances them, or raises the overflow flag when the
+//    level did not fit; the host then grows the buffers and replays it.
+//  * The plain two-pass form (count, scan, host-visible size, fill) keeps
+//    children in parent order and serves as the exact reference form.
 
 #include "kernels.h"
 
@@ -40,20 +44,17 @@ namespace tpg {
 __global__ void k_seed(ExtArgs a) {
   const int n = a.g.n;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  // tile status buffer 1 / counters are used by level 1 (odd parity)
-  for (int64_t k = i; k < a.max_tiles; k += (int64_t)gridDim.x * blockDim.x) a.tile_status[1][k] = 0;
+  LevelState* ls = a.ls;
+  // every level's claim counter starts at zero
+  for (int64_t k = i; k < kMaxLevels; k += (int64_t)gridDim.x * blockDim.x) {
+    ls->count[k] = k == 1 ? n : 0;
+    ls->off[k] = 0;
+  }
   if (i == 0) {
-    a.tile_ctr[0] = 0;
-    a.tile_ctr[1] = 0;
-    LevelState* ls = a.ls;
     ls->level = 1;
     ls->overflow = 0;
     ls->done = 0;
     ls->cur_count = n;
-    ls->count[0] = 0;
-    ls->off[0] = 0;
-    ls->count[1] = n;
-    ls->off[1] = 0;
   }
   if (i < n) {
     const int v = (int)i;
@@ -70,28 +71,51 @@ __global__ void k_seed(ExtArgs a) {
 }
 
 hipError_t launch_seed(const ExtArgs& a, hipStream_t st) {
-  const int64_t work = std::max<int64_t>(a.max_tiles, (int64_t)a.g.n * a.t.mask_words);
+  const int64_t work = std::max<int64_t>(kMaxLevels, (int64_t)a.g.n * a.t.mask_words);
   const int grid = (int)std::min<int64_t>(1024, (work + kBlock - 1) / kBlock + 1);
   k_seed<<<grid, kBlock, 0, st>>>(a);
   return hipGetLastError();
 }
 
-// Resume after an overflow: clear the tile bookkeeping of the level to replay.
+// Resume after an overflow: the level is extended again from a zero claim.
 __global__ void k_resume_fix(ExtArgs a, int level) {
-  const int par = level & 1;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.max_tiles;
-       k += (int64_t)gridDim.x * blockDim.x)
-    a.tile_status[par][k] = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    a.tile_ctr[par] = 0;
-    a.ls->done = 0;
+    a.ls->count[level + 1] = 0;
     a.ls->overflow = 0;
+    a.ls->done = 0;
   }
 }
 
 hipError_t launch_resume_fix(const ExtArgs& a, int level, hipStream_t st) {
-  const int grid = (int)std::min<int64_t>(1024, (a.max_tiles + kBlock - 1) / kBlock + 1);
-  k_resume_fix<<<grid, kBlock, 0, st>>>(a, level);
+  if (level < 1 || level + 1 >= kMaxLevels) return hipErrorInvalidValue;
+  k_resume_fix<<<1, 64, 0, st>>>(a, level);
+  return hipGetLastError();
+}
+
+// Level advance after an extension launch: the claimed total is the next
+// level's size; a level that does not fit raises the overflow flag instead
+// (the extension kernel stored nothing beyond the capacities).
+__global__ void k_advance(ExtArgs a) {
+  if (threadIdx.x != 0) return;
+  LevelState* ls = a.ls;
+  if (ls->overflow) return;
+  const int L = ls->level;
+  const int64_t F = ls->count[L];
+  if (F == 0 || L + 2 >= kMaxLevels) return;
+  const int64_t total = ls->count[L + 1];
+  const int64_t nbase = ls->off[L] + F;
+  if (nbase + total + 1 > a.t.rec_cap || total > a.t.mask_cap ||
+      nbase + total >= (int64_t)INT32_MAX) {
+    ls->overflow = 1;
+    return;
+  }
+  ls->off[L + 1] = nbase;
+  ls->cur_count = total;
+  ls->level = L + 1;
+}
+
+hipError_t launch_advance(const ExtArgs& a, hipStream_t st) {
+  k_advance<<<1, 64, 0, st>>>(a);
   return hipGetLastError();
 }
 
@@ -162,50 +186,38 @@ __device__ __forceinline__ void store_child_mask(uint64_t* dst, const uint64_t (
 }
 
 // ---------------------------------------------------------------------------
-// one-pass extension of level L -> L+1 (device-sized, order preserving)
+// one-pass extension of level L -> L+1 (device-sized, claim per tile)
 // ---------------------------------------------------------------------------
-// A tile is ITEMS * 256 consecutive parents.  Loads are strided by the
-// workgroup size (coalesced); the scan gives each thread ITEMS consecutive
-// parents; the expansion gives each thread every 256th child of the tile.
+// A tile is ITEMS * 256 consecutive parents; tile t goes to workgroup
+// t mod grid.  Loads are strided by the workgroup size (coalesced); the scan
+// gives each thread ITEMS consecutive parents; the expansion gives each
+// thread every 256th child of the tile.
 template <int W, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_extend(ExtArgs a) {
   constexpr int TILE = kBlock * ITEMS;
   constexpr bool kLdsMask = W * ITEMS <= 16;  // visited sets of the tile in LDS (<= 32 KiB)
-  __shared__ int64_t s_tile;
   __shared__ int64_t s_prefix;
   __shared__ int32_t s_off[TILE];
   __shared__ uint64_t s_vm[TILE];
   __shared__ uint32_t s_inf[TILE];
-  __shared__ int32_t s_kk[TILE];
-  __shared__ int32_t s_cb[TILE];
   __shared__ uint64_t s_mask[kLdsMask ? TILE * W : 1];
   __shared__ int32_t s_w[kBlock / 64];
 
   LevelState* ls = a.ls;
-  if (__hip_atomic_load(&ls->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  if (ls->overflow) return;
   const int L = ls->level;
   const int64_t F = ls->count[L];
-  if (F == 0) return;
+  if (F == 0 || L + 2 >= kMaxLevels) return;
   const int64_t base = ls->off[L];
   const int64_t nbase = base + F;
   const int par = L & 1;
   const uint64_t* mcur = a.t.mask[par];
   uint64_t* mnxt = a.t.mask[par ^ 1];
-  uint64_t* status = a.tile_status[par];
+  unsigned long long* claim = reinterpret_cast<unsigned long long*>(&ls->count[L + 1]);
   const int tid = (int)threadIdx.x;
 
-  // clear the other parity's tile bookkeeping for the next level
-  for (int64_t k = (int64_t)blockIdx.x * kBlock + tid; k < a.max_tiles;
-       k += (int64_t)gridDim.x * kBlock)
-    a.tile_status[par ^ 1][k] = 0;
-  if (blockIdx.x == 0 && tid == 0) a.tile_ctr[par ^ 1] = 0;
-
   const int64_t ntiles = (F + TILE - 1) / TILE;
-  for (;;) {
-    if (tid == 0) s_tile = (int64_t)atomicAdd(&a.tile_ctr[par], 1u);
-    __syncthreads();
-    const int64_t t = s_tile;
-    if (t >= ntiles) break;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t tb = t * TILE;
     // load + choices + filter, parent p = i * 256 + tid
 #pragma unroll
@@ -230,8 +242,6 @@ __global__ __launch_bounds__(kBlock) void k_extend(ExtArgs a) {
       s_off[p] = __builtin_popcountll(vm);
       s_vm[p] = vm;
       s_inf[p] = inf;
-      s_kk[p] = k0;
-      s_cb[p] = cb;
       if constexpr (kLdsMask) {
 #pragma unroll
         for (int q = 0; q < W; ++q) s_mask[p * W + q] = m[q];
@@ -253,23 +263,17 @@ __global__ __launch_bounds__(kBlock) void k_extend(ExtArgs a) {
       s_off[tid * ITEMS + i] = run;
       run += c[i];
     }
-    if (tid == 0) s_prefix = lookback_prefix(status, t, (int64_t)total32);
+    // one claim per tile (tiles without children claim nothing)
+    if (tid == 0)
+      s_prefix = total32 ? (int64_t)atomicAdd(claim, (unsigned long long)total32) : 0;
     __syncthreads();
     const int64_t prefix = s_prefix;
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       const int p = i * kBlock + tid;
-      if (tb + p < F) a.t.cstart[base + tb + p] = (int32_t)(nbase + prefix + s_off[p]);
-    }
-    if (t == ntiles - 1 && tid == 0) {
-      const int64_t total = prefix + total32;
-      ls->count[L + 1] = total;
-      const bool ovf = (nbase + total + 1 > a.t.rec_cap) || (total > a.t.mask_cap) ||
-                       (nbase + total >= (int64_t)INT32_MAX);
-      if (ovf) {
-        __hip_atomic_store(&ls->overflow, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        a.t.cstart[nbase] = (int32_t)(nbase + total);
+      if (tb + p < F) {
+        a.t.cstart[base + tb + p] = (int32_t)(nbase + prefix + s_off[p]);
+        a.t.nch[base + tb + p] = (uint8_t)__builtin_popcountll(s_vm[p]);
       }
     }
     // load-balanced expansion: thread k writes the k-th child of the tile
@@ -283,8 +287,9 @@ __global__ __launch_bounds__(kBlock) void k_extend(ExtArgs a) {
       const int slot = select_bit(s_vm[o], k - s_off[o]);
       const uint32_t pinf = s_inf[o];
       const int v1l = node_v1l(pinf);
-      const int w = a.g.s[s_kk[o] + slot];
-      const int wl = w - s_cb[o];
+      const int pv = node_v(pinf);
+      const int w = a.g.s[a.g.sp[pv] + slot];
+      const int wl = w - (pv - a.g.loc[pv]);
       const int64_t cl = prefix + k;
       const int64_t cg = nbase + cl;
       if (cg < a.t.rec_cap) {
@@ -303,24 +308,6 @@ __global__ __launch_bounds__(kBlock) void k_extend(ExtArgs a) {
       }
     }
     __syncthreads();
-  }
-
-  // level advance by the last workgroup to finish
-  if (tid == 0) {
-    __threadfence();
-    const uint32_t d = atomicAdd(&ls->done, 1u);
-    if (d == gridDim.x - 1) {
-      __threadfence();
-      ls->done = 0;
-      if (!__hip_atomic_load(&ls->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-        const int64_t cn = __hip_atomic_load(&ls->count[L + 1], __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-        ls->off[L + 1] = nbase;
-        ls->cur_count = cn;
-        __threadfence();
-        ls->level = L + 1;
-      }
-    }
   }
 }
 
@@ -341,9 +328,10 @@ static hipError_t launch_extend_items(int W, const ExtArgs& a, int grid, hipStre
 
 hipError_t launch_extend(int W, int items, const ExtArgs& a, int grid, hipStream_t st) {
   switch (items) {
-    case 1: return launch_extend_items<1>(W, a, grid, st);
     case 2: return launch_extend_items<2>(W, a, grid, st);
     case 4: return launch_extend_items<4>(W, a, grid, st);
+    case 8: return launch_extend_items<8>(W, a, grid, st);
+    case 16: return launch_extend_items<16>(W, a, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -369,6 +357,7 @@ __global__ __launch_bounds__(kBlock) void k_count(ExtArgs a, int L, int64_t base
     }
   }
   a.t.cstart[base + j] = cnt;
+  a.t.nch[base + j] = (uint8_t)cnt;
 }
 
 template <int W>
@@ -442,7 +431,7 @@ __global__ __launch_bounds__(kBlock) void k_up(ExtArgs a, int L, int64_t base, i
       l = L;
       cyc = (inf & F_CYC) ? 1 : 0;
     } else if (!(inf & F_TERM)) {
-      const int64_t c0 = a.t.cstart[g], c1 = a.t.cstart[g + 1];
+      const int64_t c0 = a.t.cstart[g], c1 = c0 + a.t.nch[g];
       for (int64_t x = c0; x < c1; ++x) {
         c += sub_cnt[x];
         l += sub_len[x];
@@ -511,7 +500,7 @@ __global__ __launch_bounds__(kBlock) void k_down(ExtArgs a, int64_t base, int64_
   if (inf & (F_CYC | F_TERM)) return;
   int64_t r = sub_cnt[g];
   int64_t o = sub_len[g];
-  const int64_t c0 = a.t.cstart[g], c1 = a.t.cstart[g + 1];
+  const int64_t c0 = a.t.cstart[g], c1 = c0 + a.t.nch[g];
   for (int64_t x = c0; x < c1; ++x) {
     const uint32_t cc = sub_cnt[x];
     const int64_t cl = sub_len[x];
@@ -546,17 +535,33 @@ hipError_t launch_pp_offsets(const int64_t* leaf_by_rank, const int64_t* sub_len
 }
 
 // Each thread writes one prime path by walking parent links from its leaf.
+// The walk yields entries back to front; they are buffered 32 at a time in
+// registers and stored as one burst of consecutive addresses, so that lines
+// are written whole instead of one word per dependent load.
 __global__ __launch_bounds__(kBlock) void k_pp_write(ExtArgs a, const int64_t* leaf_by_rank,
                                                      const int64_t* pp_off, int64_t n_pp,
                                                      int32_t* pp_vtx) {
+  constexpr int kBuf = 32;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n_pp) return;
   int64_t x = leaf_by_rank[i];
   int64_t pos = pp_off[i + 1] - 1;
   const int64_t lo = pp_off[i];
   while (pos >= lo && x >= 0) {
-    pp_vtx[pos--] = node_v(a.t.info[x]);
-    x = a.t.par[x];
+    int32_t buf[kBuf];
+    int cnt = 0;
+#pragma unroll
+    for (int j = 0; j < kBuf; ++j) {
+      if (pos - j >= lo && x >= 0) {
+        buf[j] = node_v(a.t.info[x]);
+        x = a.t.par[x];
+        cnt = j + 1;
+      }
+    }
+#pragma unroll
+    for (int j = kBuf - 1; j >= 0; --j)
+      if (j < cnt) pp_vtx[pos - j] = buf[j];
+    pos -= cnt;
   }
 }
 

@@ -1,13 +1,14 @@
-// Device-wide exclusive scans (single pass, decoupled look-back) and small
-// fill helpers.  Fills are kernels rather than memsets so that the sequences
-// that use them can be captured in HIP graphs.
+// Device-wide exclusive scans (reduce, scan of tile sums, scan down: three
+// launches, no workgroup waits on another) and small fill helpers.  Fills are
+// kernels rather than memsets so that the sequences that use them can be
+// captured in HIP graphs.
 
 #include "kernels.h"
 
 namespace tpg {
 
-constexpr int kScanItems = 4;
-constexpr int kScanTile = kBlock * kScanItems;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kBlock * kScanItems;  // 4096 items per tile
 
 int64_t scan_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
@@ -44,51 +45,108 @@ hipError_t launch_set_i64(int64_t* p, const int64_t* src, hipStream_t st) {
   return hipGetLastError();
 }
 
-// out[i] = add + sum(in[0..i)) for i <= n (out has n+1 entries; in == out is
-// allowed); *total = add + sum(in).  status / ctr must be zero on entry
-// (status: scan_tiles(n) slots).
-template <class Tin, class Tout>
-__global__ __launch_bounds__(kBlock) void k_scan(const Tin* in, Tout* out, int64_t n, int64_t add,
-                                                 int64_t* total, uint64_t* status, uint32_t* ctr) {
-  __shared__ int64_t s_tile, s_prefix;
+// Phase 1: sums[t] = sum of tile t (loads strided by the workgroup size).
+template <class Tin>
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const Tin* in, int64_t n, int64_t* sums) {
   __shared__ int64_t s_w[kBlock / 64];
-  if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(ctr, 1u);
+  const int64_t t = blockIdx.x;
+  const int64_t b = t * kScanTile + threadIdx.x;
+  int64_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = b + (int64_t)k * kBlock;
+    sum += i < n ? (int64_t)in[i] : 0;
+  }
+  int64_t tot;
+  block_excl_scan<kBlock, int64_t>(sum, tot, s_w);
+  if (threadIdx.x == 0) sums[t] = tot;
+}
+
+// Phase 2 (one workgroup): sums[t] <- add + sum(sums[0..t)), sums[ntile] and
+// *total <- add + everything.
+__global__ __launch_bounds__(1024) void k_scan_tiles(int64_t* sums, int64_t ntile, int64_t add,
+                                                     int64_t* total) {
+  __shared__ int64_t s_w[16];
+  int64_t carry = add;
+  for (int64_t c = 0; c < ntile; c += 1024) {
+    const int64_t i = c + threadIdx.x;
+    const int64_t v = i < ntile ? sums[i] : 0;
+    int64_t tot;
+    const int64_t pre = block_excl_scan<1024, int64_t>(v, tot, s_w);
+    if (i < ntile) sums[i] = carry + pre;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    sums[ntile] = carry;
+    if (total) *total = carry;
+  }
+}
+
+// Phase 3: out[i] = sums[t] + exclusive prefix inside the tile; the last tile
+// also writes out[n].  Staged through LDS so that global loads and stores are
+// strided by the workgroup size while each thread scans 16 consecutive items.
+template <class Tin, class Tout>
+__global__ __launch_bounds__(kBlock) void k_scan_down(const Tin* in, Tout* out, int64_t n,
+                                                      const int64_t* sums, int64_t ntile) {
+  constexpr int PAD = kScanTile + kScanTile / kScanItems;  // one pad slot per 16 items
+  __shared__ int64_t s_v[PAD];
+  __shared__ int64_t s_w[kBlock / 64];
+  const int64_t t = blockIdx.x;
+  const int64_t b = t * kScanTile;
+  const int tid = (int)threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int x = k * kBlock + tid;
+    const int64_t i = b + x;
+    s_v[x + x / kScanItems] = i < n ? (int64_t)in[i] : 0;
+  }
   __syncthreads();
-  const int64_t t = s_tile;
-  const int64_t b = t * kScanTile + (int64_t)threadIdx.x * kScanItems;
   int64_t v[kScanItems];
   int64_t sum = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    v[k] = (b + k < n) ? (int64_t)in[b + k] : 0;
+    v[k] = s_v[tid * (kScanItems + 1) + k];
     sum += v[k];
   }
-  int64_t agg;
-  const int64_t pre = block_excl_scan<kBlock, int64_t>(sum, agg, s_w);
-  if (threadIdx.x == 0) s_prefix = lookback_prefix(status, t, agg);
-  __syncthreads();
-  int64_t run = add + s_prefix + pre;
+  int64_t tot;
+  int64_t run = sums[t] + block_excl_scan<kBlock, int64_t>(sum, tot, s_w);
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    if (b + k < n) out[b + k] = (Tout)run;
+    s_v[tid * (kScanItems + 1) + k] = run;
     run += v[k];
   }
-  const int64_t ntile = (n + kScanTile - 1) / kScanTile;
-  if (t == (ntile > 0 ? ntile - 1 : 0) && threadIdx.x == kBlock - 1) {
-    out[n] = (Tout)run;
-    if (total) *total = run;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int x = k * kBlock + tid;
+    const int64_t i = b + x;
+    if (i < n) out[i] = (Tout)s_v[x + x / kScanItems];
   }
+  if (t == ntile - 1 && tid == 0) out[n] = (Tout)sums[ntile];
 }
 
+template <class Tout>
+__global__ void k_scan_empty(Tout* out, int64_t add, int64_t* total) {
+  out[0] = (Tout)add;
+  if (total) *total = add;
+}
+
+// out[i] = add + sum(in[0..i)) for i <= n (out has n+1 entries; in == out is
+// allowed); *total = add + sum(in).  `status` holds scan_tiles(n) tile sums;
+// `ctr` is not used.
 template <class Tin, class Tout>
 static hipError_t scan_impl(const Tin* in, Tout* out, int64_t n, int64_t add, int64_t* total,
                             uint64_t* status, uint32_t* ctr, hipStream_t st) {
-  const int64_t ntile = std::max<int64_t>(1, (n + kScanTile - 1) / kScanTile);
-  hipError_t e = launch_zero_u64(status, ntile + 1, st);
-  if (e != hipSuccess) return e;
-  e = launch_zero_u32(ctr, 1, st);
-  if (e != hipSuccess) return e;
-  k_scan<Tin, Tout><<<(unsigned)ntile, kBlock, 0, st>>>(in, out, n, add, total, status, ctr);
+  (void)ctr;
+  if (n <= 0) {
+    k_scan_empty<Tout><<<1, 1, 0, st>>>(out, add, total);
+    return hipGetLastError();
+  }
+  const int64_t ntile = (n + kScanTile - 1) / kScanTile;
+  int64_t* sums = reinterpret_cast<int64_t*>(status);
+  k_scan_reduce<Tin><<<(unsigned)ntile, kBlock, 0, st>>>(in, n, sums);
+  k_scan_tiles<<<1, 1024, 0, st>>>(sums, ntile, add, total);
+  k_scan_down<Tin, Tout><<<(unsigned)ntile, kBlock, 0, st>>>(in, out, n, sums, ntile);
   return hipGetLastError();
 }
 

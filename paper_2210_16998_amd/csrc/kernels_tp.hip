@@ -18,7 +18,8 @@
 // vertex; within a group all test paths share the prefix and keep the order
 // of their prime paths, and no two are equal.  The groups are therefore
 // already sorted runs, merged pairwise (merge path partitioning, each thread
-// merges a fixed-size chunk), after which duplicates are adjacent.
+// merges a fixed-size chunk), after which duplicates are adjacent.  Most
+// comparisons are decided by the BFS tree alone (see tp_cmp).
 
 #include <climits>
 
@@ -56,13 +57,20 @@ __device__ int lds_excl_scan(int16_t* data, int m, int32_t* s_w) {
 }
 
 // One workgroup per component: distances from the entry with the FIFO
-// (smallest discoverer) parent, distances to the exit, and next[].
+// (smallest discoverer) parent, the BFS tree's preorder (children in
+// ascending order) as rank ranges, distances to the exit, and next[].
+//
+// The forward search keeps one queue in LDS whose layers are contiguous;
+// the children of a vertex form a contiguous ascending block of the next
+// layer, which gives subtree sizes bottom-up and preorder ranks top-down.
 __global__ __launch_bounds__(kBfsThreads) void k_bfs_dist(DGraph g, BfsOut b) {
   __shared__ int16_t s_df[kMaxComp];
   __shared__ int16_t s_db[kMaxComp];
-  __shared__ int32_t s_best[kMaxComp];
-  __shared__ int16_t s_layer[2][kMaxComp];
-  __shared__ int16_t s_cnt[kMaxComp];
+  __shared__ int32_t s_key[kMaxComp];   // smallest discoverer key, then the parent (local id)
+  __shared__ int16_t s_q[kMaxComp];     // forward queue (layers contiguous), then reverse queue
+  __shared__ int16_t s_lb[kMaxComp + 2];  // layer d of the forward queue: [s_lb[d], s_lb[d + 1])
+  __shared__ int16_t s_cnt[kMaxComp];   // per-layer child counts, then preorder ranks
+  __shared__ int32_t s_sz[kMaxComp];    // subtree sizes, then reverse-search marks
   __shared__ int32_t s_w[kBfsThreads / 64];
   __shared__ int32_t s_m;
   const int c = (int)blockIdx.x;
@@ -72,87 +80,126 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_dist(DGraph g, BfsOut b) {
   for (int v = tid; v < nc; v += kBfsThreads) {
     s_df[v] = -1;
     s_db[v] = -1;
-    s_best[v] = INT_MAX;
+    s_key[v] = INT_MAX;
+    s_sz[v] = 1;
     b.parent[base + v] = -1;
     b.next[base + v] = -1;
   }
-  __syncthreads();
+  const int el = g.centry[c] - base;
   if (tid == 0) {
-    s_df[g.centry[c] - base] = 0;
-    s_layer[0][0] = (int16_t)(g.centry[c] - base);
+    s_df[el] = 0;
+    s_key[el] = -1;
+    s_q[0] = (int16_t)el;
+    s_lb[0] = 0;
+    s_lb[1] = 1;
   }
   __syncthreads();
-  int cur = 0, m = 1, d = 0;
-  while (m > 0) {
+  int qb = 0, qe = 1, d = 0;
+  while (qe > qb) {
+    const int m = qe - qb;
     for (int q = tid; q < m; q += kBfsThreads) {
-      const int u = base + s_layer[cur][q];
+      const int u = base + s_q[qb + q];
       for (int k = g.sp[u]; k < g.sp[u + 1]; ++k) {
         const int wl = g.s[k] - base;
-        if (s_df[wl] == -1) atomicMin(&s_best[wl], q * 64 + (k - g.sp[u]));
+        if (s_df[wl] == -1) atomicMin(&s_key[wl], q * 64 + (k - g.sp[u]));
       }
     }
     __syncthreads();
     for (int q = tid; q < m; q += kBfsThreads) {
-      const int u = base + s_layer[cur][q];
+      const int u = base + s_q[qb + q];
       int cnt = 0;
       for (int k = g.sp[u]; k < g.sp[u + 1]; ++k) {
         const int wl = g.s[k] - base;
-        if (s_df[wl] == -1 && s_best[wl] == q * 64 + (k - g.sp[u])) ++cnt;
+        if (s_df[wl] == -1 && s_key[wl] == q * 64 + (k - g.sp[u])) ++cnt;
       }
       s_cnt[q] = (int16_t)cnt;
     }
     __syncthreads();
     const int m2 = lds_excl_scan(s_cnt, m, s_w);
     for (int q = tid; q < m; q += kBfsThreads) {
-      const int u = base + s_layer[cur][q];
-      int pos = s_cnt[q];
+      const int u = base + s_q[qb + q];
+      int pos = qe + s_cnt[q];
       for (int k = g.sp[u]; k < g.sp[u + 1]; ++k) {
         const int wl = g.s[k] - base;
-        if (s_df[wl] == -1 && s_best[wl] == q * 64 + (k - g.sp[u])) {
-          s_layer[cur ^ 1][pos++] = (int16_t)wl;
+        if (s_df[wl] == -1 && s_key[wl] == q * 64 + (k - g.sp[u])) {
+          s_q[pos++] = (int16_t)wl;
           b.parent[base + wl] = u;
         }
       }
     }
     __syncthreads();
-    for (int i = tid; i < m2; i += kBfsThreads) s_df[s_layer[cur ^ 1][i]] = (int16_t)(d + 1);
-    __syncthreads();
-    cur ^= 1;
-    m = m2;
+    for (int i = tid; i < m2; i += kBfsThreads) {
+      const int wl = s_q[qe + i];
+      s_df[wl] = (int16_t)(d + 1);
+      s_key[wl] = s_q[qb + s_key[wl] / 64];
+    }
+    qb = qe;
+    qe += m2;
     ++d;
+    if (tid == 0) s_lb[d + 1] = (int16_t)qe;
+    __syncthreads();
   }
+  const int nlayers = d;  // layers 0 .. nlayers - 1
+  // subtree sizes, deepest layer first
+  for (int l = nlayers - 1; l >= 1; --l) {
+    for (int i = s_lb[l] + tid; i < s_lb[l + 1]; i += kBfsThreads) {
+      const int v = s_q[i];
+      atomicAdd(&s_sz[s_key[v]], s_sz[v]);
+    }
+    __syncthreads();
+  }
+  // preorder ranks, top layer first: a vertex follows its parent and the
+  // subtrees of its smaller siblings
+  if (tid == 0) s_cnt[el] = 0;
+  __syncthreads();
+  for (int l = 1; l < nlayers; ++l) {
+    const int lo = s_lb[l];
+    for (int i = lo + tid; i < s_lb[l + 1]; i += kBfsThreads) {
+      const int v = s_q[i];
+      const int p = s_key[v];
+      int acc = 0;
+      for (int j = i - 1; j >= lo && s_key[s_q[j]] == p; --j) acc += s_sz[s_q[j]];
+      s_cnt[v] = (int16_t)(s_cnt[p] + 1 + acc);
+    }
+    __syncthreads();
+  }
+  for (int v = tid; v < nc; v += kBfsThreads) {
+    const bool r = s_df[v] >= 0;
+    b.pre[base + v] = r ? base + s_cnt[v] : -1;
+    b.pend[base + v] = r ? base + s_cnt[v] + s_sz[v] : -1;
+  }
+  __syncthreads();
   // distances to the exit (reverse search; order does not matter)
-  for (int v = tid; v < nc; v += kBfsThreads) s_best[v] = 0;
+  for (int v = tid; v < nc; v += kBfsThreads) s_sz[v] = 0;
   __syncthreads();
+  const int xl = g.cexit[c] - base;
   if (tid == 0) {
-    const int xl = g.cexit[c] - base;
     s_db[xl] = 0;
-    s_layer[0][0] = (int16_t)xl;
-    s_best[xl] = 1;
+    s_q[0] = (int16_t)xl;
+    s_sz[xl] = 1;
   }
   __syncthreads();
-  cur = 0;
-  m = 1;
+  qb = 0;
+  qe = 1;
   d = 0;
-  while (m > 0) {
+  while (qe > qb) {
     if (tid == 0) s_m = 0;
     __syncthreads();
-    for (int q = tid; q < m; q += kBfsThreads) {
-      const int u = base + s_layer[cur][q];
+    for (int q = qb + tid; q < qe; q += kBfsThreads) {
+      const int u = base + s_q[q];
       for (int k = g.pp[u]; k < g.pp[u + 1]; ++k) {
         const int wl = g.p[k] - base;
-        if (atomicExch(&s_best[wl], 1) == 0) s_layer[cur ^ 1][atomicAdd(&s_m, 1)] = (int16_t)wl;
+        if (atomicExch(&s_sz[wl], 1) == 0) s_q[qe + atomicAdd(&s_m, 1)] = (int16_t)wl;
       }
     }
     __syncthreads();
     const int m2 = s_m;
-    for (int i = tid; i < m2; i += kBfsThreads) s_db[s_layer[cur ^ 1][i]] = (int16_t)(d + 1);
-    __syncthreads();
-    cur ^= 1;
-    m = m2;
+    for (int i = tid; i < m2; i += kBfsThreads) s_db[s_q[qe + i]] = (int16_t)(d + 1);
+    qb = qe;
+    qe += m2;
     ++d;
+    __syncthreads();
   }
-  const int xl = g.cexit[c] - base;
   for (int v = tid; v < nc; v += kBfsThreads) {
     b.dist_f[base + v] = s_df[v];
     b.dist_b[base + v] = s_db[v];
@@ -220,12 +267,13 @@ hipError_t launch_localize(const int32_t* loc, int32_t* v, int64_t n, hipStream_
 // splice
 // ---------------------------------------------------------------------------
 __global__ void k_tp_len(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp, BfsOut b,
-                         int64_t* tp_len) {
+                         int64_t* tp_len, int32_t* grp) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_pp) return;
   const int64_t o0 = pp_off[i], o1 = pp_off[i + 1];
   const int v1 = pp_vtx[o0], vk = pp_vtx[o1 - 1];
   tp_len[i] = (b.pfx_off[v1 + 1] - b.pfx_off[v1]) + (o1 - o0) + (b.sfx_off[vk + 1] - b.sfx_off[vk]);
+  grp[i] = v1;
 }
 
 // Prime paths are sorted, hence grouped by first vertex: rb[v] = index of the
@@ -243,10 +291,11 @@ __global__ void k_run_bounds(const int64_t* pp_off, const int32_t* pp_vtx, int64
 }
 
 hipError_t launch_tp_len(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp, int n,
-                         const BfsOut& b, int64_t* tp_len, int64_t* rb, hipStream_t st) {
+                         const BfsOut& b, int64_t* tp_len, int32_t* grp, int64_t* rb,
+                         hipStream_t st) {
   if (n_pp == 0) return hipSuccess;
   const unsigned grid = (unsigned)((n_pp + kBlock - 1) / kBlock);
-  k_tp_len<<<grid, kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, b, tp_len);
+  k_tp_len<<<grid, kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, b, tp_len, grp);
   k_run_bounds<<<grid, kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, n, rb);
   return hipGetLastError();
 }
@@ -287,26 +336,42 @@ hipError_t launch_tp_write(const int64_t* pp_off, const int32_t* pp_vtx, int64_t
 // ---------------------------------------------------------------------------
 // sort + dedup
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int tp_cmp(const int64_t* off, const int32_t* vtx, int64_t a,
-                                      int64_t c) {
-  const int32_t* pa = vtx + off[a];
-  const int32_t* pc = vtx + off[c];
-  const int64_t la = off[a + 1] - off[a], lc = off[c + 1] - off[c];
-  const int64_t l = la < lc ? la : lc;
-  for (int64_t k = 0; k < l; ++k) {
-    const int32_t x = pa[k], y = pc[k];
-    if (x != y) return x < y ? -1 : 1;
+// Lexicographic comparison of test paths x and y.  TP(x) starts with the
+// BFS-tree path to its group vertex u (the first vertex of its prime path):
+//  * same group: the order of the prime paths, i.e. of the indices;
+//  * neither group vertex an ancestor of the other: the tree paths differ
+//    first, at the children of their lowest common ancestor, and the
+//    preorder ranks (children ascending) order them;
+//  * u a proper ancestor of v: both start with the tree path to u
+//    (dist(u) + 1 entries), so the entries after it decide.
+__device__ __forceinline__ int tp_cmp(const TpOrder& K, int64_t x, int64_t y) {
+  if (x == y) return 0;
+  const int u = K.grp[x], v = K.grp[y];
+  if (u == v) return x < y ? -1 : 1;
+  const int pu = K.pre[u], pv = K.pre[v];
+  int64_t k0;
+  if (pv > pu && pv < K.pend[u]) k0 = K.dist[u] + 1;
+  else if (pu > pv && pu < K.pend[v]) k0 = K.dist[v] + 1;
+  else return pu < pv ? -1 : 1;
+  const int64_t ox = K.off[x], oy = K.off[y];
+  const int64_t lx = K.off[x + 1] - ox, ly = K.off[y + 1] - oy;
+  const int64_t l = lx < ly ? lx : ly;
+  const int32_t* px = K.vtx + ox;
+  const int32_t* py = K.vtx + oy;
+  for (int64_t k = k0; k < l; ++k) {
+    const int32_t a = px[k], c = py[k];
+    if (a != c) return a < c ? -1 : 1;
   }
-  return la < lc ? -1 : (la > lc ? 1 : 0);
+  return lx < ly ? -1 : (lx > ly ? 1 : 0);
 }
 
-constexpr int kMergeChunk = 8;
+constexpr int kMergeChunk = 16;
+constexpr int kMergeBlock = 64;
 
-__global__ __launch_bounds__(kBlock) void k_merge_round(const int64_t* off, const int32_t* vtx,
-                                                        const int32_t* in, int32_t* out,
-                                                        const int64_t* rb, int64_t n_runs,
-                                                        int64_t n) {
-  const int64_t s = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * kMergeChunk;
+__global__ __launch_bounds__(kMergeBlock) void k_merge_round(TpOrder K, const int32_t* in,
+                                                             int32_t* out, const int64_t* rb,
+                                                             int64_t n_runs, int64_t n) {
+  const int64_t s = ((int64_t)blockIdx.x * kMergeBlock + threadIdx.x) * kMergeChunk;
   if (s >= n) return;
   const int64_t e = s + kMergeChunk < n ? s + kMergeChunk : n;
   int64_t pos = s;
@@ -328,23 +393,22 @@ __global__ __launch_bounds__(kBlock) void k_merge_round(const int64_t* off, cons
     int64_t l2 = d - nb > 0 ? d - nb : 0, h2 = d < na ? d : na;
     while (l2 < h2) {
       const int64_t mid = (l2 + h2) >> 1;
-      if (tp_cmp(off, vtx, B[d - 1 - mid], A[mid]) >= 0) l2 = mid + 1; else h2 = mid;
+      if (tp_cmp(K, B[d - 1 - mid], A[mid]) >= 0) l2 = mid + 1; else h2 = mid;
     }
     int64_t i = l2, j = d - l2;
     while (pos < stop) {
-      const bool take_a = (j >= nb) || (i < na && tp_cmp(off, vtx, B[j], A[i]) >= 0);
+      const bool take_a = (j >= nb) || (i < na && tp_cmp(K, B[j], A[i]) >= 0);
       out[pos++] = take_a ? A[i++] : B[j++];
     }
   }
 }
 
-hipError_t launch_merge_round(const int64_t* tp_off, const int32_t* tp_vtx, const int32_t* idx_in,
-                              int32_t* idx_out, const int64_t* rb, int64_t n_runs, int64_t n,
-                              hipStream_t st) {
+hipError_t launch_merge_round(const TpOrder& K, const int32_t* idx_in, int32_t* idx_out,
+                              const int64_t* rb, int64_t n_runs, int64_t n, hipStream_t st) {
   if (n == 0) return hipSuccess;
   const int64_t threads = (n + kMergeChunk - 1) / kMergeChunk;
-  k_merge_round<<<(unsigned)((threads + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-      tp_off, tp_vtx, idx_in, idx_out, rb, n_runs, n);
+  k_merge_round<<<(unsigned)((threads + kMergeBlock - 1) / kMergeBlock), kMergeBlock, 0, st>>>(
+      K, idx_in, idx_out, rb, n_runs, n);
   return hipGetLastError();
 }
 
@@ -361,21 +425,21 @@ hipError_t launch_next_runs(const int64_t* rb, int64_t n_runs, int64_t* rb_out, 
   return hipGetLastError();
 }
 
-__global__ void k_dedup_flags(const int64_t* off, const int32_t* vtx, const int32_t* idx,
-                              int64_t n, int64_t* keep_cnt, int64_t* keep_len) {
+__global__ void k_dedup_flags(TpOrder K, const int32_t* idx, int64_t n, int64_t* keep_cnt,
+                              int64_t* keep_len) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const int64_t a = idx[k];
-  const bool keep = (k == 0) || tp_cmp(off, vtx, idx[k - 1], a) != 0;
+  const bool keep = (k == 0) || tp_cmp(K, idx[k - 1], a) != 0;
   keep_cnt[k] = keep ? 1 : 0;
-  keep_len[k] = keep ? off[a + 1] - off[a] : 0;
+  keep_len[k] = keep ? K.off[a + 1] - K.off[a] : 0;
 }
 
-hipError_t launch_dedup_flags(const int64_t* tp_off, const int32_t* tp_vtx, const int32_t* idx,
-                              int64_t n, int64_t* keep_cnt, int64_t* keep_len, hipStream_t st) {
+hipError_t launch_dedup_flags(const TpOrder& K, const int32_t* idx, int64_t n, int64_t* keep_cnt,
+                              int64_t* keep_len, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  k_dedup_flags<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(tp_off, tp_vtx, idx, n,
-                                                                          keep_cnt, keep_len);
+  k_dedup_flags<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(K, idx, n, keep_cnt,
+                                                                          keep_len);
   return hipGetLastError();
 }
 
