@@ -33,6 +33,35 @@ def _workload():
     return cfggen.c2_cfg(rec["seed"]), rec
 
 
+def _kernel_name(W: int, tuning) -> str:
+    """Name of the extension-kernel instantiation the library runs for
+    visited sets of W words under this tuning (mirrors the dispatch)."""
+    i = W.bit_length() - 1
+    items, var = tuning["items"][i], tuning["variant"][i]
+    if var != 0:
+        while items > 1 and items * W > 32:
+            items //= 2
+    if var != 0 and items * W <= 32:
+        return f"k_extend_tp<{W}, {items}, {256 if var == 1 else 1024}>"
+    return f"k_extend_lb<{W}, {items}>"
+
+
+def _measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on this same kernel (else None)."""
+    path = os.path.join(ROOT, "profiles", "k_extend_cfg209_hbm_traffic.md")
+    try:
+        for line in open(path):
+            line = line.strip()
+            if line.startswith("traffic kernel="):
+                name = line[len("traffic kernel="):line.index(" bytes_per_launch=")]
+                val = float(line.split("bytes_per_launch=")[1].split()[0])
+                return val if name == kernel else None
+    except OSError:
+        return None
+    return None
+
+
 def _bytes_per_extension(n: int) -> int:
     """Algorithmic HBM bytes per path extension: the child's 8-byte record is
     written once and read once as a parent (16 B), and its visited set of
@@ -64,6 +93,7 @@ def _stress(args):
     per_launch = st["n_extensions"] * bpe / max(1, st["n_extend_launches"])
     ach = per_launch / (avg * 1e-3) / 1e9 if avg > 0 else 0.0
     ms = 1000.0 * statistics.median(times)
+    kname = _kernel_name(8, tpg.get_tuning(ws))
     ws.close()
     return {"workload": f"stress CFG, {g.n} vertices, {g.n_edges} arcs (3 nested whiles, 16-way "
                         f"switch, 60 diamonds), prime paths only",
@@ -72,7 +102,7 @@ def _stress(args):
             "extensions_per_s": st["n_extensions"] / (ms * 1e-3),
             "extend_kernel_ms": k_ms / args.stress_reps,
             "device_bytes": st["device_bytes"], "pool_cap_bytes": cap,
-            "roofline": {"bound": "hbm", "kernel": "k_extend", "achieved": ach,
+            "roofline": {"bound": "hbm", "kernel": kname, "achieved": ach,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                          "bytes_per_extension": bpe, "launches_per_run": st["n_extend_launches"],
                          "avg_launch_ms": avg}}
@@ -173,6 +203,11 @@ def main() -> int:
     def med(key):
         return statistics.median(p[key] for p in phases)
 
+    W = 1
+    while W * 64 < g.n:
+        W *= 2
+    kname = _kernel_name(W, tpg.get_tuning(ws))
+
     out = {
         "metric": METRIC,
         "value": n_pp / (ms * 1e-3),
@@ -199,9 +234,11 @@ def main() -> int:
                             "test_paths": med("ms_tp"), "total_device": med("ms_total"),
                             "extend_kernel": med("ms_extend_kernel")},
         "plain_two_pass_ms_per_step": ms_plain,
-        "roofline": {"bound": "hbm", "kernel": "k_extend", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_extension": bytes_per_ext,
+                     "traffic": _measured_traffic(kname),
+                     "algorithmic_bytes_per_launch": n_ext * bytes_per_ext / max(1, st["n_extend_launches"]),
+                     "bytes_per_extension": bytes_per_ext,
                      "launches_per_step": st["n_extend_launches"],
                      "avg_launch_ms": avg_launch_ms},
     }

@@ -89,15 +89,17 @@ struct tpg_workspace {
   };
   std::vector<LevelGraph> level_graphs;
   ExtArgs graph_args{};
-  int graph_W = 0, graph_grid = 0, graph_items = 0;
+  int graph_W = 0, graph_grid = 0, graph_items = 0, graph_variant = 0;
   hipStream_t graph_stream = nullptr;
 
   // extension-kernel launch shape per visited-set width (index log2 W):
   // parents per thread (tile = 256 * items) and persistent workgroups per CU
   // parents per thread (tile = 256 * items; one output claim per tile) and
   // persistent workgroups per CU, per visited-set width
-  int tune_items[7] = {8, 8, 8, 8, 8, 8, 8};
-  int tune_wgs[7] = {4, 4, 4, 4, 4, 4, 4};
+  // defaults from a sweep on MI355X (index = log2 of the visited-set width)
+  int tune_items[7] = {2, 2, 2, 4, 2, 1, 1};
+  int tune_wgs[7] = {2, 2, 2, 8, 2, 2, 4};
+  int tune_variant[7] = {2, 2, 2, 1, 2, 2, 0};
   double tune_ms[7] = {0, 0, 0, 0, 0, 0, 0};
 };
 
@@ -219,8 +221,9 @@ tpg_status reserve_tree(tpg_workspace* ws, int64_t rec, int64_t msk, int W, hipS
   return TPG_OK;
 }
 
-ExtArgs make_args(tpg_workspace* ws) {
+ExtArgs make_args(tpg_workspace* ws, int grid = 0) {
   ExtArgs a{};
+  a.tiles_target = std::max(64, grid / 2);
   a.g = ws->dg;
   a.t.par = ws->par.as<int32_t>();
   a.t.info = ws->info.as<uint32_t>();
@@ -247,15 +250,19 @@ struct Timer {
   hipStream_t st;
   bool on;
   size_t next = 0;
-  hipEvent_t mark() {
+  // an unrecorded event from the pool (for dispatch-recorded kernel timing)
+  hipEvent_t event() {
     if (!on) return nullptr;
     if (next >= ws->ev_pool.size()) {
       hipEvent_t e;
       if (hipEventCreate(&e) != hipSuccess) return nullptr;
       ws->ev_pool.push_back(e);
     }
-    hipEvent_t e = ws->ev_pool[next++];
-    (void)hipEventRecord(e, st);
+    return ws->ev_pool[next++];
+  }
+  hipEvent_t mark() {
+    hipEvent_t e = event();
+    if (e) (void)hipEventRecord(e, st);
     return e;
   }
   static double ms(hipEvent_t a, hipEvent_t b) {
@@ -282,18 +289,19 @@ void drop_level_graphs(tpg_workspace* ws) {
   ws->level_graphs.clear();
 }
 
-// `len` levels (extension + advance launches), replayed from a captured HIP
-// graph (launch arguments are baked in; a change of buffers or stream drops
-// the graphs).
-tpg_status launch_levels_graph(tpg_workspace* ws, const ExtArgs& a, int W, int items, int grid,
-                               int len, hipStream_t st) {
+// `len` extension launches (launch li extends level batch_start + li),
+// replayed from a captured HIP graph (launch arguments are baked in; a change
+// of buffers or stream drops the graphs).
+tpg_status launch_levels_graph(tpg_workspace* ws, const ExtArgs& a, int W, int items,
+                               int variant, int grid, int len, hipStream_t st) {
   if (memcmp(&ws->graph_args, &a, sizeof a) != 0 || ws->graph_W != W || ws->graph_grid != grid ||
-      ws->graph_items != items || ws->graph_stream != st) {
+      ws->graph_items != items || ws->graph_variant != variant || ws->graph_stream != st) {
     drop_level_graphs(ws);
     ws->graph_args = a;
     ws->graph_W = W;
     ws->graph_grid = grid;
     ws->graph_items = items;
+    ws->graph_variant = variant;
     ws->graph_stream = st;
   }
   for (auto& lg : ws->level_graphs)
@@ -304,8 +312,7 @@ tpg_status launch_levels_graph(tpg_workspace* ws, const ExtArgs& a, int W, int i
   hipGraph_t graph = nullptr;
   TPG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   for (int i = 0; i < len; ++i) {
-    hipError_t e = launch_extend(W, items, a, grid, st);
-    if (e == hipSuccess) e = launch_advance(a, st);
+    hipError_t e = launch_extend(W, items, variant, a, grid, i, st);
     if (e != hipSuccess) {
       hipGraph_t g2 = nullptr;
       (void)hipStreamEndCapture(st, &g2);
@@ -326,6 +333,8 @@ tpg_status launch_levels_graph(tpg_workspace* ws, const ExtArgs& a, int W, int i
 
 // Level loop, one-pass device-sized form.  rec0 / msk0: initial capacities
 // (nodes overall / nodes of one level); 0 = what the workspace already has.
+// Levels run in batches of launches (4, 8, ... 64); the host learns the
+// sizes of a batch's levels after it, and grows and replays on overflow.
 tpg_status build_tree_onepass(tpg_workspace* ws, const HostUnion& U, hipStream_t st, Timer& tm,
                               TreeResult& R, int64_t rec0, int64_t msk0) {
   const int W = U.W;
@@ -334,72 +343,93 @@ tpg_status build_tree_onepass(tpg_workspace* ws, const HostUnion& U, hipStream_t
   if (ws->mask_words && ws->mask_cap)
     msk = std::max<int64_t>(msk, ws->mask_cap * ws->mask_words / W);
   TPG_TRY(reserve_tree(ws, rec, msk, W, st, 0, -1, 0));
-  ExtArgs a = make_args(ws);
-  TPG_HIP(launch_seed(a, st));
   int wi = 0;
   while ((1 << wi) < W) ++wi;
   const int items = ws->tune_items[wi];
+  const int variant = ws->tune_variant[wi];
   const int grid = ws->num_cus * ws->tune_wgs[wi];
+  ExtArgs a = make_args(ws, grid);
+  TPG_HIP(launch_seed(a, st));
+  LevelState* dls = ws->ls.as<LevelState>();
+  std::vector<int64_t> cnt(kMaxLevels + 1, 0);
+  cnt[1] = U.n;
+  int L0 = 1;
   int batch = 4;
-  int level_before = 1;
+  int Lmax = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
   for (;;) {
+    const int len = std::min(batch, kMaxLevels - 2 - L0);
+    if (len <= 0) return fail(TPG_ERR_UNSUPPORTED, "more levels than vertices + 1");
+    ws->h_scalars[8] = L0;
+    TPG_HIP(hipMemcpyAsync(&dls->batch_start, &ws->h_scalars[8], sizeof(int32_t),
+                           hipMemcpyHostToDevice, st));
     // timed calls launch directly with an event pair around each extension
     // launch; untimed calls replay the captured level loop
     evs.clear();
     if (tm.on) {
-      for (int b = 0; b < batch; ++b) {
-        hipEvent_t e0 = tm.mark();
-        TPG_HIP(launch_extend(W, items, a, grid, st));
-        hipEvent_t e1 = tm.mark();
-        TPG_HIP(launch_advance(a, st));
+      for (int b = 0; b < len; ++b) {
+        hipEvent_t e0 = tm.event(), e1 = tm.event();
+        TPG_HIP(launch_extend(W, items, variant, a, grid, b, st, e0, e1));
         evs.emplace_back(e0, e1);
       }
     } else {
-      TPG_TRY(launch_levels_graph(ws, a, W, items, grid, batch, st));
+      TPG_TRY(launch_levels_graph(ws, a, W, items, variant, grid, len, st));
     }
-    TPG_HIP(hipMemcpyAsync(ws->h_ls, ws->ls.p, 32, hipMemcpyDeviceToHost, st));
+    // header + sizes of levels L0 .. L0 + len
+    TPG_HIP(hipMemcpyAsync(ws->h_ls, dls, 32, hipMemcpyDeviceToHost, st));
+    TPG_HIP(hipMemcpyAsync(ws->h_ls->count + L0, dls->count + L0, sizeof(int64_t) * (len + 1),
+                           hipMemcpyDeviceToHost, st));
     TPG_HIP(hipStreamSynchronize(st));
     const LevelState& h = *ws->h_ls;
-    const int productive = h.level - level_before;
-    for (int i = 0; i < productive && i < (int)evs.size(); ++i) {
-      R.ms_kernel += Timer::ms(evs[i].first, evs[i].second);
+    const int Lo = h.overflow ? h.overflow_level : -1;
+    // levels extended for good in this batch: L0 .. last
+    const int last_ok = h.overflow ? Lo - 1 : L0 + len - 1;
+    for (int L = L0; L <= std::min(last_ok + 1, L0 + len); ++L) cnt[L] = h.count[L];
+    if (h.overflow) cnt[Lo + 1] = h.count[Lo + 1];
+    for (int b = 0; b < (int)evs.size() && L0 + b <= last_ok && cnt[L0 + b] > 0; ++b) {
+      R.ms_kernel += Timer::ms(evs[b].first, evs[b].second);
       R.launches += 1;
     }
     tm.next = 0;
-    level_before = h.level;
     if (h.overflow) {
-      // the level's exact child count is known: grow to it and replay
-      const int L = h.level;
-      LevelState* dls = ws->ls.as<LevelState>();
-      int64_t base = 0, cnt[2] = {0, 0};
-      TPG_HIP(hipMemcpy(&base, &dls->off[L], sizeof(int64_t), hipMemcpyDeviceToHost));
-      TPG_HIP(hipMemcpy(cnt, &dls->count[L], 2 * sizeof(int64_t), hipMemcpyDeviceToHost));
-      const int64_t F = cnt[0], nxt = cnt[1];
+      // the exact size of level Lo + 1 is known: grow to it and replay Lo
+      int64_t base = 0;
+      for (int L = 1; L < Lo; ++L) base += cnt[L];
+      const int64_t F = cnt[Lo], nxt = cnt[Lo + 1];
       const int64_t need_rec = base + F + nxt + 1;
       const int64_t new_rec = std::max<int64_t>(ws->rec_cap, need_rec + need_rec / 4);
       const int64_t new_msk = std::max<int64_t>(ws->mask_cap, nxt + nxt / 4 + 1024);
-      TPG_TRY(reserve_tree(ws, new_rec, new_msk, W, st, base + F, L & 1, F));
-      a = make_args(ws);
-      TPG_HIP(launch_resume_fix(a, L, st));
+      TPG_TRY(reserve_tree(ws, new_rec, new_msk, W, st, base + F, Lo & 1, F));
+      a = make_args(ws, grid);
+      TPG_HIP(launch_resume_fix(a, Lo, st));
       R.n_overflows += 1;
+      L0 = Lo;
       continue;
     }
-    if (h.cur_count == 0) break;
+    int empty = -1;
+    for (int L = L0; L <= L0 + len; ++L)
+      if (cnt[L] == 0) {
+        empty = L;
+        break;
+      }
+    if (empty > 0) {
+      Lmax = empty - 1;
+      break;
+    }
+    L0 += len;
     batch = std::min(batch * 2, 64);
   }
   R.count.assign(kMaxLevels, 0);
   R.off.assign(kMaxLevels, 0);
-  LevelState* dls = ws->ls.as<LevelState>();
-  TPG_HIP(hipMemcpy(ws->h_ls, dls, sizeof(LevelState), hipMemcpyDeviceToHost));
-  R.Lmax = ws->h_ls->level - 1;
-  for (int L = 0; L <= R.Lmax + 1; ++L) {
-    R.count[L] = ws->h_ls->count[L];
-    R.off[L] = ws->h_ls->off[L];
+  R.Lmax = Lmax;
+  int64_t off = 0;
+  for (int L = 1; L <= Lmax + 1 && L < kMaxLevels; ++L) {
+    R.count[L] = L <= Lmax ? cnt[L] : 0;
+    R.off[L] = off;
+    off += R.count[L];
     R.peak = std::max(R.peak, R.count[L]);
   }
-  R.off[R.Lmax + 1] = R.off[R.Lmax] + R.count[R.Lmax];
-  R.n_nodes = R.off[R.Lmax + 1];
+  R.n_nodes = off;
   return TPG_OK;
 }
 
@@ -1125,12 +1155,15 @@ tpg_status tpg_workspace_set_tuning(tpg_workspace* ws, const tpg_tuning* t) {
   if (!ws || !t) return fail(TPG_ERR_INVALID_ARG, "NULL argument");
   for (int i = 0; i < 7; ++i) {
     const int it = t->items[i], wg = t->wgs_per_cu[i];
-    if ((it != 2 && it != 4 && it != 8 && it != 16) || wg < 1 || wg > 32)
-      return fail(TPG_ERR_INVALID_ARG, "tuning entry %d: items %d, workgroups per CU %d", i, it, wg);
+    const int va = t->variant[i];
+    if ((it != 1 && it != 2 && it != 4 && it != 8) || wg < 1 || wg > 32 || va < 0 || va > 2)
+      return fail(TPG_ERR_INVALID_ARG, "tuning entry %d: items %d, workgroups per CU %d, variant %d",
+                  i, it, wg, va);
   }
   for (int i = 0; i < 7; ++i) {
     ws->tune_items[i] = t->items[i];
     ws->tune_wgs[i] = t->wgs_per_cu[i];
+    ws->tune_variant[i] = t->variant[i];
     ws->tune_ms[i] = t->best_ms[i];
   }
   return TPG_OK;
@@ -1141,6 +1174,7 @@ tpg_status tpg_workspace_get_tuning(const tpg_workspace* ws, tpg_tuning* t) {
   for (int i = 0; i < 7; ++i) {
     t->items[i] = ws->tune_items[i];
     t->wgs_per_cu[i] = ws->tune_wgs[i];
+    t->variant[i] = ws->tune_variant[i];
     t->best_ms[i] = ws->tune_ms[i];
   }
   return TPG_OK;
@@ -1161,7 +1195,7 @@ tpg_status tpg_autotune(const tpg_graph* const* graphs, int32_t n_graphs, const 
     while ((1 << k) < w) ++k;
     if (unions[k].n + graphs[i]->n <= kMaxUnionVertices) add_component(unions[k], graphs[i]);
   }
-  const int items_c[4] = {2, 4, 8, 16};
+  const int items_c[4] = {1, 2, 4, 8};
   const int wgs_c[4] = {1, 2, 4, 8};
   Timer tm{ws, c.st, true};
   for (int k = 0; k < 7; ++k) {
@@ -1171,11 +1205,15 @@ tpg_status tpg_autotune(const tpg_graph* const* graphs, int32_t n_graphs, const 
     TreeResult warm;
     TPG_TRY(build_tree_onepass(ws, U, c.st, tm, warm, 0, 0));
     double best = 1e30;
-    int bi = ws->tune_items[k], bw = ws->tune_wgs[k];
+    int bi = ws->tune_items[k], bw = ws->tune_wgs[k], bv = ws->tune_variant[k];
+    for (int va = 0; va < 3; ++va)
     for (int it : items_c)
       for (int wg : wgs_c) {
+        if (va == 2 && wg > 2) continue;  // 1024-thread workgroups: at most 2 per CU
+        if (va != 0 && it * (1 << k) > 32) continue;  // register-resident visited sets
         ws->tune_items[k] = it;
         ws->tune_wgs[k] = wg;
+        ws->tune_variant[k] = va;
         double t_min = 1e30;
         for (int rep = 0; rep < 2; ++rep) {
           TreeResult R;
@@ -1186,10 +1224,12 @@ tpg_status tpg_autotune(const tpg_graph* const* graphs, int32_t n_graphs, const 
           best = t_min;
           bi = it;
           bw = wg;
+          bv = va;
         }
       }
     ws->tune_items[k] = bi;
     ws->tune_wgs[k] = bw;
+    ws->tune_variant[k] = bv;
     ws->tune_ms[k] = best;
   }
   return tpg_workspace_get_tuning(ws, out);

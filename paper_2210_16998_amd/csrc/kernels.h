@@ -15,12 +15,11 @@ constexpr int kMaxLevels = 4096 + 4;  // path entries <= n + 1
 // other without the host learning their sizes.  The 32-byte header is what
 // the host polls.
 struct LevelState {
-  int32_t level;     // level currently to be extended (paths of `level` entries)
-  int32_t overflow;  // non-zero: the last level did not fit the buffers
-  uint32_t done;     // unused, kept zero
+  int32_t batch_start;     // level extended by launch 0 of the running batch
+  int32_t overflow;        // non-zero: the children of overflow_level did not fit
+  int32_t overflow_level;
   int32_t pad;
-  int64_t cur_count; // count[level]
-  int64_t pad2;
+  int64_t pad2[2];
   // nodes (paths) per level, cycle closures included; while level L is
   // extended, count[L + 1] is the running claim counter of its tiles
   int64_t count[kMaxLevels];
@@ -44,15 +43,19 @@ struct ExtArgs {
   DGraph g;
   TreeBufs t;
   LevelState* ls;
+  int64_t tiles_target;  // one-pass tiles per level aimed at (tile size grows above it)
 };
 
 // --- path tree -------------------------------------------------------------
 hipError_t launch_seed(const ExtArgs& a, hipStream_t st);
-// items: parents per thread and tile (tile = 256 * items); grid: persistent workgroups
-hipError_t launch_extend(int W, int items, const ExtArgs& a, int grid, hipStream_t st);
+// items: most parents per thread (tile <= threads * items); variant: 0
+// load-balanced tiles of 256 threads, 1 / 2 thread-per-parent with 256 /
+// 1024 threads; grid: persistent workgroups; li: index of the launch in its
+// batch (it extends level batch_start + li)
+// e0 / e1 (optional): events recorded at the kernel's own start and end
+hipError_t launch_extend(int W, int items, int variant, const ExtArgs& a, int grid, int li,
+                         hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_resume_fix(const ExtArgs& a, int level, hipStream_t st);
-// one thread: next level's offset and size from the claims, or the overflow flag
-hipError_t launch_advance(const ExtArgs& a, hipStream_t st);
 // two-pass (plain) form
 hipError_t launch_count(int W, const ExtArgs& a, int L, int64_t base, int64_t F, hipStream_t st);
 hipError_t launch_fill(int W, const ExtArgs& a, int L, int64_t base, int64_t F, hipStream_t st);

@@ -27,12 +27,15 @@
 //    children, so record and mask stores are coalesced.  No workgroup ever
 //    waits for another one; the order of tile slices inside a level is the
 //    order in which the claims landed, which ranking does not depend on.
-//  * Levels follow each other on the device: the level index, per-level
-//    counts and offsets live in device memory and a one-thread kernel after
-//    each extension advances them, or raises the overflow flag when the
-//    level did not fit; the host then grows the buffers and replays it.
+//  * Levels follow each other on the device: per-level counts and offsets
+//    live in device memory; launch li of a batch extends level
+//    batch_start + li and derives its offset from the level before, or
+//    raises the overflow flag when that level's children did not fit; the
+//    host then grows the buffers to the exact size and replays the level.
 //  * The plain two-pass form (count, scan, host-visible size, fill) keeps
 //    children in parent order and serves as the exact reference form.
+
+#include <hip/hip_ext.h>
 
 #include "kernels.h"
 
@@ -51,10 +54,9 @@ __global__ void k_seed(ExtArgs a) {
     ls->off[k] = 0;
   }
   if (i == 0) {
-    ls->level = 1;
+    ls->batch_start = 1;
     ls->overflow = 0;
-    ls->done = 0;
-    ls->cur_count = n;
+    ls->overflow_level = 0;
   }
   if (i < n) {
     const int v = (int)i;
@@ -82,7 +84,7 @@ __global__ void k_resume_fix(ExtArgs a, int level) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.ls->count[level + 1] = 0;
     a.ls->overflow = 0;
-    a.ls->done = 0;
+    a.ls->overflow_level = 0;
   }
 }
 
@@ -92,49 +94,19 @@ hipError_t launch_resume_fix(const ExtArgs& a, int level, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Level advance after an extension launch: the claimed total is the next
-// level's size; a level that does not fit raises the overflow flag instead
-// (the extension kernel stored nothing beyond the capacities).
-__global__ void k_advance(ExtArgs a) {
-  if (threadIdx.x != 0) return;
-  LevelState* ls = a.ls;
-  if (ls->overflow) return;
-  const int L = ls->level;
-  const int64_t F = ls->count[L];
-  if (F == 0 || L + 2 >= kMaxLevels) return;
-  const int64_t total = ls->count[L + 1];
-  const int64_t nbase = ls->off[L] + F;
-  if (nbase + total + 1 > a.t.rec_cap || total > a.t.mask_cap ||
-      nbase + total >= (int64_t)INT32_MAX) {
-    ls->overflow = 1;
-    return;
-  }
-  ls->off[L + 1] = nbase;
-  ls->cur_count = total;
-  ls->level = L + 1;
-}
-
-hipError_t launch_advance(const ExtArgs& a, hipStream_t st) {
-  k_advance<<<1, 64, 0, st>>>(a);
-  return hipGetLastError();
-}
-
 // ---------------------------------------------------------------------------
 // shared per-parent step: choice mask over successor slots + terminal filter
 // ---------------------------------------------------------------------------
-// Choice mask over the successor slots of the path's last vertex v: slot k
-// is set when successor w is not on the path, or is its first vertex (closes
-// a cycle).  base = graph-wide id of local id 0 of v's component.
+// Choice mask over the successor slots [k0, k1) of the path's last vertex:
+// slot k is set when successor w is not on the path, or is its first vertex
+// (closes a cycle).  cb = graph-wide id of local id 0 of the component.
 template <int W>
 __device__ __forceinline__ uint64_t choices(const DGraph& g, uint32_t inf, const uint64_t (&m)[W],
-                                            int& k0, int& base) {
-  const int v = node_v(inf), v1l = node_v1l(inf);
-  base = v - g.loc[v];
-  k0 = g.sp[v];
-  const int k1 = g.sp[v + 1];
+                                            int k0, int k1, int cb) {
+  const int v1l = node_v1l(inf);
   uint64_t vm = 0;
   for (int k = k0; k < k1; ++k) {
-    const int wl = g.s[k] - base;
+    const int wl = g.s[k] - cb;
     const bool ok = (wl == v1l) || !mask_has<W>(m, wl);
     vm |= ok ? (1ull << (k - k0)) : 0ull;
   }
@@ -188,97 +160,265 @@ __device__ __forceinline__ void store_child_mask(uint64_t* dst, const uint64_t (
 // ---------------------------------------------------------------------------
 // one-pass extension of level L -> L+1 (device-sized, claim per tile)
 // ---------------------------------------------------------------------------
-// A tile is ITEMS * 256 consecutive parents; tile t goes to workgroup
-// t mod grid.  Loads are strided by the workgroup size (coalesced); the scan
-// gives each thread ITEMS consecutive parents; the expansion gives each
-// thread every 256th child of the tile.
+// Launch `li` of a batch extends level L = batch_start + li.  Its offset is
+// derived from the previous level's final offset and size, so no kernel has
+// to advance a level counter; a level whose nodes did not fit (claimed
+// beyond the capacities by the launch before) raises the overflow flag and
+// ends the batch.
+//
+// A tile is 256 * ir consecutive parents (ir <= ITEMS, chosen per level so
+// that large levels need few claims and small ones still spread over the
+// grid); tile t goes to workgroup t mod grid.  Thread tid owns parents
+// i * 256 + tid (i < ir): their records and visited sets are loaded together
+// (coalesced), the visited sets stay in registers, and the thread writes its
+// own parents' children.  Children are laid out item-major and, inside an
+// item, in thread order, so a wave's stores land on neighbouring slots.  A
+// level that fits one tile stores its size instead of claiming.
+template <int W, int ITEMS, int NT>
+__global__ __launch_bounds__(NT) void k_extend_tp(ExtArgs a, int li) {
+  constexpr int NW = NT / 64;
+  __shared__ int32_t s_tot[ITEMS][NW];
+  __shared__ int64_t s_prefix;
+
+  LevelState* ls = a.ls;
+  if (ls->overflow) return;
+  const int L = ls->batch_start + li;
+  if (L < 1 || L + 2 >= kMaxLevels) return;
+  const int64_t F = ls->count[L];
+  if (F == 0) return;
+  const int64_t base = ls->off[L - 1] + ls->count[L - 1];
+  const int tid = (int)threadIdx.x;
+  const int lane = lane_id(), wave = tid >> 6;
+  if (base + F + 1 > a.t.rec_cap || F > a.t.mask_cap || base + F >= (int64_t)INT32_MAX) {
+    // the previous launch's children did not fit: replay that level
+    if (blockIdx.x == 0 && tid == 0) {
+      ls->overflow_level = L - 1;
+      ls->overflow = 1;
+    }
+    return;
+  }
+  if (blockIdx.x == 0 && tid == 0) ls->off[L] = base;
+  const int64_t nbase = base + F;
+  const int par = L & 1;
+  const uint64_t* mcur = a.t.mask[par];
+  uint64_t* mnxt = a.t.mask[par ^ 1];
+  unsigned long long* claim = reinterpret_cast<unsigned long long*>(&ls->count[L + 1]);
+
+  int ir = 1;
+  while (ir < ITEMS && (F + (int64_t)NT * ir - 1) / ((int64_t)NT * ir) > a.tiles_target) ir <<= 1;
+  const int64_t TR = (int64_t)NT * ir;
+  const int64_t ntiles = (F + TR - 1) / TR;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t tb = t * TR;
+    // records and visited sets of the thread's parents (independent loads;
+    // rows outside the level read parent 0's set and are ignored)
+    uint32_t inf[ITEMS];
+    uint64_t m[ITEMS][W];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const int64_t j = tb + i * NT + tid;
+      const bool ok = i < ir && j < F;
+      inf[i] = ok ? a.t.info[base + j] : F_CYC;
+      load_mask<W>(mcur + (ok ? j : 0) * W, m[i]);
+    }
+    // choice masks and the terminal filter
+    uint64_t vm[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      vm[i] = 0;
+      if (!(inf[i] & F_CYC)) {
+        const int v = node_v(inf[i]);
+        const int cb = v - a.g.loc[v];
+        vm[i] = choices<W>(a.g, inf[i], m[i], a.g.sp[v], a.g.sp[v + 1], cb);
+        if (vm[i] == 0) {
+          const bool pp = all_preds_on<W>(a.g, cb, node_v1l(inf[i]), m[i]);
+          inf[i] |= F_TERM | (pp ? F_PP : 0u);
+          a.t.info[base + tb + i * NT + tid] = inf[i];
+        }
+      }
+    }
+    // child offsets: item-major, thread order inside an item
+    int excl[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const int c = __builtin_popcountll(vm[i]);
+      const int inc = wave_incl_scan(c);
+      excl[i] = inc - c;
+      if (lane == 63) s_tot[i][wave] = inc;
+    }
+    __syncthreads();
+    int total = 0;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      int before = 0, all = 0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const int x = i < ir ? s_tot[i][w] : 0;
+        before += w < wave ? x : 0;
+        all += x;
+      }
+      excl[i] += total + before;
+      total += all;
+    }
+    if (tid == 0) {
+      int64_t pre = 0;
+      if (ntiles == 1) {
+        *claim = (unsigned long long)total;  // the only tile of the level
+      } else if (total) {
+        pre = (int64_t)atomicAdd(claim, (unsigned long long)total);
+      }
+      s_prefix = pre;
+    }
+    __syncthreads();
+    const int64_t prefix = s_prefix;
+    // expansion: each thread writes its parents' children in slot order
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const int64_t j = tb + i * NT + tid;
+      if (i < ir && j < F) {
+        int64_t cl = prefix + excl[i];
+        a.t.cstart[base + j] = (int32_t)(nbase + cl);
+        a.t.nch[base + j] = (uint8_t)__builtin_popcountll(vm[i]);
+        const int v1l = node_v1l(inf[i]);
+        uint64_t rest = vm[i];
+        const int pv = node_v(inf[i]);
+        const int k0 = rest ? a.g.sp[pv] : 0;
+        const int cb = rest ? pv - a.g.loc[pv] : 0;
+        while (rest) {
+          const int slot = __builtin_ctzll(rest);
+          rest &= rest - 1;
+          const int w = a.g.s[k0 + slot];
+          const int wl = w - cb;
+          const int64_t cg = nbase + cl;
+          if (cg < a.t.rec_cap) {
+            a.t.par[cg] = (int32_t)(base + j);
+            a.t.info[cg] = make_info(w, v1l, wl == v1l ? F_CYC : 0u);
+          }
+          if (wl != v1l && cl < a.t.mask_cap) store_child_mask<W>(mnxt + cl * W, m[i], wl);
+          ++cl;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Load-balanced form of the same step: the tile's parents are staged in LDS
+// (choice masks, records, successor-row starts, visited sets when they fit)
+// and thread k writes the k-th child of the tile, found by binary search
+// over the parents' child offsets.
 template <int W, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_extend(ExtArgs a) {
+__global__ __launch_bounds__(kBlock) void k_extend_lb(ExtArgs a, int li) {
   constexpr int TILE = kBlock * ITEMS;
   constexpr bool kLdsMask = W * ITEMS <= 16;  // visited sets of the tile in LDS (<= 32 KiB)
   __shared__ int64_t s_prefix;
   __shared__ int32_t s_off[TILE];
   __shared__ uint64_t s_vm[TILE];
   __shared__ uint32_t s_inf[TILE];
+  __shared__ int32_t s_kk[TILE];
   __shared__ uint64_t s_mask[kLdsMask ? TILE * W : 1];
   __shared__ int32_t s_w[kBlock / 64];
 
   LevelState* ls = a.ls;
   if (ls->overflow) return;
-  const int L = ls->level;
+  const int L = ls->batch_start + li;
+  if (L < 1 || L + 2 >= kMaxLevels) return;
   const int64_t F = ls->count[L];
-  if (F == 0 || L + 2 >= kMaxLevels) return;
-  const int64_t base = ls->off[L];
+  if (F == 0) return;
+  const int64_t base = ls->off[L - 1] + ls->count[L - 1];
+  const int tid = (int)threadIdx.x;
+  if (base + F + 1 > a.t.rec_cap || F > a.t.mask_cap || base + F >= (int64_t)INT32_MAX) {
+    if (blockIdx.x == 0 && tid == 0) {
+      ls->overflow_level = L - 1;
+      ls->overflow = 1;
+    }
+    return;
+  }
+  if (blockIdx.x == 0 && tid == 0) ls->off[L] = base;
   const int64_t nbase = base + F;
   const int par = L & 1;
   const uint64_t* mcur = a.t.mask[par];
   uint64_t* mnxt = a.t.mask[par ^ 1];
   unsigned long long* claim = reinterpret_cast<unsigned long long*>(&ls->count[L + 1]);
-  const int tid = (int)threadIdx.x;
 
-  const int64_t ntiles = (F + TILE - 1) / TILE;
+  int ir = 1;
+  while (ir < ITEMS && (F + (int64_t)kBlock * ir - 1) / ((int64_t)kBlock * ir) > a.tiles_target) ir <<= 1;
+  const int TR = kBlock * ir;
+  const int64_t ntiles = (F + TR - 1) / TR;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int64_t tb = t * TILE;
-    // load + choices + filter, parent p = i * 256 + tid
+    const int64_t tb = t * TR;
+    uint32_t inf[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-      const int p = i * kBlock + tid;
-      const int64_t j = tb + p;
-      uint32_t inf = j < F ? a.t.info[base + j] : F_CYC;
-      uint64_t m[W];
+      const int64_t j = tb + i * kBlock + tid;
+      inf[i] = (i < ir && j < F) ? a.t.info[base + j] : F_CYC;
+    }
 #pragma unroll
-      for (int q = 0; q < W; ++q) m[q] = 0;
-      uint64_t vm = 0;
-      int k0 = 0, cb = 0;
-      if (!(inf & F_CYC)) {
-        load_mask<W>(mcur + j * W, m);
-        vm = choices<W>(a.g, inf, m, k0, cb);
-        if (vm == 0) {
-          const bool pp = all_preds_on<W>(a.g, cb, node_v1l(inf), m);
-          inf |= F_TERM | (pp ? F_PP : 0u);
-          a.t.info[base + j] = inf;
+    for (int i = 0; i < ITEMS; ++i) {
+      if (i < ir) {
+        const int p = i * kBlock + tid;
+        const int64_t j = tb + p;
+        uint32_t in = inf[i];
+        uint64_t m[W];
+#pragma unroll
+        for (int q = 0; q < W; ++q) m[q] = 0;
+        uint64_t vm = 0;
+        int k0 = 0;
+        if (!(in & F_CYC)) {
+          const int v = node_v(in);
+          const int cb = v - a.g.loc[v];
+          k0 = a.g.sp[v];
+          load_mask<W>(mcur + j * W, m);
+          vm = choices<W>(a.g, in, m, k0, a.g.sp[v + 1], cb);
+          if (vm == 0) {
+            const bool pp = all_preds_on<W>(a.g, cb, node_v1l(in), m);
+            in |= F_TERM | (pp ? F_PP : 0u);
+            a.t.info[base + j] = in;
+          }
         }
-      }
-      s_off[p] = __builtin_popcountll(vm);
-      s_vm[p] = vm;
-      s_inf[p] = inf;
-      if constexpr (kLdsMask) {
+        s_off[p] = __builtin_popcountll(vm);
+        s_vm[p] = vm;
+        s_inf[p] = in;
+        s_kk[p] = k0;
+        if constexpr (kLdsMask) {
 #pragma unroll
-        for (int q = 0; q < W; ++q) s_mask[p * W + q] = m[q];
+          for (int q = 0; q < W; ++q) s_mask[p * W + q] = m[q];
+        }
       }
     }
     __syncthreads();
-    // exclusive scan of the child counts in parent order
     int c[ITEMS];
     int sum = 0;
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-      c[i] = s_off[tid * ITEMS + i];
+      c[i] = i < ir ? s_off[tid * ir + i] : 0;
       sum += c[i];
     }
     int32_t total32;
     int32_t run = block_excl_scan<kBlock, int32_t>(sum, total32, s_w);
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-      s_off[tid * ITEMS + i] = run;
+      if (i < ir) s_off[tid * ir + i] = run;
       run += c[i];
     }
-    // one claim per tile (tiles without children claim nothing)
-    if (tid == 0)
-      s_prefix = total32 ? (int64_t)atomicAdd(claim, (unsigned long long)total32) : 0;
+    if (tid == 0) {
+      int64_t pre = 0;
+      if (ntiles == 1) *claim = (unsigned long long)total32;
+      else if (total32) pre = (int64_t)atomicAdd(claim, (unsigned long long)total32);
+      s_prefix = pre;
+    }
     __syncthreads();
     const int64_t prefix = s_prefix;
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       const int p = i * kBlock + tid;
-      if (tb + p < F) {
+      if (i < ir && tb + p < F) {
         a.t.cstart[base + tb + p] = (int32_t)(nbase + prefix + s_off[p]);
         a.t.nch[base + tb + p] = (uint8_t)__builtin_popcountll(s_vm[p]);
       }
     }
-    // load-balanced expansion: thread k writes the k-th child of the tile
     for (int k = tid; k < total32; k += kBlock) {
-      int lo = 0, hi = TILE - 1;
+      int lo = 0, hi = TR - 1;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (s_off[mid] <= k) lo = mid; else hi = mid - 1;
@@ -288,7 +428,7 @@ __global__ __launch_bounds__(kBlock) void k_extend(ExtArgs a) {
       const uint32_t pinf = s_inf[o];
       const int v1l = node_v1l(pinf);
       const int pv = node_v(pinf);
-      const int w = a.g.s[a.g.sp[pv] + slot];
+      const int w = a.g.s[s_kk[o] + slot];
       const int wl = w - (pv - a.g.loc[pv]);
       const int64_t cl = prefix + k;
       const int64_t cg = nbase + cl;
@@ -311,27 +451,57 @@ __global__ __launch_bounds__(kBlock) void k_extend(ExtArgs a) {
   }
 }
 
-template <int ITEMS>
-static hipError_t launch_extend_items(int W, const ExtArgs& a, int grid, hipStream_t st) {
-  switch (W) {
-    case 1: k_extend<1, ITEMS><<<grid, kBlock, 0, st>>>(a); break;
-    case 2: k_extend<2, ITEMS><<<grid, kBlock, 0, st>>>(a); break;
-    case 4: k_extend<4, ITEMS><<<grid, kBlock, 0, st>>>(a); break;
-    case 8: k_extend<8, ITEMS><<<grid, kBlock, 0, st>>>(a); break;
-    case 16: k_extend<16, ITEMS><<<grid, kBlock, 0, st>>>(a); break;
-    case 32: k_extend<32, ITEMS><<<grid, kBlock, 0, st>>>(a); break;
-    case 64: k_extend<64, ITEMS><<<grid, kBlock, 0, st>>>(a); break;
-    default: return hipErrorInvalidValue;
-  }
+// Launch with optional start / stop events recorded by the dispatch itself
+// (the kernel's own execution interval, without queueing around it).
+template <class K>
+static hipError_t launch_timed(K kernel, int grid, int threads, hipEvent_t e0, hipEvent_t e1,
+                               const ExtArgs& a, int li, hipStream_t st) {
+  if (e0 && e1)
+    hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(threads), 0, st, e0, e1, 0, a, li);
+  else
+    kernel<<<grid, threads, 0, st>>>(a, li);
   return hipGetLastError();
 }
 
-hipError_t launch_extend(int W, int items, const ExtArgs& a, int grid, hipStream_t st) {
-  switch (items) {
-    case 2: return launch_extend_items<2>(W, a, grid, st);
-    case 4: return launch_extend_items<4>(W, a, grid, st);
-    case 8: return launch_extend_items<8>(W, a, grid, st);
-    case 16: return launch_extend_items<16>(W, a, grid, st);
+// variant 0: load-balanced (256 threads); 1: thread-per-parent, 256
+// threads; 2: thread-per-parent, 1024 threads.  Register-resident visited
+// sets are capped at 32 words per thread; wider sets always take variant 0.
+template <int W, int ITEMS>
+static hipError_t launch_extend_wi(int variant, const ExtArgs& a, int grid, int li, hipStream_t st,
+                                   hipEvent_t e0, hipEvent_t e1) {
+  if constexpr (ITEMS * W <= 32) {
+    if (variant == 1) return launch_timed(k_extend_tp<W, ITEMS, 256>, grid, 256, e0, e1, a, li, st);
+    if (variant == 2) return launch_timed(k_extend_tp<W, ITEMS, 1024>, grid, 1024, e0, e1, a, li, st);
+  }
+  return launch_timed(k_extend_lb<W, ITEMS>, grid, kBlock, e0, e1, a, li, st);
+}
+
+template <int W>
+static hipError_t launch_extend_w(int items, int variant, const ExtArgs& a, int grid, int li,
+                                  hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  int it = items;
+  if (variant != 0)
+    while (it > 1 && it * W > 32) it >>= 1;
+  switch (it) {
+    case 1: return launch_extend_wi<W, 1>(variant, a, grid, li, st, e0, e1);
+    case 2: return launch_extend_wi<W, 2>(variant, a, grid, li, st, e0, e1);
+    case 4: return launch_extend_wi<W, 4>(variant, a, grid, li, st, e0, e1);
+    case 8: return launch_extend_wi<W, 8>(variant, a, grid, li, st, e0, e1);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_extend(int W, int items, int variant, const ExtArgs& a, int grid, int li,
+                         hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  if (variant < 0 || variant > 2) return hipErrorInvalidValue;
+  switch (W) {
+    case 1: return launch_extend_w<1>(items, variant, a, grid, li, st, e0, e1);
+    case 2: return launch_extend_w<2>(items, variant, a, grid, li, st, e0, e1);
+    case 4: return launch_extend_w<4>(items, variant, a, grid, li, st, e0, e1);
+    case 8: return launch_extend_w<8>(items, variant, a, grid, li, st, e0, e1);
+    case 16: return launch_extend_w<16>(items, variant, a, grid, li, st, e0, e1);
+    case 32: return launch_extend_w<32>(items, variant, a, grid, li, st, e0, e1);
+    case 64: return launch_extend_w<64>(items, variant, a, grid, li, st, e0, e1);
     default: return hipErrorInvalidValue;
   }
 }
@@ -348,8 +518,9 @@ __global__ __launch_bounds__(kBlock) void k_count(ExtArgs a, int L, int64_t base
   if (!(inf & F_CYC)) {
     uint64_t m[W];
     load_mask<W>(a.t.mask[L & 1] + j * W, m);
-    int k0, cb;
-    const uint64_t vm = choices<W>(a.g, inf, m, k0, cb);
+    const int v = node_v(inf);
+    const int cb = v - a.g.loc[v];
+    const uint64_t vm = choices<W>(a.g, inf, m, a.g.sp[v], a.g.sp[v + 1], cb);
     cnt = __builtin_popcountll(vm);
     if (cnt == 0) {
       const bool pp = all_preds_on<W>(a.g, cb, node_v1l(inf), m);
@@ -368,8 +539,10 @@ __global__ __launch_bounds__(kBlock) void k_fill(ExtArgs a, int L, int64_t base,
   if (inf & F_CYC) return;
   uint64_t m[W];
   load_mask<W>(a.t.mask[L & 1] + j * W, m);
-  int k0, cb;
-  uint64_t vm = choices<W>(a.g, inf, m, k0, cb);
+  const int v = node_v(inf);
+  const int k0 = a.g.sp[v];
+  const int cb = v - a.g.loc[v];
+  uint64_t vm = choices<W>(a.g, inf, m, k0, a.g.sp[v + 1], cb);
   const int v1l = node_v1l(inf);
   const int64_t nbase = base + F;
   int64_t c = a.t.cstart[base + j];

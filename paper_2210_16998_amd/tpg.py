@@ -71,6 +71,7 @@ class _BatchResult(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("items", ctypes.c_int32 * 7), ("wgs_per_cu", ctypes.c_int32 * 7),
+                ("variant", ctypes.c_int32 * 7),
                 ("best_ms", ctypes.c_double * 7)]
 
 
@@ -497,7 +498,7 @@ class MLP:
 
 def _tuning_dict(tu: _Tuning) -> Dict[str, list]:
     return {"items": list(tu.items), "wgs_per_cu": list(tu.wgs_per_cu),
-            "best_ms": list(tu.best_ms)}
+            "variant": list(tu.variant), "best_ms": list(tu.best_ms)}
 
 
 def autotune(graphs, ws: Workspace, stream=None) -> Dict[str, list]:
@@ -522,5 +523,6 @@ def set_tuning(ws: Workspace, t: Dict[str, list]) -> None:
     for i in range(7):
         tu.items[i] = int(t["items"][i])
         tu.wgs_per_cu[i] = int(t["wgs_per_cu"][i])
+        tu.variant[i] = int(t.get("variant", [0] * 7)[i])
         tu.best_ms[i] = float(t.get("best_ms", [0.0] * 7)[i])
     _check(lib().tpg_workspace_set_tuning(ws.handle, ctypes.byref(tu)))

@@ -112,12 +112,14 @@ def test_tile_shapes_do_not_change_a_byte():
     h = tpg.load_cfg(g)
     w = tpg.Workspace()
     outs = []
-    for items in (2, 4, 8, 16):
-        for wgs in (1, 8):
-            tpg.set_tuning(w, {"items": [items] * 7, "wgs_per_cu": [wgs] * 7})
-            say("case tile shape", items, wgs)
-            pp, tp, _ = tpg.test_paths(h, ws=w)
-            outs.append((pp.offsets.tobytes(), pp.vertices.tobytes(), tp.vertices.tobytes()))
+    for variant in (0, 1, 2):
+        for items in (1, 2, 4, 8):
+            for wgs in (1, 2):
+                tpg.set_tuning(w, {"items": [items] * 7, "wgs_per_cu": [wgs] * 7,
+                                   "variant": [variant] * 7})
+                say("case tile shape", variant, items, wgs)
+                pp, tp, _ = tpg.test_paths(h, ws=w)
+                outs.append((pp.offsets.tobytes(), pp.vertices.tobytes(), tp.vertices.tobytes()))
     assert all(o == outs[0] for o in outs)
     rp = ref_pp(g, local=True)[0]
     assert np.array_equal(np.frombuffer(outs[0][1], np.int32), rp.vertices)
@@ -130,7 +132,7 @@ def test_autotune_then_batch_is_exact():
     w = tpg.Workspace()
     say("case autotune")
     t = tpg.autotune(hs, w)
-    assert t["best_ms"][0] > 0 and t["items"][0] in (2, 4, 8, 16)
+    assert t["best_ms"][0] > 0 and t["items"][0] in (1, 2, 4, 8) and t["variant"][0] in (0, 1, 2)
     res, _ = tpg.batch_test_paths(hs, ws=w)
     _check_batch(cfgs, res)
     w.close()
