@@ -61,13 +61,13 @@ struct tpg_workspace {
   int64_t rec_cap = 0, mask_cap = 0;
   int mask_words = 0;
   // ranking
-  DevBuf sub_cnt, sub_len, leaf_by_rank, totals, cycles;
+  DevBuf sub_cnt, pp_len, leaf_by_rank, totals, cycles;
   // scans
   DevBuf scan_status, scan_ctr, scalars;
   DevBuf scan2_status, scalars2;  // the side stream's own scan scratch
   // test paths
   DevBuf bfs_i32, pfx_off, sfx_off, pfx, sfx;
-  DevBuf tp_len, tp_off, tp_vtx, tp_grp, idx0, idx1, grp_cnt, rb0, rb1;
+  DevBuf tp_len, tp_off, tp_vtx, tp_key, idx0, idx1, grp_cnt, rb0, rb1;
   DevBuf keep_cnt, keep_len, keep_pos, keep_voff, comp_cnt;
   // per-level, per-component counts (batched labels)
   DevBuf lvl_comp;
@@ -501,37 +501,40 @@ tpg_status rank_and_materialize(tpg_workspace* ws, const HostUnion& U, hipStream
   ExtArgs a = make_args(ws);
   const int64_t N = R.n_nodes;
   TPG_TRY(ws_reserve(ws, ws->sub_cnt, sizeof(uint32_t) * N));
-  TPG_TRY(ws_reserve(ws, ws->sub_len, sizeof(int64_t) * N));
   TPG_TRY(ws_reserve(ws, ws->totals, sizeof(int64_t) * 4));
   TPG_TRY(ws_reserve(ws, ws->cycles, sizeof(uint64_t) * 2));
+  uint32_t* sc = ws->sub_cnt.as<uint32_t>();
   TPG_HIP(launch_zero_u64(ws->cycles.as<uint64_t>(), 1, st));
   for (int L = R.Lmax; L >= 1; --L)
-    TPG_HIP(launch_up(a, L, R.off[L], R.count[L], ws->sub_cnt.as<uint32_t>(),
-                      ws->sub_len.as<int64_t>(), ws->cycles.as<unsigned long long>(), st));
-  TPG_HIP(launch_roots(a, U.n, ws->sub_cnt.as<uint32_t>(), ws->sub_len.as<int64_t>(), nullptr,
-                       ws->totals.as<int64_t>(), 0, st));
-  TPG_HIP(hipMemcpyAsync(ws->h_scalars, ws->totals.p, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    TPG_HIP(launch_up(a, L, R.off[L], R.count[L], sc, ws->cycles.as<unsigned long long>(), st));
+  TPG_HIP(launch_roots(a, U.n, sc, nullptr, nullptr, ws->totals.as<int64_t>(), 0, st));
+  TPG_HIP(hipMemcpyAsync(ws->h_scalars, ws->totals.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TPG_HIP(hipMemcpyAsync(ws->h_scalars + 2, ws->cycles.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TPG_HIP(hipStreamSynchronize(st));
   P.n_pp = ws->h_scalars[0];
-  P.n_vtx = ws->h_scalars[1];
   P.n_cycles = ws->h_scalars[2];
   TPG_TRY(ws_reserve(ws, ws->leaf_by_rank, sizeof(int64_t) * (P.n_pp + 1)));
+  TPG_TRY(ws_reserve(ws, ws->pp_len, sizeof(int32_t) * (P.n_pp + 1)));
   TPG_TRY(ws_reserve(ws, o.pp_off, sizeof(int64_t) * (P.n_pp + 1)));
-  TPG_TRY(ws_reserve(ws, o.pp_vtx, sizeof(int32_t) * (P.n_vtx + 1)));
   TPG_TRY(ws_reserve(ws, o.comp_starts, sizeof(int64_t) * 4 * (U.n_comp + 1)));
-  TPG_HIP(launch_roots(a, U.n, ws->sub_cnt.as<uint32_t>(), ws->sub_len.as<int64_t>(),
-                       ws->leaf_by_rank.as<int64_t>(), ws->totals.as<int64_t>(), 1, st));
-  int64_t* cs = o.comp_starts.as<int64_t>();
-  TPG_HIP(launch_comp_pp_starts(ws->dg, ws->sub_cnt.as<uint32_t>(), ws->sub_len.as<int64_t>(),
-                                ws->totals.as<int64_t>(), cs, cs + (U.n_comp + 1), st));
+  TPG_TRY(reserve_scan(ws, P.n_pp));
+  int64_t* lbr = ws->leaf_by_rank.as<int64_t>();
+  int32_t* len = ws->pp_len.as<int32_t>();
+  TPG_HIP(launch_roots(a, U.n, sc, lbr, len, ws->totals.as<int64_t>(), 1, st));
   for (int L = 1; L < R.Lmax; ++L)
-    TPG_HIP(launch_down(a, R.off[L], R.count[L], ws->sub_cnt.as<uint32_t>(),
-                        ws->sub_len.as<int64_t>(), ws->leaf_by_rank.as<int64_t>(), st));
-  TPG_HIP(launch_pp_offsets(ws->leaf_by_rank.as<int64_t>(), ws->sub_len.as<int64_t>(), P.n_pp,
-                            P.n_vtx, o.pp_off.as<int64_t>(), st));
-  TPG_HIP(launch_pp_write(a, ws->leaf_by_rank.as<int64_t>(), o.pp_off.as<int64_t>(), P.n_pp,
-                          o.pp_vtx.as<int32_t>(), st));
+    TPG_HIP(launch_down(a, L, R.off[L], R.count[L], sc, lbr, len, st));
+  // offsets of the prime paths: a scan of their lengths
+  int64_t* scal = ws->scalars.as<int64_t>();
+  TPG_HIP(scan_i32_to_i64(len, o.pp_off.as<int64_t>(), P.n_pp, 0, scal + 6,
+                          ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
+  int64_t* cs = o.comp_starts.as<int64_t>();
+  TPG_HIP(launch_comp_pp_starts(ws->dg, sc, o.pp_off.as<int64_t>(), ws->totals.as<int64_t>(), cs,
+                                cs + (U.n_comp + 1), st));
+  TPG_HIP(hipMemcpyAsync(ws->h_scalars + 6, scal + 6, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TPG_HIP(hipStreamSynchronize(st));
+  P.n_vtx = ws->h_scalars[6];
+  TPG_TRY(ws_reserve(ws, o.pp_vtx, sizeof(int32_t) * (P.n_vtx + 1)));
+  TPG_HIP(launch_pp_write(a, lbr, o.pp_off.as<int64_t>(), P.n_pp, o.pp_vtx.as<int32_t>(), st));
   o.n_pp = P.n_pp;
   o.n_ppv = P.n_vtx;
   return TPG_OK;
@@ -550,6 +553,9 @@ BfsOut bfs_views(tpg_workspace* ws, int n) {
   b.next = bi + 3 * n;
   b.pre = bi + 4 * n;
   b.pend = bi + 5 * n;
+  b.cfirst = bi + 6 * n;
+  b.ccnt = bi + 7 * n;
+  b.bq = bi + 8 * n;
   b.pfx_off = ws->pfx_off.as<int64_t>();
   b.sfx_off = ws->sfx_off.as<int64_t>();
   return b;
@@ -559,7 +565,7 @@ BfsOut bfs_views(tpg_workspace* ws, int n) {
 // union, on the side stream after everything already queued on `st`.
 tpg_status bfs_start(tpg_workspace* ws, const HostUnion& U, hipStream_t st) {
   const int n = U.n;
-  TPG_TRY(ws_reserve(ws, ws->bfs_i32, sizeof(int32_t) * 6 * (size_t)n));
+  TPG_TRY(ws_reserve(ws, ws->bfs_i32, sizeof(int32_t) * 9 * (size_t)n));
   TPG_TRY(ws_reserve(ws, ws->pfx_off, sizeof(int64_t) * (n + 1)));
   TPG_TRY(ws_reserve(ws, ws->sfx_off, sizeof(int64_t) * (n + 1)));
   TPG_TRY(ws_reserve(ws, ws->scan2_status, sizeof(uint64_t) * (scan_tiles(n) + 2)));
@@ -598,10 +604,9 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
   TPG_TRY(ws_reserve(ws, ws->rb1, sizeof(int64_t) * (n + 2)));
   TPG_TRY(ws_reserve(ws, ws->idx0, sizeof(int32_t) * (np + 1)));
   TPG_TRY(ws_reserve(ws, ws->idx1, sizeof(int32_t) * (np + 1)));
-  TPG_TRY(ws_reserve(ws, ws->tp_grp, sizeof(int32_t) * (np + 1)));
+  TPG_TRY(ws_reserve(ws, ws->tp_key, sizeof(uint64_t) * 2 * (np + 1)));
   TPG_HIP(launch_tp_len(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), np, n, b,
-                        ws->tp_len.as<int64_t>(), ws->tp_grp.as<int32_t>(), ws->rb0.as<int64_t>(),
-                        st));
+                        ws->tp_len.as<int64_t>(), ws->rb0.as<int64_t>(), st));
   TPG_HIP(scan_i64(ws->tp_len.as<int64_t>(), ws->tp_off.as<int64_t>(), np, 0, sc,
                    ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
   TPG_HIP(hipMemcpyAsync(ws->h_scalars, sc, sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -616,11 +621,10 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
   TPG_HIP(launch_bfs_tables(ws->dg, b, st));
   TPG_TRY(ws_reserve(ws, ws->tp_vtx, sizeof(int32_t) * (tp_total + 1)));
   TPG_HIP(launch_tp_write(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), np, b,
-                          ws->tp_off.as<int64_t>(), ws->tp_vtx.as<int32_t>(), ws->idx0.as<int32_t>(),
-                          st));
+                          ws->tp_off.as<int64_t>(), ws->tp_vtx.as<int32_t>(),
+                          ws->tp_key.as<uint64_t>(), ws->idx0.as<int32_t>(), st));
   // merge the per-first-vertex runs
-  TpOrder K{ws->tp_off.as<int64_t>(), ws->tp_vtx.as<int32_t>(), ws->tp_grp.as<int32_t>(),
-            b.pre, b.pend, b.dist_f};
+  TpOrder K{ws->tp_off.as<int64_t>(), ws->tp_vtx.as<int32_t>(), ws->tp_key.as<uint64_t>()};
   int64_t runs = n;
   DevBuf* ri = &ws->rb0;
   DevBuf* ro = &ws->rb1;
@@ -822,10 +826,10 @@ void tpg_workspace_free(tpg_workspace* ws) {
   if (ws->own_stream) (void)hipStreamSynchronize(ws->own_stream);
   if (ws->side_stream) (void)hipStreamSynchronize(ws->side_stream);
   DevBuf* bufs[] = {&ws->g_csr, &ws->par, &ws->info, &ws->cstart, &ws->nch, &ws->mask0,
-                    &ws->mask1, &ws->ls, &ws->sub_cnt, &ws->sub_len,
+                    &ws->mask1, &ws->ls, &ws->sub_cnt, &ws->pp_len,
                     &ws->leaf_by_rank, &ws->totals, &ws->cycles, &ws->scan_status,
                     &ws->scan_ctr, &ws->scalars, &ws->bfs_i32, &ws->pfx_off, &ws->sfx_off,
-                    &ws->pfx, &ws->sfx, &ws->tp_len, &ws->tp_off, &ws->tp_vtx, &ws->tp_grp, &ws->idx0,
+                    &ws->pfx, &ws->sfx, &ws->tp_len, &ws->tp_off, &ws->tp_vtx, &ws->tp_key, &ws->idx0,
                     &ws->idx1, &ws->grp_cnt, &ws->rb0, &ws->rb1, &ws->keep_cnt, &ws->keep_len,
                     &ws->keep_pos, &ws->keep_voff, &ws->comp_cnt, &ws->lvl_comp, &ws->b_pp_off,
                     &ws->scan2_status, &ws->scalars2,

@@ -61,18 +61,17 @@ hipError_t launch_count(int W, const ExtArgs& a, int L, int64_t base, int64_t F,
 hipError_t launch_fill(int W, const ExtArgs& a, int L, int64_t base, int64_t F, hipStream_t st);
 
 // --- ranking / materialization ---------------------------------------------
-// sub_cnt / sub_len: PP leaves and their total entries per subtree, then
-// rewritten top-down into (rank of first PP, offset of its first vertex).
+// sub_cnt: PP leaves per subtree (k_up), then rewritten top-down into the
+// rank of the subtree's first PP (or 0xFFFFFFFF when it has none).
 hipError_t launch_up(const ExtArgs& a, int L, int64_t base, int64_t F, uint32_t* sub_cnt,
-                     int64_t* sub_len, unsigned long long* n_cycles, hipStream_t st);
-// mode 0: totals[0] = #PP, totals[1] = #PP vertices (no change to the arrays);
-// mode 1: level-1 subtree sums -> ranks / vertex offsets, root leaves recorded.
-hipError_t launch_roots(const ExtArgs& a, int64_t n_roots, uint32_t* sub_cnt, int64_t* sub_len,
-                        int64_t* leaf_by_rank, int64_t* totals, int mode, hipStream_t st);
-hipError_t launch_down(const ExtArgs& a, int64_t base, int64_t F, uint32_t* sub_cnt,
-                       int64_t* sub_len, int64_t* leaf_by_rank, hipStream_t st);
-hipError_t launch_pp_offsets(const int64_t* leaf_by_rank, const int64_t* sub_len, int64_t n_pp,
-                             int64_t total, int64_t* pp_off, hipStream_t st);
+                     unsigned long long* n_cycles, hipStream_t st);
+// mode 0: totals[0] = #PP (no change to the arrays); mode 1: level-1 ranks,
+// root leaves recorded (leaf_by_rank, pp_len = 1).
+hipError_t launch_roots(const ExtArgs& a, int64_t n_roots, uint32_t* sub_cnt, int64_t* leaf_by_rank,
+                        int32_t* pp_len, int64_t* totals, int mode, hipStream_t st);
+// parents of level L: ranks to the children; PP leaves record node and length
+hipError_t launch_down(const ExtArgs& a, int L, int64_t base, int64_t F, uint32_t* sub_cnt,
+                       int64_t* leaf_by_rank, int32_t* pp_len, hipStream_t st);
 hipError_t launch_pp_write(const ExtArgs& a, const int64_t* leaf_by_rank, const int64_t* pp_off,
                            int64_t n_pp, int32_t* pp_vtx, hipStream_t st);
 
@@ -101,33 +100,35 @@ struct BfsOut {
   int32_t* sfx;      // [sfx_off[n]]
   int32_t* pre;      // [n] graph-wide preorder rank in the BFS tree (children ascending)
   int32_t* pend;     // [n] end of v's subtree rank range
+  int32_t* cfirst;   // [n] v's tree children: bq[cfirst[v] .. cfirst[v] + ccnt[v]), ascending
+  int32_t* ccnt;     // [n]
+  int32_t* bq;       // [n] the search queue (graph-wide ids)
 };
-// What the test-path comparison reads.
+// What the test-path comparison reads: per test path two 64-bit keys (see
+// k_tp_write) and, for the rare ties the keys leave, the entries.
 struct TpOrder {
-  const int64_t* off;  // [n + 1] test-path offsets
-  const int32_t* vtx;  // test-path entries
-  const int32_t* grp;  // [n] first vertex of each test path's prime path
-  const int32_t* pre;  // BfsOut::pre
-  const int32_t* pend; // BfsOut::pend
-  const int32_t* dist; // BfsOut::dist_f
+  const int64_t* off;   // [n + 1] test-path offsets
+  const int32_t* vtx;   // test-path entries
+  const uint64_t* key;  // [2 n]
 };
-// one workgroup per component: dist_f, parent, pre, pend, dist_b, next
+// one workgroup per component: dist_f, parent, pre, pend, tree children, dist_b, next
 hipError_t launch_bfs_dist(const DGraph& g, const BfsOut& b, hipStream_t st);
 // after pfx_off / sfx_off are scans of dist_f / dist_b: fill pfx / sfx
 hipError_t launch_bfs_tables(const DGraph& g, const BfsOut& b, hipStream_t st);
 hipError_t launch_localize(const int32_t* loc, int32_t* v, int64_t n, hipStream_t st);
-// per-component output starts: pp_start[c] = rank of the first PP of c, etc.
-hipError_t launch_comp_pp_starts(const DGraph& g, const uint32_t* sub_cnt, const int64_t* sub_len,
+// per-component output starts: pp_start[c] = rank of the first PP of c and
+// ppv_start[c] = offset of its first entry (after the PP offsets exist)
+hipError_t launch_comp_pp_starts(const DGraph& g, const uint32_t* sub_cnt, const int64_t* pp_off,
                                  const int64_t* totals, int64_t* pp_start, int64_t* ppv_start,
                                  hipStream_t st);
 
 // test-path lengths, and rb[v] = first prime path with first vertex >= v (v = 0..n)
 hipError_t launch_tp_len(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp, int n,
-                         const BfsOut& b, int64_t* tp_len, int32_t* grp, int64_t* rb,
-                         hipStream_t st);
+                         const BfsOut& b, int64_t* tp_len, int64_t* rb, hipStream_t st);
+// writes the test paths, their comparison keys and idx[i] = i
 hipError_t launch_tp_write(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp,
                            const BfsOut& b, const int64_t* tp_off, int32_t* tp_vtx,
-                           int32_t* idx, hipStream_t st);
+                           uint64_t* key, int32_t* idx, hipStream_t st);
 // one round of pairwise merging of sorted runs [rb[r], rb[r+1]) of idx
 hipError_t launch_merge_round(const TpOrder& K, const int32_t* idx_in, int32_t* idx_out,
                               const int64_t* rb, int64_t n_runs, int64_t n, hipStream_t st);

@@ -586,11 +586,15 @@ hipError_t launch_fill(int W, const ExtArgs& a, int L, int64_t base, int64_t F, 
 }
 
 // ---------------------------------------------------------------------------
-// canonical order: subtree sums bottom-up, ranks top-down
+// canonical order: subtree counts bottom-up, ranks top-down
 // ---------------------------------------------------------------------------
+// sub_cnt[g] = prime-path leaves in g's subtree (k_up), then rewritten top-down
+// into the rank of the subtree's first prime path, or kNoRank when the
+// subtree holds none (k_down then skips it after one 4-byte read).
+constexpr uint32_t kNoRank = 0xFFFFFFFFu;
+
 __global__ __launch_bounds__(kBlock) void k_up(ExtArgs a, int L, int64_t base, int64_t F,
-                                               uint32_t* sub_cnt, int64_t* sub_len,
-                                               unsigned long long* n_cycles) {
+                                               uint32_t* sub_cnt, unsigned long long* n_cycles) {
   __shared__ int32_t s_w[kBlock / 64];
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   int cyc = 0;
@@ -598,20 +602,14 @@ __global__ __launch_bounds__(kBlock) void k_up(ExtArgs a, int L, int64_t base, i
     const int64_t g = base + j;
     const uint32_t inf = a.t.info[g];
     uint32_t c = 0;
-    int64_t l = 0;
     if (inf & (F_CYC | F_PP)) {
       c = 1;
-      l = L;
       cyc = (inf & F_CYC) ? 1 : 0;
     } else if (!(inf & F_TERM)) {
       const int64_t c0 = a.t.cstart[g], c1 = c0 + a.t.nch[g];
-      for (int64_t x = c0; x < c1; ++x) {
-        c += sub_cnt[x];
-        l += sub_len[x];
-      }
+      for (int64_t x = c0; x < c1; ++x) c += sub_cnt[x];
     }
     sub_cnt[g] = c;
-    sub_len[g] = l;
   }
   int32_t tot;
   block_excl_scan<kBlock, int32_t>(cyc, tot, s_w);
@@ -619,91 +617,72 @@ __global__ __launch_bounds__(kBlock) void k_up(ExtArgs a, int L, int64_t base, i
 }
 
 hipError_t launch_up(const ExtArgs& a, int L, int64_t base, int64_t F, uint32_t* sub_cnt,
-                     int64_t* sub_len, unsigned long long* n_cycles, hipStream_t st) {
+                     unsigned long long* n_cycles, hipStream_t st) {
   if (F == 0) return hipSuccess;
-  k_up<<<(unsigned)((F + kBlock - 1) / kBlock), kBlock, 0, st>>>(a, L, base, F, sub_cnt, sub_len,
-                                                                  n_cycles);
+  k_up<<<(unsigned)((F + kBlock - 1) / kBlock), kBlock, 0, st>>>(a, L, base, F, sub_cnt, n_cycles);
   return hipGetLastError();
 }
 
-// Level-1 nodes: exclusive scans of their subtree sums give the rank of the
-// first PP and the offset of its first vertex.  totals[0] = #PP,
-// totals[1] = #PP vertices.  One workgroup of 1024 threads (n <= 4096).
+// Level-1 nodes: an exclusive scan of their subtree counts gives the rank of
+// their first prime path.  totals[0] = #PP.  One workgroup of 1024 threads.
 __global__ __launch_bounds__(1024) void k_roots(ExtArgs a, int64_t n_roots, uint32_t* sub_cnt,
-                                                int64_t* sub_len, int64_t* leaf_by_rank,
+                                                int64_t* leaf_by_rank, int32_t* pp_len,
                                                 int64_t* totals, int mode) {
   __shared__ int64_t s_w[16];
-  __shared__ int64_t s_w2[16];
-  int64_t carry_c = 0, carry_l = 0;
+  int64_t carry = 0;
   for (int64_t b = 0; b < n_roots; b += 1024) {
     const int64_t i = b + threadIdx.x;
     const int64_t c = i < n_roots ? (int64_t)sub_cnt[i] : 0;
-    const int64_t l = i < n_roots ? sub_len[i] : 0;
-    int64_t tc, tl;
+    int64_t tc;
     const int64_t pc = block_excl_scan<1024, int64_t>(c, tc, s_w);
-    const int64_t pl = block_excl_scan<1024, int64_t>(l, tl, s_w2);
     if (i < n_roots && mode == 1) {
-      const int64_t rank = carry_c + pc;
+      const int64_t rank = carry + pc;
       sub_cnt[i] = (uint32_t)rank;
-      sub_len[i] = carry_l + pl;
-      if (a.t.info[i] & (F_PP | F_CYC)) leaf_by_rank[rank] = i;
+      if (a.t.info[i] & (F_PP | F_CYC)) {
+        leaf_by_rank[rank] = i;
+        pp_len[rank] = 1;
+      }
     }
-    carry_c += tc;
-    carry_l += tl;
+    carry += tc;
   }
-  if (threadIdx.x == 0 && mode == 0) {
-    totals[0] = carry_c;
-    totals[1] = carry_l;
-  }
+  if (threadIdx.x == 0 && mode == 0) totals[0] = carry;
 }
 
-hipError_t launch_roots(const ExtArgs& a, int64_t n_roots, uint32_t* sub_cnt, int64_t* sub_len,
-                        int64_t* leaf_by_rank, int64_t* totals, int mode, hipStream_t st) {
-  k_roots<<<1, 1024, 0, st>>>(a, n_roots, sub_cnt, sub_len, leaf_by_rank, totals, mode);
+hipError_t launch_roots(const ExtArgs& a, int64_t n_roots, uint32_t* sub_cnt, int64_t* leaf_by_rank,
+                        int32_t* pp_len, int64_t* totals, int mode, hipStream_t st) {
+  k_roots<<<1, 1024, 0, st>>>(a, n_roots, sub_cnt, leaf_by_rank, pp_len, totals, mode);
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(kBlock) void k_down(ExtArgs a, int64_t base, int64_t F,
-                                                 uint32_t* sub_cnt, int64_t* sub_len,
-                                                 int64_t* leaf_by_rank) {
+// Parents of level L hand ranks to their children in slot order; a prime
+// path leaf records its node and length (L + 1 entries) under its rank.
+__global__ __launch_bounds__(kBlock) void k_down(ExtArgs a, int L, int64_t base, int64_t F,
+                                                 uint32_t* sub_cnt, int64_t* leaf_by_rank,
+                                                 int32_t* pp_len) {
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (j >= F) return;
   const int64_t g = base + j;
+  uint32_t r = sub_cnt[g];
+  if (r == kNoRank) return;
   const uint32_t inf = a.t.info[g];
   if (inf & (F_CYC | F_TERM)) return;
-  int64_t r = sub_cnt[g];
-  int64_t o = sub_len[g];
   const int64_t c0 = a.t.cstart[g], c1 = c0 + a.t.nch[g];
   for (int64_t x = c0; x < c1; ++x) {
     const uint32_t cc = sub_cnt[x];
-    const int64_t cl = sub_len[x];
-    sub_cnt[x] = (uint32_t)r;
-    sub_len[x] = o;
-    if (a.t.info[x] & (F_PP | F_CYC)) leaf_by_rank[r] = x;
+    sub_cnt[x] = cc ? r : kNoRank;
+    if (cc && (a.t.info[x] & (F_PP | F_CYC))) {
+      leaf_by_rank[r] = x;
+      pp_len[r] = L + 1;
+    }
     r += cc;
-    o += cl;
   }
 }
 
-hipError_t launch_down(const ExtArgs& a, int64_t base, int64_t F, uint32_t* sub_cnt,
-                       int64_t* sub_len, int64_t* leaf_by_rank, hipStream_t st) {
+hipError_t launch_down(const ExtArgs& a, int L, int64_t base, int64_t F, uint32_t* sub_cnt,
+                       int64_t* leaf_by_rank, int32_t* pp_len, hipStream_t st) {
   if (F == 0) return hipSuccess;
-  k_down<<<(unsigned)((F + kBlock - 1) / kBlock), kBlock, 0, st>>>(a, base, F, sub_cnt, sub_len,
-                                                                    leaf_by_rank);
-  return hipGetLastError();
-}
-
-__global__ void k_pp_offsets(const int64_t* leaf_by_rank, const int64_t* sub_len, int64_t n_pp,
-                             int64_t total, int64_t* pp_off) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_pp) pp_off[i] = sub_len[leaf_by_rank[i]];
-  if (i == n_pp) pp_off[i] = total;
-}
-
-hipError_t launch_pp_offsets(const int64_t* leaf_by_rank, const int64_t* sub_len, int64_t n_pp,
-                             int64_t total, int64_t* pp_off, hipStream_t st) {
-  k_pp_offsets<<<(unsigned)((n_pp + 1 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-      leaf_by_rank, sub_len, n_pp, total, pp_off);
+  k_down<<<(unsigned)((F + kBlock - 1) / kBlock), kBlock, 0, st>>>(a, L, base, F, sub_cnt,
+                                                                    leaf_by_rank, pp_len);
   return hipGetLastError();
 }
 
@@ -750,24 +729,27 @@ hipError_t launch_pp_write(const ExtArgs& a, const int64_t* leaf_by_rank, const 
 
 namespace tpg {
 
-__global__ void k_comp_pp_starts(DGraph g, const uint32_t* sub_cnt, const int64_t* sub_len,
+// After the ranks and the offsets exist: first prime path of each component
+// (its first root's rank) and the offset of that path's first entry.
+__global__ void k_comp_pp_starts(DGraph g, const uint32_t* sub_cnt, const int64_t* pp_off,
                                  const int64_t* totals, int64_t* pp_start, int64_t* ppv_start) {
   const int c = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (c < g.n_comp) {
-    pp_start[c] = sub_cnt[g.cbase[c]];
-    ppv_start[c] = sub_len[g.cbase[c]];
+    const int64_t r = sub_cnt[g.cbase[c]];
+    pp_start[c] = r;
+    ppv_start[c] = pp_off[r];
   }
   if (c == g.n_comp) {
     pp_start[c] = totals[0];
-    ppv_start[c] = totals[1];
+    ppv_start[c] = pp_off[totals[0]];
   }
 }
 
-hipError_t launch_comp_pp_starts(const DGraph& g, const uint32_t* sub_cnt, const int64_t* sub_len,
+hipError_t launch_comp_pp_starts(const DGraph& g, const uint32_t* sub_cnt, const int64_t* pp_off,
                                  const int64_t* totals, int64_t* pp_start, int64_t* ppv_start,
                                  hipStream_t st) {
   k_comp_pp_starts<<<(unsigned)((g.n_comp + 1 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-      g, sub_cnt, sub_len, totals, pp_start, ppv_start);
+      g, sub_cnt, pp_off, totals, pp_start, ppv_start);
   return hipGetLastError();
 }
 

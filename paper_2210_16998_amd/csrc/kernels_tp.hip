@@ -18,8 +18,9 @@
 // vertex; within a group all test paths share the prefix and keep the order
 // of their prime paths, and no two are equal.  The groups are therefore
 // already sorted runs, merged pairwise (merge path partitioning, each thread
-// merges a fixed-size chunk), after which duplicates are adjacent.  Most
-// comparisons are decided by the BFS tree alone (see tp_cmp).
+// merges a fixed-size chunk), after which duplicates are adjacent.  Almost
+// every comparison is decided by two 64-bit keys per path derived from the
+// BFS tree (see tp_cmp).
 
 #include <climits>
 
@@ -84,6 +85,8 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_dist(DGraph g, BfsOut b) {
     s_sz[v] = 1;
     b.parent[base + v] = -1;
     b.next[base + v] = -1;
+    b.ccnt[base + v] = 0;
+    b.cfirst[base + v] = base;
   }
   const int el = g.centry[c] - base;
   if (tid == 0) {
@@ -119,6 +122,8 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_dist(DGraph g, BfsOut b) {
     for (int q = tid; q < m; q += kBfsThreads) {
       const int u = base + s_q[qb + q];
       int pos = qe + s_cnt[q];
+      b.cfirst[u] = base + pos;
+      b.ccnt[u] = (q + 1 < m ? (int)s_cnt[q + 1] : m2) - (int)s_cnt[q];
       for (int k = g.sp[u]; k < g.sp[u + 1]; ++k) {
         const int wl = g.s[k] - base;
         if (s_df[wl] == -1 && s_key[wl] == q * 64 + (k - g.sp[u])) {
@@ -140,6 +145,7 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_dist(DGraph g, BfsOut b) {
     __syncthreads();
   }
   const int nlayers = d;  // layers 0 .. nlayers - 1
+  for (int i = tid; i < qe; i += kBfsThreads) b.bq[base + i] = base + s_q[i];
   // subtree sizes, deepest layer first
   for (int l = nlayers - 1; l >= 1; --l) {
     for (int i = s_lb[l] + tid; i < s_lb[l + 1]; i += kBfsThreads) {
@@ -267,13 +273,12 @@ hipError_t launch_localize(const int32_t* loc, int32_t* v, int64_t n, hipStream_
 // splice
 // ---------------------------------------------------------------------------
 __global__ void k_tp_len(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp, BfsOut b,
-                         int64_t* tp_len, int32_t* grp) {
+                         int64_t* tp_len) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_pp) return;
   const int64_t o0 = pp_off[i], o1 = pp_off[i + 1];
   const int v1 = pp_vtx[o0], vk = pp_vtx[o1 - 1];
   tp_len[i] = (b.pfx_off[v1 + 1] - b.pfx_off[v1]) + (o1 - o0) + (b.sfx_off[vk + 1] - b.sfx_off[vk]);
-  grp[i] = v1;
 }
 
 // Prime paths are sorted, hence grouped by first vertex: rb[v] = index of the
@@ -291,19 +296,30 @@ __global__ void k_run_bounds(const int64_t* pp_off, const int32_t* pp_vtx, int64
 }
 
 hipError_t launch_tp_len(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp, int n,
-                         const BfsOut& b, int64_t* tp_len, int32_t* grp, int64_t* rb,
-                         hipStream_t st) {
+                         const BfsOut& b, int64_t* tp_len, int64_t* rb, hipStream_t st) {
   if (n_pp == 0) return hipSuccess;
   const unsigned grid = (unsigned)((n_pp + kBlock - 1) / kBlock);
-  k_tp_len<<<grid, kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, b, tp_len, grp);
+  k_tp_len<<<grid, kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, b, tp_len);
   k_run_bounds<<<grid, kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, n, rb);
   return hipGetLastError();
 }
 
-// One wave per test path: lane l writes entries l, l + 64, ... (coalesced).
+// Comparison key of a test path t (graph-wide ids; ranks fit 18 bits):
+//  * w = last vertex of the longest prefix of t that is a BFS-tree path
+//    (the tree path to the prime path's first vertex u, extended while each
+//    next entry is the tree child of the one before), D = its depth;
+//  * e = the entry after that prefix (none when t ends there);
+//  * split = preorder rank of w's first tree child larger than e (pend(w)
+//    when none; pre(w) + 1 when there is no e).
+// k1 = pre(w) | pend(w) << 18 | D << 36 | (e exists) << 49
+// k2 = e | split << 17 | pre(u) << 35
+constexpr uint64_t kM17 = (1ull << 17) - 1, kM18 = (1ull << 18) - 1, kM13 = (1ull << 13) - 1;
+
+// One wave per test path: lane l writes entries l, l + 64, ... (coalesced)
+// and checks at the same time whether its entry continues the tree path.
 __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, const int32_t* pp_vtx,
                                                      int64_t n_pp, BfsOut b, const int64_t* tp_off,
-                                                     int32_t* tp_vtx, int32_t* idx) {
+                                                     int32_t* tp_vtx, uint64_t* key, int32_t* idx) {
   const int64_t i = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   if (i >= n_pp) return;
   const int lane = lane_id();
@@ -312,70 +328,182 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
   const int64_t p0 = b.pfx_off[v1], lp = b.pfx_off[v1 + 1] - p0;
   const int64_t s0 = b.sfx_off[vk], ls = b.sfx_off[vk + 1] - s0;
   const int64_t lq = o1 - o0;
-  const int64_t w = tp_off[i];
-  for (int64_t k = lane; k < lp + lq + ls; k += 64) {
-    int32_t x;
-    if (k < lp) x = b.pfx[p0 + k];
-    else if (k < lp + lq) x = pp_vtx[o0 + (k - lp)];
-    else x = b.sfx[s0 + (k - lp - lq)];
-    tp_vtx[w + k] = x;
+  const int64_t len = lp + lq + ls;
+  const int64_t w0 = tp_off[i];
+  int64_t first_off = len;  // first position that leaves the tree path
+  int wv = -1, ev = -1;     // the entries before and at that position
+  int carry = -1;           // entry kb - 1
+  for (int64_t kb = 0; kb < len; kb += 64) {
+    const int64_t k = kb + lane;
+    int x = -1;
+    if (k < len) {
+      if (k < lp) x = b.pfx[p0 + k];
+      else if (k < lp + lq) x = pp_vtx[o0 + (k - lp)];
+      else x = b.sfx[s0 + (k - lp - lq)];
+      tp_vtx[w0 + k] = x;
+    }
+    int prev = __shfl_up(x, 1, 64);
+    if (lane == 0) prev = carry;
+    const bool leaves = k < len && k > lp && b.parent[x] != prev;
+    const uint64_t bal = __ballot(leaves);
+    if (first_off == len && bal) {
+      const int fl = __builtin_ctzll(bal);
+      first_off = kb + fl;
+      ev = __shfl(x, fl, 64);
+      const int wb = __shfl(x, fl > 0 ? fl - 1 : 0, 64);
+      wv = fl > 0 ? wb : carry;
+    }
+    const int last = (int)((len - 1 - kb) < 63 ? (len - 1 - kb) : 63);
+    carry = __shfl(x, last, 64);
   }
-  if (lane == 0) idx[i] = (int32_t)i;
+  if (lane == 0) {
+    const bool has_e = first_off < len;
+    const int w = has_e ? wv : carry;  // the whole path follows the tree: w = last entry
+    const int64_t D = first_off - 1;
+    const uint32_t prew = (uint32_t)b.pre[w], pendw = (uint32_t)b.pend[w];
+    uint32_t split;
+    if (has_e) {
+      split = pendw;
+      const int cf = b.cfirst[w], cn = b.ccnt[w];
+      for (int q = 0; q < cn; ++q) {
+        const int cv = b.bq[cf + q];
+        if (cv > ev) {
+          split = (uint32_t)b.pre[cv];
+          break;
+        }
+      }
+    } else {
+      split = prew + 1;
+    }
+    key[2 * i] = (uint64_t)prew | ((uint64_t)pendw << 18) | ((uint64_t)D << 36) |
+                 ((uint64_t)(has_e ? 1 : 0) << 49);
+    key[2 * i + 1] = (uint64_t)(has_e ? ev : 0) | ((uint64_t)split << 17) |
+                     ((uint64_t)(uint32_t)b.pre[v1] << 35);
+    idx[i] = (int32_t)i;
+  }
 }
 
 hipError_t launch_tp_write(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp,
                            const BfsOut& b, const int64_t* tp_off, int32_t* tp_vtx,
-                           int32_t* idx, hipStream_t st) {
+                           uint64_t* key, int32_t* idx, hipStream_t st) {
   if (n_pp == 0) return hipSuccess;
   const int64_t per = kBlock / 64;
   k_tp_write<<<(unsigned)((n_pp + per - 1) / per), kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, b,
-                                                                    tp_off, tp_vtx, idx);
+                                                                    tp_off, tp_vtx, key, idx);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // sort + dedup
 // ---------------------------------------------------------------------------
-// Lexicographic comparison of test paths x and y.  TP(x) starts with the
-// BFS-tree path to its group vertex u (the first vertex of its prime path):
-//  * same group: the order of the prime paths, i.e. of the indices;
-//  * neither group vertex an ancestor of the other: the tree paths differ
-//    first, at the children of their lowest common ancestor, and the
-//    preorder ranks (children ascending) order them;
-//  * u a proper ancestor of v: both start with the tree path to u
-//    (dist(u) + 1 entries), so the entries after it decide.
-__device__ __forceinline__ int tp_cmp(const TpOrder& K, int64_t x, int64_t y) {
-  if (x == y) return 0;
-  const int u = K.grp[x], v = K.grp[y];
-  if (u == v) return x < y ? -1 : 1;
-  const int pu = K.pre[u], pv = K.pre[v];
-  int64_t k0;
-  if (pv > pu && pv < K.pend[u]) k0 = K.dist[u] + 1;
-  else if (pu > pv && pu < K.pend[v]) k0 = K.dist[v] + 1;
-  else return pu < pv ? -1 : 1;
+// Entries k0.. of two test paths compared lexicographically (then by
+// length), eight entries per step with independent loads.
+__device__ __forceinline__ int tp_cmp_tail(const TpOrder& K, int64_t x, int64_t y, int64_t k0) {
   const int64_t ox = K.off[x], oy = K.off[y];
   const int64_t lx = K.off[x + 1] - ox, ly = K.off[y + 1] - oy;
   const int64_t l = lx < ly ? lx : ly;
   const int32_t* px = K.vtx + ox;
   const int32_t* py = K.vtx + oy;
-  for (int64_t k = k0; k < l; ++k) {
+  int64_t k = k0;
+  for (; k + 8 <= l; k += 8) {
+    int32_t a[8], c[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      a[q] = px[k + q];
+      c[q] = py[k + q];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (a[q] != c[q]) return a[q] < c[q] ? -1 : 1;
+  }
+  for (; k < l; ++k) {
     const int32_t a = px[k], c = py[k];
     if (a != c) return a < c ? -1 : 1;
   }
   return lx < ly ? -1 : (lx > ly ? 1 : 0);
 }
 
-constexpr int kMergeChunk = 16;
-constexpr int kMergeBlock = 64;
+// Lexicographic comparison of test paths x and y from their keys:
+//  * same prime-path first vertex: the order of the prime paths (indices);
+//  * same tree prefix w: no e sorts first (equal when both end there), then
+//    e decides, then the entries after e;
+//  * w_x a proper ancestor of w_y: t_y continues with the tree child c of
+//    w_x towards w_y, t_x with e_x (not a tree child), and e_x < c exactly
+//    when pre(w_y) < split_x; symmetric the other way round;
+//  * otherwise the tree prefixes differ first and preorder decides.
+__device__ __forceinline__ int tp_cmp(const TpOrder& K, int64_t x, int64_t y) {
+  if (x == y) return 0;
+  const uint64_t ax = K.key[2 * x], bx = K.key[2 * x + 1];
+  const uint64_t ay = K.key[2 * y], by = K.key[2 * y + 1];
+  if ((bx >> 35) == (by >> 35)) return x < y ? -1 : 1;
+  const uint32_t pwx = (uint32_t)(ax & kM18), pwy = (uint32_t)(ay & kM18);
+  if (pwx == pwy) {
+    const bool hx = (ax >> 49) & 1, hy = (ay >> 49) & 1;
+    if (!hx || !hy) return hx == hy ? 0 : (hx ? 1 : -1);
+    const uint32_t ex = (uint32_t)(bx & kM17), ey = (uint32_t)(by & kM17);
+    if (ex != ey) return ex < ey ? -1 : 1;
+    return tp_cmp_tail(K, x, y, (int64_t)((ax >> 36) & kM13) + 2);
+  }
+  const uint32_t pex = (uint32_t)((ax >> 18) & kM18), pey = (uint32_t)((ay >> 18) & kM18);
+  if (pwx < pwy && pwy < pex) return pwy >= (uint32_t)((bx >> 17) & kM18) ? -1 : 1;
+  if (pwy < pwx && pwx < pey) return pwx >= (uint32_t)((by >> 17) & kM18) ? 1 : -1;
+  return pwx < pwy ? -1 : 1;
+}
 
-__global__ __launch_bounds__(kMergeBlock) void k_merge_round(TpOrder K, const int32_t* in,
-                                                             int32_t* out, const int64_t* rb,
-                                                             int64_t n_runs, int64_t n) {
-  const int64_t s = ((int64_t)blockIdx.x * kMergeBlock + threadIdx.x) * kMergeChunk;
-  if (s >= n) return;
-  const int64_t e = s + kMergeChunk < n ? s + kMergeChunk : n;
-  int64_t pos = s;
-  while (pos < e) {
+// Comparison from keys already loaded (x, y: test-path indices).
+__device__ __forceinline__ int tp_cmp_keys(const TpOrder& K, int64_t x, uint64_t ax, uint64_t bx,
+                                           int64_t y, uint64_t ay, uint64_t by) {
+  if (x == y) return 0;
+  if ((bx >> 35) == (by >> 35)) return x < y ? -1 : 1;
+  const uint32_t pwx = (uint32_t)(ax & kM18), pwy = (uint32_t)(ay & kM18);
+  if (pwx == pwy) {
+    const bool hx = (ax >> 49) & 1, hy = (ay >> 49) & 1;
+    if (!hx || !hy) return hx == hy ? 0 : (hx ? 1 : -1);
+    const uint32_t ex = (uint32_t)(bx & kM17), ey = (uint32_t)(by & kM17);
+    if (ex != ey) return ex < ey ? -1 : 1;
+    return tp_cmp_tail(K, x, y, (int64_t)((ax >> 36) & kM13) + 2);
+  }
+  const uint32_t pex = (uint32_t)((ax >> 18) & kM18), pey = (uint32_t)((ay >> 18) & kM18);
+  if (pwx < pwy && pwy < pex) return pwy >= (uint32_t)((bx >> 17) & kM18) ? -1 : 1;
+  if (pwy < pwx && pwx < pey) return pwx >= (uint32_t)((by >> 17) & kM18) ? 1 : -1;
+  return pwx < pwy ? -1 : 1;
+}
+
+// Merge path: number of elements taken from A among the first d outputs of
+// merge(A, B) (stable: A first on ties).  A, B: test-path indices (global).
+__device__ __forceinline__ int64_t merge_split_global(const TpOrder& K, const int32_t* A, int64_t na,
+                                                      const int32_t* B, int64_t nb, int64_t d) {
+  int64_t lo = d - nb > 0 ? d - nb : 0, hi = d < na ? d : na;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (tp_cmp(K, B[d - 1 - mid], A[mid]) >= 0) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// One round of pairwise merges of the sorted runs [rb[r], rb[r + 1]): run
+// 2p with run 2p + 1.  A workgroup produces kMergeTile consecutive outputs:
+// it finds its input slices with two merge-path searches, stages their
+// indices and keys in LDS, and every thread then splits and merges its own
+// kMergeItems outputs from LDS (the entries themselves are read only when
+// two paths share their tree prefix and next entry).
+constexpr int kMergeThreads = 128;
+constexpr int kMergeItems = 8;
+constexpr int kMergeTile = kMergeThreads * kMergeItems;
+
+__global__ __launch_bounds__(kMergeThreads) void k_merge_round(TpOrder K, const int32_t* in,
+                                                               int32_t* out, const int64_t* rb,
+                                                               int64_t n_runs, int64_t n) {
+  __shared__ int32_t s_idx[kMergeTile];
+  __shared__ uint64_t s_k1[kMergeTile];
+  __shared__ uint64_t s_k2[kMergeTile];
+  __shared__ int64_t s_seg[4];
+  const int tid = (int)threadIdx.x;
+  const int64_t t0 = (int64_t)blockIdx.x * kMergeTile;
+  const int64_t t1 = t0 + kMergeTile < n ? t0 + kMergeTile : n;
+  int64_t pos = t0;
+  while (pos < t1) {
+    // the pair of runs holding output position pos
     int64_t lo = 0, hi = n_runs - 1;
     while (lo < hi) {
       const int64_t mid = (lo + hi + 1) >> 1;
@@ -388,26 +516,58 @@ __global__ __launch_bounds__(kMergeBlock) void k_merge_round(TpOrder K, const in
     const int32_t* A = in + a0;
     const int32_t* B = in + a1;
     const int64_t na = a1 - a0, nb = b1 - a1;
-    const int64_t stop = e < b1 ? e : b1;
-    const int64_t d = pos - a0;
-    int64_t l2 = d - nb > 0 ? d - nb : 0, h2 = d < na ? d : na;
-    while (l2 < h2) {
-      const int64_t mid = (l2 + h2) >> 1;
-      if (tp_cmp(K, B[d - 1 - mid], A[mid]) >= 0) l2 = mid + 1; else h2 = mid;
+    const int64_t stop = t1 < b1 ? t1 : b1;
+    // input slices of this segment (two searches, by two threads)
+    if (tid < 2) {
+      const int64_t d = (tid == 0 ? pos : stop) - a0;
+      s_seg[tid] = merge_split_global(K, A, na, B, nb, d);
     }
-    int64_t i = l2, j = d - l2;
-    while (pos < stop) {
-      const bool take_a = (j >= nb) || (i < na && tp_cmp(K, B[j], A[i]) >= 0);
-      out[pos++] = take_a ? A[i++] : B[j++];
+    __syncthreads();
+    const int64_t ia = s_seg[0], ja = (pos - a0) - ia;
+    const int64_t ib = s_seg[1], jb = (stop - a0) - ib;
+    const int la = (int)(ib - ia), lb = (int)(jb - ja);
+    for (int q = tid; q < la + lb; q += kMergeThreads) {
+      const int32_t x = q < la ? A[ia + q] : B[ja + (q - la)];
+      s_idx[q] = x;
+      s_k1[q] = K.key[2 * (int64_t)x];
+      s_k2[q] = K.key[2 * (int64_t)x + 1];
     }
+    __syncthreads();
+    // this thread's outputs within the segment, merged from LDS
+    const int m = la + lb;
+    const int d0 = tid * kMergeItems < m ? tid * kMergeItems : m;
+    const int d1 = d0 + kMergeItems < m ? d0 + kMergeItems : m;
+    if (d0 < d1) {
+      int l2 = d0 - lb > 0 ? d0 - lb : 0, h2 = d0 < la ? d0 : la;
+      while (l2 < h2) {
+        const int mid = (l2 + h2) >> 1;
+        const int qb = la + (d0 - 1 - mid);
+        if (tp_cmp_keys(K, s_idx[qb], s_k1[qb], s_k2[qb], s_idx[mid], s_k1[mid], s_k2[mid]) >= 0)
+          l2 = mid + 1;
+        else
+          h2 = mid;
+      }
+      int i = l2, j = d0 - l2;
+      for (int o = d0; o < d1; ++o) {
+        bool take_a;
+        if (j >= lb) take_a = true;
+        else if (i >= la) take_a = false;
+        else {
+          const int qb = la + j;
+          take_a = tp_cmp_keys(K, s_idx[qb], s_k1[qb], s_k2[qb], s_idx[i], s_k1[i], s_k2[i]) >= 0;
+        }
+        out[pos + o] = take_a ? s_idx[i++] : s_idx[la + j++];
+      }
+    }
+    __syncthreads();
+    pos = stop;
   }
 }
 
 hipError_t launch_merge_round(const TpOrder& K, const int32_t* idx_in, int32_t* idx_out,
                               const int64_t* rb, int64_t n_runs, int64_t n, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  const int64_t threads = (n + kMergeChunk - 1) / kMergeChunk;
-  k_merge_round<<<(unsigned)((threads + kMergeBlock - 1) / kMergeBlock), kMergeBlock, 0, st>>>(
+  k_merge_round<<<(unsigned)((n + kMergeTile - 1) / kMergeTile), kMergeThreads, 0, st>>>(
       K, idx_in, idx_out, rb, n_runs, n);
   return hipGetLastError();
 }
