@@ -53,6 +53,9 @@ struct tpg_workspace {
 
   // union on the device
   std::vector<uint64_t> union_uids;
+  // level count of the last one-pass run on this union (sizes the first batch)
+  std::vector<uint64_t> levels_uids;
+  int levels_last = 0;
   DevBuf g_csr;
   DGraph dg{};
 
@@ -354,7 +357,8 @@ tpg_status build_tree_onepass(tpg_workspace* ws, const HostUnion& U, hipStream_t
   std::vector<int64_t> cnt(kMaxLevels + 1, 0);
   cnt[1] = U.n;
   int L0 = 1;
-  int batch = 4;
+  // a union seen before: one batch covers its levels and the empty one after
+  int batch = (ws->levels_uids == U.uids && ws->levels_last > 0) ? ws->levels_last + 1 : 4;
   int Lmax = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
   for (;;) {
@@ -417,8 +421,10 @@ tpg_status build_tree_onepass(tpg_workspace* ws, const HostUnion& U, hipStream_t
       break;
     }
     L0 += len;
-    batch = std::min(batch * 2, 64);
+    batch = std::max(4, std::min(batch * 2, 64));
   }
+  ws->levels_uids = U.uids;
+  ws->levels_last = Lmax;
   R.count.assign(kMaxLevels, 0);
   R.off.assign(kMaxLevels, 0);
   R.Lmax = Lmax;

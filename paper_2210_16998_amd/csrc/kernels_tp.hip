@@ -315,51 +315,75 @@ hipError_t launch_tp_len(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n
 // k2 = e | split << 17 | pre(u) << 35
 constexpr uint64_t kM17 = (1ull << 17) - 1, kM18 = (1ull << 18) - 1, kM13 = (1ull << 13) - 1;
 
-// One wave per test path: lane l writes entries l, l + 64, ... (coalesced)
-// and checks at the same time whether its entry continues the tree path.
+// A workgroup splices kSplicePaths consecutive test paths: their layout goes
+// to LDS, then the threads write the paths' entries as one flat range (the
+// paths are contiguous in the output), and each entry that leaves the tree
+// path records its position; finally one thread per path builds its key.
+constexpr int kSplicePaths = 64;
+
+struct SpliceRow {
+  int64_t o0, p0, s0;  // prime-path entries, prefix table, suffix table
+  int32_t lp, lq, ls;  // prefix, prime-path and suffix lengths
+};
+
+__device__ __forceinline__ int splice_entry(const SpliceRow& r, const int32_t* pp_vtx,
+                                            const BfsOut& b, int64_t k) {
+  if (k < r.lp) return b.pfx[r.p0 + k];
+  if (k < r.lp + r.lq) return pp_vtx[r.o0 + (k - r.lp)];
+  return b.sfx[r.s0 + (k - r.lp - r.lq)];
+}
+
 __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, const int32_t* pp_vtx,
                                                      int64_t n_pp, BfsOut b, const int64_t* tp_off,
                                                      int32_t* tp_vtx, uint64_t* key, int32_t* idx) {
-  const int64_t i = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  if (i >= n_pp) return;
-  const int lane = lane_id();
-  const int64_t o0 = pp_off[i], o1 = pp_off[i + 1];
-  const int v1 = pp_vtx[o0], vk = pp_vtx[o1 - 1];
-  const int64_t p0 = b.pfx_off[v1], lp = b.pfx_off[v1 + 1] - p0;
-  const int64_t s0 = b.sfx_off[vk], ls = b.sfx_off[vk + 1] - s0;
-  const int64_t lq = o1 - o0;
-  const int64_t len = lp + lq + ls;
-  const int64_t w0 = tp_off[i];
-  int64_t first_off = len;  // first position that leaves the tree path
-  int wv = -1, ev = -1;     // the entries before and at that position
-  int carry = -1;           // entry kb - 1
-  for (int64_t kb = 0; kb < len; kb += 64) {
-    const int64_t k = kb + lane;
-    int x = -1;
-    if (k < len) {
-      if (k < lp) x = b.pfx[p0 + k];
-      else if (k < lp + lq) x = pp_vtx[o0 + (k - lp)];
-      else x = b.sfx[s0 + (k - lp - lq)];
-      tp_vtx[w0 + k] = x;
-    }
-    int prev = __shfl_up(x, 1, 64);
-    if (lane == 0) prev = carry;
-    const bool leaves = k < len && k > lp && b.parent[x] != prev;
-    const uint64_t bal = __ballot(leaves);
-    if (first_off == len && bal) {
-      const int fl = __builtin_ctzll(bal);
-      first_off = kb + fl;
-      ev = __shfl(x, fl, 64);
-      const int wb = __shfl(x, fl > 0 ? fl - 1 : 0, 64);
-      wv = fl > 0 ? wb : carry;
-    }
-    const int last = (int)((len - 1 - kb) < 63 ? (len - 1 - kb) : 63);
-    carry = __shfl(x, last, 64);
+  __shared__ SpliceRow s_row[kSplicePaths];
+  __shared__ int64_t s_w[kSplicePaths + 1];
+  __shared__ int32_t s_first[kSplicePaths];
+  const int tid = (int)threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * kSplicePaths;
+  const int cnt = (int)(n_pp - i0 < kSplicePaths ? n_pp - i0 : kSplicePaths);
+  if (tid < cnt) {
+    const int64_t i = i0 + tid;
+    const int64_t o0 = pp_off[i], o1 = pp_off[i + 1];
+    const int v1 = pp_vtx[o0], vk = pp_vtx[o1 - 1];
+    SpliceRow r;
+    r.o0 = o0;
+    r.p0 = b.pfx_off[v1];
+    r.lp = (int32_t)(b.pfx_off[v1 + 1] - r.p0);
+    r.lq = (int32_t)(o1 - o0);
+    r.s0 = b.sfx_off[vk];
+    r.ls = (int32_t)(b.sfx_off[vk + 1] - r.s0);
+    s_row[tid] = r;
+    s_w[tid] = tp_off[i];
+    s_first[tid] = r.lp + r.lq + r.ls;
+    idx[i] = (int32_t)i;
   }
-  if (lane == 0) {
-    const bool has_e = first_off < len;
-    const int w = has_e ? wv : carry;  // the whole path follows the tree: w = last entry
-    const int64_t D = first_off - 1;
+  if (tid == cnt) s_w[cnt] = tp_off[i0 + cnt];
+  __syncthreads();
+  const int64_t e0 = s_w[0], ne = s_w[cnt] - e0;
+  for (int64_t e = tid; e < ne; e += kBlock) {
+    const int64_t pos = e0 + e;
+    int lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_w[mid] <= pos) lo = mid; else hi = mid - 1;
+    }
+    const SpliceRow r = s_row[lo];
+    const int64_t k = pos - s_w[lo];
+    const int x = splice_entry(r, pp_vtx, b, k);
+    tp_vtx[pos] = x;
+    if (k > r.lp && b.parent[x] != splice_entry(r, pp_vtx, b, k - 1))
+      atomicMin(&s_first[lo], (int32_t)k);
+  }
+  __syncthreads();
+  if (tid < cnt) {
+    const int64_t i = i0 + tid;
+    const SpliceRow r = s_row[tid];
+    const int len = r.lp + r.lq + r.ls;
+    const int first = s_first[tid];
+    const bool has_e = first < len;
+    const int w = splice_entry(r, pp_vtx, b, first - 1);
+    const int ev = has_e ? splice_entry(r, pp_vtx, b, first) : 0;
     const uint32_t prew = (uint32_t)b.pre[w], pendw = (uint32_t)b.pend[w];
     uint32_t split;
     if (has_e) {
@@ -375,11 +399,11 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
     } else {
       split = prew + 1;
     }
-    key[2 * i] = (uint64_t)prew | ((uint64_t)pendw << 18) | ((uint64_t)D << 36) |
+    const int v1 = splice_entry(r, pp_vtx, b, r.lp);
+    key[2 * i] = (uint64_t)prew | ((uint64_t)pendw << 18) | ((uint64_t)(first - 1) << 36) |
                  ((uint64_t)(has_e ? 1 : 0) << 49);
-    key[2 * i + 1] = (uint64_t)(has_e ? ev : 0) | ((uint64_t)split << 17) |
+    key[2 * i + 1] = (uint64_t)(uint32_t)ev | ((uint64_t)split << 17) |
                      ((uint64_t)(uint32_t)b.pre[v1] << 35);
-    idx[i] = (int32_t)i;
   }
 }
 
@@ -387,9 +411,8 @@ hipError_t launch_tp_write(const int64_t* pp_off, const int32_t* pp_vtx, int64_t
                            const BfsOut& b, const int64_t* tp_off, int32_t* tp_vtx,
                            uint64_t* key, int32_t* idx, hipStream_t st) {
   if (n_pp == 0) return hipSuccess;
-  const int64_t per = kBlock / 64;
-  k_tp_write<<<(unsigned)((n_pp + per - 1) / per), kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, b,
-                                                                    tp_off, tp_vtx, key, idx);
+  k_tp_write<<<(unsigned)((n_pp + kSplicePaths - 1) / kSplicePaths), kBlock, 0, st>>>(
+      pp_off, pp_vtx, n_pp, b, tp_off, tp_vtx, key, idx);
   return hipGetLastError();
 }
 
@@ -603,23 +626,48 @@ hipError_t launch_dedup_flags(const TpOrder& K, const int32_t* idx, int64_t n, i
   return hipGetLastError();
 }
 
-// One wave per sorted test path; kept ones are copied to their final place.
+// A workgroup copies the kept paths among kSplicePaths consecutive sorted
+// positions: their sources, destinations and lengths go to LDS, then the
+// threads copy the entries as one flat range (kept paths are contiguous in
+// the output).
 __global__ __launch_bounds__(kBlock) void k_gather(const int64_t* off, const int32_t* vtx,
                                                    const int32_t* idx, int64_t n,
                                                    const int64_t* keep_pos,
                                                    const int64_t* keep_voff,
                                                    const int64_t* keep_len, int64_t* out_off,
                                                    int32_t* out_vtx) {
-  const int64_t k = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  if (k >= n) return;
-  if (keep_len[k] == 0) return;  // duplicate (every kept path has >= 1 entry)
-  const int lane = lane_id();
-  const int64_t a = idx[k];
-  const int64_t o = keep_voff[k];
-  if (lane == 0) out_off[keep_pos[k]] = o;
-  const int64_t l = off[a + 1] - off[a];
-  const int32_t* src = vtx + off[a];
-  for (int64_t q = lane; q < l; q += 64) out_vtx[o + q] = src[q];
+  __shared__ int64_t s_src[kSplicePaths];
+  __shared__ int64_t s_cum[kSplicePaths + 1];
+  __shared__ int64_t s_dst0;
+  __shared__ int32_t s_w[kBlock / 64];
+  const int tid = (int)threadIdx.x;
+  const int64_t k0 = (int64_t)blockIdx.x * kSplicePaths;
+  const int cnt = (int)(n - k0 < kSplicePaths ? n - k0 : kSplicePaths);
+  int64_t len = 0;
+  if (tid < cnt) {
+    const int64_t k = k0 + tid;
+    len = keep_len[k];  // 0 for a duplicate (every kept path has >= 1 entry)
+    if (len) {
+      const int64_t a = idx[k];
+      s_src[tid] = off[a];
+      out_off[keep_pos[k]] = keep_voff[k];
+    }
+  }
+  if (tid == 0) s_dst0 = keep_voff[k0];
+  int32_t tot;
+  const int32_t ex = block_excl_scan<kBlock, int32_t>((int32_t)len, tot, s_w);
+  if (tid < cnt) s_cum[tid] = ex;
+  if (tid == 0) s_cum[cnt] = tot;
+  __syncthreads();
+  const int64_t d0 = s_dst0;
+  for (int64_t e = tid; e < tot; e += kBlock) {
+    int lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_cum[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    out_vtx[d0 + e] = vtx[s_src[lo] + (e - s_cum[lo])];
+  }
 }
 
 hipError_t launch_gather(const int64_t* tp_off, const int32_t* tp_vtx, const int32_t* idx,
@@ -627,8 +675,7 @@ hipError_t launch_gather(const int64_t* tp_off, const int32_t* tp_vtx, const int
                          const int64_t* keep_len, int64_t* out_off, int32_t* out_vtx,
                          hipStream_t st) {
   if (n == 0) return hipSuccess;
-  const int64_t per = kBlock / 64;
-  k_gather<<<(unsigned)((n + per - 1) / per), kBlock, 0, st>>>(
+  k_gather<<<(unsigned)((n + kSplicePaths - 1) / kSplicePaths), kBlock, 0, st>>>(
       tp_off, tp_vtx, idx, n, keep_pos, keep_voff, keep_len, out_off, out_vtx);
   return hipGetLastError();
 }
