@@ -46,10 +46,29 @@ def _kernel_name(W: int, tuning) -> str:
     return f"k_extend_lb<{W}, {items}>"
 
 
-def _measured_traffic(kernel: str):
+def _copy_peak(stream, mib: int = 4096, reps: int = 10) -> float:
+    """Achievable HBM bandwidth of a plain device-to-device copy (GB/s,
+    bytes read + written), the second denominator beside the published peak."""
+    import torch
+    with torch.cuda.stream(stream):
+        src = torch.ones(mib << 18, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        best = float("inf")
+        for _ in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            dst.copy_(src)
+            e1.record(stream)
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    return 2.0 * (mib << 20) / (best * 1e-3) / 1e9
+
+
+def _measured_traffic(kernel: str, summary: str = "k_extend_cfg209_hbm_traffic.md"):
     """HBM bytes per launch from the committed counter summary, if it was
     taken on this same kernel (else None)."""
-    path = os.path.join(ROOT, "profiles", "k_extend_cfg209_hbm_traffic.md")
+    path = os.path.join(ROOT, "profiles", summary)
     try:
         for line in open(path):
             line = line.strip()
@@ -69,7 +88,7 @@ def _bytes_per_extension(n: int) -> int:
     return 16 + 2 * 8 * ((n + 63) // 64)
 
 
-def _stress(args):
+def _stress(args, copy_gbs: float):
     """The 400-vertex stress CFG: one-pass prime paths (device output), with
     the extension kernel's roofline measured on its ~4.7e8 extensions."""
     import torch
@@ -104,6 +123,9 @@ def _stress(args):
             "device_bytes": st["device_bytes"], "pool_cap_bytes": cap,
             "roofline": {"bound": "hbm", "kernel": kname, "achieved": ach,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                         "traffic": _measured_traffic(kname, "k_extend_stress400_hbm_traffic.md"),
+                         "copy_GBps": copy_gbs, "frac_of_copy": ach / copy_gbs,
+                         "algorithmic_bytes_per_launch": per_launch,
                          "bytes_per_extension": bpe, "launches_per_run": st["n_extend_launches"],
                          "avg_launch_ms": avg}}
 
@@ -120,9 +142,18 @@ def _cpu_baseline(g, reps: int):
         tp, _ = oracle.test_paths(g, pp)
         n_pp += len(pp)
     dt = time.perf_counter() - t0
+    # one core, on the start vertices 0 .. n/8 (a bounded sample)
+    hi = max(1, g.n // 8)
+    t1 = time.perf_counter()
+    pp1, _ = oracle.prime_paths_local(g, 0, hi, nthreads=1)
+    oracle.test_paths(g, pp1)
+    dt1 = time.perf_counter() - t1
     return {"value": n_pp / dt, "unit": "prime paths/s", "cores": threads, "kind": "oracle",
             "sample": f"whole workload x{reps}: DFS from all {g.n} vertices with the local "
-                      f"prime test, then test-path splice/sort/dedup; {dt:.1f} s total"}
+                      f"prime test, then test-path splice/sort/dedup; {dt:.1f} s total",
+            "one_core": {"value": len(pp1) / dt1, "unit": "prime paths/s", "cores": 1,
+                         "sample": f"start vertices 0..{hi - 1} ({len(pp1)} prime paths), same "
+                                   f"steps; {dt1:.1f} s"}}
 
 
 def main() -> int:
@@ -207,6 +238,7 @@ def main() -> int:
     while W * 64 < g.n:
         W *= 2
     kname = _kernel_name(W, tpg.get_tuning(ws))
+    copy_gbs = _copy_peak(stream)
 
     out = {
         "metric": METRIC,
@@ -237,13 +269,14 @@ def main() -> int:
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": _measured_traffic(kname),
+                     "copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs,
                      "algorithmic_bytes_per_launch": n_ext * bytes_per_ext / max(1, st["n_extend_launches"]),
                      "bytes_per_extension": bytes_per_ext,
                      "launches_per_step": st["n_extend_launches"],
                      "avg_launch_ms": avg_launch_ms},
     }
     if not args.no_stress:
-        out["stress"] = _stress(args)
+        out["stress"] = _stress(args, copy_gbs)
     if not args.no_batch:
         out["batched"] = _batched(args)
     if not args.no_cpu:

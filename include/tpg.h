@@ -229,14 +229,15 @@ void tpg_batch_result_free(tpg_batch_result* r);
 /* ------------------------------------------------------------------------
  * Launch-shape tuning of the frontier-extension kernel.
  *
- * Per visited-set width W = 2^i words (index i = 0..6): the most parents per
+ * Per visited-set width W = 2^i words (index i = 0..6; W is the register
+ * width, ceil(V / 64) rounded up to a power of two): the most parents per
  * thread (1, 2, 4 or 8; a tile is threads * items parents and claims its
  * slice of the next level with one device-scope atomic), persistent
  * workgroups per compute unit (1..32) and the kernel variant (0: load-
  * balanced tiles of 256 threads staged in LDS; 1 / 2: thread-per-parent with
- * visited sets in registers, 256 / 1024 threads).  Defaults come from a
- * sweep on MI355X (for W = 4: variant 2, 2 items, 2 workgroups; W = 8:
- * variant 1, 4 items, 8 workgroups).  tpg_autotune times every combination on the given
+ * visited sets in registers, 256 / 1024 threads).  Defaults come from sweeps
+ * on MI355X (W = 4: variant 2, 1 item, 2 workgroups; W = 8: variant 1,
+ * 4 items, 8 workgroups).  tpg_autotune times every combination on the given
  * graphs (grouped by width as in the batched form), keeps the fastest per
  * width in the workspace (opts->ws, required) and returns the table; results
  * never depend on the tuning.

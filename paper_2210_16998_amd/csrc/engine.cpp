@@ -25,7 +25,8 @@ struct OutSet {
 
 // A disjoint union of CFGs laid out as one graph (host side).
 struct HostUnion {
-  int32_t n = 0, n_comp = 0, W = 1;
+  int32_t n = 0, n_comp = 0, W = 1;  // W: visited-set words in registers (power of two)
+  int32_t Wu = 1;                     // words stored per visited set: ceil(largest component / 64)
   std::vector<int32_t> sp{0}, s, pp{0}, p, loc, comp, cbase{0}, centry, cexit;
   std::vector<uint64_t> uids;
 };
@@ -95,12 +96,11 @@ struct tpg_workspace {
   int graph_W = 0, graph_grid = 0, graph_items = 0, graph_variant = 0;
   hipStream_t graph_stream = nullptr;
 
-  // extension-kernel launch shape per visited-set width (index log2 W):
-  // parents per thread (tile = 256 * items) and persistent workgroups per CU
-  // parents per thread (tile = 256 * items; one output claim per tile) and
-  // persistent workgroups per CU, per visited-set width
-  // defaults from a sweep on MI355X (index = log2 of the visited-set width)
-  int tune_items[7] = {2, 2, 2, 4, 2, 1, 1};
+  // extension-kernel launch shape per visited-set width (index = log2 of the
+  // register width W): parents per thread (tile = threads * items, one output
+  // claim per tile), persistent workgroups per CU and kernel variant;
+  // defaults from sweeps on MI355X
+  int tune_items[7] = {2, 1, 1, 4, 2, 1, 1};
   int tune_wgs[7] = {2, 2, 2, 8, 2, 2, 4};
   int tune_variant[7] = {2, 2, 2, 1, 2, 2, 0};
   double tune_ms[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -165,6 +165,7 @@ void add_component(HostUnion& U, const tpg_graph* g) {
   U.cbase.push_back(U.n);
   U.n_comp += 1;
   U.W = std::max(U.W, pow2_words(g->n));
+  U.Wu = std::max(U.Wu, (g->n + 63) / 64);
   U.uids.push_back(g->uid);
 }
 
@@ -201,6 +202,7 @@ tpg_status upload_union(tpg_workspace* ws, const HostUnion& U, hipStream_t st) {
   return TPG_OK;
 }
 
+// W here: words stored per visited set.
 tpg_status reserve_tree(tpg_workspace* ws, int64_t rec, int64_t msk, int W, hipStream_t st,
                         int64_t keep_rec, int keep_parity, int64_t keep_mask) {
   if (rec > (int64_t)INT32_MAX - 2)
@@ -213,11 +215,38 @@ tpg_status reserve_tree(tpg_workspace* ws, int64_t rec, int64_t msk, int W, hipS
   ws->rec_cap = std::min<int64_t>(ws->par.cap / sizeof(int32_t), ws->cstart.cap / sizeof(int32_t) - 1);
   ws->rec_cap = std::min<int64_t>(ws->rec_cap, ws->info.cap / sizeof(uint32_t));
   ws->rec_cap = std::min<int64_t>(ws->rec_cap, (int64_t)ws->nch.cap);
-  const size_t mb = sizeof(uint64_t) * (size_t)msk * W;
-  TPG_TRY(ws_reserve(ws, ws->mask0, mb, keep_parity == 0 && keep_mask > 0, st,
-                     sizeof(uint64_t) * (size_t)keep_mask * W));
-  TPG_TRY(ws_reserve(ws, ws->mask1, mb, keep_parity == 1 && keep_mask > 0, st,
-                     sizeof(uint64_t) * (size_t)keep_mask * W));
+  // Visited sets are word-major (word q of slot j at q * mask_cap + j), so the
+  // stride is the capacity: both buffers always have the same size, and the
+  // kept level is copied to the new stride when they grow.
+  const size_t need = sizeof(uint64_t) * (size_t)msk * W;
+  if (ws->mask0.cap < need || ws->mask1.cap < need) {
+    size_t want = std::max(need, std::max(ws->mask0.cap, ws->mask1.cap) * 3 / 2);
+    want = (want + 255) & ~(size_t)255;
+    const bool keep = keep_mask > 0 && keep_parity >= 0 && ws->mask_words == W;
+    DevBuf& kb = keep_parity == 1 ? ws->mask1 : ws->mask0;
+    DevBuf& ob = keep_parity == 1 ? ws->mask0 : ws->mask1;
+    ws_release(ws, ob);
+    TPG_TRY(ws_reserve(ws, ob, want));
+    if (keep) {
+      DevBuf nb;
+      // the old buffer is freed right after the copy, as in a plain regrow
+      const uint64_t cap_save = ws->cap;
+      if (ws->cap) ws->cap += kb.cap;
+      const tpg_status rc = ws_reserve(ws, nb, want);
+      ws->cap = cap_save;
+      TPG_TRY(rc);
+      const size_t S_old = sizeof(uint64_t) * (size_t)ws->mask_cap;
+      const size_t S_new = sizeof(uint64_t) * (want / (sizeof(uint64_t) * W));
+      TPG_HIP(hipMemcpy2DAsync(nb.p, S_new, kb.p, S_old, sizeof(uint64_t) * (size_t)keep_mask, W,
+                               hipMemcpyDeviceToDevice, st));
+      TPG_HIP(hipStreamSynchronize(st));
+      ws_release(ws, kb);
+      kb = nb;
+    } else {
+      ws_release(ws, kb);
+      TPG_TRY(ws_reserve(ws, kb, want));
+    }
+  }
   ws->mask_cap = (int64_t)(std::min(ws->mask0.cap, ws->mask1.cap) / (sizeof(uint64_t) * W));
   TPG_TRY(ws_reserve(ws, ws->ls, sizeof(LevelState)));
   ws->mask_words = W;
@@ -344,8 +373,8 @@ tpg_status build_tree_onepass(tpg_workspace* ws, const HostUnion& U, hipStream_t
   int64_t rec = std::max<int64_t>({ws->rec_cap, (int64_t)U.n * 64 + 4096, rec0});
   int64_t msk = std::max<int64_t>((int64_t)U.n * 16 + 1024, msk0);
   if (ws->mask_words && ws->mask_cap)
-    msk = std::max<int64_t>(msk, ws->mask_cap * ws->mask_words / W);
-  TPG_TRY(reserve_tree(ws, rec, msk, W, st, 0, -1, 0));
+    msk = std::max<int64_t>(msk, ws->mask_cap * ws->mask_words / U.Wu);
+  TPG_TRY(reserve_tree(ws, rec, msk, U.Wu, st, 0, -1, 0));
   int wi = 0;
   while ((1 << wi) < W) ++wi;
   const int items = ws->tune_items[wi];
@@ -403,7 +432,7 @@ tpg_status build_tree_onepass(tpg_workspace* ws, const HostUnion& U, hipStream_t
       const int64_t need_rec = base + F + nxt + 1;
       const int64_t new_rec = std::max<int64_t>(ws->rec_cap, need_rec + need_rec / 4);
       const int64_t new_msk = std::max<int64_t>(ws->mask_cap, nxt + nxt / 4 + 1024);
-      TPG_TRY(reserve_tree(ws, new_rec, new_msk, W, st, base + F, Lo & 1, F));
+      TPG_TRY(reserve_tree(ws, new_rec, new_msk, U.Wu, st, base + F, Lo & 1, F));
       a = make_args(ws, grid);
       TPG_HIP(launch_resume_fix(a, Lo, st));
       R.n_overflows += 1;
@@ -446,8 +475,8 @@ tpg_status build_tree_twopass(tpg_workspace* ws, const HostUnion& U, hipStream_t
   int64_t rec = std::max<int64_t>(ws->rec_cap, (int64_t)U.n + 4096);
   int64_t msk = (int64_t)U.n + 1024;
   if (ws->mask_words && ws->mask_cap)
-    msk = std::max<int64_t>(msk, ws->mask_cap * ws->mask_words / W);
-  TPG_TRY(reserve_tree(ws, rec, msk, W, st, 0, -1, 0));
+    msk = std::max<int64_t>(msk, ws->mask_cap * ws->mask_words / U.Wu);
+  TPG_TRY(reserve_tree(ws, rec, msk, U.Wu, st, 0, -1, 0));
   ExtArgs a = make_args(ws);
   TPG_HIP(launch_seed(a, st));
   R.count.assign(kMaxLevels, 0);
@@ -475,7 +504,7 @@ tpg_status build_tree_twopass(tpg_workspace* ws, const HostUnion& U, hipStream_t
     if (base + F + total + 1 > ws->rec_cap || total > ws->mask_cap) {
       const int64_t need = base + F + total + 1;
       TPG_TRY(reserve_tree(ws, std::max<int64_t>(ws->rec_cap, need + need / 2),
-                           std::max<int64_t>(ws->mask_cap, total + total / 2), W, st, base + F + 1,
+                           std::max<int64_t>(ws->mask_cap, total + total / 2), U.Wu, st, base + F + 1,
                            L & 1, F));
       a = make_args(ws);
     }

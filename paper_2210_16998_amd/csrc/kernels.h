@@ -35,7 +35,7 @@ struct TreeBufs {
   uint64_t* mask[2];  // frontier visited sets, ping-pong by level parity [mask_cap * W]
   int64_t rec_cap;
   int64_t mask_cap;
-  int32_t mask_words;  // W: words per visited set (a power of two)
+  int32_t mask_words;  // words stored per visited set (<= the kernel width W)
   int32_t pad;
 };
 

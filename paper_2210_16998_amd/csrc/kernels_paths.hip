@@ -19,7 +19,10 @@
 //    order, and each node records where its children start and how many
 //    there are.
 //  * The visited set of a frontier path lives as a bitmask of W 64-bit words
-//    (registers while testing, HBM between levels, two levels alive).
+//    (registers while testing, HBM between levels, two levels alive).  In
+//    HBM the sets are stored word-major: word q of slot j sits at
+//    q * stride + j, so the threads of a wave, which own consecutive slots,
+//    read and write consecutive words.
 //  * One workgroup handles a tile of 256 * ITEMS parents: choice masks over
 //    successor slots, a block scan of child counts, then ONE device-scope
 //    atomic claim of the tile's slice of the next level, then a
@@ -66,9 +69,9 @@ __global__ void k_seed(ExtArgs a) {
   // masks of level 1 (parity 1): one bit each, at the vertex's local id
   const int W = a.t.mask_words;
   for (int64_t k = i; k < (int64_t)n * W; k += (int64_t)gridDim.x * blockDim.x) {
-    const int v = (int)(k / W), q = (int)(k % W);
+    const int q = (int)(k / n), v = (int)(k % n);
     const int l = a.g.loc[v];
-    a.t.mask[1][k] = (q == (l >> 6)) ? (1ull << (l & 63)) : 0ull;
+    a.t.mask[1][(int64_t)q * a.t.mask_cap + v] = (q == (l >> 6)) ? (1ull << (l & 63)) : 0ull;
   }
 }
 
@@ -124,37 +127,25 @@ __device__ __forceinline__ bool all_preds_on(const DGraph& g, int base, int v1l,
   return true;
 }
 
+// Visited set of slot j of a level (word-major, stride S slots).  Only the
+// first Wu words are stored (ceil(largest component / 64)); the register
+// copy is padded with zero words up to W.
 template <int W>
-__device__ __forceinline__ void load_mask(const uint64_t* src, uint64_t (&m)[W]) {
-  if constexpr (W == 1) {
-    m[0] = src[0];
-  } else {
-    const ulonglong2* s2 = reinterpret_cast<const ulonglong2*>(src);
+__device__ __forceinline__ void load_mask(const uint64_t* src, int64_t S, int Wu, int64_t j,
+                                          uint64_t (&m)[W]) {
 #pragma unroll
-    for (int k = 0; k < W / 2; ++k) {
-      const ulonglong2 x = s2[k];
-      m[2 * k] = x.x;
-      m[2 * k + 1] = x.y;
-    }
-  }
+  for (int q = 0; q < W; ++q) m[q] = q < Wu ? src[q * S + j] : 0ull;
 }
 
+// Visited set of child slot c: the parent's set plus local vertex w.
 template <int W>
-__device__ __forceinline__ void store_child_mask(uint64_t* dst, const uint64_t (&m)[W], int w) {
+__device__ __forceinline__ void store_child_mask(uint64_t* dst, int64_t S, int Wu, int64_t c,
+                                                 const uint64_t (&m)[W], int w) {
   const int q = w >> 6;
   const uint64_t bit = 1ull << (w & 63);
-  if constexpr (W == 1) {
-    dst[0] = m[0] | bit;
-  } else {
-    ulonglong2* d2 = reinterpret_cast<ulonglong2*>(dst);
 #pragma unroll
-    for (int k = 0; k < W / 2; ++k) {
-      ulonglong2 x;
-      x.x = m[2 * k] | ((2 * k == q) ? bit : 0ull);
-      x.y = m[2 * k + 1] | ((2 * k + 1 == q) ? bit : 0ull);
-      d2[k] = x;
-    }
-  }
+  for (int k = 0; k < W; ++k)
+    if (k < Wu) dst[k * S + c] = m[k] | (k == q ? bit : 0ull);
 }
 
 // ---------------------------------------------------------------------------
@@ -175,7 +166,7 @@ __device__ __forceinline__ void store_child_mask(uint64_t* dst, const uint64_t (
 // item, in thread order, so a wave's stores land on neighbouring slots.  A
 // level that fits one tile stores its size instead of claiming.
 template <int W, int ITEMS, int NT>
-__global__ __launch_bounds__(NT) void k_extend_tp(ExtArgs a, int li) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 1024 && ITEMS == 1 && W <= 8 ? 8 : 1))) void k_extend_tp(ExtArgs a, int li) {
   constexpr int NW = NT / 64;
   __shared__ int32_t s_tot[ITEMS][NW];
   __shared__ int64_t s_prefix;
@@ -219,7 +210,7 @@ __global__ __launch_bounds__(NT) void k_extend_tp(ExtArgs a, int li) {
       const int64_t j = tb + i * NT + tid;
       const bool ok = i < ir && j < F;
       inf[i] = ok ? a.t.info[base + j] : F_CYC;
-      load_mask<W>(mcur + (ok ? j : 0) * W, m[i]);
+      load_mask<W>(mcur, a.t.mask_cap, a.t.mask_words, ok ? j : 0, m[i]);
     }
     // choice masks and the terminal filter
     uint64_t vm[ITEMS];
@@ -294,7 +285,8 @@ __global__ __launch_bounds__(NT) void k_extend_tp(ExtArgs a, int li) {
             a.t.par[cg] = (int32_t)(base + j);
             a.t.info[cg] = make_info(w, v1l, wl == v1l ? F_CYC : 0u);
           }
-          if (wl != v1l && cl < a.t.mask_cap) store_child_mask<W>(mnxt + cl * W, m[i], wl);
+          if (wl != v1l && cl < a.t.mask_cap)
+            store_child_mask<W>(mnxt, a.t.mask_cap, a.t.mask_words, cl, m[i], wl);
           ++cl;
         }
       }
@@ -368,7 +360,7 @@ __global__ __launch_bounds__(kBlock) void k_extend_lb(ExtArgs a, int li) {
           const int v = node_v(in);
           const int cb = v - a.g.loc[v];
           k0 = a.g.sp[v];
-          load_mask<W>(mcur + j * W, m);
+          load_mask<W>(mcur, a.t.mask_cap, a.t.mask_words, j, m);
           vm = choices<W>(a.g, in, m, k0, a.g.sp[v + 1], cb);
           if (vm == 0) {
             const bool pp = all_preds_on<W>(a.g, cb, node_v1l(in), m);
@@ -442,9 +434,9 @@ __global__ __launch_bounds__(kBlock) void k_extend_lb(ExtArgs a, int li) {
 #pragma unroll
           for (int q = 0; q < W; ++q) pm[q] = s_mask[o * W + q];
         } else {
-          load_mask<W>(mcur + (tb + o) * W, pm);
+          load_mask<W>(mcur, a.t.mask_cap, a.t.mask_words, tb + o, pm);
         }
-        store_child_mask<W>(mnxt + cl * W, pm, wl);
+        store_child_mask<W>(mnxt, a.t.mask_cap, a.t.mask_words, cl, pm, wl);
       }
     }
     __syncthreads();
@@ -517,7 +509,7 @@ __global__ __launch_bounds__(kBlock) void k_count(ExtArgs a, int L, int64_t base
   int cnt = 0;
   if (!(inf & F_CYC)) {
     uint64_t m[W];
-    load_mask<W>(a.t.mask[L & 1] + j * W, m);
+    load_mask<W>(a.t.mask[L & 1], a.t.mask_cap, a.t.mask_words, j, m);
     const int v = node_v(inf);
     const int cb = v - a.g.loc[v];
     const uint64_t vm = choices<W>(a.g, inf, m, a.g.sp[v], a.g.sp[v + 1], cb);
@@ -538,7 +530,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(ExtArgs a, int L, int64_t base,
   const uint32_t inf = a.t.info[base + j];
   if (inf & F_CYC) return;
   uint64_t m[W];
-  load_mask<W>(a.t.mask[L & 1] + j * W, m);
+  load_mask<W>(a.t.mask[L & 1], a.t.mask_cap, a.t.mask_words, j, m);
   const int v = node_v(inf);
   const int k0 = a.g.sp[v];
   const int cb = v - a.g.loc[v];
@@ -554,7 +546,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(ExtArgs a, int L, int64_t base,
     const int wl = w - cb;
     a.t.par[c] = (int32_t)(base + j);
     a.t.info[c] = make_info(w, v1l, wl == v1l ? F_CYC : 0u);
-    if (wl != v1l) store_child_mask<W>(mnxt + (c - nbase) * W, m, wl);
+    if (wl != v1l) store_child_mask<W>(mnxt, a.t.mask_cap, a.t.mask_words, c - nbase, m, wl);
     ++c;
   }
 }
