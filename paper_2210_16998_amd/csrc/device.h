@@ -41,7 +41,13 @@ struct DGraph {
   const int32_t* centry;// [n_comp] entry (graph-wide id)
   const int32_t* cexit; // [n_comp] exit (graph-wide id)
   int32_t n, n_comp;
+  // sp, s, pp, p and loc lie back to back in one buffer starting at sp:
+  // int32 words from sp through the end of loc (what a kernel stages in LDS)
+  int32_t n_stage;
 };
+
+// Largest CSR (sp .. loc, bytes) that the extension kernel stages in LDS.
+constexpr int kGraphLdsBytes = 16384;
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 

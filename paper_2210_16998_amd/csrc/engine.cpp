@@ -92,6 +92,13 @@ struct tpg_workspace {
     hipGraphExec_t exec = nullptr;
   };
   std::vector<LevelGraph> level_graphs;
+  // captured launch sequences keyed by every argument they were captured with
+  // (the ranking sweeps): replayed only when a call repeats them exactly
+  struct SeqGraph {
+    std::vector<uint8_t> key;
+    hipGraphExec_t exec = nullptr;
+  };
+  SeqGraph rank_up, rank_down;
   ExtArgs graph_args{};
   int graph_W = 0, graph_grid = 0, graph_items = 0, graph_variant = 0;
   hipStream_t graph_stream = nullptr;
@@ -195,6 +202,7 @@ tpg_status upload_union(tpg_workspace* ws, const HostUnion& U, hipStream_t st) {
   d.cexit = put(U.cexit, 0);
   d.n = U.n;
   d.n_comp = U.n_comp;
+  d.n_stage = (int32_t)(d.comp - d.sp);
   TPG_HIP(err);
   TPG_HIP(hipStreamSynchronize(st));
   ws->dg = d;
@@ -319,6 +327,54 @@ void drop_level_graphs(tpg_workspace* ws) {
   for (auto& lg : ws->level_graphs)
     if (lg.exec) (void)hipGraphExecDestroy(lg.exec);
   ws->level_graphs.clear();
+}
+
+void drop_seq_graph(tpg_workspace::SeqGraph& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  g.exec = nullptr;
+  g.key.clear();
+}
+
+template <class T>
+void key_add(std::vector<uint8_t>& k, const T& v) {
+  const uint8_t* p = reinterpret_cast<const uint8_t*>(&v);
+  k.insert(k.end(), p, p + sizeof(T));
+}
+
+// A sequence of short launches (one per level) is issued directly the first
+// time; when the next call repeats it with the same arguments it is captured
+// once and from then on replayed as one graph, which removes the host's
+// per-launch gap between short kernels.
+template <class F>
+tpg_status run_seq(tpg_workspace::SeqGraph& g, std::vector<uint8_t>&& key, hipStream_t st,
+                   F&& launches) {
+  if (key != g.key) {
+    drop_seq_graph(g);
+    g.key = std::move(key);
+    TPG_HIP(launches());
+    return TPG_OK;
+  }
+  if (!g.exec) {
+    hipGraph_t graph = nullptr;
+    TPG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const hipError_t e = launches();
+    const hipError_t e2 = hipStreamEndCapture(st, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      g.key.clear();
+      return fail(TPG_ERR_DEVICE, "capture of a launch sequence failed: %s",
+                  hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    const hipError_t e3 = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) {
+      g.exec = nullptr;
+      g.key.clear();
+      TPG_HIP(e3);
+    }
+  }
+  TPG_HIP(hipGraphLaunch(g.exec, st));
+  return TPG_OK;
 }
 
 // `len` extension launches (launch li extends level batch_start + li),
@@ -539,10 +595,26 @@ tpg_status rank_and_materialize(tpg_workspace* ws, const HostUnion& U, hipStream
   TPG_TRY(ws_reserve(ws, ws->totals, sizeof(int64_t) * 4));
   TPG_TRY(ws_reserve(ws, ws->cycles, sizeof(uint64_t) * 2));
   uint32_t* sc = ws->sub_cnt.as<uint32_t>();
-  TPG_HIP(launch_zero_u64(ws->cycles.as<uint64_t>(), 1, st));
-  for (int L = R.Lmax; L >= 1; --L)
-    TPG_HIP(launch_up(a, L, R.off[L], R.count[L], sc, ws->cycles.as<unsigned long long>(), st));
-  TPG_HIP(launch_roots(a, U.n, sc, nullptr, nullptr, ws->totals.as<int64_t>(), 0, st));
+  // the levels' ranges and every buffer the sweeps touch key their graphs
+  std::vector<uint8_t> key;
+  key_add(key, a);
+  key_add(key, sc);
+  key_add(key, ws->cycles.p);
+  key_add(key, ws->totals.p);
+  key_add(key, U.n);
+  key_add(key, R.Lmax);
+  for (int L = 1; L <= R.Lmax; ++L) {
+    key_add(key, R.off[L]);
+    key_add(key, R.count[L]);
+  }
+  std::vector<uint8_t> key_down = key;
+  TPG_TRY(run_seq(ws->rank_up, std::move(key), st, [&]() -> hipError_t {
+    hipError_t e = launch_zero_u64(ws->cycles.as<uint64_t>(), 1, st);
+    for (int L = R.Lmax; L >= 1 && e == hipSuccess; --L)
+      e = launch_up(a, L, R.off[L], R.count[L], sc, ws->cycles.as<unsigned long long>(), st);
+    if (e == hipSuccess) e = launch_roots(a, U.n, sc, nullptr, nullptr, ws->totals.as<int64_t>(), 0, st);
+    return e;
+  }));
   TPG_HIP(hipMemcpyAsync(ws->h_scalars, ws->totals.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TPG_HIP(hipMemcpyAsync(ws->h_scalars + 2, ws->cycles.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TPG_HIP(hipStreamSynchronize(st));
@@ -555,9 +627,14 @@ tpg_status rank_and_materialize(tpg_workspace* ws, const HostUnion& U, hipStream
   TPG_TRY(reserve_scan(ws, P.n_pp));
   int64_t* lbr = ws->leaf_by_rank.as<int64_t>();
   int32_t* len = ws->pp_len.as<int32_t>();
-  TPG_HIP(launch_roots(a, U.n, sc, lbr, len, ws->totals.as<int64_t>(), 1, st));
-  for (int L = 1; L < R.Lmax; ++L)
-    TPG_HIP(launch_down(a, L, R.off[L], R.count[L], sc, lbr, len, st));
+  key_add(key_down, lbr);
+  key_add(key_down, len);
+  TPG_TRY(run_seq(ws->rank_down, std::move(key_down), st, [&]() -> hipError_t {
+    hipError_t e = launch_roots(a, U.n, sc, lbr, len, ws->totals.as<int64_t>(), 1, st);
+    for (int L = 1; L < R.Lmax && e == hipSuccess; ++L)
+      e = launch_down(a, L, R.off[L], R.count[L], sc, lbr, len, st);
+    return e;
+  }));
   // offsets of the prime paths: a scan of their lengths
   int64_t* scal = ws->scalars.as<int64_t>();
   TPG_HIP(scan_i32_to_i64(len, o.pp_off.as<int64_t>(), P.n_pp, 0, scal + 6,
@@ -879,6 +956,8 @@ void tpg_workspace_free(tpg_workspace* ws) {
   }
   for (hipEvent_t e : ws->ev_pool) (void)hipEventDestroy(e);
   drop_level_graphs(ws);
+  drop_seq_graph(ws->rank_up);
+  drop_seq_graph(ws->rank_down);
   if (ws->h_ls) (void)hipHostFree(ws->h_ls);
   if (ws->h_scalars) (void)hipHostFree(ws->h_scalars);
   if (ws->own_stream) (void)hipStreamDestroy(ws->own_stream);

@@ -165,11 +165,17 @@ __device__ __forceinline__ void store_child_mask(uint64_t* dst, int64_t S, int W
 // own parents' children.  Children are laid out item-major and, inside an
 // item, in thread order, so a wave's stores land on neighbouring slots.  A
 // level that fits one tile stores its size instead of claiming.
-template <int W, int ITEMS, int NT>
+//
+// GL: the CSR (row pointers, successors, predecessors, local ids) is copied
+// into LDS by every workgroup that has a tile, so the per-parent chain of
+// graph lookups (row range -> successor ids -> predecessor ids) reads LDS
+// instead of L2.
+template <int W, int ITEMS, int NT, bool GL>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 1024 && ITEMS == 1 && W <= 8 ? 8 : 1))) void k_extend_tp(ExtArgs a, int li) {
   constexpr int NW = NT / 64;
   __shared__ int32_t s_tot[ITEMS][NW];
   __shared__ int64_t s_prefix;
+  extern __shared__ int32_t s_graph[];
 
   LevelState* ls = a.ls;
   if (ls->overflow) return;
@@ -199,6 +205,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 1024 &
   while (ir < ITEMS && (F + (int64_t)NT * ir - 1) / ((int64_t)NT * ir) > a.tiles_target) ir <<= 1;
   const int64_t TR = (int64_t)NT * ir;
   const int64_t ntiles = (F + TR - 1) / TR;
+  DGraph g = a.g;
+  if constexpr (GL) {
+    if ((int64_t)blockIdx.x >= ntiles) return;
+    for (int i = tid; i < a.g.n_stage; i += NT) s_graph[i] = a.g.sp[i];
+    __syncthreads();
+    g.sp = s_graph;
+    g.s = s_graph + (a.g.s - a.g.sp);
+    g.pp = s_graph + (a.g.pp - a.g.sp);
+    g.p = s_graph + (a.g.p - a.g.sp);
+    g.loc = s_graph + (a.g.loc - a.g.sp);
+  }
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t tb = t * TR;
     // records and visited sets of the thread's parents (independent loads;
@@ -219,10 +236,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 1024 &
       vm[i] = 0;
       if (!(inf[i] & F_CYC)) {
         const int v = node_v(inf[i]);
-        const int cb = v - a.g.loc[v];
-        vm[i] = choices<W>(a.g, inf[i], m[i], a.g.sp[v], a.g.sp[v + 1], cb);
+        const int cb = v - g.loc[v];
+        vm[i] = choices<W>(g, inf[i], m[i], g.sp[v], g.sp[v + 1], cb);
         if (vm[i] == 0) {
-          const bool pp = all_preds_on<W>(a.g, cb, node_v1l(inf[i]), m[i]);
+          const bool pp = all_preds_on<W>(g, cb, node_v1l(inf[i]), m[i]);
           inf[i] |= F_TERM | (pp ? F_PP : 0u);
           a.t.info[base + tb + i * NT + tid] = inf[i];
         }
@@ -273,12 +290,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 1024 &
         const int v1l = node_v1l(inf[i]);
         uint64_t rest = vm[i];
         const int pv = node_v(inf[i]);
-        const int k0 = rest ? a.g.sp[pv] : 0;
-        const int cb = rest ? pv - a.g.loc[pv] : 0;
+        const int k0 = rest ? g.sp[pv] : 0;
+        const int cb = rest ? pv - g.loc[pv] : 0;
         while (rest) {
           const int slot = __builtin_ctzll(rest);
           rest &= rest - 1;
-          const int w = a.g.s[k0 + slot];
+          const int w = g.s[k0 + slot];
           const int wl = w - cb;
           const int64_t cg = nbase + cl;
           if (cg < a.t.rec_cap) {
@@ -447,11 +464,11 @@ __global__ __launch_bounds__(kBlock) void k_extend_lb(ExtArgs a, int li) {
 // (the kernel's own execution interval, without queueing around it).
 template <class K>
 static hipError_t launch_timed(K kernel, int grid, int threads, hipEvent_t e0, hipEvent_t e1,
-                               const ExtArgs& a, int li, hipStream_t st) {
+                               const ExtArgs& a, int li, hipStream_t st, size_t lds = 0) {
   if (e0 && e1)
-    hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(threads), 0, st, e0, e1, 0, a, li);
+    hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(threads), lds, st, e0, e1, 0, a, li);
   else
-    kernel<<<grid, threads, 0, st>>>(a, li);
+    kernel<<<grid, threads, lds, st>>>(a, li);
   return hipGetLastError();
 }
 
@@ -462,8 +479,15 @@ template <int W, int ITEMS>
 static hipError_t launch_extend_wi(int variant, const ExtArgs& a, int grid, int li, hipStream_t st,
                                    hipEvent_t e0, hipEvent_t e1) {
   if constexpr (ITEMS * W <= 32) {
-    if (variant == 1) return launch_timed(k_extend_tp<W, ITEMS, 256>, grid, 256, e0, e1, a, li, st);
-    if (variant == 2) return launch_timed(k_extend_tp<W, ITEMS, 1024>, grid, 1024, e0, e1, a, li, st);
+    const size_t gb = sizeof(int32_t) * (size_t)a.g.n_stage;
+    if (gb <= (size_t)kGraphLdsBytes) {
+      if (variant == 1)
+        return launch_timed(k_extend_tp<W, ITEMS, 256, true>, grid, 256, e0, e1, a, li, st, gb);
+      if (variant == 2)
+        return launch_timed(k_extend_tp<W, ITEMS, 1024, true>, grid, 1024, e0, e1, a, li, st, gb);
+    }
+    if (variant == 1) return launch_timed(k_extend_tp<W, ITEMS, 256, false>, grid, 256, e0, e1, a, li, st);
+    if (variant == 2) return launch_timed(k_extend_tp<W, ITEMS, 1024, false>, grid, 1024, e0, e1, a, li, st);
   }
   return launch_timed(k_extend_lb<W, ITEMS>, grid, kBlock, e0, e1, a, li, st);
 }

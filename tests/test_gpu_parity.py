@@ -122,6 +122,22 @@ def test_deterministic_bytes_across_runs_and_modes():
     assert outs[0] == outs[1] == outs[2]
 
 
+def test_repeated_calls_replay_captured_sweeps():
+    """The ranking sweeps are issued directly on a call, captured on the next
+    identical call and replayed after that; every call, with other work and
+    synchronizations between them, matches the oracle."""
+    w = tpg.Workspace()
+    for k, rec in enumerate(workloads()["c2"][:2]):
+        g = cfggen.c2_cfg(rec["seed"])
+        h = tpg.load_cfg(g)
+        for r in range(4):
+            say("case replay", rec["seed"], r)
+            check_tp(g, 0, w, local=True)
+            if r == 1:  # other work in between: a different graph on the same workspace
+                check_tp(cfggen.c1_cfg(3), 0, w)
+    w.close()
+
+
 def test_device_output_views():
     import torch
     g = cfggen.c1_cfg(0)
