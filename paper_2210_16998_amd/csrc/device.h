@@ -30,6 +30,17 @@ __device__ __forceinline__ uint32_t make_info(int v, int v1l, uint32_t flags) {
   return (uint32_t)v | ((uint32_t)v1l << kV1Shift) | flags;
 }
 
+// A node's child count with its leaf kind folded in, so that the ranking
+// sweeps read one byte per node: a node with children stores their number
+// (1..64); a leaf stores kNchCycle for a closed cycle, kNchPP for an acyclic
+// prime path and 0 for a terminal path that is not prime.
+constexpr uint8_t kNchPP = 254;
+constexpr uint8_t kNchCycle = 255;
+__device__ __forceinline__ uint8_t nch_code(uint32_t info, int nchildren) {
+  return nchildren ? (uint8_t)nchildren
+                   : (info & F_CYC) ? kNchCycle : (info & F_PP) ? kNchPP : (uint8_t)0;
+}
+
 struct DGraph {
   const int32_t* sp;    // successor row pointers [n+1] (graph-wide ids)
   const int32_t* s;     // successors, ascending per row

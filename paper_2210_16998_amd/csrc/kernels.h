@@ -31,7 +31,7 @@ struct TreeBufs {
   int32_t* par;       // [rec_cap]
   uint32_t* info;     // [rec_cap]
   int32_t* cstart;    // [rec_cap + 1] global index of the first child
-  uint8_t* nch;       // [rec_cap] number of children (out-degree <= 64)
+  uint8_t* nch;       // [rec_cap] number of children (<= 64) or leaf kind (nch_code)
   uint64_t* mask[2];  // frontier visited sets, ping-pong by level parity [mask_cap * W]
   int64_t rec_cap;
   int64_t mask_cap;

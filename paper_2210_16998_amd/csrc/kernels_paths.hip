@@ -286,7 +286,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 1024 &
       if (i < ir && j < F) {
         int64_t cl = prefix + excl[i];
         a.t.cstart[base + j] = (int32_t)(nbase + cl);
-        a.t.nch[base + j] = (uint8_t)__builtin_popcountll(vm[i]);
+        a.t.nch[base + j] = nch_code(inf[i], __builtin_popcountll(vm[i]));
         const int v1l = node_v1l(inf[i]);
         uint64_t rest = vm[i];
         const int pv = node_v(inf[i]);
@@ -423,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_extend_lb(ExtArgs a, int li) {
       const int p = i * kBlock + tid;
       if (i < ir && tb + p < F) {
         a.t.cstart[base + tb + p] = (int32_t)(nbase + prefix + s_off[p]);
-        a.t.nch[base + tb + p] = (uint8_t)__builtin_popcountll(s_vm[p]);
+        a.t.nch[base + tb + p] = nch_code(s_inf[p], __builtin_popcountll(s_vm[p]));
       }
     }
     for (int k = tid; k < total32; k += kBlock) {
@@ -540,11 +540,12 @@ __global__ __launch_bounds__(kBlock) void k_count(ExtArgs a, int L, int64_t base
     cnt = __builtin_popcountll(vm);
     if (cnt == 0) {
       const bool pp = all_preds_on<W>(a.g, cb, node_v1l(inf), m);
-      a.t.info[base + j] = inf | F_TERM | (pp ? F_PP : 0u);
+      inf |= F_TERM | (pp ? F_PP : 0u);
+      a.t.info[base + j] = inf;
     }
   }
   a.t.cstart[base + j] = cnt;
-  a.t.nch[base + j] = (uint8_t)cnt;
+  a.t.nch[base + j] = nch_code(inf, cnt);
 }
 
 template <int W>
@@ -616,13 +617,13 @@ __global__ __launch_bounds__(kBlock) void k_up(ExtArgs a, int L, int64_t base, i
   int cyc = 0;
   if (j < F) {
     const int64_t g = base + j;
-    const uint32_t inf = a.t.info[g];
+    const uint8_t k = a.t.nch[g];
     uint32_t c = 0;
-    if (inf & (F_CYC | F_PP)) {
+    if (k >= kNchPP) {
       c = 1;
-      cyc = (inf & F_CYC) ? 1 : 0;
-    } else if (!(inf & F_TERM)) {
-      const int64_t c0 = a.t.cstart[g], c1 = c0 + a.t.nch[g];
+      cyc = k == kNchCycle ? 1 : 0;
+    } else if (k) {
+      const int64_t c0 = a.t.cstart[g], c1 = c0 + k;
       for (int64_t x = c0; x < c1; ++x) c += sub_cnt[x];
     }
     sub_cnt[g] = c;
@@ -679,14 +680,13 @@ __global__ __launch_bounds__(kBlock) void k_down(ExtArgs a, int L, int64_t base,
   if (j >= F) return;
   const int64_t g = base + j;
   uint32_t r = sub_cnt[g];
-  if (r == kNoRank) return;
-  const uint32_t inf = a.t.info[g];
-  if (inf & (F_CYC | F_TERM)) return;
-  const int64_t c0 = a.t.cstart[g], c1 = c0 + a.t.nch[g];
+  const uint8_t k = a.t.nch[g];
+  if (r == kNoRank || k == 0 || k >= kNchPP) return;
+  const int64_t c0 = a.t.cstart[g], c1 = c0 + k;
   for (int64_t x = c0; x < c1; ++x) {
     const uint32_t cc = sub_cnt[x];
     sub_cnt[x] = cc ? r : kNoRank;
-    if (cc && (a.t.info[x] & (F_PP | F_CYC))) {
+    if (cc && a.t.nch[x] >= kNchPP) {
       leaf_by_rank[r] = x;
       pp_len[r] = L + 1;
     }
