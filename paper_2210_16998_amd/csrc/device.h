@@ -20,7 +20,9 @@ constexpr uint32_t kVMask = 0x1FFFFu;
 constexpr int kV1Shift = 17;
 constexpr uint32_t kV1Mask = 0xFFFu;
 constexpr uint32_t F_CYC = 1u << 29;   // closes a cycle (last vertex = first)
-constexpr uint32_t F_PP = 1u << 30;    // prime path leaf (set on terminal nodes)
+// F_PP and F_TERM live only in registers while a level is extended; the
+// stored leaf kind is the node's nch code
+constexpr uint32_t F_PP = 1u << 30;    // prime path leaf (terminal and not backward-extendable)
 constexpr uint32_t F_TERM = 1u << 31;  // acyclic, cannot be extended forward
 constexpr int kMaxUnionVertices = 1 << 17;
 

@@ -240,8 +240,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 1024 &
         vm[i] = choices<W>(g, inf[i], m[i], g.sp[v], g.sp[v + 1], cb);
         if (vm[i] == 0) {
           const bool pp = all_preds_on<W>(g, cb, node_v1l(inf[i]), m[i]);
-          inf[i] |= F_TERM | (pp ? F_PP : 0u);
-          a.t.info[base + tb + i * NT + tid] = inf[i];
+          inf[i] |= F_TERM | (pp ? F_PP : 0u);  // recorded through nch_code below
         }
       }
     }
@@ -381,8 +380,7 @@ __global__ __launch_bounds__(kBlock) void k_extend_lb(ExtArgs a, int li) {
           vm = choices<W>(a.g, in, m, k0, a.g.sp[v + 1], cb);
           if (vm == 0) {
             const bool pp = all_preds_on<W>(a.g, cb, node_v1l(in), m);
-            in |= F_TERM | (pp ? F_PP : 0u);
-            a.t.info[base + j] = in;
+            in |= F_TERM | (pp ? F_PP : 0u);  // recorded through nch_code
           }
         }
         s_off[p] = __builtin_popcountll(vm);
@@ -540,8 +538,7 @@ __global__ __launch_bounds__(kBlock) void k_count(ExtArgs a, int L, int64_t base
     cnt = __builtin_popcountll(vm);
     if (cnt == 0) {
       const bool pp = all_preds_on<W>(a.g, cb, node_v1l(inf), m);
-      inf |= F_TERM | (pp ? F_PP : 0u);
-      a.t.info[base + j] = inf;
+      inf |= F_TERM | (pp ? F_PP : 0u);  // recorded through nch_code
     }
   }
   a.t.cstart[base + j] = cnt;
@@ -655,7 +652,7 @@ __global__ __launch_bounds__(1024) void k_roots(ExtArgs a, int64_t n_roots, uint
     if (i < n_roots && mode == 1) {
       const int64_t rank = carry + pc;
       sub_cnt[i] = (uint32_t)rank;
-      if (a.t.info[i] & (F_PP | F_CYC)) {
+      if (a.t.nch[i] >= kNchPP) {
         leaf_by_rank[rank] = i;
         pp_len[rank] = 1;
       }
