@@ -236,8 +236,8 @@ void tpg_batch_result_free(tpg_batch_result* r);
  * workgroups per compute unit (1..32) and the kernel variant (0: load-
  * balanced tiles of 256 threads staged in LDS; 1 / 2: thread-per-parent with
  * visited sets in registers, 256 / 1024 threads).  Defaults come from sweeps
- * on MI355X (W = 4: variant 2, 1 item, 2 workgroups; W = 8: variant 1,
- * 4 items, 8 workgroups).  tpg_autotune times every combination on the given
+ * on MI355X (W = 4: variant 2, 1 item, 2 workgroups; W = 8: variant 2,
+ * 1 item, 4 workgroups).  tpg_autotune times every combination on the given
  * graphs (grouped by width as in the batched form), keeps the fastest per
  * width in the workspace (opts->ws, required) and returns the table; results
  * never depend on the tuning.

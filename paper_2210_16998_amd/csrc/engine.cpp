@@ -107,9 +107,9 @@ struct tpg_workspace {
   // register width W): parents per thread (tile = threads * items, one output
   // claim per tile), persistent workgroups per CU and kernel variant;
   // defaults from sweeps on MI355X
-  int tune_items[7] = {2, 1, 1, 4, 2, 1, 1};
-  int tune_wgs[7] = {2, 2, 2, 8, 2, 2, 4};
-  int tune_variant[7] = {2, 2, 2, 1, 2, 2, 0};
+  int tune_items[7] = {2, 1, 1, 1, 2, 1, 1};
+  int tune_wgs[7] = {2, 2, 2, 4, 2, 2, 4};
+  int tune_variant[7] = {2, 2, 2, 2, 2, 2, 0};
   double tune_ms[7] = {0, 0, 0, 0, 0, 0, 0};
 };
 
@@ -209,6 +209,9 @@ tpg_status upload_union(tpg_workspace* ws, const HostUnion& U, hipStream_t st) {
   ws->union_uids = U.uids;
   return TPG_OK;
 }
+
+// Buffer of the stored (odd) level L's visited sets.
+int mask_buf_host(int L) { return ((L - 1) >> 1) & 1; }
 
 // W here: words stored per visited set.
 tpg_status reserve_tree(tpg_workspace* ws, int64_t rec, int64_t msk, int W, hipStream_t st,
@@ -487,8 +490,12 @@ tpg_status build_tree_onepass(tpg_workspace* ws, const HostUnion& U, hipStream_t
       const int64_t F = cnt[Lo], nxt = cnt[Lo + 1];
       const int64_t need_rec = base + F + nxt + 1;
       const int64_t new_rec = std::max<int64_t>(ws->rec_cap, need_rec + need_rec / 4);
-      const int64_t new_msk = std::max<int64_t>(ws->mask_cap, nxt + nxt / 4 + 1024);
-      TPG_TRY(reserve_tree(ws, new_rec, new_msk, U.Wu, st, base + F, Lo & 1, F));
+      // visited sets: only an odd level Lo + 1 stores them; the replay of
+      // Lo reads the stored level Ls (Lo itself when odd, else Lo - 1)
+      const int64_t new_msk = (Lo + 1) & 1 ? std::max<int64_t>(ws->mask_cap, nxt + nxt / 4 + 1024)
+                                           : ws->mask_cap;
+      const int Ls = (Lo & 1) ? Lo : Lo - 1;
+      TPG_TRY(reserve_tree(ws, new_rec, new_msk, U.Wu, st, base + F, mask_buf_host(Ls), cnt[Ls]));
       a = make_args(ws, grid);
       TPG_HIP(launch_resume_fix(a, Lo, st));
       R.n_overflows += 1;
@@ -538,13 +545,13 @@ tpg_status build_tree_twopass(tpg_workspace* ws, const HostUnion& U, hipStream_t
   R.count.assign(kMaxLevels, 0);
   R.off.assign(kMaxLevels, 0);
   int L = 1;
-  int64_t base = 0, F = U.n;
+  int64_t base = 0, F = U.n, prev = 0;
   R.count[1] = F;
   R.peak = F;
   for (;;) {
     TPG_TRY(reserve_scan(ws, F));
     hipEvent_t e0 = tm.mark();
-    TPG_HIP(launch_count(W, a, L, base, F, st));
+    TPG_HIP(launch_count(W, a, L, prev, base, F, st));
     int32_t* cs = ws->cstart.as<int32_t>() + base;
     TPG_HIP(scan_i32_to_i32(cs, cs, F, base + F, ws->scalars.as<int64_t>(),
                             ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
@@ -557,14 +564,17 @@ tpg_status build_tree_twopass(tpg_workspace* ws, const HostUnion& U, hipStream_t
       tm.next = 0;
       break;
     }
-    if (base + F + total + 1 > ws->rec_cap || total > ws->mask_cap) {
+    // the children's visited sets are stored when they form an odd level
+    const bool store_next = (L + 1) & 1;
+    if (base + F + total + 1 > ws->rec_cap || (store_next && total > ws->mask_cap)) {
       const int64_t need = base + F + total + 1;
+      const int Ls = (L & 1) ? L : L - 1;  // the stored level the fill reads
       TPG_TRY(reserve_tree(ws, std::max<int64_t>(ws->rec_cap, need + need / 2),
-                           std::max<int64_t>(ws->mask_cap, total + total / 2), U.Wu, st, base + F + 1,
-                           L & 1, F));
+                           store_next ? std::max<int64_t>(ws->mask_cap, total + total / 2) : ws->mask_cap,
+                           U.Wu, st, base + F + 1, mask_buf_host(Ls), R.count[Ls]));
       a = make_args(ws);
     }
-    TPG_HIP(launch_fill(W, a, L, base, F, st));
+    TPG_HIP(launch_fill(W, a, L, prev, base, F, st));
     hipEvent_t e1 = tm.mark();
     TPG_HIP(hipStreamSynchronize(st));
     R.ms_kernel += Timer::ms(e0, e1);
@@ -573,6 +583,7 @@ tpg_status build_tree_twopass(tpg_workspace* ws, const HostUnion& U, hipStream_t
     R.off[L + 1] = base + F;
     R.count[L + 1] = total;
     R.peak = std::max(R.peak, total);
+    prev = base;
     base += F;
     F = total;
     ++L;

@@ -32,7 +32,7 @@ struct TreeBufs {
   uint32_t* info;     // [rec_cap]
   int32_t* cstart;    // [rec_cap + 1] global index of the first child
   uint8_t* nch;       // [rec_cap] number of children (<= 64) or leaf kind (nch_code)
-  uint64_t* mask[2];  // frontier visited sets, ping-pong by level parity [mask_cap * W]
+  uint64_t* mask[2];  // visited sets of the odd levels, alternating [mask_cap * mask_words]
   int64_t rec_cap;
   int64_t mask_cap;
   int32_t mask_words;  // words stored per visited set (<= the kernel width W)
@@ -57,8 +57,12 @@ hipError_t launch_extend(int W, int items, int variant, const ExtArgs& a, int gr
                          hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_resume_fix(const ExtArgs& a, int level, hipStream_t st);
 // two-pass (plain) form
-hipError_t launch_count(int W, const ExtArgs& a, int L, int64_t base, int64_t F, hipStream_t st);
-hipError_t launch_fill(int W, const ExtArgs& a, int L, int64_t base, int64_t F, hipStream_t st);
+// prev: first node of level L - 1 (an even level's visited sets are rebuilt
+// from its parents' stored sets)
+hipError_t launch_count(int W, const ExtArgs& a, int L, int64_t prev, int64_t base, int64_t F,
+                        hipStream_t st);
+hipError_t launch_fill(int W, const ExtArgs& a, int L, int64_t prev, int64_t base, int64_t F,
+                       hipStream_t st);
 
 // --- ranking / materialization ---------------------------------------------
 // sub_cnt: PP leaves per subtree (k_up), then rewritten top-down into the

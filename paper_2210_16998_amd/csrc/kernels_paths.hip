@@ -19,10 +19,12 @@
 //    order, and each node records where its children start and how many
 //    there are.
 //  * The visited set of a frontier path lives as a bitmask of W 64-bit words
-//    (registers while testing, HBM between levels, two levels alive).  In
-//    HBM the sets are stored word-major: word q of slot j sits at
-//    q * stride + j, so the threads of a wave, which own consecutive slots,
-//    read and write consecutive words.
+//    (registers while testing).  In HBM only the odd levels' sets are kept,
+//    two stored levels alive: a path on an even level is a path of the odd
+//    level before plus its last vertex, so its set is rebuilt from its
+//    parent's (siblings read the same stored set).  Sets are stored
+//    word-major: word q of slot j sits at q * stride + j, so the threads of
+//    a wave, which own consecutive slots, read and write consecutive words.
 //  * One workgroup handles a tile of 256 * ITEMS parents: choice masks over
 //    successor slots, a block scan of child counts, then ONE device-scope
 //    atomic claim of the tile's slice of the next level, then a
@@ -66,12 +68,13 @@ __global__ void k_seed(ExtArgs a) {
     a.t.par[v] = -1;
     a.t.info[v] = make_info(v, a.g.loc[v], 0);
   }
-  // masks of level 1 (parity 1): one bit each, at the vertex's local id
+  // visited sets of level 1 (stored, buffer 0): one bit each, at the
+  // vertex's local id
   const int W = a.t.mask_words;
   for (int64_t k = i; k < (int64_t)n * W; k += (int64_t)gridDim.x * blockDim.x) {
     const int q = (int)(k / n), v = (int)(k % n);
     const int l = a.g.loc[v];
-    a.t.mask[1][(int64_t)q * a.t.mask_cap + v] = (q == (l >> 6)) ? (1ull << (l & 63)) : 0ull;
+    a.t.mask[0][(int64_t)q * a.t.mask_cap + v] = (q == (l >> 6)) ? (1ull << (l & 63)) : 0ull;
   }
 }
 
@@ -148,6 +151,31 @@ __device__ __forceinline__ void store_child_mask(uint64_t* dst, int64_t S, int W
     if (k < Wu) dst[k * S + c] = m[k] | (k == q ? bit : 0ull);
 }
 
+// Stored levels (odd) alternate between the two buffers.
+__device__ __forceinline__ int mask_buf(int L) { return ((L - 1) >> 1) & 1; }
+
+// Visited set of the path in slot j of level L: an odd level's set is
+// stored; an even level's is its parent's (slot par - prev of level L - 1,
+// which starts at node prev) plus its own last vertex, local id vl.
+template <int W>
+__device__ __forceinline__ void path_mask_load(const ExtArgs& a, int L, int64_t prev, int64_t node,
+                                               int64_t j, uint64_t (&m)[W]) {
+  if (L & 1) {
+    load_mask<W>(a.t.mask[mask_buf(L)], a.t.mask_cap, a.t.mask_words, j, m);
+  } else {
+    const int64_t jp = (int64_t)a.t.par[node] - prev;
+    load_mask<W>(a.t.mask[mask_buf(L - 1)], a.t.mask_cap, a.t.mask_words, jp, m);
+  }
+}
+template <int W>
+__device__ __forceinline__ void path_mask_own(int L, int vl, uint64_t (&m)[W]) {
+  if (L & 1) return;  // stored sets already hold the last vertex
+  const int q = vl >> 6;
+  const uint64_t bit = 1ull << (vl & 63);
+#pragma unroll
+  for (int k = 0; k < W; ++k) m[k] |= (k == q) ? bit : 0ull;
+}
+
 // ---------------------------------------------------------------------------
 // one-pass extension of level L -> L+1 (device-sized, claim per tile)
 // ---------------------------------------------------------------------------
@@ -186,7 +214,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 1024 &
   const int64_t base = ls->off[L - 1] + ls->count[L - 1];
   const int tid = (int)threadIdx.x;
   const int lane = lane_id(), wave = tid >> 6;
-  if (base + F + 1 > a.t.rec_cap || F > a.t.mask_cap || base + F >= (int64_t)INT32_MAX) {
+  if (base + F + 1 > a.t.rec_cap || ((L & 1) && F > a.t.mask_cap) || base + F >= (int64_t)INT32_MAX) {
     // the previous launch's children did not fit: replay that level
     if (blockIdx.x == 0 && tid == 0) {
       ls->overflow_level = L - 1;
@@ -196,9 +224,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 1024 &
   }
   if (blockIdx.x == 0 && tid == 0) ls->off[L] = base;
   const int64_t nbase = base + F;
-  const int par = L & 1;
-  const uint64_t* mcur = a.t.mask[par];
-  uint64_t* mnxt = a.t.mask[par ^ 1];
+  const int64_t prev = ls->off[L - 1];
+  // children's sets are stored when they land on an odd level
+  uint64_t* mnxt = (L & 1) ? nullptr : a.t.mask[mask_buf(L + 1)];
   unsigned long long* claim = reinterpret_cast<unsigned long long*>(&ls->count[L + 1]);
 
   int ir = 1;
@@ -227,7 +255,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 1024 &
       const int64_t j = tb + i * NT + tid;
       const bool ok = i < ir && j < F;
       inf[i] = ok ? a.t.info[base + j] : F_CYC;
-      load_mask<W>(mcur, a.t.mask_cap, a.t.mask_words, ok ? j : 0, m[i]);
+      path_mask_load<W>(a, L, prev, base + (ok ? j : 0), ok ? j : 0, m[i]);
     }
     // choice masks and the terminal filter
     uint64_t vm[ITEMS];
@@ -237,6 +265,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 1024 &
       if (!(inf[i] & F_CYC)) {
         const int v = node_v(inf[i]);
         const int cb = v - g.loc[v];
+        path_mask_own<W>(L, v - cb, m[i]);
         vm[i] = choices<W>(g, inf[i], m[i], g.sp[v], g.sp[v + 1], cb);
         if (vm[i] == 0) {
           const bool pp = all_preds_on<W>(g, cb, node_v1l(inf[i]), m[i]);
@@ -301,7 +330,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 1024 &
             a.t.par[cg] = (int32_t)(base + j);
             a.t.info[cg] = make_info(w, v1l, wl == v1l ? F_CYC : 0u);
           }
-          if (wl != v1l && cl < a.t.mask_cap)
+          if (mnxt && wl != v1l && cl < a.t.mask_cap)
             store_child_mask<W>(mnxt, a.t.mask_cap, a.t.mask_words, cl, m[i], wl);
           ++cl;
         }
@@ -335,7 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_extend_lb(ExtArgs a, int li) {
   if (F == 0) return;
   const int64_t base = ls->off[L - 1] + ls->count[L - 1];
   const int tid = (int)threadIdx.x;
-  if (base + F + 1 > a.t.rec_cap || F > a.t.mask_cap || base + F >= (int64_t)INT32_MAX) {
+  if (base + F + 1 > a.t.rec_cap || ((L & 1) && F > a.t.mask_cap) || base + F >= (int64_t)INT32_MAX) {
     if (blockIdx.x == 0 && tid == 0) {
       ls->overflow_level = L - 1;
       ls->overflow = 1;
@@ -344,9 +373,8 @@ __global__ __launch_bounds__(kBlock) void k_extend_lb(ExtArgs a, int li) {
   }
   if (blockIdx.x == 0 && tid == 0) ls->off[L] = base;
   const int64_t nbase = base + F;
-  const int par = L & 1;
-  const uint64_t* mcur = a.t.mask[par];
-  uint64_t* mnxt = a.t.mask[par ^ 1];
+  const int64_t prev = ls->off[L - 1];
+  uint64_t* mnxt = (L & 1) ? nullptr : a.t.mask[mask_buf(L + 1)];
   unsigned long long* claim = reinterpret_cast<unsigned long long*>(&ls->count[L + 1]);
 
   int ir = 1;
@@ -376,7 +404,8 @@ __global__ __launch_bounds__(kBlock) void k_extend_lb(ExtArgs a, int li) {
           const int v = node_v(in);
           const int cb = v - a.g.loc[v];
           k0 = a.g.sp[v];
-          load_mask<W>(mcur, a.t.mask_cap, a.t.mask_words, j, m);
+          path_mask_load<W>(a, L, prev, base + j, j, m);
+          path_mask_own<W>(L, v - cb, m);
           vm = choices<W>(a.g, in, m, k0, a.g.sp[v + 1], cb);
           if (vm == 0) {
             const bool pp = all_preds_on<W>(a.g, cb, node_v1l(in), m);
@@ -443,13 +472,14 @@ __global__ __launch_bounds__(kBlock) void k_extend_lb(ExtArgs a, int li) {
         a.t.par[cg] = (int32_t)(base + tb + o);
         a.t.info[cg] = make_info(w, v1l, wl == v1l ? F_CYC : 0u);
       }
-      if (wl != v1l && cl < a.t.mask_cap) {
+      if (mnxt && wl != v1l && cl < a.t.mask_cap) {
         uint64_t pm[W];
         if constexpr (kLdsMask) {
 #pragma unroll
           for (int q = 0; q < W; ++q) pm[q] = s_mask[o * W + q];
         } else {
-          load_mask<W>(mcur, a.t.mask_cap, a.t.mask_words, tb + o, pm);
+          path_mask_load<W>(a, L, prev, base + tb + o, tb + o, pm);
+          path_mask_own<W>(L, a.g.loc[pv], pm);
         }
         store_child_mask<W>(mnxt, a.t.mask_cap, a.t.mask_words, cl, pm, wl);
       }
@@ -524,16 +554,18 @@ hipError_t launch_extend(int W, int items, int variant, const ExtArgs& a, int gr
 // two-pass (plain) form: count, host-visible scan, fill
 // ---------------------------------------------------------------------------
 template <int W>
-__global__ __launch_bounds__(kBlock) void k_count(ExtArgs a, int L, int64_t base, int64_t F) {
+__global__ __launch_bounds__(kBlock) void k_count(ExtArgs a, int L, int64_t prev, int64_t base,
+                                                  int64_t F) {
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (j >= F) return;
   uint32_t inf = a.t.info[base + j];
   int cnt = 0;
   if (!(inf & F_CYC)) {
     uint64_t m[W];
-    load_mask<W>(a.t.mask[L & 1], a.t.mask_cap, a.t.mask_words, j, m);
+    path_mask_load<W>(a, L, prev, base + j, j, m);
     const int v = node_v(inf);
     const int cb = v - a.g.loc[v];
+    path_mask_own<W>(L, v - cb, m);
     const uint64_t vm = choices<W>(a.g, inf, m, a.g.sp[v], a.g.sp[v + 1], cb);
     cnt = __builtin_popcountll(vm);
     if (cnt == 0) {
@@ -546,21 +578,23 @@ __global__ __launch_bounds__(kBlock) void k_count(ExtArgs a, int L, int64_t base
 }
 
 template <int W>
-__global__ __launch_bounds__(kBlock) void k_fill(ExtArgs a, int L, int64_t base, int64_t F) {
+__global__ __launch_bounds__(kBlock) void k_fill(ExtArgs a, int L, int64_t prev, int64_t base,
+                                                 int64_t F) {
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (j >= F) return;
   const uint32_t inf = a.t.info[base + j];
   if (inf & F_CYC) return;
   uint64_t m[W];
-  load_mask<W>(a.t.mask[L & 1], a.t.mask_cap, a.t.mask_words, j, m);
+  path_mask_load<W>(a, L, prev, base + j, j, m);
   const int v = node_v(inf);
   const int k0 = a.g.sp[v];
   const int cb = v - a.g.loc[v];
+  path_mask_own<W>(L, v - cb, m);
   uint64_t vm = choices<W>(a.g, inf, m, k0, a.g.sp[v + 1], cb);
   const int v1l = node_v1l(inf);
   const int64_t nbase = base + F;
   int64_t c = a.t.cstart[base + j];
-  uint64_t* mnxt = a.t.mask[(L + 1) & 1];
+  uint64_t* mnxt = (L & 1) ? nullptr : a.t.mask[mask_buf(L + 1)];
   while (vm) {
     const int slot = __builtin_ctzll(vm);
     vm &= vm - 1;
@@ -568,7 +602,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(ExtArgs a, int L, int64_t base,
     const int wl = w - cb;
     a.t.par[c] = (int32_t)(base + j);
     a.t.info[c] = make_info(w, v1l, wl == v1l ? F_CYC : 0u);
-    if (wl != v1l) store_child_mask<W>(mnxt, a.t.mask_cap, a.t.mask_words, c - nbase, m, wl);
+    if (mnxt && wl != v1l) store_child_mask<W>(mnxt, a.t.mask_cap, a.t.mask_words, c - nbase, m, wl);
     ++c;
   }
 }
@@ -585,17 +619,19 @@ __global__ __launch_bounds__(kBlock) void k_fill(ExtArgs a, int L, int64_t base,
     default: return hipErrorInvalidValue;                                           \
   }
 
-hipError_t launch_count(int W, const ExtArgs& a, int L, int64_t base, int64_t F, hipStream_t st) {
+hipError_t launch_count(int W, const ExtArgs& a, int L, int64_t prev, int64_t base, int64_t F,
+                        hipStream_t st) {
   if (F == 0) return hipSuccess;
   const int64_t grid = (F + kBlock - 1) / kBlock;
-  TPG_W_SWITCH(W, k_count, (unsigned)grid, a, L, base, F);
+  TPG_W_SWITCH(W, k_count, (unsigned)grid, a, L, prev, base, F);
   return hipGetLastError();
 }
 
-hipError_t launch_fill(int W, const ExtArgs& a, int L, int64_t base, int64_t F, hipStream_t st) {
+hipError_t launch_fill(int W, const ExtArgs& a, int L, int64_t prev, int64_t base, int64_t F,
+                       hipStream_t st) {
   if (F == 0) return hipSuccess;
   const int64_t grid = (F + kBlock - 1) / kBlock;
-  TPG_W_SWITCH(W, k_fill, (unsigned)grid, a, L, base, F);
+  TPG_W_SWITCH(W, k_fill, (unsigned)grid, a, L, prev, base, F);
   return hipGetLastError();
 }
 
