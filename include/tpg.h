@@ -59,8 +59,9 @@ typedef enum tpg_status {
   TPG_ERR_OOM_DEVICE = -6,
   TPG_ERR_CAPACITY = -7,      /* would exceed opts.pool_cap_bytes            */
   TPG_ERR_DEVICE = -8,        /* a HIP runtime call failed                   */
-  TPG_ERR_UNSUPPORTED = -9    /* > TPG_MAX_VERTICES vertices or out-degree
+  TPG_ERR_UNSUPPORTED = -9,   /* > TPG_MAX_VERTICES vertices or out-degree
                                  > TPG_MAX_OUT_DEGREE                        */
+  TPG_ERR_CALLBACK = -10      /* opts.on_chunk returned nonzero: stopped      */
 } tpg_status;
 
 /* load_flags */
@@ -75,6 +76,12 @@ typedef enum tpg_status {
 #define TPG_FORCE_TWO_PASS 0x2u /* plain form: per level count -> scan -> host
                                    reads the size -> fill (no device-side sizing) */
 #define TPG_NO_TIMING 0x4u      /* skip per-phase event timing in tpg_stats     */
+#define TPG_DIGEST 0x8u         /* also compute tpg_paths.digest of each set     */
+#define TPG_DIGEST_ONLY 0x10u   /* counts and digest only: no path arrays are
+                                   returned (tpg_paths.offsets / vertices NULL) */
+#define TPG_STREAM 0x20u        /* deliver the results through opts.on_chunk
+                                   (see tpg_chunk_fn); *out then holds only the
+                                   counts and the digest of the whole set      */
 
 typedef struct tpg_graph tpg_graph;         /* opaque, host memory */
 typedef struct tpg_workspace tpg_workspace; /* opaque: device arena + stream */
@@ -87,7 +94,23 @@ typedef struct tpg_paths {
   int32_t on_device; /* 1: device pointers (TPG_OUT_DEVICE) owned by the
                         workspace; 0: host memory owned by the library     */
   int32_t reserved_;
+  /* Set digest (TPG_DIGEST, TPG_DIGEST_ONLY, TPG_STREAM; else zero): with
+   * h(p) = FNV-1a 64 (offset basis 0xcbf29ce484222325, prime 0x100000001b3)
+   * over the bytes of the int32 little-endian sequence (k, v_1, .., v_k) of
+   * path p with k entries, digest[0] = sum of h(p) mod 2^64 and digest[1] =
+   * xor of h(p) over the set.  It does not depend on the order of the paths,
+   * so the digests of chunks combine by sum and xor. */
+  uint64_t digest[2];
 } tpg_paths;
+
+/* Streaming (TPG_STREAM).  Called on the calling thread, in order, once per
+ * chunk; the chunk (host memory, or device memory with TPG_OUT_DEVICE) is
+ * valid only during the call.  first / end: for prime paths the range of
+ * first vertices [first, end) whose prime paths the chunk holds (the
+ * canonical order is by first vertex, so the chunks concatenate to the
+ * canonical set); for test paths the index range of the chunk's paths in the
+ * canonical set.  A nonzero return stops the call with TPG_ERR_CALLBACK. */
+typedef int32_t (*tpg_chunk_fn)(void* ctx, const tpg_paths* chunk, int64_t first, int64_t end);
 
 typedef struct tpg_stats {
   int64_t n_levels;       /* deepest level (path entries) that held a path   */
@@ -126,6 +149,16 @@ typedef struct tpg_opts {
                                see tpg_batch_test_paths)                    */
   int32_t level_counts_len;
   int32_t reserved_;
+  /* TPG_STREAM.  tpg_prime_paths runs the graph's first vertices in ranges
+   * of chunk_vertices (0: 32) from scratch, so device memory is bounded by
+   * the largest range's path tree, and delivers each range's prime paths;
+   * tpg_test_paths delivers the canonical test paths in chunks of
+   * chunk_paths (0: 1 << 20) paths. */
+  tpg_chunk_fn on_chunk;
+  void* chunk_ctx;
+  int32_t chunk_vertices;
+  int32_t reserved2_;
+  int64_t chunk_paths;
 } tpg_opts;
 
 /* ------------------------------------------------------------------------

@@ -68,6 +68,9 @@ def _load():
         _lib.orc_test_paths.argtypes = [ctypes.c_int, i64p, i32p, ctypes.c_int,
                                         ctypes.c_int, P(_Paths), P(_Paths), i64p]
         _lib.orc_free_paths.argtypes = [P(_Paths)]
+        _lib.orc_fnv1a64.argtypes = [ctypes.c_char_p, ctypes.c_int64]
+        _lib.orc_fnv1a64.restype = ctypes.c_uint64
+        _lib.orc_digest.argtypes = [ctypes.c_int64, i64p, i32p, P(ctypes.c_uint64)]
     return _lib
 
 
@@ -217,6 +220,24 @@ def test_paths(g, pps: PathList) -> Tuple[PathList, int]:
     if rc != 0:
         raise ValueError("a prime path is not reachable from entry or cannot reach exit")
     return _take(out), int(nb.value)
+
+
+def fnv1a64(data: bytes) -> int:
+    """64-bit FNV-1a of a byte string."""
+    return int(_load().orc_fnv1a64(data, len(data)))
+
+
+def digest(pl: PathList) -> Tuple[int, int]:
+    """Order-independent set digest: (sum mod 2^64, xor) of the FNV-1a 64
+    hashes of each path's little-endian int32 bytes (k, v_1 .. v_k)."""
+    out = (ctypes.c_uint64 * 2)()
+    off = np.ascontiguousarray(pl.offsets, dtype=np.int64)
+    vtx = np.ascontiguousarray(pl.vertices, dtype=np.int32)
+    if vtx.size == 0:
+        vtx = np.zeros(1, np.int32)
+    _load().orc_digest(len(off) - 1, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                       vtx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), out)
+    return int(out[0]), int(out[1])
 
 
 def canonical_bytes(pl: PathList) -> bytes:

@@ -540,4 +540,38 @@ int orc_test_paths(int n, const int64_t* row_ptr, const int32_t* col_idx, int en
   return 0;
 }
 
+// FNV-1a, 64-bit (Fowler, Noll and Vo): start from the offset basis
+// 14695981039346656037; for every byte, xor it in, then multiply by the FNV
+// prime 1099511628211 (mod 2^64).
+uint64_t orc_fnv1a64(const uint8_t* bytes, int64_t n) {
+  uint64_t h = 14695981039346656037ull;
+  for (int64_t i = 0; i < n; ++i) {
+    h ^= bytes[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+// Set digest of a path set: for each path p with k entries the hash of the
+// little-endian int32 byte string (k, p_1, .., p_k); out[0] = their sum mod
+// 2^64, out[1] = their xor.
+void orc_digest(int64_t n_paths, const int64_t* offsets, const int32_t* vertices, uint64_t* out) {
+  uint64_t sum = 0, x = 0;
+  std::vector<uint8_t> buf;
+  for (int64_t i = 0; i < n_paths; ++i) {
+    const int64_t k = offsets[i + 1] - offsets[i];
+    buf.clear();
+    auto put = [&](uint32_t w) {
+      for (int b = 0; b < 4; ++b) buf.push_back((uint8_t)(w >> (8 * b)));
+    };
+    put((uint32_t)k);
+    for (int64_t j = offsets[i]; j < offsets[i + 1]; ++j) put((uint32_t)vertices[j]);
+    const uint64_t h = orc_fnv1a64(buf.data(), (int64_t)buf.size());
+    sum += h;
+    x ^= h;
+  }
+  out[0] = sum;
+  out[1] = x;
+}
+
 }  // extern "C"

@@ -99,6 +99,10 @@ struct tpg_workspace {
     hipGraphExec_t exec = nullptr;
   };
   SeqGraph rank_up, rank_down;
+  // level-1 seeds of the next build: first vertices seed_lo .. seed_lo + seed_n - 1
+  // (seed_n < 0: every vertex of the union)
+  int32_t seed_lo = 0, seed_n = -1;
+  DevBuf digest;  // [2] set digest of the last digest_set call
   ExtArgs graph_args{};
   int graph_W = 0, graph_grid = 0, graph_items = 0, graph_variant = 0;
   hipStream_t graph_stream = nullptr;
@@ -278,6 +282,8 @@ ExtArgs make_args(tpg_workspace* ws, int grid = 0) {
   a.t.mask_cap = ws->mask_cap;
   a.t.mask_words = ws->mask_words;
   a.ls = ws->ls.as<LevelState>();
+  a.seed_lo = ws->seed_n >= 0 ? ws->seed_lo : 0;
+  a.seed_n = ws->seed_n >= 0 ? ws->seed_n : ws->dg.n;
   return a;
 }
 
@@ -443,7 +449,7 @@ tpg_status build_tree_onepass(tpg_workspace* ws, const HostUnion& U, hipStream_t
   TPG_HIP(launch_seed(a, st));
   LevelState* dls = ws->ls.as<LevelState>();
   std::vector<int64_t> cnt(kMaxLevels + 1, 0);
-  cnt[1] = U.n;
+  cnt[1] = a.seed_n;
   int L0 = 1;
   // a union seen before: one batch covers its levels and the empty one after
   int batch = (ws->levels_uids == U.uids && ws->levels_last > 0) ? ws->levels_last + 1 : 4;
@@ -545,7 +551,7 @@ tpg_status build_tree_twopass(tpg_workspace* ws, const HostUnion& U, hipStream_t
   R.count.assign(kMaxLevels, 0);
   R.off.assign(kMaxLevels, 0);
   int L = 1;
-  int64_t base = 0, F = U.n, prev = 0;
+  int64_t base = 0, F = a.seed_n, prev = 0;
   R.count[1] = F;
   R.peak = F;
   for (;;) {
@@ -623,7 +629,8 @@ tpg_status rank_and_materialize(tpg_workspace* ws, const HostUnion& U, hipStream
     hipError_t e = launch_zero_u64(ws->cycles.as<uint64_t>(), 1, st);
     for (int L = R.Lmax; L >= 1 && e == hipSuccess; --L)
       e = launch_up(a, L, R.off[L], R.count[L], sc, ws->cycles.as<unsigned long long>(), st);
-    if (e == hipSuccess) e = launch_roots(a, U.n, sc, nullptr, nullptr, ws->totals.as<int64_t>(), 0, st);
+    if (e == hipSuccess)
+      e = launch_roots(a, R.count[1], sc, nullptr, nullptr, ws->totals.as<int64_t>(), 0, st);
     return e;
   }));
   TPG_HIP(hipMemcpyAsync(ws->h_scalars, ws->totals.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -641,7 +648,7 @@ tpg_status rank_and_materialize(tpg_workspace* ws, const HostUnion& U, hipStream
   key_add(key_down, lbr);
   key_add(key_down, len);
   TPG_TRY(run_seq(ws->rank_down, std::move(key_down), st, [&]() -> hipError_t {
-    hipError_t e = launch_roots(a, U.n, sc, lbr, len, ws->totals.as<int64_t>(), 1, st);
+    hipError_t e = launch_roots(a, R.count[1], sc, lbr, len, ws->totals.as<int64_t>(), 1, st);
     for (int L = 1; L < R.Lmax && e == hipSuccess; ++L)
       e = launch_down(a, L, R.off[L], R.count[L], sc, lbr, len, st);
     return e;
@@ -818,6 +825,36 @@ tpg_status export_paths(const DevBuf& off, const DevBuf& vtx, int64_t n, int64_t
   return TPG_OK;
 }
 
+// Digest of paths [0, n) of a device set (see tpg_paths.digest).
+tpg_status digest_set(tpg_workspace* ws, const DevBuf& off, const DevBuf& vtx, int64_t n,
+                      hipStream_t st, uint64_t out[2]) {
+  TPG_TRY(ws_reserve(ws, ws->digest, 2 * sizeof(uint64_t)));
+  TPG_HIP(launch_digest(off.as<int64_t>(), vtx.as<int32_t>(), n, ws->digest.as<uint64_t>(), st));
+  TPG_HIP(hipMemcpyAsync(ws->h_scalars + 12, ws->digest.p, 2 * sizeof(uint64_t),
+                         hipMemcpyDeviceToHost, st));
+  TPG_HIP(hipStreamSynchronize(st));
+  out[0] = (uint64_t)ws->h_scalars[12];
+  out[1] = (uint64_t)ws->h_scalars[13];
+  return TPG_OK;
+}
+
+// Result set into *out as the flags ask: arrays (host or device), digest.
+tpg_status deliver_set(tpg_workspace* ws, const DevBuf& off, const DevBuf& vtx, int64_t n,
+                       int64_t nv, uint32_t flags, hipStream_t st, tpg_paths* out) {
+  uint64_t dg[2] = {0, 0};
+  if (flags & (TPG_DIGEST | TPG_DIGEST_ONLY)) TPG_TRY(digest_set(ws, off, vtx, n, st, dg));
+  if (flags & TPG_DIGEST_ONLY) {
+    memset(out, 0, sizeof *out);
+    out->n_paths = n;
+    out->n_vertices = nv;
+  } else {
+    TPG_TRY(export_paths(off, vtx, n, nv, flags & TPG_OUT_DEVICE, st, out));
+  }
+  out->digest[0] = dg[0];
+  out->digest[1] = dg[1];
+  return TPG_OK;
+}
+
 struct CallCtx {
   tpg_workspace* ws = nullptr;
   bool own_ws = false;
@@ -850,6 +887,8 @@ tpg_status begin_call(const tpg_opts* opts, CallCtx& c) {
     return fail(TPG_ERR_CAPACITY, "workspace already holds %zu bytes (cap %llu)", c.ws->bytes,
                 (unsigned long long)c.ws->cap);
   if (c.ws->out.empty()) c.ws->out.resize(1);
+  c.ws->seed_lo = 0;
+  c.ws->seed_n = -1;
   return TPG_OK;
 }
 
@@ -872,7 +911,7 @@ void add_stats(tpg_stats* s, const HostUnion& U, const TreeResult& R, const PPRe
                const TPResult* T) {
   s->n_levels = std::max<int64_t>(s->n_levels, R.Lmax);
   s->n_nodes += R.n_nodes;
-  s->n_extensions += R.n_nodes - U.n;
+  s->n_extensions += R.n_nodes - R.count[1];
   s->n_cycles += P.n_cycles;
   s->n_pp += P.n_pp;
   s->n_pp_vertices += P.n_vtx;
@@ -890,6 +929,111 @@ void add_stats(tpg_stats* s, const HostUnion& U, const TreeResult& R, const PPRe
 
 tpg_status check_graph(const tpg_graph* g) {
   if (!g) return fail(TPG_ERR_INVALID_ARG, "graph is NULL");
+  return TPG_OK;
+}
+
+// Hands one chunk to the caller: host copies (freed right after the call)
+// or device pointers.
+tpg_status call_chunk(CallCtx& c, const tpg_paths& chunk, int64_t first, int64_t end) {
+  const int32_t r = c.opts->on_chunk(c.opts->chunk_ctx, &chunk, first, end);
+  if (r != 0) return fail(TPG_ERR_CALLBACK, "on_chunk returned %d for [%lld, %lld)", r,
+                          (long long)first, (long long)end);
+  return TPG_OK;
+}
+
+// TPG_STREAM for prime paths: the first vertices in ranges of
+// chunk_vertices, each range a fresh path tree (so device memory is bounded
+// by the largest range's tree); prime paths grouped by first vertex are
+// exactly the canonical order's consecutive blocks, so the chunks
+// concatenate to the canonical set.
+tpg_status prime_paths_stream(const tpg_graph* g, CallCtx& c, tpg_paths* out) {
+  if (!c.opts || !c.opts->on_chunk) return fail(TPG_ERR_INVALID_ARG, "TPG_STREAM needs opts.on_chunk");
+  if (c.opts->chunk_vertices < 0) return fail(TPG_ERR_INVALID_ARG, "chunk_vertices < 0");
+  HostUnion U;
+  add_component(U, g);
+  const int32_t cv = c.opts->chunk_vertices > 0 ? c.opts->chunk_vertices : 32;
+  Timer tm{c.ws, c.st, false};
+  tpg_stats acc{};
+  std::vector<int64_t> levels;
+  uint64_t dg[2] = {0, 0};
+  OutSet& o = c.ws->out[0];
+  for (int32_t lo = 0; lo < U.n; lo += cv) {
+    c.ws->seed_lo = lo;
+    c.ws->seed_n = std::min(cv, U.n - lo);
+    TreeResult R;
+    PPResult P;
+    TPG_TRY(run_pp(U, c, tm, R, P, o, nullptr));
+    uint64_t cd[2];
+    TPG_TRY(digest_set(c.ws, o.pp_off, o.pp_vtx, P.n_pp, c.st, cd));
+    dg[0] += cd[0];
+    dg[1] ^= cd[1];
+    tpg_paths chunk;
+    TPG_TRY(export_paths(o.pp_off, o.pp_vtx, P.n_pp, P.n_vtx, c.flags & TPG_OUT_DEVICE, c.st, &chunk));
+    chunk.digest[0] = cd[0];
+    chunk.digest[1] = cd[1];
+    const tpg_status rc = call_chunk(c, chunk, lo, lo + c.ws->seed_n);
+    tpg_paths_free(&chunk);
+    TPG_TRY(rc);
+    out->n_paths += P.n_pp;
+    out->n_vertices += P.n_vtx;
+    add_stats(&acc, U, R, P, nullptr);
+    if ((int)levels.size() <= R.Lmax) levels.resize(R.Lmax + 1, 0);
+    for (int L = 1; L <= R.Lmax; ++L) levels[L] += R.count[L];
+  }
+  c.ws->seed_n = -1;
+  out->digest[0] = dg[0];
+  out->digest[1] = dg[1];
+  if (c.stats) {
+    *c.stats = acc;
+    c.stats->n_unions = 1;
+    c.stats->device_bytes = (int64_t)c.ws->bytes;
+  }
+  if (c.opts->level_counts)
+    for (int L = 0; L < c.opts->level_counts_len; ++L)
+      c.opts->level_counts[L] = L < (int)levels.size() ? levels[L] : 0;
+  return TPG_OK;
+}
+
+// TPG_STREAM for test paths: the canonical set in chunks of chunk_paths,
+// each with offsets rebased to its own entries.
+tpg_status test_paths_stream_out(CallCtx& c, const OutSet& o, int64_t n_tp) {
+  if (c.opts->chunk_paths < 0) return fail(TPG_ERR_INVALID_ARG, "chunk_paths < 0");
+  const int64_t cp = c.opts->chunk_paths > 0 ? c.opts->chunk_paths : (int64_t)1 << 20;
+  const bool dev = c.flags & TPG_OUT_DEVICE;
+  std::vector<int64_t> off;
+  std::vector<int32_t> vtx;
+  DevBuf& doff = c.ws->tp_len;  // scratch for rebased device offsets (free after the sort)
+  if (dev) TPG_TRY(ws_reserve(c.ws, doff, sizeof(int64_t) * (std::min(cp, n_tp) + 1)));
+  for (int64_t k = 0; k < n_tp; k += cp) {
+    const int64_t cnt = std::min(cp, n_tp - k);
+    off.resize(cnt + 1);
+    TPG_HIP(hipMemcpyAsync(off.data(), o.tp_off.as<int64_t>() + k, sizeof(int64_t) * (cnt + 1),
+                           hipMemcpyDeviceToHost, c.st));
+    TPG_HIP(hipStreamSynchronize(c.st));
+    const int64_t v0 = off[0], nv = off[cnt] - v0;
+    for (auto& x : off) x -= v0;
+    tpg_paths chunk;
+    memset(&chunk, 0, sizeof chunk);
+    chunk.n_paths = cnt;
+    chunk.n_vertices = nv;
+    if (dev) {
+      TPG_HIP(hipMemcpyAsync(doff.p, off.data(), sizeof(int64_t) * (cnt + 1), hipMemcpyHostToDevice,
+                             c.st));
+      TPG_HIP(hipStreamSynchronize(c.st));
+      chunk.on_device = 1;
+      chunk.offsets = doff.as<int64_t>();
+      chunk.vertices = o.tp_vtx.as<int32_t>() + v0;
+    } else {
+      vtx.resize(nv > 0 ? nv : 1);
+      if (nv)
+        TPG_HIP(hipMemcpyAsync(vtx.data(), o.tp_vtx.as<int32_t>() + v0, sizeof(int32_t) * nv,
+                               hipMemcpyDeviceToHost, c.st));
+      TPG_HIP(hipStreamSynchronize(c.st));
+      chunk.offsets = off.data();
+      chunk.vertices = vtx.data();
+    }
+    TPG_TRY(call_chunk(c, chunk, k, k + cnt));
+  }
   return TPG_OK;
 }
 
@@ -955,7 +1099,7 @@ void tpg_workspace_free(tpg_workspace* ws) {
                     &ws->pfx, &ws->sfx, &ws->tp_len, &ws->tp_off, &ws->tp_vtx, &ws->tp_key, &ws->idx0,
                     &ws->idx1, &ws->grp_cnt, &ws->rb0, &ws->rb1, &ws->keep_cnt, &ws->keep_len,
                     &ws->keep_pos, &ws->keep_voff, &ws->comp_cnt, &ws->lvl_comp, &ws->b_pp_off,
-                    &ws->scan2_status, &ws->scalars2,
+                    &ws->scan2_status, &ws->scalars2, &ws->digest,
                     &ws->b_pp_vtx, &ws->b_tp_off, &ws->b_tp_vtx, &ws->b_desc};
   for (DevBuf* b : bufs) ws_release(ws, *b);
   for (OutSet& o : ws->out) {
@@ -986,6 +1130,7 @@ tpg_status tpg_prime_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* 
   TPG_TRY(check_graph(g));
   CallCtx c;
   TPG_TRY(begin_call(opts, c));
+  if (c.flags & TPG_STREAM) return prime_paths_stream(g, c, out);
   HostUnion U;
   add_component(U, g);
   Timer tm{c.ws, c.st, c.stats != nullptr && !(c.flags & TPG_NO_TIMING)};
@@ -1001,8 +1146,7 @@ tpg_status tpg_prime_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* 
   OutSet& o = c.ws->out[0];
   tpg_status s = run_pp(U, c, tm, R, P, o, &ext_done);
   if (s == TPG_OK && timing) TPG_HIP(hipEventRecord(phase[1], c.st));
-  if (s == TPG_OK)
-    s = export_paths(o.pp_off, o.pp_vtx, P.n_pp, P.n_vtx, c.flags & TPG_OUT_DEVICE, c.st, out);
+  if (s == TPG_OK) s = deliver_set(c.ws, o.pp_off, o.pp_vtx, P.n_pp, P.n_vtx, c.flags, c.st, out);
   if (s == TPG_OK) {
     TPG_HIP(hipStreamSynchronize(c.st));
     if (c.stats) {
@@ -1034,6 +1178,8 @@ tpg_status tpg_test_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* p
     return fail(TPG_ERR_UNREACHABLE, "test paths need a graph loaded with the entry/exit checks");
   CallCtx c;
   TPG_TRY(begin_call(opts, c));
+  if ((c.flags & TPG_STREAM) && (!c.opts || !c.opts->on_chunk))
+    return fail(TPG_ERR_INVALID_ARG, "TPG_STREAM needs opts.on_chunk");
   HostUnion U;
   add_component(U, g);
   Timer tm{c.ws, c.st, c.stats != nullptr && !(c.flags & TPG_NO_TIMING)};
@@ -1052,9 +1198,12 @@ tpg_status tpg_test_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* p
   if (s == TPG_OK && timing) TPG_HIP(hipEventRecord(phase[1], c.st));
   if (s == TPG_OK) s = test_paths_device(c.ws, U, c.st, P, T, o);
   if (s == TPG_OK && timing) TPG_HIP(hipEventRecord(phase[2], c.st));
-  const bool dev = c.flags & TPG_OUT_DEVICE;
-  if (s == TPG_OK && pp_out) s = export_paths(o.pp_off, o.pp_vtx, P.n_pp, P.n_vtx, dev, c.st, pp_out);
-  if (s == TPG_OK) s = export_paths(o.tp_off, o.tp_vtx, T.n_tp, T.n_vtx, dev, c.st, tp_out);
+  // with TPG_STREAM the sets come back as counts and digests and the test
+  // paths go through on_chunk
+  const uint32_t fl = (c.flags & TPG_STREAM) ? (c.flags | TPG_DIGEST_ONLY) : c.flags;
+  if (s == TPG_OK && pp_out) s = deliver_set(c.ws, o.pp_off, o.pp_vtx, P.n_pp, P.n_vtx, fl, c.st, pp_out);
+  if (s == TPG_OK) s = deliver_set(c.ws, o.tp_off, o.tp_vtx, T.n_tp, T.n_vtx, fl, c.st, tp_out);
+  if (s == TPG_OK && (c.flags & TPG_STREAM)) s = test_paths_stream_out(c, o, T.n_tp);
   if (s == TPG_OK) {
     TPG_HIP(hipStreamSynchronize(c.st));
     if (c.stats) {

@@ -56,6 +56,7 @@ const char* tpg_status_str(tpg_status s) {
     case TPG_ERR_CAPACITY: return "pool capacity exceeded";
     case TPG_ERR_DEVICE: return "device error";
     case TPG_ERR_UNSUPPORTED: return "unsupported input";
+    case TPG_ERR_CALLBACK: return "stopped by the chunk callback";
   }
   return "unknown status";
 }

@@ -44,6 +44,10 @@ struct ExtArgs {
   TreeBufs t;
   LevelState* ls;
   int64_t tiles_target;  // one-pass tiles per level aimed at (tile size grows above it)
+  // level 1: paths <v> for the first vertices v = seed_lo .. seed_lo + seed_n - 1
+  // (node k holds vertex seed_lo + k; all vertices unless a call streams by
+  // first-vertex range)
+  int32_t seed_lo, seed_n;
 };
 
 // --- path tree -------------------------------------------------------------
@@ -90,6 +94,11 @@ hipError_t scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t add, int
 int64_t scan_tiles(int64_t n);  // status slots needed by the scans for n items
 
 hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t st);
+// Set digest of paths [0, n) (offsets off, entries vtx): out[0] = sum and
+// out[1] = xor of the per-path FNV-1a 64 hashes of (k, v_1 .. v_k) as int32
+// little-endian bytes; out is cleared first.
+hipError_t launch_digest(const int64_t* off, const int32_t* vtx, int64_t n, uint64_t* out,
+                         hipStream_t st);
 hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t st);
 
 // --- test paths --------------------------------------------------------------

@@ -50,7 +50,7 @@ namespace tpg {
 // level 1
 // ---------------------------------------------------------------------------
 __global__ void k_seed(ExtArgs a) {
-  const int n = a.g.n;
+  const int n = a.seed_n;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   LevelState* ls = a.ls;
   // every level's claim counter starts at zero
@@ -64,22 +64,23 @@ __global__ void k_seed(ExtArgs a) {
     ls->overflow_level = 0;
   }
   if (i < n) {
-    const int v = (int)i;
-    a.t.par[v] = -1;
-    a.t.info[v] = make_info(v, a.g.loc[v], 0);
+    const int v = a.seed_lo + (int)i;
+    a.t.par[i] = -1;
+    a.t.info[i] = make_info(v, a.g.loc[v], 0);
   }
   // visited sets of level 1 (stored, buffer 0): one bit each, at the
   // vertex's local id
   const int W = a.t.mask_words;
   for (int64_t k = i; k < (int64_t)n * W; k += (int64_t)gridDim.x * blockDim.x) {
-    const int q = (int)(k / n), v = (int)(k % n);
-    const int l = a.g.loc[v];
-    a.t.mask[0][(int64_t)q * a.t.mask_cap + v] = (q == (l >> 6)) ? (1ull << (l & 63)) : 0ull;
+    const int q = (int)(k / n), j = (int)(k % n);
+    const int l = a.g.loc[a.seed_lo + j];
+    a.t.mask[0][(int64_t)q * a.t.mask_cap + j] = (q == (l >> 6)) ? (1ull << (l & 63)) : 0ull;
   }
 }
 
 hipError_t launch_seed(const ExtArgs& a, hipStream_t st) {
-  const int64_t work = std::max<int64_t>(kMaxLevels, (int64_t)a.g.n * a.t.mask_words);
+  if (a.seed_lo < 0 || a.seed_n < 1 || a.seed_lo + a.seed_n > a.g.n) return hipErrorInvalidValue;
+  const int64_t work = std::max<int64_t>(kMaxLevels, (int64_t)a.seed_n * a.t.mask_words);
   const int grid = (int)std::min<int64_t>(1024, (work + kBlock - 1) / kBlock + 1);
   k_seed<<<grid, kBlock, 0, st>>>(a);
   return hipGetLastError();

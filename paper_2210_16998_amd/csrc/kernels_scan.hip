@@ -28,6 +28,49 @@ hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t st) {
   k_zero_u64<<<(unsigned)std::min<int64_t>(1024, (n + kBlock - 1) / kBlock), kBlock, 0, st>>>(p, n);
   return hipGetLastError();
 }
+// FNV-1a 64 over the int32 little-endian bytes (k, v_1 .. v_k) of each path,
+// one thread per path; sums and xors are reduced per wave and added to out
+// with one 64-bit atomic pair per wave.
+__device__ __forceinline__ uint64_t fnv1a_word(uint64_t h, uint32_t w) {
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    h ^= (w >> (8 * b)) & 0xFFu;
+    h *= 0x100000001b3ull;
+  }
+  return h;
+}
+
+__global__ __launch_bounds__(kBlock) void k_digest(const int64_t* off, const int32_t* vtx, int64_t n,
+                                                   unsigned long long* out) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  uint64_t h = 0;
+  bool have = i < n;
+  if (have) {
+    const int64_t o0 = off[i], o1 = off[i + 1];
+    h = fnv1a_word(0xcbf29ce484222325ull, (uint32_t)(o1 - o0));
+    for (int64_t k = o0; k < o1; ++k) h = fnv1a_word(h, (uint32_t)vtx[k]);
+  }
+  uint64_t sum = have ? h : 0, x = have ? h : 0;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    sum += __shfl_xor(sum, d, 64);
+    x ^= __shfl_xor(x, d, 64);
+  }
+  if (lane_id() == 0) {
+    atomicAdd(&out[0], (unsigned long long)sum);
+    atomicXor(&out[1], (unsigned long long)x);
+  }
+}
+
+hipError_t launch_digest(const int64_t* off, const int32_t* vtx, int64_t n, uint64_t* out,
+                         hipStream_t st) {
+  k_zero_u64<<<1, 64, 0, st>>>(out, 2);
+  if (n > 0)
+    k_digest<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+        off, vtx, n, reinterpret_cast<unsigned long long*>(out));
+  return hipGetLastError();
+}
+
 hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   k_zero_u32<<<(unsigned)std::min<int64_t>(1024, (n + kBlock - 1) / kBlock), kBlock, 0, st>>>(p, n);

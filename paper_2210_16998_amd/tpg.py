@@ -21,11 +21,14 @@ TPG_LOAD_ANY_DIGRAPH = 0x2
 TPG_OUT_DEVICE = 0x1
 TPG_FORCE_TWO_PASS = 0x2
 TPG_NO_TIMING = 0x4
+TPG_DIGEST = 0x8
+TPG_DIGEST_ONLY = 0x10
+TPG_STREAM = 0x20
 
 STATUS = {0: "TPG_OK", -1: "TPG_ERR_INVALID_ARG", -2: "TPG_ERR_BAD_CSR",
           -3: "TPG_ERR_BAD_ENTRY_EXIT", -4: "TPG_ERR_UNREACHABLE",
           -5: "TPG_ERR_OOM_HOST", -6: "TPG_ERR_OOM_DEVICE", -7: "TPG_ERR_CAPACITY",
-          -8: "TPG_ERR_DEVICE", -9: "TPG_ERR_UNSUPPORTED"}
+          -8: "TPG_ERR_DEVICE", -9: "TPG_ERR_UNSUPPORTED", -10: "TPG_ERR_CALLBACK"}
 
 
 class TpgError(RuntimeError):
@@ -38,7 +41,13 @@ class TpgError(RuntimeError):
 class _Paths(ctypes.Structure):
     _fields_ = [("n_paths", ctypes.c_int64), ("n_vertices", ctypes.c_int64),
                 ("offsets", ctypes.c_void_p), ("vertices", ctypes.c_void_p),
-                ("on_device", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+                ("on_device", ctypes.c_int32), ("reserved_", ctypes.c_int32),
+                ("digest", ctypes.c_uint64 * 2)]
+
+
+# int32 (*)(void* ctx, const tpg_paths* chunk, int64 first, int64 end)
+_CHUNK_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(_Paths),
+                             ctypes.c_int64, ctypes.c_int64)
 
 
 class _Stats(ctypes.Structure):
@@ -60,7 +69,10 @@ class _Opts(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("ws", ctypes.c_void_p),
                 ("pool_cap_bytes", ctypes.c_uint64), ("stats", ctypes.POINTER(_Stats)),
                 ("level_counts", ctypes.POINTER(ctypes.c_int64)),
-                ("level_counts_len", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+                ("level_counts_len", ctypes.c_int32), ("reserved_", ctypes.c_int32),
+                ("on_chunk", _CHUNK_FN), ("chunk_ctx", ctypes.c_void_p),
+                ("chunk_vertices", ctypes.c_int32), ("reserved2_", ctypes.c_int32),
+                ("chunk_paths", ctypes.c_int64)]
 
 
 class _BatchResult(ctypes.Structure):
@@ -244,18 +256,34 @@ class Workspace:
             pass
 
 
-class HostPaths:
-    """Host result: offsets int64 [n+1], vertices int32 (copied out of the
-    library-owned arrays, which are then released)."""
+class SetDigest:
+    """Counts and digest of a set returned without arrays (TPG_DIGEST_ONLY,
+    TPG_STREAM)."""
 
     def __init__(self, p: _Paths) -> None:
+        self.n_paths = int(p.n_paths)
+        self.n_vertices = int(p.n_vertices)
+        self.digest = (int(p.digest[0]), int(p.digest[1]))
+
+    def __len__(self) -> int:
+        return self.n_paths
+
+
+class HostPaths:
+    """Host result: offsets int64 [n+1], vertices int32 (copied out of the
+    library-owned arrays, which are then released unless `owned` is False,
+    as for a streamed chunk the library releases itself)."""
+
+    def __init__(self, p: _Paths, owned: bool = True) -> None:
         n, nv = p.n_paths, p.n_vertices
         self.offsets = np.ctypeslib.as_array(
             ctypes.cast(p.offsets, ctypes.POINTER(ctypes.c_int64)), shape=(n + 1,)).copy()
         self.vertices = (np.ctypeslib.as_array(
             ctypes.cast(p.vertices, ctypes.POINTER(ctypes.c_int32)), shape=(nv,)).copy()
             if nv else np.zeros(0, np.int32))
-        lib().tpg_paths_free(ctypes.byref(p))
+        self.digest = (int(p.digest[0]), int(p.digest[1]))
+        if owned:
+            lib().tpg_paths_free(ctypes.byref(p))
 
     def __len__(self) -> int:
         return len(self.offsets) - 1
@@ -282,6 +310,7 @@ class DevicePaths:
         self.n_vertices = int(p.n_vertices)
         self.offsets_ptr = int(p.offsets or 0)
         self.vertices_ptr = int(p.vertices or 0)
+        self.digest = (int(p.digest[0]), int(p.digest[1]))
 
     def __len__(self) -> int:
         return self.n_paths
@@ -294,6 +323,12 @@ class DevicePaths:
         vtx = torch.as_tensor(_CudaArray(self.vertices_ptr, max(self.n_vertices, 1), "<i4"),
                               device="cuda")
         return off, vtx[:self.n_vertices]
+
+
+def _wrap(p: _Paths):
+    if not p.offsets:
+        return SetDigest(p)
+    return DevicePaths(p) if p.on_device else HostPaths(p)
 
 
 def _opts(ws: Optional[Workspace], flags: int, stream, stats: Optional[_Stats],
@@ -323,8 +358,7 @@ def prime_paths(g: Graph, ws: Optional[Workspace] = None, flags: int = 0, stream
     o = _opts(ws, flags, stream, st, pool_cap, level_counts)
     out = _Paths()
     _check(lib().tpg_prime_paths(g.handle, ctypes.byref(o), ctypes.byref(out)))
-    res = DevicePaths(out) if out.on_device else HostPaths(out)
-    return res, _stats_dict(st)
+    return _wrap(out), _stats_dict(st)
 
 
 def test_paths(g: Graph, ws: Optional[Workspace] = None, flags: int = 0, stream=None,
@@ -335,8 +369,58 @@ def test_paths(g: Graph, ws: Optional[Workspace] = None, flags: int = 0, stream=
     pp, tp = _Paths(), _Paths()
     _check(lib().tpg_test_paths(g.handle, ctypes.byref(o),
                                 ctypes.byref(pp) if want_pp else None, ctypes.byref(tp)))
-    wrap = DevicePaths if tp.on_device else HostPaths
-    return (wrap(pp) if want_pp else None), wrap(tp), _stats_dict(st)
+    return (_wrap(pp) if want_pp else None), _wrap(tp), _stats_dict(st)
+
+
+def _stream_call(fn, on_chunk, o: _Opts, *args):
+    """Runs fn with a ctypes trampoline for on_chunk(chunk, first, end); the
+    chunk is HostPaths (copied) or DevicePaths (valid during the call only).
+    A truthy return, or an exception, stops the call."""
+    err = []
+
+    def tramp(_ctx, p, first, end):
+        try:
+            c = p.contents
+            chunk = DevicePaths(c) if c.on_device else HostPaths(c, owned=False)
+            return 1 if on_chunk(chunk, int(first), int(end)) else 0
+        except BaseException as e:  # surfaced after the call returns
+            err.append(e)
+            return 1
+    cb = _CHUNK_FN(tramp)
+    o.on_chunk = cb
+    rc = fn(*args)
+    if err:
+        raise err[0]
+    _check(rc)
+
+
+def prime_paths_stream(g: Graph, on_chunk, ws: Optional[Workspace] = None, flags: int = 0,
+                       stream=None, chunk_vertices: int = 0, pool_cap: int = 0):
+    """Prime paths delivered first-vertex range by range (TPG_STREAM):
+    on_chunk(chunk, first, end) gets the prime paths whose first vertex lies
+    in [first, end), in canonical order.  Returns (SetDigest of the whole
+    set, stats)."""
+    st = _Stats()
+    o = _opts(ws, flags | TPG_STREAM, stream, st, pool_cap)
+    o.chunk_vertices = int(chunk_vertices)
+    out = _Paths()
+    _stream_call(lib().tpg_prime_paths, on_chunk, o, g.handle, ctypes.byref(o), ctypes.byref(out))
+    return SetDigest(out), _stats_dict(st)
+
+
+def test_paths_stream(g: Graph, on_chunk, ws: Optional[Workspace] = None, flags: int = 0,
+                      stream=None, chunk_paths: int = 0, pool_cap: int = 0):
+    """Test paths delivered in chunks of chunk_paths (TPG_STREAM):
+    on_chunk(chunk, first, end) gets canonical test paths [first, end).
+    Returns (SetDigest of the prime paths, SetDigest of the test paths,
+    stats)."""
+    st = _Stats()
+    o = _opts(ws, flags | TPG_STREAM, stream, st, pool_cap)
+    o.chunk_paths = int(chunk_paths)
+    pp, tp = _Paths(), _Paths()
+    _stream_call(lib().tpg_test_paths, on_chunk, o, g.handle, ctypes.byref(o), ctypes.byref(pp),
+                 ctypes.byref(tp))
+    return SetDigest(pp), SetDigest(tp), _stats_dict(st)
 
 
 def version() -> str:

@@ -266,3 +266,33 @@ def test_self_loop_is_a_prime_path():
     pp, _, _, _ = _pp(g)
     assert pp.tolist() == oracle.bruteforce_pp(g)[0].tolist()
     assert [1, 1] in pp.tolist()
+
+
+# --- set digest (streaming and digest-only results) ------------------------
+
+def test_fnv1a64_published_vectors():
+    # test vectors of the 64-bit FNV-1a hash as published with its definition
+    assert oracle.fnv1a64(b"") == 0xcbf29ce484222325
+    assert oracle.fnv1a64(b"a") == 0xaf63dc4c8601ec8c
+    assert oracle.fnv1a64(b"foobar") == 0x85944171f73967e8
+
+
+def test_digest_is_a_multiset_digest_of_path_bytes():
+    paths = [[0, 1, 2], [3], [2, 5, 2], [4, 4]]
+
+    def pl(ps):
+        off = np.cumsum([0] + [len(p) for p in ps]).astype(np.int64)
+        return PathList(off, np.array([v for p in ps for v in p], np.int32))
+    d = oracle.digest(pl(paths))
+    # one path: the FNV-1a of its little-endian int32 bytes (k, v_1 .. v_k)
+    h = [oracle.fnv1a64(np.array([len(p)] + p, "<i4").tobytes()) for p in paths]
+    assert oracle.digest(pl(paths[:1])) == (h[0], h[0])
+    assert d == (sum(h) % (1 << 64), h[0] ^ h[1] ^ h[2] ^ h[3])
+    # independent of order, split into chunks it combines by sum and xor
+    assert oracle.digest(pl(paths[::-1])) == d
+    a, b = oracle.digest(pl(paths[:2])), oracle.digest(pl(paths[2:]))
+    assert ((a[0] + b[0]) % (1 << 64), a[1] ^ b[1]) == d
+    # any change of an entry or a length changes it
+    assert oracle.digest(pl([[0, 1, 2], [3], [2, 5, 3], [4, 4]])) != d
+    assert oracle.digest(pl([[0, 1], [2], [3], [2, 5, 2], [4, 4]])) != d
+    assert oracle.digest(pl([])) == (0, 0)
