@@ -135,6 +135,44 @@ def _stress(args, copy_gbs: float):
                          "avg_launch_ms": avg}}
 
 
+def _paper_form(args):
+    """The same CFG in the paper's input form (switch vertices binarized to
+    out-degree 2 at load): whole path per step, and the prime paths grouped by
+    last vertex (the paper's per-end-vertex output) against canonical order."""
+    import torch
+    from paper_2210_16998_amd import tpg
+    g, rec = _workload()
+    h = tpg.load_cfg(g, tpg.TPG_LOAD_BINARIZE)
+    n_b, m_b, _, _ = h.info()
+    ws = tpg.Workspace(0)
+    stream = torch.cuda.Stream()
+    f = tpg.TPG_OUT_DEVICE | tpg.TPG_NO_TIMING
+
+    def timed(fn, reps):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return 1000.0 * (time.perf_counter() - t) / reps
+
+    ms = timed(lambda: tpg.test_paths(h, ws=ws, flags=f, stream=stream), args.steps)
+    _, _, st = tpg.test_paths(h, ws=ws, flags=tpg.TPG_OUT_DEVICE, stream=stream)
+    h0 = tpg.load_cfg(g)
+    ms_pp = timed(lambda: tpg.prime_paths(h0, ws=ws, flags=f, stream=stream), args.steps)
+    ms_last = timed(lambda: tpg.prime_paths(h0, ws=ws, flags=f | tpg.TPG_ORDER_BY_LAST,
+                                            stream=stream), args.steps)
+    ws.close()
+    return {"workload": f"the benchmark CFG binarized: {n_b} vertices, {m_b} arcs (from {g.n}, "
+                        f"{g.n_edges})",
+            "n_pp": st["n_pp"], "n_extensions": st["n_extensions"], "n_tp": st["n_tp"],
+            "ms_per_step": ms, "prime_paths_per_s": st["n_pp"] / (ms * 1e-3),
+            "grouped_by_last": {"prime_paths_ms": ms_pp, "grouped_ms": ms_last,
+                                "overhead_ms": ms_last - ms_pp}}
+
+
 def _cpu_baseline(g, reps: int):
     """The CPU oracle on the same graph (DFS enumeration from every vertex,
     local-rule prime test, splice + sort + dedup of test paths)."""
@@ -172,6 +210,7 @@ def main() -> int:
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--no-stress", action="store_true")
     ap.add_argument("--stress-reps", type=int, default=3)
+    ap.add_argument("--no-paper-form", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is "
@@ -285,6 +324,8 @@ def main() -> int:
     }
     if not args.no_stress:
         out["stress"] = _stress(args, copy_gbs)
+    if not args.no_paper_form:
+        out["paper_form"] = _paper_form(args)
     if not args.no_batch:
         out["batched"] = _batched(args)
     if not args.no_cpu:

@@ -69,6 +69,16 @@ typedef enum tpg_status {
 #define TPG_LOAD_ANY_DIGRAPH 0x2u     /* skip the entry/exit degree and reachability
                                          checks (prime paths of any digraph; test
                                          paths then need those checks to hold)   */
+#define TPG_LOAD_BINARIZE 0x4u        /* the paper's input form (Sec. 3): every vertex
+                                         of out-degree k > 2 keeps its first
+                                         successor and hands the rest to a chain of
+                                         k - 2 new decision vertices (ids n, n+1, ..
+                                         in vertex order), x_i -> {s_(i+1), x_(i+1)}
+                                         and the last -> {s_(k-1), s_k}, successors
+                                         ascending; every vertex then has out-degree
+                                         <= 2 and the graph's prime paths are those of
+                                         the transformed graph (ids >= n are the new
+                                         vertices; tpg_graph_info reports its size) */
 
 /* opts.flags */
 #define TPG_OUT_DEVICE 0x1u     /* results stay in device memory owned by the
@@ -82,6 +92,11 @@ typedef enum tpg_status {
 #define TPG_STREAM 0x20u        /* deliver the results through opts.on_chunk
                                    (see tpg_chunk_fn); *out then holds only the
                                    counts and the digest of the whole set      */
+#define TPG_ORDER_BY_LAST 0x40u /* prime paths grouped by their last vertex (the
+                                   paper's per-end-vertex output, Problem 1):
+                                   ascending last vertex, canonical order inside
+                                   a group; test paths keep the canonical order;
+                                   not with TPG_STREAM                          */
 
 typedef struct tpg_graph tpg_graph;         /* opaque, host memory */
 typedef struct tpg_workspace tpg_workspace; /* opaque: device arena + stream */

@@ -222,6 +222,38 @@ def test_paths(g, pps: PathList) -> Tuple[PathList, int]:
     return _take(out), int(nb.value)
 
 
+def binarize(g):
+    """The paper's input form (Sec. 3): a vertex of out-degree k > 2 keeps its
+    first (smallest) successor and passes the others to a chain of k - 2 new
+    decision vertices, numbered from n upward in vertex order; chain vertex i
+    leads to successor i + 1 and to the next chain vertex, the last one to the
+    two largest successors.  Returns a graph with the same entry and exit."""
+    from paper_2210_16998_amd.cfggen import from_edges
+    rp, ci = np.asarray(g.row_ptr), np.asarray(g.col_idx)
+    edges, nid = [], g.n
+    for v in range(g.n):
+        succ = sorted(set(int(w) for w in ci[rp[v]:rp[v + 1]]))
+        if len(succ) <= 2:
+            edges += [(v, w) for w in succ]
+            continue
+        at = v
+        for i in range(len(succ) - 2):
+            edges += [(at, succ[i]), (at, nid)]
+            at = nid
+            nid += 1
+        edges += [(at, succ[-2]), (at, succ[-1])]
+    return from_edges(nid, edges, g.entry, g.exit, name=f"{g.name}_bin")
+
+
+def group_by_last(pl: PathList) -> PathList:
+    """Prime paths grouped by last vertex: ascending last vertex, the given
+    (canonical) order inside a group."""
+    order = sorted(range(len(pl)), key=lambda i: (int(pl.vertices[pl.offsets[i + 1] - 1]), i))
+    rows = [pl.vertices[pl.offsets[i]:pl.offsets[i + 1]] for i in order]
+    off = np.cumsum([0] + [len(r) for r in rows]).astype(np.int64)
+    return PathList(off, np.concatenate(rows) if rows else np.zeros(0, np.int32))
+
+
 def fnv1a64(data: bytes) -> int:
     """64-bit FNV-1a of a byte string."""
     return int(_load().orc_fnv1a64(data, len(data)))

@@ -19,6 +19,7 @@ namespace {
 // Outputs of one union of CFGs (graph-wide ids until localized).
 struct OutSet {
   DevBuf pp_off, pp_vtx, tp_off, tp_vtx;
+  DevBuf ppg_off, ppg_vtx;  // prime paths grouped by last vertex (TPG_ORDER_BY_LAST)
   DevBuf comp_starts;  // int64 [4][n_comp+1]: pp, pp vertices, tp, tp vertices
   int64_t n_pp = 0, n_ppv = 0, n_tp = 0, n_tpv = 0;
 };
@@ -103,6 +104,7 @@ struct tpg_workspace {
   // (seed_n < 0: every vertex of the union)
   int32_t seed_lo = 0, seed_n = -1;
   DevBuf digest;  // [2] set digest of the last digest_set call
+  DevBuf grp_key, grp_hist;  // last-vertex grouping: keys, per-tile histograms
   ExtArgs graph_args{};
   int graph_W = 0, graph_grid = 0, graph_items = 0, graph_variant = 0;
   hipStream_t graph_stream = nullptr;
@@ -825,6 +827,45 @@ tpg_status export_paths(const DevBuf& off, const DevBuf& vtx, int64_t n, int64_t
   return TPG_OK;
 }
 
+// The canonical prime paths regrouped by last vertex (stable, so each
+// group keeps the canonical order) into o.ppg_off / o.ppg_vtx: a counting
+// sort over n_keys vertex ids, then a flattened gather of the rows.
+tpg_status group_by_last(tpg_workspace* ws, int32_t n_keys, hipStream_t st, OutSet& o, int64_t np,
+                         int64_t nv) {
+  const int64_t nt = group_tiles(np);
+  const int64_t nh = (int64_t)n_keys * std::max<int64_t>(nt, 1);
+  TPG_TRY(ws_reserve(ws, ws->grp_key, sizeof(int32_t) * (np + 1)));
+  TPG_TRY(ws_reserve(ws, ws->grp_hist, sizeof(int64_t) * (nh + 1)));
+  TPG_TRY(ws_reserve(ws, ws->keep_len, sizeof(int64_t) * (std::max(np, nh) + 1)));
+  TPG_TRY(ws_reserve(ws, ws->keep_pos, sizeof(int64_t) * (np + 1)));
+  TPG_TRY(ws_reserve(ws, ws->keep_voff, sizeof(int64_t) * (np + 1)));
+  TPG_TRY(ws_reserve(ws, ws->idx0, sizeof(int32_t) * (np + 1)));
+  TPG_TRY(ws_reserve(ws, o.ppg_off, sizeof(int64_t) * (np + 1)));
+  TPG_TRY(ws_reserve(ws, o.ppg_vtx, sizeof(int32_t) * (nv + 1)));
+  TPG_TRY(reserve_scan(ws, std::max(np, nh)));
+  int64_t* sc = ws->scalars.as<int64_t>();
+  uint64_t* hist = ws->grp_hist.as<uint64_t>();
+  int64_t* base = ws->keep_len.as<int64_t>();  // the scanned histograms
+  int32_t* perm = ws->idx0.as<int32_t>();
+  TPG_HIP(launch_zero_u64(hist, nh, st));
+  TPG_HIP(launch_last_hist(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), np, nt,
+                           ws->grp_key.as<int32_t>(), hist, st));
+  TPG_HIP(scan_i64(reinterpret_cast<const int64_t*>(hist), base, nh, 0, sc + 10,
+                   ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
+  TPG_HIP(launch_last_place(ws->grp_key.as<int32_t>(), np, nt, base, perm, st));
+  // row lengths in the new order (reusing the histogram buffer is safe: the
+  // placement above has consumed it), their offsets, then the rows
+  int64_t* len = ws->keep_len.as<int64_t>();
+  TPG_HIP(launch_perm_lens(o.pp_off.as<int64_t>(), perm, np, len, ws->keep_pos.as<int64_t>(), st));
+  TPG_HIP(scan_i64(len, ws->keep_voff.as<int64_t>(), np, 0, sc + 11, ws->scan_status.as<uint64_t>(),
+                   ws->scan_ctr.as<uint32_t>(), st));
+  TPG_HIP(launch_gather(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), perm, np,
+                        ws->keep_pos.as<int64_t>(), ws->keep_voff.as<int64_t>(), len,
+                        o.ppg_off.as<int64_t>(), o.ppg_vtx.as<int32_t>(), st));
+  TPG_HIP(launch_set_i64(o.ppg_off.as<int64_t>() + np, sc + 11, st));
+  return TPG_OK;
+}
+
 // Digest of paths [0, n) of a device set (see tpg_paths.digest).
 tpg_status digest_set(tpg_workspace* ws, const DevBuf& off, const DevBuf& vtx, int64_t n,
                       hipStream_t st, uint64_t out[2]) {
@@ -1099,7 +1140,7 @@ void tpg_workspace_free(tpg_workspace* ws) {
                     &ws->pfx, &ws->sfx, &ws->tp_len, &ws->tp_off, &ws->tp_vtx, &ws->tp_key, &ws->idx0,
                     &ws->idx1, &ws->grp_cnt, &ws->rb0, &ws->rb1, &ws->keep_cnt, &ws->keep_len,
                     &ws->keep_pos, &ws->keep_voff, &ws->comp_cnt, &ws->lvl_comp, &ws->b_pp_off,
-                    &ws->scan2_status, &ws->scalars2, &ws->digest,
+                    &ws->scan2_status, &ws->scalars2, &ws->digest, &ws->grp_key, &ws->grp_hist,
                     &ws->b_pp_vtx, &ws->b_tp_off, &ws->b_tp_vtx, &ws->b_desc};
   for (DevBuf* b : bufs) ws_release(ws, *b);
   for (OutSet& o : ws->out) {
@@ -1107,6 +1148,8 @@ void tpg_workspace_free(tpg_workspace* ws) {
     ws_release(ws, o.pp_vtx);
     ws_release(ws, o.tp_off);
     ws_release(ws, o.tp_vtx);
+    ws_release(ws, o.ppg_off);
+    ws_release(ws, o.ppg_vtx);
     ws_release(ws, o.comp_starts);
   }
   for (hipEvent_t e : ws->ev_pool) (void)hipEventDestroy(e);
@@ -1130,6 +1173,8 @@ tpg_status tpg_prime_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* 
   TPG_TRY(check_graph(g));
   CallCtx c;
   TPG_TRY(begin_call(opts, c));
+  if ((c.flags & TPG_STREAM) && (c.flags & TPG_ORDER_BY_LAST))
+    return fail(TPG_ERR_INVALID_ARG, "TPG_ORDER_BY_LAST cannot be streamed by first vertex");
   if (c.flags & TPG_STREAM) return prime_paths_stream(g, c, out);
   HostUnion U;
   add_component(U, g);
@@ -1145,8 +1190,12 @@ tpg_status tpg_prime_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* 
   hipEvent_t ext_done = nullptr;
   OutSet& o = c.ws->out[0];
   tpg_status s = run_pp(U, c, tm, R, P, o, &ext_done);
+  if (s == TPG_OK && (c.flags & TPG_ORDER_BY_LAST)) s = group_by_last(c.ws, U.n, c.st, o, P.n_pp, P.n_vtx);
   if (s == TPG_OK && timing) TPG_HIP(hipEventRecord(phase[1], c.st));
-  if (s == TPG_OK) s = deliver_set(c.ws, o.pp_off, o.pp_vtx, P.n_pp, P.n_vtx, c.flags, c.st, out);
+  const bool grouped = c.flags & TPG_ORDER_BY_LAST;
+  if (s == TPG_OK)
+    s = deliver_set(c.ws, grouped ? o.ppg_off : o.pp_off, grouped ? o.ppg_vtx : o.pp_vtx, P.n_pp,
+                    P.n_vtx, c.flags, c.st, out);
   if (s == TPG_OK) {
     TPG_HIP(hipStreamSynchronize(c.st));
     if (c.stats) {
@@ -1201,7 +1250,11 @@ tpg_status tpg_test_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* p
   // with TPG_STREAM the sets come back as counts and digests and the test
   // paths go through on_chunk
   const uint32_t fl = (c.flags & TPG_STREAM) ? (c.flags | TPG_DIGEST_ONLY) : c.flags;
-  if (s == TPG_OK && pp_out) s = deliver_set(c.ws, o.pp_off, o.pp_vtx, P.n_pp, P.n_vtx, fl, c.st, pp_out);
+  const bool grouped = pp_out && (c.flags & TPG_ORDER_BY_LAST);
+  if (s == TPG_OK && grouped) s = group_by_last(c.ws, U.n, c.st, o, P.n_pp, P.n_vtx);
+  if (s == TPG_OK && pp_out)
+    s = deliver_set(c.ws, grouped ? o.ppg_off : o.pp_off, grouped ? o.ppg_vtx : o.pp_vtx, P.n_pp,
+                    P.n_vtx, fl, c.st, pp_out);
   if (s == TPG_OK) s = deliver_set(c.ws, o.tp_off, o.tp_vtx, T.n_tp, T.n_vtx, fl, c.st, tp_out);
   if (s == TPG_OK && (c.flags & TPG_STREAM)) s = test_paths_stream_out(c, o, T.n_tp);
   if (s == TPG_OK) {

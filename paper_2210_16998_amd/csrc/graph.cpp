@@ -107,6 +107,44 @@ tpg_status tpg_load_cfg_csr(int32_t n, const int64_t* row_ptr, const int32_t* co
     g->succ_ptr[v + 1] = (int32_t)g->succ.size();
     maxdeg = std::max<int32_t>(maxdeg, (int32_t)row.size());
   }
+  if (load_flags & TPG_LOAD_BINARIZE) {
+    // out-degree <= 2 (Sec. 3): vertex v with successors s_1 < .. < s_k, k > 2,
+    // keeps s_1 and hands s_2 .. s_k to a chain of new decision vertices
+    int64_t extra = 0;
+    for (int32_t v = 0; v < n; ++v)
+      extra += std::max<int32_t>(0, g->succ_ptr[v + 1] - g->succ_ptr[v] - 2);
+    if (n + extra > TPG_MAX_VERTICES) {
+      delete g;
+      return fail(TPG_ERR_UNSUPPORTED, "binarized graph has %lld vertices (max %d)",
+                  (long long)(n + extra), TPG_MAX_VERTICES);
+    }
+    const int32_t nb = n + (int32_t)extra;
+    std::vector<std::vector<int32_t>> rows(nb);
+    int32_t next_id = n;
+    for (int32_t v = 0; v < n; ++v) {
+      const int32_t* sv = g->succ.data() + g->succ_ptr[v];
+      const int32_t k = g->succ_ptr[v + 1] - g->succ_ptr[v];
+      if (k <= 2) {
+        rows[v].assign(sv, sv + k);
+        continue;
+      }
+      int32_t at = v;
+      for (int32_t i = 0; i < k - 2; ++i) {
+        const int32_t x = next_id++;
+        rows[at] = {sv[i], x};
+        at = x;
+      }
+      rows[at] = {sv[k - 2], sv[k - 1]};
+    }
+    g->n = n = nb;
+    g->succ.clear();
+    g->succ_ptr.assign(n + 1, 0);
+    for (int32_t v = 0; v < n; ++v) {
+      g->succ.insert(g->succ.end(), rows[v].begin(), rows[v].end());
+      g->succ_ptr[v + 1] = (int32_t)g->succ.size();
+    }
+    maxdeg = std::min<int32_t>(maxdeg, 2);
+  }
   g->max_out_degree = maxdeg;
   if (maxdeg > TPG_MAX_OUT_DEGREE) {
     delete g;

@@ -94,6 +94,19 @@ hipError_t scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t add, int
 int64_t scan_tiles(int64_t n);  // status slots needed by the scans for n items
 
 hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t st);
+// --- prime paths grouped by last vertex (stable counting sort) ---------------
+// key[i] = last vertex of path i; hist[key * ntiles + tile] counts (hist must
+// be zero, nkeys * ntiles entries, tile = group_tiles granularity)
+int64_t group_tiles(int64_t n);
+hipError_t launch_last_hist(const int64_t* off, const int32_t* vtx, int64_t n, int64_t ntiles,
+                            int32_t* key, uint64_t* hist, hipStream_t st);
+// perm[slot] = path index, slot = base[key * ntiles + tile] + rank among the
+// tile's earlier paths with the same key (base: exclusive scan of hist)
+hipError_t launch_last_place(const int32_t* key, int64_t n, int64_t ntiles, const int64_t* base,
+                             int32_t* perm, hipStream_t st);
+// len[k] = length of path perm[k], pos[k] = k (the gather's inputs)
+hipError_t launch_perm_lens(const int64_t* off, const int32_t* perm, int64_t n, int64_t* len,
+                            int64_t* pos, hipStream_t st);
 // Set digest of paths [0, n) (offsets off, entries vtx): out[0] = sum and
 // out[1] = xor of the per-path FNV-1a 64 hashes of (k, v_1 .. v_k) as int32
 // little-endian bytes; out is cleared first.

@@ -680,6 +680,75 @@ hipError_t launch_gather(const int64_t* tp_off, const int32_t* tp_vtx, const int
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// prime paths grouped by last vertex (the paper's per-end-vertex output)
+// ---------------------------------------------------------------------------
+// A stable counting sort of the canonical list by last vertex: per tile of
+// kGroupTile paths a histogram over the keys, an exclusive scan of the
+// histograms taken key-major (so each key's slots run tile after tile),
+// then each path's slot = its key's base in its tile + the number of
+// earlier paths of the tile with the same key.
+constexpr int kGroupTile = 1024;
+
+__global__ __launch_bounds__(kBlock) void k_last_hist(const int64_t* off, const int32_t* vtx,
+                                                      int64_t n, int64_t ntiles, int32_t* key,
+                                                      unsigned long long* hist) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int32_t k = vtx[off[i + 1] - 1];
+  key[i] = k;
+  atomicAdd(&hist[(int64_t)k * ntiles + i / kGroupTile], 1ull);
+}
+
+__global__ __launch_bounds__(kGroupTile) void k_last_place(const int32_t* key, int64_t n,
+                                                           int64_t ntiles, const int64_t* base,
+                                                           int32_t* perm) {
+  __shared__ int32_t s_key[kGroupTile];
+  const int tid = (int)threadIdx.x;
+  const int64_t t = blockIdx.x;
+  const int64_t i = t * kGroupTile + tid;
+  const int32_t k = i < n ? key[i] : -1;
+  s_key[tid] = k;
+  __syncthreads();
+  if (i >= n) return;
+  int r = 0;
+  for (int j = 0; j < tid; ++j) r += s_key[j] == k ? 1 : 0;
+  perm[base[(int64_t)k * ntiles + t] + r] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(kBlock) void k_perm_lens(const int64_t* off, const int32_t* perm,
+                                                      int64_t n, int64_t* len, int64_t* pos) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  const int64_t a = perm[k];
+  len[k] = off[a + 1] - off[a];
+  pos[k] = k;
+}
+
+hipError_t launch_last_hist(const int64_t* off, const int32_t* vtx, int64_t n, int64_t ntiles,
+                            int32_t* key, uint64_t* hist, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  k_last_hist<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+      off, vtx, n, ntiles, key, reinterpret_cast<unsigned long long*>(hist));
+  return hipGetLastError();
+}
+
+hipError_t launch_last_place(const int32_t* key, int64_t n, int64_t ntiles, const int64_t* base,
+                             int32_t* perm, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  k_last_place<<<(unsigned)ntiles, kGroupTile, 0, st>>>(key, n, ntiles, base, perm);
+  return hipGetLastError();
+}
+
+hipError_t launch_perm_lens(const int64_t* off, const int32_t* perm, int64_t n, int64_t* len,
+                            int64_t* pos, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  k_perm_lens<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(off, perm, n, len, pos);
+  return hipGetLastError();
+}
+
+int64_t group_tiles(int64_t n) { return (n + kGroupTile - 1) / kGroupTile; }
+
 // Per-component starts of a sorted path list (components own contiguous
 // id ranges, so the list is grouped by the component of the first vertex):
 // start[c] = first path of component >= c, vstart[c] = its first entry

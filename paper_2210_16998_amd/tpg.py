@@ -18,12 +18,14 @@ LIB_PATH = os.path.join(_HERE, "libtpg.so")
 TPG_OK = 0
 TPG_LOAD_STRICT = 0x1
 TPG_LOAD_ANY_DIGRAPH = 0x2
+TPG_LOAD_BINARIZE = 0x4
 TPG_OUT_DEVICE = 0x1
 TPG_FORCE_TWO_PASS = 0x2
 TPG_NO_TIMING = 0x4
 TPG_DIGEST = 0x8
 TPG_DIGEST_ONLY = 0x10
 TPG_STREAM = 0x20
+TPG_ORDER_BY_LAST = 0x40
 
 STATUS = {0: "TPG_OK", -1: "TPG_ERR_INVALID_ARG", -2: "TPG_ERR_BAD_CSR",
           -3: "TPG_ERR_BAD_ENTRY_EXIT", -4: "TPG_ERR_UNREACHABLE",

@@ -296,3 +296,79 @@ def test_digest_is_a_multiset_digest_of_path_bytes():
     assert oracle.digest(pl([[0, 1, 2], [3], [2, 5, 3], [4, 4]])) != d
     assert oracle.digest(pl([[0, 1], [2], [3], [2, 5, 2], [4, 4]])) != d
     assert oracle.digest(pl([])) == (0, 0)
+
+
+# --- the paper's input form: switch vertices binarized (Sec. 3) -------------
+
+def _complete_paths(g):
+    """All entry-to-exit paths of a DAG, by depth-first enumeration."""
+    rp, ci = g.row_ptr, g.col_idx
+    out, stack = [], [[g.entry]]
+    while stack:
+        p = stack.pop()
+        v = p[-1]
+        if v == g.exit:
+            out.append(p)
+            continue
+        for w in ci[rp[v]:rp[v + 1]]:
+            stack.append(p + [int(w)])
+    return out
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_binarize_preserves_complete_paths_and_bounds_degree(seed):
+    # a DAG with switches of 3..6 arms (no loops, so complete paths are finite)
+    rng = np.random.default_rng(500 + seed)
+    n = 14
+    edges = []
+    for v in range(n - 1):
+        k = int(rng.integers(1, 7))
+        targets = sorted(set(int(x) for x in rng.integers(v + 1, n, size=k)))
+        edges += [(v, w) for w in targets]
+    g = cfggen.from_edges(n, edges, 0, n - 1)
+    b = oracle.binarize(g)
+    deg = np.diff(b.row_ptr)
+    assert deg.max() <= 2
+    assert b.n == n + int(np.maximum(np.diff(g.row_ptr) - 2, 0).sum())
+    # complete paths map one to one once the new decision vertices are dropped
+    orig = sorted(map(tuple, _complete_paths(g)))
+    mapped = sorted(tuple(v for v in p if v < n) for p in _complete_paths(b))
+    assert mapped == orig
+
+
+def test_binarize_switch_chain_shape_and_prime_paths():
+    # entry -> v; v switches to four arms a1..a4, each to the exit
+    g = cfggen.from_edges(7, [(0, 1), (1, 2), (1, 3), (1, 4), (1, 5),
+                              (2, 6), (3, 6), (4, 6), (5, 6)], 0, 6)
+    b = oracle.binarize(g)
+    rows = [b.col_idx[b.row_ptr[v]:b.row_ptr[v + 1]].tolist() for v in range(b.n)]
+    assert b.n == 9 and rows[1] == [2, 7] and rows[7] == [3, 8] and rows[8] == [4, 5]
+    pp = oracle.prime_paths(b)[0]
+    # a DAG's prime paths are its complete paths (the four arms)
+    assert pp.tolist() == sorted(_complete_paths(b))
+    assert pp.tolist() == oracle.bruteforce_pp(b)[0].tolist()
+
+
+def test_library_loader_binarizes_like_the_oracle():
+    """Host logic of the loader (no device work): the library's binarized CSR
+    equals the oracle's on graphs with switch fan-outs."""
+    from paper_2210_16998_amd import tpg
+    gs = [cfggen.c2_cfg(workloads()["c2"][k]["seed"]) for k in range(3)]
+    gs += [cfggen.random_small_cfg(60_000 + s, 10 + s, extra=3 + s % 5) for s in range(10)]
+    for g in gs:
+        b = oracle.binarize(g)
+        h = tpg.load_cfg(g, tpg.TPG_LOAD_BINARIZE)
+        rp, ci = h.csr()
+        assert np.array_equal(rp, b.row_ptr) and np.array_equal(ci, b.col_idx), g.name
+
+
+def test_group_by_last_is_a_stable_grouping():
+    g = cfggen.fig1_cfg()
+    pp = oracle.prime_paths(g)[0]
+    gp = oracle.group_by_last(pp)
+    rows = gp.tolist()
+    lasts = [r[-1] for r in rows]
+    assert lasts == sorted(lasts) and sorted(map(tuple, rows)) == sorted(map(tuple, pp.tolist()))
+    for v in set(lasts):
+        grp = [r for r in rows if r[-1] == v]
+        assert grp == sorted(grp)  # canonical order inside a group
