@@ -173,6 +173,34 @@ def _paper_form(args):
                                 "overhead_ms": ms_last - ms_pp}}
 
 
+def _covering(args):
+    """Test paths by longest-first covering (TPG_TP_GREEDY) on the benchmark
+    CFG: whole path per step, against the plain splice + dedup."""
+    import torch
+    from paper_2210_16998_amd import tpg
+    g, rec = _workload()
+    h = tpg.load_cfg(g)
+    ws = tpg.Workspace(0)
+    stream = torch.cuda.Stream()
+    out = {}
+    for name, fl in (("plain", 0), ("greedy", tpg.TPG_TP_GREEDY)):
+        f = tpg.TPG_OUT_DEVICE | fl
+        for _ in range(2):
+            tpg.test_paths(h, ws=ws, flags=f | tpg.TPG_NO_TIMING, stream=stream)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            tpg.test_paths(h, ws=ws, flags=f | tpg.TPG_NO_TIMING, stream=stream)
+        torch.cuda.synchronize()
+        ms = 1000.0 * (time.perf_counter() - t) / args.steps
+        _, _, st = tpg.test_paths(h, ws=ws, flags=f, stream=stream)
+        out[name] = {"ms_per_step": ms, "n_tp": st["n_tp"], "ms_tp": st["ms_tp"]}
+    ws.close()
+    out["workload"] = (f"the benchmark CFG ({g.n} vertices): test paths of the longest-first "
+                       f"covering vs splice + dedup, whole path per step")
+    return out
+
+
 def _cpu_baseline(g, reps: int):
     """The CPU oracle on the same graph (DFS enumeration from every vertex,
     local-rule prime test, splice + sort + dedup of test paths)."""
@@ -211,6 +239,7 @@ def main() -> int:
     ap.add_argument("--no-stress", action="store_true")
     ap.add_argument("--stress-reps", type=int, default=3)
     ap.add_argument("--no-paper-form", action="store_true")
+    ap.add_argument("--no-covering", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is "
@@ -326,6 +355,8 @@ def main() -> int:
         out["stress"] = _stress(args, copy_gbs)
     if not args.no_paper_form:
         out["paper_form"] = _paper_form(args)
+    if not args.no_covering:
+        out["covering"] = _covering(args)
     if not args.no_batch:
         out["batched"] = _batched(args)
     if not args.no_cpu:

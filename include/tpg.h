@@ -92,6 +92,14 @@ typedef enum tpg_status {
 #define TPG_STREAM 0x20u        /* deliver the results through opts.on_chunk
                                    (see tpg_chunk_fn); *out then holds only the
                                    counts and the digest of the whole set      */
+#define TPG_TP_GREEDY 0x80u     /* tpg_test_paths: longest-first covering (the
+                                   Ammann-Offutt generation the paper cites):
+                                   prime paths in order of decreasing length
+                                   (ties: canonical order); one that is already a
+                                   contiguous subpath of a test path chosen
+                                   before gets none, any other has its spliced
+                                   test path chosen; the chosen test paths are
+                                   returned in canonical order                  */
 #define TPG_ORDER_BY_LAST 0x40u /* prime paths grouped by their last vertex (the
                                    paper's per-end-vertex output, Problem 1):
                                    ascending last vertex, canonical order inside

@@ -68,6 +68,8 @@ def _load():
         _lib.orc_test_paths.argtypes = [ctypes.c_int, i64p, i32p, ctypes.c_int,
                                         ctypes.c_int, P(_Paths), P(_Paths), i64p]
         _lib.orc_free_paths.argtypes = [P(_Paths)]
+        _lib.orc_test_paths_greedy.argtypes = [ctypes.c_int, i64p, i32p, ctypes.c_int,
+                                               ctypes.c_int, P(_Paths), P(_Paths)]
         _lib.orc_fnv1a64.argtypes = [ctypes.c_char_p, ctypes.c_int64]
         _lib.orc_fnv1a64.restype = ctypes.c_uint64
         _lib.orc_digest.argtypes = [ctypes.c_int64, i64p, i32p, P(ctypes.c_uint64)]
@@ -270,6 +272,22 @@ def digest(pl: PathList) -> Tuple[int, int]:
     _load().orc_digest(len(off) - 1, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                        vtx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), out)
     return int(out[0]), int(out[1])
+
+
+def test_paths_greedy(g, pps: PathList) -> PathList:
+    """Test paths by the longest-first covering (see oracle.cpp): a prime
+    path already contained in a chosen test path gets no test path of its
+    own.  Small graphs only (every simple window of every chosen path is
+    looked up)."""
+    lib = _load()
+    rp, ci, prp, pci = _csr(g)
+    inp = pps._c()
+    out = _Paths()
+    rc = lib.orc_test_paths_greedy(g.n, prp, pci, g.entry, g.exit, ctypes.byref(inp),
+                                   ctypes.byref(out))
+    if rc != 0:
+        raise ValueError("a prime path is not reachable from the entry or cannot reach the exit")
+    return _take(out)
 
 
 def canonical_bytes(pl: PathList) -> bytes:

@@ -45,6 +45,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <thread>
 #include <vector>
 
@@ -536,6 +537,64 @@ int orc_test_paths(int n, const int64_t* row_ptr, const int32_t* col_idx, int en
   tps.erase(std::unique(tps.begin(), tps.end()), tps.end());
   PathSet ps;
   for (const Path& t : tps) ps.add(t.data(), t.data() + t.size());
+  to_out(ps, out);
+  return 0;
+}
+
+// Test paths by the longest-first covering that the paper cites for
+// generating TPs (Ammann and Offutt, in its survey of TP generation): the
+// prime paths are taken in order of decreasing length (ties: the given
+// canonical order); a prime path that is already a contiguous subpath of a
+// chosen test path gets none of its own, any other gets its spliced test
+// path (prefix + path + suffix, as above) chosen.  Every simple contiguous
+// subpath and simple cycle of a chosen test path is looked up in the prime
+// path set.  Output: the chosen test paths in lexicographic order.
+int orc_test_paths_greedy(int n, const int64_t* row_ptr, const int32_t* col_idx, int entry,
+                          int exit, const orc_paths* pp, orc_paths* out) {
+  std::vector<int32_t> df(n), par(n), db(n), nx(n);
+  orc_bfs(n, row_ptr, col_idx, entry, exit, df.data(), par.data(), db.data(), nx.data());
+  const int64_t np = pp->n_paths;
+  std::map<Path, int64_t> id;
+  std::vector<int64_t> order(np);
+  for (int64_t i = 0; i < np; ++i) {
+    const int32_t* p = pp->vertices + pp->offsets[i];
+    id[Path(p, p + (pp->offsets[i + 1] - pp->offsets[i]))] = i;
+    order[i] = i;
+  }
+  auto len = [&](int64_t i) { return pp->offsets[i + 1] - pp->offsets[i]; };
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return len(a) > len(b); });
+  std::vector<char> covered(np, 0);
+  std::vector<Path> chosen;
+  for (int64_t i : order) {
+    if (covered[i]) continue;
+    const int32_t* p = pp->vertices + pp->offsets[i];
+    const int v1 = p[0], vk = p[len(i) - 1];
+    if (df[v1] < 0 || db[vk] < 0) return -1;
+    Path t;
+    for (int v = v1; v != entry; v = par[v]) t.push_back(par[v]);
+    std::reverse(t.begin(), t.end());
+    t.insert(t.end(), p, p + len(i));
+    for (int v = vk; v != exit; v = nx[v]) t.push_back(nx[v]);
+    for (size_t a = 0; a < t.size(); ++a) {
+      Path w;
+      std::vector<char> on(n, 0);
+      for (size_t b = a; b < t.size(); ++b) {
+        const int x = t[b];
+        const bool closes = b > a && x == t[a];
+        if (on[x] && !closes) break;  // prime paths are simple paths or simple cycles
+        w.push_back(x);
+        auto it = id.find(w);
+        if (it != id.end()) covered[it->second] = 1;
+        if (closes) break;
+        on[x] = 1;
+      }
+    }
+    chosen.push_back(std::move(t));
+  }
+  std::sort(chosen.begin(), chosen.end());
+  chosen.erase(std::unique(chosen.begin(), chosen.end()), chosen.end());
+  PathSet ps;
+  for (const Path& t : chosen) ps.add(t.data(), t.data() + t.size());
   to_out(ps, out);
   return 0;
 }

@@ -105,6 +105,9 @@ struct tpg_workspace {
   int32_t seed_lo = 0, seed_n = -1;
   DevBuf digest;  // [2] set digest of the last digest_set call
   DevBuf grp_key, grp_hist;  // last-vertex grouping: keys, per-tile histograms
+  // longest-first covering: prime-path hash table, covering pairs, order,
+  // coverers per path, round states, chosen list
+  DevBuf cov_keys, cov_vals, cov_misc, pair_p, pair_q, cov_pos, gstate0, gstate1, cov_flag;
   ExtArgs graph_args{};
   int graph_W = 0, graph_grid = 0, graph_items = 0, graph_variant = 0;
   hipStream_t graph_stream = nullptr;
@@ -717,8 +720,111 @@ tpg_status bfs_start(tpg_workspace* ws, const HostUnion& U, hipStream_t st) {
   return TPG_OK;
 }
 
+// Longest-first covering (see kernels_cover.hip): from the spliced test
+// paths of all np prime paths, the chosen ones in prime-path order into idx0
+// and their per-first-vertex runs into rb0; *n_sel their number.
+tpg_status greedy_select(tpg_workspace* ws, const HostUnion& U, hipStream_t st, int64_t np,
+                         const OutSet& o, int64_t* n_sel) {
+  const int n = U.n;
+  int64_t* sc = ws->scalars.as<int64_t>();
+  int64_t* hs = ws->h_scalars;
+  TPG_TRY(ws_reserve(ws, ws->cov_misc, sizeof(uint64_t) * 4));
+  uint64_t* misc = ws->cov_misc.as<uint64_t>();  // [0] shared hashes, [1] missing windows, [2] undecided
+  // hash table of the prime paths, load factor <= 1/2
+  int64_t slots = 1024;
+  while (slots < 2 * np) slots <<= 1;
+  TPG_TRY(ws_reserve(ws, ws->cov_keys, sizeof(uint64_t) * slots));
+  TPG_TRY(ws_reserve(ws, ws->cov_vals, sizeof(int32_t) * slots));
+  uint64_t mul = 0;
+  for (int attempt = 0;; ++attempt) {
+    if (attempt == 4) return fail(TPG_ERR_UNSUPPORTED, "prime-path hashes collide for 4 multipliers");
+    mul = cover_hash_mul(attempt);
+    TPG_HIP(launch_zero_u64(ws->cov_keys.as<uint64_t>(), slots, st));
+    TPG_HIP(launch_zero_u64(misc, 4, st));
+    TPG_HIP(launch_pp_hash_insert(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), np, mul,
+                                  ws->cov_keys.as<uint64_t>(), ws->cov_vals.as<int32_t>(), slots - 1,
+                                  misc, st));
+    TPG_HIP(hipMemcpyAsync(hs + 10, misc, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    TPG_HIP(hipStreamSynchronize(st));
+    if (hs[10] == 0) break;
+  }
+  // covering pairs: count, offsets, write
+  const int64_t* tp_off = ws->tp_off.as<int64_t>();
+  const int32_t* tp_vtx = ws->tp_vtx.as<int32_t>();
+  TPG_TRY(ws_reserve(ws, ws->keep_cnt, sizeof(int64_t) * (np + 1)));
+  TPG_TRY(ws_reserve(ws, ws->keep_pos, sizeof(int64_t) * (np + 1)));
+  int64_t* cnt = ws->keep_cnt.as<int64_t>();
+  int64_t* at = ws->keep_pos.as<int64_t>();
+  TPG_HIP(launch_cover(U.W, ws->dg, tp_off, tp_vtx, np, mul, ws->cov_keys.as<uint64_t>(),
+                       ws->cov_vals.as<int32_t>(), slots - 1, cnt, at, nullptr, nullptr, 0, misc + 1,
+                       st));
+  TPG_HIP(scan_i64(cnt, at, np, 0, sc + 12, ws->scan_status.as<uint64_t>(),
+                   ws->scan_ctr.as<uint32_t>(), st));
+  TPG_HIP(hipMemcpyAsync(hs + 10, sc + 12, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TPG_HIP(hipStreamSynchronize(st));
+  const int64_t npairs = hs[10];
+  TPG_TRY(ws_reserve(ws, ws->pair_p, sizeof(int32_t) * (npairs + 1)));
+  TPG_TRY(ws_reserve(ws, ws->pair_q, sizeof(int32_t) * (npairs + 1)));
+  TPG_HIP(launch_cover(U.W, ws->dg, tp_off, tp_vtx, np, mul, ws->cov_keys.as<uint64_t>(),
+                       ws->cov_vals.as<int32_t>(), slots - 1, cnt, at, ws->pair_p.as<int32_t>(),
+                       ws->pair_q.as<int32_t>(), 1, misc + 1, st));
+  TPG_HIP(hipMemcpyAsync(hs + 11, misc + 1, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+  TPG_HIP(hipStreamSynchronize(st));
+  if (hs[11] != 0)
+    return fail(TPG_ERR_DEVICE, "%lld accepted windows are not prime paths", (long long)hs[11]);
+  // order: decreasing length, canonical order among equal lengths
+  const int64_t nt = group_tiles(np);
+  const int64_t nkeys = (int64_t)n + 2;
+  const int64_t nh = nkeys * std::max<int64_t>(nt, 1);
+  TPG_TRY(ws_reserve(ws, ws->grp_key, sizeof(int32_t) * (np + 1)));
+  TPG_TRY(ws_reserve(ws, ws->grp_hist, sizeof(int64_t) * (nh + 1)));
+  TPG_TRY(ws_reserve(ws, ws->keep_len, sizeof(int64_t) * (nh + 1)));
+  TPG_TRY(ws_reserve(ws, ws->idx1, sizeof(int32_t) * (np + 1)));
+  TPG_TRY(ws_reserve(ws, ws->cov_pos, sizeof(int32_t) * (np + 1)));
+  TPG_TRY(reserve_scan(ws, std::max(np, nh)));
+  int32_t* key = ws->grp_key.as<int32_t>();
+  int32_t* perm = ws->idx1.as<int32_t>();
+  TPG_HIP(launch_len_key(o.pp_off.as<int64_t>(), np, (int64_t)n + 1, key, st));
+  TPG_HIP(launch_zero_u64(ws->grp_hist.as<uint64_t>(), nh, st));
+  TPG_HIP(launch_key_hist(key, np, nt, ws->grp_hist.as<uint64_t>(), st));
+  TPG_HIP(scan_i64(ws->grp_hist.as<int64_t>(), ws->keep_len.as<int64_t>(), nh, 0, sc + 13,
+                   ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
+  TPG_HIP(launch_last_place(key, np, nt, ws->keep_len.as<int64_t>(), perm, st));
+  TPG_HIP(launch_invert(perm, np, ws->cov_pos.as<int32_t>(), st));
+  // rounds until every path is decided
+  TPG_TRY(ws_reserve(ws, ws->gstate0, (size_t)np + 8));
+  TPG_TRY(ws_reserve(ws, ws->gstate1, (size_t)2 * np + 16));
+  uint8_t* state = ws->gstate0.as<uint8_t>();
+  uint8_t* drop = ws->gstate1.as<uint8_t>();
+  uint8_t* block = drop + np + 8;
+  TPG_HIP(launch_zero_u32(reinterpret_cast<uint32_t*>(state), (np + 4) / 4, st));
+  TPG_HIP(launch_zero_u32(reinterpret_cast<uint32_t*>(drop), (2 * np + 16) / 4, st));
+  for (int64_t round = 0;; ++round) {
+    if (round > np + 1) return fail(TPG_ERR_DEVICE, "covering rounds did not settle");
+    TPG_HIP(launch_zero_u64(misc + 2, 1, st));
+    TPG_HIP(launch_round_pairs(ws->pair_p.as<int32_t>(), ws->pair_q.as<int32_t>(), npairs,
+                               ws->cov_pos.as<int32_t>(), state, drop, block, st));
+    TPG_HIP(launch_round_decide(np, state, drop, block, misc + 2, st));
+    TPG_HIP(hipMemcpyAsync(hs + 10, misc + 2, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    TPG_HIP(hipStreamSynchronize(st));
+    if (hs[10] == 0) break;
+  }
+  // the chosen paths in prime-path order and their runs by first vertex
+  TPG_TRY(ws_reserve(ws, ws->cov_flag, sizeof(int32_t) * (np + 1)));
+  TPG_HIP(launch_chosen_flags(state, np, ws->cov_flag.as<int32_t>(), st));
+  TPG_HIP(scan_i32_to_i64(ws->cov_flag.as<int32_t>(), at, np, 0, sc + 15,
+                          ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
+  TPG_HIP(launch_chosen_list(state, at, np, ws->idx0.as<int32_t>(), st));
+  TPG_HIP(hipMemcpyAsync(hs + 10, sc + 15, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TPG_HIP(hipStreamSynchronize(st));
+  TPG_HIP(launch_chosen_runs(ws->idx0.as<int32_t>(), hs[10], o.pp_off.as<int64_t>(),
+                             o.pp_vtx.as<int32_t>(), n, ws->rb0.as<int64_t>(), st));
+  *n_sel = hs[10];
+  return TPG_OK;
+}
+
 tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t st,
-                             const PPResult& P, TPResult& T, OutSet& o) {
+                             const PPResult& P, TPResult& T, OutSet& o, bool greedy = false) {
   const int n = U.n;
   const int nc = U.n_comp;
   if (!ws->bfs_pending) TPG_TRY(bfs_start(ws, U, st));
@@ -755,6 +861,9 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
   TPG_HIP(launch_tp_write(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), np, b,
                           ws->tp_off.as<int64_t>(), ws->tp_vtx.as<int32_t>(),
                           ws->tp_key.as<uint64_t>(), ws->idx0.as<int32_t>(), st));
+  // with longest-first covering only the chosen test paths are sorted
+  int64_t nm = np;
+  if (greedy) TPG_TRY(greedy_select(ws, U, st, np, o, &nm));
   // merge the per-first-vertex runs
   TpOrder K{ws->tp_off.as<int64_t>(), ws->tp_vtx.as<int32_t>(), ws->tp_key.as<uint64_t>()};
   int64_t runs = n;
@@ -764,7 +873,7 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
   DevBuf* io = &ws->idx1;
   while (runs > 1) {
     TPG_HIP(launch_merge_round(K, ii->as<int32_t>(), io->as<int32_t>(), ri->as<int64_t>(), runs,
-                               np, st));
+                               nm, st));
     TPG_HIP(launch_next_runs(ri->as<int64_t>(), runs, ro->as<int64_t>(), st));
     std::swap(ri, ro);
     std::swap(ii, io);
@@ -775,11 +884,11 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
   TPG_TRY(ws_reserve(ws, ws->keep_len, sizeof(int64_t) * (np + 1)));
   TPG_TRY(ws_reserve(ws, ws->keep_pos, sizeof(int64_t) * (np + 1)));
   TPG_TRY(ws_reserve(ws, ws->keep_voff, sizeof(int64_t) * (np + 1)));
-  TPG_HIP(launch_dedup_flags(K, ii->as<int32_t>(), np, ws->keep_cnt.as<int64_t>(),
+  TPG_HIP(launch_dedup_flags(K, ii->as<int32_t>(), nm, ws->keep_cnt.as<int64_t>(),
                              ws->keep_len.as<int64_t>(), st));
-  TPG_HIP(scan_i64(ws->keep_cnt.as<int64_t>(), ws->keep_pos.as<int64_t>(), np, 0, sc + 2,
+  TPG_HIP(scan_i64(ws->keep_cnt.as<int64_t>(), ws->keep_pos.as<int64_t>(), nm, 0, sc + 2,
                    ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
-  TPG_HIP(scan_i64(ws->keep_len.as<int64_t>(), ws->keep_voff.as<int64_t>(), np, 0, sc + 3,
+  TPG_HIP(scan_i64(ws->keep_len.as<int64_t>(), ws->keep_voff.as<int64_t>(), nm, 0, sc + 3,
                    ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
   TPG_HIP(hipMemcpyAsync(ws->h_scalars + 2, sc + 2, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TPG_HIP(hipStreamSynchronize(st));
@@ -787,7 +896,7 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
   T.n_vtx = ws->h_scalars[3];
   TPG_TRY(ws_reserve(ws, o.tp_off, sizeof(int64_t) * (T.n_tp + 1)));
   TPG_TRY(ws_reserve(ws, o.tp_vtx, sizeof(int32_t) * (T.n_vtx + 1)));
-  TPG_HIP(launch_gather(ws->tp_off.as<int64_t>(), ws->tp_vtx.as<int32_t>(), ii->as<int32_t>(), np,
+  TPG_HIP(launch_gather(ws->tp_off.as<int64_t>(), ws->tp_vtx.as<int32_t>(), ii->as<int32_t>(), nm,
                         ws->keep_pos.as<int64_t>(), ws->keep_voff.as<int64_t>(),
                         ws->keep_len.as<int64_t>(), o.tp_off.as<int64_t>(), o.tp_vtx.as<int32_t>(),
                         st));
@@ -1141,6 +1250,8 @@ void tpg_workspace_free(tpg_workspace* ws) {
                     &ws->idx1, &ws->grp_cnt, &ws->rb0, &ws->rb1, &ws->keep_cnt, &ws->keep_len,
                     &ws->keep_pos, &ws->keep_voff, &ws->comp_cnt, &ws->lvl_comp, &ws->b_pp_off,
                     &ws->scan2_status, &ws->scalars2, &ws->digest, &ws->grp_key, &ws->grp_hist,
+                    &ws->cov_keys, &ws->cov_vals, &ws->cov_misc, &ws->pair_p, &ws->pair_q,
+                    &ws->cov_pos, &ws->gstate0, &ws->gstate1, &ws->cov_flag,
                     &ws->b_pp_vtx, &ws->b_tp_off, &ws->b_tp_vtx, &ws->b_desc};
   for (DevBuf* b : bufs) ws_release(ws, *b);
   for (OutSet& o : ws->out) {
@@ -1245,7 +1356,7 @@ tpg_status tpg_test_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* p
   OutSet& o = c.ws->out[0];
   tpg_status s = run_pp(U, c, tm, R, P, o, &ext_done, 0, 0, true);
   if (s == TPG_OK && timing) TPG_HIP(hipEventRecord(phase[1], c.st));
-  if (s == TPG_OK) s = test_paths_device(c.ws, U, c.st, P, T, o);
+  if (s == TPG_OK) s = test_paths_device(c.ws, U, c.st, P, T, o, c.flags & TPG_TP_GREEDY);
   if (s == TPG_OK && timing) TPG_HIP(hipEventRecord(phase[2], c.st));
   // with TPG_STREAM the sets come back as counts and digests and the test
   // paths go through on_chunk

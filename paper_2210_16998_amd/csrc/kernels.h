@@ -94,6 +94,8 @@ hipError_t scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t add, int
 int64_t scan_tiles(int64_t n);  // status slots needed by the scans for n items
 
 hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t st);
+// --- stable counting sorts by a small integer key (tiles of kGroupTile) -------
+constexpr int kGroupTile = 1024;
 // --- prime paths grouped by last vertex (stable counting sort) ---------------
 // key[i] = last vertex of path i; hist[key * ntiles + tile] counts (hist must
 // be zero, nkeys * ntiles entries, tile = group_tiles granularity)
@@ -107,6 +109,41 @@ hipError_t launch_last_place(const int32_t* key, int64_t n, int64_t ntiles, cons
 // len[k] = length of path perm[k], pos[k] = k (the gather's inputs)
 hipError_t launch_perm_lens(const int64_t* off, const int32_t* perm, int64_t n, int64_t* len,
                             int64_t* pos, hipStream_t st);
+
+// --- test paths by longest-first covering (kernels_cover.hip) ----------------
+// Hash table of the prime paths (keys / vals of mask + 1 slots, keys zeroed);
+// dups counts hashes shared by two prime paths (then retry with another mul).
+uint64_t cover_hash_mul(int attempt);
+hipError_t launch_pp_hash_insert(const int64_t* off, const int32_t* vtx, int64_t n, uint64_t mul,
+                                 uint64_t* keys, int32_t* vals, int64_t mask, uint64_t* dups,
+                                 hipStream_t st);
+// Prime paths contained in each spliced test path p: pass 0 writes cnt[p],
+// pass 1 the pairs (p, q) at at[p] (exclusive scan of cnt); missing counts
+// accepted windows absent from the table (never, unless the input is bad).
+hipError_t launch_cover(int W, const DGraph& g, const int64_t* tp_off, const int32_t* tp_vtx,
+                        int64_t n, uint64_t mul, const uint64_t* keys, const int32_t* vals,
+                        int64_t mask, int64_t* cnt, const int64_t* at, int32_t* pair_p,
+                        int32_t* pair_q, int pass, uint64_t* missing, hipStream_t st);
+// key[i] = max_len - length of path i (decreasing length first)
+hipError_t launch_len_key(const int64_t* off, int64_t n, int64_t max_len, int32_t* key,
+                          hipStream_t st);
+hipError_t launch_key_hist(const int32_t* key, int64_t n, int64_t ntiles, uint64_t* hist,
+                           hipStream_t st);
+hipError_t launch_invert(const int32_t* perm, int64_t n, int32_t* pos, hipStream_t st);
+// A round of the covering decision: pass over the pairs (drop / block
+// flags, state read only), then decide every undecided path (state 0 ->
+// 1 chosen, 2 dropped) and count the ones left (undecided must be zeroed).
+hipError_t launch_round_pairs(const int32_t* pair_p, const int32_t* pair_q, int64_t np,
+                              const int32_t* pos, const uint8_t* state, uint8_t* drop,
+                              uint8_t* block, hipStream_t st);
+hipError_t launch_round_decide(int64_t n, uint8_t* state, uint8_t* drop, uint8_t* block,
+                               uint64_t* undecided, hipStream_t st);
+hipError_t launch_chosen_flags(const uint8_t* state, int64_t n, int32_t* flag, hipStream_t st);
+// list[at[q]] = q for the chosen paths; then their runs by first vertex
+hipError_t launch_chosen_list(const uint8_t* state, const int64_t* at, int64_t n, int32_t* list,
+                              hipStream_t st);
+hipError_t launch_chosen_runs(const int32_t* list, int64_t m, const int64_t* pp_off,
+                              const int32_t* pp_vtx, int nv, int64_t* rb, hipStream_t st);
 // Set digest of paths [0, n) (offsets off, entries vtx): out[0] = sum and
 // out[1] = xor of the per-path FNV-1a 64 hashes of (k, v_1 .. v_k) as int32
 // little-endian bytes; out is cleared first.

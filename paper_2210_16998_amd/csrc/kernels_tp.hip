@@ -688,8 +688,6 @@ hipError_t launch_gather(const int64_t* tp_off, const int32_t* tp_vtx, const int
 // histograms taken key-major (so each key's slots run tile after tile),
 // then each path's slot = its key's base in its tile + the number of
 // earlier paths of the tile with the same key.
-constexpr int kGroupTile = 1024;
-
 __global__ __launch_bounds__(kBlock) void k_last_hist(const int64_t* off, const int32_t* vtx,
                                                       int64_t n, int64_t ntiles, int32_t* key,
                                                       unsigned long long* hist) {

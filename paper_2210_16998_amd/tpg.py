@@ -26,6 +26,7 @@ TPG_DIGEST = 0x8
 TPG_DIGEST_ONLY = 0x10
 TPG_STREAM = 0x20
 TPG_ORDER_BY_LAST = 0x40
+TPG_TP_GREEDY = 0x80
 
 STATUS = {0: "TPG_OK", -1: "TPG_ERR_INVALID_ARG", -2: "TPG_ERR_BAD_CSR",
           -3: "TPG_ERR_BAD_ENTRY_EXIT", -4: "TPG_ERR_UNREACHABLE",

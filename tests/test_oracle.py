@@ -372,3 +372,46 @@ def test_group_by_last_is_a_stable_grouping():
     for v in set(lasts):
         grp = [r for r in rows if r[-1] == v]
         assert grp == sorted(grp)  # canonical order inside a group
+
+
+# --- longest-first covering (test-path generation the paper cites) ---------
+
+def _naive_greedy(g, pps):
+    """Longest-first covering with plain sublist scans (tiny graphs)."""
+    T = oracle.bfs_tables(g)
+    par, nxt = T["parent"], T["next"]
+
+    def splice(p):
+        pre, v = [], p[0]
+        while v != g.entry:
+            v = int(par[v])
+            pre.append(v)
+        suf, v = [], p[-1]
+        while v != g.exit:
+            v = int(nxt[v])
+            suf.append(v)
+        return pre[::-1] + p + suf
+
+    def contains(t, q):
+        return any(t[k:k + len(q)] == q for k in range(len(t) - len(q) + 1))
+    order = sorted(range(len(pps)), key=lambda i: (-len(pps[i]), i))
+    chosen = []
+    for i in order:
+        if any(contains(t, pps[i]) for t in chosen):
+            continue
+        chosen.append(splice(pps[i]))
+    return sorted(chosen)
+
+
+def test_greedy_covering_matches_naive_scan():
+    gs = [cfggen.fig1_cfg(), cfggen.c1_cfg(0), cfggen.c1_cfg(5)]
+    gs += [cfggen.random_small_cfg(80_000 + s, 4 + s % 9, extra=1 + s % 4) for s in range(25)]
+    for g in gs:
+        pp = oracle.prime_paths(g)[0]
+        got = oracle.test_paths_greedy(g, pp).tolist()
+        assert got == _naive_greedy(g, pp.tolist()), g.name
+        full = oracle.test_paths(g, pp)[0].tolist()
+        # every prime path is covered, and the chosen paths are some of the spliced ones
+        assert all(any(t[k:k + len(q)] == q for t in got for k in range(len(t)))
+                   for q in pp.tolist())
+        assert set(map(tuple, got)) <= set(map(tuple, full)) and len(got) <= len(full)
