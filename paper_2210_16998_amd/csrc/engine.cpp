@@ -72,7 +72,7 @@ struct tpg_workspace {
   DevBuf scan2_status, scalars2;  // the side stream's own scan scratch
   // test paths
   DevBuf bfs_i32, pfx_off, sfx_off, pfx, sfx;
-  DevBuf tp_len, tp_off, tp_vtx, tp_key, idx0, idx1, grp_cnt, rb0, rb1;
+  DevBuf tp_len, tp_off, tp_vtx, tp_key, tp_pk, idx0, idx1, grp_cnt, rb0, rb1;
   DevBuf keep_cnt, keep_len, keep_pos, keep_voff, comp_cnt;
   // per-level, per-component counts (batched labels)
   DevBuf lvl_comp;
@@ -832,6 +832,7 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
   TPG_HIP(hipStreamWaitEvent(st, ws->ev_join, 0));
   const int64_t np = P.n_pp;
   T.n_spliced = np;
+  const int eb = n > 1 ? 32 - __builtin_clz((unsigned)n) : 1;  // bits of entry + 1 <= n
   TPG_TRY(reserve_scan(ws, std::max<int64_t>(np, n)));
   BfsOut b = bfs_views(ws, n);
   int64_t* sc = ws->scalars.as<int64_t>();
@@ -842,7 +843,7 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
   TPG_TRY(ws_reserve(ws, ws->rb1, sizeof(int64_t) * (n + 2)));
   TPG_TRY(ws_reserve(ws, ws->idx0, sizeof(int32_t) * (np + 1)));
   TPG_TRY(ws_reserve(ws, ws->idx1, sizeof(int32_t) * (np + 1)));
-  TPG_TRY(ws_reserve(ws, ws->tp_key, sizeof(uint64_t) * 2 * (np + 1)));
+  TPG_TRY(ws_reserve(ws, ws->tp_key, sizeof(uint64_t) * kTpKeyWords * (np + 1)));
   TPG_HIP(launch_tp_len(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), np, n, b,
                         ws->tp_len.as<int64_t>(), ws->rb0.as<int64_t>(), st));
   TPG_HIP(scan_i64(ws->tp_len.as<int64_t>(), ws->tp_off.as<int64_t>(), np, 0, sc,
@@ -857,15 +858,20 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
   b.pfx = ws->pfx.as<int32_t>();
   b.sfx = ws->sfx.as<int32_t>();
   TPG_HIP(launch_bfs_tables(ws->dg, b, st));
-  TPG_TRY(ws_reserve(ws, ws->tp_vtx, sizeof(int32_t) * (tp_total + 1)));
+  // the plain spliced entries only for the covering, which reads them
+  if (greedy) TPG_TRY(ws_reserve(ws, ws->tp_vtx, sizeof(int32_t) * (tp_total + 1)));
+  const int pe = 64 / eb;
+  TPG_TRY(ws_reserve(ws, ws->tp_pk, sizeof(uint64_t) * ((tp_total + pe - 1) / pe + 2 * np + 4)));
   TPG_HIP(launch_tp_write(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), np, b,
-                          ws->tp_off.as<int64_t>(), ws->tp_vtx.as<int32_t>(),
-                          ws->tp_key.as<uint64_t>(), ws->idx0.as<int32_t>(), st));
+                          ws->tp_off.as<int64_t>(), greedy ? ws->tp_vtx.as<int32_t>() : nullptr,
+                          ws->tp_key.as<uint64_t>(), ws->tp_pk.as<uint64_t>(), eb,
+                          ws->idx0.as<int32_t>(), st));
   // with longest-first covering only the chosen test paths are sorted
   int64_t nm = np;
   if (greedy) TPG_TRY(greedy_select(ws, U, st, np, o, &nm));
   // merge the per-first-vertex runs
-  TpOrder K{ws->tp_off.as<int64_t>(), ws->tp_vtx.as<int32_t>(), ws->tp_key.as<uint64_t>()};
+  TpOrder K{ws->tp_off.as<int64_t>(), ws->tp_key.as<uint64_t>(), ws->tp_pk.as<uint64_t>(), eb,
+            pe};
   int64_t runs = n;
   DevBuf* ri = &ws->rb0;
   DevBuf* ro = &ws->rb1;
@@ -896,10 +902,10 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
   T.n_vtx = ws->h_scalars[3];
   TPG_TRY(ws_reserve(ws, o.tp_off, sizeof(int64_t) * (T.n_tp + 1)));
   TPG_TRY(ws_reserve(ws, o.tp_vtx, sizeof(int32_t) * (T.n_vtx + 1)));
-  TPG_HIP(launch_gather(ws->tp_off.as<int64_t>(), ws->tp_vtx.as<int32_t>(), ii->as<int32_t>(), nm,
-                        ws->keep_pos.as<int64_t>(), ws->keep_voff.as<int64_t>(),
-                        ws->keep_len.as<int64_t>(), o.tp_off.as<int64_t>(), o.tp_vtx.as<int32_t>(),
-                        st));
+  TPG_HIP(launch_splice_gather(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), b,
+                               ii->as<int32_t>(), nm, ws->keep_pos.as<int64_t>(),
+                               ws->keep_voff.as<int64_t>(), ws->keep_len.as<int64_t>(),
+                               o.tp_off.as<int64_t>(), o.tp_vtx.as<int32_t>(), st));
   TPG_HIP(launch_set_i64(o.tp_off.as<int64_t>() + T.n_tp, sc + 3, st));
   int64_t* cs = o.comp_starts.as<int64_t>();
   if (nc > 1)
@@ -1246,7 +1252,7 @@ void tpg_workspace_free(tpg_workspace* ws) {
                     &ws->mask1, &ws->ls, &ws->sub_cnt, &ws->pp_len,
                     &ws->leaf_by_rank, &ws->totals, &ws->cycles, &ws->scan_status,
                     &ws->scan_ctr, &ws->scalars, &ws->bfs_i32, &ws->pfx_off, &ws->sfx_off,
-                    &ws->pfx, &ws->sfx, &ws->tp_len, &ws->tp_off, &ws->tp_vtx, &ws->tp_key, &ws->idx0,
+                    &ws->pfx, &ws->sfx, &ws->tp_len, &ws->tp_off, &ws->tp_vtx, &ws->tp_key, &ws->tp_pk, &ws->idx0,
                     &ws->idx1, &ws->grp_cnt, &ws->rb0, &ws->rb1, &ws->keep_cnt, &ws->keep_len,
                     &ws->keep_pos, &ws->keep_voff, &ws->comp_cnt, &ws->lvl_comp, &ws->b_pp_off,
                     &ws->scan2_status, &ws->scalars2, &ws->digest, &ws->grp_key, &ws->grp_hist,

@@ -167,12 +167,15 @@ struct BfsOut {
   int32_t* ccnt;     // [n]
   int32_t* bq;       // [n] the search queue (graph-wide ids)
 };
-// What the test-path comparison reads: per test path two 64-bit keys (see
-// k_tp_write) and, for the rare ties the keys leave, the entries.
+// What the test-path comparison reads: per test path kTpKeyWords 64-bit keys
+// (see k_tp_write) and, for the rare ties the keys leave, the entries.
+constexpr int kTpKeyWords = 3;
 struct TpOrder {
   const int64_t* off;   // [n + 1] test-path offsets
-  const int32_t* vtx;   // test-path entries
-  const uint64_t* key;  // [2 n]
+  const uint64_t* key;  // [kTpKeyWords n]
+  const uint64_t* pk;   // the entries packed (see k_tp_pack)
+  int eb;               // bits per packed entry (entry + 1; 0 = past the end)
+  int pe;               // packed entries per 64-bit word, 64 / eb
 };
 // one workgroup per component: dist_f, parent, pre, pend, tree children, dist_b, next
 hipError_t launch_bfs_dist(const DGraph& g, const BfsOut& b, hipStream_t st);
@@ -188,20 +191,29 @@ hipError_t launch_comp_pp_starts(const DGraph& g, const uint32_t* sub_cnt, const
 // test-path lengths, and rb[v] = first prime path with first vertex >= v (v = 0..n)
 hipError_t launch_tp_len(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp, int n,
                          const BfsOut& b, int64_t* tp_len, int64_t* rb, hipStream_t st);
-// writes the test paths, their comparison keys and idx[i] = i
+// writes the test paths packed (pk: (n_entries + pe - 1) / pe + 2 n_pp + 4
+// words, pe = 64 / eb), their comparison keys, idx[i] = i and, when tp_vtx
+// is not null, their plain entries
 hipError_t launch_tp_write(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp,
                            const BfsOut& b, const int64_t* tp_off, int32_t* tp_vtx,
-                           uint64_t* key, int32_t* idx, hipStream_t st);
+                           uint64_t* key, uint64_t* pk, int eb, int32_t* idx, hipStream_t st);
 // one round of pairwise merging of sorted runs [rb[r], rb[r+1]) of idx
 hipError_t launch_merge_round(const TpOrder& K, const int32_t* idx_in, int32_t* idx_out,
                               const int64_t* rb, int64_t n_runs, int64_t n, hipStream_t st);
 hipError_t launch_next_runs(const int64_t* rb, int64_t n_runs, int64_t* rb_out, hipStream_t st);
 hipError_t launch_dedup_flags(const TpOrder& K, const int32_t* idx, int64_t n, int64_t* keep_cnt,
                               int64_t* keep_len, hipStream_t st);
+// copies the kept paths (keep_len[k] > 0) of idx to out_off / out_vtx
 hipError_t launch_gather(const int64_t* tp_off, const int32_t* tp_vtx, const int32_t* idx,
                          int64_t n, const int64_t* keep_pos, const int64_t* keep_voff,
                          const int64_t* keep_len, int64_t* out_off, int32_t* out_vtx,
                          hipStream_t st);
+// the same for test paths given by their prime paths (idx: prime-path
+// indices), spliced with the BFS prefix and suffix tables
+hipError_t launch_splice_gather(const int64_t* pp_off, const int32_t* pp_vtx, const BfsOut& b,
+                                const int32_t* idx, int64_t n, const int64_t* keep_pos,
+                                const int64_t* keep_voff, const int64_t* keep_len,
+                                int64_t* out_off, int32_t* out_vtx, hipStream_t st);
 // start[c] / vstart[c] (c = 0..n_comp) of a sorted path list; off[n] = total
 hipError_t launch_comp_bounds(const int64_t* off, const int32_t* vtx, int64_t n,
                               const int32_t* comp, int n_comp, int64_t* start, int64_t* vstart,

@@ -313,12 +313,29 @@ hipError_t launch_tp_len(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n
 //    when none; pre(w) + 1 when there is no e).
 // k1 = pre(w) | pend(w) << 18 | D << 36 | (e exists) << 49
 // k2 = e | split << 17 | pre(u) << 35
+// k3 = the P = 64 / eb entries after e, each as entry + 1 in eb bits (0 past
+//      the end), the first one highest: comparing k3 compares those entries
+//      lexicographically, a path that ends first being the smaller
 constexpr uint64_t kM17 = (1ull << 17) - 1, kM18 = (1ull << 18) - 1, kM13 = (1ull << 13) - 1;
 
+// Packed copy of test path x (entry offset off): its entries, each as
+// entry + 1 in eb bits, pe = 64 / eb to a 64-bit word with the first one
+// highest and 0 past the end, so that comparing words in order compares the
+// entries lexicographically (a path that ends first being the smaller).  The
+// words start at tp_pk_base(off, x), which is even (16-byte aligned) and
+// leaves each path at least its ceil(len / pe) words, so an aligned pair of
+// words that starts inside a path's words stays inside its slot.
+__device__ __forceinline__ int64_t tp_pk_base(int64_t off, int64_t x, int pe) {
+  return ((off + pe - 1) / pe + 2 * x + 1) & ~(int64_t)1;
+}
+
 // A workgroup splices kSplicePaths consecutive test paths: their layout goes
-// to LDS, then the threads write the paths' entries as one flat range (the
-// paths are contiguous in the output), and each entry that leaves the tree
-// path records its position; finally one thread per path builds its key.
+// to LDS, then each thread builds one packed word (pe consecutive entries;
+// the words of the paths are one flat range) and the first entry of it that
+// leaves the tree path records its position; finally one thread per path
+// builds its key.  The plain entries are written only when asked for (tp_vtx
+// not null): the comparisons read the packed words and the kept paths are
+// spliced again when gathered.
 constexpr int kSplicePaths = 64;
 
 struct SpliceRow {
@@ -335,10 +352,13 @@ __device__ __forceinline__ int splice_entry(const SpliceRow& r, const int32_t* p
 
 __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, const int32_t* pp_vtx,
                                                      int64_t n_pp, BfsOut b, const int64_t* tp_off,
-                                                     int32_t* tp_vtx, uint64_t* key, int32_t* idx) {
+                                                     int32_t* tp_vtx, uint64_t* key, uint64_t* pk,
+                                                     int eb, int32_t* idx) {
   __shared__ SpliceRow s_row[kSplicePaths];
-  __shared__ int64_t s_w[kSplicePaths + 1];
+  __shared__ int64_t s_w[kSplicePaths + 1];  // entry offsets
+  __shared__ int64_t s_a[kSplicePaths + 1];  // packed-word offsets
   __shared__ int32_t s_first[kSplicePaths];
+  const int pe = 64 / eb;
   const int tid = (int)threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.x * kSplicePaths;
   const int cnt = (int)(n_pp - i0 < kSplicePaths ? n_pp - i0 : kSplicePaths);
@@ -354,26 +374,47 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
     r.s0 = b.sfx_off[vk];
     r.ls = (int32_t)(b.sfx_off[vk + 1] - r.s0);
     s_row[tid] = r;
-    s_w[tid] = tp_off[i];
+    const int64_t o = tp_off[i];
+    s_w[tid] = o;
+    s_a[tid] = tp_pk_base(o, i, pe);
     s_first[tid] = r.lp + r.lq + r.ls;
     idx[i] = (int32_t)i;
   }
-  if (tid == cnt) s_w[cnt] = tp_off[i0 + cnt];
+  if (tid == cnt) {
+    const int64_t o = tp_off[i0 + cnt];
+    s_w[cnt] = o;
+    s_a[cnt] = tp_pk_base(o, i0 + cnt, pe);
+  }
   __syncthreads();
-  const int64_t e0 = s_w[0], ne = s_w[cnt] - e0;
-  for (int64_t e = tid; e < ne; e += kBlock) {
-    const int64_t pos = e0 + e;
+  const int64_t a0 = s_a[0], na = s_a[cnt] - a0;
+  for (int64_t s = tid; s < na; s += kBlock) {
+    const int64_t wi = a0 + s;
     int lo = 0, hi = cnt - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (s_w[mid] <= pos) lo = mid; else hi = mid - 1;
+      if (s_a[mid] <= wi) lo = mid; else hi = mid - 1;
     }
     const SpliceRow r = s_row[lo];
-    const int64_t k = pos - s_w[lo];
-    const int x = splice_entry(r, pp_vtx, b, k);
-    tp_vtx[pos] = x;
-    if (k > r.lp && b.parent[x] != splice_entry(r, pp_vtx, b, k - 1))
-      atomicMin(&s_first[lo], (int32_t)k);
+    const int len = r.lp + r.lq + r.ls;
+    const int k0 = (int)(wi - s_a[lo]) * pe;
+    if (k0 >= len) continue;  // slack between two paths
+    int prev = k0 > 0 ? splice_entry(r, pp_vtx, b, k0 - 1) : -1;
+    int leave = len;
+    uint64_t w = 0;
+    for (int q = 0; q < pe; ++q) {
+      const int k = k0 + q;
+      uint64_t code = 0;
+      if (k < len) {
+        const int x = splice_entry(r, pp_vtx, b, k);
+        if (tp_vtx) tp_vtx[s_w[lo] + k] = x;
+        if (k > r.lp && leave == len && b.parent[x] != prev) leave = k;
+        prev = x;
+        code = (uint64_t)(x + 1);
+      }
+      w = (w << eb) | code;
+    }
+    pk[wi] = w;
+    if (leave < len) atomicMin(&s_first[lo], (int32_t)leave);
   }
   __syncthreads();
   if (tid < cnt) {
@@ -400,64 +441,76 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
       split = prew + 1;
     }
     const int v1 = splice_entry(r, pp_vtx, b, r.lp);
-    key[2 * i] = (uint64_t)prew | ((uint64_t)pendw << 18) | ((uint64_t)(first - 1) << 36) |
-                 ((uint64_t)(has_e ? 1 : 0) << 49);
-    key[2 * i + 1] = (uint64_t)(uint32_t)ev | ((uint64_t)split << 17) |
-                     ((uint64_t)(uint32_t)b.pre[v1] << 35);
+    uint64_t k3 = 0;
+    for (int q = first + 1; q < first + 1 + 64 / eb; ++q)
+      k3 = (k3 << eb) | (q < len ? (uint64_t)(splice_entry(r, pp_vtx, b, q) + 1) : 0ull);
+    uint64_t* kk = key + (int64_t)kTpKeyWords * i;
+    kk[0] = (uint64_t)prew | ((uint64_t)pendw << 18) | ((uint64_t)(first - 1) << 36) |
+            ((uint64_t)(has_e ? 1 : 0) << 49);
+    kk[1] = (uint64_t)(uint32_t)ev | ((uint64_t)split << 17) | ((uint64_t)(uint32_t)b.pre[v1] << 35);
+    kk[2] = k3;
   }
 }
 
 hipError_t launch_tp_write(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp,
                            const BfsOut& b, const int64_t* tp_off, int32_t* tp_vtx,
-                           uint64_t* key, int32_t* idx, hipStream_t st) {
+                           uint64_t* key, uint64_t* pk, int eb, int32_t* idx, hipStream_t st) {
   if (n_pp == 0) return hipSuccess;
+  if (eb < 1 || eb > 32) return hipErrorInvalidValue;
   k_tp_write<<<(unsigned)((n_pp + kSplicePaths - 1) / kSplicePaths), kBlock, 0, st>>>(
-      pp_off, pp_vtx, n_pp, b, tp_off, tp_vtx, key, idx);
+      pp_off, pp_vtx, n_pp, b, tp_off, tp_vtx, key, pk, eb, idx);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // sort + dedup
 // ---------------------------------------------------------------------------
-// Entries k0.. of two test paths compared lexicographically (then by
-// length), eight entries per step with independent loads.
+// Entries k0.. of two test paths whose entries before k0 agree, compared
+// lexicographically (then by length) on their packed copies: four words per
+// step, two aligned 16-byte loads per path.
 __device__ __forceinline__ int tp_cmp_tail(const TpOrder& K, int64_t x, int64_t y, int64_t k0) {
   const int64_t ox = K.off[x], oy = K.off[y];
   const int64_t lx = K.off[x + 1] - ox, ly = K.off[y + 1] - oy;
-  const int64_t l = lx < ly ? lx : ly;
-  const int32_t* px = K.vtx + ox;
-  const int32_t* py = K.vtx + oy;
-  int64_t k = k0;
-  for (; k + 8 <= l; k += 8) {
-    int32_t a[8], c[8];
+  const int pe = K.pe;
+  const int64_t nw = ((lx < ly ? lx : ly) + pe - 1) / pe;  // words holding entries of both
+  const uint64_t* px = K.pk + tp_pk_base(ox, x, pe);
+  const uint64_t* py = K.pk + tp_pk_base(oy, y, pe);
+  for (int64_t q = (k0 / pe) & ~(int64_t)1; q < nw; q += 4) {
+    uint64_t a[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      a[q] = px[k + q];
-      c[q] = py[k + q];
+    for (int h = 0; h < 2; ++h) {
+      if (q + 2 * h < nw) {
+        const ulonglong2 u = *reinterpret_cast<const ulonglong2*>(px + q + 2 * h);
+        const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(py + q + 2 * h);
+        a[2 * h] = u.x;
+        c[2 * h] = v.x;
+        if (q + 2 * h + 1 < nw) {
+          a[2 * h + 1] = u.y;
+          c[2 * h + 1] = v.y;
+        }
+      }
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-      if (a[q] != c[q]) return a[q] < c[q] ? -1 : 1;
-  }
-  for (; k < l; ++k) {
-    const int32_t a = px[k], c = py[k];
-    if (a != c) return a < c ? -1 : 1;
+    for (int i = 0; i < 4; ++i)
+      if (a[i] != c[i]) return a[i] < c[i] ? -1 : 1;
   }
   return lx < ly ? -1 : (lx > ly ? 1 : 0);
 }
 
-// Lexicographic comparison of test paths x and y from their keys:
+// Lexicographic comparison of test paths x and y from their keys (a*: k1,
+// b*: k2, c*: k3):
 //  * same prime-path first vertex: the order of the prime paths (indices);
 //  * same tree prefix w: no e sorts first (equal when both end there), then
-//    e decides, then the entries after e;
+//    e decides, then the entries after e: the ones packed in k3, then, when
+//    k3 ties and neither path ended inside it, the rest read from memory;
 //  * w_x a proper ancestor of w_y: t_y continues with the tree child c of
 //    w_x towards w_y, t_x with e_x (not a tree child), and e_x < c exactly
 //    when pre(w_y) < split_x; symmetric the other way round;
 //  * otherwise the tree prefixes differ first and preorder decides.
-__device__ __forceinline__ int tp_cmp(const TpOrder& K, int64_t x, int64_t y) {
+__device__ __forceinline__ int tp_cmp_keys(const TpOrder& K, int64_t x, uint64_t ax, uint64_t bx,
+                                           uint64_t cx, int64_t y, uint64_t ay, uint64_t by,
+                                           uint64_t cy) {
   if (x == y) return 0;
-  const uint64_t ax = K.key[2 * x], bx = K.key[2 * x + 1];
-  const uint64_t ay = K.key[2 * y], by = K.key[2 * y + 1];
   if ((bx >> 35) == (by >> 35)) return x < y ? -1 : 1;
   const uint32_t pwx = (uint32_t)(ax & kM18), pwy = (uint32_t)(ay & kM18);
   if (pwx == pwy) {
@@ -465,7 +518,9 @@ __device__ __forceinline__ int tp_cmp(const TpOrder& K, int64_t x, int64_t y) {
     if (!hx || !hy) return hx == hy ? 0 : (hx ? 1 : -1);
     const uint32_t ex = (uint32_t)(bx & kM17), ey = (uint32_t)(by & kM17);
     if (ex != ey) return ex < ey ? -1 : 1;
-    return tp_cmp_tail(K, x, y, (int64_t)((ax >> 36) & kM13) + 2);
+    if (cx != cy) return cx < cy ? -1 : 1;
+    if ((cx & ((1ull << K.eb) - 1)) == 0) return 0;  // both ended inside k3
+    return tp_cmp_tail(K, x, y, (int64_t)((ax >> 36) & kM13) + 2 + K.pe);
   }
   const uint32_t pex = (uint32_t)((ax >> 18) & kM18), pey = (uint32_t)((ay >> 18) & kM18);
   if (pwx < pwy && pwy < pex) return pwy >= (uint32_t)((bx >> 17) & kM18) ? -1 : 1;
@@ -473,33 +528,41 @@ __device__ __forceinline__ int tp_cmp(const TpOrder& K, int64_t x, int64_t y) {
   return pwx < pwy ? -1 : 1;
 }
 
-// Comparison from keys already loaded (x, y: test-path indices).
-__device__ __forceinline__ int tp_cmp_keys(const TpOrder& K, int64_t x, uint64_t ax, uint64_t bx,
-                                           int64_t y, uint64_t ay, uint64_t by) {
+// The same, loading the keys (x, y: test-path indices).
+__device__ __forceinline__ int tp_cmp(const TpOrder& K, int64_t x, int64_t y) {
   if (x == y) return 0;
-  if ((bx >> 35) == (by >> 35)) return x < y ? -1 : 1;
-  const uint32_t pwx = (uint32_t)(ax & kM18), pwy = (uint32_t)(ay & kM18);
-  if (pwx == pwy) {
-    const bool hx = (ax >> 49) & 1, hy = (ay >> 49) & 1;
-    if (!hx || !hy) return hx == hy ? 0 : (hx ? 1 : -1);
-    const uint32_t ex = (uint32_t)(bx & kM17), ey = (uint32_t)(by & kM17);
-    if (ex != ey) return ex < ey ? -1 : 1;
-    return tp_cmp_tail(K, x, y, (int64_t)((ax >> 36) & kM13) + 2);
-  }
-  const uint32_t pex = (uint32_t)((ax >> 18) & kM18), pey = (uint32_t)((ay >> 18) & kM18);
-  if (pwx < pwy && pwy < pex) return pwy >= (uint32_t)((bx >> 17) & kM18) ? -1 : 1;
-  if (pwy < pwx && pwx < pey) return pwx >= (uint32_t)((by >> 17) & kM18) ? 1 : -1;
-  return pwx < pwy ? -1 : 1;
+  const uint64_t* kx = K.key + (int64_t)kTpKeyWords * x;
+  const uint64_t* ky = K.key + (int64_t)kTpKeyWords * y;
+  return tp_cmp_keys(K, x, kx[0], kx[1], kx[2], y, ky[0], ky[1], ky[2]);
 }
 
 // Merge path: number of elements taken from A among the first d outputs of
 // merge(A, B) (stable: A first on ties).  A, B: test-path indices (global).
-__device__ __forceinline__ int64_t merge_split_global(const TpOrder& K, const int32_t* A, int64_t na,
-                                                      const int32_t* B, int64_t nb, int64_t d) {
-  int64_t lo = d - nb > 0 ? d - nb : 0, hi = d < na ? d : na;
+// Found by one whole wave: each step its 64 lanes test 64 evenly spaced
+// candidates at once and the interval shrinks 64-fold, so a search costs
+// ~log_64(n) comparison latencies instead of log_2(n).  This matters where
+// the candidates share a long tree prefix and next entry, because then every
+// comparison reads the paths' entries (dependent global loads).
+__device__ __forceinline__ int64_t merge_split_wave(const TpOrder& K, const int32_t* A, int64_t na,
+                                                    const int32_t* B, int64_t nb, int64_t d) {
+  const int lane = lane_id();
+  int64_t lo = d - nb > 0 ? d - nb : 0, hi = d < na ? d : na;  // answer in [lo, hi]
   while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (tp_cmp(K, B[d - 1 - mid], A[mid]) >= 0) lo = mid + 1; else hi = mid;
+    const int64_t span = hi - lo;
+    const int64_t step = (span + 63) / 64;
+    const int64_t c = lo + (int64_t)lane * step;  // candidate tested by this lane
+    // P(c): the merge takes A[c] before B[d - 1 - c]; true then false along c
+    const bool p = c < hi && tp_cmp(K, B[d - 1 - c], A[c]) >= 0;
+    const uint64_t t = __ballot(p);
+    if (t == 0) {
+      hi = lo;  // P(lo) is false: the split is lo
+    } else {
+      const int k = 63 - __builtin_clzll(t);  // last lane with P true
+      const int64_t ck = lo + (int64_t)k * step;
+      lo = ck + 1;
+      const int64_t nxt = ck + step;
+      hi = nxt < hi ? nxt : hi;
+    }
   }
   return lo;
 }
@@ -520,6 +583,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_round(TpOrder K, const 
   __shared__ int32_t s_idx[kMergeTile];
   __shared__ uint64_t s_k1[kMergeTile];
   __shared__ uint64_t s_k2[kMergeTile];
+  __shared__ uint64_t s_k3[kMergeTile];
   __shared__ int64_t s_seg[4];
   const int tid = (int)threadIdx.x;
   const int64_t t0 = (int64_t)blockIdx.x * kMergeTile;
@@ -540,10 +604,12 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_round(TpOrder K, const 
     const int32_t* B = in + a1;
     const int64_t na = a1 - a0, nb = b1 - a1;
     const int64_t stop = t1 < b1 ? t1 : b1;
-    // input slices of this segment (two searches, by two threads)
-    if (tid < 2) {
-      const int64_t d = (tid == 0 ? pos : stop) - a0;
-      s_seg[tid] = merge_split_global(K, A, na, B, nb, d);
+    // input slices of this segment (two searches, one wave each)
+    {
+      const int w = tid >> 6;
+      const int64_t d = (w == 0 ? pos : stop) - a0;
+      const int64_t r = merge_split_wave(K, A, na, B, nb, d);
+      if ((tid & 63) == 0) s_seg[w] = r;
     }
     __syncthreads();
     const int64_t ia = s_seg[0], ja = (pos - a0) - ia;
@@ -552,8 +618,10 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_round(TpOrder K, const 
     for (int q = tid; q < la + lb; q += kMergeThreads) {
       const int32_t x = q < la ? A[ia + q] : B[ja + (q - la)];
       s_idx[q] = x;
-      s_k1[q] = K.key[2 * (int64_t)x];
-      s_k2[q] = K.key[2 * (int64_t)x + 1];
+      const uint64_t* kx = K.key + (int64_t)kTpKeyWords * x;
+      s_k1[q] = kx[0];
+      s_k2[q] = kx[1];
+      s_k3[q] = kx[2];
     }
     __syncthreads();
     // this thread's outputs within the segment, merged from LDS
@@ -565,7 +633,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_round(TpOrder K, const 
       while (l2 < h2) {
         const int mid = (l2 + h2) >> 1;
         const int qb = la + (d0 - 1 - mid);
-        if (tp_cmp_keys(K, s_idx[qb], s_k1[qb], s_k2[qb], s_idx[mid], s_k1[mid], s_k2[mid]) >= 0)
+        if (tp_cmp_keys(K, s_idx[qb], s_k1[qb], s_k2[qb], s_k3[qb], s_idx[mid], s_k1[mid],
+                        s_k2[mid], s_k3[mid]) >= 0)
           l2 = mid + 1;
         else
           h2 = mid;
@@ -577,7 +646,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_round(TpOrder K, const 
         else if (i >= la) take_a = false;
         else {
           const int qb = la + j;
-          take_a = tp_cmp_keys(K, s_idx[qb], s_k1[qb], s_k2[qb], s_idx[i], s_k1[i], s_k2[i]) >= 0;
+          take_a = tp_cmp_keys(K, s_idx[qb], s_k1[qb], s_k2[qb], s_k3[qb], s_idx[i], s_k1[i],
+                                   s_k2[i], s_k3[i]) >= 0;
         }
         out[pos + o] = take_a ? s_idx[i++] : s_idx[la + j++];
       }
@@ -677,6 +747,69 @@ hipError_t launch_gather(const int64_t* tp_off, const int32_t* tp_vtx, const int
   if (n == 0) return hipSuccess;
   k_gather<<<(unsigned)((n + kSplicePaths - 1) / kSplicePaths), kBlock, 0, st>>>(
       tp_off, tp_vtx, idx, n, keep_pos, keep_voff, keep_len, out_off, out_vtx);
+  return hipGetLastError();
+}
+
+// A workgroup writes the kept paths among kSplicePaths consecutive sorted
+// positions: their layouts (prefix, prime path, suffix) and destinations go
+// to LDS, then the threads splice the entries as one flat range (kept paths
+// are contiguous in the output).
+__global__ __launch_bounds__(kBlock) void k_splice_gather(const int64_t* pp_off,
+                                                          const int32_t* pp_vtx, BfsOut bo, const int32_t* idx, int64_t n,
+                                                   const int64_t* keep_pos,
+                                                   const int64_t* keep_voff,
+                                                   const int64_t* keep_len, int64_t* out_off,
+                                                   int32_t* out_vtx) {
+  __shared__ SpliceRow s_row[kSplicePaths];
+  __shared__ int64_t s_cum[kSplicePaths + 1];
+  __shared__ int64_t s_dst0;
+  __shared__ int32_t s_w[kBlock / 64];
+  const int tid = (int)threadIdx.x;
+  const int64_t k0 = (int64_t)blockIdx.x * kSplicePaths;
+  const int cnt = (int)(n - k0 < kSplicePaths ? n - k0 : kSplicePaths);
+  int64_t len = 0;
+  if (tid < cnt) {
+    const int64_t k = k0 + tid;
+    len = keep_len[k];  // 0 for a duplicate (every kept path has >= 1 entry)
+    if (len) {
+      const int64_t a = idx[k];
+      const int64_t o0 = pp_off[a], o1 = pp_off[a + 1];
+      const int v1 = pp_vtx[o0], vk = pp_vtx[o1 - 1];
+      SpliceRow r;
+      r.o0 = o0;
+      r.p0 = bo.pfx_off[v1];
+      r.lp = (int32_t)(bo.pfx_off[v1 + 1] - r.p0);
+      r.lq = (int32_t)(o1 - o0);
+      r.s0 = bo.sfx_off[vk];
+      r.ls = (int32_t)(bo.sfx_off[vk + 1] - r.s0);
+      s_row[tid] = r;
+      out_off[keep_pos[k]] = keep_voff[k];
+    }
+  }
+  if (tid == 0) s_dst0 = keep_voff[k0];
+  int32_t tot;
+  const int32_t ex = block_excl_scan<kBlock, int32_t>((int32_t)len, tot, s_w);
+  if (tid < cnt) s_cum[tid] = ex;
+  if (tid == 0) s_cum[cnt] = tot;
+  __syncthreads();
+  const int64_t d0 = s_dst0;
+  for (int64_t e = tid; e < tot; e += kBlock) {
+    int lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_cum[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    out_vtx[d0 + e] = splice_entry(s_row[lo], pp_vtx, bo, e - s_cum[lo]);
+  }
+}
+
+hipError_t launch_splice_gather(const int64_t* pp_off, const int32_t* pp_vtx, const BfsOut& b,
+                                const int32_t* idx, int64_t n, const int64_t* keep_pos,
+                                const int64_t* keep_voff, const int64_t* keep_len,
+                                int64_t* out_off, int32_t* out_vtx, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  k_splice_gather<<<(unsigned)((n + kSplicePaths - 1) / kSplicePaths), kBlock, 0, st>>>(
+      pp_off, pp_vtx, b, idx, n, keep_pos, keep_voff, keep_len, out_off, out_vtx);
   return hipGetLastError();
 }
 
