@@ -208,9 +208,9 @@ hipError_t launch_gather(const int64_t* tp_off, const int32_t* tp_vtx, const int
                          int64_t n, const int64_t* keep_pos, const int64_t* keep_voff,
                          const int64_t* keep_len, int64_t* out_off, int32_t* out_vtx,
                          hipStream_t st);
-// the same for test paths given by their prime paths (idx: prime-path
-// indices), spliced with the BFS prefix and suffix tables
-hipError_t launch_splice_gather(const int64_t* pp_off, const int32_t* pp_vtx, const BfsOut& b,
+// the same for test paths held packed (tp_off: their entry offsets, pk: the
+// words k_tp_write built with eb bits per entry)
+hipError_t launch_unpack_gather(const int64_t* tp_off, const uint64_t* pk, int eb,
                                 const int32_t* idx, int64_t n, const int64_t* keep_pos,
                                 const int64_t* keep_voff, const int64_t* keep_len,
                                 int64_t* out_off, int32_t* out_vtx, hipStream_t st);

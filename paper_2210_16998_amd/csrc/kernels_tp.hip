@@ -401,17 +401,29 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
     int prev = k0 > 0 ? splice_entry(r, pp_vtx, b, k0 - 1) : -1;
     int leave = len;
     uint64_t w = 0;
-    for (int q = 0; q < pe; ++q) {
-      const int k = k0 + q;
-      uint64_t code = 0;
-      if (k < len) {
-        const int x = splice_entry(r, pp_vtx, b, k);
-        if (tp_vtx) tp_vtx[s_w[lo] + k] = x;
-        if (k > r.lp && leave == len && b.parent[x] != prev) leave = k;
-        prev = x;
-        code = (uint64_t)(x + 1);
+    for (int q0 = 0; q0 < pe; q0 += 8) {  // eight entries at a time, loads in flight together
+      int x[8], px[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + q0 + j;
+        x[j] = q0 + j < pe && k < len ? splice_entry(r, pp_vtx, b, k) : -1;
       }
-      w = (w << eb) | code;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) px[j] = x[j] >= 0 ? b.parent[x[j]] : -1;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + q0 + j;
+        if (q0 + j < pe) {
+          uint64_t code = 0;
+          if (k < len) {
+            if (tp_vtx) tp_vtx[s_w[lo] + k] = x[j];
+            if (k > r.lp && leave == len && px[j] != prev) leave = k;
+            prev = x[j];
+            code = (uint64_t)(x[j] + 1);
+          }
+          w = (w << eb) | code;
+        }
+      }
     }
     pk[wi] = w;
     if (leave < len) atomicMin(&s_first[lo], (int32_t)leave);
@@ -751,65 +763,78 @@ hipError_t launch_gather(const int64_t* tp_off, const int32_t* tp_vtx, const int
 }
 
 // A workgroup writes the kept paths among kSplicePaths consecutive sorted
-// positions: their layouts (prefix, prime path, suffix) and destinations go
-// to LDS, then the threads splice the entries as one flat range (kept paths
-// are contiguous in the output).
-__global__ __launch_bounds__(kBlock) void k_splice_gather(const int64_t* pp_off,
-                                                          const int32_t* pp_vtx, BfsOut bo, const int32_t* idx, int64_t n,
-                                                   const int64_t* keep_pos,
-                                                   const int64_t* keep_voff,
-                                                   const int64_t* keep_len, int64_t* out_off,
-                                                   int32_t* out_vtx) {
-  __shared__ SpliceRow s_row[kSplicePaths];
-  __shared__ int64_t s_cum[kSplicePaths + 1];
+// positions from their packed words: the paths' first words, lengths and
+// destinations go to LDS, then each thread unpacks one word (pe entries) of
+// the flat range of the kept paths' words into the output, where the kept
+// paths are contiguous.
+__global__ __launch_bounds__(kBlock) void k_unpack_gather(const int64_t* tp_off, const uint64_t* pk,
+                                                          int eb, const int32_t* idx, int64_t n,
+                                                          const int64_t* keep_pos,
+                                                          const int64_t* keep_voff,
+                                                          const int64_t* keep_len,
+                                                          int64_t* out_off, int32_t* out_vtx) {
+  __shared__ int64_t s_src[kSplicePaths];
+  __shared__ int32_t s_cum[kSplicePaths + 1];  // entries before each kept path
+  __shared__ int32_t s_cw[kSplicePaths + 1];   // words before each kept path
   __shared__ int64_t s_dst0;
   __shared__ int32_t s_w[kBlock / 64];
+  const int pe = 64 / eb;
+  const uint64_t emask = (1ull << eb) - 1;
   const int tid = (int)threadIdx.x;
   const int64_t k0 = (int64_t)blockIdx.x * kSplicePaths;
   const int cnt = (int)(n - k0 < kSplicePaths ? n - k0 : kSplicePaths);
-  int64_t len = 0;
+  int32_t len = 0;
   if (tid < cnt) {
     const int64_t k = k0 + tid;
-    len = keep_len[k];  // 0 for a duplicate (every kept path has >= 1 entry)
+    len = (int32_t)keep_len[k];  // 0 for a duplicate (every kept path has >= 1 entry)
     if (len) {
       const int64_t a = idx[k];
-      const int64_t o0 = pp_off[a], o1 = pp_off[a + 1];
-      const int v1 = pp_vtx[o0], vk = pp_vtx[o1 - 1];
-      SpliceRow r;
-      r.o0 = o0;
-      r.p0 = bo.pfx_off[v1];
-      r.lp = (int32_t)(bo.pfx_off[v1 + 1] - r.p0);
-      r.lq = (int32_t)(o1 - o0);
-      r.s0 = bo.sfx_off[vk];
-      r.ls = (int32_t)(bo.sfx_off[vk + 1] - r.s0);
-      s_row[tid] = r;
+      s_src[tid] = tp_pk_base(tp_off[a], a, pe);
       out_off[keep_pos[k]] = keep_voff[k];
     }
   }
   if (tid == 0) s_dst0 = keep_voff[k0];
-  int32_t tot;
-  const int32_t ex = block_excl_scan<kBlock, int32_t>((int32_t)len, tot, s_w);
-  if (tid < cnt) s_cum[tid] = ex;
-  if (tid == 0) s_cum[cnt] = tot;
+  int32_t tot, totw;
+  const int32_t ex = block_excl_scan<kBlock, int32_t>(len, tot, s_w);
+  const int32_t exw = block_excl_scan<kBlock, int32_t>((len + pe - 1) / pe, totw, s_w);
+  if (tid < cnt) {
+    s_cum[tid] = ex;
+    s_cw[tid] = exw;
+  }
+  if (tid == 0) {
+    s_cum[cnt] = tot;
+    s_cw[cnt] = totw;
+  }
   __syncthreads();
   const int64_t d0 = s_dst0;
-  for (int64_t e = tid; e < tot; e += kBlock) {
+  for (int32_t wi = tid; wi < totw; wi += kBlock) {
     int lo = 0, hi = cnt - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (s_cum[mid] <= e) lo = mid; else hi = mid - 1;
+      if (s_cw[mid] <= wi) lo = mid; else hi = mid - 1;
     }
-    out_vtx[d0 + e] = splice_entry(s_row[lo], pp_vtx, bo, e - s_cum[lo]);
+    const int q = wi - s_cw[lo];           // word of the path
+    const int e = q * pe;                  // its first entry
+    const int m = s_cum[lo + 1] - s_cum[lo] - e;
+    const int mm = m < pe ? m : pe;        // entries in this word
+    const uint64_t w = pk[s_src[lo] + q];
+    int32_t* dst = out_vtx + d0 + s_cum[lo] + e;
+    for (int i0 = 0; i0 < mm; i0 += 8) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (i0 + j < mm) dst[i0 + j] = (int32_t)((w >> ((pe - 1 - i0 - j) * eb)) & emask) - 1;
+    }
   }
 }
 
-hipError_t launch_splice_gather(const int64_t* pp_off, const int32_t* pp_vtx, const BfsOut& b,
+hipError_t launch_unpack_gather(const int64_t* tp_off, const uint64_t* pk, int eb,
                                 const int32_t* idx, int64_t n, const int64_t* keep_pos,
                                 const int64_t* keep_voff, const int64_t* keep_len,
                                 int64_t* out_off, int32_t* out_vtx, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  k_splice_gather<<<(unsigned)((n + kSplicePaths - 1) / kSplicePaths), kBlock, 0, st>>>(
-      pp_off, pp_vtx, b, idx, n, keep_pos, keep_voff, keep_len, out_off, out_vtx);
+  if (eb < 1 || eb > 32) return hipErrorInvalidValue;
+  k_unpack_gather<<<(unsigned)((n + kSplicePaths - 1) / kSplicePaths), kBlock, 0, st>>>(
+      tp_off, pk, eb, idx, n, keep_pos, keep_voff, keep_len, out_off, out_vtx);
   return hipGetLastError();
 }
 
