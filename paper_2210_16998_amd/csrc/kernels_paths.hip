@@ -736,6 +736,97 @@ hipError_t launch_down(const ExtArgs& a, int L, int64_t base, int64_t F, uint32_
   return hipGetLastError();
 }
 
+// Two levels per launch: a launch costs ~7 us however little it does, and a
+// sweep has one per level.  One thread per node x of the upper level does
+// the per-level work for x and for each of its children, so the children's
+// level needs no launch of its own (x's children are x's alone, and their
+// counts or ranks are read right after this thread wrote them).
+__global__ __launch_bounds__(kBlock) void k_up2(ExtArgs a, int64_t base, int64_t F,
+                                                uint32_t* sub_cnt, unsigned long long* n_cycles) {
+  __shared__ int32_t s_w[kBlock / 64];
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  int cyc = 0;
+  if (j < F) {
+    const int64_t g = base + j;
+    const uint8_t k = a.t.nch[g];
+    uint32_t c = 0;
+    if (k >= kNchPP) {
+      c = 1;
+      cyc += k == kNchCycle ? 1 : 0;
+    } else if (k) {
+      const int64_t c0 = a.t.cstart[g], c1 = c0 + k;
+      for (int64_t y = c0; y < c1; ++y) {
+        const uint8_t ky = a.t.nch[y];
+        uint32_t cy = 0;
+        if (ky >= kNchPP) {
+          cy = 1;
+          cyc += ky == kNchCycle ? 1 : 0;
+        } else if (ky) {
+          const int64_t z0 = a.t.cstart[y], z1 = z0 + ky;
+          for (int64_t z = z0; z < z1; ++z) cy += sub_cnt[z];
+        }
+        sub_cnt[y] = cy;
+        c += cy;
+      }
+    }
+    sub_cnt[g] = c;
+  }
+  int32_t tot;
+  block_excl_scan<kBlock, int32_t>(cyc, tot, s_w);
+  if (threadIdx.x == 0 && tot) atomicAdd(n_cycles, (unsigned long long)tot);
+}
+
+hipError_t launch_up2(const ExtArgs& a, int64_t base, int64_t F, uint32_t* sub_cnt,
+                      unsigned long long* n_cycles, hipStream_t st) {
+  if (F == 0) return hipSuccess;
+  k_up2<<<(unsigned)((F + kBlock - 1) / kBlock), kBlock, 0, st>>>(a, base, F, sub_cnt, n_cycles);
+  return hipGetLastError();
+}
+
+// Parents of levels L and L + 1 in one launch (thread per node of L).
+__global__ __launch_bounds__(kBlock) void k_down2(ExtArgs a, int L, int64_t base, int64_t F,
+                                                  uint32_t* sub_cnt, int64_t* leaf_by_rank,
+                                                  int32_t* pp_len) {
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= F) return;
+  const int64_t g = base + j;
+  uint32_t r = sub_cnt[g];
+  const uint8_t k = a.t.nch[g];
+  if (r == kNoRank || k == 0 || k >= kNchPP) return;
+  const int64_t c0 = a.t.cstart[g], c1 = c0 + k;
+  for (int64_t y = c0; y < c1; ++y) {
+    const uint32_t cc = sub_cnt[y];
+    const uint8_t ky = a.t.nch[y];
+    sub_cnt[y] = cc ? r : kNoRank;
+    if (cc && ky >= kNchPP) {
+      leaf_by_rank[r] = y;
+      pp_len[r] = L + 1;
+    }
+    if (cc && ky != 0 && ky < kNchPP) {  // y as a parent of level L + 1
+      uint32_t ry = r;
+      const int64_t z0 = a.t.cstart[y], z1 = z0 + ky;
+      for (int64_t z = z0; z < z1; ++z) {
+        const uint32_t cz = sub_cnt[z];
+        sub_cnt[z] = cz ? ry : kNoRank;
+        if (cz && a.t.nch[z] >= kNchPP) {
+          leaf_by_rank[ry] = z;
+          pp_len[ry] = L + 2;
+        }
+        ry += cz;
+      }
+    }
+    r += cc;
+  }
+}
+
+hipError_t launch_down2(const ExtArgs& a, int L, int64_t base, int64_t F, uint32_t* sub_cnt,
+                        int64_t* leaf_by_rank, int32_t* pp_len, hipStream_t st) {
+  if (F == 0) return hipSuccess;
+  k_down2<<<(unsigned)((F + kBlock - 1) / kBlock), kBlock, 0, st>>>(a, L, base, F, sub_cnt,
+                                                                     leaf_by_rank, pp_len);
+  return hipGetLastError();
+}
+
 // Each thread writes one prime path by walking parent links from its leaf.
 // The walk yields entries back to front; they are buffered 32 at a time in
 // registers and stored as one burst of consecutive addresses, so that lines
