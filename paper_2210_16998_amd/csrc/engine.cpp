@@ -630,14 +630,19 @@ tpg_status rank_and_materialize(tpg_workspace* ws, const HostUnion& U, hipStream
     key_add(key, R.count[L]);
   }
   std::vector<uint8_t> key_down = key;
-  // both sweeps take two levels per launch (a launch costs ~7 us however
-  // little it does)
+  // both sweeps take up to kRun levels per launch (a launch costs ~7 us
+  // however little it does)
+  constexpr int kRun = 2;  // 3 measured slower: deeper per-thread chains
   TPG_TRY(run_seq(ws->rank_up, std::move(key), st, [&]() -> hipError_t {
     hipError_t e = launch_zero_u64(ws->cycles.as<uint64_t>(), 1, st);
     unsigned long long* ncyc = ws->cycles.as<unsigned long long>();
-    for (int L = R.Lmax; L >= 1 && e == hipSuccess; L -= 2)
-      e = L >= 2 ? launch_up2(a, R.off[L - 1], R.count[L - 1], sc, ncyc, st)
-                 : launch_up(a, L, R.off[L], R.count[L], sc, ncyc, st);
+    for (int L = R.Lmax; L >= 1 && e == hipSuccess;) {
+      const int n = std::min(kRun, L);  // levels L - n + 1 .. L
+      const int top = L - n + 1;
+      e = n > 1 ? launch_up_run(a, n - 1, R.off[top], R.count[top], sc, ncyc, st)
+                : launch_up(a, top, R.off[top], R.count[top], sc, ncyc, st);
+      L -= n;
+    }
     if (e == hipSuccess)
       e = launch_roots(a, R.count[1], sc, nullptr, nullptr, ws->totals.as<int64_t>(), 0, st);
     return e;
@@ -658,9 +663,12 @@ tpg_status rank_and_materialize(tpg_workspace* ws, const HostUnion& U, hipStream
   key_add(key_down, len);
   TPG_TRY(run_seq(ws->rank_down, std::move(key_down), st, [&]() -> hipError_t {
     hipError_t e = launch_roots(a, R.count[1], sc, lbr, len, ws->totals.as<int64_t>(), 1, st);
-    for (int L = 1; L < R.Lmax && e == hipSuccess; L += 2)
-      e = L + 1 < R.Lmax ? launch_down2(a, L, R.off[L], R.count[L], sc, lbr, len, st)
-                         : launch_down(a, L, R.off[L], R.count[L], sc, lbr, len, st);
+    for (int L = 1; L < R.Lmax && e == hipSuccess;) {
+      const int n = std::min(kRun, R.Lmax - L);  // parents of levels L .. L + n - 1
+      e = n > 1 ? launch_down_run(a, n - 1, L, R.off[L], R.count[L], sc, lbr, len, st)
+                : launch_down(a, L, R.off[L], R.count[L], sc, lbr, len, st);
+      L += n;
+    }
     return e;
   }));
   // offsets of the prime paths: a scan of their lengths

@@ -80,12 +80,14 @@ hipError_t launch_roots(const ExtArgs& a, int64_t n_roots, uint32_t* sub_cnt, in
 // parents of level L: ranks to the children; PP leaves record node and length
 hipError_t launch_down(const ExtArgs& a, int L, int64_t base, int64_t F, uint32_t* sub_cnt,
                        int64_t* leaf_by_rank, int32_t* pp_len, hipStream_t st);
-// the same for two levels in one launch: counts of levels L and L + 1
-// (base, F: level L), and ranks handed down by the parents of L and L + 1
-hipError_t launch_up2(const ExtArgs& a, int64_t base, int64_t F, uint32_t* sub_cnt,
-                      unsigned long long* n_cycles, hipStream_t st);
-hipError_t launch_down2(const ExtArgs& a, int L, int64_t base, int64_t F, uint32_t* sub_cnt,
-                        int64_t* leaf_by_rank, int32_t* pp_len, hipStream_t st);
+// the same for depth + 1 levels in one launch (depth 1 or 2; base, F: the
+// run's top level L): counts of levels L .. L + depth, and ranks handed down
+// by the parents of levels L .. L + depth
+hipError_t launch_up_run(const ExtArgs& a, int depth, int64_t base, int64_t F, uint32_t* sub_cnt,
+                         unsigned long long* n_cycles, hipStream_t st);
+hipError_t launch_down_run(const ExtArgs& a, int depth, int L, int64_t base, int64_t F,
+                           uint32_t* sub_cnt, int64_t* leaf_by_rank, int32_t* pp_len,
+                           hipStream_t st);
 hipError_t launch_pp_write(const ExtArgs& a, const int64_t* leaf_by_rank, const int64_t* pp_off,
                            int64_t n_pp, int32_t* pp_vtx, hipStream_t st);
 

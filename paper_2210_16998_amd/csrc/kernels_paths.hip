@@ -736,94 +736,104 @@ hipError_t launch_down(const ExtArgs& a, int L, int64_t base, int64_t F, uint32_
   return hipGetLastError();
 }
 
-// Two levels per launch: a launch costs ~7 us however little it does, and a
-// sweep has one per level.  One thread per node x of the upper level does
-// the per-level work for x and for each of its children, so the children's
-// level needs no launch of its own (x's children are x's alone, and their
-// counts or ranks are read right after this thread wrote them).
-__global__ __launch_bounds__(kBlock) void k_up2(ExtArgs a, int64_t base, int64_t F,
-                                                uint32_t* sub_cnt, unsigned long long* n_cycles) {
+// D + 1 levels per launch (D = 1, 2): a launch costs ~7 us however little it
+// does, and a sweep has one per level.  One thread per node x of the run's
+// top level does the per-level work for x and for its descendants down to D
+// levels below (they are x's alone, and each count or rank is read right
+// after this thread wrote it); the recursion unrolls at compile time.
+template <int D>
+__device__ __forceinline__ uint32_t up_node(const ExtArgs& a, int64_t x, uint32_t* sub_cnt,
+                                            int& cyc) {
+  const uint8_t k = a.t.nch[x];
+  uint32_t c = 0;
+  if (k >= kNchPP) {
+    c = 1;
+    cyc += k == kNchCycle ? 1 : 0;
+  } else if (k) {
+    const int64_t c0 = a.t.cstart[x], c1 = c0 + k;
+    for (int64_t y = c0; y < c1; ++y) {
+      if constexpr (D > 0)
+        c += up_node<D - 1>(a, y, sub_cnt, cyc);
+      else
+        c += sub_cnt[y];
+    }
+  }
+  sub_cnt[x] = c;
+  return c;
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_up_run(ExtArgs a, int64_t base, int64_t F,
+                                                   uint32_t* sub_cnt,
+                                                   unsigned long long* n_cycles) {
   __shared__ int32_t s_w[kBlock / 64];
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   int cyc = 0;
-  if (j < F) {
-    const int64_t g = base + j;
-    const uint8_t k = a.t.nch[g];
-    uint32_t c = 0;
-    if (k >= kNchPP) {
-      c = 1;
-      cyc += k == kNchCycle ? 1 : 0;
-    } else if (k) {
-      const int64_t c0 = a.t.cstart[g], c1 = c0 + k;
-      for (int64_t y = c0; y < c1; ++y) {
-        const uint8_t ky = a.t.nch[y];
-        uint32_t cy = 0;
-        if (ky >= kNchPP) {
-          cy = 1;
-          cyc += ky == kNchCycle ? 1 : 0;
-        } else if (ky) {
-          const int64_t z0 = a.t.cstart[y], z1 = z0 + ky;
-          for (int64_t z = z0; z < z1; ++z) cy += sub_cnt[z];
-        }
-        sub_cnt[y] = cy;
-        c += cy;
-      }
-    }
-    sub_cnt[g] = c;
-  }
+  if (j < F) up_node<D>(a, base + j, sub_cnt, cyc);
   int32_t tot;
   block_excl_scan<kBlock, int32_t>(cyc, tot, s_w);
   if (threadIdx.x == 0 && tot) atomicAdd(n_cycles, (unsigned long long)tot);
 }
 
-hipError_t launch_up2(const ExtArgs& a, int64_t base, int64_t F, uint32_t* sub_cnt,
-                      unsigned long long* n_cycles, hipStream_t st) {
+hipError_t launch_up_run(const ExtArgs& a, int depth, int64_t base, int64_t F, uint32_t* sub_cnt,
+                         unsigned long long* n_cycles, hipStream_t st) {
   if (F == 0) return hipSuccess;
-  k_up2<<<(unsigned)((F + kBlock - 1) / kBlock), kBlock, 0, st>>>(a, base, F, sub_cnt, n_cycles);
+  const unsigned grid = (unsigned)((F + kBlock - 1) / kBlock);
+  if (depth == 1)
+    k_up_run<1><<<grid, kBlock, 0, st>>>(a, base, F, sub_cnt, n_cycles);
+  else if (depth == 2)
+    k_up_run<2><<<grid, kBlock, 0, st>>>(a, base, F, sub_cnt, n_cycles);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-// Parents of levels L and L + 1 in one launch (thread per node of L).
-__global__ __launch_bounds__(kBlock) void k_down2(ExtArgs a, int L, int64_t base, int64_t F,
-                                                  uint32_t* sub_cnt, int64_t* leaf_by_rank,
-                                                  int32_t* pp_len) {
-  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (j >= F) return;
-  const int64_t g = base + j;
-  uint32_t r = sub_cnt[g];
-  const uint8_t k = a.t.nch[g];
-  if (r == kNoRank || k == 0 || k >= kNchPP) return;
-  const int64_t c0 = a.t.cstart[g], c1 = c0 + k;
+// x (level L, rank r, nch code k) hands ranks to its children; with D > 0
+// each ranked internal child then does the same for its own children.
+template <int D>
+__device__ __forceinline__ void down_node(const ExtArgs& a, int L, int64_t x, uint8_t k,
+                                          uint32_t r, uint32_t* sub_cnt, int64_t* leaf_by_rank,
+                                          int32_t* pp_len) {
+  if (k == 0 || k >= kNchPP) return;
+  const int64_t c0 = a.t.cstart[x], c1 = c0 + k;
   for (int64_t y = c0; y < c1; ++y) {
     const uint32_t cc = sub_cnt[y];
     const uint8_t ky = a.t.nch[y];
     sub_cnt[y] = cc ? r : kNoRank;
-    if (cc && ky >= kNchPP) {
-      leaf_by_rank[r] = y;
-      pp_len[r] = L + 1;
-    }
-    if (cc && ky != 0 && ky < kNchPP) {  // y as a parent of level L + 1
-      uint32_t ry = r;
-      const int64_t z0 = a.t.cstart[y], z1 = z0 + ky;
-      for (int64_t z = z0; z < z1; ++z) {
-        const uint32_t cz = sub_cnt[z];
-        sub_cnt[z] = cz ? ry : kNoRank;
-        if (cz && a.t.nch[z] >= kNchPP) {
-          leaf_by_rank[ry] = z;
-          pp_len[ry] = L + 2;
-        }
-        ry += cz;
+    if (cc) {
+      if (ky >= kNchPP) {
+        leaf_by_rank[r] = y;
+        pp_len[r] = L + 1;
+      } else if constexpr (D > 0) {
+        down_node<D - 1>(a, L + 1, y, ky, r, sub_cnt, leaf_by_rank, pp_len);
       }
     }
     r += cc;
   }
 }
 
-hipError_t launch_down2(const ExtArgs& a, int L, int64_t base, int64_t F, uint32_t* sub_cnt,
-                        int64_t* leaf_by_rank, int32_t* pp_len, hipStream_t st) {
+// Parents of levels L .. L + D in one launch (thread per node of L).
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_down_run(ExtArgs a, int L, int64_t base, int64_t F,
+                                                     uint32_t* sub_cnt, int64_t* leaf_by_rank,
+                                                     int32_t* pp_len) {
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= F) return;
+  const uint32_t r = sub_cnt[base + j];
+  if (r != kNoRank) down_node<D>(a, L, base + j, a.t.nch[base + j], r, sub_cnt, leaf_by_rank, pp_len);
+}
+
+hipError_t launch_down_run(const ExtArgs& a, int depth, int L, int64_t base, int64_t F,
+                           uint32_t* sub_cnt, int64_t* leaf_by_rank, int32_t* pp_len,
+                           hipStream_t st) {
   if (F == 0) return hipSuccess;
-  k_down2<<<(unsigned)((F + kBlock - 1) / kBlock), kBlock, 0, st>>>(a, L, base, F, sub_cnt,
-                                                                     leaf_by_rank, pp_len);
+  const unsigned grid = (unsigned)((F + kBlock - 1) / kBlock);
+  if (depth == 1)
+    k_down_run<1><<<grid, kBlock, 0, st>>>(a, L, base, F, sub_cnt, leaf_by_rank, pp_len);
+  else if (depth == 2)
+    k_down_run<2><<<grid, kBlock, 0, st>>>(a, L, base, F, sub_cnt, leaf_by_rank, pp_len);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
