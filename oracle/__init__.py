@@ -290,6 +290,113 @@ def test_paths_greedy(g, pps: PathList) -> PathList:
     return _take(out)
 
 
+# --- strongly connected components and the paper's path types -------------
+# Types of a prime path (Sec. 2): Def. 2 CompletePP, Def. 8 SccInternalPP,
+# Def. 9 SccExitPP, Def. 10 SccEntryPP; OTHER for none of them.
+PP_COMPLETE, PP_SCC_INTERNAL, PP_SCC_EXIT, PP_SCC_ENTRY, PP_OTHER = 1, 2, 3, 4, 5
+# Per-vertex flags: in a component with a cycle (two or more vertices, or a
+# self-loop); SccEntryVertex (Def. 4: a predecessor outside its component);
+# SccExitVertex (Def. 5: a successor outside its component).
+SCC_CYCLIC, SCC_ENTRY_VERTEX, SCC_EXIT_VERTEX = 1, 2, 4
+
+
+def scc(g) -> np.ndarray:
+    """Strongly connected components (Sec. 2; Tarjan's depth-first algorithm,
+    written with an explicit stack): scc[v] = the smallest vertex of v's
+    component, so that the labelling is unique."""
+    n = g.n
+    index, low, on = [-1] * n, [0] * n, [False] * n
+    stack, out, nxt = [], np.full(n, -1, np.int32), 0
+    for root in range(n):
+        if index[root] >= 0:
+            continue
+        index[root] = low[root] = nxt
+        nxt += 1
+        stack.append(root)
+        on[root] = True
+        work = [[root, 0]]
+        while work:
+            v, i = work[-1]
+            succ = g.succ(v)
+            if i < len(succ):
+                work[-1][1] += 1
+                w = int(succ[i])
+                if index[w] < 0:
+                    index[w] = low[w] = nxt
+                    nxt += 1
+                    stack.append(w)
+                    on[w] = True
+                    work.append([w, 0])
+                elif on[w]:
+                    low[v] = min(low[v], index[w])
+                continue
+            work.pop()
+            if work:
+                u = work[-1][0]
+                low[u] = min(low[u], low[v])
+            if low[v] == index[v]:
+                comp = []
+                while True:
+                    w = stack.pop()
+                    on[w] = False
+                    comp.append(w)
+                    if w == v:
+                        break
+                out[comp] = min(comp)
+    return out
+
+
+def scc_flags(g, comp: np.ndarray) -> np.ndarray:
+    """Per-vertex SCC_CYCLIC / SCC_ENTRY_VERTEX / SCC_EXIT_VERTEX bits."""
+    size = np.bincount(comp, minlength=g.n)
+    fl = np.zeros(g.n, np.uint8)
+    for v in range(g.n):
+        for w in g.succ(v):
+            w = int(w)
+            if w == v:
+                fl[v] |= SCC_CYCLIC
+            if comp[w] != comp[v]:
+                fl[v] |= SCC_EXIT_VERTEX
+                fl[w] |= SCC_ENTRY_VERTEX
+        if size[comp[v]] >= 2:
+            fl[v] |= SCC_CYCLIC
+    return fl
+
+
+def ccfg(g, comp: np.ndarray):
+    """Def. 3: the component graph, as a set of arcs between component
+    labels (the arcs of g whose ends lie in different components)."""
+    return sorted({(int(comp[v]), int(comp[w])) for v in range(g.n) for w in g.succ(v)
+                   if comp[v] != comp[int(w)]})
+
+
+def pp_types(g, pl: PathList) -> Tuple[np.ndarray, np.ndarray]:
+    """Type of each prime path by Defs. 2, 8, 9 and 10 (first match), and the
+    count of each type (index = type).  Def. 8 is read literally: start and
+    end in one component with a cycle; an acyclic one must not start at an
+    SccEntryVertex nor end at an SccExitVertex."""
+    comp = scc(g)
+    fl = scc_flags(g, comp)
+    types = np.zeros(len(pl), np.uint8)
+    for i in range(len(pl)):
+        p = pl[i]
+        a, b = p[0], p[-1]
+        cyclic = len(p) > 1 and a == b
+        if a == g.entry and b == g.exit:
+            t = PP_COMPLETE
+        elif (fl[a] & SCC_CYCLIC) and comp[a] == comp[b] and (
+                cyclic or not (fl[a] & SCC_ENTRY_VERTEX or fl[b] & SCC_EXIT_VERTEX)):
+            t = PP_SCC_INTERNAL
+        elif (fl[a] & SCC_CYCLIC) and b == g.exit:
+            t = PP_SCC_EXIT
+        elif a == g.entry and (fl[b] & SCC_CYCLIC):
+            t = PP_SCC_ENTRY
+        else:
+            t = PP_OTHER
+        types[i] = t
+    return types, np.bincount(types, minlength=6).astype(np.int64)
+
+
 def canonical_bytes(pl: PathList) -> bytes:
     """n (int64 LE) + offsets (int64 LE) + vertices (int32 LE)."""
     return (np.int64(len(pl)).tobytes() + pl.offsets.astype("<i8").tobytes()

@@ -415,3 +415,145 @@ def test_greedy_covering_matches_naive_scan():
         assert all(any(t[k:k + len(q)] == q for t in got for k in range(len(t)))
                    for q in pp.tolist())
         assert set(map(tuple, got)) <= set(map(tuple, full)) and len(got) <= len(full)
+
+
+# --- SCCs, component graph and path types (Sec. 2, Defs. 3-10) -------------
+
+def _fig1_groups():
+    """The Fig. 1 fixture's paths grouped by the section comment above them."""
+    import os
+    from tests.goldens import GOLDEN
+    groups, cur = {}, None
+    for line in open(os.path.join(GOLDEN, "fig1_pps.txt")):
+        if line.startswith("#"):
+            for key in ("internal", "complete", "exit", "entry"):
+                if f"SCC {key} PPs" in line or f"{key} PPs" in line:
+                    cur = key
+            continue
+        if line.strip():
+            groups.setdefault(cur, []).append([int(x) for x in line.split()])
+    return groups
+
+
+def test_fig1_scc_ccfg_and_vertices_match_paper():
+    """Sec. 2 / Defs. 3-5: one component {2,3,4,5,6,8}; its SccEntryVertex is
+    2 and its SccExitVertices are 2 and 5; the CCFG has exactly the two
+    complete paths Start,1,SCC,9,End and Start,1,SCC,7,End."""
+    g = cfggen.fig1_cfg()
+    comp = oracle.scc(g)
+    members = sorted(int(v) for v in np.nonzero(comp == comp[2])[0])
+    assert members == [2, 3, 4, 5, 6, 8]
+    assert all(comp[v] == v for v in (0, 1, 7, 9, 10))
+    fl = oracle.scc_flags(g, comp)
+    cyc = [v for v in range(g.n) if fl[v] & oracle.SCC_CYCLIC]
+    assert cyc == members
+    assert [v for v in members if fl[v] & oracle.SCC_ENTRY_VERTEX] == [2]
+    assert [v for v in members if fl[v] & oracle.SCC_EXIT_VERTEX] == [2, 5]
+    arcs = oracle.ccfg(g, comp)
+    succ = {}
+    for a, b in arcs:
+        succ.setdefault(a, []).append(b)
+    paths, stack = [], [[comp[g.entry]]]
+    while stack:
+        p = stack.pop()
+        if p[-1] == comp[g.exit]:
+            paths.append(p)
+        for b in succ.get(p[-1], []):
+            stack.append(p + [b])
+    assert sorted(paths) == [[0, 1, 2, 7, 10], [0, 1, 2, 9, 10]]
+
+
+def test_fig1_pp_types_match_the_papers_groups():
+    """Sec. 2.1: each printed path has the type of the group it is printed
+    in (11 internal, 2 complete, 4 exit, 2 entry), and no prime path of the
+    graph is of another type."""
+    g = cfggen.fig1_cfg()
+    groups = _fig1_groups()
+    assert {k: len(v) for k, v in groups.items()} == {"internal": 11, "complete": 2,
+                                                      "exit": 4, "entry": 2}
+    want = {"internal": oracle.PP_SCC_INTERNAL, "complete": oracle.PP_COMPLETE,
+            "exit": oracle.PP_SCC_EXIT, "entry": oracle.PP_SCC_ENTRY}
+    for key, paths in groups.items():
+        types, _ = oracle.pp_types(g, PathList.from_lists(paths))
+        assert set(types.tolist()) == {want[key]}, key
+    pp, _, _, _ = _pp(g)
+    _, cnt = oracle.pp_types(g, pp)
+    assert cnt.tolist() == [0, 2, 11, 4, 2, 0]
+
+
+def _reach(g):
+    n = g.n
+    r = np.eye(n, dtype=bool)
+    for v in range(n):
+        for w in g.succ(v):
+            r[v, int(w)] = True
+    for k in range(n):
+        r |= r[:, [k]] & r[[k], :]
+    return r
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_scc_is_mutual_reachability(seed):
+    """Sec. 2: two vertices share a component iff each reaches the other;
+    the label is the smallest member; flags follow Defs. 4-5 by brute force."""
+    n = 1 + seed % 12
+    g = cfggen.random_digraph(7_000 + seed, n, 0.08 + 0.03 * (seed % 6))
+    comp = oracle.scc(g)
+    r = _reach(g)
+    same = r & r.T
+    for v in range(n):
+        members = np.nonzero(same[v])[0]
+        assert comp[v] == members.min()
+    fl = oracle.scc_flags(g, comp)
+    for v in range(n):
+        preds = [u for u in range(n) if v in set(int(w) for w in g.succ(u))]
+        outside_pred = any(not same[u, v] for u in preds)
+        outside_succ = any(not same[v, int(w)] for w in g.succ(v))
+        cyc = same[v].sum() >= 2 or v in set(int(w) for w in g.succ(v))
+        assert bool(fl[v] & oracle.SCC_ENTRY_VERTEX) == outside_pred
+        assert bool(fl[v] & oracle.SCC_EXIT_VERTEX) == outside_succ
+        assert bool(fl[v] & oracle.SCC_CYCLIC) == cyc
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_ccfg_is_acyclic_and_internal_pps_come_from_the_scc_alone(seed):
+    """Defs. 3 and 8, Sec. 2.1: the component graph is a DAG; the internal
+    PPs of each component with a cycle are exactly the PPs of the component
+    taken alone that are cyclic or neither start at one of its entry
+    vertices nor end at one of its exit vertices."""
+    g = cfggen.random_small_cfg(31_000 + seed, 4 + seed % 16, extra=2 + seed % 6)
+    comp = oracle.scc(g)
+    arcs = oracle.ccfg(g, comp)
+    indeg = {}
+    for a, b in arcs:
+        indeg[b] = indeg.get(b, 0) + 1
+    ready = [c for c in set(comp.tolist()) if indeg.get(c, 0) == 0]
+    seen = 0
+    while ready:
+        c = ready.pop()
+        seen += 1
+        for a, b in arcs:
+            if a == c:
+                indeg[b] -= 1
+                if indeg[b] == 0:
+                    ready.append(b)
+    assert seen == len(set(comp.tolist()))
+    fl = oracle.scc_flags(g, comp)
+    pp, _, _, _ = _pp(g)
+    types, _ = oracle.pp_types(g, pp)
+    got = sorted(p for p, t in zip(pp.tolist(), types) if t == oracle.PP_SCC_INTERNAL)
+    want = []
+    for c in sorted(set(comp.tolist())):
+        vs = [int(v) for v in np.nonzero(comp == c)[0]]
+        if not fl[vs[0]] & oracle.SCC_CYCLIC:
+            continue
+        loc = {v: i for i, v in enumerate(vs)}
+        sub = cfggen.from_edges(len(vs), [(loc[a], loc[int(b)]) for a in vs for b in g.succ(a)
+                                          if int(b) in loc], 0, len(vs) - 1)
+        spp, _, _, _ = _pp(sub)
+        for p in spp.tolist():
+            q = [vs[i] for i in p]
+            cyclic = len(q) > 1 and q[0] == q[-1]
+            if cyclic or not (fl[q[0]] & oracle.SCC_ENTRY_VERTEX or fl[q[-1]] & oracle.SCC_EXIT_VERTEX):
+                want.append(q)
+    assert got == sorted(want)
