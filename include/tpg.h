@@ -243,6 +243,52 @@ tpg_status tpg_test_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* p
 void tpg_paths_free(tpg_paths* p);
 
 /* ------------------------------------------------------------------------
+ * Strongly connected components and prime-path types (Sec. 2).
+ *
+ * Per-vertex flags (tpg_scc): the vertex's component has a cycle (two or
+ * more vertices, or a self-loop); SccEntryVertex (Def. 4: an arc enters the
+ * vertex from another component); SccExitVertex (Def. 5: an arc leaves it
+ * for another component).
+ * ---------------------------------------------------------------------- */
+#define TPG_SCC_CYCLIC 0x1u
+#define TPG_SCC_ENTRY_VERTEX 0x2u
+#define TPG_SCC_EXIT_VERTEX 0x4u
+/* Prime-path types (tpg_prime_path_types), the first that matches in this
+ * order: Def. 2 CompletePP (from the entry to the exit); Def. 8
+ * SccInternalPP (starts and ends in one component with a cycle, and if
+ * acyclic neither starts at one of its entry vertices nor ends at one of
+ * its exit vertices); Def. 9 SccExitPP (starts in a component with a cycle,
+ * ends at the exit); Def. 10 SccEntryPP (starts at the entry, ends in a
+ * component with a cycle); TPG_PP_OTHER for none of them (for instance a
+ * path from one component with a cycle to another). */
+#define TPG_PP_COMPLETE 1
+#define TPG_PP_SCC_INTERNAL 2
+#define TPG_PP_SCC_EXIT 3
+#define TPG_PP_SCC_ENTRY 4
+#define TPG_PP_OTHER 5
+
+/* Strongly connected components of g on the device (Sec. 2; they are the
+ * vertices of the component graph, Def. 3).  comp (g's n int32) receives,
+ * per vertex, the smallest vertex of its component; flags (n bytes) the
+ * TPG_SCC_* bits; n_comp the number of components.  All three are host
+ * memory owned by the caller, and any of them may be NULL.  Of opts only
+ * the workspace and the stream are used. */
+tpg_status tpg_scc(const tpg_graph* g, const tpg_opts* opts, int32_t* comp, uint8_t* flags,
+                   int32_t* n_comp);
+
+/* The TPG_PP_* type of each path of pps, a prime-path set of g such as
+ * tpg_prime_paths' output on g, held in host or device memory as
+ * pps->on_device says (a device set must be on the workspace's device and
+ * is read in place, unchecked).  types (pps->n_paths bytes, host, may be
+ * NULL) receives each path's type; counts (6 int64, host, may be NULL) the
+ * number of paths of each type, index = type (counts[0] = 0).  A host set
+ * whose offsets are not increasing from 0 to n_vertices, or whose vertices
+ * lie outside g, gives TPG_ERR_INVALID_ARG.  Of opts only the workspace and
+ * the stream are used. */
+tpg_status tpg_prime_path_types(const tpg_graph* g, const tpg_paths* pps, const tpg_opts* opts,
+                                uint8_t* types, int64_t* counts);
+
+/* ------------------------------------------------------------------------
  * Batched form: prime and test paths of many CFGs in one call.
  *
  * The same computation as tpg_test_paths, per graph.  Graphs are grouped by

@@ -108,6 +108,9 @@ struct tpg_workspace {
   // longest-first covering: prime-path hash table, covering pairs, order,
   // coverers per path, round states, chosen list
   DevBuf cov_keys, cov_vals, cov_misc, pair_p, pair_q, cov_pos, gstate0, gstate1, cov_flag;
+  // components and prime-path types: Tarjan scratch, labels, flags, counters
+  // (n_comp int32 at 0, type counts u64 at 64), a host path set's copy, types
+  DevBuf scc_work, scc_comp, scc_flags, scc_misc, ty_off, ty_vtx, ty_types;
   ExtArgs graph_args{};
   int graph_W = 0, graph_grid = 0, graph_items = 0, graph_variant = 0;
   hipStream_t graph_stream = nullptr;
@@ -1271,6 +1274,8 @@ void tpg_workspace_free(tpg_workspace* ws) {
                     &ws->scan2_status, &ws->scalars2, &ws->digest, &ws->grp_key, &ws->grp_hist,
                     &ws->cov_keys, &ws->cov_vals, &ws->cov_misc, &ws->pair_p, &ws->pair_q,
                     &ws->cov_pos, &ws->gstate0, &ws->gstate1, &ws->cov_flag,
+                    &ws->scc_work, &ws->scc_comp, &ws->scc_flags, &ws->scc_misc, &ws->ty_off,
+                    &ws->ty_vtx, &ws->ty_types,
                     &ws->b_pp_vtx, &ws->b_tp_off, &ws->b_tp_vtx, &ws->b_desc};
   for (DevBuf* b : bufs) ws_release(ws, *b);
   for (OutSet& o : ws->out) {
@@ -1345,6 +1350,90 @@ tpg_status tpg_prime_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* 
   for (auto& e : phase)
     if (e) (void)hipEventDestroy(e);
   return s;
+}
+
+// Components of the uploaded graph (union) into the workspace's scc buffers.
+tpg_status scc_device(tpg_workspace* ws, hipStream_t st) {
+  const int64_t n = std::max<int64_t>(ws->dg.n, 1);
+  TPG_TRY(ws_reserve(ws, ws->scc_work, sizeof(int32_t) * 6 * n));
+  TPG_TRY(ws_reserve(ws, ws->scc_comp, sizeof(int32_t) * n));
+  TPG_TRY(ws_reserve(ws, ws->scc_flags, n));
+  TPG_TRY(ws_reserve(ws, ws->scc_misc, 64 + sizeof(uint64_t) * kPpTypes));
+  TPG_HIP(launch_scc(ws->dg, ws->scc_work.as<int32_t>(), ws->scc_comp.as<int32_t>(),
+                     ws->scc_flags.as<uint8_t>(), ws->scc_misc.as<int32_t>(), st));
+  return TPG_OK;
+}
+
+tpg_status tpg_scc(const tpg_graph* g, const tpg_opts* opts, int32_t* comp, uint8_t* flags,
+                   int32_t* n_comp) {
+  TPG_TRY(check_graph(g));
+  CallCtx c;
+  TPG_TRY(begin_call(opts, c));
+  HostUnion U;
+  add_component(U, g);
+  TPG_TRY(upload_union(c.ws, U, c.st));
+  TPG_TRY(scc_device(c.ws, c.st));
+  if (comp)
+    TPG_HIP(hipMemcpyAsync(comp, c.ws->scc_comp.p, sizeof(int32_t) * U.n, hipMemcpyDeviceToHost,
+                           c.st));
+  if (flags) TPG_HIP(hipMemcpyAsync(flags, c.ws->scc_flags.p, U.n, hipMemcpyDeviceToHost, c.st));
+  int32_t nc = 0;
+  TPG_HIP(hipMemcpyAsync(&nc, c.ws->scc_misc.p, sizeof nc, hipMemcpyDeviceToHost, c.st));
+  TPG_HIP(hipStreamSynchronize(c.st));
+  if (n_comp) *n_comp = nc;
+  return TPG_OK;
+}
+
+tpg_status tpg_prime_path_types(const tpg_graph* g, const tpg_paths* pps, const tpg_opts* opts,
+                                uint8_t* types, int64_t* counts) {
+  TPG_TRY(check_graph(g));
+  if (!pps) return fail(TPG_ERR_INVALID_ARG, "pps is NULL");
+  const int64_t np = pps->n_paths, nv = pps->n_vertices;
+  if (np < 0 || nv < 0 || (np > 0 && (!pps->offsets || !pps->vertices)))
+    return fail(TPG_ERR_INVALID_ARG, "malformed path set");
+  if (!pps->on_device && np > 0) {
+    const int64_t* off = pps->offsets;
+    if (off[0] != 0 || off[np] != nv) return fail(TPG_ERR_INVALID_ARG, "offsets do not span the set");
+    for (int64_t i = 0; i < np; ++i)
+      if (off[i + 1] <= off[i]) return fail(TPG_ERR_INVALID_ARG, "path %lld is empty", (long long)i);
+    for (int64_t k = 0; k < nv; ++k)
+      if (pps->vertices[k] < 0 || pps->vertices[k] >= g->n)
+        return fail(TPG_ERR_INVALID_ARG, "vertex %d outside the graph", pps->vertices[k]);
+  }
+  CallCtx c;
+  TPG_TRY(begin_call(opts, c));
+  tpg_workspace* ws = c.ws;
+  HostUnion U;
+  add_component(U, g);
+  TPG_TRY(upload_union(ws, U, c.st));
+  TPG_TRY(scc_device(ws, c.st));
+  const int64_t* d_off = pps->offsets;
+  const int32_t* d_vtx = pps->vertices;
+  if (!pps->on_device && np > 0) {
+    TPG_TRY(ws_reserve(ws, ws->ty_off, sizeof(int64_t) * (np + 1)));
+    TPG_TRY(ws_reserve(ws, ws->ty_vtx, sizeof(int32_t) * nv));
+    TPG_HIP(hipMemcpyAsync(ws->ty_off.p, pps->offsets, sizeof(int64_t) * (np + 1),
+                           hipMemcpyHostToDevice, c.st));
+    TPG_HIP(hipMemcpyAsync(ws->ty_vtx.p, pps->vertices, sizeof(int32_t) * nv,
+                           hipMemcpyHostToDevice, c.st));
+    d_off = ws->ty_off.as<int64_t>();
+    d_vtx = ws->ty_vtx.as<int32_t>();
+  }
+  uint8_t* d_types = nullptr;
+  if (types && np > 0) {
+    TPG_TRY(ws_reserve(ws, ws->ty_types, np));
+    d_types = ws->ty_types.as<uint8_t>();
+  }
+  unsigned long long* d_cnt = (unsigned long long*)(ws->scc_misc.as<uint8_t>() + 64);
+  TPG_HIP(launch_pp_types(ws->dg, ws->scc_comp.as<int32_t>(), ws->scc_flags.as<uint8_t>(), d_off,
+                          d_vtx, np, d_types, d_cnt, c.st));
+  if (d_types) TPG_HIP(hipMemcpyAsync(types, d_types, np, hipMemcpyDeviceToHost, c.st));
+  uint64_t h_cnt[kPpTypes];
+  TPG_HIP(hipMemcpyAsync(h_cnt, d_cnt, sizeof h_cnt, hipMemcpyDeviceToHost, c.st));
+  TPG_HIP(hipStreamSynchronize(c.st));
+  if (counts)
+    for (int t = 0; t < kPpTypes; ++t) counts[t] = (int64_t)h_cnt[t];
+  return TPG_OK;
 }
 
 tpg_status tpg_test_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* pp_out,

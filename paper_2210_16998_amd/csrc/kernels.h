@@ -102,6 +102,23 @@ hipError_t scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t add, int
 int64_t scan_tiles(int64_t n);  // status slots needed by the scans for n items
 
 hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t st);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
+
+// --- strongly connected components and prime-path types (Sec. 2) ----------
+// per-vertex flags (Defs. 4-5) and path types (Defs. 2, 8, 9, 10); the values
+// are the ones the C API exports
+constexpr uint8_t kSccCyclic = 1, kSccEntryVertex = 2, kSccExitVertex = 4;
+constexpr uint8_t kPpComplete = 1, kPpSccInternal = 2, kPpSccExit = 3, kPpSccEntry = 4,
+                  kPpOther = 5;
+constexpr int kPpTypes = 6;  // counts are indexed by type (index 0 unused)
+// comp[v] = smallest vertex of v's component, flags[v], n_comp[0] = number of
+// components; work: 6 n int32 of scratch
+hipError_t launch_scc(const DGraph& g, int32_t* work, int32_t* comp, uint8_t* flags,
+                      int32_t* n_comp, hipStream_t st);
+// types[i] (may be null) and counts[0 .. kPpTypes) of a prime-path set
+hipError_t launch_pp_types(const DGraph& g, const int32_t* comp, const uint8_t* flags,
+                           const int64_t* off, const int32_t* vtx, int64_t n_pp, uint8_t* types,
+                           unsigned long long* counts, hipStream_t st);
 // --- stable counting sorts by a small integer key (tiles of kGroupTile) -------
 constexpr int kGroupTile = 1024;
 // --- prime paths grouped by last vertex (stable counting sort) ---------------

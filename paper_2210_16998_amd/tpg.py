@@ -27,6 +27,9 @@ TPG_DIGEST_ONLY = 0x10
 TPG_STREAM = 0x20
 TPG_ORDER_BY_LAST = 0x40
 TPG_TP_GREEDY = 0x80
+# strongly connected components and prime-path types (Sec. 2, Defs. 2-10)
+TPG_SCC_CYCLIC, TPG_SCC_ENTRY_VERTEX, TPG_SCC_EXIT_VERTEX = 0x1, 0x2, 0x4
+TPG_PP_COMPLETE, TPG_PP_SCC_INTERNAL, TPG_PP_SCC_EXIT, TPG_PP_SCC_ENTRY, TPG_PP_OTHER = 1, 2, 3, 4, 5
 
 STATUS = {0: "TPG_OK", -1: "TPG_ERR_INVALID_ARG", -2: "TPG_ERR_BAD_CSR",
           -3: "TPG_ERR_BAD_ENTRY_EXIT", -4: "TPG_ERR_UNREACHABLE",
@@ -138,6 +141,10 @@ _SIGS = {
     "tpg_mlp_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
     "tpg_mlp_load": (ctypes.c_int, [ctypes.c_int32, ctypes.c_char_p,
                                     ctypes.POINTER(ctypes.c_void_p)]),
+    "tpg_scc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "tpg_prime_path_types": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Paths),
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "tpg_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "tpg_last_error": (ctypes.c_char_p, []),
     "tpg_version": (ctypes.c_char_p, []),
@@ -395,6 +402,46 @@ def _stream_call(fn, on_chunk, o: _Opts, *args):
     if err:
         raise err[0]
     _check(rc)
+
+
+def scc(g: Graph, ws: Optional[Workspace] = None, stream=None):
+    """(comp int32 [n], flags uint8 [n], n_comp): the smallest vertex of each
+    vertex's strongly connected component and its TPG_SCC_* flags."""
+    n = g.info()[0]
+    comp = np.zeros(max(n, 1), np.int32)
+    fl = np.zeros(max(n, 1), np.uint8)
+    nc = ctypes.c_int32(0)
+    o = _opts(ws, 0, stream, None, 0)
+    _check(lib().tpg_scc(g.handle, ctypes.byref(o), comp.ctypes.data, fl.ctypes.data,
+                         ctypes.byref(nc)))
+    return comp[:n], fl[:n], int(nc.value)
+
+
+def prime_path_types(g: Graph, pps, ws: Optional[Workspace] = None, stream=None,
+                     want_types: bool = True):
+    """(types uint8 [n] or None, counts int64 [6]) of a prime-path set of g:
+    HostPaths / anything with offsets and vertices arrays (host), or
+    DevicePaths (read in place on the device)."""
+    p = _Paths()
+    if isinstance(pps, DevicePaths):
+        p.n_paths, p.n_vertices = pps.n_paths, pps.n_vertices
+        p.offsets, p.vertices, p.on_device = pps.offsets_ptr, pps.vertices_ptr, 1
+        keep = None
+    else:
+        off = np.ascontiguousarray(pps.offsets, dtype=np.int64)
+        vtx = np.ascontiguousarray(pps.vertices, dtype=np.int32)
+        keep = (off, vtx)
+        p.n_paths, p.n_vertices = len(off) - 1, len(vtx)
+        p.offsets, p.vertices, p.on_device = off.ctypes.data, vtx.ctypes.data, 0
+    n = int(p.n_paths)
+    types = np.zeros(max(n, 1), np.uint8) if want_types else None
+    counts = np.zeros(6, np.int64)
+    o = _opts(ws, 0, stream, None, 0)
+    _check(lib().tpg_prime_path_types(g.handle, ctypes.byref(p), ctypes.byref(o),
+                                      types.ctypes.data if want_types else None,
+                                      counts.ctypes.data))
+    del keep
+    return (types[:n] if want_types else None), counts
 
 
 def prime_paths_stream(g: Graph, on_chunk, ws: Optional[Workspace] = None, flags: int = 0,
