@@ -201,6 +201,43 @@ def _covering(args):
     return out
 
 
+def _components(args):
+    """Strongly connected components and prime-path types (Sec. 2) on the
+    benchmark CFG: the device SCC pass, and the classification of its
+    device-resident prime-path set (counts only)."""
+    import torch
+    from paper_2210_16998_amd import tpg
+    g, rec = _workload()
+    h = tpg.load_cfg(g)
+    ws = tpg.Workspace(0)
+    stream = torch.cuda.Stream()
+    pp, _ = tpg.prime_paths(h, ws=ws, flags=tpg.TPG_OUT_DEVICE | tpg.TPG_NO_TIMING, stream=stream)
+    out = {}
+    for name, fn in (("scc_ms", lambda: tpg.scc(h, ws=ws, stream=stream)),
+                     ("types_ms", lambda: tpg.prime_path_types(h, pp, ws=ws, stream=stream,
+                                                               want_types=False))):
+        for _ in range(3):
+            r = fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            r = fn()
+        torch.cuda.synchronize()
+        out[name] = 1000.0 * (time.perf_counter() - t) / args.steps
+        if name == "scc_ms":
+            comp, fl = r[0], r[1]
+            out["n_components"] = r[2]
+            out["n_components_with_cycle"] = int(len(set(comp[(fl & tpg.TPG_SCC_CYCLIC) > 0].tolist())))
+        else:
+            names = ["", "complete", "scc_internal", "scc_exit", "scc_entry", "other"]
+            out["types"] = {names[t]: int(r[1][t]) for t in range(1, 6)}
+    ws.close()
+    out["workload"] = (f"the benchmark CFG ({g.n} vertices, {out['n_components']} components): "
+                       f"device SCC pass, and the types of its {len(pp)} prime paths held on the "
+                       f"device (each call includes the graph upload and the SCC pass)")
+    return out
+
+
 def _cpu_baseline(g, reps: int):
     """The CPU oracle on the same graph (DFS enumeration from every vertex,
     local-rule prime test, splice + sort + dedup of test paths)."""
@@ -240,6 +277,7 @@ def main() -> int:
     ap.add_argument("--stress-reps", type=int, default=3)
     ap.add_argument("--no-paper-form", action="store_true")
     ap.add_argument("--no-covering", action="store_true")
+    ap.add_argument("--no-components", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is "
@@ -357,6 +395,8 @@ def main() -> int:
         out["paper_form"] = _paper_form(args)
     if not args.no_covering:
         out["covering"] = _covering(args)
+    if not args.no_components:
+        out["components"] = _components(args)
     if not args.no_batch:
         out["batched"] = _batched(args)
     if not args.no_cpu:
