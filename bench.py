@@ -238,6 +238,40 @@ def _components(args):
     return out
 
 
+def _prior_schedule(args):
+    """The paper's per-vertex schedule (comparison variant) against the path
+    tree, both giving the prime paths grouped by end vertex.  Its lists copy
+    whole paths and one thread serves each vertex, so it is run on a while
+    loop around 12 if-else diamonds (163 841 prime paths), not on the
+    benchmark CFG."""
+    import torch
+    from paper_2210_16998_amd import cfggen, tpg
+    k = 12
+    g = cfggen.loop_diamond_chain(k)
+    h = tpg.load_cfg(g)
+    ws = tpg.Workspace(0)
+    stream = torch.cuda.Stream()
+    out = {}
+    for name, fn in (("vertex_lists", tpg.prime_paths_vertex_lists),
+                     ("path_tree", lambda h, **kw: tpg.prime_paths(
+                         h, **{**kw, "flags": kw["flags"] | tpg.TPG_ORDER_BY_LAST}))):
+        f = tpg.TPG_OUT_DEVICE | tpg.TPG_NO_TIMING
+        fn(h, ws=ws, flags=f, stream=stream)
+        torch.cuda.synchronize()
+        reps = max(1, min(args.steps, 5))
+        t = time.perf_counter()
+        for _ in range(reps):
+            _, st = fn(h, ws=ws, flags=f, stream=stream)
+        torch.cuda.synchronize()
+        out[name] = {"ms_per_call": 1000.0 * (time.perf_counter() - t) / reps,
+                     "n_pp": st["n_pp"], "n_extensions": st["n_extensions"]}
+    ws.close()
+    out["slowdown"] = out["vertex_lists"]["ms_per_call"] / out["path_tree"]["ms_per_call"]
+    out["workload"] = (f"while loop around {k} if-else diamonds ({g.n} vertices, "
+                       f"{(3 * k + 4) * 2 ** k + 1} prime paths), prime paths grouped by end vertex")
+    return out
+
+
 def _cpu_baseline(g, reps: int):
     """The CPU oracle on the same graph (DFS enumeration from every vertex,
     local-rule prime test, splice + sort + dedup of test paths)."""
@@ -278,6 +312,7 @@ def main() -> int:
     ap.add_argument("--no-paper-form", action="store_true")
     ap.add_argument("--no-covering", action="store_true")
     ap.add_argument("--no-components", action="store_true")
+    ap.add_argument("--no-prior-schedule", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is "
@@ -397,6 +432,8 @@ def main() -> int:
         out["covering"] = _covering(args)
     if not args.no_components:
         out["components"] = _components(args)
+    if not args.no_prior_schedule:
+        out["prior_schedule"] = _prior_schedule(args)
     if not args.no_batch:
         out["batched"] = _batched(args)
     if not args.no_cpu:

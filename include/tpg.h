@@ -243,6 +243,28 @@ tpg_status tpg_test_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* p
 void tpg_paths_free(tpg_paths* p);
 
 /* ------------------------------------------------------------------------
+ * The paper's own schedule, as a comparison variant (Sec. 4: the
+ * Update-Vertex kernel and ExtendPath).  Every vertex owns a list of whole
+ * paths ending at it; in each round one thread per vertex appends to its
+ * list every path of a predecessor's newest paths that it can extend (not a
+ * cycle, and the vertex absent from it or its first entry), marking that
+ * path as extended; a round's paths are then kept when prime (a cycle, or
+ * neither extended nor extendable backwards).  The paper lets the threads
+ * run asynchronously until no list changes; here each round is a pair of
+ * launches, so no thread waits on another, and the lists hold whole copies
+ * of the paths as in the paper.
+ *
+ * out receives the prime paths of g grouped by last vertex (ascending), the
+ * paper's output form; inside a group, by length, then in list order.  The
+ * set equals tpg_prime_paths'.  opts as for tpg_prime_paths, without
+ * TPG_STREAM or TPG_TP_GREEDY (TPG_ERR_INVALID_ARG).  stats: n_levels
+ * (rounds), n_nodes (paths in all lists), n_extensions, n_pp,
+ * n_pp_vertices, device_bytes, ms_total.
+ * ---------------------------------------------------------------------- */
+tpg_status tpg_prime_paths_vertex_lists(const tpg_graph* g, const tpg_opts* opts,
+                                        tpg_paths* out);
+
+/* ------------------------------------------------------------------------
  * Strongly connected components and prime-path types (Sec. 2).
  *
  * Per-vertex flags (tpg_scc): the vertex's component has a cycle (two or

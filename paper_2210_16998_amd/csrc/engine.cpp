@@ -111,6 +111,9 @@ struct tpg_workspace {
   // components and prime-path types: Tarjan scratch, labels, flags, counters
   // (n_comp int32 at 0, type counts u64 at 64), a host path set's copy, types
   DevBuf scc_work, scc_comp, scc_flags, scc_misc, ty_off, ty_vtx, ty_types;
+  // the per-vertex schedule: two rounds of rows, their offsets and marks,
+  // per-vertex counts, prime flags and their positions
+  DevBuf pv_rows0, pv_rows1, pv_voff0, pv_voff1, pv_ext, pv_cnt, pv_flag, pv_pos;
   ExtArgs graph_args{};
   int graph_W = 0, graph_grid = 0, graph_items = 0, graph_variant = 0;
   hipStream_t graph_stream = nullptr;
@@ -1276,6 +1279,8 @@ void tpg_workspace_free(tpg_workspace* ws) {
                     &ws->cov_pos, &ws->gstate0, &ws->gstate1, &ws->cov_flag,
                     &ws->scc_work, &ws->scc_comp, &ws->scc_flags, &ws->scc_misc, &ws->ty_off,
                     &ws->ty_vtx, &ws->ty_types,
+                    &ws->pv_rows0, &ws->pv_rows1, &ws->pv_voff0, &ws->pv_voff1, &ws->pv_ext,
+                    &ws->pv_cnt, &ws->pv_flag, &ws->pv_pos,
                     &ws->b_pp_vtx, &ws->b_tp_off, &ws->b_tp_vtx, &ws->b_desc};
   for (DevBuf* b : bufs) ws_release(ws, *b);
   for (OutSet& o : ws->out) {
@@ -1433,6 +1438,115 @@ tpg_status tpg_prime_path_types(const tpg_graph* g, const tpg_paths* pps, const 
   TPG_HIP(hipStreamSynchronize(c.st));
   if (counts)
     for (int t = 0; t < kPpTypes; ++t) counts[t] = (int64_t)h_cnt[t];
+  return TPG_OK;
+}
+
+tpg_status tpg_prime_paths_vertex_lists(const tpg_graph* g, const tpg_opts* opts,
+                                        tpg_paths* out) {
+  if (!out) return fail(TPG_ERR_INVALID_ARG, "out is NULL");
+  memset(out, 0, sizeof *out);
+  TPG_TRY(check_graph(g));
+  CallCtx c;
+  TPG_TRY(begin_call(opts, c));
+  if (c.flags & (TPG_STREAM | TPG_TP_GREEDY))
+    return fail(TPG_ERR_INVALID_ARG, "the per-vertex schedule is not streamed");
+  tpg_workspace* ws = c.ws;
+  hipStream_t st = c.st;
+  HostUnion U;
+  add_component(U, g);
+  TPG_TRY(upload_union(ws, U, st));
+  const int n = U.n;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const bool timing = c.stats && !(c.flags & TPG_NO_TIMING);
+  if (timing) {
+    TPG_HIP(hipEventCreate(&e0));
+    TPG_HIP(hipEventCreate(&e1));
+    TPG_HIP(hipEventRecord(e0, st));
+  }
+  OutSet& o = ws->out[0];
+  DevBuf* rows = &ws->pv_rows0;
+  DevBuf* nrows = &ws->pv_rows1;
+  DevBuf* voff = &ws->pv_voff0;
+  DevBuf* nvoff = &ws->pv_voff1;
+  TPG_TRY(ws_reserve(ws, *voff, sizeof(int64_t) * (n + 1)));
+  TPG_TRY(ws_reserve(ws, *nvoff, sizeof(int64_t) * (n + 1)));
+  TPG_TRY(ws_reserve(ws, *rows, sizeof(int32_t) * n));
+  TPG_TRY(ws_reserve(ws, ws->pv_cnt, sizeof(int32_t) * (n + 1)));
+  TPG_TRY(ws_reserve(ws, o.pp_off, sizeof(int64_t) * 1024));
+  TPG_TRY(ws_reserve(ws, o.pp_vtx, sizeof(int32_t) * 1024));
+  TPG_TRY(reserve_scan(ws, n));
+  TPG_HIP(launch_pv_init(n, voff->as<int64_t>(), rows->as<int32_t>(), st));
+  int64_t* sc = ws->scalars.as<int64_t>();
+  int64_t n_rows = n, n_pp = 0, n_vtx = 0, n_ext = 0, levels = 0;
+  for (int L = 1; n_rows > 0; ++L) {
+    if (L >= kMaxLevels) return fail(TPG_ERR_UNSUPPORTED, "more levels than supported");
+    levels = L;
+    // round L + 1: counts, offsets, rows; round L's rows get their marks
+    TPG_TRY(ws_reserve(ws, ws->pv_ext, (n_rows + 8) & ~(int64_t)7));
+    TPG_HIP(launch_zero_u64(ws->pv_ext.as<uint64_t>(), (n_rows + 7) / 8, st));
+    TPG_HIP(launch_pv_count(ws->dg, L, voff->as<int64_t>(), rows->as<int32_t>(),
+                            ws->pv_cnt.as<int32_t>(), st));
+    TPG_HIP(scan_i32_to_i64(ws->pv_cnt.as<int32_t>(), nvoff->as<int64_t>(), n, 0, sc,
+                            ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
+    TPG_HIP(launch_set_i64(nvoff->as<int64_t>() + n, sc, st));
+    TPG_HIP(hipMemcpyAsync(ws->h_scalars, sc, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    TPG_HIP(hipStreamSynchronize(st));
+    const int64_t n_next = ws->h_scalars[0];
+    if (n_next > 0) {
+      TPG_TRY(ws_reserve(ws, *nrows, sizeof(int32_t) * n_next * (L + 1)));
+      TPG_HIP(launch_pv_fill(ws->dg, L, voff->as<int64_t>(), rows->as<int32_t>(),
+                             ws->pv_ext.as<uint8_t>(), nvoff->as<int64_t>(),
+                             nrows->as<int32_t>(), st));
+    }
+    // round L is final: append its prime rows
+    TPG_TRY(ws_reserve(ws, ws->pv_flag, sizeof(int32_t) * (n_rows + 1)));
+    TPG_TRY(ws_reserve(ws, ws->pv_pos, sizeof(int64_t) * (n_rows + 1)));
+    TPG_TRY(reserve_scan(ws, n_rows));
+    TPG_HIP(launch_pv_prime(ws->dg, L, rows->as<int32_t>(), ws->pv_ext.as<uint8_t>(), n_rows,
+                            ws->pv_flag.as<int32_t>(), st));
+    TPG_HIP(scan_i32_to_i64(ws->pv_flag.as<int32_t>(), ws->pv_pos.as<int64_t>(), n_rows, 0, sc + 1,
+                            ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
+    TPG_HIP(hipMemcpyAsync(ws->h_scalars + 1, sc + 1, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    TPG_HIP(hipStreamSynchronize(st));
+    const int64_t np_round = ws->h_scalars[1];
+    if (np_round > 0) {
+      TPG_TRY(ws_reserve(ws, o.pp_off, sizeof(int64_t) * (n_pp + np_round + 1), true, st,
+                         sizeof(int64_t) * n_pp));
+      TPG_TRY(ws_reserve(ws, o.pp_vtx, sizeof(int32_t) * (n_vtx + np_round * L + 1), true, st,
+                         sizeof(int32_t) * n_vtx));
+      TPG_HIP(launch_pv_emit(L, rows->as<int32_t>(), ws->pv_flag.as<int32_t>(),
+                             ws->pv_pos.as<int64_t>(), n_rows, n_pp, n_vtx,
+                             o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), st));
+      n_pp += np_round;
+      n_vtx += np_round * L;
+    }
+    n_ext += n_next;
+    n_rows = n_next;
+    std::swap(rows, nrows);
+    std::swap(voff, nvoff);
+  }
+  ws->h_scalars[2] = n_vtx;
+  TPG_HIP(hipMemcpyAsync(o.pp_off.as<int64_t>() + n_pp, ws->h_scalars + 2, sizeof(int64_t),
+                         hipMemcpyHostToDevice, st));
+  // the paper's output: the prime paths ending at each vertex
+  TPG_TRY(group_by_last(ws, n, st, o, n_pp, n_vtx));
+  if (timing) TPG_HIP(hipEventRecord(e1, st));
+  TPG_TRY(deliver_set(ws, o.ppg_off, o.ppg_vtx, n_pp, n_vtx, c.flags, st, out));
+  TPG_HIP(hipStreamSynchronize(st));
+  if (c.stats) {
+    memset(c.stats, 0, sizeof *c.stats);
+    c.stats->n_levels = levels;
+    c.stats->n_nodes = n + n_ext;
+    c.stats->n_extensions = n_ext;
+    c.stats->n_pp = n_pp;
+    c.stats->n_pp_vertices = n_vtx;
+    c.stats->device_bytes = (int64_t)ws->bytes;
+    if (timing) c.stats->ms_total = Timer::ms(e0, e1);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  o.n_pp = n_pp;
+  o.n_ppv = n_vtx;
   return TPG_OK;
 }
 

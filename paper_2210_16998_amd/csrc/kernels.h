@@ -115,6 +115,18 @@ constexpr int kPpTypes = 6;  // counts are indexed by type (index 0 unused)
 // components; work: 6 n int32 of scratch
 hipError_t launch_scc(const DGraph& g, int32_t* work, int32_t* comp, uint8_t* flags,
                       int32_t* n_comp, hipStream_t st);
+// --- the paper's per-vertex schedule (comparison variant) ------------------
+hipError_t launch_pv_init(int n, int64_t* voff, int32_t* rows, hipStream_t st);
+hipError_t launch_pv_count(const DGraph& g, int L, const int64_t* voff, const int32_t* rows,
+                           int32_t* cnt, hipStream_t st);
+hipError_t launch_pv_fill(const DGraph& g, int L, const int64_t* voff, const int32_t* rows,
+                          uint8_t* extended, const int64_t* nvoff, int32_t* nrows,
+                          hipStream_t st);
+hipError_t launch_pv_prime(const DGraph& g, int L, const int32_t* rows, const uint8_t* extended,
+                           int64_t n_rows, int32_t* flag, hipStream_t st);
+hipError_t launch_pv_emit(int L, const int32_t* rows, const int32_t* flag, const int64_t* pos,
+                          int64_t n_rows, int64_t base, int64_t voff0, int64_t* out_off,
+                          int32_t* out_vtx, hipStream_t st);
 // types[i] (may be null) and counts[0 .. kPpTypes) of a prime-path set
 hipError_t launch_pp_types(const DGraph& g, const int32_t* comp, const uint8_t* flags,
                            const int64_t* off, const int32_t* vtx, int64_t n_pp, uint8_t* types,

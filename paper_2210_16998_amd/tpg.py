@@ -141,6 +141,8 @@ _SIGS = {
     "tpg_mlp_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
     "tpg_mlp_load": (ctypes.c_int, [ctypes.c_int32, ctypes.c_char_p,
                                     ctypes.POINTER(ctypes.c_void_p)]),
+    "tpg_prime_paths_vertex_lists": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                                    ctypes.POINTER(_Paths)]),
     "tpg_scc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "tpg_prime_path_types": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Paths),
@@ -402,6 +404,17 @@ def _stream_call(fn, on_chunk, o: _Opts, *args):
     if err:
         raise err[0]
     _check(rc)
+
+
+def prime_paths_vertex_lists(g: Graph, ws: Optional[Workspace] = None, flags: int = 0,
+                             stream=None, pool_cap: int = 0):
+    """(paths, stats) by the paper's per-vertex schedule: prime paths grouped
+    by last vertex, by length inside a group."""
+    st = _Stats()
+    o = _opts(ws, flags, stream, st, pool_cap)
+    out = _Paths()
+    _check(lib().tpg_prime_paths_vertex_lists(g.handle, ctypes.byref(o), ctypes.byref(out)))
+    return _wrap(out), _stats_dict(st)
 
 
 def scc(g: Graph, ws: Optional[Workspace] = None, stream=None):
