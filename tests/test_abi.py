@@ -85,3 +85,21 @@ def test_generated_workloads_load():
 def test_no_device_is_an_error_not_a_fallback():
     g = tpg.load_cfg(cfggen.fig1_cfg())
     assert _err(lambda: tpg.prime_paths(g)) == "TPG_ERR_DEVICE"
+
+
+def test_path_type_inputs_are_checked_on_the_host():
+    """Malformed host path sets are rejected before any device work; a valid
+    one reaches the device, which this machine lacks (an error, not a
+    fallback)."""
+    g = tpg.load_cfg(cfggen.fig1_cfg())
+
+    class P:
+        def __init__(self, off, vtx):
+            self.offsets = np.array(off, np.int64)
+            self.vertices = np.array(vtx, np.int32)
+    assert _err(lambda: tpg.prime_path_types(g, P([0, 2, 2], [0, 1]))) == "TPG_ERR_INVALID_ARG"
+    assert _err(lambda: tpg.prime_path_types(g, P([1, 2], [0, 1]))) == "TPG_ERR_INVALID_ARG"
+    assert _err(lambda: tpg.prime_path_types(g, P([0, 2], [0, 11]))) == "TPG_ERR_INVALID_ARG"
+    assert _err(lambda: tpg.prime_path_types(g, P([0, 2], [0, 1]))) == "TPG_ERR_DEVICE"
+    assert _err(lambda: tpg.scc(g)) == "TPG_ERR_DEVICE"
+    assert _err(lambda: tpg.prime_paths_vertex_lists(g)) == "TPG_ERR_DEVICE"
