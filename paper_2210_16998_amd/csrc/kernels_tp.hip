@@ -762,27 +762,33 @@ hipError_t launch_gather(const int64_t* tp_off, const int32_t* tp_vtx, const int
   return hipGetLastError();
 }
 
-// A workgroup writes the kept paths among kSplicePaths consecutive sorted
+// A workgroup writes the kept paths among kGatherPaths consecutive sorted
 // positions from their packed words: the paths' first words, lengths and
 // destinations go to LDS, then each thread unpacks one word (pe entries) of
-// the flat range of the kept paths' words into the output, where the kept
-// paths are contiguous.
+// the flat range of the kept paths' words.  The kept paths are contiguous in
+// the output, so when the workgroup's entries fit kGatherStage they are
+// unpacked into LDS and stored by consecutive threads (whole lines); a
+// larger range is stored straight from the words.
+constexpr int kGatherPaths = 32;
+constexpr int kGatherStage = 4096;  // int32 entries staged in LDS (16 KiB)
+
 __global__ __launch_bounds__(kBlock) void k_unpack_gather(const int64_t* tp_off, const uint64_t* pk,
                                                           int eb, const int32_t* idx, int64_t n,
                                                           const int64_t* keep_pos,
                                                           const int64_t* keep_voff,
                                                           const int64_t* keep_len,
                                                           int64_t* out_off, int32_t* out_vtx) {
-  __shared__ int64_t s_src[kSplicePaths];
-  __shared__ int32_t s_cum[kSplicePaths + 1];  // entries before each kept path
-  __shared__ int32_t s_cw[kSplicePaths + 1];   // words before each kept path
+  __shared__ int64_t s_src[kGatherPaths];
+  __shared__ int32_t s_cum[kGatherPaths + 1];  // entries before each kept path
+  __shared__ int32_t s_cw[kGatherPaths + 1];   // words before each kept path
+  __shared__ int32_t s_stage[kGatherStage];
   __shared__ int64_t s_dst0;
   __shared__ int32_t s_w[kBlock / 64];
   const int pe = 64 / eb;
   const uint64_t emask = (1ull << eb) - 1;
   const int tid = (int)threadIdx.x;
-  const int64_t k0 = (int64_t)blockIdx.x * kSplicePaths;
-  const int cnt = (int)(n - k0 < kSplicePaths ? n - k0 : kSplicePaths);
+  const int64_t k0 = (int64_t)blockIdx.x * kGatherPaths;
+  const int cnt = (int)(n - k0 < kGatherPaths ? n - k0 : kGatherPaths);
   int32_t len = 0;
   if (tid < cnt) {
     const int64_t k = k0 + tid;
@@ -807,6 +813,7 @@ __global__ __launch_bounds__(kBlock) void k_unpack_gather(const int64_t* tp_off,
   }
   __syncthreads();
   const int64_t d0 = s_dst0;
+  const bool staged = tot <= kGatherStage;  // the same for every thread
   for (int32_t wi = tid; wi < totw; wi += kBlock) {
     int lo = 0, hi = cnt - 1;
     while (lo < hi) {
@@ -818,12 +825,23 @@ __global__ __launch_bounds__(kBlock) void k_unpack_gather(const int64_t* tp_off,
     const int m = s_cum[lo + 1] - s_cum[lo] - e;
     const int mm = m < pe ? m : pe;        // entries in this word
     const uint64_t w = pk[s_src[lo] + q];
-    int32_t* dst = out_vtx + d0 + s_cum[lo] + e;
+    const int at = s_cum[lo] + e;          // position in the workgroup's range
     for (int i0 = 0; i0 < mm; i0 += 8) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if (i0 + j < mm) dst[i0 + j] = (int32_t)((w >> ((pe - 1 - i0 - j) * eb)) & emask) - 1;
+      for (int j = 0; j < 8; ++j) {
+        if (i0 + j < mm) {
+          const int32_t x = (int32_t)((w >> ((pe - 1 - i0 - j) * eb)) & emask) - 1;
+          if (staged)
+            s_stage[at + i0 + j] = x;
+          else
+            out_vtx[d0 + at + i0 + j] = x;
+        }
+      }
     }
+  }
+  if (staged) {
+    __syncthreads();
+    for (int32_t e = tid; e < tot; e += kBlock) out_vtx[d0 + e] = s_stage[e];
   }
 }
 
@@ -833,7 +851,7 @@ hipError_t launch_unpack_gather(const int64_t* tp_off, const uint64_t* pk, int e
                                 int64_t* out_off, int32_t* out_vtx, hipStream_t st) {
   if (n == 0) return hipSuccess;
   if (eb < 1 || eb > 32) return hipErrorInvalidValue;
-  k_unpack_gather<<<(unsigned)((n + kSplicePaths - 1) / kSplicePaths), kBlock, 0, st>>>(
+  k_unpack_gather<<<(unsigned)((n + kGatherPaths - 1) / kGatherPaths), kBlock, 0, st>>>(
       tp_off, pk, eb, idx, n, keep_pos, keep_voff, keep_len, out_off, out_vtx);
   return hipGetLastError();
 }
