@@ -335,7 +335,7 @@ __device__ __forceinline__ int64_t tp_pk_base(int64_t off, int64_t x, int pe) {
 // leaves the tree path records its position; finally one thread per path
 // builds its key.  The plain entries are written only when asked for (tp_vtx
 // not null): the comparisons read the packed words and the kept paths are
-// spliced again when gathered.
+// unpacked from them when gathered.
 constexpr int kSplicePaths = 64;
 
 struct SpliceRow {
