@@ -1358,13 +1358,14 @@ tpg_status tpg_prime_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* 
 }
 
 // Components of the uploaded graph (union) into the workspace's scc buffers.
-tpg_status scc_device(tpg_workspace* ws, hipStream_t st) {
+tpg_status scc_device(tpg_workspace* ws, const HostUnion& U, hipStream_t st) {
   const int64_t n = std::max<int64_t>(ws->dg.n, 1);
   TPG_TRY(ws_reserve(ws, ws->scc_work, sizeof(int32_t) * 6 * n));
   TPG_TRY(ws_reserve(ws, ws->scc_comp, sizeof(int32_t) * n));
   TPG_TRY(ws_reserve(ws, ws->scc_flags, n));
   TPG_TRY(ws_reserve(ws, ws->scc_misc, 64 + sizeof(uint64_t) * kPpTypes));
-  TPG_HIP(launch_scc(ws->dg, ws->scc_work.as<int32_t>(), ws->scc_comp.as<int32_t>(),
+  TPG_HIP(launch_scc(ws->dg, (int32_t)U.s.size(), ws->scc_work.as<int32_t>(),
+                     ws->scc_comp.as<int32_t>(),
                      ws->scc_flags.as<uint8_t>(), ws->scc_misc.as<int32_t>(), st));
   return TPG_OK;
 }
@@ -1377,7 +1378,7 @@ tpg_status tpg_scc(const tpg_graph* g, const tpg_opts* opts, int32_t* comp, uint
   HostUnion U;
   add_component(U, g);
   TPG_TRY(upload_union(c.ws, U, c.st));
-  TPG_TRY(scc_device(c.ws, c.st));
+  TPG_TRY(scc_device(c.ws, U, c.st));
   if (comp)
     TPG_HIP(hipMemcpyAsync(comp, c.ws->scc_comp.p, sizeof(int32_t) * U.n, hipMemcpyDeviceToHost,
                            c.st));
@@ -1411,7 +1412,7 @@ tpg_status tpg_prime_path_types(const tpg_graph* g, const tpg_paths* pps, const 
   HostUnion U;
   add_component(U, g);
   TPG_TRY(upload_union(ws, U, c.st));
-  TPG_TRY(scc_device(ws, c.st));
+  TPG_TRY(scc_device(ws, U, c.st));
   const int64_t* d_off = pps->offsets;
   const int32_t* d_vtx = pps->vertices;
   if (!pps->on_device && np > 0) {

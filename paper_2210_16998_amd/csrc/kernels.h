@@ -112,8 +112,8 @@ constexpr uint8_t kPpComplete = 1, kPpSccInternal = 2, kPpSccExit = 3, kPpSccEnt
                   kPpOther = 5;
 constexpr int kPpTypes = 6;  // counts are indexed by type (index 0 unused)
 // comp[v] = smallest vertex of v's component, flags[v], n_comp[0] = number of
-// components; work: 6 n int32 of scratch
-hipError_t launch_scc(const DGraph& g, int32_t* work, int32_t* comp, uint8_t* flags,
+// components; m: arcs of the union; work: 6 n int32 of scratch
+hipError_t launch_scc(const DGraph& g, int32_t m, int32_t* work, int32_t* comp, uint8_t* flags,
                       int32_t* n_comp, hipStream_t st);
 // --- the paper's per-vertex schedule (comparison variant) ------------------
 hipError_t launch_pv_init(int n, int64_t* voff, int32_t* rows, hipStream_t st);

@@ -86,6 +86,75 @@ __global__ __launch_bounds__(kBlock) void k_scc_tarjan(DGraph g, int32_t* w, int
   }
 }
 
+// The same search for a single graph small enough for LDS: the workgroup
+// copies the successor CSR in, then one thread runs the search on LDS
+// arrays (each step's loads then take LDS latency instead of a trip to
+// memory).  Dynamic LDS: sp (n + 1), s (m), index, low, on, stack, call
+// stack (2 n) = 7 n + m + 1 int32.
+__global__ __launch_bounds__(kBlock) void k_scc_tarjan_lds(DGraph g, int32_t m, int32_t* comp) {
+  extern __shared__ int32_t s_mem[];
+  const int n = g.n;
+  int32_t* sp = s_mem;
+  int32_t* sc = sp + n + 1;
+  int32_t* index = sc + m;
+  int32_t* low = index + n;
+  int32_t* on = low + n;
+  int32_t* stk = on + n;
+  int32_t* cv = stk + n;
+  int32_t* ce = cv + n;
+  for (int i = threadIdx.x; i <= n; i += kBlock) sp[i] = g.sp[i];
+  for (int i = threadIdx.x; i < m; i += kBlock) sc[i] = g.s[i];
+  for (int i = threadIdx.x; i < n; i += kBlock) index[i] = -1;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  int next = 0, top = 0, csz = 0;
+  for (int root = 0; root < n; ++root) {
+    if (index[root] >= 0) continue;
+    index[root] = low[root] = next++;
+    stk[top++] = root;
+    on[root] = 1;
+    cv[csz] = root;
+    ce[csz] = sp[root];
+    ++csz;
+    while (csz > 0) {
+      const int v = cv[csz - 1];
+      const int e = ce[csz - 1];
+      if (e < sp[v + 1]) {
+        ce[csz - 1] = e + 1;
+        const int x = sc[e];
+        if (index[x] < 0) {
+          index[x] = low[x] = next++;
+          stk[top++] = x;
+          on[x] = 1;
+          cv[csz] = x;
+          ce[csz] = sp[x];
+          ++csz;
+        } else if (on[x] && index[x] < low[v]) {
+          low[v] = index[x];
+        }
+        continue;
+      }
+      --csz;
+      if (csz > 0) {
+        const int u = cv[csz - 1];
+        if (low[v] < low[u]) low[u] = low[v];
+      }
+      if (low[v] == index[v]) {
+        int pos = top, mn = INT_MAX, x;
+        do {
+          x = stk[--pos];
+          if (x < mn) mn = x;
+        } while (x != v);
+        for (int i = pos; i < top; ++i) {
+          comp[stk[i]] = mn;
+          on[stk[i]] = 0;
+        }
+        top = pos;
+      }
+    }
+  }
+}
+
 // Per vertex: cyclic (an arc to its own component: the component has two or
 // more vertices, each with an arc inside, or v has a self-loop), entry
 // vertex (an arc from another component), exit vertex (an arc to another
@@ -110,14 +179,22 @@ __global__ __launch_bounds__(kBlock) void k_scc_flags(DGraph g, const int32_t* c
   if (threadIdx.x == 0 && tot) atomicAdd(n_comp, tot);
 }
 
-hipError_t launch_scc(const DGraph& g, int32_t* work, int32_t* comp, uint8_t* flags,
+// Largest LDS the single-graph search takes (bytes).
+constexpr int64_t kSccLdsBytes = 48 * 1024;
+
+hipError_t launch_scc(const DGraph& g, int32_t m, int32_t* work, int32_t* comp, uint8_t* flags,
                       int32_t* n_comp, hipStream_t st) {
   if (g.n == 0) return hipSuccess;
-  hipError_t e = launch_fill_i32(work, -1, g.n, st);  // index = -1
+  hipError_t e = launch_fill_i32(n_comp, 0, 1, st);
   if (e != hipSuccess) return e;
-  e = launch_fill_i32(n_comp, 0, 1, st);
-  if (e != hipSuccess) return e;
-  k_scc_tarjan<<<(unsigned)((g.n_comp + kBlock - 1) / kBlock), kBlock, 0, st>>>(g, work, comp);
+  const int64_t lds = 4 * (7 * (int64_t)g.n + m + 1);
+  if (g.n_comp == 1 && lds <= kSccLdsBytes) {
+    k_scc_tarjan_lds<<<1, kBlock, (size_t)lds, st>>>(g, m, comp);
+  } else {
+    e = launch_fill_i32(work, -1, g.n, st);  // index = -1
+    if (e != hipSuccess) return e;
+    k_scc_tarjan<<<(unsigned)((g.n_comp + kBlock - 1) / kBlock), kBlock, 0, st>>>(g, work, comp);
+  }
   k_scc_flags<<<(unsigned)((g.n + kBlock - 1) / kBlock), kBlock, 0, st>>>(g, comp, flags, n_comp);
   return hipGetLastError();
 }
