@@ -585,8 +585,8 @@ __device__ __forceinline__ int64_t merge_split_wave(const TpOrder& K, const int3
 // indices and keys in LDS, and every thread then splits and merges its own
 // kMergeItems outputs from LDS (the entries themselves are read only when
 // two paths share their tree prefix and next entry).
-constexpr int kMergeThreads = 128;
-constexpr int kMergeItems = 8;
+constexpr int kMergeThreads = 256;
+constexpr int kMergeItems = 4;
 constexpr int kMergeTile = kMergeThreads * kMergeItems;
 
 __global__ __launch_bounds__(kMergeThreads) void k_merge_round(TpOrder K, const int32_t* in,
@@ -617,7 +617,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_round(TpOrder K, const 
     const int64_t na = a1 - a0, nb = b1 - a1;
     const int64_t stop = t1 < b1 ? t1 : b1;
     // input slices of this segment (two searches, one wave each)
-    {
+    if (tid < 128) {  // waves 0 and 1
       const int w = tid >> 6;
       const int64_t d = (w == 0 ? pos : stop) - a0;
       const int64_t r = merge_split_wave(K, A, na, B, nb, d);
