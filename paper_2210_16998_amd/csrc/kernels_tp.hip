@@ -585,8 +585,8 @@ __device__ __forceinline__ int64_t merge_split_wave(const TpOrder& K, const int3
 // indices and keys in LDS, and every thread then splits and merges its own
 // kMergeItems outputs from LDS (the entries themselves are read only when
 // two paths share their tree prefix and next entry).
-constexpr int kMergeThreads = 256;
-constexpr int kMergeItems = 4;
+constexpr int kMergeThreads = 512;
+constexpr int kMergeItems = 2;
 constexpr int kMergeTile = kMergeThreads * kMergeItems;
 
 __global__ __launch_bounds__(kMergeThreads) void k_merge_round(TpOrder K, const int32_t* in,
