@@ -13,7 +13,7 @@
  *  - A test path (TP) runs from the entry to the exit and contains a prime
  *    path; here TP(p) = (lexicographically smallest shortest entry->v1 path,
  *    without v1) ++ p ++ (lexicographically smallest shortest vk->exit path,
- *    without vk)  (Sec. 6.3: every prime path is extended to the initial and
+ *    without vk)  (Sec. 7.3: every prime path is extended to the initial and
  *    final nodes).  Duplicate TPs are removed.
  *  - Every returned path set is in canonical order: lexicographic on the
  *    int32 vertex ids.  Path sets are returned as CSR-like arrays:
@@ -230,7 +230,7 @@ int64_t tpg_workspace_bytes(const tpg_workspace* ws);
 tpg_status tpg_prime_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* out);
 
 /* ------------------------------------------------------------------------
- * Test paths covering every prime path (Problem 1 output; Sec. 6.3).
+ * Test paths covering every prime path (Problem 1 output; Sec. 7.3).
  * If pp_out is non-NULL it also receives the prime paths.  tp_out receives
  * the deduplicated test paths in canonical order.  Requires the entry/exit
  * checks of tpg_load_cfg_csr to hold (else TPG_ERR_UNREACHABLE).
@@ -243,7 +243,7 @@ tpg_status tpg_test_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* p
 void tpg_paths_free(tpg_paths* p);
 
 /* ------------------------------------------------------------------------
- * The paper's own schedule, as a comparison variant (Sec. 4: the
+ * The paper's own schedule, as a comparison variant (Sec. 5: the
  * Update-Vertex kernel and ExtendPath).  Every vertex owns a list of whole
  * paths ending at it; in each round one thread per vertex appends to its
  * list every path of a predecessor's newest paths that it can extend (not a
@@ -276,11 +276,11 @@ tpg_status tpg_prime_paths_vertex_lists(const tpg_graph* g, const tpg_opts* opts
 #define TPG_SCC_ENTRY_VERTEX 0x2u
 #define TPG_SCC_EXIT_VERTEX 0x4u
 /* Prime-path types (tpg_prime_path_types), the first that matches in this
- * order: Def. 2 CompletePP (from the entry to the exit); Def. 8
+ * order: Def. 2 CompletePP (from the entry to the exit); Def. 9
  * SccInternalPP (starts and ends in one component with a cycle, and if
  * acyclic neither starts at one of its entry vertices nor ends at one of
- * its exit vertices); Def. 9 SccExitPP (starts in a component with a cycle,
- * ends at the exit); Def. 10 SccEntryPP (starts at the entry, ends in a
+ * its exit vertices); Def. 10 SccExitPP (starts in a component with a cycle,
+ * ends at the exit); Def. 11 SccEntryPP (starts at the entry, ends in a
  * component with a cycle); TPG_PP_OTHER for none of them (for instance a
  * path from one component with a cycle to another). */
 #define TPG_PP_COMPLETE 1
@@ -327,7 +327,11 @@ tpg_status tpg_prime_path_types(const tpg_graph* g, const tpg_paths* pps, const 
  * count (index 64).  With it the path pool is sized in one pass from the
  * prediction (25% margin) and, under a pool cap, graphs are admitted into
  * unions by predicted footprint; a level that outgrows its allocation is
- * detected on the device, grown to its exact size and replayed.  Without
+ * detected on the device, grown to its exact size and replayed.  A value
+ * that is not a finite number counts as 0; predicted capacities are capped
+ * at the 2^31-path limit, at half the pool cap and at half the free device
+ * memory, and a union whose predicted capacities cannot be allocated is
+ * sized from the smallest buffers by growth and replay instead.  Without
  * it, sizing starts from the workspace's current capacity (or the exact
  * two-pass form with TPG_FORCE_TWO_PASS).  Results never depend on the
  * prediction.

@@ -291,8 +291,8 @@ def test_paths_greedy(g, pps: PathList) -> PathList:
 
 
 # --- strongly connected components and the paper's path types -------------
-# Types of a prime path (Sec. 2): Def. 2 CompletePP, Def. 8 SccInternalPP,
-# Def. 9 SccExitPP, Def. 10 SccEntryPP; OTHER for none of them.
+# Types of a prime path (Sec. 2): Def. 2 CompletePP, Def. 9 SccInternalPP,
+# Def. 10 SccExitPP, Def. 11 SccEntryPP; OTHER for none of them.
 PP_COMPLETE, PP_SCC_INTERNAL, PP_SCC_EXIT, PP_SCC_ENTRY, PP_OTHER = 1, 2, 3, 4, 5
 # Per-vertex flags: in a component with a cycle (two or more vertices, or a
 # self-loop); SccEntryVertex (Def. 4: a predecessor outside its component);
@@ -371,8 +371,8 @@ def ccfg(g, comp: np.ndarray):
 
 
 def pp_types(g, pl: PathList) -> Tuple[np.ndarray, np.ndarray]:
-    """Type of each prime path by Defs. 2, 8, 9 and 10 (first match), and the
-    count of each type (index = type).  Def. 8 is read literally: start and
+    """Type of each prime path by Defs. 2, 9, 10 and 11 (first match), and the
+    count of each type (index = type).  Def. 9 is read literally: start and
     end in one component with a cycle; an acyclic one must not start at an
     SccEntryVertex nor end at an SccExitVertex."""
     comp = scc(g)

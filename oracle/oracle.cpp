@@ -10,9 +10,9 @@
 //  * A simple path is a vertex sequence v1..vk (k > 0) along arcs in which no
 //    vertex repeats, except that v1 = vk is allowed (Sec. 2, Preliminaries).
 //  * A prime path is a simple path that is not a proper subpath of any other
-//    simple path (Def. 1; Sec. 1 and Sec. 6.1 restate it as "maximal").
+//    simple path (Def. 1; Sec. 1 and Sec. 7.1 restate it as "maximal").
 //  * The enumeration follows the edge-based method the paper attributes to
-//    Ammann and Offutt (Sec. 6.2): start from every single vertex, extend by
+//    Ammann and Offutt (Sec. 7.2): start from every single vertex, extend by
 //    one arc while the path stays simple, stop a path when it cannot be
 //    extended (or when it has closed a cycle), then prune every candidate
 //    that is covered by another one.  Enumeration here is a depth-first
@@ -23,7 +23,7 @@
 //    follows it would extend it), and a closed cycle is never covered.  So the
 //    prune pass sorts the reversed acyclic candidates and drops each one that
 //    is a proper prefix of its successor in that order.
-//  * Test paths (Problem 1 output; Sec. 6.3 describes extending every prime
+//  * Test paths (Problem 1 output; Sec. 7.3 describes extending every prime
 //    path to the initial and final nodes): prefix = the lexicographically
 //    smallest shortest path from the entry to the first vertex, suffix = the
 //    lexicographically smallest shortest path from the last vertex to the

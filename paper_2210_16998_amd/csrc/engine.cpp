@@ -11,6 +11,7 @@
 
 #include "internal.h"
 #include "kernels.h"
+#include "sizing.h"
 
 using namespace tpg;
 
@@ -169,6 +170,16 @@ void ws_release(tpg_workspace* ws, DevBuf& b) {
   }
   b.p = nullptr;
   b.cap = 0;
+}
+
+// Predicted number of paths with L + 1 entries of graph i (index 63: all
+// deeper levels), from the predictor's log1p output; a value that is not a
+// finite number counts as no prediction, and the log is capped so the
+// count stays finite.
+double predicted_paths(const float* predicted, int32_t i, int L) {
+  const double x = (double)predicted[(size_t)i * 65 + L];
+  if (!std::isfinite(x) || x <= 0.0) return 0.0;
+  return std::expm1(std::min(x, 40.0));
 }
 
 void add_component(HostUnion& U, const tpg_graph* g) {
@@ -439,6 +450,91 @@ tpg_status launch_levels_graph(tpg_workspace* ws, const ExtArgs& a, int W, int i
   return TPG_OK;
 }
 
+// Frees the path tree and the visited-set buffers (capacities back to zero).
+void release_tree(tpg_workspace* ws) {
+  for (DevBuf* b : {&ws->par, &ws->info, &ws->cstart, &ws->nch, &ws->mask0, &ws->mask1})
+    ws_release(ws, *b);
+  ws->rec_cap = 0;
+  ws->mask_cap = 0;
+  ws->mask_words = 0;
+  drop_level_graphs(ws);
+  ws->levels_uids.clear();
+  ws->levels_last = 0;
+}
+
+// The device side of the one-pass level loop (see sizing.h): buffers of the
+// workspace, extension launches (replayed from captured graphs, or issued
+// one by one with an event pair each when the call is timed), and the level
+// sizes read back after each batch.
+struct OnePassDev {
+  tpg_workspace* ws;
+  const HostUnion& U;
+  hipStream_t st;
+  Timer& tm;
+  TreeResult& R;
+  int W, items, variant, grid;
+  ExtArgs a{};
+  tpg_status err = TPG_OK;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
+
+  int64_t rec_cap() const { return ws->rec_cap; }
+  int64_t mask_cap() const { return ws->mask_cap; }
+  bool ok(tpg_status s) {
+    err = s;
+    return s == TPG_OK;
+  }
+  bool hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return true;
+    err = fail(e == hipErrorOutOfMemory ? TPG_ERR_OOM_DEVICE : TPG_ERR_DEVICE, "%s: %s", what,
+               hipGetErrorString(e));
+    return false;
+  }
+  bool reserve(const TreeCaps& c, int64_t keep_rec, int keep_level, int64_t keep_mask) {
+    if (!ok(reserve_tree(ws, c.rec, c.msk, U.Wu, st, keep_rec,
+                         keep_level > 0 ? mask_buf_host(keep_level) : -1, keep_mask)))
+      return false;
+    a = make_args(ws, grid);
+    return true;
+  }
+  bool run(int L0, int len, BatchReport& r) {
+    LevelState* dls = ws->ls.as<LevelState>();
+    ws->h_scalars[8] = L0;
+    if (!hip(hipMemcpyAsync(&dls->batch_start, &ws->h_scalars[8], sizeof(int32_t),
+                            hipMemcpyHostToDevice, st), "batch start"))
+      return false;
+    evs.clear();
+    if (tm.on) {
+      for (int b = 0; b < len; ++b) {
+        hipEvent_t e0 = tm.event(), e1 = tm.event();
+        if (!hip(launch_extend(W, items, variant, a, grid, b, st, e0, e1), "extension launch"))
+          return false;
+        evs.emplace_back(e0, e1);
+      }
+    } else if (!ok(launch_levels_graph(ws, a, W, items, variant, grid, len, st))) {
+      return false;
+    }
+    // header + sizes of levels L0 .. L0 + len
+    if (!hip(hipMemcpyAsync(ws->h_ls, dls, 32, hipMemcpyDeviceToHost, st), "level header") ||
+        !hip(hipMemcpyAsync(ws->h_ls->count + L0, dls->count + L0, sizeof(int64_t) * (len + 1),
+                            hipMemcpyDeviceToHost, st), "level sizes") ||
+        !hip(hipStreamSynchronize(st), "level loop"))
+      return false;
+    const LevelState& h = *ws->h_ls;
+    r.overflow = h.overflow != 0;
+    r.overflow_level = h.overflow_level;
+    r.count = h.count;
+    // kernel time of the launches that extended a level for good
+    const int last_ok = r.overflow ? r.overflow_level - 1 : L0 + len - 1;
+    for (int b = 0; b < (int)evs.size() && L0 + b <= last_ok && h.count[L0 + b] > 0; ++b) {
+      R.ms_kernel += Timer::ms(evs[b].first, evs[b].second);
+      R.launches += 1;
+    }
+    tm.next = 0;
+    return true;
+  }
+  bool resume(int Lo) { return hip(launch_resume_fix(a, Lo, st), "replay"); }
+};
+
 // Level loop, one-pass device-sized form.  rec0 / msk0: initial capacities
 // (nodes overall / nodes of one level); 0 = what the workspace already has.
 // Levels run in batches of launches (4, 8, ... 64); the host learns the
@@ -446,91 +542,39 @@ tpg_status launch_levels_graph(tpg_workspace* ws, const ExtArgs& a, int W, int i
 tpg_status build_tree_onepass(tpg_workspace* ws, const HostUnion& U, hipStream_t st, Timer& tm,
                               TreeResult& R, int64_t rec0, int64_t msk0) {
   const int W = U.W;
-  int64_t rec = std::max<int64_t>({ws->rec_cap, (int64_t)U.n * 64 + 4096, rec0});
-  int64_t msk = std::max<int64_t>((int64_t)U.n * 16 + 1024, msk0);
-  if (ws->mask_words && ws->mask_cap)
-    msk = std::max<int64_t>(msk, ws->mask_cap * ws->mask_words / U.Wu);
-  TPG_TRY(reserve_tree(ws, rec, msk, U.Wu, st, 0, -1, 0));
+  const int64_t held_msk =
+      (ws->mask_words && ws->mask_cap) ? ws->mask_cap * ws->mask_words / U.Wu : 0;
+  const TreeCaps first = onepass_first_caps(ws->rec_cap, held_msk, U.n, rec0, msk0);
+  TPG_TRY(reserve_tree(ws, first.rec, first.msk, U.Wu, st, 0, -1, 0));
   int wi = 0;
   while ((1 << wi) < W) ++wi;
-  const int items = ws->tune_items[wi];
-  const int variant = ws->tune_variant[wi];
   const int grid = ws->num_cus * ws->tune_wgs[wi];
-  ExtArgs a = make_args(ws, grid);
-  TPG_HIP(launch_seed(a, st));
-  LevelState* dls = ws->ls.as<LevelState>();
+  OnePassDev d{ws, U, st, tm, R, W, ws->tune_items[wi], ws->tune_variant[wi], grid};
+  d.a = make_args(ws, grid);
+  TPG_HIP(launch_seed(d.a, st));
   std::vector<int64_t> cnt(kMaxLevels + 1, 0);
-  cnt[1] = a.seed_n;
-  int L0 = 1;
+  cnt[1] = d.a.seed_n;
   // a union seen before: one batch covers its levels and the empty one after
-  int batch = (ws->levels_uids == U.uids && ws->levels_last > 0) ? ws->levels_last + 1 : 4;
+  const int first_batch =
+      (ws->levels_uids == U.uids && ws->levels_last > 0) ? ws->levels_last + 1 : 4;
   int Lmax = 0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
-  for (;;) {
-    const int len = std::min(batch, kMaxLevels - 2 - L0);
-    if (len <= 0) return fail(TPG_ERR_UNSUPPORTED, "more levels than vertices + 1");
-    ws->h_scalars[8] = L0;
-    TPG_HIP(hipMemcpyAsync(&dls->batch_start, &ws->h_scalars[8], sizeof(int32_t),
-                           hipMemcpyHostToDevice, st));
-    // timed calls launch directly with an event pair around each extension
-    // launch; untimed calls replay the captured level loop
-    evs.clear();
-    if (tm.on) {
-      for (int b = 0; b < len; ++b) {
-        hipEvent_t e0 = tm.event(), e1 = tm.event();
-        TPG_HIP(launch_extend(W, items, variant, a, grid, b, st, e0, e1));
-        evs.emplace_back(e0, e1);
-      }
-    } else {
-      TPG_TRY(launch_levels_graph(ws, a, W, items, variant, grid, len, st));
-    }
-    // header + sizes of levels L0 .. L0 + len
-    TPG_HIP(hipMemcpyAsync(ws->h_ls, dls, 32, hipMemcpyDeviceToHost, st));
-    TPG_HIP(hipMemcpyAsync(ws->h_ls->count + L0, dls->count + L0, sizeof(int64_t) * (len + 1),
-                           hipMemcpyDeviceToHost, st));
-    TPG_HIP(hipStreamSynchronize(st));
-    const LevelState& h = *ws->h_ls;
-    const int Lo = h.overflow ? h.overflow_level : -1;
-    // levels extended for good in this batch: L0 .. last
-    const int last_ok = h.overflow ? Lo - 1 : L0 + len - 1;
-    for (int L = L0; L <= std::min(last_ok + 1, L0 + len); ++L) cnt[L] = h.count[L];
-    if (h.overflow) cnt[Lo + 1] = h.count[Lo + 1];
-    for (int b = 0; b < (int)evs.size() && L0 + b <= last_ok && cnt[L0 + b] > 0; ++b) {
-      R.ms_kernel += Timer::ms(evs[b].first, evs[b].second);
-      R.launches += 1;
-    }
-    tm.next = 0;
-    if (h.overflow) {
-      // the exact size of level Lo + 1 is known: grow to it and replay Lo
-      int64_t base = 0;
-      for (int L = 1; L < Lo; ++L) base += cnt[L];
-      const int64_t F = cnt[Lo], nxt = cnt[Lo + 1];
-      const int64_t need_rec = base + F + nxt + 1;
-      const int64_t new_rec = std::max<int64_t>(ws->rec_cap, need_rec + need_rec / 4);
-      // visited sets: only an odd level Lo + 1 stores them; the replay of
-      // Lo reads the stored level Ls (Lo itself when odd, else Lo - 1)
-      const int64_t new_msk = (Lo + 1) & 1 ? std::max<int64_t>(ws->mask_cap, nxt + nxt / 4 + 1024)
-                                           : ws->mask_cap;
-      const int Ls = (Lo & 1) ? Lo : Lo - 1;
-      TPG_TRY(reserve_tree(ws, new_rec, new_msk, U.Wu, st, base + F, mask_buf_host(Ls), cnt[Ls]));
-      a = make_args(ws, grid);
-      TPG_HIP(launch_resume_fix(a, Lo, st));
-      R.n_overflows += 1;
-      L0 = Lo;
-      continue;
-    }
-    int empty = -1;
-    for (int L = L0; L <= L0 + len; ++L)
-      if (cnt[L] == 0) {
-        empty = L;
-        break;
-      }
-    if (empty > 0) {
-      Lmax = empty - 1;
+  LoopFailure why;
+  switch (onepass_levels(d, first_batch, kMaxLevels, cnt, Lmax, R.n_overflows, why)) {
+    case LoopEnd::ok:
       break;
-    }
-    L0 += len;
-    batch = std::max(4, std::min(batch * 2, 64));
+    case LoopEnd::device_failed:
+      return d.err != TPG_OK ? d.err : fail(TPG_ERR_DEVICE, "level loop failed");
+    case LoopEnd::too_deep:
+      return fail(TPG_ERR_UNSUPPORTED, "more levels than vertices + 1");
+    case LoopEnd::bad_report:
+      return fail(TPG_ERR_DEVICE, "the device reported an overflow at level %d, outside the batch",
+                  why.level);
+    case LoopEnd::repeated_overflow:
+      return fail(TPG_ERR_DEVICE,
+                  "level %d overflowed again after growing to its exact size (base %lld, "
+                  "%lld paths, %lld children; capacities %lld nodes, %lld sets)",
+                  why.level, (long long)why.base, (long long)why.F, (long long)why.nxt,
+                  (long long)why.rec_cap, (long long)why.mask_cap);
   }
   ws->levels_uids = U.uids;
   ws->levels_last = Lmax;
@@ -1662,7 +1706,7 @@ tpg_status tpg_batch_test_paths(const tpg_graph* const* graphs, int32_t n_graphs
       for (int32_t i : cls[k]) {
         double gm = 0;
         if (predicted && ws->cap) {
-          for (int L = 0; L < 64; ++L) gm += std::expm1((double)predicted[(size_t)i * 65 + L]);
+          for (int L = 0; L < 64; ++L) gm += predicted_paths(predicted, i, L);
           gm *= 24.0 + 2.0 * 8.0 * (1 << k);
         }
         if (!cur.empty() && (nv + graphs[i]->n > kMaxUnionVertices ||
@@ -1693,29 +1737,55 @@ tpg_status tpg_batch_test_paths(const tpg_graph* const* graphs, int32_t n_graphs
     }
     int64_t rec0 = 0, msk0 = 0;
     if (predicted) {
-      // capacities from the predicted per-level path counts, 25% margin
+      // capacities from the predicted per-level path counts, 25% margin;
+      // index 63 pools every deeper level, so it sizes the total but not the
+      // largest single level
       std::vector<double> lv(64, 0.0);
       for (int32_t i : unions[u])
-        for (int L = 0; L < 64; ++L)
-          lv[L] += std::max(0.0, std::expm1((double)predicted[(size_t)i * 65 + L]));
+        for (int L = 0; L < 64; ++L) lv[L] += predicted_paths(predicted, i, L);
       double tot = 0, peak = 0;
-      for (double x : lv) {
-        tot += x;
-        peak = std::max(peak, x);
+      for (int L = 0; L < 64; ++L) {
+        tot += lv[L];
+        if (L < 63) peak = std::max(peak, lv[L]);
       }
-      rec0 = (int64_t)(1.25 * tot) + U.n + 1024;
-      msk0 = (int64_t)(1.25 * peak) + 1024;
+      // never more than the record limit, the pool cap or half the free
+      // device memory: an over-prediction costs capacity, not the call
+      double rec_lim = (double)INT32_MAX - 2, msk_lim = (double)INT32_MAX - 2;
+      const double node_b = 13.0, set_b = 2.0 * 8.0 * U.Wu;
+      size_t free_b = 0, total_b = 0;
+      if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0) {
+        rec_lim = std::min(rec_lim, 0.5 * (double)free_b / node_b);
+        msk_lim = std::min(msk_lim, 0.25 * (double)free_b / set_b);
+      } else {
+        (void)hipGetLastError();
+      }
+      if (ws->cap) {
+        rec_lim = std::min(rec_lim, 0.5 * (double)ws->cap / node_b);
+        msk_lim = std::min(msk_lim, 0.25 * (double)ws->cap / set_b);
+      }
+      rec0 = (int64_t)std::min(1.25 * tot + U.n + 1024, rec_lim);
+      msk0 = (int64_t)std::min(1.25 * peak + 1024, msk_lim);
       if (c.stats) {
-        c.stats->pred_nodes += (int64_t)tot;
+        c.stats->pred_nodes += (int64_t)std::min(tot, 9.0e18);
         c.stats->pred_peak_level_nodes =
-            std::max<int64_t>(c.stats->pred_peak_level_nodes, (int64_t)peak);
+            std::max<int64_t>(c.stats->pred_peak_level_nodes, (int64_t)std::min(peak, 9.0e18));
       }
     }
     OutSet& o = ws->out[u + 1];
     TreeResult R;
     PPResult P;
     TPResult T;
-    TPG_TRY(run_pp(U, c, tm, R, P, o, nullptr, rec0, msk0, true));
+    tpg_status s_pp = run_pp(U, c, tm, R, P, o, nullptr, rec0, msk0, true);
+    if (s_pp != TPG_OK && (rec0 || msk0) &&
+        (s_pp == TPG_ERR_CAPACITY || s_pp == TPG_ERR_OOM_DEVICE || s_pp == TPG_ERR_UNSUPPORTED)) {
+      // the predicted capacities did not fit: size this union exactly, by
+      // growth and replay from the smallest buffers
+      release_tree(ws);
+      R = TreeResult{};
+      P = PPResult{};
+      s_pp = run_pp(U, c, tm, R, P, o, nullptr, 0, 0, true);
+    }
+    TPG_TRY(s_pp);
     TPG_TRY(test_paths_device(ws, U, c.st, P, T, o));
     const int nc = U.n_comp;
     if (want_levels) {

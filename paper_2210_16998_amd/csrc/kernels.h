@@ -105,7 +105,7 @@ hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 
 // --- strongly connected components and prime-path types (Sec. 2) ----------
-// per-vertex flags (Defs. 4-5) and path types (Defs. 2, 8, 9, 10); the values
+// per-vertex flags (Defs. 4-5) and path types (Defs. 2, 9, 10, 11); the values
 // are the ones the C API exports
 constexpr uint8_t kSccCyclic = 1, kSccEntryVertex = 2, kSccExitVertex = 4;
 constexpr uint8_t kPpComplete = 1, kPpSccInternal = 2, kPpSccExit = 3, kPpSccEntry = 4,

@@ -43,6 +43,7 @@
 #include <hip/hip_ext.h>
 
 #include "kernels.h"
+#include "sizing.h"
 
 namespace tpg {
 
@@ -215,7 +216,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 1024 &
   const int64_t base = ls->off[L - 1] + ls->count[L - 1];
   const int tid = (int)threadIdx.x;
   const int lane = lane_id(), wave = tid >> 6;
-  if (base + F + 1 > a.t.rec_cap || ((L & 1) && F > a.t.mask_cap) || base + F >= (int64_t)INT32_MAX) {
+  if (!level_fits(L, base, F, a.t.rec_cap, a.t.mask_cap)) {
     // the previous launch's children did not fit: replay that level
     if (blockIdx.x == 0 && tid == 0) {
       ls->overflow_level = L - 1;
@@ -365,7 +366,7 @@ __global__ __launch_bounds__(kBlock) void k_extend_lb(ExtArgs a, int li) {
   if (F == 0) return;
   const int64_t base = ls->off[L - 1] + ls->count[L - 1];
   const int tid = (int)threadIdx.x;
-  if (base + F + 1 > a.t.rec_cap || ((L & 1) && F > a.t.mask_cap) || base + F >= (int64_t)INT32_MAX) {
+  if (!level_fits(L, base, F, a.t.rec_cap, a.t.mask_cap)) {
     if (blockIdx.x == 0 && tid == 0) {
       ls->overflow_level = L - 1;
       ls->overflow = 1;

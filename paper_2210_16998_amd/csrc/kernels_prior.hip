@@ -1,4 +1,4 @@
-// The paper's own schedule, kept as a comparison variant (Sec. 4, the
+// The paper's own schedule, kept as a comparison variant (Sec. 5, the
 // Update-Vertex kernel and its ExtendPath step): every vertex owns a list of
 // whole paths that end at it, one thread per vertex extends the paths its
 // predecessors added last, and no atomic is used (a row's "extended" mark is

@@ -1,7 +1,7 @@
 // Strongly connected components and the prime-path types of Sec. 2 on the
 // device: the component graph's vertices (Def. 3), SccEntryVertex and
 // SccExitVertex (Defs. 4-5), and the types CompletePP, SccInternalPP,
-// SccExitPP, SccEntryPP (Defs. 2, 8, 9, 10) of a prime-path set.
+// SccExitPP, SccEntryPP (Defs. 2, 9, 10, 11) of a prime-path set.
 #include <climits>
 
 #include "device.h"
@@ -200,7 +200,7 @@ hipError_t launch_scc(const DGraph& g, int32_t m, int32_t* work, int32_t* comp, 
 }
 
 // One thread per prime path: its type from its end vertices (a simple path
-// whose ends lie in one component stays inside it), Defs. 2, 8, 9, 10 in
+// whose ends lie in one component stays inside it), Defs. 2, 9, 10, 11 in
 // that order of precedence; counts[t] += paths of type t.
 __global__ __launch_bounds__(kBlock) void k_pp_types(DGraph g, const int32_t* comp,
                                                      const uint8_t* flags, const int64_t* off,

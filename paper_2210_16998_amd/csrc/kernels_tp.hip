@@ -1,7 +1,7 @@
 // Test-path kernels: BFS tables, splice, canonical sort and deduplication.
 //
 // A test path extends a prime path to the initial and final nodes (paper
-// Sec. 6.3, the Ammann-Offutt construction; Problem 1 asks for test paths
+// Sec. 7.3, the Ammann-Offutt construction; Problem 1 asks for test paths
 // covering every prime path).  The shortest connection is taken, and among
 // shortest ones the lexicographically smallest, so the result is unique:
 //  * prefix(v): smallest shortest entry -> v path.  A FIFO breadth-first

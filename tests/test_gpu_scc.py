@@ -1,5 +1,5 @@
 """GPU parity of the strongly connected components (Sec. 2, Defs. 3-5) and
-of the prime-path types (Defs. 2, 8, 9, 10): labels, flags and types are
+of the prime-path types (Defs. 2, 9, 10, 11): labels, flags and types are
 integers, compared exactly with the oracle."""
 import numpy as np
 import pytest
@@ -105,7 +105,7 @@ def test_malformed_host_sets_are_rejected():
 
 def _scc_subgraph_internal(g, h, comp, fl):
     """Internal prime paths from the extension run on each component with a
-    cycle taken alone (Sec. 2.1), filtered by Def. 8: the per-SCC route."""
+    cycle taken alone (Sec. 2.1), filtered by Def. 9: the per-SCC route."""
     out = []
     for c in sorted(set(comp.tolist())):
         vs = [int(v) for v in np.nonzero(comp == c)[0]]
