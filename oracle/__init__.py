@@ -73,6 +73,9 @@ def _load():
         _lib.orc_fnv1a64.argtypes = [ctypes.c_char_p, ctypes.c_int64]
         _lib.orc_fnv1a64.restype = ctypes.c_uint64
         _lib.orc_digest.argtypes = [ctypes.c_int64, i64p, i32p, P(ctypes.c_uint64)]
+        _lib.orc_set_digests.argtypes = [ctypes.c_int, i64p, i32p, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_int, i64p,
+                                         P(ctypes.c_uint64), i64p, i64p, P(ctypes.c_uint64)]
     return _lib
 
 
@@ -272,6 +275,28 @@ def digest(pl: PathList) -> Tuple[int, int]:
     _load().orc_digest(len(off) - 1, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                        vtx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), out)
     return int(out[0]), int(out[1])
+
+
+def set_digests(g, n_buckets: int = 4, nthreads: Optional[int] = None) -> Dict[str, object]:
+    """Whole-set figures without holding the sets: per-first-vertex prime
+    path counts, the prime paths' set digest, and the test paths' count
+    (after exact deduplication in hash buckets) and set digest.  For graphs
+    whose test paths do not fit in memory at once."""
+    lib = _load()
+    rp, ci, prp, pci = _csr(g)
+    per = np.zeros(g.n, np.int64)
+    ppd = (ctypes.c_uint64 * 2)()
+    tpd = (ctypes.c_uint64 * 2)()
+    ntp = np.zeros(1, np.int64)
+    nsp = np.zeros(1, np.int64)
+    i64 = ctypes.POINTER(ctypes.c_int64)
+    rc = lib.orc_set_digests(g.n, prp, pci, g.entry, g.exit, _threads(nthreads), int(n_buckets),
+                             per.ctypes.data_as(i64), ppd, ntp.ctypes.data_as(i64),
+                             nsp.ctypes.data_as(i64), tpd)
+    if rc != 0:
+        raise ValueError("a prime path is not reachable from entry or cannot reach exit")
+    return {"pp_per_start": per, "n_pp": int(per.sum()), "pp_digest": (int(ppd[0]), int(ppd[1])),
+            "n_tp": int(ntp[0]), "n_spliced": int(nsp[0]), "tp_digest": (int(tpd[0]), int(tpd[1]))}
 
 
 def test_paths_greedy(g, pps: PathList) -> PathList:

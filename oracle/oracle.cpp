@@ -633,4 +633,101 @@ void orc_digest(int64_t n_paths, const int64_t* offsets, const int32_t* vertices
   out[1] = x;
 }
 
+
+// Whole-set figures of a graph too large to hold its test paths at once:
+// the prime paths (local rule) of every first vertex, their per-start counts
+// and set digest, and the test paths' count and set digest after exact
+// deduplication.  Duplicates are removed bucket by bucket: a test path goes
+// to bucket (its FNV-1a 64 hash mod n_buckets), so equal test paths always
+// meet in one bucket, and each bucket's paths are sorted and made unique by
+// plain sequence comparison.  Every bucket enumerates the prime paths again,
+// first vertices a chunk at a time, so memory is bounded by one bucket's
+// test paths plus one chunk's candidates.
+// pp_per_start: n entries; pp_digest, tp_digest: 2 entries (sum, xor).
+int orc_set_digests(int n, const int64_t* row_ptr, const int32_t* col_idx, int entry, int exit,
+                    int nthreads, int n_buckets, int64_t* pp_per_start, uint64_t* pp_digest,
+                    int64_t* n_tp, int64_t* n_spliced, uint64_t* tp_digest) {
+  Digraph g = make_graph(n, row_ptr, col_idx);
+  std::vector<int32_t> df(n), par(n), db(n), nx(n);
+  orc_bfs(n, row_ptr, col_idx, entry, exit, df.data(), par.data(), db.data(), nx.data());
+  if (n_buckets < 1) n_buckets = 1;
+  auto path_hash = [](const int32_t* p, int64_t k) {
+    std::vector<uint8_t> buf;
+    auto put = [&](uint32_t w) {
+      for (int b = 0; b < 4; ++b) buf.push_back((uint8_t)(w >> (8 * b)));
+    };
+    put((uint32_t)k);
+    for (int64_t j = 0; j < k; ++j) put((uint32_t)p[j]);
+    return orc_fnv1a64(buf.data(), (int64_t)buf.size());
+  };
+  const int chunk = 16;
+  uint64_t ps = 0, px = 0, ts = 0, tx = 0;
+  int64_t kept = 0, spliced = 0;
+  for (int v = 0; v < n; ++v) pp_per_start[v] = 0;
+  for (int b = 0; b < n_buckets; ++b) {
+    std::vector<Path> bucket;
+    for (int s0 = 0; s0 < n; s0 += chunk) {
+      const int cnt = std::min(chunk, n - s0);
+      std::vector<StartResult> res(cnt);
+      std::vector<std::vector<Path>> tps(cnt);
+      std::vector<uint64_t> hs(cnt, 0), hx(cnt, 0);
+      std::vector<int64_t> np(cnt, 0);
+      std::atomic<int> bad{0};
+      parallel_over_starts(cnt, nthreads, [&](int i) {
+        StartResult& r = res[i];
+        dfs_from(g, s0 + i, true, r, nullptr);
+        for (size_t k = 0; k + 1 < r.offs.size(); ++k) {
+          if (!r.local_pp[k]) continue;
+          const int32_t* p = r.verts.data() + r.offs[k];
+          const int64_t len = r.offs[k + 1] - r.offs[k];
+          np[i] += 1;
+          if (b == 0) {
+            const uint64_t h = path_hash(p, len);
+            hs[i] += h;
+            hx[i] ^= h;
+          }
+          const int v1 = p[0], vk = p[len - 1];
+          if (df[v1] < 0 || db[vk] < 0) {
+            bad = 1;
+            return;
+          }
+          Path t;
+          for (int v = v1; v != entry; v = par[v]) t.push_back(par[v]);
+          std::reverse(t.begin(), t.end());
+          t.insert(t.end(), p, p + len);
+          for (int v = vk; v != exit; v = nx[v]) t.push_back(nx[v]);
+          if (path_hash(t.data(), (int64_t)t.size()) % (uint64_t)n_buckets == (uint64_t)b)
+            tps[i].push_back(std::move(t));
+        }
+        r = StartResult();  // free the candidates of this start
+      });
+      if (bad) return -1;
+      for (int i = 0; i < cnt; ++i) {
+        if (b == 0) {
+          pp_per_start[s0 + i] = np[i];
+          ps += hs[i];
+          px ^= hx[i];
+          spliced += np[i];
+        }
+        for (auto& t : tps[i]) bucket.push_back(std::move(t));
+      }
+    }
+    std::sort(bucket.begin(), bucket.end());
+    bucket.erase(std::unique(bucket.begin(), bucket.end()), bucket.end());
+    kept += (int64_t)bucket.size();
+    for (const Path& t : bucket) {
+      const uint64_t h = path_hash(t.data(), (int64_t)t.size());
+      ts += h;
+      tx ^= h;
+    }
+  }
+  pp_digest[0] = ps;
+  pp_digest[1] = px;
+  tp_digest[0] = ts;
+  tp_digest[1] = tx;
+  *n_tp = kept;
+  *n_spliced = spliced;
+  return 0;
+}
+
 }  // extern "C"

@@ -298,6 +298,43 @@ def test_digest_is_a_multiset_digest_of_path_bytes():
     assert oracle.digest(pl([])) == (0, 0)
 
 
+def test_set_digests_match_the_materialized_sets():
+    """The bounded-memory whole-set run (bucketed exact dedup) against the
+    prime-path and test-path sets built in full: counts per first vertex,
+    digests, test-path count before and after deduplication, for any number
+    of buckets; and Fig. 1's 19 prime paths and 10 test paths."""
+    graphs = [cfggen.fig1_cfg(), cfggen.c1_cfg(0), cfggen.c1_cfg(5), cfggen.loop_diamond_chain(6)]
+    graphs += [cfggen.random_small_cfg(4400 + s, 8 + 3 * s, extra=1 + s % 4) for s in range(12)]
+    for g in graphs:
+        pp, _, _, _ = oracle.prime_paths(g)
+        tp, n_spliced = oracle.test_paths(g, pp)
+        firsts = np.array([p[0] for p in pp.tolist()], np.int64)
+        per = np.bincount(firsts, minlength=g.n)
+        for b in (1, 3, 8):
+            d = oracle.set_digests(g, n_buckets=b, nthreads=3)
+            assert np.array_equal(d["pp_per_start"], per), (g.name, b)
+            assert d["n_pp"] == len(pp) and d["pp_digest"] == oracle.digest(pp), (g.name, b)
+            assert d["n_spliced"] == n_spliced and d["n_tp"] == len(tp), (g.name, b)
+            assert d["tp_digest"] == oracle.digest(tp), (g.name, b)
+    d = oracle.set_digests(cfggen.fig1_cfg())
+    assert d["n_pp"] == 19 and d["n_tp"] == 10
+
+
+def test_stress_set_figures_recorded():
+    """The stored whole-set figures of the stress CFG agree with the oracle's
+    counting run (total and per first vertex)."""
+    import json
+    import os
+    from tests.goldens import GOLDEN
+    with open(os.path.join(GOLDEN, "stress_sets.json")) as f:
+        d = json.load(f)
+    g = cfggen.c5_cfg()
+    st, _, _, per = oracle.count(g, per_start=True)
+    assert d["n_pp"] == st["n_pp"] == workloads()["c5"]["n_pp"]
+    assert np.array_equal(np.asarray(d["pp_per_start"]), per)
+    assert d["n_spliced"] == d["n_pp"] and 0 < d["n_tp"] <= d["n_spliced"]
+
+
 # --- the paper's input form: switch vertices binarized (Sec. 3) -------------
 
 def _complete_paths(g):
