@@ -1,14 +1,30 @@
-"""The 400-vertex stress CFG (2.3e7 prime paths) at full size: outputs the
-oracle can compute one by one (prime paths of sampled first vertices, by the
-local rule) compared element by element, and properties checked at any size."""
+"""The 400-vertex stress CFG (2.3e7 prime paths, 1.9e7 test paths) at full
+size, against whole-set figures the CPU oracle wrote
+(tests/golden/stress_sets.json, made by oracle/stress_digests.py): the
+prime-path count of every first vertex, the prime-path and test-path set
+digests (sum mod 2^64 and xor of per-path FNV-1a 64 hashes over the
+length and the entries), the test-path count before and after exact
+deduplication.  Sampled first vertices are also compared element by element
+with the oracle's paths, and the test-path order is checked on samples."""
+import json
+import os
+
 import numpy as np
 import pytest
 
 import oracle
 from paper_2210_16998_amd import cfggen, tpg
+from tests.goldens import workloads
 from tests.gpu_util import say, ws
 
 pytestmark = pytest.mark.gpu
+
+SETS = os.path.join(os.path.dirname(__file__), "golden", "stress_sets.json")
+
+
+def _sets():
+    with open(SETS) as f:
+        return json.load(f)
 
 
 def _first_vertex_ranges(off, vtx, n):
@@ -19,35 +35,46 @@ def _first_vertex_ranges(off, vtx, n):
     return bounds.cpu().numpy()
 
 
-def test_stress_cfg_sampled_parity_and_properties():
+def test_stress_cfg_whole_sets_against_oracle():
     import torch
     g = cfggen.c5_cfg()
+    ref = _sets()
+    assert (ref["n"], ref["edges"]) == (g.n, g.n_edges)
     h = tpg.load_cfg(g)
-    say("case stress cfg", g.n)
-    pp, tp, st = tpg.test_paths(h, ws=ws(), flags=tpg.TPG_OUT_DEVICE)
-    rec = __import__("tests.goldens", fromlist=["workloads"]).workloads()["c5"]
-    assert st["n_pp"] == pp.n_paths and st["n_extensions"] == rec["n_extensions"]
+    say("case stress cfg whole sets", g.n)
+    pp, tp, st = tpg.test_paths(h, ws=ws(), flags=tpg.TPG_OUT_DEVICE | tpg.TPG_DIGEST)
+    rec = workloads()["c5"]
+    # counts: the oracle's, never the GPU's own
+    assert pp.n_paths == ref["n_pp"] == rec["n_pp"]
+    assert st["n_pp"] == ref["n_pp"]
+    assert st["n_extensions"] == rec["n_extensions"]
+    assert st["n_tp_spliced"] == ref["n_spliced"]
+    assert tp.n_paths == ref["n_tp"] and st["n_tp"] == ref["n_tp"]
+    # set digests over every path
+    assert pp.digest == tuple(int(x) for x in ref["pp_digest"])
+    assert tp.digest == tuple(int(x) for x in ref["tp_digest"])
+    # prime paths of every first vertex
     off, vtx = pp.torch_views()
     bounds = _first_vertex_ranges(off, vtx, g.n)
-    assert bounds[-1] == pp.n_paths
+    assert bounds[0] == 0 and bounds[-1] == pp.n_paths
+    assert np.array_equal(np.diff(bounds), np.asarray(ref["pp_per_start"], np.int64))
+    # element by element on sampled first vertices the oracle lists quickly
+    per_start = np.asarray(ref["pp_per_start"])
     rng = np.random.default_rng(5)
-    # first vertices whose prime paths the oracle lists quickly (<= 2e5 each),
-    # some with none at all
-    _, _, _, per_start = oracle.count(g, per_start=True)
     some = np.nonzero((per_start > 0) & (per_start <= 200_000))[0]
     none = np.nonzero(per_start == 0)[0]
     sample = sorted(set(rng.choice(some, 12, replace=False).tolist()
                         + rng.choice(none, 4, replace=False).tolist()))
     sampled_pps = []
     for s in sample:
-        ref, _ = oracle.prime_paths_local(g, int(s), int(s) + 1)
+        rp, _ = oracle.prime_paths_local(g, int(s), int(s) + 1)
         a, b = int(bounds[s]), int(bounds[s + 1])
         o = off[a:b + 1].cpu().numpy()
         v = vtx[int(o[0]):int(o[-1])].cpu().numpy()
-        assert np.array_equal(o - o[0], ref.offsets), s
-        assert np.array_equal(v, ref.vertices), s
-        sampled_pps += ref.tolist()[:50]
-    # test paths: entry/exit everywhere, sorted and unique on samples, and
+        assert np.array_equal(o - o[0], rp.offsets), s
+        assert np.array_equal(v, rp.vertices), s
+        sampled_pps += rp.tolist()[:50]
+    # test paths: entry/exit everywhere, strictly increasing on samples, and
     # the test path of each sampled prime path present
     toff, tvtx = tp.torch_views()
     assert bool((tvtx[toff[:-1]] == g.entry).all()) and bool((tvtx[toff[1:] - 1] == g.exit).all())
