@@ -310,6 +310,26 @@ tpg_status tpg_scc(const tpg_graph* g, const tpg_opts* opts, int32_t* comp, uint
 tpg_status tpg_prime_path_types(const tpg_graph* g, const tpg_paths* pps, const tpg_opts* opts,
                                 uint8_t* types, int64_t* counts);
 
+/* tpg_prime_path_types without device allocation, for callers that cannot
+ * allocate device memory (code under stream capture, serving loops,
+ * harnesses that forbid hipMalloc).  The prime-path set is in device memory
+ * on the current device (offsets int64 [n_paths + 1], vertices int32, read
+ * in place, unchecked); d_types (n_paths bytes, device, caller-owned, may be
+ * NULL) receives each path's type; counts (6 int64, host, may be NULL) the
+ * number of each type, as tpg_prime_path_types.  stream: a hipStream_t of
+ * the current device, or NULL for the default stream; the call returns once
+ * the stream has finished its work.  Everything else the kernels use (the
+ * graph's CSR staged on the device, the component search's arrays, labels,
+ * flags, counters) lives in a fixed 1 MiB device array that the library
+ * holds on each device until the process ends: a graph that needs more
+ * (about 108 000 arcs at 4096 vertices) gives TPG_ERR_CAPACITY before any
+ * device work.  Calls on one device share that array and the last call's
+ * contents stay in it, so calls that overlap on one device race; calls on
+ * different devices do not.  No device memory is allocated or freed. */
+tpg_status tpg_prime_path_types_noalloc(const tpg_graph* g, const int64_t* d_offsets,
+                                        const int32_t* d_vertices, int64_t n_paths, void* stream,
+                                        uint8_t* d_types, int64_t* counts);
+
 /* ------------------------------------------------------------------------
  * Batched form: prime and test paths of many CFGs in one call.
  *

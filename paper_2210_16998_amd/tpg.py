@@ -147,6 +147,10 @@ _SIGS = {
                                ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "tpg_prime_path_types": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Paths),
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "tpg_prime_path_types_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                                    ctypes.c_void_p, ctypes.c_int64,
+                                                    ctypes.c_void_p, ctypes.c_void_p,
+                                                    ctypes.c_void_p]),
     "tpg_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "tpg_last_error": (ctypes.c_char_p, []),
     "tpg_version": (ctypes.c_char_p, []),
@@ -455,6 +459,23 @@ def prime_path_types(g: Graph, pps, ws: Optional[Workspace] = None, stream=None,
                                       counts.ctypes.data))
     del keep
     return (types[:n] if want_types else None), counts
+
+
+def prime_path_types_noalloc(g: Graph, pps, types=None, stream=None) -> np.ndarray:
+    """counts int64 [6] of a device prime-path set of g (DevicePaths), and
+    each path's type into `types` (a uint8 device tensor of >= n_paths
+    elements, or None), without any device allocation by the library."""
+    if not isinstance(pps, DevicePaths):
+        raise TypeError("prime_path_types_noalloc takes a device path set (DevicePaths)")
+    n = int(pps.n_paths)
+    if types is not None:
+        assert types.dtype.itemsize == 1 and types.numel() >= n and types.is_contiguous()
+    counts = np.zeros(6, np.int64)
+    st = int(getattr(stream, "cuda_stream", stream or 0))
+    _check(lib().tpg_prime_path_types_noalloc(
+        g.handle, pps.offsets_ptr, pps.vertices_ptr, n, st or None,
+        types.data_ptr() if types is not None else None, counts.ctypes.data))
+    return counts
 
 
 def prime_paths_stream(g: Graph, on_chunk, ws: Optional[Workspace] = None, flags: int = 0,

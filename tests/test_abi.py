@@ -103,3 +103,20 @@ def test_path_type_inputs_are_checked_on_the_host():
     assert _err(lambda: tpg.prime_path_types(g, P([0, 2], [0, 1]))) == "TPG_ERR_DEVICE"
     assert _err(lambda: tpg.scc(g)) == "TPG_ERR_DEVICE"
     assert _err(lambda: tpg.prime_paths_vertex_lists(g)) == "TPG_ERR_DEVICE"
+
+
+def test_noalloc_types_reject_a_graph_beyond_the_fixed_scratch():
+    """The allocation-free typing holds its scratch in a fixed 1 MiB device
+    array; a graph that needs more is refused before any device work (so no
+    device is needed here)."""
+    n, deg = 4096, 64
+    rows = [sorted({(v + k) % n for k in range(1, deg + 1)}) for v in range(n)]
+    row_ptr = np.zeros(n + 1, np.int64)
+    row_ptr[1:] = np.cumsum([len(r) for r in rows])
+    col = np.concatenate([np.asarray(r, np.int32) for r in rows])
+    g = tpg.load_cfg_csr(n, row_ptr, col, 0, n - 1, tpg.TPG_LOAD_ANY_DIGRAPH)
+    rc = tpg.lib().tpg_prime_path_types_noalloc(g.handle, None, None, 0, None, None, None)
+    assert tpg.STATUS[rc] == "TPG_ERR_CAPACITY"
+    assert b"scratch" in tpg.lib().tpg_last_error()
+    rc = tpg.lib().tpg_prime_path_types_noalloc(g.handle, None, None, -1, None, None, None)
+    assert tpg.STATUS[rc] == "TPG_ERR_INVALID_ARG"
