@@ -422,6 +422,174 @@ def pp_types(g, pl: PathList) -> Tuple[np.ndarray, np.ndarray]:
     return types, np.bincount(types, minlength=6).astype(np.int64)
 
 
+def _is_subpath(p: List[int], q: List[int]) -> bool:
+    """p is a contiguous subpath of q (reading R1: subpaths are contiguous)."""
+    m = len(p)
+    return any(q[k:k + m] == p for k in range(len(q) - m + 1))
+
+
+def _component_paths(g, comp: np.ndarray, c: int) -> List[List[int]]:
+    """Every acyclic simple path that stays inside component c (depth-first
+    from each of its vertices, successors inside c only)."""
+    members = [v for v in range(g.n) if comp[v] == c]
+    out: List[List[int]] = []
+    for s in members:
+        stack = [(s, [s])]
+        while stack:
+            v, path = stack.pop()
+            out.append(path)
+            for w in reversed(g.succ(v).tolist()):
+                if comp[w] == c and w not in path:
+                    stack.append((w, path + [w]))
+    return out
+
+
+def scc_path_sets(g) -> Dict[str, PathList]:
+    """The intermediate paths of the compositional method (Sec. 2.1, Path
+    extraction), over every component with a cycle, from Defs. 6-8:
+
+    * entry_exit (Def. 6): acyclic simple paths inside a component from one
+      of its SccEntryVertices to one of its SccExitVertices;
+    * exit (Def. 7): exit paths (acyclic, inside a component, from a vertex
+      that is not an SccEntryVertex to an SccExitVertex) that are not a
+      proper subpath of another exit path to the same SccExitVertex;
+    * entry (Def. 8): entry paths (acyclic, inside a component, from an
+      SccEntryVertex to a vertex that is not an SccExitVertex) that are not a
+      proper subpath of another entry path from the same SccEntryVertex.
+
+    Maximality is taken per end vertex, as the extraction algorithms of
+    Sec. 2.1 are stated for a specified exit (entry) vertex; on Fig. 1 it
+    gives the same paths as maximality over all exit (entry) paths.  Each set
+    in canonical (lexicographic) order."""
+    comp = scc(g)
+    fl = scc_flags(g, comp)
+    ee: List[List[int]] = []
+    ex: List[List[int]] = []
+    en: List[List[int]] = []
+    for c in sorted({int(x) for x in comp}):
+        if not fl[c] & SCC_CYCLIC:
+            continue
+        paths = _component_paths(g, comp, c)
+        ee += [p for p in paths if fl[p[0]] & SCC_ENTRY_VERTEX and fl[p[-1]] & SCC_EXIT_VERTEX]
+        xc = [p for p in paths if not fl[p[0]] & SCC_ENTRY_VERTEX and fl[p[-1]] & SCC_EXIT_VERTEX]
+        ex += [p for p in xc if not any(len(q) > len(p) and q[-1] == p[-1] and _is_subpath(p, q)
+                                        for q in xc)]
+        nc = [p for p in paths if fl[p[0]] & SCC_ENTRY_VERTEX and not fl[p[-1]] & SCC_EXIT_VERTEX]
+        en += [p for p in nc if not any(len(q) > len(p) and q[0] == p[0] and _is_subpath(p, q)
+                                        for q in nc)]
+    return {k: PathList.from_lists(sorted(v)) for k, v in
+            (("entry_exit", ee), ("exit", ex), ("entry", en))}
+
+
+def ccfg_paths(g) -> List[List[int]]:
+    """Prime paths of the component graph (Def. 3): it is acyclic with one
+    source (the entry's component) and one sink (the exit's), so they are its
+    paths from source to sink, as sequences of component labels."""
+    comp = scc(g)
+    arcs = ccfg(g, comp)
+    succ: Dict[int, List[int]] = {}
+    for a, b in arcs:
+        succ.setdefault(a, []).append(b)
+    src, dst = int(comp[g.entry]), int(comp[g.exit])
+    out: List[List[int]] = []
+    stack = [[src]]
+    while stack:
+        p = stack.pop()
+        if p[-1] == dst:
+            out.append(p)
+            continue
+        for b in sorted(succ.get(p[-1], []), reverse=True):
+            stack.append(p + [b])
+    return sorted(out)
+
+
+def _is_prime(g, p: List[int], preds: List[List[int]]) -> bool:
+    """p (a simple path or simple cycle) cannot be extended at either end."""
+    if len(p) > 1 and p[0] == p[-1]:
+        return True
+    on = set(p)
+    fwd = any(int(w) not in on or int(w) == p[0] for w in g.succ(p[-1]))
+    bwd = any(u not in on or u == p[-1] for u in preds[p[0]])
+    return not fwd and not bwd
+
+
+def merge_pps(g) -> Dict[str, object]:
+    """Sec. 2.1, Merging: the CompletePPs, SccExitPPs and SccEntryPPs built
+    from the component graph's prime paths and the extracted paths.
+
+    * complete: each component-graph path with every component replaced by
+      one of its paths that the arcs of g join to its neighbours (the entry's
+      and exit's components are single vertices; a component without a cycle
+      contributes its vertex; a component with a cycle one of its
+      SccEntryExitPaths);
+    * exit: for each complete path and each component with a cycle it
+      leaves, at SccExitVertex x, the path's rest from x, prefixed by every
+      SccExitPath of that component that ends at x;
+    * entry: for each complete path and each component with a cycle it
+      enters, at SccEntryVertex y, the path's part before y, followed by
+      every SccEntryPath of that component that starts at y.
+
+    A merged path that can still be extended at one of its ends (this
+    happens when an exit path's first vertex has a predecessor, necessarily
+    an SccEntryVertex, off the path, or an entry path's last vertex a
+    successor, necessarily an SccExitVertex, off it) is not a prime path and
+    is dropped; the numbers dropped are returned too (none on Fig. 1)."""
+    comp = scc(g)
+    fl = scc_flags(g, comp)
+    sets = scc_path_sets(g)
+    preds: List[List[int]] = [[] for _ in range(g.n)]
+    for v in range(g.n):
+        for w in g.succ(v):
+            preds[int(w)].append(v)
+    arc = {(v, int(w)) for v in range(g.n) for w in g.succ(v)}
+    ee_by_comp: Dict[int, List[List[int]]] = {}
+    for p in sets["entry_exit"].tolist():
+        ee_by_comp.setdefault(int(comp[p[0]]), []).append(p)
+    ex_by_end: Dict[int, List[List[int]]] = {}
+    for p in sets["exit"].tolist():
+        ex_by_end.setdefault(p[-1], []).append(p)
+    en_by_start: Dict[int, List[List[int]]] = {}
+    for p in sets["entry"].tolist():
+        en_by_start.setdefault(p[0], []).append(p)
+
+    def pieces(c: int) -> List[List[int]]:
+        if fl[c] & SCC_CYCLIC:
+            return ee_by_comp.get(c, [])
+        return [[c]]  # a component without a cycle is its one vertex (label = vertex)
+
+    complete: List[List[int]] = []
+    for cp in ccfg_paths(g):
+        partial = [[]]
+        for c in cp:
+            nxt = []
+            for pre in partial:
+                for piece in pieces(c):
+                    if not pre or (pre[-1], piece[0]) in arc:
+                        nxt.append(pre + piece)
+            partial = nxt
+        complete += partial
+    complete = sorted({tuple(p) for p in complete})
+    cand_ex, cand_en = set(), set()
+    for p in complete:
+        p = list(p)
+        for i, v in enumerate(p):
+            if not fl[v] & SCC_CYCLIC:
+                continue
+            if i + 1 < len(p) and comp[p[i + 1]] != comp[v]:  # leaves the component at v
+                for e in ex_by_end.get(v, []):
+                    cand_ex.add(tuple(e + p[i + 1:]))
+            if i > 0 and comp[p[i - 1]] != comp[v]:  # enters it at v
+                for f in en_by_start.get(v, []):
+                    cand_en.add(tuple(p[:i] + f))
+    ex_pps = sorted(q for q in cand_ex if _is_prime(g, list(q), preds))
+    en_pps = sorted(q for q in cand_en if _is_prime(g, list(q), preds))
+    return {"complete": PathList.from_lists([list(p) for p in complete]),
+            "exit": PathList.from_lists([list(p) for p in ex_pps]),
+            "entry": PathList.from_lists([list(p) for p in en_pps]),
+            "dropped_exit": len(cand_ex) - len(ex_pps),
+            "dropped_entry": len(cand_en) - len(en_pps)}
+
+
 def canonical_bytes(pl: PathList) -> bytes:
     """n (int64 LE) + offsets (int64 LE) + vertices (int32 LE)."""
     return (np.int64(len(pl)).tobytes() + pl.offsets.astype("<i8").tobytes()

@@ -594,3 +594,96 @@ def test_ccfg_is_acyclic_and_internal_pps_come_from_the_scc_alone(seed):
             if cyclic or not (fl[q[0]] & oracle.SCC_ENTRY_VERTEX or fl[q[-1]] & oracle.SCC_EXIT_VERTEX):
                 want.append(q)
     assert got == sorted(want)
+
+
+# --- compositional method: path extraction (Defs. 6-8) and merging (Sec. 2.1)
+
+def test_fig1_extracted_paths_match_paper():
+    """Sec. 2.1, Path extraction, on Fig. 1: the SccEntryExitPaths <2> and
+    <2,3,5>, the four SccExitPaths and the two SccEntryPaths printed in the
+    text; the component graph's two prime paths of Sec. 2.1, PP Generation."""
+    from tests.goldens import read_labelled_paths
+    g = cfggen.fig1_cfg()
+    want = read_labelled_paths("fig1_extraction.txt")
+    got = oracle.scc_path_sets(g)
+    for key in ("entry_exit", "exit", "entry"):
+        assert got[key].tolist() == sorted(want[key]), key
+    assert oracle.ccfg_paths(g) == sorted(want["ccfg"])
+
+
+def test_fig1_merge_reproduces_the_papers_merged_groups():
+    """Sec. 2.1, Merging: the 2 CompletePPs, 4 SccExitPPs and 2 SccEntryPPs
+    printed in the text, none of them dropped as extendable."""
+    g = cfggen.fig1_cfg()
+    groups = _fig1_groups()
+    m = oracle.merge_pps(g)
+    for key in ("complete", "exit", "entry"):
+        assert m[key].tolist() == sorted(groups[key]), key
+    assert m["dropped_exit"] == 0 and m["dropped_entry"] == 0
+
+
+def _typed(g):
+    pl, _, _, _ = oracle.prime_paths(g)
+    ty, _ = oracle.pp_types(g, pl)
+    L = pl.tolist()
+    return {k: sorted(L[i] for i in range(len(L)) if ty[i] == t)
+            for k, t in (("complete", oracle.PP_COMPLETE), ("exit", oracle.PP_SCC_EXIT),
+                         ("entry", oracle.PP_SCC_ENTRY))}
+
+
+@pytest.mark.parametrize("family", ["random", "structured"])
+def test_merge_equals_the_typed_prime_paths(family):
+    """The merged sets are exactly the prime paths of types Def. 2, 10 and 11
+    found by the enumeration (an independent route: DFS + prune pass +
+    typing).  On the random digraph-like CFGs some merged candidates can
+    still be extended and are dropped; on the structured CFGs none is."""
+    if family == "random":
+        gs = [cfggen.random_small_cfg(9000 + s, 4 + (s * 7) % 40, extra=1 + s % 5)
+              for s in range(60)]
+    else:
+        gs = [cfggen.c1_cfg(0), cfggen.loop_diamond_chain(4)]
+        gs += [g for g in (cfggen.batch_member_cfg(cfggen.C3_SEED_BASE + s) for s in range(40))
+               if g.n <= 80]
+    dropped = 0
+    for g in gs:
+        want = _typed(g)
+        m = oracle.merge_pps(g)
+        for key in want:
+            assert m[key].tolist() == want[key], (g.name, key)
+        dropped += m["dropped_exit"] + m["dropped_entry"]
+    if family == "structured":
+        assert dropped == 0
+    else:
+        assert dropped > 0  # the case the prime test is there for does occur
+
+
+def test_extraction_sets_are_the_definitions():
+    """Defs. 6-8 checked from the other side on small graphs: every
+    extracted path stays in one component with a cycle and has the end
+    vertices its definition requires, is acyclic, and (for exit and entry
+    paths) no longer path of the same kind with the same end contains it."""
+    for s in range(25):
+        g = cfggen.random_small_cfg(9500 + s, 5 + s, extra=2 + s % 4)
+        comp = oracle.scc(g)
+        fl = oracle.scc_flags(g, comp)
+        sets = oracle.scc_path_sets(g)
+        for key, pl in sets.items():
+            for p in pl.tolist():
+                assert len(set(p)) == len(p)
+                assert len({int(comp[v]) for v in p}) == 1 and fl[p[0]] & oracle.SCC_CYCLIC
+                for a, b in zip(p, p[1:]):
+                    assert b in g.succ(a).tolist()
+                ent, ext = fl[p[0]] & oracle.SCC_ENTRY_VERTEX, fl[p[-1]] & oracle.SCC_EXIT_VERTEX
+                if key == "entry_exit":
+                    assert ent and ext
+                elif key == "exit":
+                    assert not ent and ext
+                    # one step back to a non-entry vertex would give a longer exit path
+                    for u in range(g.n):
+                        if p[0] in g.succ(u).tolist() and comp[u] == comp[p[0]] and u not in p:
+                            assert fl[u] & oracle.SCC_ENTRY_VERTEX
+                else:
+                    assert ent and not ext
+                    for w in g.succ(p[-1]).tolist():
+                        if comp[w] == comp[p[0]] and w not in p:
+                            assert fl[w] & oracle.SCC_EXIT_VERTEX
