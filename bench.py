@@ -1,5 +1,7 @@
-"""Benchmark: exact prime paths + test paths of one ~200-vertex structured CFG
-on one MI355X.
+"""Benchmark: exact prime paths + test paths of the 400-vertex stress CFG
+(3 nested whiles, a 16-way switch, 60 if-else diamonds; 2.3e7 prime paths)
+on one MI355X, with the ~200-vertex CFG, the 4096-CFG batch (plain, batched,
+learned sizing) and the comparison variants as sub-objects.
 
 One step = one pass of the whole hot path on the GPU: level-synchronous
 extension of simple paths from every vertex, backward-extendability filter,
@@ -68,6 +70,28 @@ def _copy_peak(stream, mib: int = 4096, reps: int = 10) -> float:
     return 2.0 * (mib << 20) / (best * 1e-3) / 1e9
 
 
+def _copy_probe(mib: int) -> int:
+    """One device-to-device copy of exactly `mib` MiB (torch's copy kernel),
+    after three untimed ones: FETCH_SIZE / WRITE_SIZE read on it scale the
+    counter readings of the path kernels."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.arange(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    print(f"copied {mib} MiB in {ms:.3f} ms: {2 * mib / 1024 / (ms / 1e3):.0f} GiB/s "
+          f"(read + write)", flush=True)
+    return 0
+
+
 def _measured_traffic(kernel: str, summary: str = "k_extend_cfg209_hbm_traffic.md"):
     """HBM bytes per launch from the committed counter summary, if it was
     taken on this same kernel (else None)."""
@@ -89,50 +113,6 @@ def _bytes_per_extension(n: int) -> int:
     written once and read once as a parent (16 B), and its visited set of
     ceil(n / 64) words is written once and read once."""
     return 16 + 2 * 8 * ((n + 63) // 64)
-
-
-def _stress(args, copy_gbs: float):
-    """The 400-vertex stress CFG: one-pass prime paths (device output), with
-    the extension kernel's roofline measured on its ~4.7e8 extensions."""
-    import torch
-    from paper_2210_16998_amd import cfggen, tpg
-    g = cfggen.c5_cfg()
-    h = tpg.load_cfg(g)
-    ws = tpg.Workspace(0)
-    stream = torch.cuda.Stream()
-    cap = 64 << 30  # the stress workload's pool cap (64 GiB of HBM)
-    tpg.prime_paths(h, ws=ws, flags=tpg.TPG_OUT_DEVICE, stream=stream, pool_cap=cap)
-    torch.cuda.synchronize()
-    times, k_ms, k_launches = [], 0.0, 0
-    for _ in range(args.stress_reps):
-        t = time.perf_counter()
-        _, st = tpg.prime_paths(h, ws=ws, flags=tpg.TPG_OUT_DEVICE, stream=stream, pool_cap=cap)
-        times.append(time.perf_counter() - t)
-        k_ms += st["ms_extend_kernel"]
-        k_launches += st["n_extend_launches"]
-    bpe = _bytes_per_extension(g.n)
-    avg = k_ms / max(1, k_launches)
-    per_launch = st["n_extensions"] * bpe / max(1, st["n_extend_launches"])
-    ach = per_launch / (avg * 1e-3) / 1e9 if avg > 0 else 0.0
-    ms = 1000.0 * statistics.median(times)
-    kname = _kernel_name(8, tpg.get_tuning(ws), g)
-    traffic = _measured_traffic(kname, "k_extend_stress400_hbm_traffic.md")
-    ws.close()
-    return {"workload": f"stress CFG, {g.n} vertices, {g.n_edges} arcs (3 nested whiles, 16-way "
-                        f"switch, 60 diamonds), prime paths only",
-            "n_pp": st["n_pp"], "n_extensions": st["n_extensions"], "levels": st["n_levels"],
-            "ms_per_run_median": ms, "prime_paths_per_s": st["n_pp"] / (ms * 1e-3),
-            "extensions_per_s": st["n_extensions"] / (ms * 1e-3),
-            "extend_kernel_ms": k_ms / args.stress_reps,
-            "device_bytes": st["device_bytes"], "pool_cap_bytes": cap,
-            "roofline": {"bound": "hbm", "kernel": kname, "achieved": ach,
-                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                         "traffic": traffic,
-                         "measured_GBps": traffic / (avg * 1e-3) / 1e9 if traffic and avg > 0 else None,
-                         "copy_GBps": copy_gbs, "frac_of_copy": ach / copy_gbs,
-                         "algorithmic_bytes_per_launch": per_launch,
-                         "bytes_per_extension": bpe, "launches_per_run": st["n_extend_launches"],
-                         "avg_launch_ms": avg}}
 
 
 def _paper_form(args):
@@ -272,72 +252,100 @@ def _prior_schedule(args):
     return out
 
 
-def _cpu_baseline(g, reps: int):
-    """The CPU oracle on the same graph (DFS enumeration from every vertex,
-    local-rule prime test, splice + sort + dedup of test paths)."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_sample(g, threads: int, target_pp: int, seconds: float, chunk: int, seed: int):
+    """The oracle over start-vertex chunks of `chunk` consecutive vertices, in
+    a seeded random order, until `target_pp` prime paths are found (or
+    `seconds` of prime-path work are spent); then its test-path stage
+    (splice, sort, dedup) on the prime paths found.  Returns the timings and
+    what was processed."""
+    import numpy as np
     import oracle
-    threads = min(16, os.cpu_count() or 1)
-    t0 = time.perf_counter()
-    n_pp = 0
-    for _ in range(reps):
-        pp, st = oracle.prime_paths_local(g, 0, g.n, nthreads=threads)
-        tp, _ = oracle.test_paths(g, pp)
-        n_pp += len(pp)
-    dt = time.perf_counter() - t0
-    # one core, on the start vertices 0 .. n/8 (a bounded sample)
-    hi = max(1, g.n // 8)
-    t1 = time.perf_counter()
-    pp1, _ = oracle.prime_paths_local(g, 0, hi, nthreads=1)
-    oracle.test_paths(g, pp1)
-    dt1 = time.perf_counter() - t1
-    return {"value": n_pp / dt, "unit": "prime paths/s", "cores": threads, "kind": "oracle",
-            "sample": f"whole workload x{reps}: DFS from all {g.n} vertices with the local "
-                      f"prime test, then test-path splice/sort/dedup; {dt:.1f} s total",
-            "one_core": {"value": len(pp1) / dt1, "unit": "prime paths/s", "cores": 1,
-                         "sample": f"start vertices 0..{hi - 1} ({len(pp1)} prime paths), same "
-                                   f"steps; {dt1:.1f} s"}}
+    starts = np.random.default_rng(seed).permutation(np.arange(0, g.n, chunk))
+    parts, done, t_pp = [], [], 0.0
+    for s in starts:
+        t = time.perf_counter()
+        pl, _ = oracle.prime_paths_local(g, int(s), int(min(g.n, s + chunk)), nthreads=threads)
+        t_pp += time.perf_counter() - t
+        parts.append(pl)
+        done.append(int(s))
+        if sum(len(p) for p in parts) >= target_pp or t_pp >= seconds:
+            break
+    offs = [np.zeros(1, np.int64)]
+    base = 0
+    for pl in parts:
+        offs.append(pl.offsets[1:] + base)
+        base += int(pl.offsets[-1])
+    pps = oracle.PathList(np.concatenate(offs), np.concatenate([pl.vertices for pl in parts]))
+    t = time.perf_counter()
+    tps, _ = oracle.test_paths(g, pps)
+    t_tp = time.perf_counter() - t
+    return {"n_pp": len(pps), "n_tp": len(tps), "pp_s": t_pp, "tp_s": t_tp,
+            "starts": f"{len(done)} chunks of {chunk} start vertices (of {len(starts)}), "
+                      f"seeded order"}
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-reps", type=int, default=3)
-    ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--batch-reps", type=int, default=3)
-    ap.add_argument("--no-stress", action="store_true")
-    ap.add_argument("--stress-reps", type=int, default=3)
-    ap.add_argument("--no-paper-form", action="store_true")
-    ap.add_argument("--no-covering", action="store_true")
-    ap.add_argument("--no-components", action="store_true")
-    ap.add_argument("--no-prior-schedule", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is "
-              f"single-GPU in this build", file=sys.stderr)
-        return 2
+def _cpu_baseline(g, target_pp: int, seconds: float = 60.0):
+    """The CPU oracle on a bounded sample of the same workload: DFS enumeration
+    with the local prime test over start-vertex chunks taken in a seeded
+    random order until about `target_pp` prime paths are found, then the
+    test-path stage (splice, sort, dedup; one thread) on the prime paths
+    found.  Run with the host threads a one-GPU job gets (at most 16) and
+    with one thread."""
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    threads = max(1, min(16, avail or 1))
+    out = {"unit": "prime paths/s", "kind": "oracle", "cpu_model": _cpu_model(),
+           "host_cpus_visible": avail}
+    # both legs take the same start vertices (chunks of 16 in one seeded order)
+    for name, th in (("all", threads), ("one_core", 1)):
+        r = _oracle_sample(g, th, target_pp, seconds, 16, seed=17)
+        rate = r["n_pp"] / (r["pp_s"] + r["tp_s"])
+        rec = {"value": rate, "cores": th,
+               "prime_paths_stage": {"seconds": r["pp_s"], "prime_paths_per_s": r["n_pp"] / r["pp_s"]},
+               "test_paths_stage": {"seconds": r["tp_s"], "threads": 1,
+                                    "prime_paths_per_s": r["n_pp"] / max(r["tp_s"], 1e-9)},
+               "sample": f"{r['starts']}: {r['n_pp']} prime paths, {r['n_tp']} test paths; "
+                         f"{r['pp_s'] + r['tp_s']:.1f} s"}
+        if name == "all":
+            out.update(rec)
+        else:
+            out["one_core"] = rec
+    return out
 
+
+def _whole_path(g, args, stream, copy_gbs: float, traffic_summary: str, pool_cap: int = 0):
+    """Whole hot path (prime + test paths, device output) on graph g: a cold
+    first call on a fresh workspace, `warmup` untimed steps, `steps` timed
+    steps (level loop replayed from captured HIP graphs), then the same
+    number of steps issued one launch at a time with a HIP event pair on the
+    library's stream around every extension launch (the kernel's roofline)
+    and per-phase events."""
     import torch
     from paper_2210_16998_amd import tpg
-
-    assert torch.cuda.is_available(), "no GPU"
-    torch.cuda.set_device(0)
-    g, rec = _workload()
-    ws = tpg.Workspace(0)
     h = tpg.load_cfg(g)
-    stream = torch.cuda.Stream()
+    ws = tpg.Workspace(0)
     flags = tpg.TPG_OUT_DEVICE
 
     def step(f=flags):
-        return tpg.test_paths(h, ws=ws, flags=f, stream=stream, want_pp=True)
+        return tpg.test_paths(h, ws=ws, flags=f, stream=stream, want_pp=True, pool_cap=pool_cap)
 
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    step(flags | tpg.TPG_NO_TIMING)
+    torch.cuda.synchronize()
+    cold_ms = 1000.0 * (time.perf_counter() - t)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    # timed region: every call returns after its stream has drained; the
-    # level loop is replayed from captured HIP graphs
     times = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -345,28 +353,23 @@ def main() -> int:
         step(flags | tpg.TPG_NO_TIMING)
         times.append(time.perf_counter() - t)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms = 1000.0 * dt / args.steps
-    # kernel-timed pass over the same steps: the same launches issued one by
-    # one with a HIP event pair on the library's stream around every
-    # extension launch, plus per-phase events
+    ms = 1000.0 * (time.perf_counter() - t0) / args.steps
     k_ms, k_launches, phases = 0.0, 0, []
     t2 = time.perf_counter()
     for _ in range(args.steps):
-        pp, tp, st = step()
+        _, _, st = step()
         k_ms += st["ms_extend_kernel"]
         k_launches += st["n_extend_launches"]
         phases.append(st)
     torch.cuda.synchronize()
     ms_timed = 1000.0 * (time.perf_counter() - t2) / args.steps
     n_pp, n_ext = st["n_pp"], st["n_extensions"]
-    bytes_per_ext = _bytes_per_extension(g.n)
-    avg_launch_ms = k_ms / max(1, k_launches)
-    # algorithmic bytes of one launch: the run's extensions spread over its launches
-    achieved = (n_ext * bytes_per_ext / max(1, st["n_extend_launches"])) / (avg_launch_ms * 1e-3) / 1e9 \
-        if avg_launch_ms > 0 else 0.0
+    bpe = _bytes_per_extension(g.n)
+    avg = k_ms / max(1, k_launches)
+    per_launch = n_ext * bpe / max(1, st["n_extend_launches"])
+    achieved = per_launch / (avg * 1e-3) / 1e9 if avg > 0 else 0.0
 
-    # plain per-CFG two-pass form, same graph, for context
+    # plain per-CFG two-pass form of the same graph, for context
     for _ in range(2):
         step(flags | tpg.TPG_FORCE_TWO_PASS | tpg.TPG_NO_TIMING)
     torch.cuda.synchronize()
@@ -384,48 +387,106 @@ def main() -> int:
     while W * 64 < g.n:
         W *= 2
     kname = _kernel_name(W, tpg.get_tuning(ws), g)
-    traffic = _measured_traffic(kname)
-    copy_gbs = _copy_peak(stream)
+    traffic = _measured_traffic(kname, traffic_summary)
+    dev_bytes = st["device_bytes"]
+    ws.close()
+    measured = traffic / (avg * 1e-3) / 1e9 if traffic and avg > 0 else None
+    return {
+        "ms_per_step": ms, "n_pp": n_pp, "n_extensions": n_ext, "n_tp": st["n_tp"],
+        "n_tp_spliced": st["n_tp_spliced"], "levels": st["n_levels"],
+        "prime_paths_per_s": n_pp / (ms * 1e-3), "extensions_per_s": n_ext / (ms * 1e-3),
+        "test_paths_per_s": st["n_tp"] / (ms * 1e-3),
+        "step_ms": {"median": 1000.0 * statistics.median(times),
+                    "mean": 1000.0 * statistics.fmean(times),
+                    "kernel_timed_pass_mean": ms_timed, "cold_first_call": cold_ms},
+        "phase_ms_median": {"extend": med("ms_extend"), "rank_materialize": med("ms_rank"),
+                            "test_paths": med("ms_tp"), "total_device": med("ms_total"),
+                            "extend_kernel": med("ms_extend_kernel")},
+        "plain_two_pass_ms_per_step": ms_plain,
+        "device_bytes": dev_bytes,
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "measured_GBps": measured,
+                     "measured_frac": measured / HBM_PEAK_GBS if measured else None,
+                     "copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs,
+                     "algorithmic_bytes_per_launch": per_launch, "bytes_per_extension": bpe,
+                     "launches_per_step": st["n_extend_launches"], "avg_launch_ms": avg},
+    }
 
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-pp", type=int, default=600_000,
+                    help="prime paths in each bounded oracle sample")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--no-cfg209", action="store_true")
+    ap.add_argument("--no-paper-form", action="store_true")
+    ap.add_argument("--no-covering", action="store_true")
+    ap.add_argument("--no-components", action="store_true")
+    ap.add_argument("--no-prior-schedule", action="store_true")
+    ap.add_argument("--only", choices=["batched", "paper_form", "covering", "components",
+                                       "prior_schedule"],
+                    help="run one section alone and print its JSON (for profiling)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run one device-to-device copy of MIB MiB (the reference "
+                         "traffic that scales HBM counter readings) and exit")
+    args = ap.parse_args()
+    if args.copy_probe:
+        return _copy_probe(args.copy_probe)
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is "
+              f"single-GPU in this build", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2210_16998_amd import cfggen
+
+    assert torch.cuda.is_available(), "no GPU"
+    torch.cuda.set_device(0)
+    if args.only:
+        fn = {"batched": _batched, "paper_form": _paper_form, "covering": _covering,
+              "components": _components, "prior_schedule": _prior_schedule}[args.only]
+        print(json.dumps({args.only: fn(args)}), flush=True)
+        return 0
+    stream = torch.cuda.Stream()
+    copy_gbs = _copy_peak(stream)
+    g = cfggen.c5_cfg()
+    cap = 64 << 30  # the stress workload's pool cap (64 GiB of HBM)
+    r = _whole_path(g, args, stream, copy_gbs, "k_extend_stress400_hbm_traffic.md", pool_cap=cap)
     out = {
         "metric": METRIC,
-        "value": n_pp / (ms * 1e-3),
+        "value": r["prime_paths_per_s"],
         "unit": "prime paths/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": f"single structured CFG, {g.n} vertices, {g.n_edges} arcs, "
-                               f"cyclomatic {g.cyclomatic}, seed {rec['seed']} (prime + test paths)",
-                   "n_pp": n_pp, "n_extensions": n_ext, "n_tp": st["n_tp"],
-                   "levels": st["n_levels"]},
-        "extensions_per_s": n_ext / (ms * 1e-3),
-        "test_paths_per_s": st["n_tp"] / (ms * 1e-3),
-        "step_ms": {"median": 1000.0 * statistics.median(times),
-                    "mean": 1000.0 * statistics.fmean(times),
-                    "kernel_timed_pass_mean": ms_timed},
-        "phase_ms_median": {"extend": med("ms_extend"), "rank_materialize": med("ms_rank"),
-                            "test_paths": med("ms_tp"), "total_device": med("ms_total"),
-                            "extend_kernel": med("ms_extend_kernel")},
-        "plain_two_pass_ms_per_step": ms_plain,
-        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic,
-                     "measured_GBps": traffic / (avg_launch_ms * 1e-3) / 1e9
-                     if traffic and avg_launch_ms > 0 else None,
-                     "copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs,
-                     "algorithmic_bytes_per_launch": n_ext * bytes_per_ext / max(1, st["n_extend_launches"]),
-                     "bytes_per_extension": bytes_per_ext,
-                     "launches_per_step": st["n_extend_launches"],
-                     "avg_launch_ms": avg_launch_ms},
+        "config": {"workload": f"stress CFG, {g.n} vertices, {g.n_edges} arcs, cyclomatic "
+                               f"{g.cyclomatic} (3 nested whiles, 16-way switch, 60 if-else "
+                               f"diamonds); whole path: prime + test paths",
+                   "n_pp": r["n_pp"], "n_extensions": r["n_extensions"], "n_tp": r["n_tp"],
+                   "levels": r["levels"], "pool_cap_bytes": cap},
     }
-    if not args.no_stress:
-        out["stress"] = _stress(args, copy_gbs)
+    out["roofline"] = r.pop("roofline")
+    for k in ("extensions_per_s", "test_paths_per_s", "n_tp_spliced", "step_ms",
+              "phase_ms_median", "plain_two_pass_ms_per_step", "device_bytes"):
+        out[k] = r[k]
+    if not args.no_cfg209:
+        g2, rec = _workload()
+        r2 = _whole_path(g2, args, stream, copy_gbs, "k_extend_cfg209_hbm_traffic.md")
+        r2["workload"] = (f"single structured CFG, {g2.n} vertices, {g2.n_edges} arcs, "
+                          f"cyclomatic {g2.cyclomatic}, seed {rec['seed']} (prime + test paths)")
+        out["cfg209"] = r2
     if not args.no_paper_form:
         out["paper_form"] = _paper_form(args)
     if not args.no_covering:
@@ -437,7 +498,9 @@ def main() -> int:
     if not args.no_batch:
         out["batched"] = _batched(args)
     if not args.no_cpu:
-        out["cpu_baseline"] = _cpu_baseline(g, args.cpu_reps)
+        out["cpu_baseline"] = _cpu_baseline(g, args.cpu_pp)
+        if "cfg209" in out:
+            out["cfg209"]["cpu_baseline"] = _cpu_baseline(_workload()[0], args.cpu_pp // 2)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -447,7 +510,7 @@ def _batched(args):
     two-pass sizing vs the batched form sized by the learned predictor."""
     import numpy as np
     import torch
-    from paper_2210_16998_amd import cfggen, sizer, tpg
+    from paper_2210_16998_amd import cfggen, sizer, tpg, tuning
 
     cfgs = cfggen.c3_batch(4096)
     graphs = [tpg.load_cfg(c) for c in cfgs]
@@ -473,35 +536,70 @@ def _batched(args):
     def onepass(ws):
         return tpg.batch_test_paths(graphs, ws=ws, flags=dev)
 
+    def snapshot(r):
+        """Copies of a device result's arrays (the next call on the same
+        workspace overwrites them)."""
+        po, pv = r.pp.torch_views()
+        to, tv = r.tp.torch_views()
+        return [x.clone() for x in (po, pv, to, tv)] + [r.pp_first.copy(), r.tp_first.copy()]
+
+    def same(a, b):
+        return all((torch.equal(x, y) if torch.is_tensor(x) else np.array_equal(x, y))
+                   for x, y in zip(a, b))
+
     res = {"workload": "4096 structured CFGs, vertices lognormal (median 40, clipped 10..300), "
                        "seeds 3000000+i"}
     ws = tpg.Workspace(0)
+    # launch shapes of the extension kernel per visited-set width: the cached
+    # autotuner result for this GPU, else tuned now on this batch
+    shape = tuning.load(ws)
+    if shape is None:
+        t = time.perf_counter()
+        shape = tpg.autotune(graphs, ws)
+        res["tuning"] = {"source": "autotuned on this batch",
+                         "seconds": time.perf_counter() - t, **shape}
+    else:
+        res["tuning"] = {"source": "cache " + os.path.relpath(tuning.DEFAULT_CACHE, ROOT), **shape}
+    shape = tpg.get_tuning(ws)
+
+    def fresh():
+        w = tpg.Workspace(0)
+        tpg.set_tuning(w, shape)
+        return w
+
     twopass(ws)
     ms2, (r2, st2) = timed(lambda: twopass(ws), args.batch_reps)
+    ref = snapshot(r2)
     res["batched_two_pass_ms"] = ms2
     res["n_pp"] = int(st2["n_pp"])
     res["n_extensions"] = int(st2["n_extensions"])
     res["n_tp"] = int(st2["n_tp"])
+    onepass(ws)
+    ms1, (r1, _) = timed(lambda: onepass(ws), args.batch_reps)
+    res["batched_one_pass_unpredicted_ms"] = ms1
+    res["one_pass_same_paths_as_two_pass"] = same(snapshot(r1), ref)
     if mlp is not None:
         learned(ws)
         msl, (rl, stl) = timed(lambda: learned(ws), args.batch_reps)
         res["batched_learned_ms"] = msl
         res["prime_paths_per_s_learned"] = st2["n_pp"] / (msl * 1e-3)
         res["extensions_per_s_learned"] = st2["n_extensions"] / (msl * 1e-3)
-        res["same_results_as_two_pass"] = bool(
-            np.array_equal(rl.pp_first, r2.pp_first) and np.array_equal(rl.tp_first, r2.tp_first))
+        # every offset and vertex of both path sets, not only the counts
+        res["same_paths_as_two_pass"] = same(snapshot(rl), ref)
         res["gain_vs_batched_two_pass"] = ms2 / msl
+        res["gain_vs_batched_one_pass_unpredicted"] = ms1 / msl
         # cold start: fresh workspaces, predicted sizing vs growing by replay
-        wc = tpg.Workspace(0)
+        wc = fresh()
         msc, (_, stc) = timed(lambda: learned(wc), 1)
         wc.close()
-        wo = tpg.Workspace(0)
+        wo = fresh()
         mso, (_, sto) = timed(lambda: onepass(wo), 1)
         wo.close()
         res["cold_learned_ms"] = msc
         res["cold_learned_overflows"] = int(stc["n_overflows"])
         res["cold_unpredicted_ms"] = mso
         res["cold_unpredicted_overflows"] = int(sto["n_overflows"])
+        res["cold_gain"] = mso / msc
         res["over_allocation"] = stc["pred_nodes"] * 1.25 / max(1, stc["n_nodes"])
     ws1 = tpg.Workspace(0)
     t = time.perf_counter()

@@ -72,7 +72,7 @@ struct tpg_workspace {
   DevBuf scan_status, scan_ctr, scalars;
   DevBuf scan2_status, scalars2;  // the side stream's own scan scratch
   // test paths
-  DevBuf bfs_i32, pfx_off, sfx_off, pfx, sfx;
+  DevBuf bfs_i32, pfx_off, sfx_off, pfx, sfx, pfx_pk, sfx_pk;
   DevBuf tp_len, tp_off, tp_vtx, tp_key, tp_pk, idx0, idx1, grp_cnt, rb0, rb1;
   DevBuf keep_cnt, keep_len, keep_pos, keep_voff, comp_cnt;
   // per-level, per-component counts (batched labels)
@@ -921,9 +921,15 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
   b.pfx = ws->pfx.as<int32_t>();
   b.sfx = ws->sfx.as<int32_t>();
   TPG_HIP(launch_bfs_tables(ws->dg, b, st));
+  const int pe = 64 / eb;
+  // packed rows: row v at off[v] / pe + 2 v, ceil(len / pe) + 1 words each
+  TPG_TRY(ws_reserve(ws, ws->pfx_pk, sizeof(uint64_t) * (ws->h_scalars[4] / pe + 2 * (int64_t)n + 4)));
+  TPG_TRY(ws_reserve(ws, ws->sfx_pk, sizeof(uint64_t) * (ws->h_scalars[5] / pe + 2 * (int64_t)n + 4)));
+  b.pfx_pk = ws->pfx_pk.as<uint64_t>();
+  b.sfx_pk = ws->sfx_pk.as<uint64_t>();
+  TPG_HIP(launch_pack_tables(n, b, eb, st));
   // the plain spliced entries only for the covering, which reads them
   if (greedy) TPG_TRY(ws_reserve(ws, ws->tp_vtx, sizeof(int32_t) * (tp_total + 1)));
-  const int pe = 64 / eb;
   TPG_TRY(ws_reserve(ws, ws->tp_pk, sizeof(uint64_t) * ((tp_total + pe - 1) / pe + 2 * np + 4)));
   TPG_HIP(launch_tp_write(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), np, b,
                           ws->tp_off.as<int64_t>(), greedy ? ws->tp_vtx.as<int32_t>() : nullptr,
@@ -1315,7 +1321,7 @@ void tpg_workspace_free(tpg_workspace* ws) {
                     &ws->mask1, &ws->ls, &ws->sub_cnt, &ws->pp_len,
                     &ws->leaf_by_rank, &ws->totals, &ws->cycles, &ws->scan_status,
                     &ws->scan_ctr, &ws->scalars, &ws->bfs_i32, &ws->pfx_off, &ws->sfx_off,
-                    &ws->pfx, &ws->sfx, &ws->tp_len, &ws->tp_off, &ws->tp_vtx, &ws->tp_key, &ws->tp_pk, &ws->idx0,
+                    &ws->pfx, &ws->sfx, &ws->pfx_pk, &ws->sfx_pk, &ws->tp_len, &ws->tp_off, &ws->tp_vtx, &ws->tp_key, &ws->tp_pk, &ws->idx0,
                     &ws->idx1, &ws->grp_cnt, &ws->rb0, &ws->rb1, &ws->keep_cnt, &ws->keep_len,
                     &ws->keep_pos, &ws->keep_voff, &ws->comp_cnt, &ws->lvl_comp, &ws->b_pp_off,
                     &ws->scan2_status, &ws->scalars2, &ws->digest, &ws->grp_key, &ws->grp_hist,

@@ -203,6 +203,8 @@ struct BfsOut {
   int32_t* cfirst;   // [n] v's tree children: bq[cfirst[v] .. cfirst[v] + ccnt[v]), ascending
   int32_t* ccnt;     // [n]
   int32_t* bq;       // [n] the search queue (graph-wide ids)
+  uint64_t* pfx_pk;  // prefix rows packed like the test paths (see k_pack_tables)
+  uint64_t* sfx_pk;  // suffix rows packed likewise
 };
 // What the test-path comparison reads: per test path kTpKeyWords 64-bit keys
 // (see k_tp_write) and, for the rare ties the keys leave, the entries.
@@ -210,7 +212,7 @@ constexpr int kTpKeyWords = 3;
 struct TpOrder {
   const int64_t* off;   // [n + 1] test-path offsets
   const uint64_t* key;  // [kTpKeyWords n]
-  const uint64_t* pk;   // the entries packed (see k_tp_pack)
+  const uint64_t* pk;   // the entries packed (see k_tp_write)
   int eb;               // bits per packed entry (entry + 1; 0 = past the end)
   int pe;               // packed entries per 64-bit word, 64 / eb
 };
@@ -231,6 +233,8 @@ hipError_t launch_tp_len(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n
 // writes the test paths packed (pk: (n_entries + pe - 1) / pe + 2 n_pp + 4
 // words, pe = 64 / eb), their comparison keys, idx[i] = i and, when tp_vtx
 // is not null, their plain entries
+// Packed prefix / suffix rows of every vertex (after the tables exist).
+hipError_t launch_pack_tables(int n, const BfsOut& b, int eb, hipStream_t st);
 hipError_t launch_tp_write(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp,
                            const BfsOut& b, const int64_t* tp_off, int32_t* tp_vtx,
                            uint64_t* key, uint64_t* pk, int eb, int32_t* idx, hipStream_t st);

@@ -329,19 +329,80 @@ __device__ __forceinline__ int64_t tp_pk_base(int64_t off, int64_t x, int pe) {
   return ((off + pe - 1) / pe + 2 * x + 1) & ~(int64_t)1;
 }
 
+// Packed prefix and suffix tables: row v holds v's prefix (suffix) entries
+// packed like the test paths' words (entry + 1 in eb bits, pe per word, first
+// one highest, 0 past the end), followed by one zero word.  Row v starts at
+// word pfx_off[v] / pe + 2 v (sfx_off for the suffix rows), which leaves
+// every row its ceil(len / pe) + 1 words without a scan.
+__device__ __forceinline__ int64_t tbl_pk_base(int64_t off, int v, int pe) {
+  return off / pe + 2 * (int64_t)v;
+}
+
+__global__ void k_pack_tables(int n, BfsOut b, int eb) {
+  const int v = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (v >= n) return;
+  const int pe = 64 / eb;
+#pragma unroll 1
+  for (int side = 0; side < 2; ++side) {
+    const int64_t* off = side ? b.sfx_off : b.pfx_off;
+    const int32_t* tbl = side ? b.sfx : b.pfx;
+    uint64_t* pk = side ? b.sfx_pk : b.pfx_pk;
+    const int64_t o = off[v];
+    const int len = (int)(off[v + 1] - o);
+    const int64_t base = tbl_pk_base(o, v, pe);
+    const int nw = (len + pe - 1) / pe + 1;
+    for (int q = 0; q < nw; ++q) {
+      uint64_t w = 0;
+      for (int j = 0; j < pe; ++j) {
+        const int k = q * pe + j;
+        w = (w << eb) | (k < len ? (uint64_t)(tbl[o + k] + 1) : 0ull);
+      }
+      pk[base + q] = w;
+    }
+  }
+}
+
+hipError_t launch_pack_tables(int n, const BfsOut& b, int eb, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (eb < 1 || eb > 32) return hipErrorInvalidValue;
+  k_pack_tables<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(n, b, eb);
+  return hipGetLastError();
+}
+
 // A workgroup splices kSplicePaths consecutive test paths: their layout goes
 // to LDS, then each thread builds one packed word (pe consecutive entries;
-// the words of the paths are one flat range) and the first entry of it that
-// leaves the tree path records its position; finally one thread per path
-// builds its key.  The plain entries are written only when asked for (tp_vtx
-// not null): the comparisons read the packed words and the kept paths are
-// unpacked from them when gathered.
+// the words of the paths are one flat range).  A word that lies wholly in
+// the prefix is the same word of the first vertex's packed prefix row; one
+// that lies wholly in the suffix is cut from two consecutive words of the
+// last vertex's packed suffix row; only the words that hold prime-path
+// entries are built entry by entry (the keys come from k_tp_keys).  The
+// plain entries are written only when asked for (tp_vtx not null, every
+// word then built entry by entry): the comparisons read the packed words and
+// the kept paths are unpacked from them when gathered.
 constexpr int kSplicePaths = 64;
 
 struct SpliceRow {
   int64_t o0, p0, s0;  // prime-path entries, prefix table, suffix table
   int32_t lp, lq, ls;  // prefix, prime-path and suffix lengths
+  int32_t v1, vk;      // first and last vertex of the prime path
 };
+
+// Layout of test path i: where its prefix, prime-path and suffix entries are.
+__device__ __forceinline__ SpliceRow splice_row(const int64_t* pp_off, const int32_t* pp_vtx,
+                                                const BfsOut& b, int64_t i) {
+  const int64_t o0 = pp_off[i], o1 = pp_off[i + 1];
+  const int v1 = pp_vtx[o0], vk = pp_vtx[o1 - 1];
+  SpliceRow r;
+  r.o0 = o0;
+  r.p0 = b.pfx_off[v1];
+  r.lp = (int32_t)(b.pfx_off[v1 + 1] - r.p0);
+  r.lq = (int32_t)(o1 - o0);
+  r.s0 = b.sfx_off[vk];
+  r.ls = (int32_t)(b.sfx_off[vk + 1] - r.s0);
+  r.v1 = v1;
+  r.vk = vk;
+  return r;
+}
 
 __device__ __forceinline__ int splice_entry(const SpliceRow& r, const int32_t* pp_vtx,
                                             const BfsOut& b, int64_t k) {
@@ -357,27 +418,16 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
   __shared__ SpliceRow s_row[kSplicePaths];
   __shared__ int64_t s_w[kSplicePaths + 1];  // entry offsets
   __shared__ int64_t s_a[kSplicePaths + 1];  // packed-word offsets
-  __shared__ int32_t s_first[kSplicePaths];
   const int pe = 64 / eb;
   const int tid = (int)threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.x * kSplicePaths;
   const int cnt = (int)(n_pp - i0 < kSplicePaths ? n_pp - i0 : kSplicePaths);
   if (tid < cnt) {
     const int64_t i = i0 + tid;
-    const int64_t o0 = pp_off[i], o1 = pp_off[i + 1];
-    const int v1 = pp_vtx[o0], vk = pp_vtx[o1 - 1];
-    SpliceRow r;
-    r.o0 = o0;
-    r.p0 = b.pfx_off[v1];
-    r.lp = (int32_t)(b.pfx_off[v1 + 1] - r.p0);
-    r.lq = (int32_t)(o1 - o0);
-    r.s0 = b.sfx_off[vk];
-    r.ls = (int32_t)(b.sfx_off[vk + 1] - r.s0);
-    s_row[tid] = r;
+    s_row[tid] = splice_row(pp_off, pp_vtx, b, i);
     const int64_t o = tp_off[i];
     s_w[tid] = o;
     s_a[tid] = tp_pk_base(o, i, pe);
-    s_first[tid] = r.lp + r.lq + r.ls;
     idx[i] = (int32_t)i;
   }
   if (tid == cnt) {
@@ -396,44 +446,80 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
     }
     const SpliceRow r = s_row[lo];
     const int len = r.lp + r.lq + r.ls;
-    const int k0 = (int)(wi - s_a[lo]) * pe;
+    const int q = (int)(wi - s_a[lo]);
+    const int k0 = q * pe;
     if (k0 >= len) continue;  // slack between two paths
-    int prev = k0 > 0 ? splice_entry(r, pp_vtx, b, k0 - 1) : -1;
-    int leave = len;
     uint64_t w = 0;
-    for (int q0 = 0; q0 < pe; q0 += 8) {  // eight entries at a time, loads in flight together
-      int x[8], px[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int k = k0 + q0 + j;
-        x[j] = q0 + j < pe && k < len ? splice_entry(r, pp_vtx, b, k) : -1;
+    if (!tp_vtx && k0 + pe <= r.lp) {
+      w = b.pfx_pk[tbl_pk_base(r.p0, r.v1, pe) + q];
+    } else if (!tp_vtx && k0 >= r.lp + r.lq) {
+      const int j0 = k0 - r.lp - r.lq;  // first suffix entry of the word
+      const int sq = j0 / pe, sr = j0 - sq * pe;
+      const uint64_t* row = b.sfx_pk + tbl_pk_base(r.s0, r.vk, pe);
+      const uint64_t A = row[sq];
+      if (sr == 0) {
+        w = A;
+      } else {
+        // entries sr .. pe-1 of A, then entries 0 .. sr-1 of the next word
+        const int hb = (pe - sr) * eb;  // bits of A's entries sr .. pe-1
+        const uint64_t B = row[sq + 1];
+        w = ((A & ((1ull << hb) - 1)) << (sr * eb)) | (B >> hb);
       }
+    } else {
+      for (int q0 = 0; q0 < pe; q0 += 8) {  // eight entries at a time, loads in flight together
+        int x[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) px[j] = x[j] >= 0 ? b.parent[x[j]] : -1;
+        for (int j = 0; j < 8; ++j) {
+          const int k = k0 + q0 + j;
+          x[j] = q0 + j < pe && k < len ? splice_entry(r, pp_vtx, b, k) : -1;
+        }
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int k = k0 + q0 + j;
-        if (q0 + j < pe) {
-          uint64_t code = 0;
-          if (k < len) {
-            if (tp_vtx) tp_vtx[s_w[lo] + k] = x[j];
-            if (k > r.lp && leave == len && px[j] != prev) leave = k;
-            prev = x[j];
-            code = (uint64_t)(x[j] + 1);
+        for (int j = 0; j < 8; ++j) {
+          const int k = k0 + q0 + j;
+          if (q0 + j < pe) {
+            uint64_t code = 0;
+            if (k < len) {
+              if (tp_vtx) tp_vtx[s_w[lo] + k] = x[j];
+              code = (uint64_t)(x[j] + 1);
+            }
+            w = (w << eb) | code;
           }
-          w = (w << eb) | code;
         }
       }
     }
     pk[wi] = w;
-    if (leave < len) atomicMin(&s_first[lo], (int32_t)leave);
   }
-  __syncthreads();
-  if (tid < cnt) {
-    const int64_t i = i0 + tid;
-    const SpliceRow r = s_row[tid];
+}
+
+// The comparison keys of test path i (see above): where it leaves the BFS
+// tree (the first entry after the prime path's first vertex whose tree
+// parent is not the entry before it), that tree path's preorder range and
+// depth, the entry after it and the split rank, and the next pe entries.
+// One thread per test path.
+__global__ __launch_bounds__(kBlock) void k_tp_keys(const int64_t* pp_off, const int32_t* pp_vtx,
+                                                    int64_t n_pp, BfsOut b, uint64_t* key, int eb) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n_pp) {
+    const SpliceRow r = splice_row(pp_off, pp_vtx, b, i);
     const int len = r.lp + r.lq + r.ls;
-    const int first = s_first[tid];
+    // where the path leaves the BFS tree: entries up to the prime path's
+    // first vertex are its tree path; scan on, eight entries at a time
+    int first = len;
+    int prev = r.v1;
+    for (int k0 = r.lp + 1; k0 < len && first == len; k0 += 8) {
+      int x[8], px[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) x[j] = k0 + j < len ? splice_entry(r, pp_vtx, b, k0 + j) : -1;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) px[j] = x[j] >= 0 ? b.parent[x[j]] : -1;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (k0 + j < len && first == len) {
+          if (px[j] != prev) first = k0 + j;
+          prev = x[j];
+        }
+      }
+    }
     const bool has_e = first < len;
     const int w = splice_entry(r, pp_vtx, b, first - 1);
     const int ev = has_e ? splice_entry(r, pp_vtx, b, first) : 0;
@@ -452,14 +538,13 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
     } else {
       split = prew + 1;
     }
-    const int v1 = splice_entry(r, pp_vtx, b, r.lp);
     uint64_t k3 = 0;
     for (int q = first + 1; q < first + 1 + 64 / eb; ++q)
       k3 = (k3 << eb) | (q < len ? (uint64_t)(splice_entry(r, pp_vtx, b, q) + 1) : 0ull);
     uint64_t* kk = key + (int64_t)kTpKeyWords * i;
     kk[0] = (uint64_t)prew | ((uint64_t)pendw << 18) | ((uint64_t)(first - 1) << 36) |
             ((uint64_t)(has_e ? 1 : 0) << 49);
-    kk[1] = (uint64_t)(uint32_t)ev | ((uint64_t)split << 17) | ((uint64_t)(uint32_t)b.pre[v1] << 35);
+    kk[1] = (uint64_t)(uint32_t)ev | ((uint64_t)split << 17) | ((uint64_t)(uint32_t)b.pre[r.v1] << 35);
     kk[2] = k3;
   }
 }
@@ -471,6 +556,8 @@ hipError_t launch_tp_write(const int64_t* pp_off, const int32_t* pp_vtx, int64_t
   if (eb < 1 || eb > 32) return hipErrorInvalidValue;
   k_tp_write<<<(unsigned)((n_pp + kSplicePaths - 1) / kSplicePaths), kBlock, 0, st>>>(
       pp_off, pp_vtx, n_pp, b, tp_off, tp_vtx, key, pk, eb, idx);
+  k_tp_keys<<<(unsigned)((n_pp + kBlock - 1) / kBlock), kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, b,
+                                                                        key, eb);
   return hipGetLastError();
 }
 
@@ -763,29 +850,31 @@ hipError_t launch_gather(const int64_t* tp_off, const int32_t* tp_vtx, const int
 }
 
 // A workgroup writes the kept paths among kGatherPaths consecutive sorted
-// positions from their packed words: the paths' first words, lengths and
-// destinations go to LDS, then each thread unpacks one word (pe entries) of
-// the flat range of the kept paths' words.  The kept paths are contiguous in
-// the output, so when the workgroup's entries fit kGatherStage they are
-// unpacked into LDS and stored by consecutive threads (whole lines); a
-// larger range is stored straight from the words.
-constexpr int kGatherPaths = 32;
-constexpr int kGatherStage = 4096;  // int32 entries staged in LDS (16 KiB)
+// positions from their packed words.  The kept paths are contiguous in the
+// output, so the workgroup's output is one range [d0, d0 + tot): the paths'
+// first words, lengths and entry counts go to LDS, then each thread produces
+// four consecutive entries of the range at a time (aligned to 16 bytes of
+// the output array) and stores them with one 16-byte store, so a wave writes
+// 1 KiB of consecutive addresses per instruction.  The aligned groups at the
+// two ends of the range are shared with the neighbouring workgroups' ranges;
+// there only the entries inside the range are stored, one by one.  Each
+// entry is read out of its packed word (pe entries of eb bits, first one
+// highest); neighbouring threads read the same words, which the cache serves.
+constexpr int kGatherPaths = 64;
 
+template <int EB>
 __global__ __launch_bounds__(kBlock) void k_unpack_gather(const int64_t* tp_off, const uint64_t* pk,
-                                                          int eb, const int32_t* idx, int64_t n,
+                                                          const int32_t* idx, int64_t n,
                                                           const int64_t* keep_pos,
                                                           const int64_t* keep_voff,
                                                           const int64_t* keep_len,
                                                           int64_t* out_off, int32_t* out_vtx) {
   __shared__ int64_t s_src[kGatherPaths];
   __shared__ int32_t s_cum[kGatherPaths + 1];  // entries before each kept path
-  __shared__ int32_t s_cw[kGatherPaths + 1];   // words before each kept path
-  __shared__ int32_t s_stage[kGatherStage];
   __shared__ int64_t s_dst0;
   __shared__ int32_t s_w[kBlock / 64];
-  const int pe = 64 / eb;
-  const uint64_t emask = (1ull << eb) - 1;
+  constexpr int pe = 64 / EB;  // a compile-time divisor: no division per entry
+  constexpr uint64_t emask = (1ull << EB) - 1;
   const int tid = (int)threadIdx.x;
   const int64_t k0 = (int64_t)blockIdx.x * kGatherPaths;
   const int cnt = (int)(n - k0 < kGatherPaths ? n - k0 : kGatherPaths);
@@ -793,6 +882,7 @@ __global__ __launch_bounds__(kBlock) void k_unpack_gather(const int64_t* tp_off,
   if (tid < cnt) {
     const int64_t k = k0 + tid;
     len = (int32_t)keep_len[k];  // 0 for a duplicate (every kept path has >= 1 entry)
+    s_src[tid] = 0;
     if (len) {
       const int64_t a = idx[k];
       s_src[tid] = tp_pk_base(tp_off[a], a, pe);
@@ -800,48 +890,44 @@ __global__ __launch_bounds__(kBlock) void k_unpack_gather(const int64_t* tp_off,
     }
   }
   if (tid == 0) s_dst0 = keep_voff[k0];
-  int32_t tot, totw;
+  int32_t tot;
   const int32_t ex = block_excl_scan<kBlock, int32_t>(len, tot, s_w);
-  const int32_t exw = block_excl_scan<kBlock, int32_t>((len + pe - 1) / pe, totw, s_w);
-  if (tid < cnt) {
-    s_cum[tid] = ex;
-    s_cw[tid] = exw;
-  }
-  if (tid == 0) {
-    s_cum[cnt] = tot;
-    s_cw[cnt] = totw;
-  }
+  if (tid < cnt) s_cum[tid] = ex;
+  if (tid == 0) s_cum[cnt] = tot;
   __syncthreads();
-  const int64_t d0 = s_dst0;
-  const bool staged = tot <= kGatherStage;  // the same for every thread
-  for (int32_t wi = tid; wi < totw; wi += kBlock) {
+  if (tot == 0) return;
+  const int64_t d0 = s_dst0, d1 = d0 + tot;
+  const int64_t a0 = d0 & ~(int64_t)3;  // first 16-byte group touching the range
+  const int64_t ngroups = (d1 - a0 + 3) >> 2;
+  for (int64_t gi = tid; gi < ngroups; gi += kBlock) {
+    const int64_t g0 = a0 + 4 * gi;
+    // kept path holding the group's first entry inside the range
+    const int32_t e0 = (int32_t)((g0 > d0 ? g0 : d0) - d0);
     int lo = 0, hi = cnt - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (s_cw[mid] <= wi) lo = mid; else hi = mid - 1;
+      if (s_cum[mid] <= e0) lo = mid; else hi = mid - 1;
     }
-    const int q = wi - s_cw[lo];           // word of the path
-    const int e = q * pe;                  // its first entry
-    const int m = s_cum[lo + 1] - s_cum[lo] - e;
-    const int mm = m < pe ? m : pe;        // entries in this word
-    const uint64_t w = pk[s_src[lo] + q];
-    const int at = s_cum[lo] + e;          // position in the workgroup's range
-    for (int i0 = 0; i0 < mm; i0 += 8) {
+    int32_t x[4];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        if (i0 + j < mm) {
-          const int32_t x = (int32_t)((w >> ((pe - 1 - i0 - j) * eb)) & emask) - 1;
-          if (staged)
-            s_stage[at + i0 + j] = x;
-          else
-            out_vtx[d0 + at + i0 + j] = x;
-        }
+    for (int j = 0; j < 4; ++j) {
+      const int64_t gpos = g0 + j;
+      x[j] = 0;
+      if (gpos >= d0 && gpos < d1) {
+        const int32_t e = (int32_t)(gpos - d0);
+        while (e >= s_cum[lo + 1]) ++lo;  // next kept path (duplicates have no entries)
+        const int32_t r = e - s_cum[lo];
+        const uint64_t w = pk[s_src[lo] + r / pe];
+        x[j] = (int32_t)((w >> ((pe - 1 - r % pe) * EB)) & emask) - 1;
       }
     }
-  }
-  if (staged) {
-    __syncthreads();
-    for (int32_t e = tid; e < tot; e += kBlock) out_vtx[d0 + e] = s_stage[e];
+    if (g0 >= d0 && g0 + 4 <= d1) {
+      *reinterpret_cast<int4*>(out_vtx + g0) = make_int4(x[0], x[1], x[2], x[3]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (g0 + j >= d0 && g0 + j < d1) out_vtx[g0 + j] = x[j];
+    }
   }
 }
 
@@ -850,9 +936,22 @@ hipError_t launch_unpack_gather(const int64_t* tp_off, const uint64_t* pk, int e
                                 const int64_t* keep_voff, const int64_t* keep_len,
                                 int64_t* out_off, int32_t* out_vtx, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  if (eb < 1 || eb > 32) return hipErrorInvalidValue;
-  k_unpack_gather<<<(unsigned)((n + kGatherPaths - 1) / kGatherPaths), kBlock, 0, st>>>(
-      tp_off, pk, eb, idx, n, keep_pos, keep_voff, keep_len, out_off, out_vtx);
+  const unsigned grid = (unsigned)((n + kGatherPaths - 1) / kGatherPaths);
+#define TPG_UNPACK_CASE(E)                                                                  \
+  case E:                                                                                   \
+    k_unpack_gather<E><<<grid, kBlock, 0, st>>>(tp_off, pk, idx, n, keep_pos, keep_voff,    \
+                                                keep_len, out_off, out_vtx);                \
+    break;
+  switch (eb) {
+    TPG_UNPACK_CASE(1) TPG_UNPACK_CASE(2) TPG_UNPACK_CASE(3) TPG_UNPACK_CASE(4)
+    TPG_UNPACK_CASE(5) TPG_UNPACK_CASE(6) TPG_UNPACK_CASE(7) TPG_UNPACK_CASE(8)
+    TPG_UNPACK_CASE(9) TPG_UNPACK_CASE(10) TPG_UNPACK_CASE(11) TPG_UNPACK_CASE(12)
+    TPG_UNPACK_CASE(13) TPG_UNPACK_CASE(14) TPG_UNPACK_CASE(15) TPG_UNPACK_CASE(16)
+    TPG_UNPACK_CASE(17) TPG_UNPACK_CASE(18)
+    default:
+      return hipErrorInvalidValue;  // more than 2^18 - 1 vertices in one union
+  }
+#undef TPG_UNPACK_CASE
   return hipGetLastError();
 }
 
