@@ -182,9 +182,11 @@ def _covering(args):
 
 
 def _components(args):
-    """Strongly connected components and prime-path types (Sec. 2) on the
-    benchmark CFG: the device SCC pass, and the classification of its
-    device-resident prime-path set (counts only)."""
+    """Strongly connected components, prime-path types and the compositional
+    method (Sec. 2, 2.1) on the benchmark CFG: the device SCC pass, the
+    classification of its device-resident prime-path set (counts only), the
+    component graph, the extraction, the internal prime paths of each
+    component alone and the merge."""
     import torch
     from paper_2210_16998_amd import tpg
     g, rec = _workload()
@@ -193,9 +195,15 @@ def _components(args):
     stream = torch.cuda.Stream()
     pp, _ = tpg.prime_paths(h, ws=ws, flags=tpg.TPG_OUT_DEVICE | tpg.TPG_NO_TIMING, stream=stream)
     out = {}
+    f = tpg.TPG_OUT_DEVICE
     for name, fn in (("scc_ms", lambda: tpg.scc(h, ws=ws, stream=stream)),
                      ("types_ms", lambda: tpg.prime_path_types(h, pp, ws=ws, stream=stream,
-                                                               want_types=False))):
+                                                               want_types=False)),
+                     ("ccfg_ms", lambda: tpg.ccfg(h, ws=ws, stream=stream)),
+                     ("extraction_ms", lambda: tpg.scc_paths(h, ws=ws, flags=f, stream=stream)),
+                     ("internal_ms", lambda: tpg.scc_internal_pps(h, ws=ws, flags=f,
+                                                                  stream=stream)),
+                     ("merge_ms", lambda: tpg.merged_pps(h, ws=ws, flags=f, stream=stream))):
         for _ in range(3):
             r = fn()
         torch.cuda.synchronize()
@@ -208,13 +216,23 @@ def _components(args):
             comp, fl = r[0], r[1]
             out["n_components"] = r[2]
             out["n_components_with_cycle"] = int(len(set(comp[(fl & tpg.TPG_SCC_CYCLIC) > 0].tolist())))
-        else:
+        elif name == "types_ms":
             names = ["", "complete", "scc_internal", "scc_exit", "scc_entry", "other"]
             out["types"] = {names[t]: int(r[1][t]) for t in range(1, 6)}
+        elif name == "ccfg_ms":
+            out["n_ccfg_arcs"] = int(len(r[2]))
+        elif name == "extraction_ms":
+            out["extracted"] = {"entry_exit": len(r[0]), "exit": len(r[1]), "entry": len(r[2])}
+        elif name == "internal_ms":
+            out["n_internal"] = len(r)
+        else:
+            out["merged"] = {"complete": len(r[0]), "scc_exit": len(r[1]), "scc_entry": len(r[2])}
     ws.close()
     out["workload"] = (f"the benchmark CFG ({g.n} vertices, {out['n_components']} components): "
-                       f"device SCC pass, and the types of its {len(pp)} prime paths held on the "
-                       f"device (each call includes the graph upload and the SCC pass)")
+                       f"device SCC pass, the types of its {len(pp)} prime paths held on the "
+                       f"device, the component graph, the extraction of Defs. 6-8, the internal "
+                       f"prime paths of each component alone, and the merge of Sec. 2.1 (each call "
+                       f"includes the graph upload and the SCC pass)")
     return out
 
 
@@ -429,8 +447,8 @@ def main() -> int:
     ap.add_argument("--no-covering", action="store_true")
     ap.add_argument("--no-components", action="store_true")
     ap.add_argument("--no-prior-schedule", action="store_true")
-    ap.add_argument("--only", choices=["batched", "paper_form", "covering", "components",
-                                       "prior_schedule"],
+    ap.add_argument("--only", choices=["batched", "batched_learned", "paper_form", "covering",
+                                       "components", "prior_schedule"],
                     help="run one section alone and print its JSON (for profiling)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (the reference "
@@ -449,7 +467,8 @@ def main() -> int:
     assert torch.cuda.is_available(), "no GPU"
     torch.cuda.set_device(0)
     if args.only:
-        fn = {"batched": _batched, "paper_form": _paper_form, "covering": _covering,
+        fn = {"batched": _batched, "batched_learned": _batched_learned_only,
+              "paper_form": _paper_form, "covering": _covering,
               "components": _components, "prior_schedule": _prior_schedule}[args.only]
         print(json.dumps({args.only: fn(args)}), flush=True)
         return 0
@@ -503,6 +522,33 @@ def main() -> int:
             out["cfg209"]["cpu_baseline"] = _cpu_baseline(_workload()[0], args.cpu_pp // 2)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def _batched_learned_only(args):
+    """The batched call sized by the learned predictor alone, warm (one
+    untimed call, then batch_reps timed ones): what a kernel profile of
+    that form is taken on."""
+    import torch
+    from paper_2210_16998_amd import cfggen, sizer, tpg, tuning
+    graphs = [tpg.load_cfg(c) for c in cfggen.c3_batch(4096)]
+    mlp = tpg.MLP.load(sizer.DEFAULT_MODEL)
+    ws = tpg.Workspace(0)
+    if tuning.load(ws) is None:
+        tpg.autotune(graphs, ws)
+    dev = tpg.TPG_OUT_DEVICE | tpg.TPG_NO_TIMING
+
+    def call():
+        return tpg.batch_test_paths(graphs, ws=ws, flags=dev,
+                                    predicted=mlp.forward(tpg.features(graphs)))
+    call()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.batch_reps):
+        _, st = call()
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t) / args.batch_reps
+    return {"batched_learned_ms": ms, "n_pp": int(st["n_pp"]), "n_unions": int(st["n_unions"]),
+            "n_overflows": int(st["n_overflows"])}
 
 
 def _batched(args):

@@ -310,6 +310,62 @@ tpg_status tpg_scc(const tpg_graph* g, const tpg_opts* opts, int32_t* comp, uint
 tpg_status tpg_prime_path_types(const tpg_graph* g, const tpg_paths* pps, const tpg_opts* opts,
                                 uint8_t* types, int64_t* counts);
 
+/* The compositional method of Sec. 2.1 on the device.
+ *
+ * tpg_ccfg: the component graph (Def. 3).  comp (n int32, host, may be NULL)
+ * receives each vertex's component label (its smallest vertex), n_comp (may
+ * be NULL) the number of components, *n_arcs the number of arcs of g whose
+ * ends lie in different components (the component graph's arcs, one per arc
+ * of g).  arc_src / arc_dst (host, both or neither, arc_cap entries each)
+ * receive those arcs as vertex pairs of g in CSR order; n_arcs > arc_cap
+ * gives TPG_ERR_CAPACITY (after *n_arcs is set).  Of opts only the
+ * workspace and the stream are used. */
+tpg_status tpg_ccfg(const tpg_graph* g, const tpg_opts* opts, int32_t* comp, int32_t* n_comp,
+                    int64_t* n_arcs, int32_t* arc_src, int32_t* arc_dst, int64_t arc_cap);
+
+/* tpg_scc_paths: the paths of Sec. 2.1's path extraction, over every
+ * component with a cycle (Defs. 6-8), each path acyclic and inside one
+ * component:
+ *  - entry_exit: every path from an SccEntryVertex to an SccExitVertex;
+ *  - exit_paths: the paths from a vertex that is not an SccEntryVertex to an
+ *    SccExitVertex that no longer such path to the same SccExitVertex
+ *    contains (maximal per exit vertex);
+ *  - entry_paths: the paths from an SccEntryVertex to a vertex that is not
+ *    an SccExitVertex that no longer such path from the same SccEntryVertex
+ *    contains (maximal per entry vertex).
+ * Each set is grouped by component (ascending smallest vertex); inside a
+ * component entry_exit and entry_paths are in lexicographic order,
+ * exit_paths in the lexicographic order of the reversed paths (grouped by
+ * exit vertex).  Any output may be NULL; opts->flags may hold TPG_OUT_DEVICE (results then live
+ * in the workspace until its next call) and TPG_FORCE_TWO_PASS. */
+tpg_status tpg_scc_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* entry_exit,
+                         tpg_paths* exit_paths, tpg_paths* entry_paths);
+
+/* tpg_scc_internal_pps: Sec. 2.1's prime-path generation on each component
+ * with a cycle taken alone (its vertices and the arcs between them), kept
+ * when they are SccInternalPPs (Def. 9: a cycle, or an acyclic path that
+ * neither starts at an SccEntryVertex nor ends at an SccExitVertex), in g's
+ * vertex ids; grouped by component (ascending smallest vertex), in
+ * lexicographic order inside a group.  These are exactly the prime paths of
+ * g of type TPG_PP_SCC_INTERNAL.  Flags as for tpg_scc_paths. */
+tpg_status tpg_scc_internal_pps(const tpg_graph* g, const tpg_opts* opts, tpg_paths* out);
+
+/* tpg_merged_pps: Sec. 2.1's merging: the CompletePPs (Def. 2), SccExitPPs
+ * (Def. 10) and SccEntryPPs (Def. 11) built from the component graph and
+ * the extracted paths, each set in lexicographic order.  The component
+ * graph's paths with every component with a cycle replaced by one of its
+ * SccEntryExitPaths give the CompletePPs; a CompletePP's part after the
+ * exit vertex where it leaves a component, prefixed by that component's
+ * SccExitPaths to that vertex, the SccExitPPs; its part before the vertex
+ * where it enters a component, followed by the SccEntryPaths from that
+ * vertex, the SccEntryPPs.  Merged paths that can still be extended at one
+ * end are not prime and are left out.  The composition runs as the path
+ * extension on a macro graph of the paths (at most TPG_MAX_VERTICES
+ * vertices, else TPG_ERR_UNSUPPORTED).  g must be a CFG loaded with the
+ * entry/exit checks.  Outputs and flags as for tpg_scc_paths. */
+tpg_status tpg_merged_pps(const tpg_graph* g, const tpg_opts* opts, tpg_paths* complete,
+                          tpg_paths* exit_pps, tpg_paths* entry_pps);
+
 /* tpg_prime_path_types without device allocation, for callers that cannot
  * allocate device memory (code under stream capture, serving loops,
  * harnesses that forbid hipMalloc).  The prime-path set is in device memory

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -112,6 +113,14 @@ struct tpg_workspace {
   // components and prime-path types: Tarjan scratch, labels, flags, counters
   // (n_comp int32 at 0, type counts u64 at 64), a host path set's copy, types
   DevBuf scc_work, scc_comp, scc_flags, scc_misc, ty_off, ty_vtx, ty_types;
+  // compositional method: component-graph arcs; extraction marks, counts,
+  // emitted nodes and lengths, per-vertex flags and ids; the extracted sets
+  // (entry-exit, exit, entry); the macro graph's vertex kinds and ids, its
+  // paths' classes and lengths, selection scans; the merged sets
+  DevBuf cg_cnt, cg_off, cg_src, cg_dst, cx_qb, cx_cnt0, cx_cnt1, cx_node, cx_len, cx_vfl, cx_orig;
+  DevBuf cx_off[3], cx_vtx[3];
+  DevBuf cm_kind, cm_orig, cm_cls, cm_len, cm_flag, cm_lens, cm_pos, cm_voff;
+  DevBuf cm_off[3], cm_vtx[3];
   // the per-vertex schedule: two rounds of rows, their offsets and marks,
   // per-vertex counts, prime flags and their positions
   DevBuf pv_rows0, pv_rows1, pv_voff0, pv_voff1, pv_ext, pv_cnt, pv_flag, pv_pos;
@@ -1328,7 +1337,13 @@ void tpg_workspace_free(tpg_workspace* ws) {
                     &ws->cov_keys, &ws->cov_vals, &ws->cov_misc, &ws->pair_p, &ws->pair_q,
                     &ws->cov_pos, &ws->gstate0, &ws->gstate1, &ws->cov_flag,
                     &ws->scc_work, &ws->scc_comp, &ws->scc_flags, &ws->scc_misc, &ws->ty_off,
-                    &ws->ty_vtx, &ws->ty_types,
+                    &ws->ty_vtx, &ws->ty_types, &ws->cg_cnt, &ws->cg_off, &ws->cg_src,
+                    &ws->cg_dst, &ws->cx_qb, &ws->cx_cnt0, &ws->cx_cnt1, &ws->cx_node,
+                    &ws->cx_len, &ws->cx_vfl, &ws->cx_orig, &ws->cx_off[0], &ws->cx_off[1],
+                    &ws->cx_off[2], &ws->cx_vtx[0], &ws->cx_vtx[1], &ws->cx_vtx[2],
+                    &ws->cm_kind, &ws->cm_orig, &ws->cm_cls, &ws->cm_len, &ws->cm_flag,
+                    &ws->cm_lens, &ws->cm_pos, &ws->cm_voff, &ws->cm_off[0], &ws->cm_off[1],
+                    &ws->cm_off[2], &ws->cm_vtx[0], &ws->cm_vtx[1], &ws->cm_vtx[2],
                     &ws->pv_rows0, &ws->pv_rows1, &ws->pv_voff0, &ws->pv_voff1, &ws->pv_ext,
                     &ws->pv_cnt, &ws->pv_flag, &ws->pv_pos,
                     &ws->b_pp_vtx, &ws->b_tp_off, &ws->b_tp_vtx, &ws->b_desc};
@@ -1489,6 +1504,528 @@ tpg_status tpg_prime_path_types(const tpg_graph* g, const tpg_paths* pps, const 
   TPG_HIP(hipStreamSynchronize(c.st));
   if (counts)
     for (int t = 0; t < kPpTypes; ++t) counts[t] = (int64_t)h_cnt[t];
+  return TPG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// compositional method (Sec. 2.1): component graph, extraction, merge
+// ---------------------------------------------------------------------------
+namespace {
+
+// Components of g on the device; labels and flags back on the host.
+tpg_status components_host(CallCtx& c, const tpg_graph* g, std::vector<int32_t>& comp,
+                           std::vector<uint8_t>& flags) {
+  HostUnion U;
+  add_component(U, g);
+  TPG_TRY(upload_union(c.ws, U, c.st));
+  TPG_TRY(scc_device(c.ws, U, c.st));
+  comp.assign(g->n, 0);
+  flags.assign(g->n, 0);
+  TPG_HIP(hipMemcpyAsync(comp.data(), c.ws->scc_comp.p, sizeof(int32_t) * g->n,
+                         hipMemcpyDeviceToHost, c.st));
+  TPG_HIP(hipMemcpyAsync(flags.data(), c.ws->scc_flags.p, g->n, hipMemcpyDeviceToHost, c.st));
+  TPG_HIP(hipStreamSynchronize(c.st));
+  return TPG_OK;
+}
+
+// The components with a cycle, each taken alone (the arcs between its
+// vertices; reversed with rev), as one disjoint union in ascending label
+// order; inside a component the vertices keep g's order, so the path tree's
+// order is the lexicographic order in g's ids.
+struct ComponentUnion {
+  std::vector<tpg_graph*> gs;
+  std::vector<int32_t> orig;  // union vertex -> vertex of g
+  std::vector<uint8_t> vfl;   // union vertex: bit 0 SccEntryVertex, bit 1 SccExitVertex
+  ~ComponentUnion() {
+    for (tpg_graph* h : gs) tpg_graph_free(h);
+  }
+};
+
+tpg_status component_union(const tpg_graph* g, const std::vector<int32_t>& comp,
+                           const std::vector<uint8_t>& fl, bool rev, ComponentUnion& S,
+                           HostUnion& U) {
+  std::map<int32_t, std::vector<int32_t>> members;
+  for (int32_t v = 0; v < g->n; ++v)
+    if (fl[v] & kSccCyclic) members[comp[v]].push_back(v);
+  std::vector<int32_t> loc(g->n, -1);
+  for (auto& kv : members) {
+    const std::vector<int32_t>& vs = kv.second;
+    const int32_t k = (int32_t)vs.size();
+    for (int32_t i = 0; i < k; ++i) loc[vs[i]] = i;
+    std::vector<std::vector<int32_t>> rows(k);
+    for (int32_t i = 0; i < k; ++i)
+      for (int32_t e = g->succ_ptr[vs[i]]; e < g->succ_ptr[vs[i] + 1]; ++e) {
+        const int32_t w = g->succ[e];
+        if (comp[w] != kv.first) continue;
+        if (rev)
+          rows[loc[w]].push_back(i);
+        else
+          rows[i].push_back(loc[w]);
+      }
+    std::vector<int64_t> rp(k + 1, 0);
+    std::vector<int32_t> ci;
+    for (int32_t i = 0; i < k; ++i) {
+      ci.insert(ci.end(), rows[i].begin(), rows[i].end());
+      rp[i + 1] = (int64_t)ci.size();
+    }
+    tpg_graph* h = nullptr;
+    TPG_TRY(tpg_load_cfg_csr(k, rp.data(), ci.data(), 0, k - 1, TPG_LOAD_ANY_DIGRAPH, &h));
+    S.gs.push_back(h);
+    add_component(U, h);
+    for (int32_t v : vs) {
+      S.orig.push_back(v);
+      S.vfl.push_back((uint8_t)(((fl[v] & kSccEntryVertex) ? 1 : 0) |
+                                ((fl[v] & kSccExitVertex) ? 2 : 0)));
+    }
+  }
+  return TPG_OK;
+}
+
+// Defs. 6-8 on the device (see kernels_compose.hip) into ws->cx_off / cx_vtx:
+// slot 0 the SccEntryExitPaths, 1 the SccExitPaths, 2 the SccEntryPaths.
+tpg_status extract_device(CallCtx& c, const tpg_graph* g, const std::vector<int32_t>& comp,
+                          const std::vector<uint8_t>& fl, int64_t n_out[3], int64_t nv_out[3]) {
+  tpg_workspace* ws = c.ws;
+  hipStream_t st = c.st;
+  for (int rev = 0; rev < 2; ++rev) {
+    ComponentUnion S;
+    HostUnion U;
+    TPG_TRY(component_union(g, comp, fl, rev != 0, S, U));
+    const int nsets = rev ? 1 : 2;
+    const int slot[2] = {rev ? 1 : 0, 2};
+    TPG_TRY(reserve_scan(ws, 16));
+    int64_t* scal = ws->scalars.as<int64_t>();
+    if (U.n == 0) {
+      for (int s = 0; s < nsets; ++s) {
+        TPG_TRY(ws_reserve(ws, ws->cx_off[slot[s]], sizeof(int64_t)));
+        TPG_TRY(ws_reserve(ws, ws->cx_vtx[slot[s]], sizeof(int32_t)));
+        TPG_HIP(launch_zero_u64(ws->cx_off[slot[s]].as<uint64_t>(), 1, st));
+        n_out[slot[s]] = nv_out[slot[s]] = 0;
+      }
+      continue;
+    }
+    TPG_TRY(upload_union(ws, U, st));
+    ws->seed_lo = 0;
+    ws->seed_n = -1;
+    TreeResult R;
+    Timer tm{ws, st, false};
+    if (c.flags & TPG_FORCE_TWO_PASS)
+      TPG_TRY(build_tree_twopass(ws, U, st, tm, R));
+    else
+      TPG_TRY(build_tree_onepass(ws, U, st, tm, R, 0, 0));
+    const int64_t N = R.n_nodes;
+    TPG_TRY(ws_reserve(ws, ws->cx_qb, (size_t)N + 1));
+    TPG_TRY(ws_reserve(ws, ws->cx_cnt0, sizeof(uint32_t) * (N + 1)));
+    TPG_TRY(ws_reserve(ws, ws->cx_cnt1, sizeof(uint32_t) * (N + 1)));
+    TPG_TRY(ws_reserve(ws, ws->cx_vfl, (size_t)U.n));
+    TPG_TRY(ws_reserve(ws, ws->cx_orig, sizeof(int32_t) * U.n));
+    TPG_HIP(hipMemcpyAsync(ws->cx_vfl.p, S.vfl.data(), U.n, hipMemcpyHostToDevice, st));
+    TPG_HIP(hipMemcpyAsync(ws->cx_orig.p, S.orig.data(), sizeof(int32_t) * U.n,
+                           hipMemcpyHostToDevice, st));
+    const ExtArgs a = make_args(ws);
+    uint8_t* qb = ws->cx_qb.as<uint8_t>();
+    uint32_t* cnt[2] = {ws->cx_cnt0.as<uint32_t>(), ws->cx_cnt1.as<uint32_t>()};
+    for (int L = R.Lmax; L >= 1; --L)
+      TPG_HIP(launch_ex_up(a, R.off[L], R.count[L], ws->cx_vfl.as<uint8_t>(), rev, qb, cnt[0],
+                           nsets > 1 ? cnt[1] : nullptr, st));
+    for (int s = 0; s < nsets; ++s) {
+      TPG_HIP(launch_ex_roots(cnt[s], R.count[1], scal, st));
+      TPG_HIP(hipMemcpyAsync(ws->h_scalars, scal, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      TPG_HIP(hipStreamSynchronize(st));
+      const int64_t np = ws->h_scalars[0];
+      TPG_TRY(ws_reserve(ws, ws->cx_node, sizeof(int64_t) * (np + 1)));
+      TPG_TRY(ws_reserve(ws, ws->cx_len, sizeof(int32_t) * (np + 1)));
+      for (int L = 1; L <= R.Lmax; ++L)
+        TPG_HIP(launch_ex_down(a, L, R.off[L], R.count[L], qb, cnt[s], rev, s,
+                               ws->cx_node.as<int64_t>(), ws->cx_len.as<int32_t>(), st));
+      DevBuf& off = ws->cx_off[slot[s]];
+      TPG_TRY(ws_reserve(ws, off, sizeof(int64_t) * (np + 1)));
+      TPG_TRY(reserve_scan(ws, std::max<int64_t>(np, 16)));
+      scal = ws->scalars.as<int64_t>();
+      TPG_HIP(scan_i32_to_i64(ws->cx_len.as<int32_t>(), off.as<int64_t>(), np, 0, scal + 1,
+                              ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
+      TPG_HIP(launch_set_i64(off.as<int64_t>() + np, scal + 1, st));
+      TPG_HIP(hipMemcpyAsync(ws->h_scalars + 1, scal + 1, sizeof(int64_t), hipMemcpyDeviceToHost,
+                             st));
+      TPG_HIP(hipStreamSynchronize(st));
+      const int64_t nv = ws->h_scalars[1];
+      DevBuf& vtx = ws->cx_vtx[slot[s]];
+      TPG_TRY(ws_reserve(ws, vtx, sizeof(int32_t) * (nv + 1)));
+      TPG_HIP(launch_ex_write(a, ws->cx_node.as<int64_t>(), off.as<int64_t>(), np, rev,
+                              ws->cx_orig.as<int32_t>(), vtx.as<int32_t>(), st));
+      n_out[slot[s]] = np;
+      nv_out[slot[s]] = nv;
+    }
+  }
+  TPG_HIP(hipStreamSynchronize(st));
+  return TPG_OK;
+}
+
+struct HostSet {
+  std::vector<int64_t> off;
+  std::vector<int32_t> vtx;
+  int64_t size() const { return (int64_t)off.size() - 1; }
+};
+
+tpg_status fetch_set(const DevBuf& off, const DevBuf& vtx, int64_t n, int64_t nv, hipStream_t st,
+                     HostSet& h) {
+  h.off.assign(n + 1, 0);
+  h.vtx.assign(nv, 0);
+  TPG_HIP(hipMemcpyAsync(h.off.data(), off.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, st));
+  if (nv) TPG_HIP(hipMemcpyAsync(h.vtx.data(), vtx.p, sizeof(int32_t) * nv, hipMemcpyDeviceToHost, st));
+  TPG_HIP(hipStreamSynchronize(st));
+  return TPG_OK;
+}
+
+// A prefix trie of paths: node = a prefix; end bits mark the paths that end
+// at a node (bit 0 SccEntryExitPath, 1 SccEntryPath, 2 SccExitPath).
+struct PathTrie {
+  std::vector<int32_t> v;
+  std::vector<uint8_t> end;
+  std::vector<std::vector<int32_t>> kids;
+  std::map<std::pair<int32_t, int32_t>, int32_t> at;  // (parent or -1, vertex) -> node
+  void add(const HostSet& h, uint8_t bit) {
+    for (int64_t i = 0; i < h.size(); ++i) {
+      int32_t x = -1;
+      for (int64_t k = h.off[i]; k < h.off[i + 1]; ++k) {
+        const auto key = std::make_pair(x, h.vtx[k]);
+        auto it = at.find(key);
+        if (it == at.end()) {
+          const int32_t id = (int32_t)v.size();
+          v.push_back(h.vtx[k]);
+          end.push_back(0);
+          kids.emplace_back();
+          if (x >= 0) kids[x].push_back(id);
+          it = at.emplace(key, id).first;
+        }
+        x = it->second;
+      }
+      if (x >= 0) end[x] |= bit;
+    }
+  }
+  int32_t root(int32_t vertex) const {
+    auto it = at.find(std::make_pair(-1, vertex));
+    return it == at.end() ? -1 : it->second;
+  }
+};
+
+}  // namespace
+
+tpg_status tpg_ccfg(const tpg_graph* g, const tpg_opts* opts, int32_t* comp, int32_t* n_comp,
+                    int64_t* n_arcs, int32_t* arc_src, int32_t* arc_dst, int64_t arc_cap) {
+  TPG_TRY(check_graph(g));
+  if (!n_arcs) return fail(TPG_ERR_INVALID_ARG, "n_arcs is NULL");
+  CallCtx c;
+  TPG_TRY(begin_call(opts, c));
+  tpg_workspace* ws = c.ws;
+  HostUnion U;
+  add_component(U, g);
+  TPG_TRY(upload_union(ws, U, c.st));
+  TPG_TRY(scc_device(ws, U, c.st));
+  const int n = g->n;
+  TPG_TRY(ws_reserve(ws, ws->cg_cnt, sizeof(int32_t) * (n + 1)));
+  TPG_TRY(ws_reserve(ws, ws->cg_off, sizeof(int64_t) * (n + 1)));
+  TPG_TRY(reserve_scan(ws, std::max(n, 16)));
+  int64_t* scal = ws->scalars.as<int64_t>();
+  const int32_t* d_comp = ws->scc_comp.as<int32_t>();
+  TPG_HIP(launch_ccfg_count(ws->dg, d_comp, ws->cg_cnt.as<int32_t>(), c.st));
+  TPG_HIP(scan_i32_to_i64(ws->cg_cnt.as<int32_t>(), ws->cg_off.as<int64_t>(), n, 0, scal,
+                          ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), c.st));
+  int32_t nc = 0;
+  TPG_HIP(hipMemcpyAsync(ws->h_scalars, scal, sizeof(int64_t), hipMemcpyDeviceToHost, c.st));
+  TPG_HIP(hipMemcpyAsync(&nc, ws->scc_misc.p, sizeof nc, hipMemcpyDeviceToHost, c.st));
+  TPG_HIP(hipStreamSynchronize(c.st));
+  const int64_t na = ws->h_scalars[0];
+  *n_arcs = na;
+  if (n_comp) *n_comp = nc;
+  if (comp)
+    TPG_HIP(hipMemcpyAsync(comp, d_comp, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c.st));
+  if (arc_src || arc_dst) {
+    if (!arc_src || !arc_dst) return fail(TPG_ERR_INVALID_ARG, "arc_src and arc_dst go together");
+    if (na > arc_cap)
+      return fail(TPG_ERR_CAPACITY, "%lld component-graph arcs, room for %lld", (long long)na,
+                  (long long)arc_cap);
+    TPG_TRY(ws_reserve(ws, ws->cg_src, sizeof(int32_t) * (na + 1)));
+    TPG_TRY(ws_reserve(ws, ws->cg_dst, sizeof(int32_t) * (na + 1)));
+    TPG_HIP(launch_ccfg_write(ws->dg, d_comp, ws->cg_off.as<int64_t>(), ws->cg_src.as<int32_t>(),
+                              ws->cg_dst.as<int32_t>(), c.st));
+    if (na) {
+      TPG_HIP(hipMemcpyAsync(arc_src, ws->cg_src.p, sizeof(int32_t) * na, hipMemcpyDeviceToHost,
+                             c.st));
+      TPG_HIP(hipMemcpyAsync(arc_dst, ws->cg_dst.p, sizeof(int32_t) * na, hipMemcpyDeviceToHost,
+                             c.st));
+    }
+  }
+  TPG_HIP(hipStreamSynchronize(c.st));
+  return TPG_OK;
+}
+
+tpg_status tpg_scc_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* entry_exit,
+                         tpg_paths* exit_paths, tpg_paths* entry_paths) {
+  for (tpg_paths* p : {entry_exit, exit_paths, entry_paths})
+    if (p) memset(p, 0, sizeof *p);
+  TPG_TRY(check_graph(g));
+  CallCtx c;
+  TPG_TRY(begin_call(opts, c));
+  std::vector<int32_t> comp;
+  std::vector<uint8_t> fl;
+  TPG_TRY(components_host(c, g, comp, fl));
+  int64_t n[3], nv[3];
+  TPG_TRY(extract_device(c, g, comp, fl, n, nv));
+  tpg_paths* outs[3] = {entry_exit, exit_paths, entry_paths};
+  for (int s = 0; s < 3; ++s)
+    if (outs[s])
+      TPG_TRY(export_paths(c.ws->cx_off[s], c.ws->cx_vtx[s], n[s], nv[s],
+                           (c.flags & TPG_OUT_DEVICE) != 0, c.st, outs[s]));
+  return TPG_OK;
+}
+
+tpg_status tpg_scc_internal_pps(const tpg_graph* g, const tpg_opts* opts, tpg_paths* out) {
+  if (!out) return fail(TPG_ERR_INVALID_ARG, "out is NULL");
+  memset(out, 0, sizeof *out);
+  TPG_TRY(check_graph(g));
+  CallCtx c;
+  TPG_TRY(begin_call(opts, c));
+  tpg_workspace* ws = c.ws;
+  hipStream_t st = c.st;
+  std::vector<int32_t> comp;
+  std::vector<uint8_t> fl;
+  TPG_TRY(components_host(c, g, comp, fl));
+  ComponentUnion S;
+  HostUnion U;
+  TPG_TRY(component_union(g, comp, fl, false, S, U));
+  DevBuf& ooff = ws->cm_off[0];
+  DevBuf& ovtx = ws->cm_vtx[0];
+  if (U.n == 0) {
+    TPG_TRY(ws_reserve(ws, ooff, sizeof(int64_t)));
+    TPG_TRY(ws_reserve(ws, ovtx, sizeof(int32_t)));
+    TPG_HIP(launch_zero_u64(ooff.as<uint64_t>(), 1, st));
+    return export_paths(ooff, ovtx, 0, 0, (c.flags & TPG_OUT_DEVICE) != 0, st, out);
+  }
+  // the extension on every component alone (one union), then Def. 9
+  Timer tm{ws, st, false};
+  TreeResult R;
+  PPResult P;
+  OutSet& o = ws->out[0];
+  TPG_TRY(run_pp(U, c, tm, R, P, o, nullptr));
+  const int64_t np = P.n_pp;
+  TPG_TRY(ws_reserve(ws, ws->cx_vfl, (size_t)U.n));
+  TPG_TRY(ws_reserve(ws, ws->cx_orig, sizeof(int32_t) * U.n));
+  TPG_HIP(hipMemcpyAsync(ws->cx_vfl.p, S.vfl.data(), U.n, hipMemcpyHostToDevice, st));
+  TPG_HIP(hipMemcpyAsync(ws->cx_orig.p, S.orig.data(), sizeof(int32_t) * U.n,
+                         hipMemcpyHostToDevice, st));
+  TPG_TRY(ws_reserve(ws, ws->cm_cls, (size_t)np + 1));
+  TPG_TRY(ws_reserve(ws, ws->cm_len, sizeof(int32_t) * (np + 1)));
+  TPG_TRY(ws_reserve(ws, ws->cm_flag, sizeof(int32_t) * (np + 1)));
+  TPG_TRY(ws_reserve(ws, ws->cm_lens, sizeof(int32_t) * (np + 1)));
+  TPG_TRY(ws_reserve(ws, ws->cm_pos, sizeof(int64_t) * (np + 1)));
+  TPG_TRY(ws_reserve(ws, ws->cm_voff, sizeof(int64_t) * (np + 1)));
+  TPG_HIP(launch_internal_class(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), np,
+                                ws->cx_vfl.as<uint8_t>(), ws->cm_cls.as<uint8_t>(),
+                                ws->cm_len.as<int32_t>(), st));
+  TPG_TRY(reserve_scan(ws, std::max<int64_t>(np, 16)));
+  int64_t* scal = ws->scalars.as<int64_t>();
+  TPG_HIP(launch_merge_sel(ws->cm_cls.as<uint8_t>(), ws->cm_len.as<int32_t>(), np, 1,
+                           ws->cm_flag.as<int32_t>(), ws->cm_lens.as<int32_t>(), st));
+  TPG_HIP(scan_i32_to_i64(ws->cm_flag.as<int32_t>(), ws->cm_pos.as<int64_t>(), np, 0, scal + 2,
+                          ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
+  TPG_HIP(scan_i32_to_i64(ws->cm_lens.as<int32_t>(), ws->cm_voff.as<int64_t>(), np, 0, scal + 3,
+                          ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
+  TPG_HIP(hipMemcpyAsync(ws->h_scalars + 2, scal + 2, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TPG_HIP(hipStreamSynchronize(st));
+  const int64_t k = ws->h_scalars[2], kv = ws->h_scalars[3];
+  TPG_TRY(ws_reserve(ws, ooff, sizeof(int64_t) * (k + 1)));
+  TPG_TRY(ws_reserve(ws, ovtx, sizeof(int32_t) * (kv + 1)));
+  TPG_HIP(launch_merge_emit(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), np,
+                            ws->cm_cls.as<uint8_t>(), 1, ws->cm_pos.as<int64_t>(),
+                            ws->cm_voff.as<int64_t>(), ws->cm_len.as<int32_t>(),
+                            ws->cx_orig.as<int32_t>(), ooff.as<int64_t>(), ovtx.as<int32_t>(), st));
+  TPG_HIP(launch_set_i64(ooff.as<int64_t>() + k, scal + 3, st));
+  TPG_HIP(hipStreamSynchronize(st));
+  return export_paths(ooff, ovtx, k, kv, (c.flags & TPG_OUT_DEVICE) != 0, st, out);
+}
+
+tpg_status tpg_merged_pps(const tpg_graph* g, const tpg_opts* opts, tpg_paths* complete,
+                          tpg_paths* exit_pps, tpg_paths* entry_pps) {
+  for (tpg_paths* p : {complete, exit_pps, entry_pps})
+    if (p) memset(p, 0, sizeof *p);
+  TPG_TRY(check_graph(g));
+  if (g->load_flags & TPG_LOAD_ANY_DIGRAPH)
+    return fail(TPG_ERR_UNREACHABLE, "the merge needs a CFG loaded with the entry/exit checks");
+  CallCtx c;
+  TPG_TRY(begin_call(opts, c));
+  tpg_workspace* ws = c.ws;
+  hipStream_t st = c.st;
+  std::vector<int32_t> comp;
+  std::vector<uint8_t> fl;
+  TPG_TRY(components_host(c, g, comp, fl));
+  int64_t n[3], nv[3];
+  TPG_TRY(extract_device(c, g, comp, fl, n, nv));
+  HostSet ee, ex, en;
+  TPG_TRY(fetch_set(ws->cx_off[0], ws->cx_vtx[0], n[0], nv[0], st, ee));
+  TPG_TRY(fetch_set(ws->cx_off[1], ws->cx_vtx[1], n[1], nv[1], st, ex));
+  TPG_TRY(fetch_set(ws->cx_off[2], ws->cx_vtx[2], n[2], nv[2], st, en));
+
+  // The macro graph H (graph preparation on the host): a vertex for every
+  // vertex of g outside the components with a cycle; the trie of the
+  // SccEntryExitPaths and SccEntryPaths (they start at SccEntryVertices); the
+  // trie of the SccExitPaths; a terminal mark after every node where an
+  // SccEntryPath ends.  Arcs: g's arcs out of the vertices outside the
+  // components, trie arcs, and g's arcs that leave a component out of every
+  // node where an SccEntryExitPath or an SccExitPath ends; an arc into a
+  // component lands on the trie root of the vertex it enters.  H is acyclic
+  // and its prime paths are the merged candidates: from the entry to the
+  // exit (complete), from an exit-path trie root to the exit, from the entry
+  // to a terminal mark.  H's ids follow g's vertex order (terminal marks
+  // first), and the successors of an H vertex are distinct vertices of g, so
+  // the lexicographic order of H's paths is that of the paths in g.
+  PathTrie tin, tex;
+  tin.add(ee, 1);
+  tin.add(en, 2);
+  tex.add(ex, 4);
+  const int32_t n0 = g->n;
+  const int32_t b_in = n0, b_ex = b_in + (int32_t)tin.v.size();
+  const int32_t b_mk = b_ex + (int32_t)tex.v.size();
+  std::vector<int32_t> mark_of(tin.v.size(), -1);
+  int32_t nh = b_mk;
+  for (size_t x = 0; x < tin.v.size(); ++x)
+    if (tin.end[x] & 2) mark_of[x] = nh++;
+  std::vector<uint8_t> kind(nh, 0);
+  std::vector<int32_t> horig(nh, -1);
+  for (int32_t v = 0; v < n0; ++v) horig[v] = v;  // ids of cyclic vertices stay unused
+  for (size_t x = 0; x < tin.v.size(); ++x) {
+    kind[b_in + x] = 1;
+    horig[b_in + x] = tin.v[x];
+  }
+  for (size_t x = 0; x < tex.v.size(); ++x) {
+    kind[b_ex + x] = 2;
+    horig[b_ex + x] = tex.v[x];
+  }
+  for (int32_t h = b_mk; h < nh; ++h) kind[h] = 3;
+  auto target = [&](int32_t w) -> int32_t {
+    if (!(fl[w] & kSccCyclic)) return w;
+    const int32_t r = tin.root(w);
+    return r < 0 ? -1 : b_in + r;
+  };
+  std::vector<std::vector<int32_t>> adj(nh);
+  std::vector<uint8_t> live(nh, 1);
+  for (int32_t v = 0; v < n0; ++v) {
+    if (fl[v] & kSccCyclic) {
+      live[v] = 0;
+      continue;
+    }
+    for (int32_t e = g->succ_ptr[v]; e < g->succ_ptr[v + 1]; ++e) {
+      const int32_t t = target(g->succ[e]);
+      if (t >= 0) adj[v].push_back(t);
+    }
+  }
+  auto leave_arcs = [&](int32_t h, int32_t a) {
+    for (int32_t e = g->succ_ptr[a]; e < g->succ_ptr[a + 1]; ++e) {
+      const int32_t w = g->succ[e];
+      if (comp[w] == comp[a]) continue;
+      const int32_t t = target(w);
+      if (t >= 0) adj[h].push_back(t);
+    }
+  };
+  for (size_t x = 0; x < tin.v.size(); ++x) {
+    const int32_t h = b_in + (int32_t)x;
+    for (int32_t k : tin.kids[x]) adj[h].push_back(b_in + k);
+    if (tin.end[x] & 1) leave_arcs(h, tin.v[x]);
+    if (tin.end[x] & 2) adj[h].push_back(mark_of[x]);
+  }
+  for (size_t x = 0; x < tex.v.size(); ++x) {
+    const int32_t h = b_ex + (int32_t)x;
+    for (int32_t k : tex.kids[x]) adj[h].push_back(b_ex + k);
+    if (tex.end[x] & 4) leave_arcs(h, tex.v[x]);
+  }
+  // renumber: live vertices by (vertex of g, kind, id); terminal marks first
+  std::vector<int32_t> order;
+  for (int32_t h = 0; h < nh; ++h)
+    if (live[h]) order.push_back(h);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    if (horig[x] != horig[y]) return horig[x] < horig[y];
+    return kind[x] < kind[y];
+  });
+  const int32_t nH = (int32_t)order.size();
+  if (nH > TPG_MAX_VERTICES)
+    return fail(TPG_ERR_UNSUPPORTED, "the merge graph has %d vertices (at most %d)", nH,
+                TPG_MAX_VERTICES);
+  std::vector<int32_t> nid(nh, -1);
+  for (int32_t i = 0; i < nH; ++i) nid[order[i]] = i;
+  std::vector<int64_t> rp(nH + 1, 0);
+  std::vector<int32_t> ci;
+  std::vector<uint8_t> hk(nH);
+  std::vector<int32_t> ho(nH);
+  for (int32_t i = 0; i < nH; ++i) {
+    const int32_t h = order[i];
+    for (int32_t t : adj[h]) ci.push_back(nid[t]);
+    rp[i + 1] = (int64_t)ci.size();
+    hk[i] = kind[h];
+    ho[i] = horig[h];
+  }
+  if (ci.empty()) ci.push_back(0);
+  tpg_graph* H = nullptr;
+  TPG_TRY(tpg_load_cfg_csr(nH, rp.data(), ci.data(), nid[g->entry], nid[g->exit],
+                           TPG_LOAD_ANY_DIGRAPH, &H));
+  struct Free {
+    tpg_graph* h;
+    ~Free() { tpg_graph_free(h); }
+  } free_h{H};
+  // prime paths of H on the device
+  HostUnion UH;
+  add_component(UH, H);
+  Timer tm{ws, st, false};
+  TreeResult R;
+  PPResult P;
+  OutSet& o = ws->out[0];
+  TPG_TRY(run_pp(UH, c, tm, R, P, o, nullptr));
+  // classify them in g (its CSR back on the device), keep the prime ones
+  HostUnion UG;
+  add_component(UG, g);
+  TPG_TRY(upload_union(ws, UG, st));
+  const int64_t np = P.n_pp;
+  TPG_TRY(ws_reserve(ws, ws->cm_kind, (size_t)nH));
+  TPG_TRY(ws_reserve(ws, ws->cm_orig, sizeof(int32_t) * nH));
+  TPG_TRY(ws_reserve(ws, ws->cm_cls, (size_t)np + 1));
+  TPG_TRY(ws_reserve(ws, ws->cm_len, sizeof(int32_t) * (np + 1)));
+  TPG_TRY(ws_reserve(ws, ws->cm_flag, sizeof(int32_t) * (np + 1)));
+  TPG_TRY(ws_reserve(ws, ws->cm_lens, sizeof(int32_t) * (np + 1)));
+  TPG_TRY(ws_reserve(ws, ws->cm_pos, sizeof(int64_t) * (np + 1)));
+  TPG_TRY(ws_reserve(ws, ws->cm_voff, sizeof(int64_t) * (np + 1)));
+  TPG_HIP(hipMemcpyAsync(ws->cm_kind.p, hk.data(), nH, hipMemcpyHostToDevice, st));
+  TPG_HIP(hipMemcpyAsync(ws->cm_orig.p, ho.data(), sizeof(int32_t) * nH, hipMemcpyHostToDevice, st));
+  TPG_HIP(launch_merge_class(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), np,
+                             ws->cm_kind.as<uint8_t>(), ws->cm_orig.as<int32_t>(), ws->dg,
+                             nid[g->entry], nid[g->exit], ws->cm_cls.as<uint8_t>(),
+                             ws->cm_len.as<int32_t>(), st));
+  TPG_TRY(reserve_scan(ws, std::max<int64_t>(np, 16)));
+  int64_t* scal = ws->scalars.as<int64_t>();
+  const int cls_of[3] = {1, 3, 4};
+  tpg_paths* outs[3] = {complete, exit_pps, entry_pps};
+  for (int s = 0; s < 3; ++s) {
+    TPG_HIP(launch_merge_sel(ws->cm_cls.as<uint8_t>(), ws->cm_len.as<int32_t>(), np, cls_of[s],
+                             ws->cm_flag.as<int32_t>(), ws->cm_lens.as<int32_t>(), st));
+    TPG_HIP(scan_i32_to_i64(ws->cm_flag.as<int32_t>(), ws->cm_pos.as<int64_t>(), np, 0, scal + 2,
+                            ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
+    TPG_HIP(scan_i32_to_i64(ws->cm_lens.as<int32_t>(), ws->cm_voff.as<int64_t>(), np, 0, scal + 3,
+                            ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
+    TPG_HIP(hipMemcpyAsync(ws->h_scalars + 2, scal + 2, 2 * sizeof(int64_t), hipMemcpyDeviceToHost,
+                           st));
+    TPG_HIP(hipStreamSynchronize(st));
+    const int64_t k = ws->h_scalars[2], kv = ws->h_scalars[3];
+    TPG_TRY(ws_reserve(ws, ws->cm_off[s], sizeof(int64_t) * (k + 1)));
+    TPG_TRY(ws_reserve(ws, ws->cm_vtx[s], sizeof(int32_t) * (kv + 1)));
+    TPG_HIP(launch_merge_emit(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), np,
+                              ws->cm_cls.as<uint8_t>(), cls_of[s], ws->cm_pos.as<int64_t>(),
+                              ws->cm_voff.as<int64_t>(), ws->cm_len.as<int32_t>(),
+                              ws->cm_orig.as<int32_t>(), ws->cm_off[s].as<int64_t>(),
+                              ws->cm_vtx[s].as<int32_t>(), st));
+    TPG_HIP(launch_set_i64(ws->cm_off[s].as<int64_t>() + k, scal + 3, st));
+    if (outs[s])
+      TPG_TRY(export_paths(ws->cm_off[s], ws->cm_vtx[s], k, kv, (c.flags & TPG_OUT_DEVICE) != 0, st,
+                           outs[s]));
+  }
+  TPG_HIP(hipStreamSynchronize(st));
   return TPG_OK;
 }
 

@@ -128,6 +128,32 @@ hipError_t launch_pv_emit(int L, const int32_t* rows, const int32_t* flag, const
                           int64_t n_rows, int64_t base, int64_t voff0, int64_t* out_off,
                           int32_t* out_vtx, hipStream_t st);
 // types[i] (may be null) and counts[0 .. kPpTypes) of a prime-path set
+// --- compositional method (Sec. 2.1): component graph, extraction, merge ---
+hipError_t launch_ccfg_count(const DGraph& g, const int32_t* comp, int32_t* cnt, hipStream_t st);
+hipError_t launch_ccfg_write(const DGraph& g, const int32_t* comp, const int64_t* off, int32_t* src,
+                             int32_t* dst, hipStream_t st);
+// mode 0: forward tree of the components (set 0 entry-exit paths, set 1 entry
+// paths); mode 1: tree of the reversed components (set 0 exit paths)
+hipError_t launch_ex_up(const ExtArgs& a, int64_t base, int64_t F, const uint8_t* vfl, int mode,
+                        uint8_t* qb, uint32_t* cnt0, uint32_t* cnt1, hipStream_t st);
+hipError_t launch_ex_roots(uint32_t* cnt, int64_t n_roots, int64_t* total, hipStream_t st);
+hipError_t launch_ex_down(const ExtArgs& a, int L, int64_t base, int64_t F, const uint8_t* qb,
+                          uint32_t* cnt, int mode, int set, int64_t* out_node, int32_t* out_len,
+                          hipStream_t st);
+hipError_t launch_ex_write(const ExtArgs& a, const int64_t* out_node, const int64_t* off,
+                           int64_t n, int reversed, const int32_t* orig, int32_t* vtx,
+                           hipStream_t st);
+hipError_t launch_merge_class(const int64_t* off, const int32_t* vtx, int64_t n,
+                              const uint8_t* hkind, const int32_t* horig, const DGraph& g,
+                              int h_entry, int h_exit, uint8_t* cls, int32_t* len, hipStream_t st);
+hipError_t launch_internal_class(const int64_t* off, const int32_t* vtx, int64_t n,
+                                 const uint8_t* vfl, uint8_t* cls, int32_t* len, hipStream_t st);
+hipError_t launch_merge_sel(const uint8_t* cls, const int32_t* len, int64_t n, int c, int32_t* flag,
+                            int32_t* lens, hipStream_t st);
+hipError_t launch_merge_emit(const int64_t* off, const int32_t* vtx, int64_t n, const uint8_t* cls,
+                             int c, const int64_t* pos, const int64_t* voff, const int32_t* len,
+                             const int32_t* horig, int64_t* out_off, int32_t* out_vtx,
+                             hipStream_t st);
 hipError_t launch_pp_types(const DGraph& g, const int32_t* comp, const uint8_t* flags,
                            const int64_t* off, const int32_t* vtx, int64_t n_pp, uint8_t* types,
                            unsigned long long* counts, hipStream_t st);

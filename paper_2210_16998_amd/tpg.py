@@ -147,6 +147,17 @@ _SIGS = {
                                ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "tpg_prime_path_types": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Paths),
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "tpg_ccfg": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Opts), ctypes.c_void_p,
+                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
+    "tpg_scc_paths": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Opts),
+                                     ctypes.POINTER(_Paths), ctypes.POINTER(_Paths),
+                                     ctypes.POINTER(_Paths)]),
+    "tpg_scc_internal_pps": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Opts),
+                                            ctypes.POINTER(_Paths)]),
+    "tpg_merged_pps": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Opts),
+                                      ctypes.POINTER(_Paths), ctypes.POINTER(_Paths),
+                                      ctypes.POINTER(_Paths)]),
     "tpg_prime_path_types_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                                     ctypes.c_void_p, ctypes.c_int64,
                                                     ctypes.c_void_p, ctypes.c_void_p,
@@ -459,6 +470,48 @@ def prime_path_types(g: Graph, pps, ws: Optional[Workspace] = None, stream=None,
                                       counts.ctypes.data))
     del keep
     return (types[:n] if want_types else None), counts
+
+
+def ccfg(g: Graph, ws: Optional[Workspace] = None, stream=None):
+    """(comp int32 [n], n_comp, arcs int32 [k, 2]): component labels and the
+    component graph's arcs (arcs of g between components, CSR order)."""
+    n, m = g.info()[0], g.info()[1]
+    comp = np.zeros(max(n, 1), np.int32)
+    nc = ctypes.c_int32(0)
+    na = ctypes.c_int64(0)
+    src = np.zeros(max(m, 1), np.int32)
+    dst = np.zeros(max(m, 1), np.int32)
+    o = _opts(ws, 0, stream, None, 0)
+    _check(lib().tpg_ccfg(g.handle, ctypes.byref(o), comp.ctypes.data, ctypes.byref(nc),
+                          ctypes.byref(na), src.ctypes.data, dst.ctypes.data, len(src)))
+    k = int(na.value)
+    return comp[:n], int(nc.value), np.stack([src[:k], dst[:k]], axis=1)
+
+
+def scc_paths(g: Graph, ws: Optional[Workspace] = None, flags: int = 0, stream=None):
+    """(entry_exit, exit_paths, entry_paths) of the components with a cycle
+    (Defs. 6-8): HostPaths, or DevicePaths with TPG_OUT_DEVICE."""
+    outs = [_Paths(), _Paths(), _Paths()]
+    o = _opts(ws, flags, stream, None, 0)
+    _check(lib().tpg_scc_paths(g.handle, ctypes.byref(o), *[ctypes.byref(x) for x in outs]))
+    return tuple(_wrap(x) for x in outs)
+
+
+def scc_internal_pps(g: Graph, ws: Optional[Workspace] = None, flags: int = 0, stream=None):
+    """SccInternalPPs from the extension on each component with a cycle
+    alone (Def. 9), grouped by component."""
+    out = _Paths()
+    o = _opts(ws, flags, stream, None, 0)
+    _check(lib().tpg_scc_internal_pps(g.handle, ctypes.byref(o), ctypes.byref(out)))
+    return _wrap(out)
+
+
+def merged_pps(g: Graph, ws: Optional[Workspace] = None, flags: int = 0, stream=None):
+    """(complete, scc_exit, scc_entry) prime paths merged as in Sec. 2.1."""
+    outs = [_Paths(), _Paths(), _Paths()]
+    o = _opts(ws, flags, stream, None, 0)
+    _check(lib().tpg_merged_pps(g.handle, ctypes.byref(o), *[ctypes.byref(x) for x in outs]))
+    return tuple(_wrap(x) for x in outs)
 
 
 def prime_path_types_noalloc(g: Graph, pps, types=None, stream=None) -> np.ndarray:
