@@ -157,6 +157,14 @@ typedef struct tpg_stats {
   int64_t n_unions;              /* graph unions processed (batched form)     */
   int64_t pred_nodes;            /* predicted paths (batched form with predictions) */
   int64_t pred_peak_level_nodes; /* predicted largest level                  */
+  int64_t call_graph;            /* batched form: 0 an ordinary call, 1 captured
+                                    into one HIP graph by this call, 2 replayed
+                                    from that graph (one launch, one wait), 3 an
+                                    ordinary call because capturing this call
+                                    failed (tpg_last_error() says why) */
+  int64_t n_allocs;              /* batched form: device allocations and releases
+                                    the call made in the workspace (a call that
+                                    made any is not captured the next time) */
 } tpg_stats;
 
 typedef struct tpg_opts {
@@ -407,10 +415,23 @@ tpg_status tpg_prime_path_types_noalloc(const tpg_graph* g, const int64_t* d_off
  * that is not a finite number counts as 0; predicted capacities are capped
  * at the 2^31-path limit, at half the pool cap and at half the free device
  * memory, and a union whose predicted capacities cannot be allocated is
- * sized from the smallest buffers by growth and replay instead.  Without
- * it, sizing starts from the workspace's current capacity (or the exact
- * two-pass form with TPG_FORCE_TWO_PASS).  Results never depend on the
- * prediction.
+ * sized from the smallest buffers by growth and replay instead (the
+ * workspace remembers up to 64 such unions and sizes them from the capacity
+ * it holds on later calls).  Without it, sizing starts from the workspace's
+ * current capacity (or the exact two-pass form with TPG_FORCE_TWO_PASS).
+ * Results never depend on the prediction.
+ *
+ * Repeated calls: with opts->ws set, TPG_NO_TIMING (or no stats), no level
+ * counts and none of TPG_FORCE_TWO_PASS, TPG_STREAM, TPG_TP_GREEDY,
+ * TPG_DIGEST, TPG_DIGEST_ONLY, a call that repeats the workspace's previous
+ * batched call (same graph handles, flags, stream, pool cap, predictions and
+ * tuning) and whose predecessor allocated nothing is captured into one HIP
+ * graph, and later repeats replay it: one launch and one wait instead of a
+ * host round trip per step.  Every device value the host read during the
+ * recorded call is copied out again by the graph and compared after each
+ * replay; a mismatch drops the graph and the call runs the ordinary way, so
+ * results are those of an ordinary call.  stats->call_graph says which way
+ * the call ran.  Calls on one workspace must not overlap (as always).
  *
  * opts->level_counts, if it holds >= 64 * n_graphs entries, receives the
  * per-graph path counts of levels 1..64 (deeper levels pooled into 64):

@@ -43,6 +43,24 @@ int pow2_words(int n) {
 
 }  // namespace
 
+// The batched form's whole call as one HIP graph (see tpg_batch_test_paths):
+// what the call depended on, every value the host read from the device
+// during the recorded call, the host-side results it produced, and the
+// instantiated graph.
+struct CallGraph {
+  std::vector<uint8_t> key;
+  std::vector<uint8_t> vals;    // host reads of the recorded call, in order
+  size_t stage_bytes = 0;       // host data the call uploaded
+  uint64_t gen = 0;             // the workspace's allocation generation after the record
+  bool recorded = false;
+  bool failed = false;          // capture did not work for this key: stay eager
+  hipGraphExec_t exec = nullptr;
+  // host results of the call
+  std::vector<int64_t> pp_first, tp_first;
+  int64_t ppv = 0, tpv = 0;
+  tpg_stats stats{};
+};
+
 struct tpg_workspace {
   int device = 0;
   hipStream_t own_stream = nullptr;
@@ -55,11 +73,31 @@ struct tpg_workspace {
   size_t bytes = 0;
   uint64_t cap = 0;  // pool cap of the running call (0: none)
 
+  // Host <-> device traffic of a call whose device work may be captured
+  // into one graph: io_mode 0 an ordinary call; 1 an ordinary call that
+  // records every value the host reads from the device and the host data
+  // it uploads; 2 capture, where the reads come from the record (the graph
+  // copies the device's values into io_check for the check after each
+  // replay) and uploads come from pinned staging that the graph keeps.
+  int io_mode = 0;
+  const std::vector<uint8_t>* io_rec = nullptr;  // mode 2: the recorded reads
+  std::vector<uint8_t> io_vals;                  // mode 1: reads being recorded
+  size_t io_pos = 0;
+  uint8_t* io_check = nullptr;
+  size_t io_check_cap = 0, io_check_used = 0;
+  uint8_t* io_stage = nullptr;
+  size_t io_stage_cap = 0, io_stage_used = 0;
+  bool io_diverged = false;  // a capture left the recorded call's path
+  uint64_t alloc_gen = 0;    // bumped by every device allocation and release
+  CallGraph cg;
+
   // union on the device
   std::vector<uint64_t> union_uids;
   // level count of the last one-pass run on this union (sizes the first batch)
   std::vector<uint64_t> levels_uids;
   int levels_last = 0;
+  // unions (by graph uids) whose predicted capacities could not be allocated
+  std::vector<std::vector<uint64_t>> pred_failed;
   DevBuf g_csr;
   DGraph dg{};
 
@@ -144,6 +182,11 @@ tpg_status ws_reserve(tpg_workspace* ws, DevBuf& b, size_t bytes, bool keep = fa
                       hipStream_t st = nullptr, size_t keep_bytes = 0) {
   if (bytes == 0) bytes = 16;
   if (b.cap >= bytes) return TPG_OK;
+  if (ws->io_mode == 2) {
+    ws->io_diverged = true;
+    return fail(TPG_ERR_UNSUPPORTED, "the captured call needed a larger buffer");
+  }
+  ws->alloc_gen += 1;
   size_t want = std::max(bytes, b.cap + b.cap / 2);
   want = (want + 255) & ~(size_t)255;
   if (ws->cap && ws->bytes - b.cap + want > ws->cap) {
@@ -174,11 +217,82 @@ tpg_status ws_reserve(tpg_workspace* ws, DevBuf& b, size_t bytes, bool keep = fa
 
 void ws_release(tpg_workspace* ws, DevBuf& b) {
   if (b.p) {
+    if (ws->io_mode == 2) {  // no free under capture; the capture is abandoned
+      ws->io_diverged = true;
+      return;
+    }
     (void)hipFree(b.p);
     ws->bytes -= b.cap;
+    ws->alloc_gen += 1;
   }
   b.p = nullptr;
   b.cap = 0;
+}
+
+// The host's reads of device values on the batched path.  An ordinary call
+// copies and waits (recording the bytes in io_mode 1).  Under capture the
+// value comes from the record and the graph copies the device's value into
+// io_check, compared with the record after every replay.
+tpg_status io_read(tpg_workspace* ws, hipStream_t st, void* dst, const void* dev, size_t bytes) {
+  if (ws->io_mode == 2) {
+    if (!ws->io_rec || ws->io_pos + bytes > ws->io_rec->size() ||
+        ws->io_check_used + bytes > ws->io_check_cap) {
+      ws->io_diverged = true;
+      memset(dst, 0, bytes);
+      return fail(TPG_ERR_UNSUPPORTED, "the captured call read more than the recorded one");
+    }
+    TPG_HIP(hipMemcpyAsync(ws->io_check + ws->io_check_used, dev, bytes, hipMemcpyDeviceToHost,
+                           st));
+    memcpy(dst, ws->io_rec->data() + ws->io_pos, bytes);
+    ws->io_pos += bytes;
+    ws->io_check_used += bytes;
+    return TPG_OK;
+  }
+  TPG_HIP(hipMemcpyAsync(dst, dev, bytes, hipMemcpyDeviceToHost, st));
+  TPG_HIP(hipStreamSynchronize(st));
+  if (ws->io_mode == 1) {
+    const uint8_t* p = static_cast<const uint8_t*>(dst);
+    ws->io_vals.insert(ws->io_vals.end(), p, p + bytes);
+  }
+  return TPG_OK;
+}
+
+// A value the host decides from device state it queries (free memory):
+// recorded in io_mode 1, taken from the record under capture.
+void io_value(tpg_workspace* ws, int64_t& v) {
+  if (ws->io_mode == 1) {
+    const uint8_t* p = reinterpret_cast<const uint8_t*>(&v);
+    ws->io_vals.insert(ws->io_vals.end(), p, p + sizeof v);
+  } else if (ws->io_mode == 2) {
+    if (!ws->io_rec || ws->io_pos + sizeof v > ws->io_rec->size() ||
+        ws->io_check_used + sizeof v > ws->io_check_cap) {
+      ws->io_diverged = true;
+      return;
+    }
+    memcpy(&v, ws->io_rec->data() + ws->io_pos, sizeof v);
+    // the check buffer holds it too (no device copy writes there), so the
+    // values after a replay line up with the record
+    memcpy(ws->io_check + ws->io_check_used, &v, sizeof v);
+    ws->io_pos += sizeof v;
+    ws->io_check_used += sizeof v;
+  }
+}
+
+// Host data about to be uploaded on the batched path: under capture it is
+// copied to pinned staging that the graph reads at every replay (in io_mode
+// 1 its size is counted for that staging).
+const void* io_src(tpg_workspace* ws, const void* host, size_t bytes) {
+  const size_t b = (bytes + 255) & ~(size_t)255;
+  if (ws->io_mode == 1) ws->io_stage_used += b;
+  if (ws->io_mode != 2) return host;
+  if (ws->io_stage_used + b > ws->io_stage_cap) {
+    ws->io_diverged = true;
+    return host;
+  }
+  uint8_t* at = ws->io_stage + ws->io_stage_used;
+  memcpy(at, host, bytes);
+  ws->io_stage_used += b;
+  return at;
 }
 
 // Predicted number of paths with L + 1 entries of graph i (index 63: all
@@ -212,7 +326,8 @@ void add_component(HostUnion& U, const tpg_graph* g) {
 }
 
 tpg_status upload_union(tpg_workspace* ws, const HostUnion& U, hipStream_t st) {
-  if (ws->union_uids == U.uids) return TPG_OK;
+  // a recorded or captured call always uploads, so that every replay does
+  if (ws->io_mode == 0 && ws->union_uids == U.uids) return TPG_OK;
   const size_t n1 = (size_t)U.n + 1, m = U.s.size(), nc = (size_t)U.n_comp;
   const size_t words = 2 * n1 + 2 * (m + 1) + 2 * (size_t)U.n + (nc + 1) + 2 * nc + 8;
   TPG_TRY(ws_reserve(ws, ws->g_csr, sizeof(int32_t) * words));
@@ -221,7 +336,8 @@ tpg_status upload_union(tpg_workspace* ws, const HostUnion& U, hipStream_t st) {
   auto put = [&](const std::vector<int32_t>& v, size_t pad) -> int32_t* {
     int32_t* at = q;
     if (!v.empty() && err == hipSuccess)
-      err = hipMemcpyAsync(at, v.data(), sizeof(int32_t) * v.size(), hipMemcpyHostToDevice, st);
+      err = hipMemcpyAsync(at, io_src(ws, v.data(), sizeof(int32_t) * v.size()),
+                           sizeof(int32_t) * v.size(), hipMemcpyHostToDevice, st);
     q += v.size() + pad;
     return at;
   };
@@ -239,7 +355,7 @@ tpg_status upload_union(tpg_workspace* ws, const HostUnion& U, hipStream_t st) {
   d.n_comp = U.n_comp;
   d.n_stage = (int32_t)(d.comp - d.sp);
   TPG_HIP(err);
-  TPG_HIP(hipStreamSynchronize(st));
+  if (ws->io_mode != 2) TPG_HIP(hipStreamSynchronize(st));  // the host vectors are freed after
   ws->dg = d;
   ws->union_uids = U.uids;
   return TPG_OK;
@@ -261,6 +377,7 @@ tpg_status reserve_tree(tpg_workspace* ws, int64_t rec, int64_t msk, int W, hipS
   ws->rec_cap = std::min<int64_t>(ws->par.cap / sizeof(int32_t), ws->cstart.cap / sizeof(int32_t) - 1);
   ws->rec_cap = std::min<int64_t>(ws->rec_cap, ws->info.cap / sizeof(uint32_t));
   ws->rec_cap = std::min<int64_t>(ws->rec_cap, (int64_t)ws->nch.cap);
+  ws->rec_cap = std::min<int64_t>(ws->rec_cap, kMaxTreeNodes);  // buffers may hold more
   // Visited sets are word-major (word q of slot j at q * mask_cap + j), so the
   // stride is the capacity: both buffers always have the same size, and the
   // kept level is copied to the new stride when they grow.
@@ -386,8 +503,12 @@ void key_add(std::vector<uint8_t>& k, const T& v) {
 // once and from then on replayed as one graph, which removes the host's
 // per-launch gap between short kernels.
 template <class F>
-tpg_status run_seq(tpg_workspace::SeqGraph& g, std::vector<uint8_t>&& key, hipStream_t st,
-                   F&& launches) {
+tpg_status run_seq(tpg_workspace* ws, tpg_workspace::SeqGraph& g, std::vector<uint8_t>&& key,
+                   hipStream_t st, F&& launches) {
+  if (ws->io_mode == 2) {  // inside a whole-call capture: plain launches
+    TPG_HIP(launches());
+    return TPG_OK;
+  }
   if (key != g.key) {
     drop_seq_graph(g);
     g.key = std::move(key);
@@ -422,6 +543,10 @@ tpg_status run_seq(tpg_workspace::SeqGraph& g, std::vector<uint8_t>&& key, hipSt
 // of buffers or stream drops the graphs).
 tpg_status launch_levels_graph(tpg_workspace* ws, const ExtArgs& a, int W, int items,
                                int variant, int grid, int len, hipStream_t st) {
+  if (ws->io_mode == 2) {  // inside a whole-call capture: plain launches
+    for (int i = 0; i < len; ++i) TPG_HIP(launch_extend(W, items, variant, a, grid, i, st));
+    return TPG_OK;
+  }
   if (memcmp(&ws->graph_args, &a, sizeof a) != 0 || ws->graph_W != W || ws->graph_grid != grid ||
       ws->graph_items != items || ws->graph_variant != variant || ws->graph_stream != st) {
     drop_level_graphs(ws);
@@ -508,8 +633,8 @@ struct OnePassDev {
   bool run(int L0, int len, BatchReport& r) {
     LevelState* dls = ws->ls.as<LevelState>();
     ws->h_scalars[8] = L0;
-    if (!hip(hipMemcpyAsync(&dls->batch_start, &ws->h_scalars[8], sizeof(int32_t),
-                            hipMemcpyHostToDevice, st), "batch start"))
+    if (!hip(hipMemcpyAsync(&dls->batch_start, io_src(ws, &ws->h_scalars[8], sizeof(int32_t)),
+                            sizeof(int32_t), hipMemcpyHostToDevice, st), "batch start"))
       return false;
     evs.clear();
     if (tm.on) {
@@ -523,10 +648,8 @@ struct OnePassDev {
       return false;
     }
     // header + sizes of levels L0 .. L0 + len
-    if (!hip(hipMemcpyAsync(ws->h_ls, dls, 32, hipMemcpyDeviceToHost, st), "level header") ||
-        !hip(hipMemcpyAsync(ws->h_ls->count + L0, dls->count + L0, sizeof(int64_t) * (len + 1),
-                            hipMemcpyDeviceToHost, st), "level sizes") ||
-        !hip(hipStreamSynchronize(st), "level loop"))
+    if (!ok(io_read(ws, st, ws->h_ls, dls, 32)) ||
+        !ok(io_read(ws, st, ws->h_ls->count + L0, dls->count + L0, sizeof(int64_t) * (len + 1))))
       return false;
     const LevelState& h = *ws->h_ls;
     r.overflow = h.overflow != 0;
@@ -639,7 +762,8 @@ tpg_status build_tree_twopass(tpg_workspace* ws, const HostUnion& U, hipStream_t
     if (base + F + total + 1 > ws->rec_cap || (store_next && total > ws->mask_cap)) {
       const int64_t need = base + F + total + 1;
       const int Ls = (L & 1) ? L : L - 1;  // the stored level the fill reads
-      TPG_TRY(reserve_tree(ws, std::max<int64_t>(ws->rec_cap, need + need / 2),
+      TPG_TRY(reserve_tree(ws, std::max(need, std::min(std::max<int64_t>(ws->rec_cap, need + need / 2),
+                                                       kMaxTreeNodes)),
                            store_next ? std::max<int64_t>(ws->mask_cap, total + total / 2) : ws->mask_cap,
                            U.Wu, st, base + F + 1, mask_buf_host(Ls), R.count[Ls]));
       a = make_args(ws);
@@ -692,7 +816,7 @@ tpg_status rank_and_materialize(tpg_workspace* ws, const HostUnion& U, hipStream
   // both sweeps take up to kRun levels per launch (a launch costs ~7 us
   // however little it does)
   constexpr int kRun = 2;  // 3 measured slower: deeper per-thread chains
-  TPG_TRY(run_seq(ws->rank_up, std::move(key), st, [&]() -> hipError_t {
+  TPG_TRY(run_seq(ws, ws->rank_up, std::move(key), st, [&]() -> hipError_t {
     hipError_t e = launch_zero_u64(ws->cycles.as<uint64_t>(), 1, st);
     unsigned long long* ncyc = ws->cycles.as<unsigned long long>();
     for (int L = R.Lmax; L >= 1 && e == hipSuccess;) {
@@ -706,9 +830,8 @@ tpg_status rank_and_materialize(tpg_workspace* ws, const HostUnion& U, hipStream
       e = launch_roots(a, R.count[1], sc, nullptr, nullptr, ws->totals.as<int64_t>(), 0, st);
     return e;
   }));
-  TPG_HIP(hipMemcpyAsync(ws->h_scalars, ws->totals.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  TPG_HIP(hipMemcpyAsync(ws->h_scalars + 2, ws->cycles.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  TPG_HIP(hipStreamSynchronize(st));
+  TPG_TRY(io_read(ws, st, ws->h_scalars, ws->totals.p, sizeof(int64_t)));
+  TPG_TRY(io_read(ws, st, ws->h_scalars + 2, ws->cycles.p, sizeof(int64_t)));
   P.n_pp = ws->h_scalars[0];
   P.n_cycles = ws->h_scalars[2];
   TPG_TRY(ws_reserve(ws, ws->leaf_by_rank, sizeof(int64_t) * (P.n_pp + 1)));
@@ -720,7 +843,7 @@ tpg_status rank_and_materialize(tpg_workspace* ws, const HostUnion& U, hipStream
   int32_t* len = ws->pp_len.as<int32_t>();
   key_add(key_down, lbr);
   key_add(key_down, len);
-  TPG_TRY(run_seq(ws->rank_down, std::move(key_down), st, [&]() -> hipError_t {
+  TPG_TRY(run_seq(ws, ws->rank_down, std::move(key_down), st, [&]() -> hipError_t {
     hipError_t e = launch_roots(a, R.count[1], sc, lbr, len, ws->totals.as<int64_t>(), 1, st);
     for (int L = 1; L < R.Lmax && e == hipSuccess;) {
       const int n = std::min(kRun, R.Lmax - L);  // parents of levels L .. L + n - 1
@@ -737,8 +860,7 @@ tpg_status rank_and_materialize(tpg_workspace* ws, const HostUnion& U, hipStream
   int64_t* cs = o.comp_starts.as<int64_t>();
   TPG_HIP(launch_comp_pp_starts(ws->dg, sc, o.pp_off.as<int64_t>(), ws->totals.as<int64_t>(), cs,
                                 cs + (U.n_comp + 1), st));
-  TPG_HIP(hipMemcpyAsync(ws->h_scalars + 6, scal + 6, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  TPG_HIP(hipStreamSynchronize(st));
+  TPG_TRY(io_read(ws, st, ws->h_scalars + 6, scal + 6, sizeof(int64_t)));
   P.n_vtx = ws->h_scalars[6];
   TPG_TRY(ws_reserve(ws, o.pp_vtx, sizeof(int32_t) * (P.n_vtx + 1)));
   TPG_HIP(launch_pp_write(a, lbr, o.pp_off.as<int64_t>(), P.n_pp, o.pp_vtx.as<int32_t>(), st));
@@ -920,10 +1042,8 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
                         ws->tp_len.as<int64_t>(), ws->rb0.as<int64_t>(), st));
   TPG_HIP(scan_i64(ws->tp_len.as<int64_t>(), ws->tp_off.as<int64_t>(), np, 0, sc,
                    ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
-  TPG_HIP(hipMemcpyAsync(ws->h_scalars, sc, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  TPG_HIP(hipMemcpyAsync(ws->h_scalars + 4, ws->scalars2.p, 2 * sizeof(int64_t),
-                         hipMemcpyDeviceToHost, st));
-  TPG_HIP(hipStreamSynchronize(st));
+  TPG_TRY(io_read(ws, st, ws->h_scalars, sc, sizeof(int64_t)));
+  TPG_TRY(io_read(ws, st, ws->h_scalars + 4, ws->scalars2.p, 2 * sizeof(int64_t)));
   const int64_t tp_total = ws->h_scalars[0];
   TPG_TRY(ws_reserve(ws, ws->pfx, sizeof(int32_t) * (ws->h_scalars[4] + 1)));
   TPG_TRY(ws_reserve(ws, ws->sfx, sizeof(int32_t) * (ws->h_scalars[5] + 1)));
@@ -974,8 +1094,7 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
                    ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
   TPG_HIP(scan_i64(ws->keep_len.as<int64_t>(), ws->keep_voff.as<int64_t>(), nm, 0, sc + 3,
                    ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
-  TPG_HIP(hipMemcpyAsync(ws->h_scalars + 2, sc + 2, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  TPG_HIP(hipStreamSynchronize(st));
+  TPG_TRY(io_read(ws, st, ws->h_scalars + 2, sc + 2, 2 * sizeof(int64_t)));
   T.n_tp = ws->h_scalars[2];
   T.n_vtx = ws->h_scalars[3];
   TPG_TRY(ws_reserve(ws, o.tp_off, sizeof(int64_t) * (T.n_tp + 1)));
@@ -1326,6 +1445,9 @@ void tpg_workspace_free(tpg_workspace* ws) {
   (void)hipSetDevice(ws->device);
   if (ws->own_stream) (void)hipStreamSynchronize(ws->own_stream);
   if (ws->side_stream) (void)hipStreamSynchronize(ws->side_stream);
+  if (ws->cg.exec) (void)hipGraphExecDestroy(ws->cg.exec);
+  if (ws->io_check) (void)hipHostFree(ws->io_check);
+  if (ws->io_stage) (void)hipHostFree(ws->io_stage);
   DevBuf* bufs[] = {&ws->g_csr, &ws->par, &ws->info, &ws->cstart, &ws->nch, &ws->mask0,
                     &ws->mask1, &ws->ls, &ws->sub_cnt, &ws->pp_len,
                     &ws->leaf_by_rank, &ws->totals, &ws->cycles, &ws->scan_status,
@@ -2205,32 +2327,15 @@ tpg_status tpg_test_paths(const tpg_graph* g, const tpg_opts* opts, tpg_paths* p
 // batched form
 // ---------------------------------------------------------------------------
 
-tpg_status tpg_batch_test_paths(const tpg_graph* const* graphs, int32_t n_graphs,
-                                const tpg_opts* opts, const float* predicted,
-                                tpg_batch_result* out) {
-  if (!out) return fail(TPG_ERR_INVALID_ARG, "out is NULL");
-  memset(out, 0, sizeof *out);
-  if (!graphs || n_graphs < 1) return fail(TPG_ERR_INVALID_ARG, "no graphs");
-  for (int32_t i = 0; i < n_graphs; ++i) {
-    TPG_TRY(check_graph(graphs[i]));
-    if (graphs[i]->load_flags & TPG_LOAD_ANY_DIGRAPH)
-      return fail(TPG_ERR_UNREACHABLE, "graph %d was loaded without the entry/exit checks", i);
-  }
-  CallCtx c;
-  TPG_TRY(begin_call(opts, c));
+// The device work of a batched call (everything between the call's set-up
+// and the export of its results): unions by visited-set width, each one's
+// prime and test paths, and the packing graph by graph.  pp_first /
+// tp_first / ppv / tpv: the packed results' index arrays and sizes.
+static tpg_status batch_body(CallCtx& c, const tpg_graph* const* graphs, int32_t n_graphs,
+                      const float* predicted, bool want_levels, Timer& tm,
+                      std::vector<int64_t>& pp_first, std::vector<int64_t>& tp_first,
+                      int64_t& ppv, int64_t& tpv) {
   tpg_workspace* ws = c.ws;
-  const bool dev = c.flags & TPG_OUT_DEVICE;
-  const bool want_levels = c.opts && c.opts->level_counts &&
-                           (int64_t)c.opts->level_counts_len >= (int64_t)64 * n_graphs;
-  Timer tm{ws, c.st, c.stats != nullptr && !(c.flags & TPG_NO_TIMING)};
-  hipEvent_t t0 = nullptr, t1 = nullptr;
-  if (tm.on) {
-    TPG_HIP(hipEventCreate(&t0));
-    TPG_HIP(hipEventCreate(&t1));
-    TPG_HIP(hipEventRecord(t0, c.st));
-  }
-  if (c.stats) memset(c.stats, 0, sizeof *c.stats);
-
   // unions: one per visited-set width class, split at 2^17 vertices and, with
   // predictions and a pool cap, at half the cap of predicted footprint
   std::vector<std::vector<int32_t>> unions;
@@ -2279,7 +2384,10 @@ tpg_status tpg_batch_test_paths(const tpg_graph* const* graphs, int32_t n_graphs
       g_comp[i] = (int32_t)k;
     }
     int64_t rec0 = 0, msk0 = 0;
-    if (predicted) {
+    const bool use_pred =
+        predicted &&
+        std::find(ws->pred_failed.begin(), ws->pred_failed.end(), U.uids) == ws->pred_failed.end();
+    if (use_pred) {
       // capacities from the predicted per-level path counts, 25% margin;
       // index 63 pools every deeper level, so it sizes the total but not the
       // largest single level
@@ -2296,7 +2404,7 @@ tpg_status tpg_batch_test_paths(const tpg_graph* const* graphs, int32_t n_graphs
       double rec_lim = (double)INT32_MAX - 2, msk_lim = (double)INT32_MAX - 2;
       const double node_b = 13.0, set_b = 2.0 * 8.0 * U.Wu;
       size_t free_b = 0, total_b = 0;
-      if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0) {
+      if (ws->io_mode != 2 && hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0) {
         rec_lim = std::min(rec_lim, 0.5 * (double)free_b / node_b);
         msk_lim = std::min(msk_lim, 0.25 * (double)free_b / set_b);
       } else {
@@ -2308,6 +2416,8 @@ tpg_status tpg_batch_test_paths(const tpg_graph* const* graphs, int32_t n_graphs
       }
       rec0 = (int64_t)std::min(1.25 * tot + U.n + 1024, rec_lim);
       msk0 = (int64_t)std::min(1.25 * peak + 1024, msk_lim);
+      io_value(ws, rec0);  // free device memory may differ between calls
+      io_value(ws, msk0);
       if (c.stats) {
         c.stats->pred_nodes += (int64_t)std::min(tot, 9.0e18);
         c.stats->pred_peak_level_nodes =
@@ -2322,7 +2432,10 @@ tpg_status tpg_batch_test_paths(const tpg_graph* const* graphs, int32_t n_graphs
     if (s_pp != TPG_OK && (rec0 || msk0) &&
         (s_pp == TPG_ERR_CAPACITY || s_pp == TPG_ERR_OOM_DEVICE || s_pp == TPG_ERR_UNSUPPORTED)) {
       // the predicted capacities did not fit: size this union exactly, by
-      // growth and replay from the smallest buffers
+      // growth and replay from the smallest buffers, and from what the
+      // workspace holds on later calls
+      if (ws->pred_failed.size() >= 64) ws->pred_failed.erase(ws->pred_failed.begin());
+      ws->pred_failed.push_back(U.uids);
       release_tree(ws);
       R = TreeResult{};
       P = PPResult{};
@@ -2354,9 +2467,8 @@ tpg_status tpg_batch_test_paths(const tpg_graph* const* graphs, int32_t n_graphs
     if (nc == 1) {
       starts[u] = {0, o.n_pp, 0, o.n_ppv, 0, o.n_tp, 0, o.n_tpv};
     } else {
-      TPG_HIP(hipMemcpyAsync(starts[u].data(), o.comp_starts.p, sizeof(int64_t) * starts[u].size(),
-                             hipMemcpyDeviceToHost, c.st));
-      TPG_HIP(hipStreamSynchronize(c.st));
+      TPG_TRY(io_read(ws, c.st, starts[u].data(), o.comp_starts.p,
+                      sizeof(int64_t) * starts[u].size()));
       starts[u][2 * (nc + 1) + nc] = o.n_tp;
       starts[u][3 * (nc + 1) + nc] = o.n_tpv;
     }
@@ -2365,8 +2477,10 @@ tpg_status tpg_batch_test_paths(const tpg_graph* const* graphs, int32_t n_graphs
 
   // pack the unions' outputs graph by graph in caller order
   std::vector<PackDesc> d_pp(n_graphs), d_tp(n_graphs);
-  std::vector<int64_t> pp_first(n_graphs + 1, 0), tp_first(n_graphs + 1, 0);
-  int64_t ppv = 0, tpv = 0;
+  pp_first.assign(n_graphs + 1, 0);
+  tp_first.assign(n_graphs + 1, 0);
+  ppv = 0;
+  tpv = 0;
   for (int32_t i = 0; i < n_graphs; ++i) {
     const auto& S = starts[g_union[i]];
     const int nc = (int)unions[g_union[i]].size();
@@ -2387,9 +2501,13 @@ tpg_status tpg_batch_test_paths(const tpg_graph* const* graphs, int32_t n_graphs
   TPG_TRY(ws_reserve(ws, ws->b_tp_vtx, sizeof(int32_t) * (tpv + 1)));
   TPG_TRY(ws_reserve(ws, ws->b_desc, sizeof(PackDesc) * 2 * (size_t)n_graphs));
   PackDesc* dd = ws->b_desc.as<PackDesc>();
-  TPG_HIP(hipMemcpyAsync(dd, d_pp.data(), sizeof(PackDesc) * n_graphs, hipMemcpyHostToDevice, c.st));
-  TPG_HIP(hipMemcpyAsync(dd + n_graphs, d_tp.data(), sizeof(PackDesc) * n_graphs,
-                         hipMemcpyHostToDevice, c.st));
+  TPG_HIP(hipMemcpyAsync(dd, io_src(ws, d_pp.data(), sizeof(PackDesc) * n_graphs),
+                         sizeof(PackDesc) * n_graphs, hipMemcpyHostToDevice, c.st));
+  TPG_HIP(hipMemcpyAsync(dd + n_graphs, io_src(ws, d_tp.data(), sizeof(PackDesc) * n_graphs),
+                         sizeof(PackDesc) * n_graphs, hipMemcpyHostToDevice, c.st));
+  // the packed descriptors are read by the kernels above; an ordinary call
+  // waits so the host vectors can go
+  if (ws->io_mode != 2) TPG_HIP(hipStreamSynchronize(c.st));
   for (size_t u = 0; u < unions.size(); ++u) {
     OutSet& o = ws->out[u + 1];
     TPG_HIP(launch_pack(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), dd, n_graphs, (int32_t)u,
@@ -2399,6 +2517,186 @@ tpg_status tpg_batch_test_paths(const tpg_graph* const* graphs, int32_t n_graphs
   }
   TPG_HIP(launch_set_value_i64(ws->b_pp_off.as<int64_t>() + pp_first[n_graphs], ppv, c.st));
   TPG_HIP(launch_set_value_i64(ws->b_tp_off.as<int64_t>() + tp_first[n_graphs], tpv, c.st));
+  return TPG_OK;
+}
+
+tpg_status tpg_batch_test_paths(const tpg_graph* const* graphs, int32_t n_graphs,
+                                const tpg_opts* opts, const float* predicted,
+                                tpg_batch_result* out) {
+  if (!out) return fail(TPG_ERR_INVALID_ARG, "out is NULL");
+  memset(out, 0, sizeof *out);
+  if (!graphs || n_graphs < 1) return fail(TPG_ERR_INVALID_ARG, "no graphs");
+  for (int32_t i = 0; i < n_graphs; ++i) {
+    TPG_TRY(check_graph(graphs[i]));
+    if (graphs[i]->load_flags & TPG_LOAD_ANY_DIGRAPH)
+      return fail(TPG_ERR_UNREACHABLE, "graph %d was loaded without the entry/exit checks", i);
+  }
+  CallCtx c;
+  TPG_TRY(begin_call(opts, c));
+  tpg_workspace* ws = c.ws;
+  const bool want_levels = c.opts && c.opts->level_counts &&
+                           (int64_t)c.opts->level_counts_len >= (int64_t)64 * n_graphs;
+  Timer tm{ws, c.st, c.stats != nullptr && !(c.flags & TPG_NO_TIMING)};
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (tm.on) {
+    TPG_HIP(hipEventCreate(&t0));
+    TPG_HIP(hipEventCreate(&t1));
+    TPG_HIP(hipEventRecord(t0, c.st));
+  }
+  if (c.stats) memset(c.stats, 0, sizeof *c.stats);
+
+  std::vector<int64_t> pp_first, tp_first;
+  int64_t ppv = 0, tpv = 0;
+  // A call that repeats the previous one exactly (same graphs, flags,
+  // predictions, stream and launch shapes, and no buffer changed since) runs
+  // as one captured HIP graph: the call after a recorded one is captured and
+  // from then on replayed with one launch and one wait.  The record holds
+  // every value the host read from the device; the graph copies the
+  // device's values beside them and a replay whose values differ is
+  // discarded and the call run again the ordinary way.
+  CallGraph& cg = ws->cg;
+  const bool graphable = !tm.on && !want_levels &&
+                         !(c.flags & (TPG_FORCE_TWO_PASS | TPG_STREAM | TPG_TP_GREEDY |
+                                      TPG_DIGEST | TPG_DIGEST_ONLY)) &&
+                         c.opts && c.opts->ws;
+  std::vector<uint8_t> key;
+  if (graphable) {
+    key_add(key, n_graphs);
+    for (int32_t i = 0; i < n_graphs; ++i) key_add(key, graphs[i]->uid);
+    key_add(key, c.flags);
+    key_add(key, c.st);
+    key_add(key, ws->cap);
+    key_add(key, predicted != nullptr);
+    if (predicted) {
+      const uint8_t* pb = reinterpret_cast<const uint8_t*>(predicted);
+      key.insert(key.end(), pb, pb + sizeof(float) * 65 * (size_t)n_graphs);
+    }
+    for (int k = 0; k < 7; ++k) {
+      key_add(key, ws->tune_items[k]);
+      key_add(key, ws->tune_wgs[k]);
+      key_add(key, ws->tune_variant[k]);
+    }
+  }
+  const bool same = graphable && cg.recorded && cg.key == key && cg.gen == ws->alloc_gen;
+  int32_t graph_state = 0;  // 0 ordinary, 1 captured by this call, 2 replayed
+  bool done = false;
+  if (same && !cg.failed) {
+    if (!cg.exec) {
+      // capture the call into one graph
+      ws->io_mode = 2;
+      ws->io_rec = &cg.vals;
+      ws->io_pos = 0;
+      ws->io_check_used = 0;
+      ws->io_stage_used = 0;
+      ws->io_diverged = false;
+      hipGraph_t graph = nullptr;
+      tpg_status bs = TPG_OK;
+      if (hipStreamBeginCapture(c.st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        std::vector<int64_t> pf, tf;
+        int64_t a = 0, b = 0;
+        tpg_stats saved{};
+        if (c.stats) saved = *c.stats;
+        bs = batch_body(c, graphs, n_graphs, predicted, want_levels, tm, pf, tf, a, b);
+        if (c.stats) *c.stats = saved;
+        const hipError_t ee = hipStreamEndCapture(c.st, &graph);
+        hipError_t ei = hipSuccess;
+        if (bs == TPG_OK && ee == hipSuccess && !ws->io_diverged && ws->io_pos == cg.vals.size() &&
+            graph && (ei = hipGraphInstantiate(&cg.exec, graph, nullptr, nullptr, 0)) == hipSuccess) {
+          graph_state = 1;
+        } else {
+          // the reason stays in the error text; the call runs the ordinary way
+          if (bs == TPG_OK)
+            (void)fail(TPG_ERR_UNSUPPORTED,
+                       "call graph not used: end of capture %s, instantiation %s, %s, %zu of %zu "
+                       "recorded values read",
+                       hipGetErrorString(ee), hipGetErrorString(ei),
+                       ws->io_diverged ? "diverged" : "on the recorded path", ws->io_pos,
+                       cg.vals.size());
+          cg.exec = nullptr;
+          cg.failed = true;
+        }
+      } else {
+        (void)fail(TPG_ERR_UNSUPPORTED, "call graph not used: the stream could not be captured");
+        (void)hipGetLastError();
+        cg.failed = true;
+      }
+      if (graph) (void)hipGraphDestroy(graph);
+      ws->io_mode = 0;
+      ws->io_rec = nullptr;
+      (void)hipGetLastError();
+    }
+    if (cg.exec) {
+      TPG_HIP(hipGraphLaunch(cg.exec, c.st));
+      TPG_HIP(hipStreamSynchronize(c.st));
+      if (ws->io_check_used == cg.vals.size() &&
+          memcmp(ws->io_check, cg.vals.data(), cg.vals.size()) == 0) {
+        pp_first = cg.pp_first;
+        tp_first = cg.tp_first;
+        ppv = cg.ppv;
+        tpv = cg.tpv;
+        if (c.stats) *c.stats = cg.stats;
+        if (graph_state == 0) graph_state = 2;
+        done = true;
+      } else {
+        // the device took another path than the recorded call: run it again
+        (void)hipGraphExecDestroy(cg.exec);
+        cg.exec = nullptr;
+        cg.recorded = false;
+        if (c.stats) memset(c.stats, 0, sizeof *c.stats);
+        graph_state = 0;
+      }
+    }
+  }
+  if (!done) {
+    // an ordinary call, recorded when it may be captured next time
+    if (cg.exec && !same) {
+      (void)hipGraphExecDestroy(cg.exec);
+      cg.exec = nullptr;
+    }
+    ws->io_mode = graphable ? 1 : 0;
+    ws->io_vals.clear();
+    ws->io_stage_used = 0;
+    const uint64_t gen0 = ws->alloc_gen;
+    const tpg_status bs = batch_body(c, graphs, n_graphs, predicted, want_levels, tm, pp_first,
+                                     tp_first, ppv, tpv);
+    ws->io_mode = 0;
+    TPG_TRY(bs);
+    if (c.stats) c.stats->n_allocs = (int64_t)(ws->alloc_gen - gen0);
+    if (same && cg.failed) graph_state = 3;
+    if (graphable) {
+      // worth recording only when nothing grew: a replay must not allocate
+      const bool stable = ws->alloc_gen == gen0;
+      const bool new_key = !(cg.key == key);
+      cg.key = key;
+      cg.recorded = stable;
+      if (new_key) cg.failed = false;
+      cg.vals.swap(ws->io_vals);
+      cg.stage_bytes = ws->io_stage_used;
+      cg.gen = ws->alloc_gen;
+      cg.pp_first = pp_first;
+      cg.tp_first = tp_first;
+      cg.ppv = ppv;
+      cg.tpv = tpv;
+      if (c.stats) cg.stats = *c.stats;
+      // pinned room for the next call's capture (allocated now, outside it)
+      if (stable && cg.vals.size() > ws->io_check_cap) {
+        if (ws->io_check) (void)hipHostFree(ws->io_check);
+        ws->io_check = nullptr;
+        ws->io_check_cap = 0;
+        TPG_HIP(hipHostMalloc((void**)&ws->io_check, cg.vals.size() + 64));
+        ws->io_check_cap = cg.vals.size() + 64;
+      }
+      if (stable && cg.stage_bytes > ws->io_stage_cap) {
+        if (ws->io_stage) (void)hipHostFree(ws->io_stage);
+        ws->io_stage = nullptr;
+        ws->io_stage_cap = 0;
+        TPG_HIP(hipHostMalloc((void**)&ws->io_stage, cg.stage_bytes + 256));
+        ws->io_stage_cap = cg.stage_bytes + 256;
+      }
+    }
+  }
+  if (c.stats) c.stats->call_graph = graph_state;
+  const bool dev = c.flags & TPG_OUT_DEVICE;
   if (tm.on) TPG_HIP(hipEventRecord(t1, c.st));
 
   tpg_status s = export_paths(ws->b_pp_off, ws->b_pp_vtx, pp_first[n_graphs], ppv, dev, c.st, &out->pp);

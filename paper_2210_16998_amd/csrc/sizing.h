@@ -28,12 +28,17 @@ struct TreeCaps {
   int64_t rec = 0, msk = 0;
 };
 
+// Node indices are int32 (one spare slot for the child-range sentinel): a
+// request never goes beyond this many nodes unless the tree needs more,
+// whatever the workspace holds or the caller predicted.
+constexpr int64_t kMaxTreeNodes = (int64_t)INT32_MAX - 2;
+
 // First request of a run: what the workspace already holds (held_rec, and
 // held_msk slots at the run's set width), a floor from the vertex count, and
 // the caller's predicted sizes (0: none).
 constexpr TreeCaps onepass_first_caps(int64_t held_rec, int64_t held_msk, int n, int64_t rec0,
                                       int64_t msk0) {
-  return TreeCaps{std::max({held_rec, (int64_t)n * 64 + 4096, rec0}),
+  return TreeCaps{std::min(std::max({held_rec, (int64_t)n * 64 + 4096, rec0}), kMaxTreeNodes),
                   std::max({(int64_t)n * 16 + 1024, msk0, held_msk})};
 }
 
@@ -43,7 +48,7 @@ constexpr TreeCaps onepass_first_caps(int64_t held_rec, int64_t held_msk, int n,
 constexpr TreeCaps onepass_grown_caps(int64_t rec_cap, int64_t mask_cap, int Lo, int64_t base,
                                       int64_t F, int64_t nxt) {
   const int64_t need = base + F + nxt + 1;
-  return TreeCaps{std::max(rec_cap, need + need / 4),
+  return TreeCaps{std::max(need, std::min(std::max(rec_cap, need + need / 4), kMaxTreeNodes)),
                   ((Lo + 1) & 1) ? std::max(mask_cap, nxt + nxt / 4 + 1024) : mask_cap};
 }
 

@@ -67,7 +67,8 @@ class _Stats(ctypes.Structure):
                 ("ms_total", ctypes.c_double), ("ms_extend_kernel", ctypes.c_double),
                 ("n_extend_launches", ctypes.c_int64), ("peak_level_nodes", ctypes.c_int64),
                 ("n_unions", ctypes.c_int64), ("pred_nodes", ctypes.c_int64),
-                ("pred_peak_level_nodes", ctypes.c_int64)]
+                ("pred_peak_level_nodes", ctypes.c_int64), ("call_graph", ctypes.c_int64),
+                ("n_allocs", ctypes.c_int64)]
 
 
 class _Opts(ctypes.Structure):

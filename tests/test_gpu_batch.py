@@ -5,6 +5,7 @@ import pytest
 
 import oracle
 from paper_2210_16998_amd import cfggen, tpg
+from tests.goldens import workloads
 from tests.gpu_util import ref_pp, ref_tp, say, ws
 
 pytestmark = pytest.mark.gpu
@@ -135,4 +136,56 @@ def test_autotune_then_batch_is_exact():
     assert t["best_ms"][0] > 0 and t["items"][0] in (1, 2, 4, 8) and t["variant"][0] in (0, 1, 2)
     res, _ = tpg.batch_test_paths(hs, ws=w)
     _check_batch(cfgs, res)
+    w.close()
+
+
+def _same_result(a, b):
+    return (np.array_equal(a.pp_first, b.pp_first) and np.array_equal(a.tp_first, b.tp_first)
+            and np.array_equal(a.pp.offsets, b.pp.offsets)
+            and np.array_equal(a.pp.vertices, b.pp.vertices)
+            and np.array_equal(a.tp.offsets, b.tp.offsets)
+            and np.array_equal(a.tp.vertices, b.tp.vertices))
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_repeated_batch_call_runs_as_one_graph(learned):
+    """A batched call that repeats the previous one is captured into one HIP
+    graph and then replayed (one launch, one wait): every replay gives the
+    bytes of the ordinary call, graph by graph equal to the oracle; a call
+    in between that changes the workspace only sends the next one back to
+    the ordinary path."""
+    cfgs = _mixed()
+    hs = [tpg.load_cfg(g) for g in cfgs]
+    pred = None
+    if learned:
+        from paper_2210_16998_amd import sizer
+        pred = sizer.predict(tpg.MLP.load(sizer.DEFAULT_MODEL), hs)
+    w = tpg.Workspace()
+    say("case batch call graph", learned)
+    first, st = tpg.batch_test_paths(hs, ws=w, flags=tpg.TPG_NO_TIMING, predicted=pred)
+    _check_batch(cfgs, first)
+    states, allocs = [st["call_graph"]], [st["n_allocs"]]
+    for _ in range(4):
+        r, st = tpg.batch_test_paths(hs, ws=w, flags=tpg.TPG_NO_TIMING, predicted=pred)
+        states.append(st["call_graph"])
+        allocs.append(st["n_allocs"])
+        assert _same_result(r, first)
+        assert st["n_pp"] == len(first.pp)
+    say("  states", states, "allocations", allocs)
+    if 3 in states:
+        say("  ", tpg.lib().tpg_last_error().decode())
+    assert states[0] == 0 and 1 in states and states[-1] == 2
+    # another call on the workspace (larger buffers): the batch stays exact
+    tpg.test_paths(tpg.load_cfg(cfggen.c2_cfg(workloads()["c2"][0]["seed"])), ws=w)
+    for _ in range(3):
+        r, st = tpg.batch_test_paths(hs, ws=w, flags=tpg.TPG_NO_TIMING, predicted=pred)
+        assert _same_result(r, first)
+    # device output through the graph
+    for _ in range(3):
+        r, st = tpg.batch_test_paths(hs, ws=w, flags=tpg.TPG_NO_TIMING | tpg.TPG_OUT_DEVICE,
+                                     predicted=pred)
+    off, vtx = r.tp.torch_views()
+    assert np.array_equal(off.cpu().numpy(), first.tp.offsets)
+    assert np.array_equal(vtx.cpu().numpy(), first.tp.vertices)
+    assert st["call_graph"] == 2
     w.close()

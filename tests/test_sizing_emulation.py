@@ -91,3 +91,20 @@ def test_a_device_reporting_too_few_children_is_an_error(sim):
     s = _sizes(cfggen.c2_cfg(workloads()["c2"][3]["seed"]))
     r = sim(s, stale=10**9)
     assert r["status"] == REPEATED
+
+
+def test_held_capacity_beyond_the_node_limit_is_not_asked_for(sim):
+    """A workspace whose buffers grew past the 2^31-node index range (a
+    union sized from a large prediction before): the next run asks for at
+    most the index range, never for more nodes than a tree may hold, and
+    ends exact; growth near the limit stops at it as well."""
+    lim = 2**31 - 3
+    s = _sizes(cfggen.fig1_cfg())
+    r = sim(s, held=(3 * 2**30, 0))
+    assert r["status"] == OK and r["equal"] and r["rec"] == lim
+    r = sim(s, pred=(3 * 2**30, 0))
+    assert r["status"] == OK and r["equal"] and r["rec"] == lim
+    big = np.array([1, 1_500_000_000, 500_000_000], np.int64)
+    r = sim(big, held=(1_000_000_000, 2_000_000_000))
+    assert r["status"] == OK and r["equal"] and r["n_overflows"] == 2 and r["rec"] == lim
+
