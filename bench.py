@@ -458,7 +458,7 @@ def main() -> int:
         return _copy_probe(args.copy_probe)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is "
-              f"single-GPU in this build", file=sys.stderr)
+              f"single-GPU", file=sys.stderr)
         return 2
 
     import torch
@@ -525,9 +525,10 @@ def main() -> int:
 
 
 def _batched_learned_only(args):
-    """The batched call sized by the learned predictor alone, warm (one
-    untimed call, then batch_reps timed ones): what a kernel profile of
-    that form is taken on."""
+    """The batched call sized by the learned predictor alone, warm (two
+    untimed calls, then batch_reps timed ones), planned on the host each
+    time and then replayed as one graph: what a kernel profile of that form
+    is taken on."""
     import torch
     from paper_2210_16998_amd import cfggen, sizer, tpg, tuning
     graphs = [tpg.load_cfg(c) for c in cfggen.c3_batch(4096)]
@@ -536,19 +537,25 @@ def _batched_learned_only(args):
     if tuning.load(ws) is None:
         tpg.autotune(graphs, ws)
     dev = tpg.TPG_OUT_DEVICE | tpg.TPG_NO_TIMING
-
-    def call():
-        return tpg.batch_test_paths(graphs, ws=ws, flags=dev,
-                                    predicted=mlp.forward(tpg.features(graphs)))
-    call()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(args.batch_reps):
-        _, st = call()
-    torch.cuda.synchronize()
-    ms = 1000.0 * (time.perf_counter() - t) / args.batch_reps
-    return {"batched_learned_ms": ms, "n_pp": int(st["n_pp"]), "n_unions": int(st["n_unions"]),
-            "n_overflows": int(st["n_overflows"])}
+    out = {}
+    # every call planned on the host, then the same call replayed as one graph
+    for name, flags in (("batched_learned_ms", dev | tpg.TPG_NO_CALL_GRAPH),
+                        ("batched_learned_replayed_ms", dev)):
+        def call():
+            return tpg.batch_test_paths(graphs, ws=ws, flags=flags,
+                                        predicted=mlp.forward(tpg.features(graphs)))
+        call()
+        call()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.batch_reps):
+            _, st = call()
+        torch.cuda.synchronize()
+        out[name] = 1000.0 * (time.perf_counter() - t) / args.batch_reps
+        out[name.replace("_ms", "_call_graph")] = int(st["call_graph"])
+    out.update({"n_pp": int(st["n_pp"]), "n_unions": int(st["n_unions"]),
+                "n_overflows": int(st["n_overflows"])})
+    return out
 
 
 def _batched(args):
@@ -572,15 +579,19 @@ def _batched(args):
         torch.cuda.synchronize()
         return 1000.0 * (time.perf_counter() - t) / reps, r
 
-    def learned(ws):
+    # ordinary calls (launches planned on the host every time); the *_replayed
+    # figures repeat the same call, which then runs as one captured graph
+    plan = tpg.TPG_NO_CALL_GRAPH
+
+    def learned(ws, extra=plan):
         pred = mlp.forward(tpg.features(graphs))
-        return tpg.batch_test_paths(graphs, ws=ws, flags=dev, predicted=pred)
+        return tpg.batch_test_paths(graphs, ws=ws, flags=dev | extra, predicted=pred)
 
     def twopass(ws):
         return tpg.batch_test_paths(graphs, ws=ws, flags=dev | tpg.TPG_FORCE_TWO_PASS)
 
-    def onepass(ws):
-        return tpg.batch_test_paths(graphs, ws=ws, flags=dev)
+    def onepass(ws, extra=plan):
+        return tpg.batch_test_paths(graphs, ws=ws, flags=dev | extra)
 
     def snapshot(r):
         """Copies of a device result's arrays (the next call on the same
@@ -624,6 +635,12 @@ def _batched(args):
     ms1, (r1, _) = timed(lambda: onepass(ws), args.batch_reps)
     res["batched_one_pass_unpredicted_ms"] = ms1
     res["one_pass_same_paths_as_two_pass"] = same(snapshot(r1), ref)
+    onepass(ws, 0)
+    onepass(ws, 0)
+    ms1r, (r1r, st1r) = timed(lambda: onepass(ws, 0), args.batch_reps)
+    res["batched_one_pass_replayed_ms"] = ms1r
+    res["one_pass_replayed_call_graph"] = int(st1r["call_graph"])
+    res["one_pass_replayed_same_paths_as_two_pass"] = same(snapshot(r1r), ref)
     if mlp is not None:
         learned(ws)
         msl, (rl, stl) = timed(lambda: learned(ws), args.batch_reps)
@@ -634,6 +651,12 @@ def _batched(args):
         res["same_paths_as_two_pass"] = same(snapshot(rl), ref)
         res["gain_vs_batched_two_pass"] = ms2 / msl
         res["gain_vs_batched_one_pass_unpredicted"] = ms1 / msl
+        learned(ws, 0)
+        learned(ws, 0)
+        mslr, (rlr, stlr) = timed(lambda: learned(ws, 0), args.batch_reps)
+        res["batched_learned_replayed_ms"] = mslr
+        res["learned_replayed_call_graph"] = int(stlr["call_graph"])
+        res["learned_replayed_same_paths_as_two_pass"] = same(snapshot(rlr), ref)
         # cold start: fresh workspaces, predicted sizing vs growing by replay
         wc = fresh()
         msc, (_, stc) = timed(lambda: learned(wc), 1)

@@ -105,6 +105,9 @@ typedef enum tpg_status {
                                    ascending last vertex, canonical order inside
                                    a group; test paths keep the canonical order;
                                    not with TPG_STREAM                          */
+#define TPG_NO_CALL_GRAPH 0x100u /* tpg_batch_test_paths: never capture or replay
+                                   the call as one HIP graph (every call plans
+                                   its launches on the host)                   */
 
 typedef struct tpg_graph tpg_graph;         /* opaque, host memory */
 typedef struct tpg_workspace tpg_workspace; /* opaque: device arena + stream */
@@ -423,7 +426,7 @@ tpg_status tpg_prime_path_types_noalloc(const tpg_graph* g, const int64_t* d_off
  *
  * Repeated calls: with opts->ws set, TPG_NO_TIMING (or no stats), no level
  * counts and none of TPG_FORCE_TWO_PASS, TPG_STREAM, TPG_TP_GREEDY,
- * TPG_DIGEST, TPG_DIGEST_ONLY, a call that repeats the workspace's previous
+ * TPG_DIGEST, TPG_DIGEST_ONLY, TPG_NO_CALL_GRAPH, a call that repeats the workspace's previous
  * batched call (same graph handles, flags, stream, pool cap, predictions and
  * tuning) and whose predecessor allocated nothing is captured into one HIP
  * graph, and later repeats replay it: one launch and one wait instead of a

@@ -2475,45 +2475,63 @@ static tpg_status batch_body(CallCtx& c, const tpg_graph* const* graphs, int32_t
     if (c.stats) add_stats(c.stats, U, R, P, &T);
   }
 
-  // pack the unions' outputs graph by graph in caller order
-  std::vector<PackDesc> d_pp(n_graphs), d_tp(n_graphs);
+  // pack the unions' outputs graph by graph in caller order: per union and
+  // set one launch over its graphs' segments, cut into fixed-size chunks
+  const size_t nu = unions.size();
+  std::vector<PackDesc> desc(2 * (size_t)n_graphs);
+  std::vector<size_t> at(2 * nu + 1, 0);  // descriptors of (union, set) from at[2u + set]
+  for (size_t u = 0; u < nu; ++u) {
+    at[2 * u + 1] = at[2 * u] + unions[u].size();
+    at[2 * u + 2] = at[2 * u + 1] + unions[u].size();
+  }
+  std::vector<int64_t> n_chunks(2 * nu, 0);
   pp_first.assign(n_graphs + 1, 0);
   tp_first.assign(n_graphs + 1, 0);
   ppv = 0;
   tpv = 0;
   for (int32_t i = 0; i < n_graphs; ++i) {
-    const auto& S = starts[g_union[i]];
-    const int nc = (int)unions[g_union[i]].size();
+    const int u = g_union[i];
+    const auto& S = starts[u];
+    const int nc = (int)unions[u].size();
     const int k = g_comp[i];
     const int64_t p0 = S[k], p1 = S[k + 1], v0 = S[(nc + 1) + k], v1 = S[(nc + 1) + k + 1];
     const int64_t q0 = S[2 * (nc + 1) + k], q1 = S[2 * (nc + 1) + k + 1];
     const int64_t w0 = S[3 * (nc + 1) + k], w1 = S[3 * (nc + 1) + k + 1];
-    d_pp[i] = PackDesc{p0, p1 - p0, v0, v1 - v0, pp_first[i], ppv, g_union[i], 0};
-    d_tp[i] = PackDesc{q0, q1 - q0, w0, w1 - w0, tp_first[i], tpv, g_union[i], 0};
+    // graphs of a union are in caller order, so segment k of the union is graph i
+    PackDesc& dp = desc[at[2 * u] + k];
+    PackDesc& dt = desc[at[2 * u + 1] + k];
+    dp = PackDesc{p0, p1 - p0, v0, v1 - v0, pp_first[i], ppv, 0, 0};
+    dt = PackDesc{q0, q1 - q0, w0, w1 - w0, tp_first[i], tpv, 0, 0};
     pp_first[i + 1] = pp_first[i] + (p1 - p0);
     tp_first[i + 1] = tp_first[i] + (q1 - q0);
     ppv += v1 - v0;
     tpv += w1 - w0;
   }
+  for (size_t r = 0; r < 2 * nu; ++r)
+    for (size_t j = at[r]; j < at[r + 1]; ++j) {
+      desc[j].chunk0 = n_chunks[r];
+      n_chunks[r] += pack_chunks(desc[j]);
+    }
   TPG_TRY(ws_reserve(ws, ws->b_pp_off, sizeof(int64_t) * (pp_first[n_graphs] + 1)));
   TPG_TRY(ws_reserve(ws, ws->b_pp_vtx, sizeof(int32_t) * (ppv + 1)));
   TPG_TRY(ws_reserve(ws, ws->b_tp_off, sizeof(int64_t) * (tp_first[n_graphs] + 1)));
   TPG_TRY(ws_reserve(ws, ws->b_tp_vtx, sizeof(int32_t) * (tpv + 1)));
-  TPG_TRY(ws_reserve(ws, ws->b_desc, sizeof(PackDesc) * 2 * (size_t)n_graphs));
+  TPG_TRY(ws_reserve(ws, ws->b_desc, sizeof(PackDesc) * desc.size()));
   PackDesc* dd = ws->b_desc.as<PackDesc>();
-  TPG_HIP(hipMemcpyAsync(dd, io_src(ws, d_pp.data(), sizeof(PackDesc) * n_graphs),
-                         sizeof(PackDesc) * n_graphs, hipMemcpyHostToDevice, c.st));
-  TPG_HIP(hipMemcpyAsync(dd + n_graphs, io_src(ws, d_tp.data(), sizeof(PackDesc) * n_graphs),
-                         sizeof(PackDesc) * n_graphs, hipMemcpyHostToDevice, c.st));
-  // the packed descriptors are read by the kernels above; an ordinary call
-  // waits so the host vectors can go
+  TPG_HIP(hipMemcpyAsync(dd, io_src(ws, desc.data(), sizeof(PackDesc) * desc.size()),
+                         sizeof(PackDesc) * desc.size(), hipMemcpyHostToDevice, c.st));
+  // an ordinary call waits so the host vector can go (under capture the
+  // graph reads its staged copy)
   if (ws->io_mode != 2) TPG_HIP(hipStreamSynchronize(c.st));
-  for (size_t u = 0; u < unions.size(); ++u) {
+  for (size_t u = 0; u < nu; ++u) {
     OutSet& o = ws->out[u + 1];
-    TPG_HIP(launch_pack(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), dd, n_graphs, (int32_t)u,
-                        ws->b_pp_off.as<int64_t>(), ws->b_pp_vtx.as<int32_t>(), c.st));
-    TPG_HIP(launch_pack(o.tp_off.as<int64_t>(), o.tp_vtx.as<int32_t>(), dd + n_graphs, n_graphs,
-                        (int32_t)u, ws->b_tp_off.as<int64_t>(), ws->b_tp_vtx.as<int32_t>(), c.st));
+    const int32_t nd = (int32_t)unions[u].size();
+    TPG_HIP(launch_pack(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), dd + at[2 * u], nd,
+                        n_chunks[2 * u], ws->b_pp_off.as<int64_t>(), ws->b_pp_vtx.as<int32_t>(),
+                        c.st));
+    TPG_HIP(launch_pack(o.tp_off.as<int64_t>(), o.tp_vtx.as<int32_t>(), dd + at[2 * u + 1], nd,
+                        n_chunks[2 * u + 1], ws->b_tp_off.as<int64_t>(),
+                        ws->b_tp_vtx.as<int32_t>(), c.st));
   }
   TPG_HIP(launch_set_value_i64(ws->b_pp_off.as<int64_t>() + pp_first[n_graphs], ppv, c.st));
   TPG_HIP(launch_set_value_i64(ws->b_tp_off.as<int64_t>() + tp_first[n_graphs], tpv, c.st));
@@ -2557,7 +2575,7 @@ tpg_status tpg_batch_test_paths(const tpg_graph* const* graphs, int32_t n_graphs
   CallGraph& cg = ws->cg;
   const bool graphable = !tm.on && !want_levels &&
                          !(c.flags & (TPG_FORCE_TWO_PASS | TPG_STREAM | TPG_TP_GREEDY |
-                                      TPG_DIGEST | TPG_DIGEST_ONLY)) &&
+                                      TPG_DIGEST | TPG_DIGEST_ONLY | TPG_NO_CALL_GRAPH)) &&
                          c.opts && c.opts->ws;
   std::vector<uint8_t> key;
   if (graphable) {

@@ -289,16 +289,25 @@ hipError_t launch_set_i64(int64_t* p, const int64_t* src, hipStream_t st);
 hipError_t launch_set_value_i64(int64_t* p, int64_t value, hipStream_t st);
 
 // --- batched form --------------------------------------------------------------
-// One graph's segment of a union's output, and where it goes in the packed
-// output (caller order).
+// One graph's segment of a union's output, where it goes in the packed
+// output (caller order), and the first of its copy chunks in the launch
+// (its offsets in chunks of kPackPaths, then its entries in chunks of
+// kPackVtx).
+constexpr int kPackPaths = 1024;
+constexpr int kPackVtx = 4096;
 struct PackDesc {
   int64_t src_path, n_paths, src_v0, n_v;
   int64_t dst_path, dst_v;
-  int32_t union_id, pad;
+  int64_t chunk0;
+  int64_t pad;
 };
-// copies the segments of union `union_id` (one workgroup per descriptor)
+inline int64_t pack_chunks(const PackDesc& e) {
+  return (e.n_paths + kPackPaths - 1) / kPackPaths + (e.n_v + kPackVtx - 1) / kPackVtx;
+}
+// copies the segments d[0 .. n_desc) of one union (chunk0 ascending from 0;
+// n_chunks in all): one workgroup per chunk
 hipError_t launch_pack(const int64_t* src_off, const int32_t* src_vtx, const PackDesc* d,
-                       int32_t n_desc, int32_t union_id, int64_t* dst_off, int32_t* dst_vtx,
+                       int32_t n_desc, int64_t n_chunks, int64_t* dst_off, int32_t* dst_vtx,
                        hipStream_t st);
 // lvl_comp[c * 64 + min(L, 64) - 1] += paths of level L in component c
 hipError_t launch_level_comp_counts(const ExtArgs& a, int L, int64_t base, int64_t F,

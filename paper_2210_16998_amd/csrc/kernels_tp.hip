@@ -369,17 +369,23 @@ hipError_t launch_pack_tables(int n, const BfsOut& b, int eb, hipStream_t st) {
   return hipGetLastError();
 }
 
-// A workgroup splices kSplicePaths consecutive test paths: their layout goes
-// to LDS, then each thread builds one packed word (pe consecutive entries;
-// the words of the paths are one flat range).  A word that lies wholly in
-// the prefix is the same word of the first vertex's packed prefix row; one
-// that lies wholly in the suffix is cut from two consecutive words of the
-// last vertex's packed suffix row; only the words that hold prime-path
-// entries are built entry by entry (the keys come from k_tp_keys).  The
-// plain entries are written only when asked for (tp_vtx not null, every
-// word then built entry by entry): the comparisons read the packed words and
-// the kept paths are unpacked from them when gathered.
+// A workgroup splices kSplicePaths consecutive test paths.  Their layout
+// (where each one's prefix, prime-path and suffix entries are, and the word
+// offsets of its packed prefix and suffix rows) goes to LDS with a map of the
+// workgroup's packed words to their paths, then each thread builds one packed
+// word at a time (pe consecutive entries; the words of the paths are one flat
+// range).  A word that lies wholly in the prefix is the same word of the
+// first vertex's packed prefix row; one that lies wholly in the suffix is cut
+// from two consecutive words of the last vertex's packed suffix row; one that
+// lies wholly in the prime path packs pe consecutive prime-path entries; only
+// the words across two of these parts are built entry by entry (the keys come
+// from k_tp_keys).  The entry width is a compile-time constant, so the shifts
+// and the divisions by pe are constants: the kernel is bound by its work per
+// word.  The plain entries are written only when asked for (tp_vtx not
+// null, every word then built entry by entry): the comparisons read the
+// packed words and the kept paths are unpacked from them when gathered.
 constexpr int kSplicePaths = 64;
+constexpr int kSpliceMap = 8192;  // words a workgroup maps to paths in LDS
 
 struct SpliceRow {
   int64_t o0, p0, s0;  // prime-path entries, prefix table, suffix table
@@ -411,60 +417,88 @@ __device__ __forceinline__ int splice_entry(const SpliceRow& r, const int32_t* p
   return b.sfx[r.s0 + (k - r.lp - r.lq)];
 }
 
+template <int EB>
 __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, const int32_t* pp_vtx,
                                                      int64_t n_pp, BfsOut b, const int64_t* tp_off,
-                                                     int32_t* tp_vtx, uint64_t* key, uint64_t* pk,
-                                                     int eb, int32_t* idx) {
+                                                     int32_t* tp_vtx, uint64_t* pk, int32_t* idx) {
+  constexpr int pe = 64 / EB;
   __shared__ SpliceRow s_row[kSplicePaths];
-  __shared__ int64_t s_w[kSplicePaths + 1];  // entry offsets
-  __shared__ int64_t s_a[kSplicePaths + 1];  // packed-word offsets
-  const int pe = 64 / eb;
+  __shared__ int64_t s_w[kSplicePaths + 1];   // entry offsets
+  __shared__ int32_t s_a[kSplicePaths + 1];   // packed-word offsets from the first path's
+  __shared__ int64_t s_pb[kSplicePaths];      // first word of the packed prefix row
+  __shared__ int64_t s_sb[kSplicePaths];      // first word of the packed suffix row
+  __shared__ uint8_t s_map[kSpliceMap];       // word -> path
+  __shared__ int64_t s_a0;
   const int tid = (int)threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.x * kSplicePaths;
   const int cnt = (int)(n_pp - i0 < kSplicePaths ? n_pp - i0 : kSplicePaths);
+  int64_t a_mine = 0;
   if (tid < cnt) {
     const int64_t i = i0 + tid;
-    s_row[tid] = splice_row(pp_off, pp_vtx, b, i);
+    const SpliceRow r = splice_row(pp_off, pp_vtx, b, i);
+    s_row[tid] = r;
     const int64_t o = tp_off[i];
     s_w[tid] = o;
-    s_a[tid] = tp_pk_base(o, i, pe);
+    a_mine = tp_pk_base(o, i, pe);
+    s_pb[tid] = tbl_pk_base(r.p0, r.v1, pe);
+    s_sb[tid] = tbl_pk_base(r.s0, r.vk, pe);
     idx[i] = (int32_t)i;
   }
   if (tid == cnt) {
     const int64_t o = tp_off[i0 + cnt];
     s_w[cnt] = o;
-    s_a[cnt] = tp_pk_base(o, i0 + cnt, pe);
+    a_mine = tp_pk_base(o, i0 + cnt, pe);
   }
+  if (tid == 0) s_a0 = a_mine;
   __syncthreads();
-  const int64_t a0 = s_a[0], na = s_a[cnt] - a0;
-  for (int64_t s = tid; s < na; s += kBlock) {
-    const int64_t wi = a0 + s;
-    int lo = 0, hi = cnt - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (s_a[mid] <= wi) lo = mid; else hi = mid - 1;
+  const int64_t a0 = s_a0;
+  if (tid <= cnt) s_a[tid] = (int32_t)(a_mine - a0);
+  __syncthreads();
+  const int32_t na = s_a[cnt];
+  const bool mapped = na <= kSpliceMap;
+  if (mapped && tid < cnt)
+    for (int32_t w = s_a[tid]; w < s_a[tid + 1]; ++w) s_map[w] = (uint8_t)tid;
+  __syncthreads();
+  for (int32_t w = tid; w < na; w += kBlock) {
+    int t;
+    if (mapped) {
+      t = s_map[w];
+    } else {
+      int lo = 0, hi = cnt - 1;  // the last path whose words start at or before w
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_a[mid] <= w) lo = mid; else hi = mid - 1;
+      }
+      t = lo;
     }
-    const SpliceRow r = s_row[lo];
+    const SpliceRow r = s_row[t];
     const int len = r.lp + r.lq + r.ls;
-    const int q = (int)(wi - s_a[lo]);
+    const int q = w - s_a[t];
     const int k0 = q * pe;
     if (k0 >= len) continue;  // slack between two paths
-    uint64_t w = 0;
+    uint64_t word = 0;
     if (!tp_vtx && k0 + pe <= r.lp) {
-      w = b.pfx_pk[tbl_pk_base(r.p0, r.v1, pe) + q];
+      word = b.pfx_pk[s_pb[t] + q];
     } else if (!tp_vtx && k0 >= r.lp + r.lq) {
       const int j0 = k0 - r.lp - r.lq;  // first suffix entry of the word
       const int sq = j0 / pe, sr = j0 - sq * pe;
-      const uint64_t* row = b.sfx_pk + tbl_pk_base(r.s0, r.vk, pe);
+      const uint64_t* row = b.sfx_pk + s_sb[t];
       const uint64_t A = row[sq];
       if (sr == 0) {
-        w = A;
+        word = A;
       } else {
         // entries sr .. pe-1 of A, then entries 0 .. sr-1 of the next word
-        const int hb = (pe - sr) * eb;  // bits of A's entries sr .. pe-1
+        const int hb = (pe - sr) * EB;  // bits of A's entries sr .. pe-1
         const uint64_t B = row[sq + 1];
-        w = ((A & ((1ull << hb) - 1)) << (sr * eb)) | (B >> hb);
+        word = ((A & ((1ull << hb) - 1)) << (sr * EB)) | (B >> hb);
       }
+    } else if (pe <= 16 && !tp_vtx && k0 >= r.lp && k0 + pe <= r.lp + r.lq) {
+      const int32_t* src = pp_vtx + r.o0 + (k0 - r.lp);
+      int32_t x[pe <= 16 ? pe : 1];
+#pragma unroll
+      for (int j = 0; j < (pe <= 16 ? pe : 1); ++j) x[j] = src[j];
+#pragma unroll
+      for (int j = 0; j < (pe <= 16 ? pe : 1); ++j) word = (word << EB) | (uint64_t)(uint32_t)(x[j] + 1);
     } else {
       for (int q0 = 0; q0 < pe; q0 += 8) {  // eight entries at a time, loads in flight together
         int x[8];
@@ -479,15 +513,15 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
           if (q0 + j < pe) {
             uint64_t code = 0;
             if (k < len) {
-              if (tp_vtx) tp_vtx[s_w[lo] + k] = x[j];
+              if (tp_vtx) tp_vtx[s_w[t] + k] = x[j];
               code = (uint64_t)(x[j] + 1);
             }
-            w = (w << eb) | code;
+            word = (word << EB) | code;
           }
         }
       }
     }
-    pk[wi] = w;
+    pk[a0 + w] = word;
   }
 }
 
@@ -553,9 +587,21 @@ hipError_t launch_tp_write(const int64_t* pp_off, const int32_t* pp_vtx, int64_t
                            const BfsOut& b, const int64_t* tp_off, int32_t* tp_vtx,
                            uint64_t* key, uint64_t* pk, int eb, int32_t* idx, hipStream_t st) {
   if (n_pp == 0) return hipSuccess;
-  if (eb < 1 || eb > 32) return hipErrorInvalidValue;
-  k_tp_write<<<(unsigned)((n_pp + kSplicePaths - 1) / kSplicePaths), kBlock, 0, st>>>(
-      pp_off, pp_vtx, n_pp, b, tp_off, tp_vtx, key, pk, eb, idx);
+  const unsigned grid = (unsigned)((n_pp + kSplicePaths - 1) / kSplicePaths);
+#define TPG_SPLICE_CASE(E)                                                                  \
+  case E:                                                                                   \
+    k_tp_write<E><<<grid, kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, b, tp_off, tp_vtx, pk, idx); \
+    break;
+  switch (eb) {
+    TPG_SPLICE_CASE(1) TPG_SPLICE_CASE(2) TPG_SPLICE_CASE(3) TPG_SPLICE_CASE(4)
+    TPG_SPLICE_CASE(5) TPG_SPLICE_CASE(6) TPG_SPLICE_CASE(7) TPG_SPLICE_CASE(8)
+    TPG_SPLICE_CASE(9) TPG_SPLICE_CASE(10) TPG_SPLICE_CASE(11) TPG_SPLICE_CASE(12)
+    TPG_SPLICE_CASE(13) TPG_SPLICE_CASE(14) TPG_SPLICE_CASE(15) TPG_SPLICE_CASE(16)
+    TPG_SPLICE_CASE(17) TPG_SPLICE_CASE(18)
+    default:
+      return hipErrorInvalidValue;  // more than 2^18 - 1 vertices in one union
+  }
+#undef TPG_SPLICE_CASE
   k_tp_keys<<<(unsigned)((n_pp + kBlock - 1) / kBlock), kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, b,
                                                                         key, eb);
   return hipGetLastError();
@@ -851,16 +897,20 @@ hipError_t launch_gather(const int64_t* tp_off, const int32_t* tp_vtx, const int
 
 // A workgroup writes the kept paths among kGatherPaths consecutive sorted
 // positions from their packed words.  The kept paths are contiguous in the
-// output, so the workgroup's output is one range [d0, d0 + tot): the paths'
-// first words, lengths and entry counts go to LDS, then each thread produces
-// four consecutive entries of the range at a time (aligned to 16 bytes of
-// the output array) and stores them with one 16-byte store, so a wave writes
-// 1 KiB of consecutive addresses per instruction.  The aligned groups at the
-// two ends of the range are shared with the neighbouring workgroups' ranges;
-// there only the entries inside the range are stored, one by one.  Each
-// entry is read out of its packed word (pe entries of eb bits, first one
-// highest); neighbouring threads read the same words, which the cache serves.
+// output, so the workgroup's output is one range [d0, d0 + tot) and the
+// paths' packed words form one flat list.  The list is taken a window of
+// words at a time: each thread decodes whole words into an LDS copy of the
+// window's entries (the word's path from a map of the workgroup's words to
+// paths built in LDS, or a search over the paths when the list is longer
+// than the map; with the entry width a compile-time constant every entry is
+// a shift and a mask), then the window's entries go out as aligned 16-byte
+// stores, so a wave writes 1 KiB of consecutive addresses per instruction.
+// The aligned groups at the two ends of a window are shared with the
+// neighbouring windows (or workgroups); there only the entries inside the
+// window are stored, one by one.
 constexpr int kGatherPaths = 64;
+constexpr int kUnpackMap = 4096;  // words a workgroup maps to paths in LDS
+constexpr int kUnpackWin = 4096;  // entries of one window in LDS
 
 template <int EB>
 __global__ __launch_bounds__(kBlock) void k_unpack_gather(const int64_t* tp_off, const uint64_t* pk,
@@ -869,12 +919,16 @@ __global__ __launch_bounds__(kBlock) void k_unpack_gather(const int64_t* tp_off,
                                                           const int64_t* keep_voff,
                                                           const int64_t* keep_len,
                                                           int64_t* out_off, int32_t* out_vtx) {
-  __shared__ int64_t s_src[kGatherPaths];
-  __shared__ int32_t s_cum[kGatherPaths + 1];  // entries before each kept path
-  __shared__ int64_t s_dst0;
-  __shared__ int32_t s_w[kBlock / 64];
   constexpr int pe = 64 / EB;  // a compile-time divisor: no division per entry
   constexpr uint64_t emask = (1ull << EB) - 1;
+  constexpr int kWinWords = kUnpackWin / pe;
+  __shared__ int64_t s_src[kGatherPaths];
+  __shared__ int32_t s_cum[kGatherPaths + 1];  // entries before each kept path
+  __shared__ int32_t s_wc[kGatherPaths + 1];   // packed words before each kept path
+  __shared__ uint8_t s_map[kUnpackMap];        // word -> path
+  __shared__ int32_t s_e[kUnpackWin];          // the window's entries
+  __shared__ int64_t s_dst0;
+  __shared__ int32_t s_w[kBlock / 64];
   const int tid = (int)threadIdx.x;
   const int64_t k0 = (int64_t)blockIdx.x * kGatherPaths;
   const int cnt = (int)(n - k0 < kGatherPaths ? n - k0 : kGatherPaths);
@@ -890,44 +944,69 @@ __global__ __launch_bounds__(kBlock) void k_unpack_gather(const int64_t* tp_off,
     }
   }
   if (tid == 0) s_dst0 = keep_voff[k0];
-  int32_t tot;
+  int32_t tot, nw_tot;
   const int32_t ex = block_excl_scan<kBlock, int32_t>(len, tot, s_w);
-  if (tid < cnt) s_cum[tid] = ex;
-  if (tid == 0) s_cum[cnt] = tot;
+  const int32_t nw = (len + pe - 1) / pe;
+  const int32_t wx = block_excl_scan<kBlock, int32_t>(nw, nw_tot, s_w);
+  if (tid < cnt) {
+    s_cum[tid] = ex;
+    s_wc[tid] = wx;
+  }
+  if (tid == 0) {
+    s_cum[cnt] = tot;
+    s_wc[cnt] = nw_tot;
+  }
+  const bool mapped = nw_tot <= kUnpackMap;
+  if (mapped && tid < cnt)
+    for (int32_t w = 0; w < nw; ++w) s_map[wx + w] = (uint8_t)tid;
   __syncthreads();
   if (tot == 0) return;
-  const int64_t d0 = s_dst0, d1 = d0 + tot;
-  const int64_t a0 = d0 & ~(int64_t)3;  // first 16-byte group touching the range
-  const int64_t ngroups = (d1 - a0 + 3) >> 2;
-  for (int64_t gi = tid; gi < ngroups; gi += kBlock) {
-    const int64_t g0 = a0 + 4 * gi;
-    // kept path holding the group's first entry inside the range
-    const int32_t e0 = (int32_t)((g0 > d0 ? g0 : d0) - d0);
-    int lo = 0, hi = cnt - 1;
+  const int64_t d0 = s_dst0;
+  // the path of word w (w < nw_tot), and the first entry of word w
+  auto path_of = [&](int32_t w) -> int {
+    if (mapped) return s_map[w];
+    int lo = 0, hi = cnt - 1;  // the last path whose words start at or before w
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (s_cum[mid] <= e0) lo = mid; else hi = mid - 1;
+      if (s_wc[mid] <= w) lo = mid; else hi = mid - 1;
     }
-    int32_t x[4];
+    return lo;
+  };
+  auto entry_of = [&](int32_t w) -> int32_t {
+    if (w >= nw_tot) return tot;
+    const int t = path_of(w);
+    return s_cum[t] + (w - s_wc[t]) * pe;
+  };
+  for (int32_t w0 = 0; w0 < nw_tot; w0 += kWinWords) {
+    const int32_t w1 = w0 + kWinWords < nw_tot ? w0 + kWinWords : nw_tot;
+    const int32_t e_a = entry_of(w0), e_b = entry_of(w1);
+    for (int32_t w = w0 + tid; w < w1; w += kBlock) {
+      const int t = path_of(w);
+      const int32_t qw = w - s_wc[t];
+      const uint64_t word = pk[s_src[t] + qw];
+      const int32_t e0 = s_cum[t] + qw * pe;
+      const int32_t ne = s_cum[t + 1] - e0;  // entries of the path from this word on
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t gpos = g0 + j;
-      x[j] = 0;
-      if (gpos >= d0 && gpos < d1) {
-        const int32_t e = (int32_t)(gpos - d0);
-        while (e >= s_cum[lo + 1]) ++lo;  // next kept path (duplicates have no entries)
-        const int32_t r = e - s_cum[lo];
-        const uint64_t w = pk[s_src[lo] + r / pe];
-        x[j] = (int32_t)((w >> ((pe - 1 - r % pe) * EB)) & emask) - 1;
+      for (int j = 0; j < pe; ++j)
+        if (j < ne) s_e[e0 - e_a + j] = (int32_t)((word >> ((pe - 1 - j) * EB)) & emask) - 1;
+    }
+    __syncthreads();
+    const int64_t ga = d0 + e_a, gb = d0 + e_b;  // the window's output range
+    const int64_t g_first = ga & ~(int64_t)3;
+    const int64_t ngroups = (gb - g_first + 3) >> 2;
+    for (int64_t gi = tid; gi < ngroups; gi += kBlock) {
+      const int64_t g0 = g_first + 4 * gi;
+      const int32_t l0 = (int32_t)(g0 - ga);  // LDS position of the group's first entry
+      if (g0 >= ga && g0 + 4 <= gb) {
+        *reinterpret_cast<int4*>(out_vtx + g0) =
+            make_int4(s_e[l0], s_e[l0 + 1], s_e[l0 + 2], s_e[l0 + 3]);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (g0 + j >= ga && g0 + j < gb) out_vtx[g0 + j] = s_e[l0 + j];
       }
     }
-    if (g0 >= d0 && g0 + 4 <= d1) {
-      *reinterpret_cast<int4*>(out_vtx + g0) = make_int4(x[0], x[1], x[2], x[3]);
-    } else {
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (g0 + j >= d0 && g0 + j < d1) out_vtx[g0 + j] = x[j];
-    }
+    __syncthreads();
   }
 }
 
@@ -1055,21 +1134,42 @@ hipError_t launch_comp_bounds(const int64_t* off, const int32_t* vtx, int64_t n,
 // ---------------------------------------------------------------------------
 // batched form: packing in caller order
 // ---------------------------------------------------------------------------
+// One workgroup per chunk of a union's segments: the chunk's segment is the
+// last descriptor whose first chunk is at or before it (a segment with no
+// chunks shares its first chunk with the next one, which wins the search).
+// Fixed-size chunks keep the largest graphs of a batch from leaving one
+// workgroup copying long after the others are done.
 __global__ __launch_bounds__(kBlock) void k_pack(const int64_t* src_off, const int32_t* src_vtx,
-                                                 const PackDesc* d, int32_t union_id,
+                                                 const PackDesc* d, int32_t n_desc,
                                                  int64_t* dst_off, int32_t* dst_vtx) {
-  const PackDesc e = d[blockIdx.x];
-  if (e.union_id != union_id) return;
-  for (int64_t j = threadIdx.x; j < e.n_paths; j += kBlock)
-    dst_off[e.dst_path + j] = src_off[e.src_path + j] - e.src_v0 + e.dst_v;
-  for (int64_t q = threadIdx.x; q < e.n_v; q += kBlock) dst_vtx[e.dst_v + q] = src_vtx[e.src_v0 + q];
+  const int64_t b = blockIdx.x;
+  int lo = 0, hi = n_desc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d[mid].chunk0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const PackDesc e = d[lo];
+  const int64_t c = b - e.chunk0;
+  const int64_t n_oc = (e.n_paths + kPackPaths - 1) / kPackPaths;
+  if (c < n_oc) {
+    const int64_t j0 = c * kPackPaths, j1 = min(e.n_paths, j0 + kPackPaths);
+    const int64_t shift = e.dst_v - e.src_v0;
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += kBlock)
+      dst_off[e.dst_path + j] = src_off[e.src_path + j] + shift;
+  } else {
+    const int64_t q0 = (c - n_oc) * kPackVtx, q1 = min(e.n_v, q0 + kPackVtx);
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += kBlock)
+      dst_vtx[e.dst_v + q] = src_vtx[e.src_v0 + q];
+  }
 }
 
 hipError_t launch_pack(const int64_t* src_off, const int32_t* src_vtx, const PackDesc* d,
-                       int32_t n_desc, int32_t union_id, int64_t* dst_off, int32_t* dst_vtx,
+                       int32_t n_desc, int64_t n_chunks, int64_t* dst_off, int32_t* dst_vtx,
                        hipStream_t st) {
-  if (n_desc <= 0) return hipSuccess;
-  k_pack<<<(unsigned)n_desc, kBlock, 0, st>>>(src_off, src_vtx, d, union_id, dst_off, dst_vtx);
+  if (n_desc <= 0 || n_chunks <= 0) return hipSuccess;
+  if (n_chunks > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+  k_pack<<<(unsigned)n_chunks, kBlock, 0, st>>>(src_off, src_vtx, d, n_desc, dst_off, dst_vtx);
   return hipGetLastError();
 }
 

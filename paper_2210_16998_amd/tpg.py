@@ -27,6 +27,7 @@ TPG_DIGEST_ONLY = 0x10
 TPG_STREAM = 0x20
 TPG_ORDER_BY_LAST = 0x40
 TPG_TP_GREEDY = 0x80
+TPG_NO_CALL_GRAPH = 0x100
 # strongly connected components and prime-path types (Sec. 2, Defs. 2-10)
 TPG_SCC_CYCLIC, TPG_SCC_ENTRY_VERTEX, TPG_SCC_EXIT_VERTEX = 0x1, 0x2, 0x4
 TPG_PP_COMPLETE, TPG_PP_SCC_INTERNAL, TPG_PP_SCC_EXIT, TPG_PP_SCC_ENTRY, TPG_PP_OTHER = 1, 2, 3, 4, 5
