@@ -717,9 +717,12 @@ __device__ __forceinline__ int64_t merge_split_wave(const TpOrder& K, const int3
 // it finds its input slices with two merge-path searches, stages their
 // indices and keys in LDS, and every thread then splits and merges its own
 // kMergeItems outputs from LDS (the entries themselves are read only when
-// two paths share their tree prefix and next entry).
-constexpr int kMergeThreads = 512;
-constexpr int kMergeItems = 2;
+// two paths share their tree prefix and next entry).  A thread's split costs
+// a binary search over the tile, so several outputs per thread mean fewer
+// comparisons per output; 256 threads of 6 outputs timed fastest on the
+// stress CFG among 128..512 threads of 2..8 outputs.
+constexpr int kMergeThreads = 256;
+constexpr int kMergeItems = 6;
 constexpr int kMergeTile = kMergeThreads * kMergeItems;
 
 __global__ __launch_bounds__(kMergeThreads) void k_merge_round(TpOrder K, const int32_t* in,
