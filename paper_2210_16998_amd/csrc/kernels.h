@@ -233,8 +233,11 @@ struct BfsOut {
   uint64_t* sfx_pk;  // suffix rows packed likewise
 };
 // What the test-path comparison reads: per test path kTpKeyWords 64-bit keys
-// (see k_tp_write) and, for the rare ties the keys leave, the entries.
-constexpr int kTpKeyWords = 3;
+// (see k_tp_keys: two words of tree position, then kTpKeyTail words of the
+// entries after the tree prefix) and, for the ties the keys leave, the
+// packed entries.
+constexpr int kTpKeyTail = 4;
+constexpr int kTpKeyWords = 2 + kTpKeyTail;
 struct TpOrder {
   const int64_t* off;   // [n + 1] test-path offsets
   const uint64_t* key;  // [kTpKeyWords n]

@@ -313,9 +313,10 @@ hipError_t launch_tp_len(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n
 //    when none; pre(w) + 1 when there is no e).
 // k1 = pre(w) | pend(w) << 18 | D << 36 | (e exists) << 49
 // k2 = e | split << 17 | pre(u) << 35
-// k3 = the P = 64 / eb entries after e, each as entry + 1 in eb bits (0 past
-//      the end), the first one highest: comparing k3 compares those entries
-//      lexicographically, a path that ends first being the smaller
+// k3 .. = kTpKeyTail words of the entries after e, P = 64 / eb to a word,
+//      each as entry + 1 in eb bits (0 past the end), the first one highest:
+//      comparing them word by word compares those entries lexicographically,
+//      a path that ends first being the smaller
 constexpr uint64_t kM17 = (1ull << 17) - 1, kM18 = (1ull << 18) - 1, kM13 = (1ull << 13) - 1;
 
 // Packed copy of test path x (entry offset off): its entries, each as
@@ -417,11 +418,36 @@ __device__ __forceinline__ int splice_entry(const SpliceRow& r, const int32_t* p
   return b.sfx[r.s0 + (k - r.lp - r.lq)];
 }
 
+// Entries k .. k + pe - 1 of a packed test path (words p, len entries) in
+// the packed word format, entries past the end 0: cut from two consecutive
+// words, the second read only when the window reaches into it.
+__device__ __forceinline__ uint64_t packed_window(const uint64_t* p, int64_t len, int64_t k, int pe,
+                                                  int eb) {
+  if (k >= len) return 0;
+  const int64_t q = k / pe;
+  const int r = (int)(k - q * pe);
+  uint64_t w = p[q];
+  if (r != 0) {
+    const int hb = (pe - r) * eb;  // bits of the first word's entries r .. pe-1
+    w = (w & ((1ull << hb) - 1)) << (r * eb);
+    if (k + (pe - r) < len) w |= p[q + 1] >> hb;
+  }
+  const int64_t nv = len - k;
+  if (nv < pe) w &= ~((1ull << ((pe - nv) * eb)) - 1);
+  return w;
+}
+
 template <int EB>
 __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, const int32_t* pp_vtx,
                                                      int64_t n_pp, BfsOut b, const int64_t* tp_off,
-                                                     int32_t* tp_vtx, uint64_t* pk, int32_t* idx) {
+                                                     int32_t* tp_vtx, uint64_t* pk, uint64_t* key,
+                                                     int32_t* idx) {
   constexpr int pe = 64 / EB;
+  // the words each key's entry windows are cut from (k_tp_keys has stored
+  // where the window starts), kept as they are built
+  __shared__ uint64_t s_kw[kSplicePaths][kTpKeyTail + 1];
+  __shared__ int32_t s_kf[kSplicePaths];  // first entry of the windows
+  __shared__ int32_t s_kq[kSplicePaths];  // its word
   __shared__ SpliceRow s_row[kSplicePaths];
   __shared__ int64_t s_w[kSplicePaths + 1];   // entry offsets
   __shared__ int32_t s_a[kSplicePaths + 1];   // packed-word offsets from the first path's
@@ -443,6 +469,12 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
     s_pb[tid] = tbl_pk_base(r.p0, r.v1, pe);
     s_sb[tid] = tbl_pk_base(r.s0, r.vk, pe);
     idx[i] = (int32_t)i;
+    // the entries after e start two past the tree prefix's last entry
+    const int32_t f = (int32_t)((key[(int64_t)kTpKeyWords * i] >> 36) & kM13) + 2;
+    s_kf[tid] = f;
+    s_kq[tid] = f / pe;
+#pragma unroll
+    for (int j = 0; j <= kTpKeyTail; ++j) s_kw[tid][j] = 0;
   }
   if (tid == cnt) {
     const int64_t o = tp_off[i0 + cnt];
@@ -522,6 +554,17 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
       }
     }
     pk[a0 + w] = word;
+    const int kq = q - s_kq[t];
+    if (kq >= 0 && kq <= kTpKeyTail) s_kw[t][kq] = word;
+  }
+  __syncthreads();
+  // the key's entry words: windows of pe entries from the first entry after e
+  for (int u = tid; u < cnt * kTpKeyTail; u += kBlock) {
+    const int t = u / kTpKeyTail, j = u - t * kTpKeyTail;
+    const SpliceRow& r = s_row[t];
+    const int64_t len = (int64_t)r.lp + r.lq + r.ls - (int64_t)s_kq[t] * pe;  // from word s_kq
+    const int64_t k = (int64_t)(s_kf[t] - s_kq[t] * pe) + (int64_t)j * pe;
+    key[(int64_t)kTpKeyWords * (i0 + t) + 2 + j] = packed_window(s_kw[t], len, k, pe, EB);
   }
 }
 
@@ -531,7 +574,7 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
 // depth, the entry after it and the split rank, and the next pe entries.
 // One thread per test path.
 __global__ __launch_bounds__(kBlock) void k_tp_keys(const int64_t* pp_off, const int32_t* pp_vtx,
-                                                    int64_t n_pp, BfsOut b, uint64_t* key, int eb) {
+                                                    int64_t n_pp, BfsOut b, uint64_t* key) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n_pp) {
     const SpliceRow r = splice_row(pp_off, pp_vtx, b, i);
@@ -572,14 +615,11 @@ __global__ __launch_bounds__(kBlock) void k_tp_keys(const int64_t* pp_off, const
     } else {
       split = prew + 1;
     }
-    uint64_t k3 = 0;
-    for (int q = first + 1; q < first + 1 + 64 / eb; ++q)
-      k3 = (k3 << eb) | (q < len ? (uint64_t)(splice_entry(r, pp_vtx, b, q) + 1) : 0ull);
     uint64_t* kk = key + (int64_t)kTpKeyWords * i;
     kk[0] = (uint64_t)prew | ((uint64_t)pendw << 18) | ((uint64_t)(first - 1) << 36) |
             ((uint64_t)(has_e ? 1 : 0) << 49);
     kk[1] = (uint64_t)(uint32_t)ev | ((uint64_t)split << 17) | ((uint64_t)(uint32_t)b.pre[r.v1] << 35);
-    kk[2] = k3;
+    // the words of entries after e come from k_tp_write, which runs next
   }
 }
 
@@ -587,10 +627,14 @@ hipError_t launch_tp_write(const int64_t* pp_off, const int32_t* pp_vtx, int64_t
                            const BfsOut& b, const int64_t* tp_off, int32_t* tp_vtx,
                            uint64_t* key, uint64_t* pk, int eb, int32_t* idx, hipStream_t st) {
   if (n_pp == 0) return hipSuccess;
+  if (eb < 1 || eb > 18) return hipErrorInvalidValue;  // more than 2^18 - 1 vertices in one union
+  // the tree-position keys first: the splice cuts the entry words after e
+  k_tp_keys<<<(unsigned)((n_pp + kBlock - 1) / kBlock), kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, b,
+                                                                        key);
   const unsigned grid = (unsigned)((n_pp + kSplicePaths - 1) / kSplicePaths);
-#define TPG_SPLICE_CASE(E)                                                                  \
-  case E:                                                                                   \
-    k_tp_write<E><<<grid, kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, b, tp_off, tp_vtx, pk, idx); \
+#define TPG_SPLICE_CASE(E)                                                                     \
+  case E:                                                                                      \
+    k_tp_write<E><<<grid, kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, b, tp_off, tp_vtx, pk, key, idx); \
     break;
   switch (eb) {
     TPG_SPLICE_CASE(1) TPG_SPLICE_CASE(2) TPG_SPLICE_CASE(3) TPG_SPLICE_CASE(4)
@@ -599,11 +643,9 @@ hipError_t launch_tp_write(const int64_t* pp_off, const int32_t* pp_vtx, int64_t
     TPG_SPLICE_CASE(13) TPG_SPLICE_CASE(14) TPG_SPLICE_CASE(15) TPG_SPLICE_CASE(16)
     TPG_SPLICE_CASE(17) TPG_SPLICE_CASE(18)
     default:
-      return hipErrorInvalidValue;  // more than 2^18 - 1 vertices in one union
+      return hipErrorInvalidValue;
   }
 #undef TPG_SPLICE_CASE
-  k_tp_keys<<<(unsigned)((n_pp + kBlock - 1) / kBlock), kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, b,
-                                                                        key, eb);
   return hipGetLastError();
 }
 
@@ -642,20 +684,23 @@ __device__ __forceinline__ int tp_cmp_tail(const TpOrder& K, int64_t x, int64_t 
   return lx < ly ? -1 : (lx > ly ? 1 : 0);
 }
 
-// Lexicographic comparison of test paths x and y from their keys (a*: k1,
-// b*: k2, c*: k3):
+// Lexicographic comparison of test paths x and y from their keys (kx(i),
+// ky(i): key word i; word 0 holds pre(w), pend(w) and the prefix depth, word
+// 1 the entry e, split and the prime path's first vertex, words 2.. the
+// entries after e):
 //  * same prime-path first vertex: the order of the prime paths (indices);
 //  * same tree prefix w: no e sorts first (equal when both end there), then
-//    e decides, then the entries after e: the ones packed in k3, then, when
-//    k3 ties and neither path ended inside it, the rest read from memory;
+//    e decides, then the entries after e: the ones packed in the keys, then,
+//    when those tie and neither path ended inside them, the rest read from
+//    memory;
 //  * w_x a proper ancestor of w_y: t_y continues with the tree child c of
 //    w_x towards w_y, t_x with e_x (not a tree child), and e_x < c exactly
 //    when pre(w_y) < split_x; symmetric the other way round;
 //  * otherwise the tree prefixes differ first and preorder decides.
-__device__ __forceinline__ int tp_cmp_keys(const TpOrder& K, int64_t x, uint64_t ax, uint64_t bx,
-                                           uint64_t cx, int64_t y, uint64_t ay, uint64_t by,
-                                           uint64_t cy) {
+template <class KX, class KY>
+__device__ __forceinline__ int tp_cmp_keys(const TpOrder& K, int64_t x, KX kx, int64_t y, KY ky) {
   if (x == y) return 0;
+  const uint64_t ax = kx(0), ay = ky(0), bx = kx(1), by = ky(1);
   if ((bx >> 35) == (by >> 35)) return x < y ? -1 : 1;
   const uint32_t pwx = (uint32_t)(ax & kM18), pwy = (uint32_t)(ay & kM18);
   if (pwx == pwy) {
@@ -663,9 +708,13 @@ __device__ __forceinline__ int tp_cmp_keys(const TpOrder& K, int64_t x, uint64_t
     if (!hx || !hy) return hx == hy ? 0 : (hx ? 1 : -1);
     const uint32_t ex = (uint32_t)(bx & kM17), ey = (uint32_t)(by & kM17);
     if (ex != ey) return ex < ey ? -1 : 1;
-    if (cx != cy) return cx < cy ? -1 : 1;
-    if ((cx & ((1ull << K.eb) - 1)) == 0) return 0;  // both ended inside k3
-    return tp_cmp_tail(K, x, y, (int64_t)((ax >> 36) & kM13) + 2 + K.pe);
+#pragma unroll
+    for (int t = 0; t < kTpKeyTail; ++t) {
+      const uint64_t cx = kx(2 + t), cy = ky(2 + t);
+      if (cx != cy) return cx < cy ? -1 : 1;
+      if ((cx & ((1ull << K.eb) - 1)) == 0) return 0;  // both ended inside this word
+    }
+    return tp_cmp_tail(K, x, y, (int64_t)((ax >> 36) & kM13) + 2 + (int64_t)kTpKeyTail * K.pe);
   }
   const uint32_t pex = (uint32_t)((ax >> 18) & kM18), pey = (uint32_t)((ay >> 18) & kM18);
   if (pwx < pwy && pwy < pex) return pwy >= (uint32_t)((bx >> 17) & kM18) ? -1 : 1;
@@ -673,12 +722,12 @@ __device__ __forceinline__ int tp_cmp_keys(const TpOrder& K, int64_t x, uint64_t
   return pwx < pwy ? -1 : 1;
 }
 
-// The same, loading the keys (x, y: test-path indices).
+// The same, reading the keys from memory (x, y: test-path indices).
 __device__ __forceinline__ int tp_cmp(const TpOrder& K, int64_t x, int64_t y) {
   if (x == y) return 0;
   const uint64_t* kx = K.key + (int64_t)kTpKeyWords * x;
   const uint64_t* ky = K.key + (int64_t)kTpKeyWords * y;
-  return tp_cmp_keys(K, x, kx[0], kx[1], kx[2], y, ky[0], ky[1], ky[2]);
+  return tp_cmp_keys(K, x, [kx](int i) { return kx[i]; }, y, [ky](int i) { return ky[i]; });
 }
 
 // Merge path: number of elements taken from A among the first d outputs of
@@ -722,16 +771,14 @@ __device__ __forceinline__ int64_t merge_split_wave(const TpOrder& K, const int3
 // comparisons per output; 256 threads of 6 outputs timed fastest on the
 // stress CFG among 128..512 threads of 2..8 outputs.
 constexpr int kMergeThreads = 256;
-constexpr int kMergeItems = 6;
+constexpr int kMergeItems = 4;
 constexpr int kMergeTile = kMergeThreads * kMergeItems;
 
 __global__ __launch_bounds__(kMergeThreads) void k_merge_round(TpOrder K, const int32_t* in,
                                                                int32_t* out, const int64_t* rb,
                                                                int64_t n_runs, int64_t n) {
   __shared__ int32_t s_idx[kMergeTile];
-  __shared__ uint64_t s_k1[kMergeTile];
-  __shared__ uint64_t s_k2[kMergeTile];
-  __shared__ uint64_t s_k3[kMergeTile];
+  __shared__ uint64_t s_key[kTpKeyWords][kMergeTile];
   __shared__ int64_t s_seg[4];
   const int tid = (int)threadIdx.x;
   const int64_t t0 = (int64_t)blockIdx.x * kMergeTile;
@@ -767,9 +814,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_round(TpOrder K, const 
       const int32_t x = q < la ? A[ia + q] : B[ja + (q - la)];
       s_idx[q] = x;
       const uint64_t* kx = K.key + (int64_t)kTpKeyWords * x;
-      s_k1[q] = kx[0];
-      s_k2[q] = kx[1];
-      s_k3[q] = kx[2];
+#pragma unroll
+      for (int t = 0; t < kTpKeyWords; ++t) s_key[t][q] = kx[t];
     }
     __syncthreads();
     // this thread's outputs within the segment, merged from LDS
@@ -781,8 +827,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_round(TpOrder K, const 
       while (l2 < h2) {
         const int mid = (l2 + h2) >> 1;
         const int qb = la + (d0 - 1 - mid);
-        if (tp_cmp_keys(K, s_idx[qb], s_k1[qb], s_k2[qb], s_k3[qb], s_idx[mid], s_k1[mid],
-                        s_k2[mid], s_k3[mid]) >= 0)
+        if (tp_cmp_keys(K, s_idx[qb], [&](int t) { return s_key[t][qb]; }, s_idx[mid],
+                        [&](int t) { return s_key[t][mid]; }) >= 0)
           l2 = mid + 1;
         else
           h2 = mid;
@@ -794,8 +840,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_round(TpOrder K, const 
         else if (i >= la) take_a = false;
         else {
           const int qb = la + j;
-          take_a = tp_cmp_keys(K, s_idx[qb], s_k1[qb], s_k2[qb], s_k3[qb], s_idx[i], s_k1[i],
-                                   s_k2[i], s_k3[i]) >= 0;
+          take_a = tp_cmp_keys(K, s_idx[qb], [&](int t) { return s_key[t][qb]; }, s_idx[i],
+                               [&](int t) { return s_key[t][i]; }) >= 0;
         }
         out[pos + o] = take_a ? s_idx[i++] : s_idx[la + j++];
       }
