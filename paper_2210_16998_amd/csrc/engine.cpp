@@ -1099,7 +1099,8 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
   T.n_vtx = ws->h_scalars[3];
   TPG_TRY(ws_reserve(ws, o.tp_off, sizeof(int64_t) * (T.n_tp + 1)));
   TPG_TRY(ws_reserve(ws, o.tp_vtx, sizeof(int32_t) * (T.n_vtx + 1)));
-  TPG_HIP(launch_unpack_gather(ws->tp_off.as<int64_t>(), ws->tp_pk.as<uint64_t>(), eb,
+  TPG_HIP(launch_unpack_gather(ws->tp_off.as<int64_t>(), ws->tp_pk.as<uint64_t>(),
+                               o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), b, eb,
                                ii->as<int32_t>(), nm, ws->keep_pos.as<int64_t>(),
                                ws->keep_voff.as<int64_t>(), ws->keep_len.as<int64_t>(),
                                o.tp_off.as<int64_t>(), o.tp_vtx.as<int32_t>(), st));

@@ -279,8 +279,11 @@ hipError_t launch_gather(const int64_t* tp_off, const int32_t* tp_vtx, const int
                          const int64_t* keep_len, int64_t* out_off, int32_t* out_vtx,
                          hipStream_t st);
 // the same for test paths held packed (tp_off: their entry offsets, pk: the
-// words k_tp_write built with eb bits per entry)
-hipError_t launch_unpack_gather(const int64_t* tp_off, const uint64_t* pk, int eb,
+// words k_tp_write built with eb bits per entry; the words that hold only
+// prefix entries come from the packed prefix rows in b, test path a having
+// been spliced from prime path a of pp_off / pp_vtx)
+hipError_t launch_unpack_gather(const int64_t* tp_off, const uint64_t* pk, const int64_t* pp_off,
+                                const int32_t* pp_vtx, const BfsOut& b, int eb,
                                 const int32_t* idx, int64_t n, const int64_t* keep_pos,
                                 const int64_t* keep_voff, const int64_t* keep_len,
                                 int64_t* out_off, int32_t* out_vtx, hipStream_t st);

@@ -372,19 +372,23 @@ hipError_t launch_pack_tables(int n, const BfsOut& b, int eb, hipStream_t st) {
 
 // A workgroup splices kSplicePaths consecutive test paths.  Their layout
 // (where each one's prefix, prime-path and suffix entries are, and the word
-// offsets of its packed prefix and suffix rows) goes to LDS with a map of the
-// workgroup's packed words to their paths, then each thread builds one packed
-// word at a time (pe consecutive entries; the words of the paths are one flat
-// range).  A word that lies wholly in the prefix is the same word of the
-// first vertex's packed prefix row; one that lies wholly in the suffix is cut
-// from two consecutive words of the last vertex's packed suffix row; one that
-// lies wholly in the prime path packs pe consecutive prime-path entries; only
-// the words across two of these parts are built entry by entry (the keys come
-// from k_tp_keys).  The entry width is a compile-time constant, so the shifts
-// and the divisions by pe are constants: the kernel is bound by its work per
-// word.  The plain entries are written only when asked for (tp_vtx not
-// null, every word then built entry by entry): the comparisons read the
-// packed words and the kept paths are unpacked from them when gathered.
+// offset of its packed suffix row) goes to LDS with a map of the workgroup's
+// packed words to their paths, then each thread builds one packed word at a
+// time (pe consecutive entries; the words of the paths are one flat range).
+// A word that lies wholly in the prefix is not written: it is the same word
+// of the first vertex's packed prefix row, from which the unpack takes it,
+// and no comparison reads it (they start past the prime path's first
+// vertex).  A word that lies wholly in the suffix is cut from two
+// consecutive words of the last vertex's packed suffix row; one that lies
+// wholly in the prime path packs pe consecutive prime-path entries; only the
+// words across two of these parts are built entry by entry.  The entry width
+// is a compile-time constant, so the shifts and the divisions by pe are
+// constants: the kernel is bound by its work per word.  The words the key's
+// entry windows start in are kept in LDS, and after a barrier the windows
+// (k_tp_keys has stored where they start) are cut from them.  The plain
+// entries are written only when asked for (tp_vtx not null, every word then
+// built entry by entry): the comparisons read the packed words and the kept
+// paths are unpacked from them when gathered.
 constexpr int kSplicePaths = 64;
 constexpr int kSpliceMap = 8192;  // words a workgroup maps to paths in LDS
 
@@ -451,7 +455,6 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
   __shared__ SpliceRow s_row[kSplicePaths];
   __shared__ int64_t s_w[kSplicePaths + 1];   // entry offsets
   __shared__ int32_t s_a[kSplicePaths + 1];   // packed-word offsets from the first path's
-  __shared__ int64_t s_pb[kSplicePaths];      // first word of the packed prefix row
   __shared__ int64_t s_sb[kSplicePaths];      // first word of the packed suffix row
   __shared__ uint8_t s_map[kSpliceMap];       // word -> path
   __shared__ int64_t s_a0;
@@ -466,7 +469,6 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
     const int64_t o = tp_off[i];
     s_w[tid] = o;
     a_mine = tp_pk_base(o, i, pe);
-    s_pb[tid] = tbl_pk_base(r.p0, r.v1, pe);
     s_sb[tid] = tbl_pk_base(r.s0, r.vk, pe);
     idx[i] = (int32_t)i;
     // the entries after e start two past the tree prefix's last entry
@@ -510,7 +512,7 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
     if (k0 >= len) continue;  // slack between two paths
     uint64_t word = 0;
     if (!tp_vtx && k0 + pe <= r.lp) {
-      word = b.pfx_pk[s_pb[t] + q];
+      continue;  // wholly in the prefix: left to the packed prefix row
     } else if (!tp_vtx && k0 >= r.lp + r.lq) {
       const int j0 = k0 - r.lp - r.lq;  // first suffix entry of the word
       const int sq = j0 / pe, sr = j0 - sq * pe;
@@ -963,6 +965,8 @@ constexpr int kUnpackWin = 4096;  // entries of one window in LDS
 
 template <int EB>
 __global__ __launch_bounds__(kBlock) void k_unpack_gather(const int64_t* tp_off, const uint64_t* pk,
+                                                          const int64_t* pp_off,
+                                                          const int32_t* pp_vtx, BfsOut b,
                                                           const int32_t* idx, int64_t n,
                                                           const int64_t* keep_pos,
                                                           const int64_t* keep_voff,
@@ -972,6 +976,8 @@ __global__ __launch_bounds__(kBlock) void k_unpack_gather(const int64_t* tp_off,
   constexpr uint64_t emask = (1ull << EB) - 1;
   constexpr int kWinWords = kUnpackWin / pe;
   __shared__ int64_t s_src[kGatherPaths];
+  __shared__ int64_t s_pfx[kGatherPaths];      // first word of the path's packed prefix row
+  __shared__ int32_t s_lpw[kGatherPaths];      // its words that hold prefix entries only
   __shared__ int32_t s_cum[kGatherPaths + 1];  // entries before each kept path
   __shared__ int32_t s_wc[kGatherPaths + 1];   // packed words before each kept path
   __shared__ uint8_t s_map[kUnpackMap];        // word -> path
@@ -986,9 +992,17 @@ __global__ __launch_bounds__(kBlock) void k_unpack_gather(const int64_t* tp_off,
     const int64_t k = k0 + tid;
     len = (int32_t)keep_len[k];  // 0 for a duplicate (every kept path has >= 1 entry)
     s_src[tid] = 0;
+    s_pfx[tid] = 0;
+    s_lpw[tid] = 0;
     if (len) {
       const int64_t a = idx[k];
       s_src[tid] = tp_pk_base(tp_off[a], a, pe);
+      // test path a was spliced from prime path a: its prefix is the packed
+      // prefix row of that path's first vertex
+      const int v1 = pp_vtx[pp_off[a]];
+      const int64_t p0 = b.pfx_off[v1];
+      s_pfx[tid] = tbl_pk_base(p0, v1, pe);
+      s_lpw[tid] = (int32_t)((b.pfx_off[v1 + 1] - p0) / pe);
       out_off[keep_pos[k]] = keep_voff[k];
     }
   }
@@ -1032,7 +1046,7 @@ __global__ __launch_bounds__(kBlock) void k_unpack_gather(const int64_t* tp_off,
     for (int32_t w = w0 + tid; w < w1; w += kBlock) {
       const int t = path_of(w);
       const int32_t qw = w - s_wc[t];
-      const uint64_t word = pk[s_src[t] + qw];
+      const uint64_t word = qw < s_lpw[t] ? b.pfx_pk[s_pfx[t] + qw] : pk[s_src[t] + qw];
       const int32_t e0 = s_cum[t] + qw * pe;
       const int32_t ne = s_cum[t + 1] - e0;  // entries of the path from this word on
 #pragma unroll
@@ -1059,7 +1073,8 @@ __global__ __launch_bounds__(kBlock) void k_unpack_gather(const int64_t* tp_off,
   }
 }
 
-hipError_t launch_unpack_gather(const int64_t* tp_off, const uint64_t* pk, int eb,
+hipError_t launch_unpack_gather(const int64_t* tp_off, const uint64_t* pk, const int64_t* pp_off,
+                                const int32_t* pp_vtx, const BfsOut& b, int eb,
                                 const int32_t* idx, int64_t n, const int64_t* keep_pos,
                                 const int64_t* keep_voff, const int64_t* keep_len,
                                 int64_t* out_off, int32_t* out_vtx, hipStream_t st) {
@@ -1067,8 +1082,9 @@ hipError_t launch_unpack_gather(const int64_t* tp_off, const uint64_t* pk, int e
   const unsigned grid = (unsigned)((n + kGatherPaths - 1) / kGatherPaths);
 #define TPG_UNPACK_CASE(E)                                                                  \
   case E:                                                                                   \
-    k_unpack_gather<E><<<grid, kBlock, 0, st>>>(tp_off, pk, idx, n, keep_pos, keep_voff,    \
-                                                keep_len, out_off, out_vtx);                \
+    k_unpack_gather<E><<<grid, kBlock, 0, st>>>(tp_off, pk, pp_off, pp_vtx, b, idx, n,      \
+                                                keep_pos, keep_voff, keep_len, out_off,     \
+                                                out_vtx);                                   \
     break;
   switch (eb) {
     TPG_UNPACK_CASE(1) TPG_UNPACK_CASE(2) TPG_UNPACK_CASE(3) TPG_UNPACK_CASE(4)
