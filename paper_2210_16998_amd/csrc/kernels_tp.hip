@@ -391,6 +391,7 @@ hipError_t launch_pack_tables(int n, const BfsOut& b, int eb, hipStream_t st) {
 // paths are unpacked from them when gathered.
 constexpr int kSplicePaths = 64;
 constexpr int kSpliceMap = 8192;  // words a workgroup maps to paths in LDS
+constexpr int kSpliceMixed = 512;  // words across two parts listed per workgroup
 
 struct SpliceRow {
   int64_t o0, p0, s0;  // prime-path entries, prefix table, suffix table
@@ -452,6 +453,9 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
   __shared__ uint64_t s_kw[kSplicePaths][kTpKeyTail + 1];
   __shared__ int32_t s_kf[kSplicePaths];  // first entry of the windows
   __shared__ int32_t s_kq[kSplicePaths];  // its word
+  // words across two parts, built after the others (see below)
+  __shared__ int32_t s_mix[kSpliceMixed];
+  __shared__ int32_t s_nmix;
   __shared__ SpliceRow s_row[kSplicePaths];
   __shared__ int64_t s_w[kSplicePaths + 1];   // entry offsets
   __shared__ int32_t s_a[kSplicePaths + 1];   // packed-word offsets from the first path's
@@ -483,7 +487,10 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
     s_w[cnt] = o;
     a_mine = tp_pk_base(o, i0 + cnt, pe);
   }
-  if (tid == 0) s_a0 = a_mine;
+  if (tid == 0) {
+    s_a0 = a_mine;
+    s_nmix = 0;
+  }
   __syncthreads();
   const int64_t a0 = s_a0;
   if (tid <= cnt) s_a[tid] = (int32_t)(a_mine - a0);
@@ -493,27 +500,70 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
   if (mapped && tid < cnt)
     for (int32_t w = s_a[tid]; w < s_a[tid + 1]; ++w) s_map[w] = (uint8_t)tid;
   __syncthreads();
-  for (int32_t w = tid; w < na; w += kBlock) {
-    int t;
-    if (mapped) {
-      t = s_map[w];
-    } else {
-      int lo = 0, hi = cnt - 1;  // the last path whose words start at or before w
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_a[mid] <= w) lo = mid; else hi = mid - 1;
-      }
-      t = lo;
+  // the path of word w
+  auto path_of = [&](int32_t w) -> int {
+    if (mapped) return s_map[w];
+    int lo = 0, hi = cnt - 1;  // the last path whose words start at or before w
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_a[mid] <= w) lo = mid; else hi = mid - 1;
     }
+    return lo;
+  };
+  // stores word w of path t and keeps it when a key window starts in it
+  auto store = [&](int32_t w, int t, int q, uint64_t word) {
+    pk[a0 + w] = word;
+    const int kq = q - s_kq[t];
+    if (kq >= 0 && kq <= kTpKeyTail) s_kw[t][kq] = word;
+  };
+  // a word across two (or three) parts, entry by entry
+  auto build_mixed = [&](int32_t w, int t) {
+    const SpliceRow r = s_row[t];
+    const int len = r.lp + r.lq + r.ls;
+    const int q = w - s_a[t];
+    const int k0 = q * pe;
+    uint64_t word = 0;
+    for (int q0 = 0; q0 < pe; q0 += 8) {  // eight entries at a time, loads in flight together
+      int x[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + q0 + j;
+        x[j] = q0 + j < pe && k < len ? splice_entry(r, pp_vtx, b, k) : -1;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + q0 + j;
+        if (q0 + j < pe) {
+          uint64_t code = 0;
+          if (k < len) {
+            if (tp_vtx) tp_vtx[s_w[t] + k] = x[j];
+            code = (uint64_t)(x[j] + 1);
+          }
+          word = (word << EB) | code;
+        }
+      }
+    }
+    store(w, t, q, word);
+  };
+  // Words wholly inside one part take a short path of their own; the words
+  // across two parts (about two per test path) would make every wave run
+  // the entry-by-entry path as well, so they are listed and built after the
+  // others, all lanes then taking that path together.
+  for (int32_t w = tid; w < na; w += kBlock) {
+    const int t = path_of(w);
     const SpliceRow r = s_row[t];
     const int len = r.lp + r.lq + r.ls;
     const int q = w - s_a[t];
     const int k0 = q * pe;
     if (k0 >= len) continue;  // slack between two paths
+    if (tp_vtx) {
+      build_mixed(w, t);  // plain entries asked for: every word entry by entry
+      continue;
+    }
     uint64_t word = 0;
-    if (!tp_vtx && k0 + pe <= r.lp) {
+    if (k0 + pe <= r.lp) {
       continue;  // wholly in the prefix: left to the packed prefix row
-    } else if (!tp_vtx && k0 >= r.lp + r.lq) {
+    } else if (k0 >= r.lp + r.lq) {
       const int j0 = k0 - r.lp - r.lq;  // first suffix entry of the word
       const int sq = j0 / pe, sr = j0 - sq * pe;
       const uint64_t* row = b.sfx_pk + s_sb[t];
@@ -526,7 +576,7 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
         const uint64_t B = row[sq + 1];
         word = ((A & ((1ull << hb) - 1)) << (sr * EB)) | (B >> hb);
       }
-    } else if (pe <= 16 && !tp_vtx && k0 >= r.lp && k0 + pe <= r.lp + r.lq) {
+    } else if (pe <= 16 && k0 >= r.lp && k0 + pe <= r.lp + r.lq) {
       const int32_t* src = pp_vtx + r.o0 + (k0 - r.lp);
       int32_t x[pe <= 16 ? pe : 1];
 #pragma unroll
@@ -534,30 +584,18 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
 #pragma unroll
       for (int j = 0; j < (pe <= 16 ? pe : 1); ++j) word = (word << EB) | (uint64_t)(uint32_t)(x[j] + 1);
     } else {
-      for (int q0 = 0; q0 < pe; q0 += 8) {  // eight entries at a time, loads in flight together
-        int x[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int k = k0 + q0 + j;
-          x[j] = q0 + j < pe && k < len ? splice_entry(r, pp_vtx, b, k) : -1;
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int k = k0 + q0 + j;
-          if (q0 + j < pe) {
-            uint64_t code = 0;
-            if (k < len) {
-              if (tp_vtx) tp_vtx[s_w[t] + k] = x[j];
-              code = (uint64_t)(x[j] + 1);
-            }
-            word = (word << EB) | code;
-          }
-        }
-      }
+      const int m = atomicAdd(&s_nmix, 1);
+      if (m < kSpliceMixed) s_mix[m] = w;
+      else build_mixed(w, t);  // the list is full: build it here
+      continue;
     }
-    pk[a0 + w] = word;
-    const int kq = q - s_kq[t];
-    if (kq >= 0 && kq <= kTpKeyTail) s_kw[t][kq] = word;
+    store(w, t, q, word);
+  }
+  __syncthreads();
+  const int nmix = s_nmix < kSpliceMixed ? s_nmix : kSpliceMixed;
+  for (int m = tid; m < nmix; m += kBlock) {
+    const int32_t w = s_mix[m];
+    build_mixed(w, path_of(w));
   }
   __syncthreads();
   // the key's entry words: windows of pe entries from the first entry after e
