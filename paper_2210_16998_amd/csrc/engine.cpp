@@ -112,7 +112,7 @@ struct tpg_workspace {
   DevBuf scan2_status, scalars2;  // the side stream's own scan scratch
   // test paths
   DevBuf bfs_i32, pfx_off, sfx_off, pfx, sfx, pfx_pk, sfx_pk;
-  DevBuf tp_len, tp_off, tp_vtx, tp_key, tp_pk, idx0, idx1, grp_cnt, rb0, rb1;
+  DevBuf tp_len, tp_off, tp_vtx, tp_key, tp_pk, idx0, idx1, grp_cnt, rb0, rb1, merge_split;
   DevBuf keep_cnt, keep_len, keep_pos, keep_voff, comp_cnt;
   // per-level, per-component counts (batched labels)
   DevBuf lvl_comp;
@@ -1071,13 +1071,14 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
   TpOrder K{ws->tp_off.as<int64_t>(), ws->tp_key.as<uint64_t>(), ws->tp_pk.as<uint64_t>(), eb,
             pe};
   int64_t runs = n;
+  TPG_TRY(ws_reserve(ws, ws->merge_split, sizeof(int64_t) * merge_split_slots(nm)));
   DevBuf* ri = &ws->rb0;
   DevBuf* ro = &ws->rb1;
   DevBuf* ii = &ws->idx0;
   DevBuf* io = &ws->idx1;
   while (runs > 1) {
     TPG_HIP(launch_merge_round(K, ii->as<int32_t>(), io->as<int32_t>(), ri->as<int64_t>(), runs,
-                               nm, st));
+                               nm, ws->merge_split.as<int64_t>(), st));
     TPG_HIP(launch_next_runs(ri->as<int64_t>(), runs, ro->as<int64_t>(), st));
     std::swap(ri, ro);
     std::swap(ii, io);
@@ -1454,7 +1455,7 @@ void tpg_workspace_free(tpg_workspace* ws) {
                     &ws->leaf_by_rank, &ws->totals, &ws->cycles, &ws->scan_status,
                     &ws->scan_ctr, &ws->scalars, &ws->bfs_i32, &ws->pfx_off, &ws->sfx_off,
                     &ws->pfx, &ws->sfx, &ws->pfx_pk, &ws->sfx_pk, &ws->tp_len, &ws->tp_off, &ws->tp_vtx, &ws->tp_key, &ws->tp_pk, &ws->idx0,
-                    &ws->idx1, &ws->grp_cnt, &ws->rb0, &ws->rb1, &ws->keep_cnt, &ws->keep_len,
+                    &ws->idx1, &ws->grp_cnt, &ws->rb0, &ws->rb1, &ws->merge_split, &ws->keep_cnt, &ws->keep_len,
                     &ws->keep_pos, &ws->keep_voff, &ws->comp_cnt, &ws->lvl_comp, &ws->b_pp_off,
                     &ws->scan2_status, &ws->scalars2, &ws->digest, &ws->grp_key, &ws->grp_hist,
                     &ws->cov_keys, &ws->cov_vals, &ws->cov_misc, &ws->pair_p, &ws->pair_q,

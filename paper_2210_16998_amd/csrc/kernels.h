@@ -267,9 +267,12 @@ hipError_t launch_pack_tables(int n, const BfsOut& b, int eb, hipStream_t st);
 hipError_t launch_tp_write(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp,
                            const BfsOut& b, const int64_t* tp_off, int32_t* tp_vtx,
                            uint64_t* key, uint64_t* pk, int eb, int32_t* idx, hipStream_t st);
-// one round of pairwise merging of sorted runs [rb[r], rb[r+1]) of idx
+// one round of pairwise merging of sorted runs [rb[r], rb[r+1]) of idx;
+// split: device scratch of merge_split_slots(n) int64 (the tiles' splits)
 hipError_t launch_merge_round(const TpOrder& K, const int32_t* idx_in, int32_t* idx_out,
-                              const int64_t* rb, int64_t n_runs, int64_t n, hipStream_t st);
+                              const int64_t* rb, int64_t n_runs, int64_t n, int64_t* split,
+                              hipStream_t st);
+int64_t merge_split_slots(int64_t n);
 hipError_t launch_next_runs(const int64_t* rb, int64_t n_runs, int64_t* rb_out, hipStream_t st);
 hipError_t launch_dedup_flags(const TpOrder& K, const int32_t* idx, int64_t n, int64_t* keep_cnt,
                               int64_t* keep_len, hipStream_t st);

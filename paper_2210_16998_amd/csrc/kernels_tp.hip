@@ -802,53 +802,70 @@ __device__ __forceinline__ int64_t merge_split_wave(const TpOrder& K, const int3
 }
 
 // One round of pairwise merges of the sorted runs [rb[r], rb[r + 1]): run
-// 2p with run 2p + 1.  A workgroup produces kMergeTile consecutive outputs:
-// it finds its input slices with two merge-path searches, stages their
-// indices and keys in LDS, and every thread then splits and merges its own
+// 2p with run 2p + 1.  A workgroup produces kMergeTile consecutive outputs.
+// Where its input slices start is found beforehand, by k_merge_splits (one
+// merge-path search per tile, a whole wave each, at full occupancy: the
+// searches are chains of dependent loads); the workgroup stages the slices'
+// indices and keys in LDS and every thread then splits and merges its own
 // kMergeItems outputs from LDS (the entries themselves are read only when
-// two paths share their tree prefix and next entry).  A thread's split costs
-// a binary search over the tile, so several outputs per thread mean fewer
-// comparisons per output; 256 threads of 6 outputs timed fastest on the
-// stress CFG among 128..512 threads of 2..8 outputs.
+// two paths share their tree prefix, next entry and the entries the keys
+// hold).  A thread's split costs a binary search over the tile, so several
+// outputs per thread mean fewer comparisons per output.
 constexpr int kMergeThreads = 256;
 constexpr int kMergeItems = 4;
 constexpr int kMergeTile = kMergeThreads * kMergeItems;
+constexpr int kSplitWaves = 4;  // splits found per workgroup of k_merge_splits
+
+// The pair of runs holding output position pos: [a0, a1) with [a1, b1).
+__device__ __forceinline__ void merge_pair(const int64_t* rb, int64_t n_runs, int64_t pos,
+                                           int64_t& a0, int64_t& a1, int64_t& b1) {
+  int64_t lo = 0, hi = n_runs - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (rb[mid] <= pos) lo = mid; else hi = mid - 1;
+  }
+  const int64_t p = lo >> 1;
+  a0 = rb[2 * p];
+  a1 = rb[2 * p + 1 < n_runs ? 2 * p + 1 : n_runs];
+  b1 = rb[2 * p + 2 < n_runs ? 2 * p + 2 : n_runs];
+}
+
+// split[b]: how many of the first (b * kMergeTile - a0) outputs of its pair's
+// merge come from the pair's first run.
+__global__ __launch_bounds__(64 * kSplitWaves) void k_merge_splits(TpOrder K, const int32_t* in,
+                                                                  const int64_t* rb, int64_t n_runs,
+                                                                  int64_t n_tiles, int64_t* split) {
+  const int64_t b = (int64_t)blockIdx.x * kSplitWaves + (threadIdx.x >> 6);
+  if (b >= n_tiles) return;  // whole waves
+  const int64_t pos = b * kMergeTile;
+  int64_t a0, a1, b1;
+  merge_pair(rb, n_runs, pos, a0, a1, b1);
+  const int64_t r = merge_split_wave(K, in + a0, a1 - a0, in + a1, b1 - a1, pos - a0);
+  if (lane_id() == 0) split[b] = r;
+}
 
 __global__ __launch_bounds__(kMergeThreads) void k_merge_round(TpOrder K, const int32_t* in,
                                                                int32_t* out, const int64_t* rb,
-                                                               int64_t n_runs, int64_t n) {
+                                                               int64_t n_runs, int64_t n,
+                                                               const int64_t* split) {
   __shared__ int32_t s_idx[kMergeTile];
   __shared__ uint64_t s_key[kTpKeyWords][kMergeTile];
-  __shared__ int64_t s_seg[4];
   const int tid = (int)threadIdx.x;
   const int64_t t0 = (int64_t)blockIdx.x * kMergeTile;
   const int64_t t1 = t0 + kMergeTile < n ? t0 + kMergeTile : n;
   int64_t pos = t0;
   while (pos < t1) {
-    // the pair of runs holding output position pos
-    int64_t lo = 0, hi = n_runs - 1;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi + 1) >> 1;
-      if (rb[mid] <= pos) lo = mid; else hi = mid - 1;
-    }
-    const int64_t p = lo >> 1;
-    const int64_t a0 = rb[2 * p];
-    const int64_t a1 = rb[2 * p + 1 < n_runs ? 2 * p + 1 : n_runs];
-    const int64_t b1 = rb[2 * p + 2 < n_runs ? 2 * p + 2 : n_runs];
+    int64_t a0, a1, b1;
+    merge_pair(rb, n_runs, pos, a0, a1, b1);
     const int32_t* A = in + a0;
     const int32_t* B = in + a1;
-    const int64_t na = a1 - a0, nb = b1 - a1;
+    const int64_t na = a1 - a0;
     const int64_t stop = t1 < b1 ? t1 : b1;
-    // input slices of this segment (two searches, one wave each)
-    if (tid < 128) {  // waves 0 and 1
-      const int w = tid >> 6;
-      const int64_t d = (w == 0 ? pos : stop) - a0;
-      const int64_t r = merge_split_wave(K, A, na, B, nb, d);
-      if ((tid & 63) == 0) s_seg[w] = r;
-    }
-    __syncthreads();
-    const int64_t ia = s_seg[0], ja = (pos - a0) - ia;
-    const int64_t ib = s_seg[1], jb = (stop - a0) - ib;
+    // input slices of this segment: the tile's first segment starts at its
+    // split, a later one at the start of its pair; a segment ends at the end
+    // of its pair or at the next tile's split
+    const int64_t ia = pos == t0 ? split[blockIdx.x] : 0, ja = (pos - a0) - ia;
+    const int64_t ib = stop == b1 ? na : split[blockIdx.x + 1], jb = (stop - a0) - ib;
     const int la = (int)(ib - ia), lb = (int)(jb - ja);
     for (int q = tid; q < la + lb; q += kMergeThreads) {
       const int32_t x = q < la ? A[ia + q] : B[ja + (q - la)];
@@ -891,11 +908,17 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_round(TpOrder K, const 
   }
 }
 
+int64_t merge_split_slots(int64_t n) { return (n + kMergeTile - 1) / kMergeTile + 1; }
+
 hipError_t launch_merge_round(const TpOrder& K, const int32_t* idx_in, int32_t* idx_out,
-                              const int64_t* rb, int64_t n_runs, int64_t n, hipStream_t st) {
+                              const int64_t* rb, int64_t n_runs, int64_t n, int64_t* split,
+                              hipStream_t st) {
   if (n == 0) return hipSuccess;
-  k_merge_round<<<(unsigned)((n + kMergeTile - 1) / kMergeTile), kMergeThreads, 0, st>>>(
-      K, idx_in, idx_out, rb, n_runs, n);
+  const int64_t n_tiles = (n + kMergeTile - 1) / kMergeTile;
+  k_merge_splits<<<(unsigned)((n_tiles + kSplitWaves - 1) / kSplitWaves), 64 * kSplitWaves, 0,
+                   st>>>(K, idx_in, rb, n_runs, n_tiles, split);
+  k_merge_round<<<(unsigned)n_tiles, kMergeThreads, 0, st>>>(K, idx_in, idx_out, rb, n_runs, n,
+                                                             split);
   return hipGetLastError();
 }
 
