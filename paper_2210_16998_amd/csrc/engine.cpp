@@ -1070,13 +1070,34 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
   // merge the per-first-vertex runs
   TpOrder K{ws->tp_off.as<int64_t>(), ws->tp_key.as<uint64_t>(), ws->tp_pk.as<uint64_t>(), eb,
             pe};
-  int64_t runs = n;
+  int64_t runs = n, final_runs = 1;
   TPG_TRY(ws_reserve(ws, ws->merge_split, sizeof(int64_t) * merge_split_slots(nm)));
   DevBuf* ri = &ws->rb0;
   DevBuf* ro = &ws->rb1;
   DevBuf* ii = &ws->idx0;
   DevBuf* io = &ws->idx1;
-  while (runs > 1) {
+  if (nc > 1) {
+    // a union of graphs: merge within each graph only (its runs padded to a
+    // power of two), as the graphs' test paths already follow each other in
+    // order; worth it when that takes fewer rounds
+    int32_t largest = 1;
+    for (int c = 0; c < nc; ++c) largest = std::max(largest, U.cbase[c + 1] - U.cbase[c]);
+    int R = 0;
+    while ((1 << R) < largest) ++R;
+    int R_all = 0;
+    while ((int64_t)1 << R_all < n) ++R_all;
+    if (R < R_all) {
+      const int64_t P = (int64_t)nc << R;
+      TPG_TRY(ws_reserve(ws, ws->rb0, sizeof(int64_t) * (std::max<int64_t>(P, n) + 2), true, st,
+                         sizeof(int64_t) * (n + 1)));
+      TPG_TRY(ws_reserve(ws, ws->rb1, sizeof(int64_t) * (std::max<int64_t>(P, n) + 2)));
+      TPG_HIP(launch_pad_runs(ws->dg, ws->rb0.as<int64_t>(), R, P, ws->rb1.as<int64_t>(), st));
+      std::swap(ri, ro);
+      runs = P;
+      final_runs = nc;
+    }
+  }
+  while (runs > final_runs) {
     TPG_HIP(launch_merge_round(K, ii->as<int32_t>(), io->as<int32_t>(), ri->as<int64_t>(), runs,
                                nm, ws->merge_split.as<int64_t>(), st));
     TPG_HIP(launch_next_runs(ri->as<int64_t>(), runs, ro->as<int64_t>(), st));

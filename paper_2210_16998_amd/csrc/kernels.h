@@ -274,6 +274,10 @@ hipError_t launch_merge_round(const TpOrder& K, const int32_t* idx_in, int32_t* 
                               hipStream_t st);
 int64_t merge_split_slots(int64_t n);
 hipError_t launch_next_runs(const int64_t* rb, int64_t n_runs, int64_t* rb_out, hipStream_t st);
+// the per-vertex runs rb[0..n] of a union, each graph's padded to 2^R runs:
+// out[0..n_out], n_out = n_comp * 2^R
+hipError_t launch_pad_runs(const DGraph& g, const int64_t* rb, int R, int64_t n_out, int64_t* out,
+                           hipStream_t st);
 hipError_t launch_dedup_flags(const TpOrder& K, const int32_t* idx, int64_t n, int64_t* keep_cnt,
                               int64_t* keep_len, hipStream_t st);
 // copies the kept paths (keep_len[k] > 0) of idx to out_off / out_vtx

@@ -922,6 +922,31 @@ hipError_t launch_merge_round(const TpOrder& K, const int32_t* idx_in, int32_t* 
   return hipGetLastError();
 }
 
+// Runs of a union of graphs, each graph's runs padded to 2^R with empty
+// ones: out[s] for s = c * 2^R + j (j < 2^R) is the start of graph c's j-th
+// run (its end once j reaches its run count), out[n_comp * 2^R] the end.
+// Pairing runs 2p, 2p + 1 then never crosses two graphs, so R rounds sort
+// every graph's test paths, and the graphs already follow each other in
+// order (their ids are disjoint ranges).
+__global__ void k_pad_runs(DGraph g, const int64_t* rb, int R, int64_t n_out, int64_t* out) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s > n_out) return;
+  const int64_t c = s >> R;
+  if (c >= g.n_comp) {
+    out[s] = rb[g.n];
+    return;
+  }
+  const int64_t j = s & ((1ll << R) - 1);
+  const int64_t nc = g.cbase[c + 1] - g.cbase[c];
+  out[s] = rb[g.cbase[c] + (j < nc ? j : nc)];
+}
+
+hipError_t launch_pad_runs(const DGraph& g, const int64_t* rb, int R, int64_t n_out, int64_t* out,
+                           hipStream_t st) {
+  k_pad_runs<<<(unsigned)((n_out + 1 + kBlock - 1) / kBlock), kBlock, 0, st>>>(g, rb, R, n_out, out);
+  return hipGetLastError();
+}
+
 __global__ void k_next_runs(const int64_t* rb, int64_t n_runs, int64_t* rb_out) {
   const int64_t h = (n_runs + 1) / 2;
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
