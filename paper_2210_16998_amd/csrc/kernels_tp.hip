@@ -816,18 +816,25 @@ constexpr int kMergeItems = 4;
 constexpr int kMergeTile = kMergeThreads * kMergeItems;
 constexpr int kSplitWaves = 4;  // splits found per workgroup of k_merge_splits
 
-// The pair of runs holding output position pos: [a0, a1) with [a1, b1).
-__device__ __forceinline__ void merge_pair(const int64_t* rb, int64_t n_runs, int64_t pos,
-                                           int64_t& a0, int64_t& a1, int64_t& b1) {
+// The pair of runs holding output position pos: its index p, and [a0, a1)
+// with [a1, b1).
+__device__ __forceinline__ int64_t merge_pair_of(const int64_t* rb, int64_t n_runs, int64_t pos) {
   int64_t lo = 0, hi = n_runs - 1;
   while (lo < hi) {
     const int64_t mid = (lo + hi + 1) >> 1;
     if (rb[mid] <= pos) lo = mid; else hi = mid - 1;
   }
-  const int64_t p = lo >> 1;
+  return lo >> 1;
+}
+__device__ __forceinline__ void merge_pair_bounds(const int64_t* rb, int64_t n_runs, int64_t p,
+                                                  int64_t& a0, int64_t& a1, int64_t& b1) {
   a0 = rb[2 * p];
   a1 = rb[2 * p + 1 < n_runs ? 2 * p + 1 : n_runs];
   b1 = rb[2 * p + 2 < n_runs ? 2 * p + 2 : n_runs];
+}
+__device__ __forceinline__ void merge_pair(const int64_t* rb, int64_t n_runs, int64_t pos,
+                                           int64_t& a0, int64_t& a1, int64_t& b1) {
+  merge_pair_bounds(rb, n_runs, merge_pair_of(rb, n_runs, pos), a0, a1, b1);
 }
 
 // split[b]: how many of the first (b * kMergeTile - a0) outputs of its pair's
@@ -854,9 +861,14 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_round(TpOrder K, const 
   const int64_t t0 = (int64_t)blockIdx.x * kMergeTile;
   const int64_t t1 = t0 + kMergeTile < n ? t0 + kMergeTile : n;
   int64_t pos = t0;
+  // the tile's first pair by search; each later segment starts the next pair
+  // (an empty pair ends where it starts and is stepped over)
+  int64_t p = merge_pair_of(rb, n_runs, pos);
   while (pos < t1) {
     int64_t a0, a1, b1;
-    merge_pair(rb, n_runs, pos, a0, a1, b1);
+    merge_pair_bounds(rb, n_runs, p, a0, a1, b1);
+    ++p;
+    if (b1 <= pos) continue;
     const int32_t* A = in + a0;
     const int32_t* B = in + a1;
     const int64_t na = a1 - a0;
