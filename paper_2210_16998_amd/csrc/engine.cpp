@@ -112,7 +112,8 @@ struct tpg_workspace {
   DevBuf scan2_status, scalars2;  // the side stream's own scan scratch
   // test paths
   DevBuf bfs_i32, pfx_off, sfx_off, pfx, sfx, pfx_pk, sfx_pk;
-  DevBuf tp_len, tp_off, tp_vtx, tp_key, tp_pk, idx0, idx1, grp_cnt, rb0, rb1, merge_split;
+  DevBuf tp_len, tp_off, tp_vtx, tp_key, tp_pk, idx0, idx1, grp_cnt, rb0, rb1, merge_split, tp_lead;
+  bool tp_len_ready = false;  // the prime-path writer filled tp_len and tp_lead for this union
   DevBuf keep_cnt, keep_len, keep_pos, keep_voff, comp_cnt;
   // per-level, per-component counts (batched labels)
   DevBuf lvl_comp;
@@ -792,6 +793,8 @@ struct PPResult {
   int64_t n_pp = 0, n_vtx = 0, n_cycles = 0;
 };
 
+BfsOut bfs_views(tpg_workspace* ws, int n);
+
 tpg_status rank_and_materialize(tpg_workspace* ws, const HostUnion& U, hipStream_t st,
                                 const TreeResult& R, PPResult& P, OutSet& o) {
   ExtArgs a = make_args(ws);
@@ -863,7 +866,22 @@ tpg_status rank_and_materialize(tpg_workspace* ws, const HostUnion& U, hipStream
   TPG_TRY(io_read(ws, st, ws->h_scalars + 6, scal + 6, sizeof(int64_t)));
   P.n_vtx = ws->h_scalars[6];
   TPG_TRY(ws_reserve(ws, o.pp_vtx, sizeof(int32_t) * (P.n_vtx + 1)));
-  TPG_HIP(launch_pp_write(a, lbr, o.pp_off.as<int64_t>(), P.n_pp, o.pp_vtx.as<int32_t>(), st));
+  // with the BFS under way (test paths follow), the writer also records each
+  // test path's length and where its prime path leaves the BFS tree; the BFS
+  // ran beside the extension and is long done
+  PPWriteTp tpx{};
+  ws->tp_len_ready = false;
+  if (ws->bfs_pending) {
+    TPG_TRY(ws_reserve(ws, ws->tp_len, sizeof(int64_t) * (P.n_pp + 1)));
+    TPG_TRY(ws_reserve(ws, ws->tp_lead, sizeof(int32_t) * (P.n_pp + 1)));
+    TPG_HIP(hipStreamWaitEvent(st, ws->ev_join, 0));
+    const BfsOut bv = bfs_views(ws, U.n);
+    tpx = PPWriteTp{bv.parent, bv.pfx_off, bv.sfx_off, ws->tp_len.as<int64_t>(),
+                    ws->tp_lead.as<int32_t>()};
+    ws->tp_len_ready = true;
+  }
+  TPG_HIP(launch_pp_write(a, lbr, o.pp_off.as<int64_t>(), P.n_pp, o.pp_vtx.as<int32_t>(), tpx,
+                          st));
   o.n_pp = P.n_pp;
   o.n_ppv = P.n_vtx;
   return TPG_OK;
@@ -1038,8 +1056,11 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
   TPG_TRY(ws_reserve(ws, ws->idx0, sizeof(int32_t) * (np + 1)));
   TPG_TRY(ws_reserve(ws, ws->idx1, sizeof(int32_t) * (np + 1)));
   TPG_TRY(ws_reserve(ws, ws->tp_key, sizeof(uint64_t) * kTpKeyWords * (np + 1)));
+  const bool from_writer = ws->tp_len_ready;
+  ws->tp_len_ready = false;
   TPG_HIP(launch_tp_len(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), np, n, b,
-                        ws->tp_len.as<int64_t>(), ws->rb0.as<int64_t>(), st));
+                        from_writer ? nullptr : ws->tp_len.as<int64_t>(), ws->rb0.as<int64_t>(),
+                        st));
   TPG_HIP(scan_i64(ws->tp_len.as<int64_t>(), ws->tp_off.as<int64_t>(), np, 0, sc,
                    ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
   TPG_TRY(io_read(ws, st, ws->h_scalars, sc, sizeof(int64_t)));
@@ -1063,7 +1084,8 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
   TPG_HIP(launch_tp_write(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), np, b,
                           ws->tp_off.as<int64_t>(), greedy ? ws->tp_vtx.as<int32_t>() : nullptr,
                           ws->tp_key.as<uint64_t>(), ws->tp_pk.as<uint64_t>(), eb,
-                          ws->idx0.as<int32_t>(), st));
+                          ws->idx0.as<int32_t>(), from_writer ? ws->tp_lead.as<int32_t>() : nullptr,
+                          st));
   // with longest-first covering only the chosen test paths are sorted
   int64_t nm = np;
   if (greedy) TPG_TRY(greedy_select(ws, U, st, np, o, &nm));
@@ -1476,7 +1498,7 @@ void tpg_workspace_free(tpg_workspace* ws) {
                     &ws->leaf_by_rank, &ws->totals, &ws->cycles, &ws->scan_status,
                     &ws->scan_ctr, &ws->scalars, &ws->bfs_i32, &ws->pfx_off, &ws->sfx_off,
                     &ws->pfx, &ws->sfx, &ws->pfx_pk, &ws->sfx_pk, &ws->tp_len, &ws->tp_off, &ws->tp_vtx, &ws->tp_key, &ws->tp_pk, &ws->idx0,
-                    &ws->idx1, &ws->grp_cnt, &ws->rb0, &ws->rb1, &ws->merge_split, &ws->keep_cnt, &ws->keep_len,
+                    &ws->idx1, &ws->grp_cnt, &ws->rb0, &ws->rb1, &ws->merge_split, &ws->tp_lead, &ws->keep_cnt, &ws->keep_len,
                     &ws->keep_pos, &ws->keep_voff, &ws->comp_cnt, &ws->lvl_comp, &ws->b_pp_off,
                     &ws->scan2_status, &ws->scalars2, &ws->digest, &ws->grp_key, &ws->grp_hist,
                     &ws->cov_keys, &ws->cov_vals, &ws->cov_misc, &ws->pair_p, &ws->pair_q,

@@ -88,8 +88,19 @@ hipError_t launch_up_run(const ExtArgs& a, int depth, int64_t base, int64_t F, u
 hipError_t launch_down_run(const ExtArgs& a, int depth, int L, int64_t base, int64_t F,
                            uint32_t* sub_cnt, int64_t* leaf_by_rank, int32_t* pp_len,
                            hipStream_t st);
+// What the prime-path writer also records for the test paths when the BFS
+// tables are ready (tp_len null: nothing): per prime path i, the length of
+// its test path, and lead[i] = the first index t >= 1 whose entry's BFS
+// parent is not entry t - 1 (the path's length when there is none).
+struct PPWriteTp {
+  const int32_t* parent;   // BFS parent of each vertex
+  const int64_t* pfx_off;  // prefix / suffix table offsets (their lengths)
+  const int64_t* sfx_off;
+  int64_t* tp_len;
+  int32_t* lead;
+};
 hipError_t launch_pp_write(const ExtArgs& a, const int64_t* leaf_by_rank, const int64_t* pp_off,
-                           int64_t n_pp, int32_t* pp_vtx, hipStream_t st);
+                           int64_t n_pp, int32_t* pp_vtx, const PPWriteTp& tp, hipStream_t st);
 
 // --- scans -------------------------------------------------------------------
 // out[i] = add + sum(in[0..i)), *total = add + sum(in); n may be 0.
@@ -264,9 +275,11 @@ hipError_t launch_tp_len(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n
 // is not null, their plain entries
 // Packed prefix / suffix rows of every vertex (after the tables exist).
 hipError_t launch_pack_tables(int n, const BfsOut& b, int eb, hipStream_t st);
+// lead: what the prime-path writer recorded (null: found here by a scan)
 hipError_t launch_tp_write(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp,
                            const BfsOut& b, const int64_t* tp_off, int32_t* tp_vtx,
-                           uint64_t* key, uint64_t* pk, int eb, int32_t* idx, hipStream_t st);
+                           uint64_t* key, uint64_t* pk, int eb, int32_t* idx,
+                           const int32_t* lead, hipStream_t st);
 // one round of pairwise merging of sorted runs [rb[r], rb[r+1]) of idx;
 // split: device scratch of merge_split_slots(n) int64 (the tiles' splits)
 hipError_t launch_merge_round(const TpOrder& K, const int32_t* idx_in, int32_t* idx_out,

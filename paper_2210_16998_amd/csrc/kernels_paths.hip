@@ -841,16 +841,22 @@ hipError_t launch_down_run(const ExtArgs& a, int depth, int L, int64_t base, int
 // Each thread writes one prime path by walking parent links from its leaf.
 // The walk yields entries back to front; they are buffered 32 at a time in
 // registers and stored as one burst of consecutive addresses, so that lines
-// are written whole instead of one word per dependent load.
+// are written whole instead of one word per dependent load.  With the BFS
+// tables given, the walk also checks each entry against the BFS parent of
+// the one after it and records the test path's length and where the path
+// leaves the BFS tree (the test-path keys start from there).
 __global__ __launch_bounds__(kBlock) void k_pp_write(ExtArgs a, const int64_t* leaf_by_rank,
                                                      const int64_t* pp_off, int64_t n_pp,
-                                                     int32_t* pp_vtx) {
+                                                     int32_t* pp_vtx, PPWriteTp tp) {
   constexpr int kBuf = 32;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n_pp) return;
   int64_t x = leaf_by_rank[i];
   int64_t pos = pp_off[i + 1] - 1;
   const int64_t lo = pp_off[i];
+  const bool with_tp = tp.tp_len != nullptr;
+  int32_t nxt = -1, vk = -1;  // the entry after the current one; the last entry
+  int32_t lead = (int32_t)(pos + 1 - lo);
   while (pos >= lo && x >= 0) {
     int32_t buf[kBuf];
     int cnt = 0;
@@ -865,15 +871,29 @@ __global__ __launch_bounds__(kBlock) void k_pp_write(ExtArgs a, const int64_t* l
 #pragma unroll
     for (int j = kBuf - 1; j >= 0; --j)
       if (j < cnt) pp_vtx[pos - j] = buf[j];
+    if (with_tp) {
+      for (int j = 0; j < cnt; ++j) {
+        const int32_t v = buf[j];
+        if (nxt < 0) vk = v;
+        else if (tp.parent[nxt] != v) lead = (int32_t)(pos - j + 1 - lo);
+        nxt = v;
+      }
+    }
     pos -= cnt;
+  }
+  if (with_tp && nxt >= 0) {
+    const int32_t v1 = nxt;
+    tp.tp_len[i] = (tp.pfx_off[v1 + 1] - tp.pfx_off[v1]) + (pp_off[i + 1] - lo) +
+                   (tp.sfx_off[vk + 1] - tp.sfx_off[vk]);
+    tp.lead[i] = lead;
   }
 }
 
 hipError_t launch_pp_write(const ExtArgs& a, const int64_t* leaf_by_rank, const int64_t* pp_off,
-                           int64_t n_pp, int32_t* pp_vtx, hipStream_t st) {
+                           int64_t n_pp, int32_t* pp_vtx, const PPWriteTp& tp, hipStream_t st) {
   if (n_pp == 0) return hipSuccess;
   k_pp_write<<<(unsigned)((n_pp + kBlock - 1) / kBlock), kBlock, 0, st>>>(a, leaf_by_rank, pp_off,
-                                                                          n_pp, pp_vtx);
+                                                                          n_pp, pp_vtx, tp);
   return hipGetLastError();
 }
 

@@ -299,7 +299,7 @@ hipError_t launch_tp_len(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n
                          const BfsOut& b, int64_t* tp_len, int64_t* rb, hipStream_t st) {
   if (n_pp == 0) return hipSuccess;
   const unsigned grid = (unsigned)((n_pp + kBlock - 1) / kBlock);
-  k_tp_len<<<grid, kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, b, tp_len);
+  if (tp_len) k_tp_len<<<grid, kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, b, tp_len);
   k_run_bounds<<<grid, kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, n, rb);
   return hipGetLastError();
 }
@@ -614,16 +614,29 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
 // depth, the entry after it and the split rank, and the next pe entries.
 // One thread per test path.
 __global__ __launch_bounds__(kBlock) void k_tp_keys(const int64_t* pp_off, const int32_t* pp_vtx,
-                                                    int64_t n_pp, BfsOut b, uint64_t* key) {
+                                                    int64_t n_pp, BfsOut b, const int32_t* lead,
+                                                    uint64_t* key) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n_pp) {
     const SpliceRow r = splice_row(pp_off, pp_vtx, b, i);
     const int len = r.lp + r.lq + r.ls;
     // where the path leaves the BFS tree: entries up to the prime path's
-    // first vertex are its tree path; scan on, eight entries at a time
+    // first vertex are its tree path; then the prime path's own entries, as
+    // far as the prime-path writer found them following the tree (lead), and
+    // past those the suffix, scanned eight entries at a time
     int first = len;
     int prev = r.v1;
-    for (int k0 = r.lp + 1; k0 < len && first == len; k0 += 8) {
+    int kscan = r.lp + 1;
+    if (lead) {
+      const int ld = lead[i];
+      if (ld < r.lq) {
+        first = r.lp + ld;
+      } else {
+        prev = r.vk;
+        kscan = r.lp + r.lq;
+      }
+    }
+    for (int k0 = kscan; k0 < len && first == len; k0 += 8) {
       int x[8], px[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) x[j] = k0 + j < len ? splice_entry(r, pp_vtx, b, k0 + j) : -1;
@@ -665,12 +678,13 @@ __global__ __launch_bounds__(kBlock) void k_tp_keys(const int64_t* pp_off, const
 
 hipError_t launch_tp_write(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp,
                            const BfsOut& b, const int64_t* tp_off, int32_t* tp_vtx,
-                           uint64_t* key, uint64_t* pk, int eb, int32_t* idx, hipStream_t st) {
+                           uint64_t* key, uint64_t* pk, int eb, int32_t* idx,
+                           const int32_t* lead, hipStream_t st) {
   if (n_pp == 0) return hipSuccess;
   if (eb < 1 || eb > 18) return hipErrorInvalidValue;  // more than 2^18 - 1 vertices in one union
   // the tree-position keys first: the splice cuts the entry words after e
   k_tp_keys<<<(unsigned)((n_pp + kBlock - 1) / kBlock), kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, b,
-                                                                        key);
+                                                                        lead, key);
   const unsigned grid = (unsigned)((n_pp + kSplicePaths - 1) / kSplicePaths);
 #define TPG_SPLICE_CASE(E)                                                                     \
   case E:                                                                                      \
