@@ -114,6 +114,7 @@ struct tpg_workspace {
   DevBuf bfs_i32, pfx_off, sfx_off, pfx, sfx, pfx_pk, sfx_pk;
   DevBuf tp_len, tp_off, tp_vtx, tp_key, tp_pk, idx0, idx1, grp_cnt, rb0, rb1, merge_split, tp_lead;
   bool tp_len_ready = false;  // the prime-path writer filled tp_len and tp_lead for this union
+  bool rb_ready = false;      // the root ranking wrote the runs by first vertex into rb0
   DevBuf keep_cnt, keep_len, keep_pos, keep_voff, comp_cnt;
   // per-level, per-component counts (batched labels)
   DevBuf lvl_comp;
@@ -830,7 +831,8 @@ tpg_status rank_and_materialize(tpg_workspace* ws, const HostUnion& U, hipStream
       L -= n;
     }
     if (e == hipSuccess)
-      e = launch_roots(a, R.count[1], sc, nullptr, nullptr, ws->totals.as<int64_t>(), 0, st);
+      e = launch_roots(a, R.count[1], sc, nullptr, nullptr, ws->totals.as<int64_t>(), 0, nullptr,
+                       st);
     return e;
   }));
   TPG_TRY(io_read(ws, st, ws->h_scalars, ws->totals.p, sizeof(int64_t)));
@@ -844,10 +846,20 @@ tpg_status rank_and_materialize(tpg_workspace* ws, const HostUnion& U, hipStream
   TPG_TRY(reserve_scan(ws, P.n_pp));
   int64_t* lbr = ws->leaf_by_rank.as<int64_t>();
   int32_t* len = ws->pp_len.as<int32_t>();
+  // with every vertex a root (in id order) the root ranks are also the test
+  // paths' runs by first vertex
+  int64_t* rbw = nullptr;
+  if (ws->seed_lo == 0 && R.count[1] == U.n) {
+    TPG_TRY(ws_reserve(ws, ws->rb0, sizeof(int64_t) * (U.n + 2)));
+    rbw = ws->rb0.as<int64_t>();
+  }
+  ws->rb_ready = rbw != nullptr;
   key_add(key_down, lbr);
   key_add(key_down, len);
+  key_add(key_down, rbw);
   TPG_TRY(run_seq(ws, ws->rank_down, std::move(key_down), st, [&]() -> hipError_t {
-    hipError_t e = launch_roots(a, R.count[1], sc, lbr, len, ws->totals.as<int64_t>(), 1, st);
+    hipError_t e =
+        launch_roots(a, R.count[1], sc, lbr, len, ws->totals.as<int64_t>(), 1, rbw, st);
     for (int L = 1; L < R.Lmax && e == hipSuccess;) {
       const int n = std::min(kRun, R.Lmax - L);  // parents of levels L .. L + n - 1
       e = n > 1 ? launch_down_run(a, n - 1, L, R.off[L], R.count[L], sc, lbr, len, st)
@@ -1056,11 +1068,12 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
   TPG_TRY(ws_reserve(ws, ws->idx0, sizeof(int32_t) * (np + 1)));
   TPG_TRY(ws_reserve(ws, ws->idx1, sizeof(int32_t) * (np + 1)));
   TPG_TRY(ws_reserve(ws, ws->tp_key, sizeof(uint64_t) * kTpKeyWords * (np + 1)));
-  const bool from_writer = ws->tp_len_ready;
+  const bool from_writer = ws->tp_len_ready, rb_from_roots = ws->rb_ready;
   ws->tp_len_ready = false;
+  ws->rb_ready = false;
   TPG_HIP(launch_tp_len(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), np, n, b,
-                        from_writer ? nullptr : ws->tp_len.as<int64_t>(), ws->rb0.as<int64_t>(),
-                        st));
+                        from_writer ? nullptr : ws->tp_len.as<int64_t>(),
+                        rb_from_roots ? nullptr : ws->rb0.as<int64_t>(), st));
   TPG_HIP(scan_i64(ws->tp_len.as<int64_t>(), ws->tp_off.as<int64_t>(), np, 0, sc,
                    ws->scan_status.as<uint64_t>(), ws->scan_ctr.as<uint32_t>(), st));
   TPG_TRY(io_read(ws, st, ws->h_scalars, sc, sizeof(int64_t)));

@@ -74,9 +74,11 @@ hipError_t launch_fill(int W, const ExtArgs& a, int L, int64_t prev, int64_t bas
 hipError_t launch_up(const ExtArgs& a, int L, int64_t base, int64_t F, uint32_t* sub_cnt,
                      unsigned long long* n_cycles, hipStream_t st);
 // mode 0: totals[0] = #PP (no change to the arrays); mode 1: level-1 ranks,
-// root leaves recorded (leaf_by_rank, pp_len = 1).
+// root leaves recorded (leaf_by_rank, pp_len = 1), and with rb given (roots
+// = every vertex, in id order) rb[v] = rank of the first prime path whose
+// first vertex is >= v (v = 0 .. n_roots).
 hipError_t launch_roots(const ExtArgs& a, int64_t n_roots, uint32_t* sub_cnt, int64_t* leaf_by_rank,
-                        int32_t* pp_len, int64_t* totals, int mode, hipStream_t st);
+                        int32_t* pp_len, int64_t* totals, int mode, int64_t* rb, hipStream_t st);
 // parents of level L: ranks to the children; PP leaves record node and length
 hipError_t launch_down(const ExtArgs& a, int L, int64_t base, int64_t F, uint32_t* sub_cnt,
                        int64_t* leaf_by_rank, int32_t* pp_len, hipStream_t st);
@@ -267,7 +269,8 @@ hipError_t launch_comp_pp_starts(const DGraph& g, const uint32_t* sub_cnt, const
                                  const int64_t* totals, int64_t* pp_start, int64_t* ppv_start,
                                  hipStream_t st);
 
-// test-path lengths, and rb[v] = first prime path with first vertex >= v (v = 0..n)
+// test-path lengths, and rb[v] = first prime path with first vertex >= v
+// (v = 0..n); either output may be null (not computed)
 hipError_t launch_tp_len(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp, int n,
                          const BfsOut& b, int64_t* tp_len, int64_t* rb, hipStream_t st);
 // writes the test paths packed (pk: (n_entries + pe - 1) / pe + 2 n_pp + 4

@@ -679,7 +679,7 @@ hipError_t launch_up(const ExtArgs& a, int L, int64_t base, int64_t F, uint32_t*
 // their first prime path.  totals[0] = #PP.  One workgroup of 1024 threads.
 __global__ __launch_bounds__(1024) void k_roots(ExtArgs a, int64_t n_roots, uint32_t* sub_cnt,
                                                 int64_t* leaf_by_rank, int32_t* pp_len,
-                                                int64_t* totals, int mode) {
+                                                int64_t* totals, int mode, int64_t* rb) {
   __shared__ int64_t s_w[16];
   int64_t carry = 0;
   for (int64_t b = 0; b < n_roots; b += 1024) {
@@ -689,6 +689,7 @@ __global__ __launch_bounds__(1024) void k_roots(ExtArgs a, int64_t n_roots, uint
     const int64_t pc = block_excl_scan<1024, int64_t>(c, tc, s_w);
     if (i < n_roots && mode == 1) {
       const int64_t rank = carry + pc;
+      if (rb) rb[i] = rank;  // root i is vertex i: its first prime path's rank
       sub_cnt[i] = (uint32_t)rank;
       if (a.t.nch[i] >= kNchPP) {
         leaf_by_rank[rank] = i;
@@ -698,11 +699,12 @@ __global__ __launch_bounds__(1024) void k_roots(ExtArgs a, int64_t n_roots, uint
     carry += tc;
   }
   if (threadIdx.x == 0 && mode == 0) totals[0] = carry;
+  if (threadIdx.x == 0 && mode == 1 && rb) rb[n_roots] = carry;
 }
 
 hipError_t launch_roots(const ExtArgs& a, int64_t n_roots, uint32_t* sub_cnt, int64_t* leaf_by_rank,
-                        int32_t* pp_len, int64_t* totals, int mode, hipStream_t st) {
-  k_roots<<<1, 1024, 0, st>>>(a, n_roots, sub_cnt, leaf_by_rank, pp_len, totals, mode);
+                        int32_t* pp_len, int64_t* totals, int mode, int64_t* rb, hipStream_t st) {
+  k_roots<<<1, 1024, 0, st>>>(a, n_roots, sub_cnt, leaf_by_rank, pp_len, totals, mode, rb);
   return hipGetLastError();
 }
 

@@ -300,7 +300,7 @@ hipError_t launch_tp_len(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n
   if (n_pp == 0) return hipSuccess;
   const unsigned grid = (unsigned)((n_pp + kBlock - 1) / kBlock);
   if (tp_len) k_tp_len<<<grid, kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, b, tp_len);
-  k_run_bounds<<<grid, kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, n, rb);
+  if (rb) k_run_bounds<<<grid, kBlock, 0, st>>>(pp_off, pp_vtx, n_pp, n, rb);
   return hipGetLastError();
 }
 
