@@ -20,6 +20,14 @@ def _check_batch(cfgs, res):
         assert np.array_equal(to, rt.offsets) and np.array_equal(tv, rt.vertices), (i, g.name, "TP")
 
 
+def _same_result(a, b):
+    return (np.array_equal(a.pp_first, b.pp_first) and np.array_equal(a.tp_first, b.tp_first)
+            and np.array_equal(a.pp.offsets, b.pp.offsets)
+            and np.array_equal(a.pp.vertices, b.pp.vertices)
+            and np.array_equal(a.tp.offsets, b.tp.offsets)
+            and np.array_equal(a.tp.vertices, b.tp.vertices))
+
+
 def _mixed():
     cfgs = [cfggen.fig1_cfg(), cfggen.from_edges(1, [], 0, 0)]
     cfgs += [cfggen.c1_cfg(s) for s in range(4)]
@@ -92,6 +100,31 @@ def test_batch_underpredicted_sizes_fall_back_exactly():
     w.close()
 
 
+def test_batch_overpredicted_and_nonfinite_sizes_fall_back_exactly():
+    """Predictions far above anything real (every level at log1p 40), and
+    infinite or not-a-number entries, under a pool cap: the capacities are
+    clamped, unions that cannot be allocated are sized exactly instead, and
+    every byte equals the two-pass result, on a fresh workspace and again on
+    the warm one."""
+    cfgs = [cfggen.batch_member_cfg(cfggen.C3_SEED_BASE + s) for s in range(120)]
+    hs = [tpg.load_cfg(g) for g in cfgs]
+    say("case batch over-prediction")
+    ref, _ = tpg.batch_test_paths(hs, ws=ws(), flags=tpg.TPG_FORCE_TWO_PASS)
+    pred = np.full((len(cfgs), 65), 40.0, np.float32)
+    pred[3, :] = np.inf
+    pred[7, 5] = np.nan
+    pred[11, 63] = -np.inf
+    w = tpg.Workspace()
+    cap = 8 << 30
+    res, st = tpg.batch_test_paths(hs, ws=w, predicted=pred, pool_cap=cap)
+    assert _same_result(res, ref)
+    assert w.bytes <= cap
+    res2, _ = tpg.batch_test_paths(hs, ws=w, predicted=pred, pool_cap=cap)
+    assert _same_result(res2, ref)
+    say("  unions", st["n_unions"], "overflows", st["n_overflows"], "bytes", w.bytes)
+    w.close()
+
+
 def test_batch_device_output():
     cfgs = [cfggen.c1_cfg(s) for s in range(3)] + [cfggen.fig1_cfg()]
     hs = [tpg.load_cfg(g) for g in cfgs]
@@ -137,14 +170,6 @@ def test_autotune_then_batch_is_exact():
     res, _ = tpg.batch_test_paths(hs, ws=w)
     _check_batch(cfgs, res)
     w.close()
-
-
-def _same_result(a, b):
-    return (np.array_equal(a.pp_first, b.pp_first) and np.array_equal(a.tp_first, b.tp_first)
-            and np.array_equal(a.pp.offsets, b.pp.offsets)
-            and np.array_equal(a.pp.vertices, b.pp.vertices)
-            and np.array_equal(a.tp.offsets, b.tp.offsets)
-            and np.array_equal(a.tp.vertices, b.tp.vertices))
 
 
 @pytest.mark.parametrize("learned", [False, True])
