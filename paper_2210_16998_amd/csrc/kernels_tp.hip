@@ -372,13 +372,13 @@ hipError_t launch_pack_tables(int n, const BfsOut& b, int eb, hipStream_t st) {
 
 // A workgroup splices kSplicePaths consecutive test paths.  Their layout
 // (where each one's prefix, prime-path and suffix entries are, and the word
-// offset of its packed suffix row) goes to LDS with a map of the workgroup's
-// packed words to their paths, then each thread builds one packed word at a
-// time (pe consecutive entries; the words of the paths are one flat range).
-// A word that lies wholly in the prefix is not written: it is the same word
-// of the first vertex's packed prefix row, from which the unpack takes it,
-// and no comparison reads it (they start past the prime path's first
-// vertex).  A word that lies wholly in the suffix is cut from two
+// offset of its packed suffix row) goes to LDS with a map of the words it
+// builds to their paths, then each thread builds one packed word at a time
+// (pe consecutive entries; the built words of the paths are one flat range).
+// A word that lies wholly in the prefix is neither written nor visited: it is
+// the same word of the first vertex's packed prefix row, from which the
+// unpack takes it, and no comparison reads it (they start past the prime
+// path's first vertex).  A word that lies wholly in the suffix is cut from two
 // consecutive words of the last vertex's packed suffix row; one that lies
 // wholly in the prime path packs pe consecutive prime-path entries; only the
 // words across two of these parts are built entry by entry.  The entry width
@@ -390,7 +390,7 @@ hipError_t launch_pack_tables(int n, const BfsOut& b, int eb, hipStream_t st) {
 // built entry by entry): the comparisons read the packed words and the kept
 // paths are unpacked from them when gathered.
 constexpr int kSplicePaths = 64;
-constexpr int kSpliceMap = 8192;  // words a workgroup maps to paths in LDS
+constexpr int kSpliceMap = 8192;  // built words a workgroup maps to paths in LDS
 constexpr int kSpliceMixed = 512;  // words across two parts listed per workgroup
 
 struct SpliceRow {
@@ -460,7 +460,9 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
   __shared__ int64_t s_w[kSplicePaths + 1];   // entry offsets
   __shared__ int32_t s_a[kSplicePaths + 1];   // packed-word offsets from the first path's
   __shared__ int64_t s_sb[kSplicePaths];      // first word of the packed suffix row
-  __shared__ uint8_t s_map[kSpliceMap];       // word -> path
+  __shared__ int32_t s_c[kSplicePaths + 1];   // built words before each path
+  __shared__ int32_t s_q0[kSplicePaths];      // a path's first built word
+  __shared__ uint8_t s_map[kSpliceMap];       // built word -> path
   __shared__ int64_t s_a0;
   const int tid = (int)threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.x * kSplicePaths;
@@ -494,19 +496,35 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
   __syncthreads();
   const int64_t a0 = s_a0;
   if (tid <= cnt) s_a[tid] = (int32_t)(a_mine - a0);
+  // The words built here: from the first one holding an entry past the tree
+  // prefix (the prefix-only words are the packed prefix row's, left alone)
+  // to the last one holding an entry; the slack after it is not touched.
+  // Without plain entries to write, the loop below runs over these words
+  // only, counted from 0 across the workgroup's paths.
+  int32_t nb = 0;
+  if (tid < cnt) {
+    const SpliceRow& r = s_row[tid];
+    const int len = r.lp + r.lq + r.ls;
+    const int q0 = tp_vtx ? 0 : r.lp / pe;
+    s_q0[tid] = q0;
+    nb = (len + pe - 1) / pe - q0;
+  }
+  const int32_t nb_inc = wave_incl_scan(nb);  // the paths fit in the first wave
+  if (tid < cnt) s_c[tid + 1] = nb_inc;
+  if (tid == 0) s_c[0] = 0;
   __syncthreads();
-  const int32_t na = s_a[cnt];
-  const bool mapped = na <= kSpliceMap;
+  const int32_t nc = s_c[cnt];
+  const bool mapped = nc <= kSpliceMap;
   if (mapped && tid < cnt)
-    for (int32_t w = s_a[tid]; w < s_a[tid + 1]; ++w) s_map[w] = (uint8_t)tid;
+    for (int32_t c = s_c[tid]; c < s_c[tid + 1]; ++c) s_map[c] = (uint8_t)tid;
   __syncthreads();
-  // the path of word w
-  auto path_of = [&](int32_t w) -> int {
-    if (mapped) return s_map[w];
-    int lo = 0, hi = cnt - 1;  // the last path whose words start at or before w
+  // the path of built word c
+  auto path_of = [&](int32_t c) -> int {
+    if (mapped) return s_map[c];
+    int lo = 0, hi = cnt - 1;  // the last path whose built words start at or before c
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (s_a[mid] <= w) lo = mid; else hi = mid - 1;
+      if (s_c[mid] <= c) lo = mid; else hi = mid - 1;
     }
     return lo;
   };
@@ -549,21 +567,18 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
   // across two parts (about two per test path) would make every wave run
   // the entry-by-entry path as well, so they are listed and built after the
   // others, all lanes then taking that path together.
-  for (int32_t w = tid; w < na; w += kBlock) {
-    const int t = path_of(w);
+  for (int32_t c = tid; c < nc; c += kBlock) {
+    const int t = path_of(c);
     const SpliceRow r = s_row[t];
-    const int len = r.lp + r.lq + r.ls;
-    const int q = w - s_a[t];
+    const int q = s_q0[t] + (c - s_c[t]);
+    const int32_t w = s_a[t] + q;
     const int k0 = q * pe;
-    if (k0 >= len) continue;  // slack between two paths
     if (tp_vtx) {
       build_mixed(w, t);  // plain entries asked for: every word entry by entry
       continue;
     }
     uint64_t word = 0;
-    if (k0 + pe <= r.lp) {
-      continue;  // wholly in the prefix: left to the packed prefix row
-    } else if (k0 >= r.lp + r.lq) {
+    if (k0 >= r.lp + r.lq) {
       const int j0 = k0 - r.lp - r.lq;  // first suffix entry of the word
       const int sq = j0 / pe, sr = j0 - sq * pe;
       const uint64_t* row = b.sfx_pk + s_sb[t];
@@ -585,7 +600,7 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
       for (int j = 0; j < (pe <= 16 ? pe : 1); ++j) word = (word << EB) | (uint64_t)(uint32_t)(x[j] + 1);
     } else {
       const int m = atomicAdd(&s_nmix, 1);
-      if (m < kSpliceMixed) s_mix[m] = w;
+      if (m < kSpliceMixed) s_mix[m] = c;
       else build_mixed(w, t);  // the list is full: build it here
       continue;
     }
@@ -594,8 +609,9 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
   __syncthreads();
   const int nmix = s_nmix < kSpliceMixed ? s_nmix : kSpliceMixed;
   for (int m = tid; m < nmix; m += kBlock) {
-    const int32_t w = s_mix[m];
-    build_mixed(w, path_of(w));
+    const int32_t c = s_mix[m];
+    const int t = path_of(c);
+    build_mixed(s_a[t] + s_q0[t] + (c - s_c[t]), t);
   }
   __syncthreads();
   // the key's entry words: windows of pe entries from the first entry after e
