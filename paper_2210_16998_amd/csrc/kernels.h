@@ -253,7 +253,7 @@ constexpr int kTpKeyTail = 4;
 constexpr int kTpKeyWords = 2 + kTpKeyTail;
 struct TpOrder {
   const int64_t* off;   // [n + 1] test-path offsets
-  const uint64_t* key;  // [kTpKeyWords n]
+  const uint64_t* key;  // [kTpKeyWords n], 16-byte aligned
   const uint64_t* pk;   // the entries packed (see k_tp_write)
   int eb;               // bits per packed entry (entry + 1; 0 = past the end)
   int pe;               // packed entries per 64-bit word, 64 / eb

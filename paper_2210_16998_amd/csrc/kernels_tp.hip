@@ -844,6 +844,7 @@ __device__ __forceinline__ int64_t merge_split_wave(const TpOrder& K, const int3
 constexpr int kMergeThreads = 256;
 constexpr int kMergeItems = 4;
 constexpr int kMergeTile = kMergeThreads * kMergeItems;
+static_assert(kTpKeyWords % 2 == 0, "keys are loaded 16 bytes at a time");
 constexpr int kSplitWaves = 4;  // splits found per workgroup of k_merge_splits
 
 // The pair of runs holding output position pos: its index p, and [a0, a1)
@@ -909,12 +910,37 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_round(TpOrder K, const 
     const int64_t ia = pos == t0 ? split[blockIdx.x] : 0, ja = (pos - a0) - ia;
     const int64_t ib = stop == b1 ? na : split[blockIdx.x + 1], jb = (stop - a0) - ib;
     const int la = (int)(ib - ia), lb = (int)(jb - ja);
-    for (int q = tid; q < la + lb; q += kMergeThreads) {
-      const int32_t x = q < la ? A[ia + q] : B[ja + (q - la)];
-      s_idx[q] = x;
-      const uint64_t* kx = K.key + (int64_t)kTpKeyWords * x;
+    // A segment has at most kMergeTile inputs: kMergeItems per thread.  All
+    // of a thread's index loads go out together, then all its key loads (a
+    // key is kTpKeyWords words at a 16-byte aligned address), so the staging
+    // waits for two load latencies, not two per input.
+    {
+      int32_t xs[kMergeItems];
 #pragma unroll
-      for (int t = 0; t < kTpKeyWords; ++t) s_key[t][q] = kx[t];
+      for (int u = 0; u < kMergeItems; ++u) {
+        const int q = tid + u * kMergeThreads;
+        xs[u] = q < la ? A[ia + q] : (q < la + lb ? B[ja + (q - la)] : -1);
+      }
+      ulonglong2 kv[kMergeItems][kTpKeyWords / 2];
+#pragma unroll
+      for (int u = 0; u < kMergeItems; ++u) {
+        if (xs[u] < 0) continue;
+        const ulonglong2* kx =
+            reinterpret_cast<const ulonglong2*>(K.key + (int64_t)kTpKeyWords * xs[u]);
+#pragma unroll
+        for (int h = 0; h < kTpKeyWords / 2; ++h) kv[u][h] = kx[h];
+      }
+#pragma unroll
+      for (int u = 0; u < kMergeItems; ++u) {
+        if (xs[u] < 0) continue;
+        const int q = tid + u * kMergeThreads;
+        s_idx[q] = xs[u];
+#pragma unroll
+        for (int h = 0; h < kTpKeyWords / 2; ++h) {
+          s_key[2 * h][q] = kv[u][h].x;
+          s_key[2 * h + 1][q] = kv[u][h].y;
+        }
+      }
     }
     __syncthreads();
     // this thread's outputs within the segment, merged from LDS
