@@ -74,6 +74,15 @@ __device__ __forceinline__ T wave_incl_scan(T x) {
   return x;
 }
 
+// Orders the LDS accesses of one wave's lanes: what a lane wrote before it is
+// seen by the other lanes of its wave after it (a wave runs in lockstep; this
+// keeps the compiler from moving LDS accesses across it and waits for them).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Exclusive scan across a workgroup of NT threads; s_w needs NT/64 slots.
 template <int NT, class T>
 __device__ __forceinline__ T block_excl_scan(T x, T& total, T* s_w) {

@@ -840,52 +840,101 @@ hipError_t launch_down_run(const ExtArgs& a, int depth, int L, int64_t base, int
   return hipGetLastError();
 }
 
-// Each thread writes one prime path by walking parent links from its leaf.
-// The walk yields entries back to front; they are buffered 32 at a time in
-// registers and stored as one burst of consecutive addresses, so that lines
-// are written whole instead of one word per dependent load.  With the BFS
-// tables given, the walk also checks each entry against the BFS parent of
-// the one after it and records the test path's length and where the path
-// leaves the BFS tree (the test-path keys start from there).
+// Each wave writes the prime paths of 64 consecutive ranks, one per lane, by
+// walking parent links from their leaves.  The walks are aligned by depth: a
+// lane starts when the wave reaches the depth of its leaf, so at every step
+// the active lanes stand on one tree level, at nodes close together in that
+// level's array (consecutive ranks are neighbours in depth-first order), and
+// a load touches few cache lines.  The entries of kPPSeg consecutive depths
+// go to LDS, one row per lane; then the wave stores the rows, kPPSeg lanes
+// per row, so that a store covers a few whole row segments instead of one
+// word in each of 64 lines.  With the BFS tables given, the walk also checks
+// each entry against the BFS parent of the one after it and records the test
+// path's length and where the path leaves the BFS tree (the test-path keys
+// start from there).
+constexpr int kPPSeg = 16;
+constexpr int kPPRow = kPPSeg + 1;  // LDS row stride (odd: rows fall in different banks)
+
 __global__ __launch_bounds__(kBlock) void k_pp_write(ExtArgs a, const int64_t* leaf_by_rank,
                                                      const int64_t* pp_off, int64_t n_pp,
                                                      int32_t* pp_vtx, PPWriteTp tp) {
-  constexpr int kBuf = 32;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n_pp) return;
-  int64_t x = leaf_by_rank[i];
-  int64_t pos = pp_off[i + 1] - 1;
-  const int64_t lo = pp_off[i];
+  __shared__ int32_t s_row[kBlock * kPPRow];
+  __shared__ int64_t s_lo[kBlock];
+  __shared__ int32_t s_len[kBlock];
+  __shared__ int32_t s_done[kBlock];
+  const int tid = (int)threadIdx.x, lane = lane_id(), wb = tid - lane;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + tid;
+  int64_t lo = 0;
+  int32_t len = 0;
+  int32_t x = -1;
+  if (i < n_pp) {
+    lo = pp_off[i];
+    len = (int32_t)(pp_off[i + 1] - lo);
+    x = (int32_t)leaf_by_rank[i];
+  }
+  s_lo[tid] = lo;
+  s_len[tid] = len;
+  int32_t lmax = len;  // the wave's longest path
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const int32_t y = __shfl_xor(lmax, d, 64);
+    lmax = y > lmax ? y : lmax;
+  }
   const bool with_tp = tp.tp_len != nullptr;
-  int32_t nxt = -1, vk = -1;  // the entry after the current one; the last entry
-  int32_t lead = (int32_t)(pos + 1 - lo);
-  while (pos >= lo && x >= 0) {
-    int32_t buf[kBuf];
-    int cnt = 0;
+  int32_t done = len;  // entries done .. len - 1 are walked
+  int32_t nxt = -1, vk = -1, lead = len;  // the entry after the current one; the last entry
+  int32_t pn = -1;                        // BFS parent of nxt
+  int32_t* row = s_row + tid * kPPRow;
+  for (int kb = lmax > 0 ? (lmax - 1) / kPPSeg * kPPSeg : -1; kb >= 0; kb -= kPPSeg) {
+    // depths kb + kPPSeg - 1 down to kb: one dependent load per step
+    const int32_t top = done;
+    int32_t v[kPPSeg];
 #pragma unroll
-    for (int j = 0; j < kBuf; ++j) {
-      if (pos - j >= lo && x >= 0) {
-        buf[j] = node_v(a.t.info[x]);
+    for (int m = kPPSeg - 1; m >= 0; --m) {
+      const int k = kb + m;
+      v[m] = -1;
+      if (k < len && x >= 0) {
+        v[m] = node_v(a.t.info[x]);
         x = a.t.par[x];
-        cnt = j + 1;
+        done = k;
       }
     }
 #pragma unroll
-    for (int j = kBuf - 1; j >= 0; --j)
-      if (j < cnt) pp_vtx[pos - j] = buf[j];
+    for (int m = 0; m < kPPSeg; ++m) row[m] = v[m];
     if (with_tp) {
-      for (int j = 0; j < cnt; ++j) {
-        const int32_t v = buf[j];
-        if (nxt < 0) vk = v;
-        else if (tp.parent[nxt] != v) lead = (int32_t)(pos - j + 1 - lo);
-        nxt = v;
+      // the BFS parents of the round's entries, loaded together, then the
+      // pairs (entry k, entry k + 1) checked from the last one down
+      int32_t pv[kPPSeg];
+#pragma unroll
+      for (int m = 0; m < kPPSeg; ++m) {
+        const int k = kb + m;
+        pv[m] = k >= done && k < top ? tp.parent[v[m]] : -1;
+      }
+#pragma unroll
+      for (int m = kPPSeg - 1; m >= 0; --m) {
+        const int k = kb + m;
+        if (k >= done && k < top) {
+          if (nxt < 0) vk = v[m];
+          else if (pn != v[m]) lead = k + 1;
+          nxt = v[m];
+          pn = pv[m];
+        }
       }
     }
-    pos -= cnt;
+    s_done[tid] = done;
+    wave_sync();
+    // the wave's rows, kPPSeg lanes per row: depths kb .. kb + kPPSeg - 1 of
+    // each path, those walked in this round
+#pragma unroll
+    for (int r0 = 0; r0 < 64; r0 += 64 / kPPSeg) {
+      const int r = wb + r0 + lane / kPPSeg, k = kb + lane % kPPSeg;
+      if (k >= s_done[r] && k < s_len[r]) pp_vtx[s_lo[r] + k] = s_row[r * kPPRow + (k - kb)];
+    }
+    wave_sync();  // the rows are read before the next round writes them
   }
   if (with_tp && nxt >= 0) {
     const int32_t v1 = nxt;
-    tp.tp_len[i] = (tp.pfx_off[v1 + 1] - tp.pfx_off[v1]) + (pp_off[i + 1] - lo) +
+    tp.tp_len[i] = (tp.pfx_off[v1 + 1] - tp.pfx_off[v1]) + len +
                    (tp.sfx_off[vk + 1] - tp.sfx_off[vk]);
     tp.lead[i] = lead;
   }
