@@ -284,7 +284,7 @@ hipError_t launch_tp_write(const int64_t* pp_off, const int32_t* pp_vtx, int64_t
                            uint64_t* key, uint64_t* pk, int eb, int32_t* idx,
                            const int32_t* lead, hipStream_t st);
 // one round of pairwise merging of sorted runs [rb[r], rb[r+1]) of idx;
-// split: device scratch of merge_split_slots(n) int64 (the tiles' splits)
+// split: device scratch of merge_split_slots(n) int64 (the tiles' splits and pairs)
 hipError_t launch_merge_round(const TpOrder& K, const int32_t* idx_in, int32_t* idx_out,
                               const int64_t* rb, int64_t n_runs, int64_t n, int64_t* split,
                               hipStream_t st);

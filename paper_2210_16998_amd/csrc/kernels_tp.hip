@@ -847,39 +847,50 @@ constexpr int kMergeTile = kMergeThreads * kMergeItems;
 static_assert(kTpKeyWords % 2 == 0, "keys are loaded 16 bytes at a time");
 constexpr int kSplitWaves = 4;  // splits found per workgroup of k_merge_splits
 
-// The pair of runs holding output position pos: its index p, and [a0, a1)
-// with [a1, b1).
-__device__ __forceinline__ int64_t merge_pair_of(const int64_t* rb, int64_t n_runs, int64_t pos) {
-  int64_t lo = 0, hi = n_runs - 1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (rb[mid] <= pos) lo = mid; else hi = mid - 1;
-  }
-  return lo >> 1;
-}
+// Pair p of runs: [a0, a1) with [a1, b1).
 __device__ __forceinline__ void merge_pair_bounds(const int64_t* rb, int64_t n_runs, int64_t p,
                                                   int64_t& a0, int64_t& a1, int64_t& b1) {
   a0 = rb[2 * p];
   a1 = rb[2 * p + 1 < n_runs ? 2 * p + 1 : n_runs];
   b1 = rb[2 * p + 2 < n_runs ? 2 * p + 2 : n_runs];
 }
-__device__ __forceinline__ void merge_pair(const int64_t* rb, int64_t n_runs, int64_t pos,
-                                           int64_t& a0, int64_t& a1, int64_t& b1) {
-  merge_pair_bounds(rb, n_runs, merge_pair_of(rb, n_runs, pos), a0, a1, b1);
+// The pair of runs holding output position pos, found by a whole wave: each
+// step its lanes test 64 evenly spaced run starts at once.
+__device__ __forceinline__ int64_t merge_pair_of_wave(const int64_t* rb, int64_t n_runs,
+                                                      int64_t pos) {
+  int64_t lo = 0, hi = n_runs - 1;  // the last run starting at or before pos is in [lo, hi]
+  while (lo < hi) {
+    const int64_t step = (hi - lo + 63) / 64;
+    const int64_t c = lo + 1 + (int64_t)lane_id() * step;  // candidates lo + 1 .. hi
+    const uint64_t t = __ballot(c <= hi && rb[c] <= pos);
+    if (t == 0) {
+      hi = lo;
+    } else {
+      const int64_t ck = lo + 1 + (int64_t)(63 - __builtin_clzll(t)) * step;
+      lo = ck;
+      hi = ck + step - 1 < hi ? ck + step - 1 : hi;
+    }
+  }
+  return lo >> 1;
 }
 
-// split[b]: how many of the first (b * kMergeTile - a0) outputs of its pair's
-// merge come from the pair's first run.
+// For tile b (its first output at b * kMergeTile): split[b], how many of the
+// first (b * kMergeTile - a0) outputs of its pair's merge come from the
+// pair's first run, and split[n_tiles + 1 + b], the pair's index.
 __global__ __launch_bounds__(64 * kSplitWaves) void k_merge_splits(TpOrder K, const int32_t* in,
                                                                   const int64_t* rb, int64_t n_runs,
                                                                   int64_t n_tiles, int64_t* split) {
   const int64_t b = (int64_t)blockIdx.x * kSplitWaves + (threadIdx.x >> 6);
   if (b >= n_tiles) return;  // whole waves
   const int64_t pos = b * kMergeTile;
+  const int64_t p = merge_pair_of_wave(rb, n_runs, pos);
   int64_t a0, a1, b1;
-  merge_pair(rb, n_runs, pos, a0, a1, b1);
+  merge_pair_bounds(rb, n_runs, p, a0, a1, b1);
   const int64_t r = merge_split_wave(K, in + a0, a1 - a0, in + a1, b1 - a1, pos - a0);
-  if (lane_id() == 0) split[b] = r;
+  if (lane_id() == 0) {
+    split[b] = r;
+    split[n_tiles + 1 + b] = p;
+  }
 }
 
 __global__ __launch_bounds__(kMergeThreads) void k_merge_round(TpOrder K, const int32_t* in,
@@ -892,9 +903,11 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_round(TpOrder K, const 
   const int64_t t0 = (int64_t)blockIdx.x * kMergeTile;
   const int64_t t1 = t0 + kMergeTile < n ? t0 + kMergeTile : n;
   int64_t pos = t0;
-  // the tile's first pair by search; each later segment starts the next pair
-  // (an empty pair ends where it starts and is stepped over)
-  int64_t p = merge_pair_of(rb, n_runs, pos);
+  // the tile's first pair as k_merge_splits found it; each later segment
+  // starts the next pair (an empty pair ends where it starts and is stepped
+  // over)
+  const int64_t n_tiles = (n + kMergeTile - 1) / kMergeTile;
+  int64_t p = split[n_tiles + 1 + blockIdx.x];
   while (pos < t1) {
     int64_t a0, a1, b1;
     merge_pair_bounds(rb, n_runs, p, a0, a1, b1);
@@ -976,7 +989,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_round(TpOrder K, const 
   }
 }
 
-int64_t merge_split_slots(int64_t n) { return (n + kMergeTile - 1) / kMergeTile + 1; }
+int64_t merge_split_slots(int64_t n) { return 2 * ((n + kMergeTile - 1) / kMergeTile + 1); }
 
 hipError_t launch_merge_round(const TpOrder& K, const int32_t* idx_in, int32_t* idx_out,
                               const int64_t* rb, int64_t n_runs, int64_t n, int64_t* split,
