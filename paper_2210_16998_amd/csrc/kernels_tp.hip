@@ -876,7 +876,10 @@ __device__ __forceinline__ int64_t merge_pair_of_wave(const int64_t* rb, int64_t
 
 // For tile b (its first output at b * kMergeTile): split[b], how many of the
 // first (b * kMergeTile - a0) outputs of its pair's merge come from the
-// pair's first run, and split[n_tiles + 1 + b], the pair's index.
+// pair's first run, and split[n_tiles + 1 + b], the pair's index times two,
+// plus one when the pair is already in order (its first run's last path does
+// not come after the second run's first, or a run is empty).  The merge of
+// such a pair is its input as it stands, and the split needs no search.
 __global__ __launch_bounds__(64 * kSplitWaves) void k_merge_splits(TpOrder K, const int32_t* in,
                                                                   const int64_t* rb, int64_t n_runs,
                                                                   int64_t n_tiles, int64_t* split) {
@@ -886,10 +889,13 @@ __global__ __launch_bounds__(64 * kSplitWaves) void k_merge_splits(TpOrder K, co
   const int64_t p = merge_pair_of_wave(rb, n_runs, pos);
   int64_t a0, a1, b1;
   merge_pair_bounds(rb, n_runs, p, a0, a1, b1);
-  const int64_t r = merge_split_wave(K, in + a0, a1 - a0, in + a1, b1 - a1, pos - a0);
+  const bool ordered = a1 == a0 || b1 == a1 || tp_cmp(K, in[a1 - 1], in[a1]) <= 0;
+  const int64_t d = pos - a0;
+  const int64_t r = ordered ? (d < a1 - a0 ? d : a1 - a0)
+                            : merge_split_wave(K, in + a0, a1 - a0, in + a1, b1 - a1, d);
   if (lane_id() == 0) {
     split[b] = r;
-    split[n_tiles + 1 + b] = p;
+    split[n_tiles + 1 + b] = 2 * p + (ordered ? 1 : 0);
   }
 }
 
@@ -907,7 +913,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_round(TpOrder K, const 
   // starts the next pair (an empty pair ends where it starts and is stepped
   // over)
   const int64_t n_tiles = (n + kMergeTile - 1) / kMergeTile;
-  int64_t p = split[n_tiles + 1 + blockIdx.x];
+  const int64_t pv = split[n_tiles + 1 + blockIdx.x];
+  int64_t p = pv >> 1;
   while (pos < t1) {
     int64_t a0, a1, b1;
     merge_pair_bounds(rb, n_runs, p, a0, a1, b1);
@@ -917,6 +924,12 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_round(TpOrder K, const 
     const int32_t* B = in + a1;
     const int64_t na = a1 - a0;
     const int64_t stop = t1 < b1 ? t1 : b1;
+    if (pos == t0 && (pv & 1)) {
+      // the first pair (it holds t0) is in order: output q is input q
+      for (int64_t q = pos + tid; q < stop; q += kMergeThreads) out[q] = in[q];
+      pos = stop;
+      continue;
+    }
     // input slices of this segment: the tile's first segment starts at its
     // split, a later one at the start of its pair; a segment ends at the end
     // of its pair or at the next tile's split
