@@ -74,6 +74,50 @@ __device__ __forceinline__ T wave_incl_scan(T x) {
   return x;
 }
 
+// Words 0 and 1 of a test path's comparison key, from where the path leaves
+// the BFS tree: w, the tree path's last vertex, at entry index first - 1;
+// the entry e after it (has_e: the path goes on past w); v1, the prime
+// path's first vertex.  Word 0: pre(w) | pend(w) << 18 | (first - 1) << 36 |
+// has_e << 49.  Word 1: e | split << 17 | pre(v1) << 35, where split is the
+// preorder rank of w's first tree child with an id above e (pend(w) if none;
+// pre(w) + 1 without e).  pre, pend: BFS-tree preorder ranks; w's tree
+// children are bq[cfirst[w] .. cfirst[w] + ccnt[w]), ascending.  kk: 16-byte
+// aligned.
+__device__ __forceinline__ void tp_tree_key(const int32_t* pre, const int32_t* pend,
+                                            const int32_t* cfirst, const int32_t* ccnt,
+                                            const int32_t* bq, int w, int first, bool has_e,
+                                            int ev, int v1, uint64_t* kk) {
+  const uint32_t prew = (uint32_t)pre[w], pendw = (uint32_t)pend[w];
+  uint32_t split;
+  if (has_e) {
+    split = pendw;
+    const int cf = cfirst[w], cn = ccnt[w];
+    // the children eight at a time, their loads in flight together
+    for (int q0 = 0; q0 < cn; q0 += 8) {
+      int cv[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) cv[j] = q0 + j < cn ? bq[cf + q0 + j] : -1;
+      int hit = -1;
+#pragma unroll
+      for (int j = 7; j >= 0; --j)
+        if (cv[j] > ev) hit = cv[j];
+      if (hit >= 0) {
+        split = (uint32_t)pre[hit];
+        break;
+      }
+    }
+  } else {
+    split = prew + 1;
+  }
+  // one 16-byte store (kk is 16-byte aligned)
+  ulonglong2 kw;
+  kw.x = (uint64_t)prew | ((uint64_t)pendw << 18) | ((uint64_t)(first - 1) << 36) |
+         ((uint64_t)(has_e ? 1 : 0) << 49);
+  kw.y = (uint64_t)(uint32_t)(has_e ? ev : 0) | ((uint64_t)split << 17) |
+         ((uint64_t)(uint32_t)pre[v1] << 35);
+  *reinterpret_cast<ulonglong2*>(kk) = kw;
+}
+
 // Orders the LDS accesses of one wave's lanes: what a lane wrote before it is
 // seen by the other lanes of its wave after it (a wave runs in lockstep; this
 // keeps the compiler from moving LDS accesses across it and waits for them).

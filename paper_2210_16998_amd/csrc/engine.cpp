@@ -879,17 +879,18 @@ tpg_status rank_and_materialize(tpg_workspace* ws, const HostUnion& U, hipStream
   P.n_vtx = ws->h_scalars[6];
   TPG_TRY(ws_reserve(ws, o.pp_vtx, sizeof(int32_t) * (P.n_vtx + 1)));
   // with the BFS under way (test paths follow), the writer also records each
-  // test path's length and where its prime path leaves the BFS tree; the BFS
-  // ran beside the extension and is long done
+  // test path's length and where its prime path leaves the BFS tree, with
+  // the entries around that point; the BFS ran beside the extension and is
+  // long done
   PPWriteTp tpx{};
   ws->tp_len_ready = false;
   if (ws->bfs_pending) {
     TPG_TRY(ws_reserve(ws, ws->tp_len, sizeof(int64_t) * (P.n_pp + 1)));
-    TPG_TRY(ws_reserve(ws, ws->tp_lead, sizeof(int32_t) * (P.n_pp + 1)));
+    TPG_TRY(ws_reserve(ws, ws->tp_lead, sizeof(int4) * (P.n_pp + 1)));
     TPG_HIP(hipStreamWaitEvent(st, ws->ev_join, 0));
     const BfsOut bv = bfs_views(ws, U.n);
     tpx = PPWriteTp{bv.parent, bv.pfx_off, bv.sfx_off, ws->tp_len.as<int64_t>(),
-                    ws->tp_lead.as<int32_t>()};
+                    ws->tp_lead.as<int4>()};
     ws->tp_len_ready = true;
   }
   TPG_HIP(launch_pp_write(a, lbr, o.pp_off.as<int64_t>(), P.n_pp, o.pp_vtx.as<int32_t>(), tpx,
@@ -1097,7 +1098,7 @@ tpg_status test_paths_device(tpg_workspace* ws, const HostUnion& U, hipStream_t 
   TPG_HIP(launch_tp_write(o.pp_off.as<int64_t>(), o.pp_vtx.as<int32_t>(), np, b,
                           ws->tp_off.as<int64_t>(), greedy ? ws->tp_vtx.as<int32_t>() : nullptr,
                           ws->tp_key.as<uint64_t>(), ws->tp_pk.as<uint64_t>(), eb,
-                          ws->idx0.as<int32_t>(), from_writer ? ws->tp_lead.as<int32_t>() : nullptr,
+                          ws->idx0.as<int32_t>(), from_writer ? ws->tp_lead.as<int4>() : nullptr,
                           st));
   // with longest-first covering only the chosen test paths are sorted
   int64_t nm = np;

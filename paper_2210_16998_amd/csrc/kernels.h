@@ -99,7 +99,10 @@ struct PPWriteTp {
   const int64_t* pfx_off;  // prefix / suffix table offsets (their lengths)
   const int64_t* sfx_off;
   int64_t* tp_len;
-  int32_t* lead;
+  // per prime path: (lead, w, e, v1): the first entry index t >= 1 whose BFS
+  // parent is not entry t - 1 (the length if none), the entries w at lead - 1
+  // and e at lead (-1 if none), and the first vertex
+  int4* lead;
 };
 hipError_t launch_pp_write(const ExtArgs& a, const int64_t* leaf_by_rank, const int64_t* pp_off,
                            int64_t n_pp, int32_t* pp_vtx, const PPWriteTp& tp, hipStream_t st);
@@ -282,7 +285,7 @@ hipError_t launch_pack_tables(int n, const BfsOut& b, int eb, hipStream_t st);
 hipError_t launch_tp_write(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp,
                            const BfsOut& b, const int64_t* tp_off, int32_t* tp_vtx,
                            uint64_t* key, uint64_t* pk, int eb, int32_t* idx,
-                           const int32_t* lead, hipStream_t st);
+                           const int4* lead, hipStream_t st);
 // one round of pairwise merging of sorted runs [rb[r], rb[r+1]) of idx;
 // split: device scratch of merge_split_slots(n) int64 (the tiles' splits and pairs)
 hipError_t launch_merge_round(const TpOrder& K, const int32_t* idx_in, int32_t* idx_out,

@@ -850,8 +850,9 @@ hipError_t launch_down_run(const ExtArgs& a, int depth, int L, int64_t base, int
 // per row, so that a store covers a few whole row segments instead of one
 // word in each of 64 lines.  With the BFS tables given, the walk also checks
 // each entry against the BFS parent of the one after it and records the test
-// path's length and where the path leaves the BFS tree (the test-path keys
-// start from there).
+// path's length and where the path leaves the BFS tree, with the entries on
+// either side of that point and the first vertex, from which the test-path
+// keys are built.
 constexpr int kPPSeg = 16;
 constexpr int kPPRow = kPPSeg + 1;  // LDS row stride (odd: rows fall in different banks)
 
@@ -884,6 +885,7 @@ __global__ __launch_bounds__(kBlock) void k_pp_write(ExtArgs a, const int64_t* l
   int32_t done = len;  // entries done .. len - 1 are walked
   int32_t nxt = -1, vk = -1, lead = len;  // the entry after the current one; the last entry
   int32_t pn = -1;                        // BFS parent of nxt
+  int32_t lw = -1, le = -1;               // the entries at lead - 1 and lead
   int32_t* row = s_row + tid * kPPRow;
   for (int kb = lmax > 0 ? (lmax - 1) / kPPSeg * kPPSeg : -1; kb >= 0; kb -= kPPSeg) {
     // depths kb + kPPSeg - 1 down to kb: one dependent load per step
@@ -915,7 +917,11 @@ __global__ __launch_bounds__(kBlock) void k_pp_write(ExtArgs a, const int64_t* l
         const int k = kb + m;
         if (k >= done && k < top) {
           if (nxt < 0) vk = v[m];
-          else if (pn != v[m]) lead = k + 1;
+          else if (pn != v[m]) {
+            lead = k + 1;
+            lw = v[m];
+            le = nxt;
+          }
           nxt = v[m];
           pn = pv[m];
         }
@@ -934,9 +940,9 @@ __global__ __launch_bounds__(kBlock) void k_pp_write(ExtArgs a, const int64_t* l
   }
   if (with_tp && nxt >= 0) {
     const int32_t v1 = nxt;
-    tp.tp_len[i] = (tp.pfx_off[v1 + 1] - tp.pfx_off[v1]) + len +
-                   (tp.sfx_off[vk + 1] - tp.sfx_off[vk]);
-    tp.lead[i] = lead;
+    const int64_t lp = tp.pfx_off[v1 + 1] - tp.pfx_off[v1];
+    tp.tp_len[i] = lp + len + (tp.sfx_off[vk + 1] - tp.sfx_off[vk]);
+    tp.lead[i] = make_int4(lead, lw, le, v1);
   }
 }
 

@@ -630,10 +630,21 @@ __global__ __launch_bounds__(kBlock) void k_tp_write(const int64_t* pp_off, cons
 // depth, the entry after it and the split rank, and the next pe entries.
 // One thread per test path.
 __global__ __launch_bounds__(kBlock) void k_tp_keys(const int64_t* pp_off, const int32_t* pp_vtx,
-                                                    int64_t n_pp, BfsOut b, const int32_t* lead,
+                                                    int64_t n_pp, BfsOut b, const int4* lead,
                                                     uint64_t* key) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n_pp) {
+    // a path that leaves the tree inside its prime path: the prime-path
+    // writer has recorded where (entry lp + lead) and the entries w and e
+    if (lead) {
+      const int4 ld = lead[i];
+      if (ld.x < pp_off[i + 1] - pp_off[i]) {
+        const int lp = (int)(b.pfx_off[ld.w + 1] - b.pfx_off[ld.w]);
+        tp_tree_key(b.pre, b.pend, b.cfirst, b.ccnt, b.bq, ld.y, lp + ld.x, true, ld.z, ld.w,
+                    key + (int64_t)kTpKeyWords * i);
+        return;
+      }
+    }
     const SpliceRow r = splice_row(pp_off, pp_vtx, b, i);
     const int len = r.lp + r.lq + r.ls;
     // where the path leaves the BFS tree: entries up to the prime path's
@@ -643,14 +654,9 @@ __global__ __launch_bounds__(kBlock) void k_tp_keys(const int64_t* pp_off, const
     int first = len;
     int prev = r.v1;
     int kscan = r.lp + 1;
-    if (lead) {
-      const int ld = lead[i];
-      if (ld < r.lq) {
-        first = r.lp + ld;
-      } else {
-        prev = r.vk;
-        kscan = r.lp + r.lq;
-      }
+    if (lead) {  // the whole prime path follows the tree
+      prev = r.vk;
+      kscan = r.lp + r.lq;
     }
     for (int k0 = kscan; k0 < len && first == len; k0 += 8) {
       int x[8], px[8];
@@ -669,25 +675,8 @@ __global__ __launch_bounds__(kBlock) void k_tp_keys(const int64_t* pp_off, const
     const bool has_e = first < len;
     const int w = splice_entry(r, pp_vtx, b, first - 1);
     const int ev = has_e ? splice_entry(r, pp_vtx, b, first) : 0;
-    const uint32_t prew = (uint32_t)b.pre[w], pendw = (uint32_t)b.pend[w];
-    uint32_t split;
-    if (has_e) {
-      split = pendw;
-      const int cf = b.cfirst[w], cn = b.ccnt[w];
-      for (int q = 0; q < cn; ++q) {
-        const int cv = b.bq[cf + q];
-        if (cv > ev) {
-          split = (uint32_t)b.pre[cv];
-          break;
-        }
-      }
-    } else {
-      split = prew + 1;
-    }
-    uint64_t* kk = key + (int64_t)kTpKeyWords * i;
-    kk[0] = (uint64_t)prew | ((uint64_t)pendw << 18) | ((uint64_t)(first - 1) << 36) |
-            ((uint64_t)(has_e ? 1 : 0) << 49);
-    kk[1] = (uint64_t)(uint32_t)ev | ((uint64_t)split << 17) | ((uint64_t)(uint32_t)b.pre[r.v1] << 35);
+    tp_tree_key(b.pre, b.pend, b.cfirst, b.ccnt, b.bq, w, first, has_e, ev, r.v1,
+                key + (int64_t)kTpKeyWords * i);
     // the words of entries after e come from k_tp_write, which runs next
   }
 }
@@ -695,7 +684,7 @@ __global__ __launch_bounds__(kBlock) void k_tp_keys(const int64_t* pp_off, const
 hipError_t launch_tp_write(const int64_t* pp_off, const int32_t* pp_vtx, int64_t n_pp,
                            const BfsOut& b, const int64_t* tp_off, int32_t* tp_vtx,
                            uint64_t* key, uint64_t* pk, int eb, int32_t* idx,
-                           const int32_t* lead, hipStream_t st) {
+                           const int4* lead, hipStream_t st) {
   if (n_pp == 0) return hipSuccess;
   if (eb < 1 || eb > 18) return hipErrorInvalidValue;  // more than 2^18 - 1 vertices in one union
   // the tree-position keys first: the splice cuts the entry words after e
