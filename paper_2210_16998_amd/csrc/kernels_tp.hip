@@ -1127,7 +1127,9 @@ hipError_t launch_gather(const int64_t* tp_off, const int32_t* tp_vtx, const int
 // stores, so a wave writes 1 KiB of consecutive addresses per instruction.
 // The aligned groups at the two ends of a window are shared with the
 // neighbouring windows (or workgroups); there only the entries inside the
-// window are stored, one by one.
+// window are stored, one by one.  A thread loads its words of the next
+// window into registers before the current window's stores, so that their
+// latency overlaps those.
 constexpr int kGatherPaths = 64;
 constexpr int kUnpackMap = 4096;  // words a workgroup maps to paths in LDS
 constexpr int kUnpackWin = 4096;  // entries of one window in LDS
@@ -1144,6 +1146,7 @@ __global__ __launch_bounds__(kBlock) void k_unpack_gather(const int64_t* tp_off,
   constexpr int pe = 64 / EB;  // a compile-time divisor: no division per entry
   constexpr uint64_t emask = (1ull << EB) - 1;
   constexpr int kWinWords = kUnpackWin / pe;
+  constexpr int kWinIter = (kWinWords + kBlock - 1) / kBlock;  // a thread's words per window
   __shared__ int64_t s_src[kGatherPaths];
   __shared__ int64_t s_pfx[kGatherPaths];      // first word of the path's packed prefix row
   __shared__ int32_t s_lpw[kGatherPaths];      // its words that hold prefix entries only
@@ -1209,20 +1212,42 @@ __global__ __launch_bounds__(kBlock) void k_unpack_gather(const int64_t* tp_off,
     const int t = path_of(w);
     return s_cum[t] + (w - s_wc[t]) * pe;
   };
+  // a thread's words of the window starting at word w0: w0 + tid + u kBlock
+  auto load_words = [&](int32_t w0, uint64_t (&wd)[kWinIter]) {
+    const int32_t w1 = w0 + kWinWords < nw_tot ? w0 + kWinWords : nw_tot;
+#pragma unroll
+    for (int u = 0; u < kWinIter; ++u) {
+      const int32_t w = w0 + tid + u * kBlock;
+      wd[u] = 0;
+      if (w < w1) {
+        const int t = path_of(w);
+        const int32_t qw = w - s_wc[t];
+        wd[u] = qw < s_lpw[t] ? b.pfx_pk[s_pfx[t] + qw] : pk[s_src[t] + qw];
+      }
+    }
+  };
+  uint64_t cur[kWinIter];
+  load_words(0, cur);
   for (int32_t w0 = 0; w0 < nw_tot; w0 += kWinWords) {
     const int32_t w1 = w0 + kWinWords < nw_tot ? w0 + kWinWords : nw_tot;
     const int32_t e_a = entry_of(w0), e_b = entry_of(w1);
-    for (int32_t w = w0 + tid; w < w1; w += kBlock) {
-      const int t = path_of(w);
-      const int32_t qw = w - s_wc[t];
-      const uint64_t word = qw < s_lpw[t] ? b.pfx_pk[s_pfx[t] + qw] : pk[s_src[t] + qw];
-      const int32_t e0 = s_cum[t] + qw * pe;
-      const int32_t ne = s_cum[t + 1] - e0;  // entries of the path from this word on
 #pragma unroll
-      for (int j = 0; j < pe; ++j)
-        if (j < ne) s_e[e0 - e_a + j] = (int32_t)((word >> ((pe - 1 - j) * EB)) & emask) - 1;
+    for (int u = 0; u < kWinIter; ++u) {
+      const int32_t w = w0 + tid + u * kBlock;
+      if (w < w1) {
+        const int t = path_of(w);
+        const int32_t qw = w - s_wc[t];
+        const uint64_t word = cur[u];
+        const int32_t e0 = s_cum[t] + qw * pe;
+        const int32_t ne = s_cum[t + 1] - e0;  // entries of the path from this word on
+#pragma unroll
+        for (int j = 0; j < pe; ++j)
+          if (j < ne) s_e[e0 - e_a + j] = (int32_t)((word >> ((pe - 1 - j) * EB)) & emask) - 1;
+      }
     }
     __syncthreads();
+    // the next window's words are loaded while this window's entries leave
+    if (w1 < nw_tot) load_words(w1, cur);
     const int64_t ga = d0 + e_a, gb = d0 + e_b;  // the window's output range
     const int64_t g_first = ga & ~(int64_t)3;
     const int64_t ngroups = (gb - g_first + 3) >> 2;
