@@ -1043,12 +1043,41 @@ hipError_t launch_next_runs(const int64_t* rb, int64_t n_runs, int64_t* rb_out, 
   return hipGetLastError();
 }
 
-__global__ void k_dedup_flags(TpOrder K, const int32_t* idx, int64_t n, int64_t* keep_cnt,
-                              int64_t* keep_len) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// keep_cnt[k] = 1 unless sorted position k holds the same test path as k - 1;
+// keep_len[k] = its length when kept, else 0.  A workgroup stages the keys
+// of positions k0 - 1 .. k0 + kBlock - 1 in LDS, each key loaded once and
+// whole (16 bytes at a time), then each thread compares its position with
+// the one before.
+__global__ __launch_bounds__(kBlock) void k_dedup_flags(TpOrder K, const int32_t* idx, int64_t n,
+                                                        int64_t* keep_cnt, int64_t* keep_len) {
+  __shared__ uint64_t s_key[kTpKeyWords][kBlock + 1];
+  __shared__ int32_t s_idx[kBlock + 1];
+  const int tid = (int)threadIdx.x;
+  const int64_t k0 = (int64_t)blockIdx.x * kBlock;
+  for (int q = tid; q <= kBlock; q += kBlock) {  // slot q: position k0 - 1 + q
+    const int64_t k = k0 - 1 + q;
+    if (k >= 0 && k < n) {
+      const int32_t x = idx[k];
+      s_idx[q] = x;
+      const ulonglong2* kx = reinterpret_cast<const ulonglong2*>(K.key + (int64_t)kTpKeyWords * x);
+      ulonglong2 w[kTpKeyWords / 2];
+#pragma unroll
+      for (int h = 0; h < kTpKeyWords / 2; ++h) w[h] = kx[h];
+#pragma unroll
+      for (int h = 0; h < kTpKeyWords / 2; ++h) {
+        s_key[2 * h][q] = w[h].x;
+        s_key[2 * h + 1][q] = w[h].y;
+      }
+    }
+  }
+  __syncthreads();
+  const int64_t k = k0 + tid;
   if (k >= n) return;
-  const int64_t a = idx[k];
-  const bool keep = (k == 0) || tp_cmp(K, idx[k - 1], a) != 0;
+  const int q = tid + 1;
+  const int64_t a = s_idx[q];
+  const bool keep = k == 0 || tp_cmp_keys(K, (int64_t)s_idx[q - 1],
+                                          [&](int t) { return s_key[t][q - 1]; }, a,
+                                          [&](int t) { return s_key[t][q]; }) != 0;
   keep_cnt[k] = keep ? 1 : 0;
   keep_len[k] = keep ? K.off[a + 1] - K.off[a] : 0;
 }
