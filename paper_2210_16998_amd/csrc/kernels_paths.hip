@@ -843,9 +843,10 @@ hipError_t launch_down_run(const ExtArgs& a, int depth, int L, int64_t base, int
 // Each wave writes the prime paths of 64 consecutive ranks, one per lane, by
 // walking parent links from their leaves.  The walks are aligned by depth: a
 // lane starts when the wave reaches the depth of its leaf, so at every step
-// the active lanes stand on one tree level, at nodes close together in that
-// level's array (consecutive ranks are neighbours in depth-first order), and
-// a load touches few cache lines.  The entries of kPPSeg consecutive depths
+// the active lanes stand on one tree level, mostly at nodes close together
+// in that level's array (consecutive ranks are neighbours in depth-first
+// order, and a tile's children are stored in its parents' order), and a load
+// touches few cache lines.  The entries of kPPSeg consecutive depths
 // go to LDS, one row per lane; then the wave stores the rows, kPPSeg lanes
 // per row, so that a store covers a few whole row segments instead of one
 // word in each of 64 lines.  With the BFS tables given, the walk also checks
