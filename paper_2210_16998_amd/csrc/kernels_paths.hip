@@ -765,6 +765,66 @@ __device__ __forceinline__ uint32_t up_node(const ExtArgs& a, int64_t x, uint32_
   return c;
 }
 
+// The same for D = 1 with the loads batched: x's children's codes and child
+// ranges kSweepBatch at a time, then their own children's counts all
+// together, so that a thread waits for about three load latencies instead of
+// a few per child.  (The down sweep keeps its per-child loop: batched the
+// same way it measured slower, its stores and rank chain per child.)
+constexpr int kSweepBatch = 4;
+__device__ __forceinline__ bool nch_internal(uint8_t k) { return k >= 1 && k < kNchPP; }
+
+__device__ __forceinline__ void up_node_batched(const ExtArgs& a, int64_t x, uint32_t* sub_cnt,
+                                                int& cyc) {
+  const uint8_t k = a.t.nch[x];
+  uint32_t c = 0;
+  if (k >= kNchPP) {
+    c = 1;
+    cyc += k == kNchCycle ? 1 : 0;
+  } else if (k) {
+    const int64_t c0 = a.t.cstart[x];
+    for (int j0 = 0; j0 < k; j0 += kSweepBatch) {
+      uint8_t ky[kSweepBatch];
+      int64_t cs[kSweepBatch];
+#pragma unroll
+      for (int j = 0; j < kSweepBatch; ++j) {
+        const bool in = j0 + j < k;
+        ky[j] = in ? a.t.nch[c0 + j0 + j] : (uint8_t)0;
+        cs[j] = in ? (int64_t)a.t.cstart[c0 + j0 + j] : 0;
+      }
+      uint32_t cy[kSweepBatch];
+#pragma unroll
+      for (int j = 0; j < kSweepBatch; ++j) {
+        cy[j] = ky[j] >= kNchPP ? 1u : 0u;
+        cyc += ky[j] == kNchCycle ? 1 : 0;
+      }
+      for (int g0 = 0;; g0 += kSweepBatch) {
+        uint32_t v[kSweepBatch][kSweepBatch];
+#pragma unroll
+        for (int j = 0; j < kSweepBatch; ++j)
+#pragma unroll
+          for (int g = 0; g < kSweepBatch; ++g)
+            v[j][g] = nch_internal(ky[j]) && g0 + g < ky[j] ? sub_cnt[cs[j] + g0 + g] : 0u;
+        bool more = false;
+#pragma unroll
+        for (int j = 0; j < kSweepBatch; ++j) {
+#pragma unroll
+          for (int g = 0; g < kSweepBatch; ++g) cy[j] += v[j][g];
+          more |= nch_internal(ky[j]) && g0 + kSweepBatch < ky[j];
+        }
+        if (!more) break;
+      }
+#pragma unroll
+      for (int j = 0; j < kSweepBatch; ++j) {
+        if (j0 + j < k) {
+          sub_cnt[c0 + j0 + j] = cy[j];
+          c += cy[j];
+        }
+      }
+    }
+  }
+  sub_cnt[x] = c;
+}
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_up_run(ExtArgs a, int64_t base, int64_t F,
                                                    uint32_t* sub_cnt,
@@ -772,7 +832,12 @@ __global__ __launch_bounds__(kBlock) void k_up_run(ExtArgs a, int64_t base, int6
   __shared__ int32_t s_w[kBlock / 64];
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   int cyc = 0;
-  if (j < F) up_node<D>(a, base + j, sub_cnt, cyc);
+  if (j < F) {
+    if constexpr (D == 1)
+      up_node_batched(a, base + j, sub_cnt, cyc);
+    else
+      up_node<D>(a, base + j, sub_cnt, cyc);
+  }
   int32_t tot;
   block_excl_scan<kBlock, int32_t>(cyc, tot, s_w);
   if (threadIdx.x == 0 && tot) atomicAdd(n_cycles, (unsigned long long)tot);
