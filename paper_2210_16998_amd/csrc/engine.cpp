@@ -802,7 +802,7 @@ tpg_status rank_and_materialize(tpg_workspace* ws, const HostUnion& U, hipStream
   const int64_t N = R.n_nodes;
   TPG_TRY(ws_reserve(ws, ws->sub_cnt, sizeof(uint32_t) * N));
   TPG_TRY(ws_reserve(ws, ws->totals, sizeof(int64_t) * 4));
-  TPG_TRY(ws_reserve(ws, ws->cycles, sizeof(uint64_t) * 2));
+  TPG_TRY(ws_reserve(ws, ws->cycles, sizeof(uint64_t) * (kCycleSlots + 1)));
   uint32_t* sc = ws->sub_cnt.as<uint32_t>();
   // the levels' ranges and every buffer the sweeps touch key their graphs
   std::vector<uint8_t> key;
@@ -821,7 +821,7 @@ tpg_status rank_and_materialize(tpg_workspace* ws, const HostUnion& U, hipStream
   // however little it does)
   constexpr int kRun = 2;  // 3 measured slower: deeper per-thread chains
   TPG_TRY(run_seq(ws, ws->rank_up, std::move(key), st, [&]() -> hipError_t {
-    hipError_t e = launch_zero_u64(ws->cycles.as<uint64_t>(), 1, st);
+    hipError_t e = launch_zero_u64(ws->cycles.as<uint64_t>(), kCycleSlots, st);
     unsigned long long* ncyc = ws->cycles.as<unsigned long long>();
     for (int L = R.Lmax; L >= 1 && e == hipSuccess;) {
       const int n = std::min(kRun, L);  // levels L - n + 1 .. L
@@ -831,12 +831,13 @@ tpg_status rank_and_materialize(tpg_workspace* ws, const HostUnion& U, hipStream
       L -= n;
     }
     if (e == hipSuccess)
-      e = launch_roots(a, R.count[1], sc, nullptr, nullptr, ws->totals.as<int64_t>(), 0, nullptr,
+      e = launch_roots(a, R.count[1], sc, nullptr, nullptr, ws->totals.as<int64_t>(), 0, nullptr, ncyc,
                        st);
     return e;
   }));
   TPG_TRY(io_read(ws, st, ws->h_scalars, ws->totals.p, sizeof(int64_t)));
-  TPG_TRY(io_read(ws, st, ws->h_scalars + 2, ws->cycles.p, sizeof(int64_t)));
+  TPG_TRY(io_read(ws, st, ws->h_scalars + 2, ws->cycles.as<uint64_t>() + kCycleSlots,
+                  sizeof(int64_t)));
   P.n_pp = ws->h_scalars[0];
   P.n_cycles = ws->h_scalars[2];
   TPG_TRY(ws_reserve(ws, ws->leaf_by_rank, sizeof(int64_t) * (P.n_pp + 1)));
@@ -859,7 +860,7 @@ tpg_status rank_and_materialize(tpg_workspace* ws, const HostUnion& U, hipStream
   key_add(key_down, rbw);
   TPG_TRY(run_seq(ws, ws->rank_down, std::move(key_down), st, [&]() -> hipError_t {
     hipError_t e =
-        launch_roots(a, R.count[1], sc, lbr, len, ws->totals.as<int64_t>(), 1, rbw, st);
+        launch_roots(a, R.count[1], sc, lbr, len, ws->totals.as<int64_t>(), 1, rbw, nullptr, st);
     for (int L = 1; L < R.Lmax && e == hipSuccess;) {
       const int n = std::min(kRun, R.Lmax - L);  // parents of levels L .. L + n - 1
       e = n > 1 ? launch_down_run(a, n - 1, L, R.off[L], R.count[L], sc, lbr, len, st)

@@ -71,14 +71,20 @@ hipError_t launch_fill(int W, const ExtArgs& a, int L, int64_t prev, int64_t bas
 // --- ranking / materialization ---------------------------------------------
 // sub_cnt: PP leaves per subtree (k_up), then rewritten top-down into the
 // rank of the subtree's first PP (or 0xFFFFFFFF when it has none).
+// n_cycles: kCycleSlots counters, zeroed before the sweep; a workgroup adds
+// its closed cycles to slot blockIdx.x % kCycleSlots (one address for all
+// would serialize the adds of a large level)
+constexpr int kCycleSlots = 64;
 hipError_t launch_up(const ExtArgs& a, int L, int64_t base, int64_t F, uint32_t* sub_cnt,
                      unsigned long long* n_cycles, hipStream_t st);
-// mode 0: totals[0] = #PP (no change to the arrays); mode 1: level-1 ranks,
-// root leaves recorded (leaf_by_rank, pp_len = 1), and with rb given (roots
-// = every vertex, in id order) rb[v] = rank of the first prime path whose
+// mode 0: totals[0] = #PP (no change to the arrays) and, with n_cycles given,
+// n_cycles[kCycleSlots] = the sum of its slots; mode 1: level-1 ranks, root
+// leaves recorded (leaf_by_rank, pp_len = 1), and with rb given (roots =
+// every vertex, in id order) rb[v] = rank of the first prime path whose
 // first vertex is >= v (v = 0 .. n_roots).
 hipError_t launch_roots(const ExtArgs& a, int64_t n_roots, uint32_t* sub_cnt, int64_t* leaf_by_rank,
-                        int32_t* pp_len, int64_t* totals, int mode, int64_t* rb, hipStream_t st);
+                        int32_t* pp_len, int64_t* totals, int mode, int64_t* rb,
+                        unsigned long long* n_cycles, hipStream_t st);
 // parents of level L: ranks to the children; PP leaves record node and length
 hipError_t launch_down(const ExtArgs& a, int L, int64_t base, int64_t F, uint32_t* sub_cnt,
                        int64_t* leaf_by_rank, int32_t* pp_len, hipStream_t st);

@@ -665,7 +665,7 @@ __global__ __launch_bounds__(kBlock) void k_up(ExtArgs a, int L, int64_t base, i
   }
   int32_t tot;
   block_excl_scan<kBlock, int32_t>(cyc, tot, s_w);
-  if (threadIdx.x == 0 && tot) atomicAdd(n_cycles, (unsigned long long)tot);
+  if (threadIdx.x == 0 && tot) atomicAdd(n_cycles + blockIdx.x % kCycleSlots, (unsigned long long)tot);
 }
 
 hipError_t launch_up(const ExtArgs& a, int L, int64_t base, int64_t F, uint32_t* sub_cnt,
@@ -679,7 +679,8 @@ hipError_t launch_up(const ExtArgs& a, int L, int64_t base, int64_t F, uint32_t*
 // their first prime path.  totals[0] = #PP.  One workgroup of 1024 threads.
 __global__ __launch_bounds__(1024) void k_roots(ExtArgs a, int64_t n_roots, uint32_t* sub_cnt,
                                                 int64_t* leaf_by_rank, int32_t* pp_len,
-                                                int64_t* totals, int mode, int64_t* rb) {
+                                                int64_t* totals, int mode, int64_t* rb,
+                                                unsigned long long* n_cycles) {
   __shared__ int64_t s_w[16];
   int64_t carry = 0;
   for (int64_t b = 0; b < n_roots; b += 1024) {
@@ -699,12 +700,24 @@ __global__ __launch_bounds__(1024) void k_roots(ExtArgs a, int64_t n_roots, uint
     carry += tc;
   }
   if (threadIdx.x == 0 && mode == 0) totals[0] = carry;
+  if (mode == 0 && n_cycles && threadIdx.x < 64) {  // the first wave sums the cycle slots
+    unsigned long long c = 0;
+    for (int s = (int)threadIdx.x; s < kCycleSlots; s += 64) c += n_cycles[s];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      const unsigned lo = __shfl_xor((unsigned)c, d, 64), hi = __shfl_xor((unsigned)(c >> 32), d, 64);
+      c += ((unsigned long long)hi << 32) | lo;
+    }
+    if (threadIdx.x == 0) n_cycles[kCycleSlots] = c;
+  }
   if (threadIdx.x == 0 && mode == 1 && rb) rb[n_roots] = carry;
 }
 
 hipError_t launch_roots(const ExtArgs& a, int64_t n_roots, uint32_t* sub_cnt, int64_t* leaf_by_rank,
-                        int32_t* pp_len, int64_t* totals, int mode, int64_t* rb, hipStream_t st) {
-  k_roots<<<1, 1024, 0, st>>>(a, n_roots, sub_cnt, leaf_by_rank, pp_len, totals, mode, rb);
+                        int32_t* pp_len, int64_t* totals, int mode, int64_t* rb,
+                        unsigned long long* n_cycles, hipStream_t st) {
+  k_roots<<<1, 1024, 0, st>>>(a, n_roots, sub_cnt, leaf_by_rank, pp_len, totals, mode, rb,
+                              n_cycles);
   return hipGetLastError();
 }
 
@@ -840,7 +853,7 @@ __global__ __launch_bounds__(kBlock) void k_up_run(ExtArgs a, int64_t base, int6
   }
   int32_t tot;
   block_excl_scan<kBlock, int32_t>(cyc, tot, s_w);
-  if (threadIdx.x == 0 && tot) atomicAdd(n_cycles, (unsigned long long)tot);
+  if (threadIdx.x == 0 && tot) atomicAdd(n_cycles + blockIdx.x % kCycleSlots, (unsigned long long)tot);
 }
 
 hipError_t launch_up_run(const ExtArgs& a, int depth, int64_t base, int64_t F, uint32_t* sub_cnt,
