@@ -712,8 +712,10 @@ hipError_t launch_tp_write(const int64_t* pp_off, const int32_t* pp_vtx, int64_t
 // sort + dedup
 // ---------------------------------------------------------------------------
 // Entries k0.. of two test paths whose entries before k0 agree, compared
-// lexicographically (then by length) on their packed copies: four words per
-// step, two aligned 16-byte loads per path.
+// lexicographically (then by length) on their packed copies: 2 P words per
+// step, P aligned 16-byte loads per path.  P = 2 by default; the split
+// search, which moves few bytes and waits on each step, takes 4.
+template <int P = 2>
 __device__ __forceinline__ int tp_cmp_tail(const TpOrder& K, int64_t x, int64_t y, int64_t k0) {
   const int64_t ox = K.off[x], oy = K.off[y];
   const int64_t lx = K.off[x + 1] - ox, ly = K.off[y + 1] - oy;
@@ -721,10 +723,12 @@ __device__ __forceinline__ int tp_cmp_tail(const TpOrder& K, int64_t x, int64_t 
   const int64_t nw = ((lx < ly ? lx : ly) + pe - 1) / pe;  // words holding entries of both
   const uint64_t* px = K.pk + tp_pk_base(ox, x, pe);
   const uint64_t* py = K.pk + tp_pk_base(oy, y, pe);
-  for (int64_t q = (k0 / pe) & ~(int64_t)1; q < nw; q += 4) {
-    uint64_t a[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0};
+  for (int64_t q = (k0 / pe) & ~(int64_t)1; q < nw; q += 2 * P) {
+    uint64_t a[2 * P], c[2 * P];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int i = 0; i < 2 * P; ++i) a[i] = c[i] = 0;
+#pragma unroll
+    for (int h = 0; h < P; ++h) {
       if (q + 2 * h < nw) {
         const ulonglong2 u = *reinterpret_cast<const ulonglong2*>(px + q + 2 * h);
         const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(py + q + 2 * h);
@@ -737,7 +741,7 @@ __device__ __forceinline__ int tp_cmp_tail(const TpOrder& K, int64_t x, int64_t 
       }
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2 * P; ++i)
       if (a[i] != c[i]) return a[i] < c[i] ? -1 : 1;
   }
   return lx < ly ? -1 : (lx > ly ? 1 : 0);
@@ -756,7 +760,7 @@ __device__ __forceinline__ int tp_cmp_tail(const TpOrder& K, int64_t x, int64_t 
 //    w_x towards w_y, t_x with e_x (not a tree child), and e_x < c exactly
 //    when pre(w_y) < split_x; symmetric the other way round;
 //  * otherwise the tree prefixes differ first and preorder decides.
-template <class KX, class KY>
+template <int P = 2, class KX, class KY>
 __device__ __forceinline__ int tp_cmp_keys(const TpOrder& K, int64_t x, KX kx, int64_t y, KY ky) {
   if (x == y) return 0;
   const uint64_t ax = kx(0), ay = ky(0), bx = kx(1), by = ky(1);
@@ -773,7 +777,7 @@ __device__ __forceinline__ int tp_cmp_keys(const TpOrder& K, int64_t x, KX kx, i
       if (cx != cy) return cx < cy ? -1 : 1;
       if ((cx & ((1ull << K.eb) - 1)) == 0) return 0;  // both ended inside this word
     }
-    return tp_cmp_tail(K, x, y, (int64_t)((ax >> 36) & kM13) + 2 + (int64_t)kTpKeyTail * K.pe);
+    return tp_cmp_tail<P>(K, x, y, (int64_t)((ax >> 36) & kM13) + 2 + (int64_t)kTpKeyTail * K.pe);
   }
   const uint32_t pex = (uint32_t)((ax >> 18) & kM18), pey = (uint32_t)((ay >> 18) & kM18);
   if (pwx < pwy && pwy < pex) return pwy >= (uint32_t)((bx >> 17) & kM18) ? -1 : 1;
@@ -782,11 +786,12 @@ __device__ __forceinline__ int tp_cmp_keys(const TpOrder& K, int64_t x, KX kx, i
 }
 
 // The same, reading the keys from memory (x, y: test-path indices).
+template <int P = 2>
 __device__ __forceinline__ int tp_cmp(const TpOrder& K, int64_t x, int64_t y) {
   if (x == y) return 0;
   const uint64_t* kx = K.key + (int64_t)kTpKeyWords * x;
   const uint64_t* ky = K.key + (int64_t)kTpKeyWords * y;
-  return tp_cmp_keys(K, x, [kx](int i) { return kx[i]; }, y, [ky](int i) { return ky[i]; });
+  return tp_cmp_keys<P>(K, x, [kx](int i) { return kx[i]; }, y, [ky](int i) { return ky[i]; });
 }
 
 // Merge path: number of elements taken from A among the first d outputs of
@@ -805,7 +810,7 @@ __device__ __forceinline__ int64_t merge_split_wave(const TpOrder& K, const int3
     const int64_t step = (span + 63) / 64;
     const int64_t c = lo + (int64_t)lane * step;  // candidate tested by this lane
     // P(c): the merge takes A[c] before B[d - 1 - c]; true then false along c
-    const bool p = c < hi && tp_cmp(K, B[d - 1 - c], A[c]) >= 0;
+    const bool p = c < hi && tp_cmp<4>(K, B[d - 1 - c], A[c]) >= 0;
     const uint64_t t = __ballot(p);
     if (t == 0) {
       hi = lo;  // P(lo) is false: the split is lo
@@ -878,7 +883,7 @@ __global__ __launch_bounds__(64 * kSplitWaves) void k_merge_splits(TpOrder K, co
   const int64_t p = merge_pair_of_wave(rb, n_runs, pos);
   int64_t a0, a1, b1;
   merge_pair_bounds(rb, n_runs, p, a0, a1, b1);
-  const bool ordered = a1 == a0 || b1 == a1 || tp_cmp(K, in[a1 - 1], in[a1]) <= 0;
+  const bool ordered = a1 == a0 || b1 == a1 || tp_cmp<4>(K, in[a1 - 1], in[a1]) <= 0;
   const int64_t d = pos - a0;
   const int64_t r = ordered ? (d < a1 - a0 ? d : a1 - a0)
                             : merge_split_wave(K, in + a0, a1 - a0, in + a1, b1 - a1, d);
